@@ -1,0 +1,194 @@
+"""Semi-implicit bidomain time step and the normalised linear solve.
+
+Sec. 3.2 (scheme and resolution algorithm): with gamma = chi*c/dt,
+
+  Step 1  Y = [0 ; M_H (gamma V^n - chi (I_ion(V^n, W^n) - I_st^n))]
+  Step 2  Lambda X = Y, X = [U^{n+1}; V^{n+1}],
+          Lambda = [[S_1, Pi^T S_i], [S_i Pi, gamma M_H + S_i]],
+          normalised so that the integral of U^{n+1} over the thorax is 0
+  Step 3  W^{n+1} = W^n + dt g(V^n, W^n)   (explicit on the reaction)
+
+Vertices are reordered heart-first (assumption H1), so that Pi is the
+truncation to the first N_H entries and Pi^T the zero padding.
+
+Prop. 1: Lambda is symmetric positive semi-definite with kernel
+1_Omega x {0}; for Y in its range the solution with (M U, 1) = 0 is unique,
+obtained from any solution by U <- U - alpha 1 with
+alpha = (M U, 1) / (M 1, 1).
+
+The normalised solution is computed three independent ways:
+  solve_dense   Cholesky of the SPD matrix Lambda + c w w^T, w = [M 1; 0]
+  solve_sparse  sparse LU of Lambda with one u unknown fixed to 0, then the
+                normalisation of Prop. 1
+  solve_cg      Jacobi-preconditioned CG with a stop that accounts for the
+                Lanczos estimate of the condition number, then normalisation
+"""
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import fem, ionic
+
+
+class System:
+    """Assembled bidomain system for one mesh and one time step."""
+
+    def __init__(self, cfg, dt=None):
+        self.cfg = cfg
+        a = fem.assemble(cfg)
+        self.N, self.NH = a["N"], a["NH"]
+        self.hn = a["hn"]
+        N, NH = self.N, self.NH
+        is_h = np.zeros(N, dtype=bool)
+        is_h[self.hn] = True
+        self.torso = np.nonzero(~is_h)[0]
+        # heart-first order: heart vertices (ascending id), then torso ones
+        self.perm = np.concatenate([self.hn, self.torso])
+        self.chi, self.cm = cfg["chi"], cfg["cm"]
+        self.dt = cfg["dt"] if dt is None else dt
+        self.gamma = self.chi * self.cm / self.dt
+        P = self.perm
+        self.S1 = a["S1"][P][:, P].tocsr()
+        self.Se = a["Se"][P][:, P].tocsr()
+        self.Si, self.Sm = a["Si"], a["Sm"]
+        self.m = a["m"][P]
+        self.mH = a["mH"]
+        Pi_T = sp.vstack([sp.identity(NH, format="csr"),
+                          sp.csr_matrix((N - NH, NH))]).tocsr()
+        self.PiT = Pi_T
+        g = self.gamma
+        self.Lam = sp.bmat([[self.S1, Pi_T @ self.Si],
+                            [self.Si @ Pi_T.T, g * sp.diags(self.mH) + self.Si]],
+                           format="csr")
+        stim = cfg["stim_mask"].astype(bool)[self.hn]
+        self.stim_h = stim
+        self.n0 = int(round(cfg["stim_t0"] / self.dt))
+        self.n1 = int(round(cfg["stim_t1"] / self.dt))
+
+    # ---- ordering helpers --------------------------------------------
+    def to_global_u(self, Uperm):
+        u = np.empty(self.N)
+        u[self.perm] = Uperm
+        return u
+
+    def from_global_u(self, u):
+        return u[self.perm]
+
+    # ---- Step 1 and Step 3 --------------------------------------------
+    def i_stim(self, n):
+        amp = self.cfg["stim_amp"] if self.n0 <= n < self.n1 else 0.0
+        return np.where(self.stim_h, amp, 0.0)
+
+    def rhs(self, V, h, n):
+        """Step 1: the right-hand side Y (heart-first order)."""
+        Iion = ionic.i_ion(V, h, self.cm)
+        Y2 = self.mH * (self.gamma * V - self.chi * (Iion - self.i_stim(n)))
+        return np.concatenate([np.zeros(self.N), Y2])
+
+    def gate(self, V, h):
+        """Step 3, forward Euler on the old state."""
+        return h + self.dt * ionic.gate_rate(V, h)
+
+    # ---- normalisation (Prop. 1) ---------------------------------------
+    def normalise(self, X):
+        X = X.copy()
+        U = X[:self.N]
+        alpha = np.dot(self.m, U) / np.sum(self.m)
+        X[:self.N] = U - alpha
+        return X
+
+    # ---- Step 2: three solvers -----------------------------------------
+    def solve_dense(self, Y):
+        L = self.Lam.toarray()
+        w = np.concatenate([self.m, np.zeros(self.NH)])
+        c = np.abs(L).sum(axis=1).max() / np.dot(w, w)
+        A = L + c * np.outer(w, w)
+        cf = sla.cho_factor(A, lower=True)
+        return sla.cho_solve(cf, Y)
+
+    def solve_sparse(self, Y):
+        n2 = self.N + self.NH
+        k = self.N - 1                       # the u unknown fixed to 0
+        keep = np.concatenate([np.arange(k), np.arange(k + 1, n2)])
+        A = self.Lam[keep][:, keep].tocsc()
+        lu = spla.splu(A, permc_spec="COLAMD")
+        x = np.zeros(n2)
+        x[keep] = lu.solve(Y[keep])
+        # refine once against the full (consistent) system
+        r = Y - self.Lam @ x
+        x[keep] += lu.solve(r[keep])
+        return self.normalise(x)
+
+    def solve_cg(self, Y, x0=None, rtol=1e-12, kappa_rtol=1e-10,
+                 max_iter=200000):
+        A = self.Lam
+        dinv = 1.0 / A.diagonal()
+        x = np.zeros_like(Y) if x0 is None else x0.copy()
+        r = Y - A @ x
+        ny = np.linalg.norm(Y)
+        z = dinv * r
+        p = z.copy()
+        rz = r @ z
+        alphas, betas = [], []
+        kappa = 1.0
+        for it in range(max_iter):
+            q = A @ p
+            alpha = rz / (p @ q)
+            x += alpha * p
+            r -= alpha * q
+            alphas.append(alpha)
+            rel = np.linalg.norm(r) / ny
+            if rel <= rtol and (it % 25 == 0 or rel * kappa <= kappa_rtol):
+                kappa = _lanczos_kappa(alphas, betas)
+                if rel * kappa <= kappa_rtol:
+                    break
+            z = dinv * r
+            rz_new = r @ z
+            beta = rz_new / rz
+            betas.append(beta)
+            rz = rz_new
+            p = z + beta * p
+        self.last_cg = dict(iters=it + 1, rel=rel, kappa=kappa)
+        return self.normalise(x)
+
+    def solve(self, Y, method="auto", x0=None):
+        n2 = self.N + self.NH
+        if method == "auto":
+            method = "dense" if n2 <= 6000 else (
+                "sparse" if self.cfg["dim"] == 2 else "cg")
+        if method == "dense":
+            return self.solve_dense(Y)
+        if method == "sparse":
+            return self.solve_sparse(Y)
+        return self.solve_cg(Y, x0=x0)
+
+    # ---- a full time step ------------------------------------------------
+    def step(self, V, h, n, method="auto", U0=None):
+        """Advance (V^n, h^n) -> (U^{n+1}, V^{n+1}, h^{n+1})."""
+        Y = self.rhs(V, h, n)
+        x0 = None
+        if U0 is not None:
+            x0 = np.concatenate([U0, V])
+        X = self.solve(Y, method=method, x0=x0)
+        h1 = self.gate(V, h)
+        return X[:self.N], X[self.N:], h1
+
+
+def _lanczos_kappa(alphas, betas):
+    """Condition-number estimate of the preconditioned operator from the CG
+    coefficients (the Lanczos tridiagonal of the CG recurrences)."""
+    k = len(alphas)
+    a = np.asarray(alphas)
+    b = np.asarray(betas[:k - 1]) if k > 1 else np.zeros(0)
+    diag = 1.0 / a
+    diag[1:] += b / a[:-1]
+    off = np.sqrt(np.maximum(b, 0.0)) / a[:-1]
+    ev = sla.eigh_tridiagonal(diag, off, eigvals_only=True)
+    ev = ev[ev > 0]
+    return float(ev.max() / ev.min()) if len(ev) else 1.0
+
+
+def rel_err(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))

@@ -1,0 +1,115 @@
+"""Pins for the oracle's system matrix, normalised solve and time step
+(Sec. 3.2, Prop. 1) and for the Mitchell-Schaeffer reaction terms."""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import bidomain as bd
+from oracle import ionic
+
+
+@pytest.fixture(scope="module")
+def small():
+    return bd.System(w.square2d(n=12))
+
+
+def test_lambda_symmetric_psd_kernel(small):
+    """Prop. 1: symmetric PSD, kernel 1_Omega x {0}."""
+    L = small.Lam.toarray()
+    assert np.abs(L - L.T).max() <= 1e-14 * np.abs(L).max()
+    ev, vec = np.linalg.eigh(L)
+    scale = np.abs(ev).max()
+    assert ev.min() >= -1e-12 * scale
+    assert (np.abs(ev) <= 1e-11 * scale).sum() == 1
+    k = vec[:, np.argmin(np.abs(ev))]
+    ref = np.concatenate([np.ones(small.N), np.zeros(small.NH)])
+    ref /= np.linalg.norm(ref)
+    assert abs(abs(k @ ref) - 1.0) < 1e-10
+
+
+def test_range_and_restriction(small):
+    """Ran Lambda = 1^perp x R^NH; Pi Pi^T = id; Pi^T S_i Pi = S_1 - S_e."""
+    rng = np.random.default_rng(1)
+    X = rng.normal(size=small.N + small.NH)
+    assert abs((small.Lam @ X)[:small.N].sum()) < 1e-11 * np.abs(small.Lam @ X).max()
+    PiT = small.PiT.toarray()
+    np.testing.assert_allclose(PiT.T @ PiT, np.eye(small.NH))
+    lhs = PiT @ small.Si.toarray() @ PiT.T
+    np.testing.assert_allclose(lhs, (small.S1 - small.Se).toarray(), atol=1e-13)
+
+
+@pytest.mark.parametrize("mk", [lambda: w.square2d(n=12),
+                                lambda: w.slab3d(n=4),
+                                lambda: w.thorax2d(n_target=1500, seed=2)])
+def test_three_solvers_agree(mk):
+    """Dense augmented Cholesky, grounded sparse LU and Jacobi-CG reach the
+    same normalised solution; it satisfies Lambda X = Y and (M U, 1) = 0."""
+    s = bd.System(mk())
+    rng = np.random.default_rng(2)
+    V = rng.uniform(0, 100, s.NH)
+    h = rng.uniform(0, 1, s.NH)
+    Y = s.rhs(V, h, 0)
+    Xd = s.solve_dense(Y)
+    Xs = s.solve_sparse(Y)
+    Xc = s.solve_cg(Y)
+    assert np.linalg.norm(s.Lam @ Xd - Y) <= 1e-12 * np.linalg.norm(Y)
+    assert abs(s.m @ Xd[:s.N]) <= 1e-12 * np.abs(Xd).max()
+    assert bd.rel_err(Xs, Xd) < 1e-11
+    assert bd.rel_err(Xc, Xd) < 1e-9
+
+
+def test_constant_potential_is_stationary(small):
+    """With Y = [0; gamma M_H c 1] the normalised solution is U = 0, V = c 1
+    (S_i 1 = 0 and Pi^T S_i 1 = 0)."""
+    c = 37.5
+    Y = np.concatenate([np.zeros(small.N), small.gamma * small.mH * c])
+    X = small.solve_dense(Y)
+    np.testing.assert_allclose(X[:small.N], 0.0, atol=1e-10)
+    np.testing.assert_allclose(X[small.N:], c, rtol=1e-12)
+
+
+def test_rest_state_stays_at_rest(small):
+    """At rest (V = 0, h = 1, no stimulus) every step returns exactly rest."""
+    V = np.zeros(small.NH)
+    h = np.ones(small.NH)
+    U, V1, h1 = small.step(V, h, n=10**6)   # far outside the stimulus window
+    assert np.abs(U).max() < 1e-13 and np.abs(V1).max() < 1e-13
+    np.testing.assert_allclose(h1, 1.0)
+
+
+def test_stimulus_window():
+    s = bd.System(w.square2d(n=12))
+    assert s.n0 == 0 and s.n1 == 20
+    assert s.i_stim(19).max() == 50.0 and s.i_stim(20).max() == 0.0
+
+
+def test_ms_fixed_points():
+    """With h = 1 frozen the MS model has equilibria at vt = 0 and at the two
+    roots of vt (1 - vt) = tau_in / tau_out; between the lower two roots
+    the current is depolarising (negative I_ion)."""
+    r = ionic.TAU_IN / ionic.TAU_OUT
+    lo = (1 - np.sqrt(1 - 4 * r)) / 2
+    hi = (1 + np.sqrt(1 - 4 * r)) / 2
+    assert abs(lo - 0.0528) < 1e-4 and abs(hi - 0.9472) < 1e-4
+    for vt in (0.0, lo, hi):
+        assert abs(ionic.i_ion(vt * ionic.DV, 1.0, 1.0)) < 1e-12
+    assert ionic.i_ion(0.5 * lo * ionic.DV, 1.0, 1.0) > 0
+    assert ionic.i_ion(0.5 * ionic.DV, 1.0, 1.0) < 0
+    assert ionic.i_ion(1.2 * ionic.DV, 1.0, 1.0) > 0
+
+
+def test_gate_relaxation():
+    """Forward Euler on dh/dt converges to the exponential relaxation
+    h(t) = 1 - (1 - h0) exp(-t / tau_open) below the gate threshold, and
+    h(t) = h0 exp(-t / tau_close) above it."""
+    for V, h0, exact in ((0.0, 0.2, lambda t: 1 - 0.8 * np.exp(-t / 120.0)),
+                         (50.0, 0.9, lambda t: 0.9 * np.exp(-t / 150.0))):
+        T = 30.0
+        errs = []
+        for n in (100, 200):
+            h = np.array([h0])
+            dt = T / n
+            for _ in range(n):
+                h = h + dt * ionic.gate_rate(np.array([V]), h)
+            errs.append(abs(h[0] - exact(T)))
+        assert errs[1] < 0.6 * errs[0] and errs[1] < 1e-3
