@@ -1,0 +1,189 @@
+/*
+ * bido.h - C ABI of the MI355X bidomain per-step solver.
+ *
+ * The library advances the semi-implicit heart-torso bidomain scheme of
+ * C. Pierre, "Preconditioning the bidomain model with almost linear
+ * complexity" (Sec. 3.2, resolution algorithm):
+ *
+ *   Step 1  Y = [0 ; M_H (gamma V^n - chi (I_ion(V^n, W^n) - I_st^n))]
+ *   Step 2  Lambda X = Y with Lambda = [[S_1, Pi^T S_i], [S_i Pi, gamma M_H + S_i]],
+ *           X = [U^{n+1}; V^{n+1}], normalised so that (M U, 1) = 0 (Prop. 1)
+ *   Step 3  W^{n+1} = W^n + dt g(V^n, W^n)
+ *
+ * with gamma = chi * c / dt.  Step 2 is solved by preconditioned conjugate
+ * gradient with the block-LU preconditioner of Def. 2, the Schur complement
+ * replaced by the monodomain matrix K_m = gamma M_H + S_m (Sec. 5.2) and the
+ * inner solves P_1 ~ S_1, P_K ~ K_m given by hierarchical Cholesky factors
+ * built at accuracy eps (Sec. 5.3).
+ *
+ * Conventions
+ *   - Every pointer named "host" is host memory that the library only reads
+ *     during the call and copies; the caller keeps ownership.
+ *   - Every pointer named "dev" is device memory on the context's device,
+ *     borrowed for the duration of the call and used on the context's
+ *     stream; the library never frees it.
+ *   - u is indexed by the caller's global vertex numbering (length N);
+ *     v and w are indexed in the heart-local order returned by
+ *     bido_heart_nodes (heart vertices in ascending global id, length N_H).
+ *   - All functions return BIDO_OK (0) or a negative bido_status; the text
+ *     of the last error of the calling thread is given by bido_last_error.
+ *   - A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef BIDO_H
+#define BIDO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int bido_status;
+#define BIDO_OK                 0
+#define BIDO_ERR_ARG           -1  /* bad argument, size or layout          */
+#define BIDO_ERR_DEVICE        -2  /* HIP runtime error, or no device       */
+#define BIDO_ERR_NOT_SPD       -3  /* factorisation failed / CG breakdown   */
+#define BIDO_ERR_NOT_CONVERGED -4  /* max_iter reached; best iterate kept   */
+#define BIDO_ERR_DT_MISMATCH   -5  /* dt differs from the factored one      */
+#define BIDO_ERR_RANGE         -6  /* rhs not in Ran(Lambda) (Prop. 1)      */
+#define BIDO_ERR_STATE         -7  /* call not valid in the current state   */
+
+/* region code of heart elements; every other code is a torso organ whose
+ * isotropic conductivity is region_sigma[code] (Sec. 2, sigma_T = k(x) Id) */
+#define BIDO_REGION_HEART 1
+
+#define BIDO_PREC_FP64  0  /* preconditioner applied in FP64               */
+#define BIDO_PREC_MIXED 1  /* preconditioner in FP32 (FP64 outer PCG)      */
+
+#define BIDO_PRECOND_PLAIN   0  /* block-LU / monodomain preconditioner    */
+#define BIDO_PRECOND_LEARNED 1  /* plus a learned correction, flexible CG  */
+
+typedef struct bido_ctx bido_ctx;
+
+/* Mesh of the thorax Omega (Sec. 3.1): P1 simplices; heart elements form the
+ * sub-mesh of H.  For an isolated heart (Sec. 2.2) every element is heart. */
+typedef struct {
+    int dim;                /* 2 (triangles) or 3 (tetrahedra)              */
+    int64_t n_nodes;        /* N                                            */
+    const double* xyz;      /* host, n_nodes x dim, row-major [cm]          */
+    int64_t n_elems;
+    const int32_t* elems;   /* host, n_elems x (dim+1) vertex ids           */
+    const int8_t* region;   /* host, n_elems region codes                   */
+} bido_mesh;
+
+/* Tissue description (Sec. 2): sigma_i, sigma_e diagonal in the local fibre
+ * frame of each heart element; torso isotropic per region code.           */
+typedef struct {
+    double sigma_i[3];          /* along fibre, sheet, normal [mS/cm]       */
+    double sigma_e[3];
+    const double* fibre;        /* host, n_elems x dim x dim, row-major;
+                                   column k = k-th frame axis               */
+    const double* region_sigma; /* host, n_region_sigma entries             */
+    int n_region_sigma;
+    const uint8_t* stim_mask;   /* host, n_nodes; 1 = stimulated vertex     */
+    double stim_amp;            /* [uA/cm^2]                                */
+    double stim_t0, stim_t1;    /* active at step n iff
+                                   round(t0/dt) <= n < round(t1/dt)          */
+} bido_tissue;
+
+typedef struct {
+    double chi;        /* membrane surface-to-volume ratio [1/cm]            */
+    double cm;         /* membrane capacitance [uF/cm^2]                      */
+    double dt;         /* time step [ms]; gamma = chi*cm/dt                   */
+    double eps_h;      /* H-matrix accuracy eps (Sec. 5.3); 0 = exact factor */
+    double eta;        /* admissibility parameter, min diam <= eta * dist    */
+    double tol;        /* default relative residual |Lambda X - Y| / |Y|     */
+    int leaf;          /* nested-dissection leaf size (default 64)           */
+    int max_iter;      /* PCG iteration cap (default 200)                    */
+    int precision;     /* BIDO_PREC_*                                         */
+    int precond;       /* BIDO_PRECOND_*                                      */
+    int ionic;         /* 0 = Mitchell-Schaeffer (one gate per vertex)       */
+    int n_threads;     /* host threads for set-up; 0 = library default       */
+} bido_params;
+
+typedef struct {
+    int iterations;        /* PCG iterations of the (last) solve            */
+    int converged;         /* 1 if the tolerance was met                    */
+    double rel_residual;   /* final |Lambda X - Y| / |Y|                    */
+    double ms;             /* wall time of the call on the stream [ms]       */
+    int fallbacks;         /* learned-correction fallbacks to the plain one */
+    double range_removed;  /* |component of Y_1 along 1| removed (solve)    */
+    int64_t total_iterations; /* summed over the steps of bido_run          */
+} bido_stats;
+
+typedef struct {
+    int64_t n_nodes, n_heart, n_elems;
+    int64_t nnz_lambda;          /* stored entries of Lambda                  */
+    int64_t bytes_lambda;        /* bytes read by one Lambda product          */
+    int64_t bytes_p1, bytes_pk;  /* bytes of the P_1 / P_K factors as stored
+                                    (the active precision)                    */
+    int64_t dense_bytes_p1, dense_bytes_pk; /* same factors uncompressed      */
+    int levels_p1, levels_pk;    /* nested-dissection tree heights           */
+    int64_t lowrank_blocks;      /* admissible (low-rank) blocks stored       */
+    double setup_seconds;        /* host set-up time of bido_create           */
+    int ground_index;            /* internal index of the grounded u node    */
+} bido_info;
+
+/* Last error message of the calling thread ("" if none).                  */
+const char* bido_last_error(void);
+
+/* Fill *p with the defaults (chi 200, cm 1, dt 0.1, eps 1e-3, eta 2,
+ * tol 1e-10, leaf 64, max_iter 200, FP64, plain, MS).                     */
+void bido_default_params(bido_params* p);
+
+/* Assemble S_1, S_i, S_m and the lumped M, M_H from the mesh (Sec. 3.1,
+ * Sec. 5.2), order the unknowns, build the hierarchical Cholesky factors of
+ * the grounded S_1 and of K_m (Sec. 5.3) and upload everything to the
+ * current HIP device.  `stream` (a hipStream_t, may be NULL for the null
+ * stream) is the stream every later call enqueues on.  Returns
+ * BIDO_ERR_NOT_SPD if a factorisation meets a non-positive pivot.       */
+bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue,
+                        const bido_params* params, void* stream,
+                        bido_ctx** out);
+
+void bido_destroy(bido_ctx* ctx);
+
+bido_status bido_get_info(const bido_ctx* ctx, bido_info* info);
+
+/* Heart vertices (global ids, ascending) in the order used for v and w.
+ * The array is library-owned host memory valid until bido_destroy.       */
+bido_status bido_heart_nodes(const bido_ctx* ctx, const int64_t** ids,
+                             int64_t* n_h);
+
+/* One time step (Steps 1-3).  v (dev, N_H), w (dev, N_H gates) and u (dev,
+ * N) are updated in place; n is the step index (stimulus window).  The
+ * solve starts from X0 = (U^n, V^n) and stops at the context's tol.
+ * dt must equal params.dt (gamma is built into K_m), else
+ * BIDO_ERR_DT_MISMATCH.  Synchronises the stream once.                  */
+bido_status bido_step(bido_ctx* ctx, double* v, double* w, double* u,
+                      double dt, int64_t n, bido_stats* st);
+
+/* n_steps consecutive steps starting at index n0, same contract as
+ * bido_step; st->total_iterations sums the steps.                        */
+bido_status bido_run(bido_ctx* ctx, double* v, double* w, double* u,
+                     double dt, int64_t n0, int64_t n_steps, bido_stats* st);
+
+/* Step 2 alone: solve Lambda X = Y (Prop. 1).  rhs (dev, N + N_H) is
+ * [Y_1 (global order); Y_2 (heart-local order)]; x (dev, same layout) holds
+ * the initial guess on entry and the normalised solution on return.  If the
+ * mean of Y_1 exceeds 1e-8 |Y| / sqrt(N) the call returns BIDO_ERR_RANGE
+ * and leaves x untouched; otherwise that mean is removed and reported.
+ * tol <= 0 selects the context's tol.  On BIDO_ERR_NOT_CONVERGED x holds
+ * the last iterate (normalised).                                        */
+bido_status bido_solve(bido_ctx* ctx, const double* rhs, double* x,
+                       double tol, bido_stats* st);
+
+/* Change the preconditioner precision (BIDO_PREC_*) of an existing context.
+ * Mixed precision keeps FP32 copies of the factors and runs the outer
+ * solve as flexible CG in FP64.                                         */
+bido_status bido_set_precision(bido_ctx* ctx, int precision);
+
+/* Override tolerance and iteration cap (tol <= 0 / max_iter <= 0 keep the
+ * current values).                                                      */
+bido_status bido_set_solver(bido_ctx* ctx, double tol, int max_iter);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIDO_H */

@@ -1,0 +1,65 @@
+/*
+ * bido_host.h - host-only inspection entry points of libbido.
+ *
+ * These run the host set-up of bido_create (assembly of Sec. 3.1, the
+ * nested-dissection orderings, the hierarchical Cholesky factors of the
+ * grounded S_1 and of K_m, Sec. 5.3) without touching a GPU, and expose
+ * its results for checks.  They are not part of the solve path: bido_step,
+ * bido_run and bido_solve never call them.
+ *
+ * Ownership: every returned pointer is owned by the bido_host object and
+ * stays valid until bido_host_free.  Errors are reported as in bido.h.
+ */
+#ifndef BIDO_HOST_H
+#define BIDO_HOST_H
+
+#include "bido.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bido_host bido_host;
+
+#define BIDO_MAT_S1     0  /* S_1, caller's global numbering, N x N          */
+#define BIDO_MAT_SI     1  /* S_i, heart-local numbering, N_H x N_H           */
+#define BIDO_MAT_SM     2  /* S_m, heart-local numbering                      */
+#define BIDO_MAT_LAMBDA 3  /* Lambda in the internal order (u then v)         */
+
+#define BIDO_VEC_M      0  /* lumped M, global numbering                      */
+#define BIDO_VEC_MH     1  /* lumped M_H, heart-local numbering               */
+
+#define BIDO_IDX_UPOS   0  /* global id -> internal u index                    */
+#define BIDO_IDX_VPOS   1  /* heart-local index -> internal v index            */
+#define BIDO_IDX_HEART  2  /* heart-local index -> global id                   */
+
+#define BIDO_FACTOR_P1  0  /* factor of the grounded S_1 (internal u order)   */
+#define BIDO_FACTOR_PK  1  /* factor of K_m (internal v order)                */
+
+/* Last error message of the host entry points on the calling thread.    */
+const char* bido_host_last_error(void);
+
+bido_status bido_host_setup(const bido_mesh* mesh, const bido_tissue* tissue,
+                            const bido_params* params, bido_host** out);
+void bido_host_free(bido_host* h);
+
+/* CSR view: row pointers (n+1, int64), columns (int32), values (double). */
+bido_status bido_host_csr(const bido_host* h, int which, int64_t* n, int64_t* nnz,
+                          const int64_t** ptr, const int32_t** col, const double** val);
+bido_status bido_host_vec(const bido_host* h, int which, int64_t* n, const double** data);
+bido_status bido_host_index(const bido_host* h, int which, int64_t* n, const int64_t** data);
+
+/* Sizes of a factor: entries uncompressed / as stored, low-rank blocks,
+ * tree height, largest separator.                                        */
+bido_status bido_host_factor_stats(const bido_host* h, int which, int64_t* dense_entries,
+                                   int64_t* stored_entries, int64_t* n_lowrank,
+                                   int* height, int* max_sep);
+
+/* Apply the factor on the host: x = (L L^T)^-1 b in the factor's internal
+ * order (for P_1 the grounded entry of b is ignored and x there is 0).     */
+bido_status bido_host_factor_apply(const bido_host* h, int which, const double* b, double* x);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIDO_HOST_H */

@@ -1,0 +1,331 @@
+"""Python binding of libbido, the MI355X bidomain per-step solver.
+
+Argument marshalling only: every step of the solve runs inside libbido.so
+(HIP kernels for gfx950 plus its host set-up).  PyTorch supplies device
+memory and the stream.  Importing this package fails loudly when the
+library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbido.so")
+
+BIDO_OK = 0
+ERRORS = {-1: "BIDO_ERR_ARG", -2: "BIDO_ERR_DEVICE", -3: "BIDO_ERR_NOT_SPD",
+          -4: "BIDO_ERR_NOT_CONVERGED", -5: "BIDO_ERR_DT_MISMATCH",
+          -6: "BIDO_ERR_RANGE", -7: "BIDO_ERR_STATE"}
+PREC_FP64, PREC_MIXED = 0, 1
+PRECOND_PLAIN, PRECOND_LEARNED = 0, 1
+MAT_S1, MAT_SI, MAT_SM, MAT_LAMBDA = 0, 1, 2, 3
+VEC_M, VEC_MH = 0, 1
+IDX_UPOS, IDX_VPOS, IDX_HEART = 0, 1, 2
+FACTOR_P1, FACTOR_PK = 0, 1
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_i64_p = ctypes.POINTER(ctypes.c_int64)
+_c_i32_p = ctypes.POINTER(ctypes.c_int32)
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_nodes", ctypes.c_int64),
+                ("xyz", ctypes.c_void_p), ("n_elems", ctypes.c_int64),
+                ("elems", ctypes.c_void_p), ("region", ctypes.c_void_p)]
+
+
+class Tissue(ctypes.Structure):
+    _fields_ = [("sigma_i", ctypes.c_double * 3), ("sigma_e", ctypes.c_double * 3),
+                ("fibre", ctypes.c_void_p), ("region_sigma", ctypes.c_void_p),
+                ("n_region_sigma", ctypes.c_int), ("stim_mask", ctypes.c_void_p),
+                ("stim_amp", ctypes.c_double), ("stim_t0", ctypes.c_double),
+                ("stim_t1", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("chi", ctypes.c_double), ("cm", ctypes.c_double), ("dt", ctypes.c_double),
+                ("eps_h", ctypes.c_double), ("eta", ctypes.c_double), ("tol", ctypes.c_double),
+                ("leaf", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
+                ("precond", ctypes.c_int), ("ionic", ctypes.c_int), ("n_threads", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double),
+                ("fallbacks", ctypes.c_int), ("range_removed", ctypes.c_double),
+                ("total_iterations", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_heart", ctypes.c_int64),
+                ("n_elems", ctypes.c_int64), ("nnz_lambda", ctypes.c_int64),
+                ("bytes_lambda", ctypes.c_int64), ("bytes_p1", ctypes.c_int64),
+                ("bytes_pk", ctypes.c_int64), ("dense_bytes_p1", ctypes.c_int64),
+                ("dense_bytes_pk", ctypes.c_int64), ("levels_p1", ctypes.c_int),
+                ("levels_pk", ctypes.c_int), ("lowrank_blocks", ctypes.c_int64),
+                ("setup_seconds", ctypes.c_double), ("ground_index", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# name -> (restype, argtypes); mirrors include/bido.h and include/bido_host.h
+ABI = {
+    "bido_last_error": (ctypes.c_char_p, []),
+    "bido_default_params": (None, [ctypes.POINTER(Params)]),
+    "bido_create": (ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.POINTER(Tissue),
+                                   ctypes.POINTER(Params), ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_void_p)]),
+    "bido_destroy": (None, [ctypes.c_void_p]),
+    "bido_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
+    "bido_heart_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_c_i64_p),
+                                        ctypes.POINTER(ctypes.c_int64)]),
+    "bido_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
+                                 ctypes.POINTER(Stats)]),
+    "bido_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
+                                ctypes.c_int64, ctypes.POINTER(Stats)]),
+    "bido_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_double, ctypes.POINTER(Stats)]),
+    "bido_set_precision": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "bido_set_solver": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]),
+    "bido_host_last_error": (ctypes.c_char_p, []),
+    "bido_host_setup": (ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.POINTER(Tissue),
+                                       ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_void_p)]),
+    "bido_host_free": (None, [ctypes.c_void_p]),
+    "bido_host_csr": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p, _c_i64_p,
+                                     ctypes.POINTER(_c_i64_p), ctypes.POINTER(_c_i32_p),
+                                     ctypes.POINTER(_c_double_p)]),
+    "bido_host_vec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p,
+                                     ctypes.POINTER(_c_double_p)]),
+    "bido_host_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p,
+                                       ctypes.POINTER(_c_i64_p)]),
+    "bido_host_factor_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p, _c_i64_p,
+                                              _c_i64_p, ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_int)]),
+    "bido_host_factor_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p,
+                                              _c_double_p]),
+}
+
+
+class BidoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libbido.so not built ({LIB_PATH}); run "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in ABI.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(code, host=False):
+    if code != BIDO_OK:
+        msg = (lib.bido_host_last_error() if host else lib.bido_last_error()) or b""
+        raise BidoError(code, msg.decode())
+
+
+def default_params(**kw):
+    p = Params()
+    lib.bido_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _marshal(cfg):
+    """ctypes views of a workload dict (see workloads.meshes); the returned
+    list keeps the numpy buffers alive."""
+    keep = []
+
+    def ptr(a, dtype):
+        a = _arr(a, dtype)
+        keep.append(a)
+        return a.ctypes.data
+
+    d = int(cfg["dim"])
+    mesh = Mesh(d, len(cfg["xyz"]), ptr(cfg["xyz"], np.float64), len(cfg["elems"]),
+                ptr(cfg["elems"], np.int32), ptr(cfg["region"], np.int8))
+    si = (ctypes.c_double * 3)(*list(cfg["sigma_i"]) + [0.0] * (3 - d))
+    se = (ctypes.c_double * 3)(*list(cfg["sigma_e"]) + [0.0] * (3 - d))
+    tissue = Tissue(si, se, ptr(cfg["fibre"], np.float64), ptr(cfg["region_sigma"], np.float64),
+                    len(cfg["region_sigma"]), ptr(cfg["stim_mask"], np.uint8),
+                    float(cfg["stim_amp"]), float(cfg["stim_t0"]), float(cfg["stim_t1"]))
+    return mesh, tissue, keep
+
+
+def make_params(cfg, **kw):
+    p = default_params(chi=float(cfg["chi"]), cm=float(cfg["cm"]), dt=float(cfg["dt"]),
+                       tol=float(cfg.get("tol", 1e-10)))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class Solver:
+    """One solver context on the current HIP device and torch stream."""
+
+    def __init__(self, cfg, stream=None, **params):
+        import torch
+        if not torch.cuda.is_available():
+            raise BidoError(-2, "no GPU visible to torch")
+        self.torch = torch
+        mesh, tissue, keep = _marshal(cfg)
+        self.params = make_params(cfg, **params)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        ctx = ctypes.c_void_p()
+        _check(lib.bido_create(ctypes.byref(mesh), ctypes.byref(tissue),
+                               ctypes.byref(self.params), ctypes.c_void_p(stream.cuda_stream),
+                               ctypes.byref(ctx)))
+        del keep
+        self.ctx = ctx
+        info = Info()
+        _check(lib.bido_get_info(self.ctx, ctypes.byref(info)))
+        self.info = info.as_dict()
+        ids = _c_i64_p()
+        nh = ctypes.c_int64()
+        _check(lib.bido_heart_nodes(self.ctx, ctypes.byref(ids), ctypes.byref(nh)))
+        self.heart_nodes = np.ctypeslib.as_array(ids, shape=(nh.value,)).copy()
+        self.N = int(self.info["n_nodes"])
+        self.NH = int(self.info["n_heart"])
+        self.dt = float(self.params.dt)
+
+    def _dev(self, t, n):
+        torch = self.torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous() and t.numel() == n):
+            raise BidoError(-1, f"expected a contiguous float64 CUDA tensor of {n} entries")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def state(self, device="cuda"):
+        """Rest state (V = 0, h = 1, U = 0) as float64 device tensors."""
+        torch = self.torch
+        v = torch.zeros(self.NH, dtype=torch.float64, device=device)
+        w = torch.ones(self.NH, dtype=torch.float64, device=device)
+        u = torch.zeros(self.N, dtype=torch.float64, device=device)
+        return v, w, u
+
+    def step(self, v, w, u, n):
+        st = Stats()
+        _check(lib.bido_step(self.ctx, self._dev(v, self.NH), self._dev(w, self.NH),
+                             self._dev(u, self.N), self.dt, int(n), ctypes.byref(st)))
+        return st.as_dict()
+
+    def run(self, v, w, u, n0, n_steps, check=True):
+        st = Stats()
+        code = lib.bido_run(self.ctx, self._dev(v, self.NH), self._dev(w, self.NH),
+                            self._dev(u, self.N), self.dt, int(n0), int(n_steps),
+                            ctypes.byref(st))
+        if check:
+            _check(code)
+        return st.as_dict()
+
+    def solve(self, rhs, x, tol=0.0):
+        st = Stats()
+        n2 = self.N + self.NH
+        _check(lib.bido_solve(self.ctx, self._dev(rhs, n2), self._dev(x, n2), float(tol),
+                              ctypes.byref(st)))
+        return st.as_dict()
+
+    def set_precision(self, precision):
+        _check(lib.bido_set_precision(self.ctx, int(precision)))
+
+    def set_solver(self, tol=0.0, max_iter=0):
+        _check(lib.bido_set_solver(self.ctx, float(tol), int(max_iter)))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib.bido_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HostSetup:
+    """Host-only set-up (no GPU) exposing assembled matrices, orderings and
+    factor statistics for checks."""
+
+    def __init__(self, cfg, **params):
+        mesh, tissue, keep = _marshal(cfg)
+        self.params = make_params(cfg, **params)
+        h = ctypes.c_void_p()
+        _check(lib.bido_host_setup(ctypes.byref(mesh), ctypes.byref(tissue),
+                                   ctypes.byref(self.params), ctypes.byref(h)), host=True)
+        del keep
+        self.h = h
+
+    def csr(self, which):
+        import scipy.sparse as sp
+        n = ctypes.c_int64()
+        nnz = ctypes.c_int64()
+        ptr, col, val = _c_i64_p(), _c_i32_p(), _c_double_p()
+        _check(lib.bido_host_csr(self.h, which, ctypes.byref(n), ctypes.byref(nnz),
+                                 ctypes.byref(ptr), ctypes.byref(col), ctypes.byref(val)), host=True)
+        p = np.ctypeslib.as_array(ptr, shape=(n.value + 1,)).copy()
+        c = np.ctypeslib.as_array(col, shape=(nnz.value,)).copy() if nnz.value else np.zeros(0, np.int32)
+        v = np.ctypeslib.as_array(val, shape=(nnz.value,)).copy() if nnz.value else np.zeros(0)
+        return sp.csr_matrix((v, c, p), shape=(n.value, n.value))
+
+    def vec(self, which):
+        n = ctypes.c_int64()
+        d = _c_double_p()
+        _check(lib.bido_host_vec(self.h, which, ctypes.byref(n), ctypes.byref(d)), host=True)
+        return np.ctypeslib.as_array(d, shape=(n.value,)).copy()
+
+    def index(self, which):
+        n = ctypes.c_int64()
+        d = _c_i64_p()
+        _check(lib.bido_host_index(self.h, which, ctypes.byref(n), ctypes.byref(d)), host=True)
+        return np.ctypeslib.as_array(d, shape=(n.value,)).copy()
+
+    def factor_stats(self, which):
+        de, se, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        h, ms = ctypes.c_int(), ctypes.c_int()
+        _check(lib.bido_host_factor_stats(self.h, which, ctypes.byref(de), ctypes.byref(se),
+                                          ctypes.byref(nl), ctypes.byref(h), ctypes.byref(ms)),
+               host=True)
+        return dict(dense_entries=de.value, stored_entries=se.value, n_lowrank=nl.value,
+                    height=h.value, max_sep=ms.value)
+
+    def factor_apply(self, which, b):
+        b = _arr(b, np.float64)
+        x = np.zeros_like(b)
+        _check(lib.bido_host_factor_apply(self.h, which, b.ctypes.data_as(_c_double_p),
+                                          x.ctypes.data_as(_c_double_p)), host=True)
+        return x
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.bido_host_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,579 @@
+// Device context, PCG driver and the C ABI (include/bido.h).
+//
+// Step 2 of the resolution algorithm (Sec. 3.2) is solved by conjugate
+// gradient on Lambda X = Y, preconditioned by the block-LU preconditioner
+// of Def. 2: with P_1 ~ S_1 (grounded, hierarchical Cholesky) and
+// P_K ~ K_m = gamma M_H + S_m (Sec. 5.2), X = P_Lambda^-1 R is
+//     Z1 = P_1^-1 R1,  Z2 = P_K^-1 (R2 - S_i Pi Z1),
+//     X1 = Z1 - P_1^-1 Pi^T S_i Z2,  X2 = Z2.
+// Scalars, dot products and vector updates stay in FP64; in mixed mode only
+// the factors are read in FP32 and the outer iteration is flexible CG.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/bido.h"
+#include "launch.h"
+#include "setup.h"
+
+using namespace bido;
+
+namespace {
+
+thread_local std::string g_err;
+
+bido_status fail(bido_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(BIDO_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+hipError_t upload(T** dst, const T* src, size_t n) {
+    *dst = nullptr;
+    if (n == 0) return hipSuccess;
+    hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+int pow2_at_least(int n, int cap) {
+    int g = 1;
+    while (g < n && g < cap) g <<= 1;
+    return g;
+}
+
+// Device copy of one hierarchical Cholesky factor.
+struct FactorDev {
+    int64_t n = 0, ground = -1;
+    int height = 0;
+    TriNode* nodes = nullptr;
+    double* panel64 = nullptr;
+    float* panel32 = nullptr;
+    int2* ea = nullptr;
+    int64_t* bidx = nullptr;
+    double* upd = nullptr;
+    double* ytmp = nullptr;
+    TriItem* items = nullptr;
+    std::vector<TriLevel> levels;
+    int64_t panel_entries = 0;
+    int64_t dense_entries = 0;
+    int64_t meta_bytes = 0;
+    int max_nI = 0;
+
+    void release() {
+        hipFree(nodes); hipFree(panel64); hipFree(panel32); hipFree(ea); hipFree(bidx);
+        hipFree(upd); hipFree(ytmp); hipFree(items);
+        nodes = nullptr; panel64 = nullptr; panel32 = nullptr; ea = nullptr; bidx = nullptr;
+        upd = nullptr; ytmp = nullptr; items = nullptr;
+    }
+};
+
+struct CsrHostView {
+    static bido_status up(const Csr& a, CsrDev& d) {
+        d.n = a.n;
+        d.nnz = a.nnz();
+        HIP_OK(upload(&d.ptr, a.ptr.data(), a.ptr.size()));
+        HIP_OK(upload(&d.col, a.col.data(), a.col.size()));
+        HIP_OK(upload(&d.val, a.val.data(), a.val.size()));
+        return BIDO_OK;
+    }
+    static void release(CsrDev& d) {
+        hipFree(d.ptr); hipFree(d.col); hipFree(d.val);
+        d = CsrDev();
+    }
+};
+
+bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd) {
+    const NdTree& t = f.tree;
+    const int nn = (int)t.nodes.size();
+    fd.n = f.n;
+    fd.ground = f.ground;
+    fd.height = t.height;
+    std::vector<TriNode> nodes(nn);
+    int64_t poff = 0, boff = 0, uoff = 0, eoff = 0;
+    for (int id = 0; id < nn; ++id) {
+        const Front& fr = f.fronts[id];
+        TriNode& d = nodes[id];
+        d.off = fr.off;
+        d.nI = fr.nI;
+        d.nB = fr.nB;
+        d.panel = poff;
+        d.bidx = boff;
+        d.upd = uoff;
+        d.ea = eoff;
+        d.child[0] = t.nodes[id].child[0];
+        d.child[1] = t.nodes[id].child[1];
+        poff += (int64_t)fr.nI * (fr.nI + 1) / 2 + (int64_t)fr.nB * fr.nI;
+        boff += fr.nB;
+        uoff += fr.nB;
+        eoff += fr.nI + fr.nB;
+        fd.max_nI = std::max(fd.max_nI, fr.nI);
+    }
+    if (fd.max_nI > 8192)
+        return fail(BIDO_ERR_ARG, "separator of " + std::to_string(fd.max_nI) +
+                                      " vertices exceeds the 8192-entry LDS staging limit");
+    fd.panel_entries = poff;
+    fd.dense_entries = f.dense_entries();
+    std::vector<double> panel((size_t)poff);
+    std::vector<int64_t> bidx((size_t)std::max<int64_t>(boff, 1));
+    std::vector<int2> ea((size_t)std::max<int64_t>(eoff, 1), make_int2(-1, -1));
+    for (int id = 0; id < nn; ++id) {
+        const Front& fr = f.fronts[id];
+        const TriNode& d = nodes[id];
+        const int nI = fr.nI;
+        if (fr.compressed) {
+            // dense view of the compressed panel, rebuilt from its blocks
+            std::vector<double> P((size_t)(nI + fr.nB) * nI, 0.0);
+            for (const auto& b : fr.dense)
+                for (int r = 0; r < b.nr; ++r)
+                    for (int c = 0; c < (b.lower_tri ? r + 1 : b.nc); ++c)
+                        P[(size_t)(b.r0 + r) * nI + b.c0 + c] = b.D[(size_t)r * b.nc + c];
+            for (const auto& l : fr.lowrank)
+                for (int r = 0; r < l.nr; ++r)
+                    for (int c = 0; c < l.nc; ++c) {
+                        double s = 0.0;
+                        for (int k = 0; k < l.rank; ++k) s += l.U[(size_t)r * l.rank + k] * l.V[(size_t)c * l.rank + k];
+                        P[(size_t)(l.r0 + r) * nI + l.c0 + c] = s;
+                    }
+            int64_t o = d.panel;
+            for (int r = 0; r < nI + fr.nB; ++r) {
+                int len = r < nI ? r + 1 : nI;
+                for (int c = 0; c < len; ++c) panel[o++] = P[(size_t)r * nI + c];
+            }
+        } else {
+            int64_t o = d.panel;
+            for (int r = 0; r < nI + fr.nB; ++r) {
+                int len = r < nI ? r + 1 : nI;
+                for (int c = 0; c < len; ++c) panel[o++] = fr.P[(size_t)r * nI + c];
+            }
+        }
+        for (int r = 0; r < fr.nB; ++r) bidx[d.bidx + r] = fr.B[r];
+        const NdNode& nd = t.nodes[id];
+        for (int c = 0; c < 2; ++c) {
+            int ch = nd.child[c];
+            if (ch < 0) continue;
+            const Front& cf = f.fronts[ch];
+            for (int j = 0; j < cf.nB; ++j) {
+                int64_t g = cf.B[j];
+                int pos;
+                if (g < nd.end) pos = (int)(g - nd.begin);
+                else pos = nI + (int)(std::lower_bound(fr.B.begin(), fr.B.end(), g) - fr.B.begin());
+                int2& m = ea[d.ea + pos];
+                if (c == 0) m.x = j; else m.y = j;
+            }
+        }
+    }
+    // work items per level (tree height)
+    std::vector<std::vector<int>> by_h(t.height + 1);
+    for (int id = 0; id < nn; ++id) by_h[t.nodes[id].height].push_back(id);
+    std::vector<TriItem> items;
+    struct Span { size_t f0, nf, b0, nb; size_t lds; };
+    std::vector<Span> spans;
+    for (int h = 0; h <= t.height; ++h) {
+        Span sp{items.size(), 0, 0, 0, 0};
+        for (int id : by_h[h]) {
+            const Front& fr = f.fronts[id];
+            const int nI = fr.nI, nF = fr.nI + fr.nB;
+            if (nI == 0) continue;
+            const int G = pow2_at_least(std::min(nI, 64), 64);
+            int R = std::max(256 / G, std::min(nF, 16384 / std::max(nI, 1)));
+            for (int r0 = 0; r0 < nF; r0 += R) items.push_back({id, r0, std::min(R, nF - r0), G});
+            sp.lds = std::max(sp.lds, (size_t)nI * sizeof(double));
+        }
+        sp.nf = items.size() - sp.f0;
+        sp.b0 = items.size();
+        for (int id : by_h[h]) {
+            const Front& fr = f.fronts[id];
+            const int nI = fr.nI;
+            if (nI == 0) continue;
+            const int W = pow2_at_least(std::min(nI, 64), 64);
+            for (int c0 = 0; c0 < nI; c0 += W) items.push_back({id, c0, std::min(W, nI - c0), W});
+        }
+        sp.nb = items.size() - sp.b0;
+        spans.push_back(sp);
+    }
+    HIP_OK(upload(&fd.nodes, nodes.data(), nodes.size()));
+    HIP_OK(upload(&fd.panel64, panel.data(), panel.size()));
+    if (want32) {
+        std::vector<float> p32(panel.begin(), panel.end());
+        HIP_OK(upload(&fd.panel32, p32.data(), p32.size()));
+    }
+    HIP_OK(upload(&fd.ea, ea.data(), ea.size()));
+    HIP_OK(upload(&fd.bidx, bidx.data(), bidx.size()));
+    HIP_OK(upload(&fd.items, items.data(), items.size()));
+    HIP_OK(hipMalloc((void**)&fd.upd, std::max<int64_t>(uoff, 1) * sizeof(double)));
+    HIP_OK(hipMalloc((void**)&fd.ytmp, std::max<int64_t>(f.n, 1) * sizeof(double)));
+    fd.levels.clear();
+    for (const Span& sp : spans) {
+        TriLevel L;
+        L.fwd_items = fd.items + sp.f0;
+        L.n_items = (int)sp.nf;
+        L.bwd_items = fd.items + sp.b0;
+        L.n_bwd_items = (int)sp.nb;
+        L.lds_bytes = sp.lds;
+        fd.levels.push_back(L);
+    }
+    fd.meta_bytes = (int64_t)(nodes.size() * sizeof(TriNode) + bidx.size() * 8 + ea.size() * 8 +
+                              items.size() * sizeof(TriItem));
+    return BIDO_OK;
+}
+
+}  // namespace
+
+struct bido_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    HostSetup hs;
+    bido_params params{};
+    int64_t N = 0, NH = 0, n2 = 0;
+    int spmv_group = 8;
+    int precision = BIDO_PREC_FP64;
+    CsrDev lam, avu, auv;
+    FactorDev p1, pk;
+    double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *Y = nullptr;
+    double *tA = nullptr, *tB = nullptr, *tC = nullptr, *tD = nullptr, *r_old = nullptr;
+    double* sc = nullptr;
+    double* sc_host = nullptr;   // pinned
+    Reduce rd;
+    int64_t *u_pos = nullptr, *v_pos = nullptr;
+    double *m_int = nullptr, *mh_loc = nullptr, *stim_loc = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<int64_t> heart_ids;
+
+    ~bido_ctx() {
+        if (stream) hipStreamSynchronize(stream);
+        p1.release();
+        pk.release();
+        CsrHostView::release(lam);
+        CsrHostView::release(avu);
+        CsrHostView::release(auv);
+        for (double* b : {x, r, z, p, q, Y, tA, tB, tC, tD, r_old, sc, m_int, mh_loc, stim_loc}) hipFree(b);
+        hipFree(rd.partials);
+        hipFree(rd.counter);
+        hipFree(u_pos);
+        hipFree(v_pos);
+        if (sc_host) hipHostFree(sc_host);
+        if (ev0) hipEventDestroy(ev0);
+        if (ev1) hipEventDestroy(ev1);
+    }
+};
+
+namespace {
+
+template <typename T>
+void tri_solve(bido_ctx* c, const FactorDev& f, const T* panel, const double* in, double* out) {
+    hipStream_t s = c->stream;
+    for (int h = 0; h <= f.height; ++h)
+        launch_tri_fwd<T>(s, f.levels[h], f.nodes, panel, f.ea, in, f.ytmp, f.upd, f.ground);
+    for (int h = f.height; h >= 0; --h)
+        launch_tri_bwd<T>(s, f.levels[h], f.nodes, panel, f.bidx, f.ytmp, out);
+}
+
+void inner_solve(bido_ctx* c, const FactorDev& f, const double* in, double* out) {
+    if (c->precision == BIDO_PREC_MIXED && f.panel32)
+        tri_solve<float>(c, f, f.panel32, in, out);
+    else
+        tri_solve<double>(c, f, f.panel64, in, out);
+}
+
+// z = P_Lambda^-1 r  and  rho_new = r.z  (plus z.r_old for flexible CG)
+void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old) {
+    hipStream_t s = c->stream;
+    const int64_t N = c->N;
+    inner_solve(c, c->p1, r, c->tA);                                 // Z1 = P1^-1 R1
+    launch_spmv_csr(s, c->avu, c->spmv_group, c->tA, r + N, c->tB);  // R2 - S_i Pi Z1
+    inner_solve(c, c->pk, c->tB, z + N);                             // Z2 = PK^-1 (...)
+    launch_spmv_csr(s, c->auv, c->spmv_group, z + N, nullptr, c->tC);   // Pi^T S_i Z2
+    inner_solve(c, c->p1, c->tC, c->tD);                             // P1^-1 Pi^T S_i Z2
+    launch_combine_dot(s, N, c->n2, z, c->tA, c->tD, r, r_old, c->rd, c->sc);
+}
+
+bido_status read_scalars(bido_ctx* c) {
+    HIP_OK(hipMemcpyAsync(c->sc_host, c->sc, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return BIDO_OK;
+}
+
+// PCG on the internal vectors: x (initial guess in, solution out), Y.
+bido_status pcg(bido_ctx* c, double tol, bido_stats* st) {
+    hipStream_t s = c->stream;
+    const int64_t n = c->n2;
+    const bool flexible = c->precision == BIDO_PREC_MIXED;
+    double* r_old = flexible ? c->r_old : nullptr;
+    launch_spmv_lambda(s, c->lam, c->spmv_group, 1, c->x, c->Y, c->r, c->rd, c->sc);
+    bido_status e = read_scalars(c);
+    if (e) return e;
+    const double yy = c->sc_host[S_YY];
+    double rel = yy > 0 ? std::sqrt(c->sc_host[S_RR] / yy) : 0.0;
+    int it = 0;
+    bool conv = rel <= tol || yy == 0.0;
+    if (yy == 0.0) launch_fill(s, n, c->x, 0.0);
+    if (!conv) {
+        precond_apply(c, c->r, c->z, nullptr);
+        launch_p_update(s, n, c->z, c->p, c->sc, 1, 0);
+        for (it = 1; it <= c->params.max_iter; ++it) {
+            launch_copy_scalar(s, c->sc, S_RHO, S_RHO_NEW);
+            launch_spmv_lambda(s, c->lam, c->spmv_group, 0, c->p, nullptr, c->q, c->rd, c->sc);
+            launch_pcg_update(s, n, c->x, c->r, r_old, c->p, c->q, c->rd, c->sc);
+            if ((e = read_scalars(c))) return e;
+            const double pq = c->sc_host[S_PQ], rho = c->sc_host[S_RHO];
+            rel = std::sqrt(c->sc_host[S_RR] / yy);
+            if (!(pq > 0.0) || !(rho > 0.0) || !std::isfinite(rel)) {
+                if (st) { st->iterations = it; st->rel_residual = rel; st->converged = 0; }
+                return fail(BIDO_ERR_NOT_SPD, "CG breakdown (p.Ap = " + std::to_string(pq) +
+                                                  ", r.z = " + std::to_string(rho) + ")");
+            }
+            if (rel <= tol) { conv = true; break; }
+            precond_apply(c, c->r, c->z, r_old);
+            launch_p_update(s, n, c->z, c->p, c->sc, 0, flexible ? 1 : 0);
+        }
+        if (it > c->params.max_iter) it = c->params.max_iter;
+    }
+    if (st) {
+        st->iterations = it;
+        st->rel_residual = rel;
+        st->converged = conv ? 1 : 0;
+    }
+    return conv ? BIDO_OK : fail(BIDO_ERR_NOT_CONVERGED, "tolerance not reached within max_iter");
+}
+
+IonicConst ionic_consts(const bido_ctx* c) {
+    IonicConst k;
+    k.gamma = c->hs.gamma;
+    k.chi = c->params.chi;
+    k.cm = c->params.cm;
+    k.dt = c->params.dt;
+    k.dv = 100.0;
+    k.inv_dv = 1.0 / 100.0;
+    k.inv_tau_in = 1.0 / 0.3;
+    k.inv_tau_out = 1.0 / 6.0;
+    k.inv_tau_open = 1.0 / 120.0;
+    k.inv_tau_close = 1.0 / 150.0;
+    k.v_gate = 0.13;
+    return k;
+}
+
+// one time step on device arrays (no sync, no timing)
+bido_status step_once(bido_ctx* c, double* v, double* w, double* u, int64_t n, bido_stats* st) {
+    hipStream_t s = c->stream;
+    const int64_t N = c->N, NH = c->NH;
+    launch_scatter_in(s, N, c->u_pos, u, c->x);                        // X0 = (U^n, V^n)
+    const double on = (n >= c->hs.stim_n0 && n < c->hs.stim_n1) ? 1.0 : 0.0;
+    launch_ionic(s, NH, v, w, c->stim_loc, on, c->mh_loc, c->v_pos, c->Y + N, c->x + N,
+                 ionic_consts(c));                                     // Steps 1 and 3
+    launch_fill(s, N, c->Y, 0.0);                                      // Y1 = 0
+    bido_status e = pcg(c, c->params.tol, st);                         // Step 2
+    if (e && e != BIDO_ERR_NOT_CONVERGED) return e;
+    launch_dot_reduce(s, N, c->m_int, c->x, c->rd, c->sc + S_MU);      // (M U, 1)
+    launch_gather_out(s, N, c->u_pos, c->x, u, c->sc, S_MU, c->hs.msum);
+    launch_gather_out(s, NH, c->v_pos, c->x + N, v, c->sc, -1, 1.0);
+    return e;
+}
+
+bool dt_matches(const bido_ctx* c, double dt) {
+    return std::fabs(dt - c->params.dt) <= 1e-12 * std::fabs(c->params.dt);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* bido_last_error(void) { return g_err.c_str(); }
+
+void bido_default_params(bido_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->chi = 200.0;
+    p->cm = 1.0;
+    p->dt = 0.1;
+    p->eps_h = 1e-3;
+    p->eta = 2.0;
+    p->tol = 1e-10;
+    p->leaf = 64;
+    p->max_iter = 200;
+    p->precision = BIDO_PREC_FP64;
+    p->precond = BIDO_PRECOND_PLAIN;
+    p->ionic = 0;
+    p->n_threads = 0;
+}
+
+bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const bido_params* params,
+                        void* stream, bido_ctx** out) {
+    if (!out) return fail(BIDO_ERR_ARG, "out is null");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+        return fail(BIDO_ERR_DEVICE, "no HIP device available");
+    std::unique_ptr<bido_ctx> c(new bido_ctx());
+    std::string err;
+    if (!build_host(mesh, tissue, params, c->hs, err))
+        return fail(err.find("pivot") != std::string::npos ? BIDO_ERR_NOT_SPD : BIDO_ERR_ARG, err);
+    HostSetup& hs = c->hs;
+    c->params = *params;
+    c->precision = params->precision;
+    c->stream = (hipStream_t)stream;
+    HIP_OK(hipGetDevice(&c->device));
+    c->N = hs.A.N;
+    c->NH = hs.A.NH;
+    c->n2 = c->N + c->NH;
+    c->spmv_group = hs.A.dim == 2 ? 8 : 16;
+    c->heart_ids = hs.A.heart;
+    bido_status e;
+    if ((e = CsrHostView::up(hs.lam, c->lam))) return e;
+    if ((e = CsrHostView::up(hs.avu, c->avu))) return e;
+    if ((e = CsrHostView::up(hs.auv, c->auv))) return e;
+    if ((e = build_factor_dev(hs.p1, true, c->p1))) return e;
+    if ((e = build_factor_dev(hs.pk, true, c->pk))) return e;
+    const int64_t n2 = c->n2;
+    for (double** b : {&c->x, &c->r, &c->z, &c->p, &c->q, &c->Y, &c->r_old})
+        HIP_OK(hipMalloc((void**)b, n2 * sizeof(double)));
+    for (double** b : {&c->tA, &c->tC, &c->tD}) HIP_OK(hipMalloc((void**)b, c->N * sizeof(double)));
+    HIP_OK(hipMalloc((void**)&c->tB, std::max<int64_t>(c->NH, 1) * sizeof(double)));
+    HIP_OK(hipMalloc((void**)&c->sc, S_COUNT * sizeof(double)));
+    HIP_OK(hipMemset(c->sc, 0, S_COUNT * sizeof(double)));
+    HIP_OK(hipHostMalloc((void**)&c->sc_host, S_COUNT * sizeof(double), hipHostMallocDefault));
+    HIP_OK(hipMalloc((void**)&c->rd.partials, 2 * c->rd.max_blocks * sizeof(double)));
+    HIP_OK(hipMalloc((void**)&c->rd.counter, sizeof(unsigned)));
+    HIP_OK(hipMemset(c->rd.counter, 0, sizeof(unsigned)));
+    HIP_OK(upload(&c->u_pos, hs.u_pos.data(), hs.u_pos.size()));
+    HIP_OK(upload(&c->v_pos, hs.v_pos.data(), hs.v_pos.size()));
+    HIP_OK(upload(&c->m_int, hs.m_int.data(), hs.m_int.size()));
+    HIP_OK(upload(&c->mh_loc, hs.mh_loc.data(), hs.mh_loc.size()));
+    HIP_OK(upload(&c->stim_loc, hs.stim_loc.data(), hs.stim_loc.size()));
+    HIP_OK(hipEventCreate(&c->ev0));
+    HIP_OK(hipEventCreate(&c->ev1));
+    HIP_OK(hipDeviceSynchronize());
+    *out = c.release();
+    return BIDO_OK;
+}
+
+void bido_destroy(bido_ctx* ctx) { delete ctx; }
+
+bido_status bido_get_info(const bido_ctx* c, bido_info* info) {
+    if (!c || !info) return fail(BIDO_ERR_ARG, "null argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n_nodes = c->N;
+    info->n_heart = c->NH;
+    info->n_elems = 0;
+    info->nnz_lambda = c->lam.nnz;
+    // one Lambda product: values + columns + row pointers + x read + y write
+    info->bytes_lambda = c->lam.nnz * 12 + (c->n2 + 1) * 8 + c->n2 * 16;
+    const int64_t w = c->precision == BIDO_PREC_MIXED ? 4 : 8;
+    info->bytes_p1 = c->p1.panel_entries * w + c->p1.meta_bytes;
+    info->bytes_pk = c->pk.panel_entries * w + c->pk.meta_bytes;
+    info->dense_bytes_p1 = c->p1.dense_entries * 8;
+    info->dense_bytes_pk = c->pk.dense_entries * 8;
+    info->levels_p1 = c->p1.height + 1;
+    info->levels_pk = c->pk.height + 1;
+    info->lowrank_blocks = c->hs.p1.n_lowrank() + c->hs.pk.n_lowrank();
+    info->setup_seconds = c->hs.setup_seconds;
+    info->ground_index = (int)c->p1.ground;
+    return BIDO_OK;
+}
+
+bido_status bido_heart_nodes(const bido_ctx* c, const int64_t** ids, int64_t* n_h) {
+    if (!c || !ids || !n_h) return fail(BIDO_ERR_ARG, "null argument");
+    *ids = c->heart_ids.data();
+    *n_h = (int64_t)c->heart_ids.size();
+    return BIDO_OK;
+}
+
+bido_status bido_set_precision(bido_ctx* c, int precision) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    if (precision != BIDO_PREC_FP64 && precision != BIDO_PREC_MIXED)
+        return fail(BIDO_ERR_ARG, "bad precision");
+    c->precision = precision;
+    return BIDO_OK;
+}
+
+bido_status bido_set_solver(bido_ctx* c, double tol, int max_iter) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    if (tol > 0) c->params.tol = tol;
+    if (max_iter > 0) c->params.max_iter = max_iter;
+    return BIDO_OK;
+}
+
+bido_status bido_step(bido_ctx* c, double* v, double* w, double* u, double dt, int64_t n,
+                      bido_stats* st) {
+    return bido_run(c, v, w, u, dt, n, 1, st);
+}
+
+bido_status bido_run(bido_ctx* c, double* v, double* w, double* u, double dt, int64_t n0,
+                     int64_t n_steps, bido_stats* st) {
+    if (!c || !v || !w || !u || n_steps < 0) return fail(BIDO_ERR_ARG, "null argument");
+    if (!dt_matches(c, dt))
+        return fail(BIDO_ERR_DT_MISMATCH, "dt differs from the factored time step");
+    bido_stats local{};
+    auto t0 = std::chrono::steady_clock::now();
+    HIP_OK(hipEventRecord(c->ev0, c->stream));
+    bido_status e = BIDO_OK;
+    int64_t total = 0;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        e = step_once(c, v, w, u, n0 + k, &local);
+        total += local.iterations;
+        if (e) break;
+    }
+    HIP_OK(hipEventRecord(c->ev1, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    if (st) {
+        *st = local;
+        st->total_iterations = total;
+        st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    (void)ms;
+    return e;
+}
+
+bido_status bido_solve(bido_ctx* c, const double* rhs, double* x, double tol, bido_stats* st) {
+    if (!c || !rhs || !x) return fail(BIDO_ERR_ARG, "null argument");
+    hipStream_t s = c->stream;
+    const int64_t N = c->N, NH = c->NH;
+    auto t0 = std::chrono::steady_clock::now();
+    launch_scatter_in(s, N, c->u_pos, rhs, c->Y);
+    launch_scatter_in(s, NH, c->v_pos, rhs + N, c->Y + N);
+    launch_dot_reduce(s, N, c->Y, nullptr, c->rd, c->sc + S_Y1SUM);
+    launch_dot_reduce(s, c->n2, c->Y, c->Y, c->rd, c->sc + S_YY);
+    bido_status e = read_scalars(c);
+    if (e) return e;
+    const double y1sum = c->sc_host[S_Y1SUM], ynorm = std::sqrt(c->sc_host[S_YY]);
+    const double removed = std::fabs(y1sum) / std::sqrt((double)N);
+    if (removed > 1e-8 * ynorm)
+        return fail(BIDO_ERR_RANGE, "rhs not in the range of Lambda: its u part has a mean (Prop. 1)");
+    launch_shift(s, N, c->Y, c->sc, S_Y1SUM, (double)N);   // project Y1 on 1^perp
+    launch_scatter_in(s, N, c->u_pos, x, c->x);
+    launch_scatter_in(s, NH, c->v_pos, x + N, c->x + N);
+    bido_stats local{};
+    e = pcg(c, tol > 0 ? tol : c->params.tol, &local);
+    if (e && e != BIDO_ERR_NOT_CONVERGED) return e;
+    launch_dot_reduce(s, N, c->m_int, c->x, c->rd, c->sc + S_MU);
+    launch_gather_out(s, N, c->u_pos, c->x, x, c->sc, S_MU, c->hs.msum);
+    launch_gather_out(s, NH, c->v_pos, c->x + N, x + N, c->sc, -1, 1.0);
+    HIP_OK(hipStreamSynchronize(s));
+    if (st) {
+        *st = local;
+        st->range_removed = removed;
+        st->total_iterations = local.iterations;
+        st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return e;
+}
+
+}  // extern "C"

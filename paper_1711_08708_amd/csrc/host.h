@@ -1,0 +1,133 @@
+// Host-side set-up of the bidomain solver: P1 assembly, nested-dissection
+// ordering, multifrontal Cholesky and hierarchical (low-rank) compression of
+// the inner-solve factors.  Pure C++ (no HIP); compiled into libbido.so.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace bido {
+
+// Compressed sparse rows with int64 row pointers and int32 columns.
+struct Csr {
+    int64_t n = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    int64_t nnz() const { return (int64_t)col.size(); }
+};
+
+struct MeshIn {
+    int dim = 2;
+    int64_t n_nodes = 0, n_elems = 0;
+    const double* xyz = nullptr;
+    const int32_t* elems = nullptr;
+    const int8_t* region = nullptr;
+    const double* fibre = nullptr;
+    const double* region_sigma = nullptr;
+    int n_region_sigma = 0;
+    double sigma_i[3] = {0, 0, 0}, sigma_e[3] = {0, 0, 0};
+};
+
+// Matrices of Sec. 3.1 and Sec. 5.2 in the caller's numbering:
+// S1 (N x N, sigma_1 on Omega), Si and Sm (N_H x N_H on heart elements,
+// heart-local numbering = heart vertices in ascending global id),
+// lumped masses m (N) and mH (N_H).
+struct Assembled {
+    int dim = 2;
+    int64_t N = 0, NH = 0;
+    std::vector<int64_t> heart;       // heart-local -> global id
+    std::vector<int64_t> heart_loc;   // global -> heart-local or -1
+    Csr S1, Si, Sm;
+    std::vector<double> m, mH;
+};
+
+bool assemble(const MeshIn& in, Assembled& out, std::string& err);
+
+// ---------------------------------------------------------------------
+// Nested dissection (domain-decomposition clustering).
+// ---------------------------------------------------------------------
+struct NdNode {
+    int64_t begin = 0, end = 0;     // own index range [begin, end) (new order)
+    int64_t sub_begin = 0;          // first index of the subtree
+    int parent = -1;
+    int child[2] = {-1, -1};
+    int height = 0;                 // 0 for leaves
+    int depth = 0;                  // 0 for the root
+    int nchild() const { return (child[0] >= 0) + (child[1] >= 0); }
+};
+
+struct NdTree {
+    std::vector<NdNode> nodes;      // post-order (children before parents)
+    std::vector<int64_t> perm;      // new -> old
+    std::vector<int64_t> iperm;     // old -> new
+    int root = -1;
+    int height = 0;
+};
+
+// Build the tree for a symmetric pattern `g` (n x n) with coordinates
+// xyz (n x dim).  Leaves hold at most `leaf` vertices.
+void nested_dissection(const Csr& g, const double* xyz, int dim, int leaf,
+                       NdTree& t);
+
+// Symmetric permutation B = P A P^T with perm = new -> old.
+Csr permute(const Csr& a, const std::vector<int64_t>& perm,
+            const std::vector<int64_t>& iperm);
+
+// ---------------------------------------------------------------------
+// Multifrontal Cholesky on the nested-dissection tree.
+//
+// For every tree node t with own indices I_t and boundary B(t) (ancestor
+// indices coupled to the subtree of t), the factor is stored as the panel
+//     P_t = [ L_tt^{-1} ; L_Bt L_tt^{-1} ]     ((nI + nB) x nI)
+// so that the forward solve of L y = b is  [y_t; c_t] = P_t w_t  (c_t is the
+// contribution subtracted from the boundary) and the backward solve of
+// L^T x = y is  x_t = P_t^T [y_t; -x_B].
+// ---------------------------------------------------------------------
+struct LowRank {               // admissible block U V^T of a panel
+    int r0, nr, c0, nc, rank;
+    std::vector<double> U;     // nr x rank, row-major
+    std::vector<double> V;     // nc x rank, row-major
+};
+struct DenseBlk {              // inadmissible (or small) block of a panel
+    int r0, nr, c0, nc;
+    bool lower_tri;            // diagonal block of L^-1: only c <= r stored
+    std::vector<double> D;     // nr x nc row-major (full storage)
+};
+
+struct Front {
+    int node = -1;
+    int64_t off = 0;                 // first own index
+    int nI = 0, nB = 0;
+    std::vector<int64_t> B;          // boundary indices (sorted, new order)
+    std::vector<double> P;           // dense panel, (nI+nB) x nI row-major
+    bool compressed = false;
+    std::vector<DenseBlk> dense;     // hierarchical form (when compressed)
+    std::vector<LowRank> lowrank;
+};
+
+struct Factor {
+    int64_t n = 0;
+    int64_t ground = -1;             // grounded index (new order) or -1
+    NdTree tree;
+    std::vector<Front> fronts;       // indexed like tree.nodes
+    int64_t dense_entries() const;
+    int64_t stored_entries() const;  // after compression
+    int64_t n_lowrank() const;
+};
+
+// Factor the SPD matrix a (already in tree order).  If ground >= 0 the
+// row and column `ground` are replaced by the unit vector first.
+bool multifrontal(const Csr& a, Factor& f, int64_t ground, int n_threads,
+                  std::string& err);
+
+// Hierarchical compression of every panel at relative accuracy eps with
+// admissibility parameter eta, using the vertex coordinates (tree order).
+void compress(Factor& f, const double* xyz, int dim, double eps, double eta,
+              int n_threads);
+
+// Host application of the factor (test hook): x = (L L^T)^-1 b with the
+// grounded entry fixed to zero.  Uses the compressed form when present.
+void host_solve(const Factor& f, const double* b, double* x);
+
+}  // namespace bido

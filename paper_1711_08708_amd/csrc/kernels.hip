@@ -1,0 +1,478 @@
+// HIP kernels for gfx950 (CDNA4, 64-lane wavefronts).
+//
+//   tri_fwd / tri_bwd   level sweeps of the hierarchical-Cholesky solves
+//                       (inner solves P_1^-1, P_K^-1 of Def. 2, Sec. 5.3)
+//   spmv_*              Lambda products (Sec. 3.2, eq. (system)) and the
+//                       S_i Pi / Pi^T S_i products of the preconditioner
+//   pcg_*               FP64 CG recurrences with fused, deterministic dot
+//                       products (the last block reduces the partials)
+//   ionic_rhs           Steps 1 and 3 of the resolution algorithm
+//   mean_*              normalisation (M U, 1) = 0 of Prop. 1
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "launch.h"
+
+namespace bido {
+
+constexpr int BLOCK = 256;
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// Sum over the block (BLOCK threads); result valid in every thread.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / WAVE; ++i) s += sh[i];
+    return s;
+}
+
+// Store this block's partials; the last block to arrive sums all partials in
+// block order (deterministic) and writes them to out[0..K).
+template <int K>
+__device__ void finish_reduce(const double (&part)[K], double* partials, unsigned* counter,
+                              double* out, double* sh) {
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < K; ++k) partials[(size_t)k * gridDim.x + blockIdx.x] = part[k];
+        __threadfence();
+        unsigned t = atomicAdd(counter, 1u);
+        last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (unsigned b = threadIdx.x; b < gridDim.x; b += BLOCK)
+            s += partials[(size_t)k * gridDim.x + b];
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) out[k] = s;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// simple vector kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill(int64_t n, double* x, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        x[i] = v;
+}
+
+// dst[pos[i]] = src[i]
+__global__ void k_scatter_in(int64_t n, const int64_t* __restrict__ pos,
+                             const double* __restrict__ src, double* __restrict__ dst) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        dst[pos[i]] = src[i];
+}
+
+// dst[i] = src[pos[i]] - (shift ? *shift_num / shift_den : 0)
+__global__ void k_gather_out(int64_t n, const int64_t* __restrict__ pos,
+                             const double* __restrict__ src, double* __restrict__ dst,
+                             const double* __restrict__ sc, int shift_slot, double shift_den) {
+    const double s = shift_slot >= 0 ? sc[shift_slot] / shift_den : 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        dst[i] = src[pos[i]] - s;
+}
+
+// (M U, 1) for the normalisation, and optionally sum of a second vector
+__global__ void k_dot_reduce(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                             double* partials, unsigned* counter, double* out) {
+    __shared__ double sh[BLOCK / WAVE];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        s += b ? a[i] * b[i] : a[i];
+    s = block_sum(s, sh);
+    double part[1] = {s};
+    finish_reduce<1>(part, partials, counter, out, sh);
+}
+
+// x[i] -= sc[slot] / den   for i < n
+__global__ void k_shift(int64_t n, double* x, const double* sc, int slot, double den) {
+    const double s = sc[slot] / den;
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        x[i] -= s;
+}
+
+// ---------------------------------------------------------------------------
+// Steps 1 and 3 (Mitchell-Schaeffer), heart-local order in, internal out.
+// ---------------------------------------------------------------------------
+__global__ void k_ionic_rhs(int64_t nh, const double* __restrict__ v, double* __restrict__ h,
+                            const double* __restrict__ stim, double stim_on,
+                            const double* __restrict__ mh, const int64_t* __restrict__ pos,
+                            double* __restrict__ y2, double* __restrict__ x2, IonicConst c) {
+    for (int64_t k = blockIdx.x * (int64_t)BLOCK + threadIdx.x; k < nh; k += (int64_t)gridDim.x * BLOCK) {
+        const double V = v[k], hk = h[k];
+        const double vt = V * c.inv_dv;
+        const double iion = c.cm * c.dv * (-hk * vt * vt * (1.0 - vt) * c.inv_tau_in + vt * c.inv_tau_out);
+        const double ist = stim[k] * stim_on;
+        const int64_t p = pos[k];
+        y2[p] = mh[k] * (c.gamma * V - c.chi * (iion - ist));
+        x2[p] = V;
+        const double g = (vt < c.v_gate) ? (1.0 - hk) * c.inv_tau_open : -hk * c.inv_tau_close;
+        h[k] = hk + c.dt * g;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lambda products.  Rows handled by groups of G lanes.
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// mode 0: q = A p, partial p.q            (reduction slot S_PQ)
+// mode 1: r = y - A x, partials |r|^2, |y|^2 (slots S_RR, S_YY)
+template <int G, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_spmv_lambda(int64_t n, const int64_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ y,
+                                                       double* __restrict__ out, double* partials,
+                                                       unsigned* counter, double* sc) {
+    __shared__ double sh[BLOCK / WAVE];
+    const int lane = threadIdx.x % G;
+    const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
+    const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int64_t r = gid; r < n; r += ngroups) {
+        double s = 0.0;
+        for (int64_t p = ptr[r] + lane; p < ptr[r + 1]; p += G) s += val[p] * x[col[p]];
+        s = group_sum<G>(s);
+        if (lane == 0) {
+            if (MODE == 0) {
+                out[r] = s;
+                acc0 += s * x[r];
+            } else {
+                const double rv = y[r] - s;
+                out[r] = rv;
+                acc0 += rv * rv;
+                acc1 += y[r] * y[r];
+            }
+        }
+    }
+    acc0 = block_sum(acc0, sh);
+    if (MODE == 0) {
+        double part[1] = {acc0};
+        finish_reduce<1>(part, partials, counter, sc + S_PQ, sh);
+    } else {
+        acc1 = block_sum(acc1, sh);
+        double part[2] = {acc0, acc1};
+        finish_reduce<2>(part, partials, counter, sc + S_RR, sh);  // S_RR, S_YY adjacent
+    }
+}
+
+// y = b - A x  (b may be null: y = A x), rows of a CSR block
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_spmv_csr(int64_t n, const int64_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ val,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ b,
+                                                    double* __restrict__ y) {
+    const int lane = threadIdx.x % G;
+    const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
+    const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
+    for (int64_t r = gid; r < n; r += ngroups) {
+        double s = 0.0;
+        for (int64_t p = ptr[r] + lane; p < ptr[r + 1]; p += G) s += val[p] * x[col[p]];
+        s = group_sum<G>(s);
+        if (lane == 0) y[r] = b ? b[r] - s : s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// PCG vector recurrences
+// ---------------------------------------------------------------------------
+// rho <- rho_new (start of an iteration is marked by the caller)
+__global__ void k_copy_scalar(double* sc, int dst, int src) { sc[dst] = sc[src]; }
+
+// alpha = rho / pq ; x += alpha p ; r -= alpha q ; |r|^2
+__global__ __launch_bounds__(BLOCK) void k_pcg_update(int64_t n, double* __restrict__ x,
+                                                      double* __restrict__ r,
+                                                      double* __restrict__ r_old,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ q,
+                                                      double* partials, unsigned* counter,
+                                                      double* sc) {
+    __shared__ double sh[BLOCK / WAVE];
+    const double alpha = sc[S_RHO] / sc[S_PQ];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        x[i] += alpha * p[i];
+        if (r_old) r_old[i] = r[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    acc = block_sum(acc, sh);
+    double part[1] = {acc};
+    finish_reduce<1>(part, partials, counter, sc + S_RR, sh);
+}
+
+// z1 = a - b over the first n1 entries (z2 already in place); rho_new = r.z;
+// with flexible CG also z.r_old (slot S_ZR_OLD) when r_old is given.
+__global__ __launch_bounds__(BLOCK) void k_combine_dot(int64_t n1, int64_t n, double* __restrict__ z,
+                                                       const double* __restrict__ a,
+                                                       const double* __restrict__ b,
+                                                       const double* __restrict__ r,
+                                                       const double* __restrict__ r_old,
+                                                       double* partials, unsigned* counter,
+                                                       double* sc) {
+    __shared__ double sh[BLOCK / WAVE];
+    double acc = 0.0, acc2 = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        double zi;
+        if (i < n1) {
+            zi = a[i] - b[i];
+            z[i] = zi;
+        } else {
+            zi = z[i];
+        }
+        acc += r[i] * zi;
+        if (r_old) acc2 += r_old[i] * zi;
+    }
+    acc = block_sum(acc, sh);
+    if (r_old) {
+        acc2 = block_sum(acc2, sh);
+        double part[2] = {acc, acc2};
+        finish_reduce<2>(part, partials, counter, sc + S_RHO_NEW, sh);  // S_RHO_NEW, S_ZR_OLD
+    } else {
+        double part[1] = {acc};
+        finish_reduce<1>(part, partials, counter, sc + S_RHO_NEW, sh);
+    }
+}
+
+// beta = rho_new / rho (or from flexible-CG slots), p = z + beta p
+__global__ void k_p_update(int64_t n, const double* __restrict__ z, double* __restrict__ p,
+                           const double* __restrict__ sc, int first, int flexible) {
+    double beta = 0.0;
+    if (!first) {
+        if (flexible) {
+            // Polak-Ribiere form: beta = (z.r - z.r_old) / rho_old
+            beta = (sc[S_RHO_NEW] - sc[S_ZR_OLD]) / sc[S_RHO];
+        } else {
+            beta = sc[S_RHO_NEW] / sc[S_RHO];
+        }
+    }
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        p[i] = z[i] + beta * p[i];
+}
+
+// ---------------------------------------------------------------------------
+// Hierarchical-Cholesky level sweeps
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t panel_row_off(int64_t r, int64_t nI) {
+    return r < nI ? r * (r + 1) / 2 : nI * (nI + 1) / 2 + (r - nI) * nI;
+}
+
+// Forward sweep of one level.  For node t: w_t = b_t - (children's updates at
+// I_t); rows [start, start+count) of P_t w_t go to y_t (own rows) or to the
+// update vector c_t (boundary rows, plus the children's updates there).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_tri_fwd(const TriNode* __restrict__ nodes,
+                                                   const TriItem* __restrict__ items,
+                                                   const T* __restrict__ panel,
+                                                   const int2* __restrict__ ea,
+                                                   const double* __restrict__ b,
+                                                   double* __restrict__ y,
+                                                   double* __restrict__ upd, int64_t ground) {
+    extern __shared__ double w[];
+    const TriItem it = items[blockIdx.x];
+    const TriNode nd = nodes[it.node];
+    const int nI = nd.nI;
+    const int64_t u0 = nd.child[0] >= 0 ? nodes[nd.child[0]].upd : 0;
+    const int64_t u1 = nd.child[1] >= 0 ? nodes[nd.child[1]].upd : 0;
+    const int rmax = min(it.start + it.count, nI);   // own rows need w[0..rmax)
+    const int wlen = it.start + it.count > nI ? nI : rmax;
+    for (int i = threadIdx.x; i < wlen; i += BLOCK) {
+        double s = b[nd.off + i];
+        const int2 m = ea[nd.ea + i];
+        if (m.x >= 0) s -= upd[u0 + m.x];
+        if (m.y >= 0) s -= upd[u1 + m.y];
+        if (nd.off + i == ground) s = 0.0;
+        w[i] = s;
+    }
+    __syncthreads();
+    const int G = it.group;
+    const int lane = threadIdx.x % G;
+    const int grp = threadIdx.x / G;
+    const int ngrp = BLOCK / G;
+    const T* P = panel + nd.panel;
+    for (int r = it.start + grp; r < it.start + it.count; r += ngrp) {
+        const int len = r < nI ? r + 1 : nI;
+        const T* row = P + panel_row_off(r, nI);
+        double s = 0.0;
+        for (int c = lane; c < len; c += G) s += (double)row[c] * w[c];
+        for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
+        if (lane == 0) {
+            if (r < nI) {
+                y[nd.off + r] = s;
+            } else {
+                const int2 m = ea[nd.ea + r];
+                if (m.x >= 0) s += upd[u0 + m.x];
+                if (m.y >= 0) s += upd[u1 + m.y];
+                upd[nd.upd + (r - nI)] = s;
+            }
+        }
+    }
+}
+
+// Backward sweep of one level: x_t[c] = sum_r P_t[r][c] z[r] with
+// z = [y_t ; -x_B], for the columns [start, start+count) (count <= 64).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_tri_bwd(const TriNode* __restrict__ nodes,
+                                                   const TriItem* __restrict__ items,
+                                                   const T* __restrict__ panel,
+                                                   const int64_t* __restrict__ bidx,
+                                                   const double* __restrict__ y,
+                                                   double* __restrict__ x) {
+    __shared__ double red[BLOCK];
+    const TriItem it = items[blockIdx.x];
+    const TriNode nd = nodes[it.node];
+    const int nI = nd.nI, nF = nd.nI + nd.nB;
+    const int W = it.group;                 // columns per row step (pow2 <= 64)
+    const int cl = threadIdx.x % W;
+    const int sub = threadIdx.x / W;        // row offset within a step
+    const int nsub = BLOCK / W;
+    const int c = it.start + cl;
+    const bool valid = cl < it.count;
+    const T* P = panel + nd.panel;
+    double acc = 0.0;
+    for (int r = it.start + sub; r < nF; r += nsub) {
+        double zr;
+        if (r < nI) zr = y[nd.off + r];
+        else zr = -x[bidx[nd.bidx + (r - nI)]];
+        if (valid && (r >= nI || c <= r)) acc += (double)P[panel_row_off(r, nI) + c] * zr;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < W && valid) {
+        double s = 0.0;
+        for (int k = 0; k < nsub; ++k) s += red[k * W + threadIdx.x];
+        x[nd.off + c] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+static inline unsigned grid_for(int64_t n, int64_t per_block = BLOCK, unsigned cap = 2048) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+void launch_fill(hipStream_t s, int64_t n, double* x, double v) {
+    if (n <= 0) return;
+    k_fill<<<grid_for(n), BLOCK, 0, s>>>(n, x, v);
+}
+void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst) {
+    if (n <= 0) return;
+    k_scatter_in<<<grid_for(n), BLOCK, 0, s>>>(n, pos, src, dst);
+}
+void launch_gather_out(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst,
+                       const double* sc, int shift_slot, double shift_den) {
+    if (n <= 0) return;
+    k_gather_out<<<grid_for(n), BLOCK, 0, s>>>(n, pos, src, dst, sc, shift_slot, shift_den);
+}
+void launch_dot_reduce(hipStream_t s, int64_t n, const double* a, const double* b, Reduce rd, double* out) {
+    k_dot_reduce<<<grid_for(n, BLOCK * 4, rd.max_blocks), BLOCK, 0, s>>>(n, a, b, rd.partials, rd.counter, out);
+}
+void launch_shift(hipStream_t s, int64_t n, double* x, const double* sc, int slot, double den) {
+    if (n <= 0) return;
+    k_shift<<<grid_for(n), BLOCK, 0, s>>>(n, x, sc, slot, den);
+}
+void launch_ionic(hipStream_t s, int64_t nh, const double* v, double* h, const double* stim,
+                  double stim_on, const double* mh, const int64_t* pos, double* y2, double* x2,
+                  const IonicConst& c) {
+    if (nh <= 0) return;
+    k_ionic_rhs<<<grid_for(nh), BLOCK, 0, s>>>(nh, v, h, stim, stim_on, mh, pos, y2, x2, c);
+}
+
+void launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode, const double* x,
+                        const double* y, double* out, Reduce rd, double* sc) {
+    const unsigned g = grid_for(A.n * group, BLOCK * 2, rd.max_blocks);
+#define BIDO_SPMV_CASE(G)                                                                       \
+    if (group == G) {                                                                           \
+        if (mode == 0)                                                                          \
+            k_spmv_lambda<G, 0><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, y, out,        \
+                                                     rd.partials, rd.counter, sc);              \
+        else                                                                                    \
+            k_spmv_lambda<G, 1><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, y, out,        \
+                                                     rd.partials, rd.counter, sc);              \
+        return;                                                                                 \
+    }
+    BIDO_SPMV_CASE(4) BIDO_SPMV_CASE(8) BIDO_SPMV_CASE(16) BIDO_SPMV_CASE(32)
+#undef BIDO_SPMV_CASE
+}
+
+void launch_spmv_csr(hipStream_t s, const CsrDev& A, int group, const double* x, const double* b,
+                     double* y) {
+    if (A.n <= 0) return;
+    const unsigned g = grid_for(A.n * group, BLOCK * 2, 4096);
+    if (group == 4) k_spmv_csr<4><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, b, y);
+    else if (group == 8) k_spmv_csr<8><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, b, y);
+    else if (group == 16) k_spmv_csr<16><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, b, y);
+    else k_spmv_csr<32><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, b, y);
+}
+
+void launch_copy_scalar(hipStream_t s, double* sc, int dst, int src) {
+    k_copy_scalar<<<1, 1, 0, s>>>(sc, dst, src);
+}
+void launch_pcg_update(hipStream_t s, int64_t n, double* x, double* r, double* r_old, const double* p,
+                       const double* q, Reduce rd, double* sc) {
+    k_pcg_update<<<grid_for(n, BLOCK * 4, rd.max_blocks), BLOCK, 0, s>>>(n, x, r, r_old, p, q,
+                                                                          rd.partials, rd.counter, sc);
+}
+void launch_combine_dot(hipStream_t s, int64_t n1, int64_t n, double* z, const double* a, const double* b,
+                        const double* r, const double* r_old, Reduce rd, double* sc) {
+    k_combine_dot<<<grid_for(n, BLOCK * 4, rd.max_blocks), BLOCK, 0, s>>>(n1, n, z, a, b, r, r_old,
+                                                                           rd.partials, rd.counter, sc);
+}
+void launch_p_update(hipStream_t s, int64_t n, const double* z, double* p, const double* sc, int first,
+                     int flexible) {
+    k_p_update<<<grid_for(n), BLOCK, 0, s>>>(n, z, p, sc, first, flexible);
+}
+
+template <typename T>
+void launch_tri_fwd(hipStream_t s, const TriLevel& L, const TriNode* nodes, const T* panel,
+                    const int2* ea, const double* b, double* y, double* upd, int64_t ground) {
+    if (L.n_items == 0) return;
+    k_tri_fwd<T><<<L.n_items, BLOCK, L.lds_bytes, s>>>(nodes, L.fwd_items, panel, ea, b, y, upd, ground);
+}
+template <typename T>
+void launch_tri_bwd(hipStream_t s, const TriLevel& L, const TriNode* nodes, const T* panel,
+                    const int64_t* bidx, const double* y, double* x) {
+    if (L.n_bwd_items == 0) return;
+    k_tri_bwd<T><<<L.n_bwd_items, BLOCK, 0, s>>>(nodes, L.bwd_items, panel, bidx, y, x);
+}
+template void launch_tri_fwd<double>(hipStream_t, const TriLevel&, const TriNode*, const double*,
+                                     const int2*, const double*, double*, double*, int64_t);
+template void launch_tri_fwd<float>(hipStream_t, const TriLevel&, const TriNode*, const float*,
+                                    const int2*, const double*, double*, double*, int64_t);
+template void launch_tri_bwd<double>(hipStream_t, const TriLevel&, const TriNode*, const double*,
+                                     const int64_t*, const double*, double*);
+template void launch_tri_bwd<float>(hipStream_t, const TriLevel&, const TriNode*, const float*,
+                                    const int64_t*, const double*, double*);
+
+}  // namespace bido

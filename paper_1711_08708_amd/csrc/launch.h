@@ -1,0 +1,67 @@
+// Host-side launch wrappers of the HIP kernels (implemented in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace bido {
+
+struct CsrDev {
+    int64_t n = 0;
+    int64_t nnz = 0;
+    int64_t* ptr = nullptr;
+    int32_t* col = nullptr;
+    double* val = nullptr;
+};
+
+// partial-sum scratch of the fused reductions (last block reduces)
+struct Reduce {
+    double* partials = nullptr;   // 2 * max_blocks doubles
+    unsigned* counter = nullptr;
+    unsigned max_blocks = 2048;
+};
+
+struct IonicConst {
+    double gamma, chi, cm, dt;
+    double dv, inv_dv, inv_tau_in, inv_tau_out, inv_tau_open, inv_tau_close, v_gate;
+};
+
+// One level (tree height) of a factor: work items of both sweeps.
+struct TriLevel {
+    TriItem* fwd_items = nullptr;   // device
+    int n_items = 0;
+    TriItem* bwd_items = nullptr;   // device
+    int n_bwd_items = 0;
+    size_t lds_bytes = 0;           // forward: max nI * 8
+};
+
+void launch_fill(hipStream_t s, int64_t n, double* x, double v);
+void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst);
+void launch_gather_out(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst,
+                       const double* sc, int shift_slot, double shift_den);
+void launch_dot_reduce(hipStream_t s, int64_t n, const double* a, const double* b, Reduce rd, double* out);
+void launch_shift(hipStream_t s, int64_t n, double* x, const double* sc, int slot, double den);
+void launch_ionic(hipStream_t s, int64_t nh, const double* v, double* h, const double* stim,
+                  double stim_on, const double* mh, const int64_t* pos, double* y2, double* x2,
+                  const IonicConst& c);
+void launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode, const double* x,
+                        const double* y, double* out, Reduce rd, double* sc);
+void launch_spmv_csr(hipStream_t s, const CsrDev& A, int group, const double* x, const double* b,
+                     double* y);
+void launch_copy_scalar(hipStream_t s, double* sc, int dst, int src);
+void launch_pcg_update(hipStream_t s, int64_t n, double* x, double* r, double* r_old, const double* p,
+                       const double* q, Reduce rd, double* sc);
+void launch_combine_dot(hipStream_t s, int64_t n1, int64_t n, double* z, const double* a, const double* b,
+                        const double* r, const double* r_old, Reduce rd, double* sc);
+void launch_p_update(hipStream_t s, int64_t n, const double* z, double* p, const double* sc, int first,
+                     int flexible);
+
+template <typename T>
+void launch_tri_fwd(hipStream_t s, const TriLevel& L, const TriNode* nodes, const T* panel,
+                    const int2* ea, const double* b, double* y, double* upd, int64_t ground);
+template <typename T>
+void launch_tri_bwd(hipStream_t s, const TriLevel& L, const TriNode* nodes, const T* panel,
+                    const int64_t* bidx, const double* y, double* x);
+
+}  // namespace bido

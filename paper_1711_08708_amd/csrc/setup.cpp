@@ -1,0 +1,169 @@
+// Host set-up (no HIP): assembly (Sec. 3.1), orderings, the system matrix
+// Lambda (Sec. 3.2) in the internal order, and the inner-solve factors of
+// the block-LU preconditioner (Def. 2 with K ~ K_m, Sec. 5.2-5.3).
+#include "setup.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace bido {
+namespace {
+
+Csr add_diag(const Csr& a, const std::vector<double>& d, double scale) {
+    Csr b = a;
+    for (int64_t r = 0; r < a.n; ++r) {
+        bool found = false;
+        for (int64_t p = a.ptr[r]; p < a.ptr[r + 1]; ++p)
+            if (a.col[p] == r) { b.val[p] += scale * d[r]; found = true; }
+        if (!found) { b.n = -1; return b; }   // P1 matrices always store the diagonal
+    }
+    return b;
+}
+
+}  // namespace
+
+bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_params* params,
+                HostSetup& hs, std::string& err) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!mesh || !tissue || !params) { err = "null argument"; return false; }
+    const bido_params& P = *params;
+    if (!(P.chi > 0) || !(P.cm > 0) || !(P.dt > 0)) { err = "chi, cm and dt must be > 0"; return false; }
+    if (P.eps_h < 0 || P.leaf < 1 || P.max_iter < 1 || !(P.tol > 0)) { err = "bad solver parameters"; return false; }
+    if (P.ionic != 0) { err = "only the Mitchell-Schaeffer model (ionic = 0) is built in"; return false; }
+    if (P.precision != BIDO_PREC_FP64 && P.precision != BIDO_PREC_MIXED) { err = "bad precision"; return false; }
+    if (P.precond != BIDO_PRECOND_PLAIN && P.precond != BIDO_PRECOND_LEARNED) { err = "bad precond"; return false; }
+#ifdef _OPENMP
+    if (P.n_threads > 0) omp_set_num_threads(P.n_threads);
+#endif
+    hs.params = P;
+    MeshIn in;
+    in.dim = mesh->dim;
+    in.n_nodes = mesh->n_nodes;
+    in.n_elems = mesh->n_elems;
+    in.xyz = mesh->xyz;
+    in.elems = mesh->elems;
+    in.region = mesh->region;
+    in.fibre = tissue->fibre;
+    in.region_sigma = tissue->region_sigma;
+    in.n_region_sigma = tissue->n_region_sigma;
+    for (int i = 0; i < 3; ++i) { in.sigma_i[i] = tissue->sigma_i[i]; in.sigma_e[i] = tissue->sigma_e[i]; }
+    if (!assemble(in, hs.A, err)) return false;
+    const Assembled& A = hs.A;
+    const int64_t N = A.N, NH = A.NH;
+    const int d = A.dim;
+    hs.gamma = P.chi * P.cm / P.dt;
+
+    // orderings: nested dissection of S_1 (u) and of K_m (v)
+    nested_dissection(A.S1, mesh->xyz, d, P.leaf, hs.p1.tree);
+    std::vector<double> xyz_h((size_t)NH * d);
+    for (int64_t k = 0; k < NH; ++k)
+        for (int a = 0; a < d; ++a) xyz_h[k * d + a] = mesh->xyz[A.heart[k] * d + a];
+    nested_dissection(A.Si, xyz_h.data(), d, P.leaf, hs.pk.tree);
+    const NdTree& t1 = hs.p1.tree;
+    const NdTree& tk = hs.pk.tree;
+    hs.u_pos = t1.iperm;
+    hs.v_pos = tk.iperm;
+
+    // inner-solve matrices: grounded S_1 and K_m = gamma M_H + S_m
+    Csr S1p = permute(A.S1, t1.perm, t1.iperm);
+    Csr Km = add_diag(A.Sm, A.mH, hs.gamma);
+    if (Km.n < 0) { err = "missing diagonal in S_m"; return false; }
+    Csr Kmp = permute(Km, tk.perm, tk.iperm);
+    const int nth = P.n_threads;
+    if (!multifrontal(S1p, hs.p1, N - 1, nth, err)) { err = "P_1: " + err; return false; }
+    if (!multifrontal(Kmp, hs.pk, -1, nth, err)) { err = "P_K: " + err; return false; }
+    if (P.eps_h > 0.0) {
+        std::vector<double> x1((size_t)N * d), xk((size_t)NH * d);
+        for (int64_t p = 0; p < N; ++p)
+            for (int a = 0; a < d; ++a) x1[p * d + a] = mesh->xyz[t1.perm[p] * d + a];
+        for (int64_t p = 0; p < NH; ++p)
+            for (int a = 0; a < d; ++a) xk[p * d + a] = xyz_h[tk.perm[p] * d + a];
+        compress(hs.p1, x1.data(), d, P.eps_h, P.eta, nth);
+        compress(hs.pk, xk.data(), d, P.eps_h, P.eta, nth);
+    }
+
+    // coupling blocks S_i Pi and Pi^T S_i in internal numbering
+    const Csr& Si = A.Si;
+    hs.avu.n = NH;
+    hs.avu.ptr.assign(NH + 1, 0);
+    for (int64_t l = 0; l < NH; ++l) {
+        int64_t k = tk.perm[l];
+        hs.avu.ptr[l + 1] = hs.avu.ptr[l] + (Si.ptr[k + 1] - Si.ptr[k]);
+    }
+    hs.avu.col.resize(hs.avu.ptr[NH]);
+    hs.avu.val.resize(hs.avu.ptr[NH]);
+    for (int64_t l = 0; l < NH; ++l) {
+        int64_t k = tk.perm[l], base = hs.avu.ptr[l];
+        std::vector<std::pair<int32_t, double>> row;
+        for (int64_t p = Si.ptr[k]; p < Si.ptr[k + 1]; ++p)
+            row.emplace_back((int32_t)hs.u_pos[A.heart[Si.col[p]]], Si.val[p]);
+        std::sort(row.begin(), row.end());
+        for (size_t q = 0; q < row.size(); ++q) { hs.avu.col[base + q] = row[q].first; hs.avu.val[base + q] = row[q].second; }
+    }
+    hs.auv.n = N;
+    hs.auv.ptr.assign(N + 1, 0);
+    for (int64_t p = 0; p < N; ++p) {
+        int64_t g = t1.perm[p], k = A.heart_loc[g];
+        hs.auv.ptr[p + 1] = hs.auv.ptr[p] + (k >= 0 ? Si.ptr[k + 1] - Si.ptr[k] : 0);
+    }
+    hs.auv.col.resize(hs.auv.ptr[N]);
+    hs.auv.val.resize(hs.auv.ptr[N]);
+    for (int64_t p = 0; p < N; ++p) {
+        int64_t g = t1.perm[p], k = A.heart_loc[g];
+        if (k < 0) continue;
+        std::vector<std::pair<int32_t, double>> row;
+        for (int64_t q = Si.ptr[k]; q < Si.ptr[k + 1]; ++q)
+            row.emplace_back((int32_t)hs.v_pos[Si.col[q]], Si.val[q]);
+        std::sort(row.begin(), row.end());
+        int64_t base = hs.auv.ptr[p];
+        for (size_t q = 0; q < row.size(); ++q) { hs.auv.col[base + q] = row[q].first; hs.auv.val[base + q] = row[q].second; }
+    }
+
+    // Lambda = [[S_1, Pi^T S_i], [S_i Pi, gamma M_H + S_i]] in internal order
+    Csr Sip = permute(Si, tk.perm, tk.iperm);
+    const int64_t n2 = N + NH;
+    Csr& L = hs.lam;
+    L.n = n2;
+    L.ptr.assign(n2 + 1, 0);
+    for (int64_t p = 0; p < N; ++p)
+        L.ptr[p + 1] = L.ptr[p] + (S1p.ptr[p + 1] - S1p.ptr[p]) + (hs.auv.ptr[p + 1] - hs.auv.ptr[p]);
+    for (int64_t l = 0; l < NH; ++l)
+        L.ptr[N + l + 1] = L.ptr[N + l] + (hs.avu.ptr[l + 1] - hs.avu.ptr[l]) + (Sip.ptr[l + 1] - Sip.ptr[l]);
+    L.col.resize(L.ptr[n2]);
+    L.val.resize(L.ptr[n2]);
+    for (int64_t p = 0; p < N; ++p) {
+        int64_t o = L.ptr[p];
+        for (int64_t q = S1p.ptr[p]; q < S1p.ptr[p + 1]; ++q) { L.col[o] = S1p.col[q]; L.val[o++] = S1p.val[q]; }
+        for (int64_t q = hs.auv.ptr[p]; q < hs.auv.ptr[p + 1]; ++q) { L.col[o] = (int32_t)(N + hs.auv.col[q]); L.val[o++] = hs.auv.val[q]; }
+    }
+    for (int64_t l = 0; l < NH; ++l) {
+        int64_t o = L.ptr[N + l];
+        int64_t k = tk.perm[l];
+        for (int64_t q = hs.avu.ptr[l]; q < hs.avu.ptr[l + 1]; ++q) { L.col[o] = hs.avu.col[q]; L.val[o++] = hs.avu.val[q]; }
+        for (int64_t q = Sip.ptr[l]; q < Sip.ptr[l + 1]; ++q) {
+            L.col[o] = (int32_t)(N + Sip.col[q]);
+            L.val[o++] = Sip.val[q] + (Sip.col[q] == l ? hs.gamma * A.mH[k] : 0.0);
+        }
+    }
+
+    hs.m_int.resize(N);
+    for (int64_t p = 0; p < N; ++p) hs.m_int[p] = A.m[t1.perm[p]];
+    hs.msum = 0.0;
+    for (double v : A.m) hs.msum += v;
+    hs.mh_loc = A.mH;
+    hs.stim_loc.assign(NH, 0.0);
+    if (tissue->stim_mask)
+        for (int64_t k = 0; k < NH; ++k)
+            if (tissue->stim_mask[A.heart[k]]) hs.stim_loc[k] = tissue->stim_amp;
+    hs.stim_n0 = std::llround(tissue->stim_t0 / P.dt);
+    hs.stim_n1 = std::llround(tissue->stim_t1 / P.dt);
+    hs.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return true;
+}
+
+}  // namespace bido

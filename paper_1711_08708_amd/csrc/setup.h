@@ -1,0 +1,34 @@
+// Host set-up of a solver context: everything bido_create computes before
+// the upload to the device (also reachable without a GPU through the
+// bido_host_* checks).
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/bido.h"
+#include "host.h"
+
+namespace bido {
+
+struct HostSetup {
+    bido_params params{};
+    Assembled A;
+    Factor p1, pk;                 // factors of the grounded S_1 and of K_m
+    Csr lam;                       // Lambda, internal order [u (ND of S_1); v (ND of K_m)]
+    Csr avu;                       // S_i Pi: N_H rows (v order), u columns
+    Csr auv;                       // Pi^T S_i: N rows (u order), v columns
+    std::vector<int64_t> u_pos;    // global id   -> internal u index
+    std::vector<int64_t> v_pos;    // heart-local -> internal v index (0-based)
+    std::vector<double> m_int;     // lumped M in internal u order
+    std::vector<double> mh_loc;    // lumped M_H, heart-local order
+    std::vector<double> stim_loc;  // stimulus amplitude per heart vertex (heart-local)
+    int64_t stim_n0 = 0, stim_n1 = 0;
+    double gamma = 0.0;
+    double msum = 0.0;
+    double setup_seconds = 0.0;
+};
+
+bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_params* params,
+                HostSetup& hs, std::string& err);
+
+}  // namespace bido

@@ -1,0 +1,133 @@
+"""CPU checks of the C ABI library: it loads, exports every declared symbol,
+and its host set-up (assembly, orderings, factors) agrees with the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as w
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in ("bido.h", "bido_host.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"\b(bido_\w+)\s*\(", txt):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1711_08708_amd as B
+    names = _declared_functions()
+    assert "bido_create" in names and "bido_solve" in names
+    missing = [n for n in names if not hasattr(B.lib, n)]
+    assert not missing, missing
+    for n in names:
+        assert n in B.ABI, f"binding does not wrap {n}"
+
+
+def test_struct_sizes_match_header():
+    import paper_1711_08708_amd as B
+    # bido_params: 6 doubles + 6 ints; bido_stats: 2 ints, 2 doubles, int, double, int64
+    assert ctypes.sizeof(B.Params) == 6 * 8 + 6 * 4
+    assert ctypes.sizeof(B.Stats) == 48
+    p = B.default_params()
+    assert p.leaf == 64 and p.max_iter == 200 and p.tol == 1e-10
+
+
+def test_create_without_gpu_reports_device_error():
+    import torch
+    import paper_1711_08708_amd as B
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    cfg = w.square2d(n=6)
+    mesh, tissue, keep = B._marshal(cfg)
+    p = B.make_params(cfg)
+    ctx = ctypes.c_void_p()
+    code = B.lib.bido_create(ctypes.byref(mesh), ctypes.byref(tissue), ctypes.byref(p), None,
+                             ctypes.byref(ctx))
+    assert code == -2 and not ctx.value
+
+
+@pytest.mark.parametrize("mk", [lambda: w.square2d(n=20), lambda: w.slab3d(n=5),
+                                lambda: w.thorax2d(n_target=4000, seed=9)])
+def test_host_assembly_matches_oracle(mk):
+    import paper_1711_08708_amd as B
+    from oracle import fem
+    cfg = mk()
+    hs = B.HostSetup(cfg, eps_h=0.0)
+    A = fem.assemble(cfg)
+    for which, ref in ((B.MAT_S1, A["S1"]), (B.MAT_SI, A["Si"]), (B.MAT_SM, A["Sm"])):
+        M = hs.csr(which)
+        assert abs(M - ref).max() <= 1e-13 * abs(ref).max()
+    np.testing.assert_allclose(hs.vec(B.VEC_M), A["m"], rtol=1e-13)
+    np.testing.assert_allclose(hs.vec(B.VEC_MH), A["mH"], rtol=1e-13)
+    assert np.array_equal(hs.index(B.IDX_HEART), A["hn"])
+
+
+def test_host_lambda_is_the_oracle_lambda_reordered():
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd
+    cfg = w.square2d(n=16)
+    hs = B.HostSetup(cfg, eps_h=0.0)
+    s = bd.System(cfg)
+    upos, vpos = hs.index(B.IDX_UPOS), hs.index(B.IDX_VPOS)
+    N, NH = s.N, s.NH
+    assert sorted(upos.tolist()) == list(range(N)) and sorted(vpos.tolist()) == list(range(NH))
+    o2i = np.concatenate([upos[s.perm], N + vpos])
+    P = np.empty(N + NH, dtype=np.int64)
+    P[o2i] = np.arange(N + NH)
+    L = hs.csr(B.MAT_LAMBDA)
+    Lo = s.Lam[P][:, P]
+    assert abs(L - Lo).max() <= 1e-13 * abs(Lo).max()
+
+
+@pytest.mark.parametrize("mk", [lambda: w.square2d(n=30), lambda: w.slab3d(n=7),
+                                lambda: w.thorax2d(n_target=6000, seed=4)])
+def test_exact_factors_invert_the_inner_matrices(mk):
+    """With eps = 0 the factors are exact Cholesky factors: P_1 is the
+    grounded inverse of S_1 (entry N-1 fixed to zero), P_K inverts K_m."""
+    import paper_1711_08708_amd as B
+    from oracle import fem
+    cfg = mk()
+    hs = B.HostSetup(cfg, eps_h=0.0, leaf=16)
+    A = fem.assemble(cfg)
+    upos, vpos = hs.index(B.IDX_UPOS), hs.index(B.IDX_VPOS)
+    iu, iv = np.argsort(upos), np.argsort(vpos)
+    S1 = A["S1"][iu][:, iu]
+    gamma = cfg["chi"] * cfg["cm"] / cfg["dt"]
+    import scipy.sparse as sp
+    Km = (A["Sm"] + gamma * sp.diags(A["mH"]))[iv][:, iv]
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=S1.shape[0])
+    x[-1] = 0.0
+    y = hs.factor_apply(B.FACTOR_P1, S1 @ x)
+    assert np.linalg.norm(y - x) <= 1e-9 * np.linalg.norm(x)
+    xk = rng.normal(size=Km.shape[0])
+    yk = hs.factor_apply(B.FACTOR_PK, Km @ xk)
+    assert np.linalg.norm(yk - xk) <= 1e-11 * np.linalg.norm(xk)
+    st = hs.factor_stats(B.FACTOR_P1)
+    assert st["stored_entries"] == st["dense_entries"] and st["n_lowrank"] == 0
+
+
+def test_bad_inputs_are_rejected():
+    import paper_1711_08708_amd as B
+    cfg = w.square2d(n=6)
+    bad = dict(cfg)
+    bad["elems"] = cfg["elems"].copy()
+    bad["elems"][0, 0] = 10**6
+    with pytest.raises(B.BidoError) as e:
+        B.HostSetup(bad)
+    assert e.value.code == -1
+    with pytest.raises(B.BidoError):
+        B.HostSetup(cfg, dt=-1.0)
+    no_heart = dict(cfg)
+    no_heart["region"] = np.zeros_like(cfg["region"])
+    with pytest.raises(B.BidoError):
+        B.HostSetup(no_heart)

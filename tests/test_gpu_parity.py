@@ -1,0 +1,157 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+The bar is the relative error of Step 2's unique normalised solution
+(Prop. 1): e_v = |V - V*| / |V*| <= 1e-8 and e_u = |U - U*| / |U*| <= 1e-8,
+with the oracle solving the very right-hand side the GPU step used
+(per-solve parity).  The oracle never sees GPU outputs except the state it
+is asked to step from.
+"""
+import numpy as np
+import pytest
+
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+TOL_PARITY = 1e-8
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _errs(U, V, Uo, Vo):
+    eu = np.linalg.norm(U - Uo) / max(np.linalg.norm(Uo), 1e-300)
+    ev = np.linalg.norm(V - Vo) / max(np.linalg.norm(Vo), 1e-300)
+    return eu, ev
+
+
+def _oracle_solution_global(sysm, X):
+    """Oracle X (heart-first order) -> (U in global order, V heart-local)."""
+    return sysm.to_global_u(X[:sysm.N]), X[sysm.N:]
+
+
+def _check_solve(torch, cfg, method="auto", **params):
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd
+    s = bd.System(cfg)
+    rng = np.random.default_rng(7)
+    V = rng.uniform(0, 100, s.NH)
+    h = rng.uniform(0, 1, s.NH)
+    Y = s.rhs(V, h, 0)
+    Xo = s.solve(Y, method=method)
+    Uo, Vo = _oracle_solution_global(s, Xo)
+    solver = B.Solver(cfg, **params)
+    assert np.array_equal(solver.heart_nodes, s.hn)
+    rhs = np.concatenate([s.to_global_u(Y[:s.N]), Y[s.N:]])
+    rhs_d = torch.tensor(rhs, dtype=torch.float64, device="cuda")
+    x_d = torch.zeros_like(rhs_d)
+    st = solver.solve(rhs_d, x_d, tol=params.get("tol", 1e-12))
+    x = x_d.cpu().numpy()
+    eu, ev = _errs(x[:s.N], x[s.N:], Uo, Vo)
+    print(f"{cfg['name']}: iters={st['iterations']} rel_res={st['rel_residual']:.2e} "
+          f"e_u={eu:.2e} e_v={ev:.2e}", flush=True)
+    assert st["converged"] == 1
+    assert eu <= TOL_PARITY and ev <= TOL_PARITY
+    return st, solver
+
+
+@pytest.mark.parametrize("mk", [
+    lambda: w.square2d(n=5),            # 36 vertices: several single-node levels
+    lambda: w.square2d(n=48),           # the 2,401-vertex square (ragged leaves)
+    lambda: w.thorax2d(n_target=3000, seed=11),
+    lambda: w.slab3d(n=6),
+])
+def test_solve_parity_exact_factor(torch, mk):
+    _check_solve(torch, mk(), eps_h=0.0, tol=1e-12)
+
+
+def test_exact_factor_iteration_count_matches_dense_block_lu(torch):
+    """With exact inner factors the GPU preconditioner is the block-LU of
+    Def. 2 with P_1 = grounded S_1 and P_K = K_m exactly, so its iteration
+    count equals that of the dense oracle PCG with the same blocks."""
+    from oracle import bidomain as bd, blocklu as bl
+    import paper_1711_08708_amd as B
+    cfg = w.square2d(n=24)
+    s = bd.System(cfg)
+    b = bl.dense_blocks(s)
+    rng = np.random.default_rng(3)
+    Y = s.rhs(rng.uniform(0, 100, s.NH), rng.uniform(0, 1, s.NH), 0)
+    Pinv = bl.block_prec(b, bl.grounded_solver(b["S1"]), bl.chol_solver(bl.K_monodomain(b)))
+    _, it_ref, _ = bl.pcg(s.Lam, Y, Pinv, tol=1e-10)
+    solver = B.Solver(cfg, eps_h=0.0)
+    rhs = torch.tensor(np.concatenate([s.to_global_u(Y[:s.N]), Y[s.N:]]), device="cuda")
+    x = torch.zeros_like(rhs)
+    st = solver.solve(rhs, x, tol=1e-10)
+    print("iterations gpu", st["iterations"], "oracle", it_ref)
+    assert st["iterations"] == it_ref
+
+
+def test_step_trajectory_square48(torch):
+    """20 steps of the 2,401-vertex square: every step's solve matches the
+    oracle's solve of the same right-hand side, and the gating update is
+    bit-for-bit the oracle's formula up to rounding."""
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd
+    cfg = w.make_config("square48")
+    s = bd.System(cfg)
+    solver = B.Solver(cfg, eps_h=0.0, tol=1e-12)
+    v, h, u = solver.state()
+    worst = 0.0
+    for n in range(cfg["n_steps"]):
+        Vn = v.cpu().numpy().copy()
+        hn = h.cpu().numpy().copy()
+        st = solver.step(v, h, u, n)
+        Uo_p, Vo, ho = s.step(Vn, hn, n, method="dense")
+        Uo = s.to_global_u(Uo_p)
+        eu, ev = _errs(u.cpu().numpy(), v.cpu().numpy(), Uo, Vo)
+        eh = np.abs(h.cpu().numpy() - ho).max()
+        worst = max(worst, eu, ev)
+        assert eu <= TOL_PARITY and ev <= TOL_PARITY, (n, eu, ev)
+        assert eh <= 1e-14
+    print("square48 worst per-step error", worst)
+
+
+def test_thorax200k_solve_parity(torch):
+    """Full-size thorax slice (about 200k vertices): the normalised solution
+    of one step's system matches the oracle's sparse direct solve."""
+    _check_solve(torch, w.make_config("thorax200k"), eps_h=0.0, tol=1e-12)
+
+
+def test_range_and_dt_errors(torch):
+    import paper_1711_08708_amd as B
+    cfg = w.square2d(n=8)
+    solver = B.Solver(cfg, eps_h=0.0)
+    n2 = solver.N + solver.NH
+    rhs = torch.zeros(n2, dtype=torch.float64, device="cuda")
+    rhs[: solver.N] = 1.0      # not in Ran(Lambda)
+    x = torch.zeros_like(rhs)
+    with pytest.raises(B.BidoError) as e:
+        solver.solve(rhs, x)
+    assert e.value.code == -6
+    v, h, u = solver.state()
+    with pytest.raises(B.BidoError) as e:
+        B._check(B.lib.bido_step(solver.ctx, solver._dev(v, solver.NH), solver._dev(h, solver.NH),
+                                 solver._dev(u, solver.N), 0.05, 0, None))
+    assert e.value.code == -5
+
+
+def test_zero_rhs_and_not_converged(torch):
+    import paper_1711_08708_amd as B
+    cfg = w.square2d(n=12)
+    solver = B.Solver(cfg, eps_h=0.0)
+    n2 = solver.N + solver.NH
+    rhs = torch.zeros(n2, dtype=torch.float64, device="cuda")
+    x = torch.ones_like(rhs)
+    st = solver.solve(rhs, x)
+    assert st["iterations"] == 0 and float(x.abs().max()) == 0.0
+    rhs[solver.N:] = 1.0
+    x.zero_()
+    solver.set_solver(tol=1e-14, max_iter=1)
+    with pytest.raises(B.BidoError) as e:
+        solver.solve(rhs, x)
+    assert e.value.code == -4
