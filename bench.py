@@ -1,0 +1,181 @@
+"""Throughput benchmark of the bidomain per-step solve on one MI355X.
+
+A step is one pass of the whole hot path (Steps 1-3 of the resolution
+algorithm: ionic RHS and gating, the block-LU preconditioned CG solve of
+Lambda X = Y, the normalisation of U) over the synthetic thorax-like slice
+of about 200k vertices.  Prints ONE JSON line.
+
+Roofline: the same timed steps are replayed (from the same saved state) with
+HIP events around every launch; the dominant kernel class is the one with
+the largest summed duration, and `achieved` is its algorithmic bytes (inputs
+read once, outputs written once) divided by its summed event time.
+
+CPU baseline: the FP64 oracle (sparse direct solve of the normalised system)
+timed on a bounded sample of the same workload's steps on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "bidomain time steps/sec at 1e-8 rel error; learned+mixed vs plain PCG; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="thorax200k")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--eps", type=float, default=0.0)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-parity", action="store_true", help="skip the sampled parity check")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--variants", action="store_true", help="also time the mixed variant")
+    return ap.parse_args()
+
+
+def _timed_steps(torch, solver, state, n0, k):
+    v, h, u = state
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    iters = 0
+    t0 = time.perf_counter()
+    e0.record()
+    for n in range(n0, n0 + k):
+        st = solver.step(v, h, u, n)
+        iters += st["iterations"]
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1000.0, wall, iters
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1711_08708_amd as B
+    import workloads as w
+
+    torch.cuda.set_device(0)
+    cfg = w.make_config(args.config)
+    prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
+    t_setup = time.perf_counter()
+    solver = B.Solver(cfg, tol=args.tol, eps_h=args.eps, precision=prec)
+    t_setup = time.perf_counter() - t_setup
+    info = solver.info
+    print(f"[bench] {cfg['name']}: N={solver.N} N_H={solver.NH} setup {t_setup:.2f}s "
+          f"P1 {info['bytes_p1']/1e6:.1f} MB PK {info['bytes_pk']/1e6:.1f} MB", file=sys.stderr,
+          flush=True)
+
+    v, h, u = solver.state()
+    for n in range(args.warmup):
+        solver.step(v, h, u, n)
+    saved = [t.clone() for t in (v, h, u)]
+    n0 = args.warmup
+    gpu_s, wall_s, iters = _timed_steps(torch, solver, (v, h, u), n0, args.steps)
+    steps_per_s = args.steps / wall_s
+    print(f"[bench] {args.steps} steps: {wall_s*1e3/args.steps:.3f} ms/step (events "
+          f"{gpu_s*1e3/args.steps:.3f}), {iters/args.steps:.2f} CG iterations/step",
+          file=sys.stderr, flush=True)
+
+    # replay the timed steps from the saved state with per-launch events
+    v2, h2, u2 = [t.clone() for t in saved]
+    solver.profile(True)
+    last_state = None
+    for n in range(n0, n0 + args.steps):
+        if n == n0 + args.steps - 1:
+            last_state = [t.cpu().numpy().copy() for t in (v2, h2)]
+        solver.step(v2, h2, u2, n)
+    prof = solver.profile_read()
+    solver.profile(False)
+    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    achieved = dom["bytes"] / (dom["ms"] / 1e3) / 1e9
+    total_bytes = sum(p["bytes"] for p in prof.values())
+    total_ms = sum(p["ms"] for p in prof.values())
+    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None,
+                "launches": dom["launches"], "avg_launch_us": round(dom["ms"] * 1e3 / dom["launches"], 2),
+                "bytes_per_launch": round(dom["bytes"] / dom["launches"]),
+                "step_bytes": round(total_bytes / args.steps),
+                "step_kernel_ms": round(total_ms / args.steps, 4)}
+    kernels = {k: {"launches": p["launches"], "ms": round(p["ms"], 3),
+                   "GBps": round(p["bytes"] / max(p["ms"], 1e-9) / 1e6, 1)} for k, p in prof.items()}
+
+    result = {
+        "metric": METRIC, "value": round(steps_per_s, 3), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall_s * 1e3 / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == B.PREC_FP64 else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg['name']}: 2D thorax-like slice, {solver.N} vertices "
+                               f"({solver.NH} heart), semi-implicit bidomain step, block-LU/"
+                               f"monodomain PCG, {args.precision} preconditioner",
+                   "n_nodes": solver.N, "n_heart": solver.NH, "dt_ms": cfg["dt"],
+                   "tol": args.tol, "eps_h": args.eps, "precision": args.precision,
+                   "first_step": n0, "cg_iterations_per_step": round(iters / args.steps, 3),
+                   "setup_s": round(t_setup, 2)},
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+
+    if not args.no_parity and last_state is not None:
+        from oracle import bidomain as bd
+        s = bd.System(cfg)
+        Uo, Vo, _ = s.step(last_state[0], last_state[1], n0 + args.steps - 1)
+        Uo = s.to_global_u(Uo)
+        U, V = u2.cpu().numpy(), v2.cpu().numpy()
+        result["parity"] = {"step": n0 + args.steps - 1,
+                            "e_u": float(np.linalg.norm(U - Uo) / np.linalg.norm(Uo)),
+                            "e_v": float(np.linalg.norm(V - Vo) / np.linalg.norm(Vo))}
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_steps)
+
+    if args.variants and prec == B.PREC_FP64:
+        solver.set_precision(B.PREC_MIXED)
+        v3, h3, u3 = [t.clone() for t in saved]
+        gs, ws, it3 = _timed_steps(torch, solver, (v3, h3, u3), n0, args.steps)
+        result["variants"] = {"mixed": {"steps_per_s": round(args.steps / ws, 3),
+                                        "cg_iterations_per_step": round(it3 / args.steps, 3)}}
+        solver.set_precision(B.PREC_FP64)
+    print(json.dumps(result), flush=True)
+
+
+def _cpu_baseline(cfg, n_steps):
+    """Oracle steps from rest on the host (sparse direct solve per step)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import bidomain as bd
+    with threadpool_limits(limits=1):
+        s = bd.System(cfg)
+        V = np.zeros(s.NH)
+        h = np.ones(s.NH)
+        t0 = time.perf_counter()
+        for n in range(n_steps):
+            U, V, h = s.step(V, h, n)
+        el = time.perf_counter() - t0
+    return {"value": round(n_steps / el, 5), "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_steps} steps of {cfg['name']} from rest (FP64 NumPy/SciPy oracle: "
+                      f"Step 1, sparse LU of the grounded Lambda, normalisation, Step 3; "
+                      f"assembly excluded), {el:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

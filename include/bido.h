@@ -183,6 +183,25 @@ bido_status bido_set_precision(bido_ctx* ctx, int precision);
  * current values).                                                      */
 bido_status bido_set_solver(bido_ctx* ctx, double tol, int max_iter);
 
+/* Per-kernel profile: launches, summed event-timed duration [ms] and the
+ * algorithmic bytes those launches must move (inputs read once, outputs
+ * written once), aggregated by kernel class.                            */
+typedef struct {
+    char name[24];
+    int64_t launches;
+    double ms;
+    double bytes;
+} bido_kprof;
+
+/* enable != 0 brackets every later launch on the context's stream with a
+ * pair of HIP events (adds a little launch overhead); resets the records. */
+bido_status bido_profile(bido_ctx* ctx, int enable);
+
+/* Synchronise, aggregate the records since the last read or enable into
+ * out[0..cap) (one entry per kernel class seen), set *n to the number of
+ * classes and clear the records.                                         */
+bido_status bido_profile_read(bido_ctx* ctx, bido_kprof* out, int cap, int* n);
+
 #ifdef __cplusplus
 }
 #endif

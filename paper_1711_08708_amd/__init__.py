@@ -73,6 +73,11 @@ class Info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class KProf(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
+                ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); mirrors include/bido.h and include/bido_host.h
 ABI = {
     "bido_last_error": (ctypes.c_char_p, []),
@@ -94,6 +99,9 @@ ABI = {
                                   ctypes.c_double, ctypes.POINTER(Stats)]),
     "bido_set_precision": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_set_solver": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]),
+    "bido_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "bido_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KProf), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int)]),
     "bido_host_last_error": (ctypes.c_char_p, []),
     "bido_host_setup": (ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.POINTER(Tissue),
                                        ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_void_p)]),
@@ -253,6 +261,16 @@ class Solver:
 
     def set_solver(self, tol=0.0, max_iter=0):
         _check(lib.bido_set_solver(self.ctx, float(tol), int(max_iter)))
+
+    def profile(self, enable=True):
+        _check(lib.bido_profile(self.ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        buf = (KProf * 16)()
+        n = ctypes.c_int()
+        _check(lib.bido_profile_read(self.ctx, buf, 16, ctypes.byref(n)))
+        return {buf[i].name.decode(): dict(launches=buf[i].launches, ms=buf[i].ms,
+                                           bytes=buf[i].bytes) for i in range(min(n.value, 16))}
 
     def close(self):
         if getattr(self, "ctx", None):

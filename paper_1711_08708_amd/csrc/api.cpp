@@ -55,6 +55,30 @@ int pow2_at_least(int n, int cap) {
     return g;
 }
 
+// Kernel classes of the optional per-launch profiler.
+enum KClass { K_SPMV_LAMBDA = 0, K_PCG_UPDATE, K_COMBINE_DOT, K_P_UPDATE, K_TRI_FWD, K_TRI_BWD,
+              K_SPMV_CSR, K_IONIC, K_MISC, K_NCLASS };
+const char* const kclass_name[K_NCLASS] = {"spmv_lambda", "pcg_update", "combine_dot", "p_update",
+                                           "tri_fwd", "tri_bwd", "spmv_csr", "ionic_rhs", "misc"};
+
+// Per-launch HIP-event timing with the algorithmic bytes of each launch.
+struct Profiler {
+    bool on = false;
+    struct Rec { int cls; hipEvent_t a, b; double bytes; };
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<Rec> recs;
+    hipEvent_t get() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            hipEventCreate(&e);
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    ~Profiler() { for (auto e : pool) hipEventDestroy(e); }
+};
+
 // Device copy of one hierarchical Cholesky factor.
 struct FactorDev {
     int64_t n = 0, ground = -1;
@@ -68,6 +92,8 @@ struct FactorDev {
     double* ytmp = nullptr;
     TriItem* items = nullptr;
     std::vector<TriLevel> levels;
+    std::vector<double> fwd_bytes64, bwd_bytes64;   // algorithmic bytes per level (FP64 panel)
+    std::vector<double> fwd_bytes32, bwd_bytes32;   // same with the FP32 panel
     int64_t panel_entries = 0;
     int64_t dense_entries = 0;
     int64_t meta_bytes = 0;
@@ -182,6 +208,26 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd) {
     std::vector<TriItem> items;
     struct Span { size_t f0, nf, b0, nb; size_t lds; };
     std::vector<Span> spans;
+    fd.fwd_bytes64.assign(t.height + 1, 0.0);
+    fd.bwd_bytes64.assign(t.height + 1, 0.0);
+    fd.fwd_bytes32.assign(t.height + 1, 0.0);
+    fd.bwd_bytes32.assign(t.height + 1, 0.0);
+    for (int h = 0; h <= t.height; ++h)
+        for (int id : by_h[h]) {
+            const Front& fr = f.fronts[id];
+            const double pe = (double)fr.nI * (fr.nI + 1) / 2 + (double)fr.nB * fr.nI;
+            double cb = 0.0;
+            for (int c = 0; c < 2; ++c)
+                if (t.nodes[id].child[c] >= 0) cb += f.fronts[t.nodes[id].child[c]].nB;
+            // forward: panel + b_t + extend-add maps + children's updates + y_t + c_t
+            const double fv = 8.0 * (fr.nI + (fr.nI + fr.nB) + cb + fr.nI + fr.nB);
+            // backward: panel + y_t + boundary ids + x_B + x_t
+            const double bv = 8.0 * (fr.nI + 2.0 * fr.nB + fr.nI);
+            fd.fwd_bytes64[h] += 8.0 * pe + fv;
+            fd.bwd_bytes64[h] += 8.0 * pe + bv;
+            fd.fwd_bytes32[h] += 4.0 * pe + fv;
+            fd.bwd_bytes32[h] += 4.0 * pe + bv;
+        }
     for (int h = 0; h <= t.height; ++h) {
         Span sp{items.size(), 0, 0, 0, 0};
         for (int id : by_h[h]) {
@@ -252,6 +298,7 @@ struct bido_ctx {
     double *m_int = nullptr, *mh_loc = nullptr, *stim_loc = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<int64_t> heart_ids;
+    Profiler prof;
 
     ~bido_ctx() {
         if (stream) hipStreamSynchronize(stream);
@@ -273,13 +320,34 @@ struct bido_ctx {
 
 namespace {
 
+// Launch `stmt`, bracketed by profiler events when profiling is on.
+#define PROF(c, cls, bytes, stmt)                                                \
+    do {                                                                         \
+        if ((c)->prof.on) {                                                      \
+            hipEvent_t a_ = (c)->prof.get(), b_ = (c)->prof.get();               \
+            hipEventRecord(a_, (c)->stream);                                     \
+            stmt;                                                                \
+            hipEventRecord(b_, (c)->stream);                                     \
+            (c)->prof.recs.push_back({(cls), a_, b_, (double)(bytes)});          \
+        } else {                                                                 \
+            stmt;                                                                \
+        }                                                                        \
+    } while (0)
+
+double csr_bytes(const CsrDev& a, int64_t ncols_read) {
+    return 12.0 * a.nnz + 8.0 * (a.n + 1) + 8.0 * ncols_read + 8.0 * a.n;
+}
+
 template <typename T>
 void tri_solve(bido_ctx* c, const FactorDev& f, const T* panel, const double* in, double* out) {
     hipStream_t s = c->stream;
+    const bool f32 = sizeof(T) == 4;
     for (int h = 0; h <= f.height; ++h)
-        launch_tri_fwd<T>(s, f.levels[h], f.nodes, panel, f.ea, in, f.ytmp, f.upd, f.ground);
+        PROF(c, K_TRI_FWD, f32 ? f.fwd_bytes32[h] : f.fwd_bytes64[h],
+             launch_tri_fwd<T>(s, f.levels[h], f.nodes, panel, f.ea, in, f.ytmp, f.upd, f.ground));
     for (int h = f.height; h >= 0; --h)
-        launch_tri_bwd<T>(s, f.levels[h], f.nodes, panel, f.bidx, f.ytmp, out);
+        PROF(c, K_TRI_BWD, f32 ? f.bwd_bytes32[h] : f.bwd_bytes64[h],
+             launch_tri_bwd<T>(s, f.levels[h], f.nodes, panel, f.bidx, f.ytmp, out));
 }
 
 void inner_solve(bido_ctx* c, const FactorDev& f, const double* in, double* out) {
@@ -294,11 +362,14 @@ void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old)
     hipStream_t s = c->stream;
     const int64_t N = c->N;
     inner_solve(c, c->p1, r, c->tA);                                 // Z1 = P1^-1 R1
-    launch_spmv_csr(s, c->avu, c->spmv_group, c->tA, r + N, c->tB);  // R2 - S_i Pi Z1
+    PROF(c, K_SPMV_CSR, csr_bytes(c->avu, c->NH) + 8.0 * c->NH,
+         launch_spmv_csr(s, c->avu, c->spmv_group, c->tA, r + N, c->tB));  // R2 - S_i Pi Z1
     inner_solve(c, c->pk, c->tB, z + N);                             // Z2 = PK^-1 (...)
-    launch_spmv_csr(s, c->auv, c->spmv_group, z + N, nullptr, c->tC);   // Pi^T S_i Z2
+    PROF(c, K_SPMV_CSR, csr_bytes(c->auv, c->NH),
+         launch_spmv_csr(s, c->auv, c->spmv_group, z + N, nullptr, c->tC));   // Pi^T S_i Z2
     inner_solve(c, c->p1, c->tC, c->tD);                             // P1^-1 Pi^T S_i Z2
-    launch_combine_dot(s, N, c->n2, z, c->tA, c->tD, r, r_old, c->rd, c->sc);
+    PROF(c, K_COMBINE_DOT, 8.0 * (3 * N + c->NH + c->n2 * (r_old ? 2 : 1)),
+         launch_combine_dot(s, N, c->n2, z, c->tA, c->tD, r, r_old, c->rd, c->sc));
 }
 
 bido_status read_scalars(bido_ctx* c) {
@@ -313,7 +384,8 @@ bido_status pcg(bido_ctx* c, double tol, bido_stats* st) {
     const int64_t n = c->n2;
     const bool flexible = c->precision == BIDO_PREC_MIXED;
     double* r_old = flexible ? c->r_old : nullptr;
-    launch_spmv_lambda(s, c->lam, c->spmv_group, 1, c->x, c->Y, c->r, c->rd, c->sc);
+    PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n) + 8.0 * n,
+         launch_spmv_lambda(s, c->lam, c->spmv_group, 1, c->x, c->Y, c->r, c->rd, c->sc));
     bido_status e = read_scalars(c);
     if (e) return e;
     const double yy = c->sc_host[S_YY];
@@ -323,11 +395,13 @@ bido_status pcg(bido_ctx* c, double tol, bido_stats* st) {
     if (yy == 0.0) launch_fill(s, n, c->x, 0.0);
     if (!conv) {
         precond_apply(c, c->r, c->z, nullptr);
-        launch_p_update(s, n, c->z, c->p, c->sc, 1, 0);
+        PROF(c, K_P_UPDATE, 24.0 * n, launch_p_update(s, n, c->z, c->p, c->sc, 1, 0));
         for (it = 1; it <= c->params.max_iter; ++it) {
-            launch_copy_scalar(s, c->sc, S_RHO, S_RHO_NEW);
-            launch_spmv_lambda(s, c->lam, c->spmv_group, 0, c->p, nullptr, c->q, c->rd, c->sc);
-            launch_pcg_update(s, n, c->x, c->r, r_old, c->p, c->q, c->rd, c->sc);
+            PROF(c, K_MISC, 16.0, launch_copy_scalar(s, c->sc, S_RHO, S_RHO_NEW));
+            PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n),
+                 launch_spmv_lambda(s, c->lam, c->spmv_group, 0, c->p, nullptr, c->q, c->rd, c->sc));
+            PROF(c, K_PCG_UPDATE, (r_old ? 56.0 : 48.0) * n,
+                 launch_pcg_update(s, n, c->x, c->r, r_old, c->p, c->q, c->rd, c->sc));
             if ((e = read_scalars(c))) return e;
             const double pq = c->sc_host[S_PQ], rho = c->sc_host[S_RHO];
             rel = std::sqrt(c->sc_host[S_RR] / yy);
@@ -338,7 +412,7 @@ bido_status pcg(bido_ctx* c, double tol, bido_stats* st) {
             }
             if (rel <= tol) { conv = true; break; }
             precond_apply(c, c->r, c->z, r_old);
-            launch_p_update(s, n, c->z, c->p, c->sc, 0, flexible ? 1 : 0);
+            PROF(c, K_P_UPDATE, 24.0 * n, launch_p_update(s, n, c->z, c->p, c->sc, 0, flexible ? 1 : 0));
         }
         if (it > c->params.max_iter) it = c->params.max_iter;
     }
@@ -370,16 +444,17 @@ IonicConst ionic_consts(const bido_ctx* c) {
 bido_status step_once(bido_ctx* c, double* v, double* w, double* u, int64_t n, bido_stats* st) {
     hipStream_t s = c->stream;
     const int64_t N = c->N, NH = c->NH;
-    launch_scatter_in(s, N, c->u_pos, u, c->x);                        // X0 = (U^n, V^n)
+    PROF(c, K_MISC, 24.0 * N, launch_scatter_in(s, N, c->u_pos, u, c->x));   // X0 = (U^n, V^n)
     const double on = (n >= c->hs.stim_n0 && n < c->hs.stim_n1) ? 1.0 : 0.0;
-    launch_ionic(s, NH, v, w, c->stim_loc, on, c->mh_loc, c->v_pos, c->Y + N, c->x + N,
-                 ionic_consts(c));                                     // Steps 1 and 3
-    launch_fill(s, N, c->Y, 0.0);                                      // Y1 = 0
+    PROF(c, K_IONIC, 64.0 * NH,
+         launch_ionic(s, NH, v, w, c->stim_loc, on, c->mh_loc, c->v_pos, c->Y + N, c->x + N,
+                      ionic_consts(c)));                               // Steps 1 and 3
+    PROF(c, K_MISC, 8.0 * N, launch_fill(s, N, c->Y, 0.0));           // Y1 = 0
     bido_status e = pcg(c, c->params.tol, st);                         // Step 2
     if (e && e != BIDO_ERR_NOT_CONVERGED) return e;
-    launch_dot_reduce(s, N, c->m_int, c->x, c->rd, c->sc + S_MU);      // (M U, 1)
-    launch_gather_out(s, N, c->u_pos, c->x, u, c->sc, S_MU, c->hs.msum);
-    launch_gather_out(s, NH, c->v_pos, c->x + N, v, c->sc, -1, 1.0);
+    PROF(c, K_MISC, 16.0 * N, launch_dot_reduce(s, N, c->m_int, c->x, c->rd, c->sc + S_MU));  // (M U, 1)
+    PROF(c, K_MISC, 24.0 * N, launch_gather_out(s, N, c->u_pos, c->x, u, c->sc, S_MU, c->hs.msum));
+    PROF(c, K_MISC, 24.0 * NH, launch_gather_out(s, NH, c->v_pos, c->x + N, v, c->sc, -1, 1.0));
     return e;
 }
 
@@ -499,6 +574,40 @@ bido_status bido_set_precision(bido_ctx* c, int precision) {
     if (precision != BIDO_PREC_FP64 && precision != BIDO_PREC_MIXED)
         return fail(BIDO_ERR_ARG, "bad precision");
     c->precision = precision;
+    return BIDO_OK;
+}
+
+bido_status bido_profile(bido_ctx* c, int enable) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->prof.recs.clear();
+    c->prof.used = 0;
+    c->prof.on = enable != 0;
+    return BIDO_OK;
+}
+
+bido_status bido_profile_read(bido_ctx* c, bido_kprof* out, int cap, int* n) {
+    if (!c || !n) return fail(BIDO_ERR_ARG, "null argument");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    bido_kprof agg[K_NCLASS];
+    std::memset(agg, 0, sizeof(agg));
+    for (int k = 0; k < K_NCLASS; ++k) std::strncpy(agg[k].name, kclass_name[k], sizeof(agg[k].name) - 1);
+    for (const auto& r : c->prof.recs) {
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+        agg[r.cls].launches += 1;
+        agg[r.cls].ms += ms;
+        agg[r.cls].bytes += r.bytes;
+    }
+    int m = 0;
+    for (int k = 0; k < K_NCLASS; ++k)
+        if (agg[k].launches > 0) {
+            if (out && m < cap) out[m] = agg[k];
+            ++m;
+        }
+    *n = m;
+    c->prof.recs.clear();
+    c->prof.used = 0;
     return BIDO_OK;
 }
 
