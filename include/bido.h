@@ -123,6 +123,8 @@ typedef struct {
     int64_t lowrank_blocks;      /* admissible (low-rank) blocks stored       */
     double setup_seconds;        /* host set-up time of bido_create           */
     int ground_index;            /* internal index of the grounded u node    */
+    int launches_per_sweep_p1;   /* kernel launches of one triangular sweep   */
+    int launches_per_sweep_pk;
 } bido_info;
 
 /* Last error message of the calling thread ("" if none).                  */
@@ -182,6 +184,13 @@ bido_status bido_set_precision(bido_ctx* ctx, int precision);
 /* Override tolerance and iteration cap (tol <= 0 / max_iter <= 0 keep the
  * current values).                                                      */
 bido_status bido_set_solver(bido_ctx* ctx, double tol, int max_iter);
+
+/* Apply one inner solve on the device: which = 0 for P_1^-1 (grounded S_1,
+ * internal u order, N entries), 1 for P_K^-1 (K_m, internal v order, N_H
+ * entries).  b and x are device arrays in that internal order (the orders
+ * are those of bido_host_index); synchronises the stream.  A check entry
+ * point for the triangular sweeps; the solve path does not call it.      */
+bido_status bido_inner_solve(bido_ctx* ctx, int which, const double* b, double* x);
 
 /* Per-kernel profile: launches, summed event-timed duration [ms] and the
  * algorithmic bytes those launches must move (inputs read once, outputs

@@ -55,9 +55,24 @@ bido_status bido_host_factor_stats(const bido_host* h, int which, int64_t* dense
                                    int64_t* stored_entries, int64_t* n_lowrank,
                                    int* height, int* max_sep);
 
+/* Per tree node (post-order): nI, nB, height, depth, parent, low-rank block
+ * count, as 6 int32 per node into out[0..6*cap).  *n_nodes gets the count. */
+bido_status bido_host_factor_nodes(const bido_host* h, int which, int64_t* n_nodes, int32_t* out,
+                                   int64_t cap);
+
 /* Apply the factor on the host: x = (L L^T)^-1 b in the factor's internal
  * order (for P_1 the grounded entry of b is ignored and x there is 0).     */
 bido_status bido_host_factor_apply(const bido_host* h, int which, const double* b, double* x);
+
+/* Run the device execution plan of a factor (the work items the GPU sweep
+ * kernels process, in launch order) through a sequential CPU emulation of
+ * those kernels with bounds-checked accesses; x as bido_host_factor_apply. */
+bido_status bido_host_factor_emulate(const bido_host* h, int which, const double* b, double* x);
+
+/* Shape of that plan: subtree cut height, subtrees, level launches per
+ * sweep above the cut, forward and backward work items.                   */
+bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n_sub, int* n_levels,
+                                  int64_t* n_fwd_items, int64_t* n_bwd_items);
 
 #ifdef __cplusplus
 }

@@ -67,7 +67,8 @@ class Info(ctypes.Structure):
                 ("bytes_pk", ctypes.c_int64), ("dense_bytes_p1", ctypes.c_int64),
                 ("dense_bytes_pk", ctypes.c_int64), ("levels_p1", ctypes.c_int),
                 ("levels_pk", ctypes.c_int), ("lowrank_blocks", ctypes.c_int64),
-                ("setup_seconds", ctypes.c_double), ("ground_index", ctypes.c_int)]
+                ("setup_seconds", ctypes.c_double), ("ground_index", ctypes.c_int),
+                ("launches_per_sweep_p1", ctypes.c_int), ("launches_per_sweep_pk", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -99,6 +100,8 @@ ABI = {
                                   ctypes.c_double, ctypes.POINTER(Stats)]),
     "bido_set_precision": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_set_solver": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]),
+    "bido_inner_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
     "bido_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KProf), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int)]),
@@ -116,6 +119,13 @@ ABI = {
     "bido_host_factor_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p, _c_i64_p,
                                               _c_i64_p, ctypes.POINTER(ctypes.c_int),
                                               ctypes.POINTER(ctypes.c_int)]),
+    "bido_host_factor_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p, _c_i32_p,
+                                              ctypes.c_int64]),
+    "bido_host_factor_emulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p,
+                                                _c_double_p]),
+    "bido_host_factor_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                             _c_i64_p, _c_i64_p]),
     "bido_host_factor_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p,
                                               _c_double_p]),
 }
@@ -256,6 +266,10 @@ class Solver:
                               ctypes.byref(st)))
         return st.as_dict()
 
+    def inner_solve(self, which, b, x):
+        n = self.N if which == FACTOR_P1 else self.NH
+        _check(lib.bido_inner_solve(self.ctx, int(which), self._dev(b, n), self._dev(x, n)))
+
     def set_precision(self, precision):
         _check(lib.bido_set_precision(self.ctx, int(precision)))
 
@@ -329,6 +343,31 @@ class HostSetup:
                host=True)
         return dict(dense_entries=de.value, stored_entries=se.value, n_lowrank=nl.value,
                     height=h.value, max_sep=ms.value)
+
+    def factor_nodes(self, which):
+        """(n_nodes, 6) int32: nI, nB, height, depth, parent, low-rank blocks."""
+        n = ctypes.c_int64()
+        _check(lib.bido_host_factor_nodes(self.h, which, ctypes.byref(n), None, 0), host=True)
+        out = np.zeros((n.value, 6), dtype=np.int32)
+        _check(lib.bido_host_factor_nodes(self.h, which, ctypes.byref(n),
+                                          out.ctypes.data_as(_c_i32_p), n.value), host=True)
+        return out
+
+    def factor_emulate(self, which, b):
+        """CPU emulation of the GPU sweep kernels over the device plan."""
+        b = _arr(b, np.float64)
+        x = np.zeros_like(b)
+        _check(lib.bido_host_factor_emulate(self.h, which, b.ctypes.data_as(_c_double_p),
+                                            x.ctypes.data_as(_c_double_p)), host=True)
+        return x
+
+    def factor_plan(self, which):
+        hc, ns, nl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        nf, nb = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.bido_host_factor_plan(self.h, which, ctypes.byref(hc), ctypes.byref(ns),
+                                         ctypes.byref(nl), ctypes.byref(nf), ctypes.byref(nb)), host=True)
+        return dict(hc=hc.value, n_sub=ns.value, n_levels=nl.value, n_fwd_items=nf.value,
+                    n_bwd_items=nb.value)
 
     def factor_apply(self, which, b):
         b = _arr(b, np.float64)

@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -20,6 +22,7 @@
 
 #include "../../include/bido.h"
 #include "launch.h"
+#include "plan.h"
 #include "setup.h"
 
 using namespace bido;
@@ -56,10 +59,11 @@ int pow2_at_least(int n, int cap) {
 }
 
 // Kernel classes of the optional per-launch profiler.
-enum KClass { K_SPMV_LAMBDA = 0, K_PCG_UPDATE, K_COMBINE_DOT, K_P_UPDATE, K_TRI_FWD, K_TRI_BWD,
-              K_SPMV_CSR, K_IONIC, K_MISC, K_NCLASS };
+enum KClass { K_SPMV_LAMBDA = 0, K_PCG_UPDATE, K_COMBINE_DOT, K_P_UPDATE, K_TRI_FWD_SUB,
+              K_TRI_FWD_LVL, K_TRI_BWD_SUB, K_TRI_BWD_LVL, K_SPMV_CSR, K_IONIC, K_MISC, K_NCLASS };
 const char* const kclass_name[K_NCLASS] = {"spmv_lambda", "pcg_update", "combine_dot", "p_update",
-                                           "tri_fwd", "tri_bwd", "spmv_csr", "ionic_rhs", "misc"};
+                                           "tri_fwd_sub", "tri_fwd_lvl", "tri_bwd_sub", "tri_bwd_lvl",
+                                           "spmv_csr", "ionic_rhs", "misc"};
 
 // Per-launch HIP-event timing with the algorithmic bytes of each launch.
 struct Profiler {
@@ -84,26 +88,36 @@ struct FactorDev {
     int64_t n = 0, ground = -1;
     int height = 0;
     TriNode* nodes = nullptr;
-    double* panel64 = nullptr;
+    double* panel64 = nullptr;      // row-major copy (backward sweep)
     float* panel32 = nullptr;
-    int2* ea = nullptr;
+    double* panel64_cm = nullptr;   // column-major copy (forward sweep)
+    float* panel32_cm = nullptr;
+    Ea* ea = nullptr;
     int64_t* bidx = nullptr;
     double* upd = nullptr;
     double* ytmp = nullptr;
     TriItem* items = nullptr;
-    std::vector<TriLevel> levels;
-    std::vector<double> fwd_bytes64, bwd_bytes64;   // algorithmic bytes per level (FP64 panel)
+    BwdItem* bitems = nullptr;
+    TriPlan plan;
+    std::vector<TriTopLevel> top;                   // heights hc+1 .. height
+    std::vector<double> fwd_bytes64, bwd_bytes64;   // algorithmic bytes per height (FP64 panel)
     std::vector<double> fwd_bytes32, bwd_bytes32;   // same with the FP32 panel
+    double sub_fwd_bytes64 = 0, sub_bwd_bytes64 = 0, sub_fwd_bytes32 = 0, sub_bwd_bytes32 = 0;
     int64_t panel_entries = 0;
     int64_t dense_entries = 0;
     int64_t meta_bytes = 0;
+    int64_t upd_size = 0;
     int max_nI = 0;
 
     void release() {
-        hipFree(nodes); hipFree(panel64); hipFree(panel32); hipFree(ea); hipFree(bidx);
-        hipFree(upd); hipFree(ytmp); hipFree(items);
-        nodes = nullptr; panel64 = nullptr; panel32 = nullptr; ea = nullptr; bidx = nullptr;
-        upd = nullptr; ytmp = nullptr; items = nullptr;
+        hipFree(nodes); hipFree(panel64); hipFree(panel32); hipFree(panel64_cm); hipFree(panel32_cm);
+        hipFree(ea); hipFree(bidx);
+        hipFree(upd); hipFree(ytmp); hipFree(items); hipFree(bitems);
+        hipFree(plan.sub_nodes); hipFree(plan.sub_hoff); hipFree(plan.scratch); hipFree(plan.counters);
+        nodes = nullptr; panel64 = nullptr; panel32 = nullptr; panel64_cm = nullptr; panel32_cm = nullptr;
+        ea = nullptr; bidx = nullptr;
+        upd = nullptr; ytmp = nullptr; items = nullptr; bitems = nullptr;
+        plan = TriPlan();
     }
 };
 
@@ -123,157 +137,59 @@ struct CsrHostView {
 };
 
 bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd) {
-    const NdTree& t = f.tree;
-    const int nn = (int)t.nodes.size();
-    fd.n = f.n;
-    fd.ground = f.ground;
-    fd.height = t.height;
-    std::vector<TriNode> nodes(nn);
-    int64_t poff = 0, boff = 0, uoff = 0, eoff = 0;
-    for (int id = 0; id < nn; ++id) {
-        const Front& fr = f.fronts[id];
-        TriNode& d = nodes[id];
-        d.off = fr.off;
-        d.nI = fr.nI;
-        d.nB = fr.nB;
-        d.panel = poff;
-        d.bidx = boff;
-        d.upd = uoff;
-        d.ea = eoff;
-        d.child[0] = t.nodes[id].child[0];
-        d.child[1] = t.nodes[id].child[1];
-        poff += (int64_t)fr.nI * (fr.nI + 1) / 2 + (int64_t)fr.nB * fr.nI;
-        boff += fr.nB;
-        uoff += fr.nB;
-        eoff += fr.nI + fr.nB;
-        fd.max_nI = std::max(fd.max_nI, fr.nI);
-    }
-    if (fd.max_nI > 8192)
-        return fail(BIDO_ERR_ARG, "separator of " + std::to_string(fd.max_nI) +
-                                      " vertices exceeds the 8192-entry LDS staging limit");
-    fd.panel_entries = poff;
+    FactorPlan p;
+    std::string err;
+    if (!build_plan(f, p, err)) return fail(BIDO_ERR_ARG, err);
+    fd.n = p.n;
+    fd.ground = p.ground;
+    fd.height = p.height;
+    fd.max_nI = p.max_nI;
+    fd.upd_size = p.upd_size;
+    fd.panel_entries = (int64_t)p.panel.size();
     fd.dense_entries = f.dense_entries();
-    std::vector<double> panel((size_t)poff);
-    std::vector<int64_t> bidx((size_t)std::max<int64_t>(boff, 1));
-    std::vector<int2> ea((size_t)std::max<int64_t>(eoff, 1), make_int2(-1, -1));
-    for (int id = 0; id < nn; ++id) {
-        const Front& fr = f.fronts[id];
-        const TriNode& d = nodes[id];
-        const int nI = fr.nI;
-        if (fr.compressed) {
-            // dense view of the compressed panel, rebuilt from its blocks
-            std::vector<double> P((size_t)(nI + fr.nB) * nI, 0.0);
-            for (const auto& b : fr.dense)
-                for (int r = 0; r < b.nr; ++r)
-                    for (int c = 0; c < (b.lower_tri ? r + 1 : b.nc); ++c)
-                        P[(size_t)(b.r0 + r) * nI + b.c0 + c] = b.D[(size_t)r * b.nc + c];
-            for (const auto& l : fr.lowrank)
-                for (int r = 0; r < l.nr; ++r)
-                    for (int c = 0; c < l.nc; ++c) {
-                        double s = 0.0;
-                        for (int k = 0; k < l.rank; ++k) s += l.U[(size_t)r * l.rank + k] * l.V[(size_t)c * l.rank + k];
-                        P[(size_t)(l.r0 + r) * nI + l.c0 + c] = s;
-                    }
-            int64_t o = d.panel;
-            for (int r = 0; r < nI + fr.nB; ++r) {
-                int len = r < nI ? r + 1 : nI;
-                for (int c = 0; c < len; ++c) panel[o++] = P[(size_t)r * nI + c];
-            }
-        } else {
-            int64_t o = d.panel;
-            for (int r = 0; r < nI + fr.nB; ++r) {
-                int len = r < nI ? r + 1 : nI;
-                for (int c = 0; c < len; ++c) panel[o++] = fr.P[(size_t)r * nI + c];
-            }
-        }
-        for (int r = 0; r < fr.nB; ++r) bidx[d.bidx + r] = fr.B[r];
-        const NdNode& nd = t.nodes[id];
-        for (int c = 0; c < 2; ++c) {
-            int ch = nd.child[c];
-            if (ch < 0) continue;
-            const Front& cf = f.fronts[ch];
-            for (int j = 0; j < cf.nB; ++j) {
-                int64_t g = cf.B[j];
-                int pos;
-                if (g < nd.end) pos = (int)(g - nd.begin);
-                else pos = nI + (int)(std::lower_bound(fr.B.begin(), fr.B.end(), g) - fr.B.begin());
-                int2& m = ea[d.ea + pos];
-                if (c == 0) m.x = j; else m.y = j;
-            }
-        }
-    }
-    // work items per level (tree height)
-    std::vector<std::vector<int>> by_h(t.height + 1);
-    for (int id = 0; id < nn; ++id) by_h[t.nodes[id].height].push_back(id);
-    std::vector<TriItem> items;
-    struct Span { size_t f0, nf, b0, nb; size_t lds; };
-    std::vector<Span> spans;
-    fd.fwd_bytes64.assign(t.height + 1, 0.0);
-    fd.bwd_bytes64.assign(t.height + 1, 0.0);
-    fd.fwd_bytes32.assign(t.height + 1, 0.0);
-    fd.bwd_bytes32.assign(t.height + 1, 0.0);
-    for (int h = 0; h <= t.height; ++h)
-        for (int id : by_h[h]) {
-            const Front& fr = f.fronts[id];
-            const double pe = (double)fr.nI * (fr.nI + 1) / 2 + (double)fr.nB * fr.nI;
-            double cb = 0.0;
-            for (int c = 0; c < 2; ++c)
-                if (t.nodes[id].child[c] >= 0) cb += f.fronts[t.nodes[id].child[c]].nB;
-            // forward: panel + b_t + extend-add maps + children's updates + y_t + c_t
-            const double fv = 8.0 * (fr.nI + (fr.nI + fr.nB) + cb + fr.nI + fr.nB);
-            // backward: panel + y_t + boundary ids + x_B + x_t
-            const double bv = 8.0 * (fr.nI + 2.0 * fr.nB + fr.nI);
-            fd.fwd_bytes64[h] += 8.0 * pe + fv;
-            fd.bwd_bytes64[h] += 8.0 * pe + bv;
-            fd.fwd_bytes32[h] += 4.0 * pe + fv;
-            fd.bwd_bytes32[h] += 4.0 * pe + bv;
-        }
-    for (int h = 0; h <= t.height; ++h) {
-        Span sp{items.size(), 0, 0, 0, 0};
-        for (int id : by_h[h]) {
-            const Front& fr = f.fronts[id];
-            const int nI = fr.nI, nF = fr.nI + fr.nB;
-            if (nI == 0) continue;
-            const int G = pow2_at_least(std::min(nI, 64), 64);
-            int R = std::max(256 / G, std::min(nF, 16384 / std::max(nI, 1)));
-            for (int r0 = 0; r0 < nF; r0 += R) items.push_back({id, r0, std::min(R, nF - r0), G});
-            sp.lds = std::max(sp.lds, (size_t)nI * sizeof(double));
-        }
-        sp.nf = items.size() - sp.f0;
-        sp.b0 = items.size();
-        for (int id : by_h[h]) {
-            const Front& fr = f.fronts[id];
-            const int nI = fr.nI;
-            if (nI == 0) continue;
-            const int W = pow2_at_least(std::min(nI, 64), 64);
-            for (int c0 = 0; c0 < nI; c0 += W) items.push_back({id, c0, std::min(W, nI - c0), W});
-        }
-        sp.nb = items.size() - sp.b0;
-        spans.push_back(sp);
-    }
-    HIP_OK(upload(&fd.nodes, nodes.data(), nodes.size()));
-    HIP_OK(upload(&fd.panel64, panel.data(), panel.size()));
+    HIP_OK(upload(&fd.nodes, p.nodes.data(), p.nodes.size()));
+    HIP_OK(upload(&fd.panel64, p.panel.data(), p.panel.size()));
+    HIP_OK(upload(&fd.panel64_cm, p.panel_cm.data(), p.panel_cm.size()));
     if (want32) {
-        std::vector<float> p32(panel.begin(), panel.end());
+        std::vector<float> p32(p.panel.begin(), p.panel.end());
         HIP_OK(upload(&fd.panel32, p32.data(), p32.size()));
+        std::vector<float> c32(p.panel_cm.begin(), p.panel_cm.end());
+        HIP_OK(upload(&fd.panel32_cm, c32.data(), c32.size()));
     }
-    HIP_OK(upload(&fd.ea, ea.data(), ea.size()));
-    HIP_OK(upload(&fd.bidx, bidx.data(), bidx.size()));
-    HIP_OK(upload(&fd.items, items.data(), items.size()));
-    HIP_OK(hipMalloc((void**)&fd.upd, std::max<int64_t>(uoff, 1) * sizeof(double)));
-    HIP_OK(hipMalloc((void**)&fd.ytmp, std::max<int64_t>(f.n, 1) * sizeof(double)));
-    fd.levels.clear();
-    for (const Span& sp : spans) {
-        TriLevel L;
-        L.fwd_items = fd.items + sp.f0;
-        L.n_items = (int)sp.nf;
-        L.bwd_items = fd.items + sp.b0;
-        L.n_bwd_items = (int)sp.nb;
-        L.lds_bytes = sp.lds;
-        fd.levels.push_back(L);
+    HIP_OK(upload(&fd.ea, p.ea.data(), p.ea.size()));
+    HIP_OK(upload(&fd.bidx, p.bidx.data(), p.bidx.size()));
+    HIP_OK(upload(&fd.items, p.fwd_items.data(), p.fwd_items.size()));
+    HIP_OK(upload(&fd.bitems, p.bwd_items.data(), p.bwd_items.size()));
+    fd.plan.hc = p.hc;
+    fd.plan.n_sub = p.n_sub;
+    fd.plan.sub_maxw = p.sub_maxw;
+    HIP_OK(upload(&fd.plan.sub_nodes, p.sub_nodes.data(), p.sub_nodes.size()));
+    HIP_OK(upload(&fd.plan.sub_hoff, p.sub_hoff.data(), p.sub_hoff.size()));
+    HIP_OK(hipMalloc((void**)&fd.plan.scratch, std::max<int64_t>(p.scratch_size, 1) * sizeof(double)));
+    HIP_OK(hipMalloc((void**)&fd.plan.counters, std::max(p.n_tiles, 1) * sizeof(unsigned)));
+    HIP_OK(hipMemset(fd.plan.counters, 0, std::max(p.n_tiles, 1) * sizeof(unsigned)));
+    HIP_OK(hipMalloc((void**)&fd.upd, std::max<int64_t>(p.upd_size, 1) * sizeof(double)));
+    HIP_OK(hipMalloc((void**)&fd.ytmp, std::max<int64_t>(p.n, 1) * sizeof(double)));
+    fd.top.clear();
+    for (const auto& sp : p.spans) {
+        TriTopLevel L;
+        L.fwd = fd.items + sp.f0;
+        L.n_fwd = (int)sp.nf;
+        L.bwd = fd.bitems + sp.b0;
+        L.n_bwd = (int)sp.nb;
+        L.lds_f = sp.lds_f;
+        L.lds_b = sp.lds_b;
+        fd.top.push_back(L);
     }
-    fd.meta_bytes = (int64_t)(nodes.size() * sizeof(TriNode) + bidx.size() * 8 + ea.size() * 8 +
-                              items.size() * sizeof(TriItem));
+    fd.fwd_bytes64 = p.fwd_bytes64;
+    fd.bwd_bytes64 = p.bwd_bytes64;
+    fd.fwd_bytes32 = p.fwd_bytes32;
+    fd.bwd_bytes32 = p.bwd_bytes32;
+    fd.sub_fwd_bytes64 = p.sub_fwd_bytes64;
+    fd.sub_bwd_bytes64 = p.sub_bwd_bytes64;
+    fd.sub_fwd_bytes32 = p.sub_fwd_bytes32;
+    fd.sub_bwd_bytes32 = p.sub_bwd_bytes32;
+    fd.meta_bytes = p.meta_bytes;
     return BIDO_OK;
 }
 
@@ -339,35 +255,77 @@ double csr_bytes(const CsrDev& a, int64_t ncols_read) {
 }
 
 template <typename T>
-void tri_solve(bido_ctx* c, const FactorDev& f, const T* panel, const double* in, double* out) {
+void tri_solve(bido_ctx* c, const FactorDev& f, const T* panel, const T* panel_cm, const double* in,
+               double* out) {
     hipStream_t s = c->stream;
     const bool f32 = sizeof(T) == 4;
-    for (int h = 0; h <= f.height; ++h)
-        PROF(c, K_TRI_FWD, f32 ? f.fwd_bytes32[h] : f.fwd_bytes64[h],
-             launch_tri_fwd<T>(s, f.levels[h], f.nodes, panel, f.ea, in, f.ytmp, f.upd, f.ground));
-    for (int h = f.height; h >= 0; --h)
-        PROF(c, K_TRI_BWD, f32 ? f.bwd_bytes32[h] : f.bwd_bytes64[h],
-             launch_tri_bwd<T>(s, f.levels[h], f.nodes, panel, f.bidx, f.ytmp, out));
+    const int hc = f.plan.hc;
+    PROF(c, K_TRI_FWD_SUB, f32 ? f.sub_fwd_bytes32 : f.sub_fwd_bytes64,
+         launch_tri_fwd_sub<T>(s, f.plan, f.nodes, panel_cm, f.ea, in, f.ytmp, f.upd, f.ground));
+    for (size_t k = 0; k < f.top.size(); ++k) {
+        const int h = hc + 1 + (int)k;
+        PROF(c, K_TRI_FWD_LVL, f32 ? f.fwd_bytes32[h] : f.fwd_bytes64[h],
+             launch_tri_fwd_lvl<T>(s, f.top[k], f.plan, f.nodes, panel_cm, f.ea, in, f.ytmp, f.upd,
+                                   f.ground));
+    }
+    for (size_t k = f.top.size(); k-- > 0;) {
+        const int h = hc + 1 + (int)k;
+        PROF(c, K_TRI_BWD_LVL, f32 ? f.bwd_bytes32[h] : f.bwd_bytes64[h],
+             launch_tri_bwd_lvl<T>(s, f.top[k], f.plan, f.nodes, panel, f.bidx, f.ytmp, out));
+    }
+    PROF(c, K_TRI_BWD_SUB, f32 ? f.sub_bwd_bytes32 : f.sub_bwd_bytes64,
+         launch_tri_bwd_sub<T>(s, f.plan, f.nodes, panel, f.bidx, f.ytmp, out));
 }
 
 void inner_solve(bido_ctx* c, const FactorDev& f, const double* in, double* out) {
     if (c->precision == BIDO_PREC_MIXED && f.panel32)
-        tri_solve<float>(c, f, f.panel32, in, out);
+        tri_solve<float>(c, f, f.panel32, f.panel32_cm, in, out);
     else
-        tri_solve<double>(c, f, f.panel64, in, out);
+        tri_solve<double>(c, f, f.panel64, f.panel64_cm, in, out);
+}
+
+// Opt-in check (environment BIDO_DEBUG=1): report the first non-finite
+// intermediate vector of a preconditioner apply on stderr.
+bool debug_on() {
+    static int on = -1;
+    if (on < 0) {
+        const char* e = std::getenv("BIDO_DEBUG");
+        on = (e && e[0] == '1') ? 1 : 0;
+    }
+    return on == 1;
+}
+void debug_check(bido_ctx* c, const char* name, const double* v, int64_t n) {
+    if (!debug_on()) return;
+    std::vector<double> h(n);
+    hipStreamSynchronize(c->stream);
+    hipMemcpy(h.data(), v, n * sizeof(double), hipMemcpyDeviceToHost);
+    int64_t bad = 0, first = -1;
+    double mx = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(h[i])) { if (first < 0) first = i; ++bad; }
+        else mx = std::max(mx, std::fabs(h[i]));
+    }
+    std::fprintf(stderr, "[bido debug] %-6s n=%lld nonfinite=%lld first=%lld max|.|=%.3e\n", name,
+                 (long long)n, (long long)bad, (long long)first, mx);
 }
 
 // z = P_Lambda^-1 r  and  rho_new = r.z  (plus z.r_old for flexible CG)
 void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old) {
     hipStream_t s = c->stream;
     const int64_t N = c->N;
+    debug_check(c, "r", r, c->n2);
     inner_solve(c, c->p1, r, c->tA);                                 // Z1 = P1^-1 R1
+    debug_check(c, "Z1", c->tA, N);
     PROF(c, K_SPMV_CSR, csr_bytes(c->avu, c->NH) + 8.0 * c->NH,
          launch_spmv_csr(s, c->avu, c->spmv_group, c->tA, r + N, c->tB));  // R2 - S_i Pi Z1
+    debug_check(c, "t", c->tB, c->NH);
     inner_solve(c, c->pk, c->tB, z + N);                             // Z2 = PK^-1 (...)
+    debug_check(c, "Z2", z + N, c->NH);
     PROF(c, K_SPMV_CSR, csr_bytes(c->auv, c->NH),
          launch_spmv_csr(s, c->auv, c->spmv_group, z + N, nullptr, c->tC));   // Pi^T S_i Z2
+    debug_check(c, "PiSZ2", c->tC, N);
     inner_solve(c, c->p1, c->tC, c->tD);                             // P1^-1 Pi^T S_i Z2
+    debug_check(c, "W", c->tD, N);
     PROF(c, K_COMBINE_DOT, 8.0 * (3 * N + c->NH + c->n2 * (r_old ? 2 : 1)),
          launch_combine_dot(s, N, c->n2, z, c->tA, c->tD, r, r_old, c->rd, c->sc));
 }
@@ -521,7 +479,17 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     for (double** b : {&c->tA, &c->tC, &c->tD}) HIP_OK(hipMalloc((void**)b, c->N * sizeof(double)));
     HIP_OK(hipMalloc((void**)&c->tB, std::max<int64_t>(c->NH, 1) * sizeof(double)));
     HIP_OK(hipMalloc((void**)&c->sc, S_COUNT * sizeof(double)));
-    HIP_OK(hipMemset(c->sc, 0, S_COUNT * sizeof(double)));
+    // Work vectors start as NaN (all-ones bit pattern): a kernel that reads
+    // one before writing it shows up in every result instead of by chance.
+    for (double* b : {c->x, c->r, c->z, c->p, c->q, c->Y, c->r_old})
+        HIP_OK(hipMemset(b, 0xFF, n2 * sizeof(double)));
+    for (double* b : {c->tA, c->tC, c->tD}) HIP_OK(hipMemset(b, 0xFF, c->N * sizeof(double)));
+    HIP_OK(hipMemset(c->tB, 0xFF, std::max<int64_t>(c->NH, 1) * sizeof(double)));
+    HIP_OK(hipMemset(c->sc, 0xFF, S_COUNT * sizeof(double)));
+    for (FactorDev* f : {&c->p1, &c->pk}) {
+        HIP_OK(hipMemset(f->ytmp, 0xFF, std::max<int64_t>(f->n, 1) * sizeof(double)));
+        HIP_OK(hipMemset(f->upd, 0xFF, std::max<int64_t>(f->upd_size, 1) * sizeof(double)));
+    }
     HIP_OK(hipHostMalloc((void**)&c->sc_host, S_COUNT * sizeof(double), hipHostMallocDefault));
     HIP_OK(hipMalloc((void**)&c->rd.partials, 2 * c->rd.max_blocks * sizeof(double)));
     HIP_OK(hipMalloc((void**)&c->rd.counter, sizeof(unsigned)));
@@ -556,6 +524,8 @@ bido_status bido_get_info(const bido_ctx* c, bido_info* info) {
     info->dense_bytes_pk = c->pk.dense_entries * 8;
     info->levels_p1 = c->p1.height + 1;
     info->levels_pk = c->pk.height + 1;
+    info->launches_per_sweep_p1 = (int)c->p1.top.size() + (c->p1.plan.n_sub > 0);
+    info->launches_per_sweep_pk = (int)c->pk.top.size() + (c->pk.plan.n_sub > 0);
     info->lowrank_blocks = c->hs.p1.n_lowrank() + c->hs.pk.n_lowrank();
     info->setup_seconds = c->hs.setup_seconds;
     info->ground_index = (int)c->p1.ground;
@@ -608,6 +578,14 @@ bido_status bido_profile_read(bido_ctx* c, bido_kprof* out, int cap, int* n) {
     *n = m;
     c->prof.recs.clear();
     c->prof.used = 0;
+    return BIDO_OK;
+}
+
+bido_status bido_inner_solve(bido_ctx* c, int which, const double* b, double* x) {
+    if (!c || !b || !x || (which != 0 && which != 1)) return fail(BIDO_ERR_ARG, "bad argument");
+    inner_solve(c, which == 0 ? c->p1 : c->pk, b, x);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
     return BIDO_OK;
 }
 

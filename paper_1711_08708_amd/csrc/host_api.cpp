@@ -4,6 +4,7 @@
 #include <string>
 
 #include "../../include/bido_host.h"
+#include "plan.h"
 #include "setup.h"
 
 struct bido_host {
@@ -93,6 +94,57 @@ bido_status bido_host_factor_stats(const bido_host* h, int which, int64_t* dense
         for (const auto& fr : f->fronts) m = fr.nI > m ? fr.nI : m;
         *max_sep = m;
     }
+    return BIDO_OK;
+}
+
+bido_status bido_host_factor_nodes(const bido_host* h, int which, int64_t* n_nodes, int32_t* out,
+                                   int64_t cap) {
+    if (!h || !n_nodes) return hfail(BIDO_ERR_ARG, "null argument");
+    const bido::Factor* f = which == BIDO_FACTOR_P1 ? &h->hs.p1 : which == BIDO_FACTOR_PK ? &h->hs.pk : nullptr;
+    if (!f) return hfail(BIDO_ERR_ARG, "unknown factor");
+    const int64_t nn = (int64_t)f->fronts.size();
+    *n_nodes = nn;
+    if (out)
+        for (int64_t i = 0; i < nn && i < cap; ++i) {
+            const auto& nd = f->tree.nodes[i];
+            out[i * 6 + 0] = f->fronts[i].nI;
+            out[i * 6 + 1] = f->fronts[i].nB;
+            out[i * 6 + 2] = nd.height;
+            out[i * 6 + 3] = nd.depth;
+            out[i * 6 + 4] = nd.parent;
+            out[i * 6 + 5] = (int32_t)f->fronts[i].lowrank.size();
+        }
+    return BIDO_OK;
+}
+
+bido_status bido_host_factor_emulate(const bido_host* h, int which, const double* b, double* x) {
+    if (!h || !b || !x) return hfail(BIDO_ERR_ARG, "null argument");
+    const bido::Factor* f = which == BIDO_FACTOR_P1 ? &h->hs.p1 : which == BIDO_FACTOR_PK ? &h->hs.pk : nullptr;
+    if (!f) return hfail(BIDO_ERR_ARG, "unknown factor");
+    bido::FactorPlan p;
+    std::string err;
+    if (!bido::build_plan(*f, p, err)) return hfail(BIDO_ERR_ARG, err);
+    try {
+        bido::emulate_plan(p, b, x);
+    } catch (const std::exception& e) {
+        return hfail(BIDO_ERR_STATE, std::string("plan emulation: ") + e.what());
+    }
+    return BIDO_OK;
+}
+
+bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n_sub, int* n_levels,
+                                  int64_t* n_fwd_items, int64_t* n_bwd_items) {
+    if (!h) return hfail(BIDO_ERR_ARG, "null argument");
+    const bido::Factor* f = which == BIDO_FACTOR_P1 ? &h->hs.p1 : which == BIDO_FACTOR_PK ? &h->hs.pk : nullptr;
+    if (!f) return hfail(BIDO_ERR_ARG, "unknown factor");
+    bido::FactorPlan p;
+    std::string err;
+    if (!bido::build_plan(*f, p, err)) return hfail(BIDO_ERR_ARG, err);
+    if (hc) *hc = p.hc;
+    if (n_sub) *n_sub = p.n_sub;
+    if (n_levels) *n_levels = (int)p.spans.size();
+    if (n_fwd_items) *n_fwd_items = (int64_t)p.fwd_items.size();
+    if (n_bwd_items) *n_bwd_items = (int64_t)p.bwd_items.size();
     return BIDO_OK;
 }
 

@@ -1,14 +1,17 @@
 // Device data layouts shared by the HIP kernels and the driver.
 #pragma once
-#include <hip/hip_runtime.h>
 #include <cstdint>
 
 namespace bido {
 
 // One tree node of a hierarchical Cholesky factor, as seen by the kernels.
-// The panel P_t = [L_tt^-1 ; L_Bt L_tt^-1] is stored row-major with the
-// L_tt^-1 rows packed (row r holds r+1 entries) followed by nB full rows of
-// nI entries.
+// The panel P_t = [L_tt^-1 ; L_Bt L_tt^-1] ((nI+nB) x nI, lower-triangular
+// top block) is stored twice, at the same offset of two arrays:
+//   row-major:    row r holds r+1 entries (r < nI) or nI entries (r >= nI)
+//   column-major: column c holds rows c .. nI+nB-1
+// The forward sweep (one thread per row) reads the column-major copy, the
+// backward sweep (one thread per column) the row-major one, so both read
+// consecutive addresses across the lanes of a wave.
 struct TriNode {
     int64_t off;     // first own index in the vector
     int64_t panel;   // offset of P_t in the panel array (elements)
@@ -19,13 +22,38 @@ struct TriNode {
     int32_t child[2];
 };
 
-// A unit of work of one level: rows [start, start+count) of a panel in the
-// forward sweep, or columns [start, start+count) in the backward sweep.
+// Extend-add map entry: position in each child's update vector (-1: none).
+struct Ea {
+    int32_t a, b;
+};
+
+// Forward work item of one level above the subtree cut: rows
+// [r0, r0+nrows) (nrows <= 64) of the panel of `node`, columns [cs, ce).
+// Items that split a row tile's columns write 64 partial sums each; the last
+// one to finish sums the parts in order and stores the rows.
 struct TriItem {
     int32_t node;
-    int32_t start;
-    int32_t count;
-    int32_t group;   // lanes per row (forward) / per column tile width (backward)
+    int32_t r0, nrows;
+    int32_t cs, ce;
+    int32_t nparts;      // items of this row tile
+    int32_t tile;        // completion counter of the tile
+    int32_t pad;
+    int64_t part;        // scratch offset of this item's partial sums
+    int64_t part0;       // scratch offset of the tile's first part
+};
+
+// Backward work item of one level above the subtree cut: columns
+// [c0, c0+ncols) of the panel of `node`, rows [rs, re).  Items that share a
+// column tile write W partial sums each; the last one to finish sums the
+// parts in order (deterministic) and writes x.
+struct BwdItem {
+    int32_t node;
+    int32_t c0, ncols, W;
+    int32_t rs, re;
+    int32_t nparts;      // items of this column tile
+    int32_t tile;        // completion counter of the tile
+    int64_t part;        // scratch offset of this item's partial sums
+    int64_t part0;       // scratch offset of the tile's first part
 };
 
 // Scalars of the PCG recurrences, resident on the device.

@@ -273,103 +273,293 @@ __global__ void k_p_update(int64_t n, const double* __restrict__ z, double* __re
             beta = sc[S_RHO_NEW] / sc[S_RHO];
         }
     }
+    // the first direction is z itself: p may hold stale bits (0 * NaN = NaN)
     for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
-        p[i] = z[i] + beta * p[i];
+        p[i] = first ? z[i] : z[i] + beta * p[i];
 }
 
 // ---------------------------------------------------------------------------
-// Hierarchical-Cholesky level sweeps
+// Hierarchical-Cholesky sweeps
+//
+// Node t owns the panel P_t = [L_tt^-1 ; L_Bt L_tt^-1].  Forward: w_t = b_t -
+// (children's updates at I_t), [y_t ; c_t] = P_t w_t, c_t also collects the
+// children's updates at B(t).  Backward: x_t = P_t^T [y_t ; -x_B].
+// Forward threads own rows and read the column-major copy; backward threads
+// own columns and read the row-major copy (see TriNode).
 // ---------------------------------------------------------------------------
+constexpr int SUB_BLOCK = 1024;    // subtree phase: 16 waves per workgroup
+constexpr int SUB_NW = SUB_BLOCK / WAVE;
+constexpr int SUB_MAXW = 256;      // max own size of a node below the cut
+constexpr int SUB_MAXF = 384;      // max panel rows of a node below the cut
+constexpr int FWD_ROWS = 64;       // forward row tile of the level phase
+
 __device__ __forceinline__ int64_t panel_row_off(int64_t r, int64_t nI) {
     return r < nI ? r * (r + 1) / 2 : nI * (nI + 1) / 2 + (r - nI) * nI;
 }
+__device__ __forceinline__ int64_t panel_col_off(int64_t c, int64_t nI, int64_t nB) {
+    return c * (nI + nB) - c * (c - 1) / 2;
+}
 
-// Forward sweep of one level.  For node t: w_t = b_t - (children's updates at
-// I_t); rows [start, start+count) of P_t w_t go to y_t (own rows) or to the
-// update vector c_t (boundary rows, plus the children's updates there).
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_tri_fwd(const TriNode* __restrict__ nodes,
-                                                   const TriItem* __restrict__ items,
-                                                   const T* __restrict__ panel,
-                                                   const int2* __restrict__ ea,
-                                                   const double* __restrict__ b,
-                                                   double* __restrict__ y,
-                                                   double* __restrict__ upd, int64_t ground) {
-    extern __shared__ double w[];
-    const TriItem it = items[blockIdx.x];
-    const TriNode nd = nodes[it.node];
-    const int nI = nd.nI;
-    const int64_t u0 = nd.child[0] >= 0 ? nodes[nd.child[0]].upd : 0;
-    const int64_t u1 = nd.child[1] >= 0 ? nodes[nd.child[1]].upd : 0;
-    const int rmax = min(it.start + it.count, nI);   // own rows need w[0..rmax)
-    const int wlen = it.start + it.count > nI ? nI : rmax;
-    for (int i = threadIdx.x; i < wlen; i += BLOCK) {
-        double s = b[nd.off + i];
-        const int2 m = ea[nd.ea + i];
-        if (m.x >= 0) s -= upd[u0 + m.x];
-        if (m.y >= 0) s -= upd[u1 + m.y];
-        if (nd.off + i == ground) s = 0.0;
-        w[i] = s;
-    }
-    __syncthreads();
-    const int G = it.group;
-    const int lane = threadIdx.x % G;
-    const int grp = threadIdx.x / G;
-    const int ngrp = BLOCK / G;
-    const T* P = panel + nd.panel;
-    for (int r = it.start + grp; r < it.start + it.count; r += ngrp) {
-        const int len = r < nI ? r + 1 : nI;
-        const T* row = P + panel_row_off(r, nI);
-        double s = 0.0;
-        for (int c = lane; c < len; c += G) s += (double)row[c] * w[c];
-        for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
-        if (lane == 0) {
-            if (r < nI) {
-                y[nd.off + r] = s;
-            } else {
-                const int2 m = ea[nd.ea + r];
-                if (m.x >= 0) s += upd[u0 + m.x];
-                if (m.y >= 0) s += upd[u1 + m.y];
-                upd[nd.upd + (r - nI)] = s;
-            }
-        }
+__device__ __forceinline__ int pow2_ceil64(int n) {
+    int g = 1;
+    while (g < n && g < 64) g <<= 1;
+    return g;
+}
+
+__device__ __forceinline__ int64_t child_upd(const TriNode* __restrict__ nodes, int c) {
+    return c >= 0 ? nodes[c].upd : 0;
+}
+
+// w_t[i] = b[off+i] - children's updates at own position i (ground -> 0)
+__device__ __forceinline__ double gather_w(const TriNode& nd, int i, const Ea* __restrict__ ea,
+                                           const double* __restrict__ b, const double* upd,
+                                           int64_t u0, int64_t u1, int64_t ground) {
+    double v = b[nd.off + i];
+    const Ea m = ea[nd.ea + i];
+    if (m.a >= 0) v -= upd[u0 + m.a];
+    if (m.b >= 0) v -= upd[u1 + m.b];
+    return (nd.off + i == ground) ? 0.0 : v;
+}
+
+// store row r of P_t w_t: own rows to y, boundary rows (plus the children's
+// updates there) to the update vector of the node
+__device__ __forceinline__ void store_row(const TriNode& nd, int r, double s, const Ea* __restrict__ ea,
+                                          double* __restrict__ y, double* upd, int64_t u0, int64_t u1) {
+    if (r < nd.nI) {
+        y[nd.off + r] = s;
+    } else {
+        const Ea m = ea[nd.ea + r];
+        if (m.a >= 0) s += upd[u0 + m.a];
+        if (m.b >= 0) s += upd[u1 + m.b];
+        upd[nd.upd + (r - nd.nI)] = s;
     }
 }
 
-// Backward sweep of one level: x_t[c] = sum_r P_t[r][c] z[r] with
-// z = [y_t ; -x_B], for the columns [start, start+count) (count <= 64).
+// sum_{c in [cs, ce), c <= r if r < nI} P(r, c) w[c - cs]   (column-major copy).
+// Entry (r, c) sits at col_off(c) + r - c; moving to column c+1 adds
+// nI + nB - c - 1.  Eight independent accumulators keep eight loads in flight.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_tri_bwd(const TriNode* __restrict__ nodes,
-                                                   const TriItem* __restrict__ items,
-                                                   const T* __restrict__ panel,
-                                                   const int64_t* __restrict__ bidx,
-                                                   const double* __restrict__ y,
-                                                   double* __restrict__ x) {
-    __shared__ double red[BLOCK];
+__device__ __forceinline__ double row_part(const T* __restrict__ Pc, int nI, int nB, int r, int cs,
+                                           int ce, const double* w) {
+    const int cend = r < nI ? min(ce, r + 1) : ce;
+    const int nF = nI + nB;
+    int64_t off = panel_col_off(cs, nI, nB) + (r - cs);
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int c = cs;
+    for (; c + 8 <= cend; c += 8) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            a[k] += (double)Pc[off] * w[c + k - cs];
+            off += nF - (c + k) - 1;
+        }
+    }
+    for (int k = 0; c < cend; ++c, ++k) {
+        a[k] += (double)Pc[off] * w[c - cs];
+        off += nF - c - 1;
+    }
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// sum over rows r = r0, r0+S, ... < re of P(r, c) z[r - z0] (row-major copy),
+// skipping the unstored entries c > r of the triangle.  All lanes of a wave
+// walk the same rows, so each row is read as one contiguous segment.
+template <typename T>
+__device__ __forceinline__ double col_part(const T* __restrict__ P, int nI, int c, int r0, int re, int S,
+                                           const double* z, int z0) {
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int r = r0;
+    for (; r + 7 * S < re; r += 8 * S) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int rr = r + k * S;
+            if (rr >= nI || c <= rr) a[k] += (double)P[panel_row_off(rr, nI) + c] * z[rr - z0];
+        }
+    }
+    for (int k = 0; r < re; r += S, ++k)
+        if (r >= nI || c <= r) a[k] += (double)P[panel_row_off(r, nI) + c] * z[r - z0];
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// Subtree phase, forward: workgroup s walks its subtree from the leaves up;
+// each node is handled by one wave, one panel row per lane.
+template <typename T>
+__global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __restrict__ nodes,
+                                                           const int32_t* __restrict__ sub_nodes,
+                                                           const int32_t* __restrict__ sub_hoff, int hc,
+                                                           const T* __restrict__ panel_cm,
+                                                           const Ea* __restrict__ ea,
+                                                           const double* __restrict__ b,
+                                                           double* __restrict__ y,
+                                                           double* upd, int64_t ground) {
+    __shared__ double wbuf[SUB_NW][SUB_MAXW];
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int32_t* hoff = sub_hoff + (size_t)blockIdx.x * (hc + 2);
+    double* w = wbuf[wave];
+    for (int h = 0; h <= hc; ++h) {
+        for (int k = hoff[h] + wave; k < hoff[h + 1]; k += SUB_NW) {
+            const TriNode nd = nodes[sub_nodes[k]];
+            const int64_t u0 = child_upd(nodes, nd.child[0]), u1 = child_upd(nodes, nd.child[1]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            for (int i = lane; i < nd.nI; i += WAVE) w[i] = gather_w(nd, i, ea, b, upd, u0, u1, ground);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const T* Pc = panel_cm + nd.panel;
+            const int nF = nd.nI + nd.nB;
+            for (int r = lane; r < nF; r += WAVE) {
+                const double s = row_part<T>(Pc, nd.nI, nd.nB, r, 0, nd.nI, w);
+                store_row(nd, r, s, ea, y, upd, u0, u1);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Subtree phase, backward: heights from the subtree root down; one wave per
+// node: z = [y_t ; -x_B] staged in LDS, lanes own columns (and row streams
+// when the node has fewer than 64 columns).
+template <typename T>
+__global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __restrict__ nodes,
+                                                           const int32_t* __restrict__ sub_nodes,
+                                                           const int32_t* __restrict__ sub_hoff, int hc,
+                                                           const T* __restrict__ panel,
+                                                           const int64_t* __restrict__ bidx,
+                                                           const double* __restrict__ y,
+                                                           double* x) {
+    __shared__ double zbuf[SUB_NW][SUB_MAXF];
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int32_t* hoff = sub_hoff + (size_t)blockIdx.x * (hc + 2);
+    double* z = zbuf[wave];
+    for (int h = hc; h >= 0; --h) {
+        for (int k = hoff[h] + wave; k < hoff[h + 1]; k += SUB_NW) {
+            const TriNode nd = nodes[sub_nodes[k]];
+            const int nI = nd.nI, nF = nd.nI + nd.nB;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            for (int r = lane; r < nF; r += WAVE) z[r] = r < nI ? y[nd.off + r] : -x[bidx[nd.bidx + (r - nI)]];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const T* P = panel + nd.panel;
+            for (int cb = 0; cb < nI; cb += WAVE) {
+                const int ncols = min(WAVE, nI - cb);
+                const int W = pow2_ceil64(ncols);
+                const int S = WAVE / W;
+                const int col = lane % W, st = lane / W;
+                const int c = cb + col;
+                double acc = 0.0;
+                if (col < ncols) acc = col_part<T>(P, nI, c, cb + st, nF, S, z, 0);
+                for (int m = W; m < WAVE; m <<= 1) acc += __shfl_xor(acc, m, WAVE);
+                if (st == 0 && col < ncols) x[nd.off + c] = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Level phase, forward: item = (64-row tile, column chunk) of one node.  The
+// four waves split the chunk's columns; partial sums over split chunks are
+// combined by the last item of the tile to finish.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_tri_fwd_lvl(const TriNode* __restrict__ nodes,
+                                                       const TriItem* __restrict__ items,
+                                                       const T* __restrict__ panel_cm,
+                                                       const Ea* __restrict__ ea,
+                                                       const double* __restrict__ b,
+                                                       double* __restrict__ y,
+                                                       double* upd, int64_t ground,
+                                                       double* scratch, unsigned* counters) {
+    extern __shared__ double w[];
+    __shared__ double red[BLOCK / WAVE][FWD_ROWS];
+    __shared__ bool last;
     const TriItem it = items[blockIdx.x];
     const TriNode nd = nodes[it.node];
-    const int nI = nd.nI, nF = nd.nI + nd.nB;
-    const int W = it.group;                 // columns per row step (pow2 <= 64)
-    const int cl = threadIdx.x % W;
-    const int sub = threadIdx.x / W;        // row offset within a step
-    const int nsub = BLOCK / W;
-    const int c = it.start + cl;
-    const bool valid = cl < it.count;
+    const int64_t u0 = child_upd(nodes, nd.child[0]), u1 = child_upd(nodes, nd.child[1]);
+    const int ncol = it.ce - it.cs;
+    for (int i = threadIdx.x; i < ncol; i += BLOCK) w[i] = gather_w(nd, it.cs + i, ea, b, upd, u0, u1, ground);
+    __syncthreads();
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int nw = BLOCK / WAVE;
+    const int per = (ncol + nw - 1) / nw;
+    const int c0 = it.cs + wave * per, c1 = min(it.ce, c0 + per);
+    const int r = it.r0 + lane;
+    double s = 0.0;
+    if (lane < it.nrows && c0 < c1)
+        s = row_part<T>(panel_cm + nd.panel, nd.nI, nd.nB, r, c0, c1, w + (c0 - it.cs));
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave != 0) return;
+    double tot = 0.0;
+    for (int k = 0; k < nw; ++k) tot += red[k][lane];
+    if (it.nparts == 1) {
+        if (lane < it.nrows) store_row(nd, r, tot, ea, y, upd, u0, u1);
+        return;
+    }
+    scratch[it.part + lane] = tot;
+    __threadfence();
+    if (lane == 0) last = atomicAdd(&counters[it.tile], 1u) == (unsigned)(it.nparts - 1);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (!last) return;
+    __threadfence();
+    if (lane < it.nrows) {
+        double t = 0.0;
+        for (int k = 0; k < it.nparts; ++k) t += scratch[it.part0 + (int64_t)k * FWD_ROWS + lane];
+        store_row(nd, r, t, ea, y, upd, u0, u1);
+    }
+    if (lane == 0) counters[it.tile] = 0u;
+}
+
+// Level phase, backward: item = (column tile, row range) of one node; z for
+// the row range is staged in LDS first.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_tri_bwd_lvl(const TriNode* __restrict__ nodes,
+                                                       const BwdItem* __restrict__ items,
+                                                       const T* __restrict__ panel,
+                                                       const int64_t* __restrict__ bidx,
+                                                       const double* __restrict__ y,
+                                                       double* x, double* scratch,
+                                                       unsigned* counters) {
+    extern __shared__ double z[];
+    __shared__ double red[BLOCK];
+    __shared__ bool last;
+    const BwdItem it = items[blockIdx.x];
+    const TriNode nd = nodes[it.node];
+    const int nI = nd.nI;
+    for (int r = it.rs + threadIdx.x; r < it.re; r += BLOCK)
+        z[r - it.rs] = r < nI ? y[nd.off + r] : -x[bidx[nd.bidx + (r - nI)]];
+    __syncthreads();
+    const int W = it.W;
+    const int col = threadIdx.x % W, st = threadIdx.x / W;
+    const int S = BLOCK / W;
+    const int c = it.c0 + col;
     const T* P = panel + nd.panel;
     double acc = 0.0;
-    for (int r = it.start + sub; r < nF; r += nsub) {
-        double zr;
-        if (r < nI) zr = y[nd.off + r];
-        else zr = -x[bidx[nd.bidx + (r - nI)]];
-        if (valid && (r >= nI || c <= r)) acc += (double)P[panel_row_off(r, nI) + c] * zr;
-    }
+    if (col < it.ncols) acc = col_part<T>(P, nI, c, max(it.rs, it.c0) + st, it.re, S, z, it.rs);
     red[threadIdx.x] = acc;
     __syncthreads();
-    if (threadIdx.x < W && valid) {
-        double s = 0.0;
-        for (int k = 0; k < nsub; ++k) s += red[k * W + threadIdx.x];
-        x[nd.off + c] = s;
+    double s = 0.0;
+    if (threadIdx.x < W)
+        for (int k = 0; k < S; ++k) s += red[k * W + threadIdx.x];
+    if (it.nparts == 1) {
+        if (threadIdx.x < it.ncols) x[nd.off + c] = s;
+        return;
     }
+    if (threadIdx.x < W) scratch[it.part + threadIdx.x] = s;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&counters[it.tile], 1u) == (unsigned)(it.nparts - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (threadIdx.x < it.ncols) {
+        double t = 0.0;
+        for (int k = 0; k < it.nparts; ++k) t += scratch[it.part0 + (int64_t)k * W + threadIdx.x];
+        x[nd.off + c] = t;
+    }
+    if (threadIdx.x == 0) counters[it.tile] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -455,24 +645,44 @@ void launch_p_update(hipStream_t s, int64_t n, const double* z, double* p, const
 }
 
 template <typename T>
-void launch_tri_fwd(hipStream_t s, const TriLevel& L, const TriNode* nodes, const T* panel,
-                    const int2* ea, const double* b, double* y, double* upd, int64_t ground) {
-    if (L.n_items == 0) return;
-    k_tri_fwd<T><<<L.n_items, BLOCK, L.lds_bytes, s>>>(nodes, L.fwd_items, panel, ea, b, y, upd, ground);
+void launch_tri_fwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel_cm,
+                        const Ea* ea, const double* b, double* y, double* upd, int64_t ground) {
+    if (P.n_sub == 0) return;
+    k_tri_fwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(nodes, P.sub_nodes, P.sub_hoff, P.hc, panel_cm, ea, b,
+                                                   y, upd, ground);
 }
 template <typename T>
-void launch_tri_bwd(hipStream_t s, const TriLevel& L, const TriNode* nodes, const T* panel,
-                    const int64_t* bidx, const double* y, double* x) {
-    if (L.n_bwd_items == 0) return;
-    k_tri_bwd<T><<<L.n_bwd_items, BLOCK, 0, s>>>(nodes, L.bwd_items, panel, bidx, y, x);
+void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
+                        const int64_t* bidx, const double* y, double* x) {
+    if (P.n_sub == 0) return;
+    k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(nodes, P.sub_nodes, P.sub_hoff, P.hc, panel, bidx, y, x);
 }
-template void launch_tri_fwd<double>(hipStream_t, const TriLevel&, const TriNode*, const double*,
-                                     const int2*, const double*, double*, double*, int64_t);
-template void launch_tri_fwd<float>(hipStream_t, const TriLevel&, const TriNode*, const float*,
-                                    const int2*, const double*, double*, double*, int64_t);
-template void launch_tri_bwd<double>(hipStream_t, const TriLevel&, const TriNode*, const double*,
-                                     const int64_t*, const double*, double*);
-template void launch_tri_bwd<float>(hipStream_t, const TriLevel&, const TriNode*, const float*,
-                                    const int64_t*, const double*, double*);
+template <typename T>
+void launch_tri_fwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
+                        const T* panel_cm, const Ea* ea, const double* b, double* y, double* upd,
+                        int64_t ground) {
+    if (L.n_fwd == 0) return;
+    k_tri_fwd_lvl<T><<<L.n_fwd, BLOCK, L.lds_f, s>>>(nodes, L.fwd, panel_cm, ea, b, y, upd, ground,
+                                                     P.scratch, P.counters);
+}
+template <typename T>
+void launch_tri_bwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
+                        const T* panel, const int64_t* bidx, const double* y, double* x) {
+    if (L.n_bwd == 0) return;
+    k_tri_bwd_lvl<T><<<L.n_bwd, BLOCK, L.lds_b, s>>>(nodes, L.bwd, panel, bidx, y, x, P.scratch, P.counters);
+}
+
+#define BIDO_INST(T)                                                                                   \
+    template void launch_tri_fwd_sub<T>(hipStream_t, const TriPlan&, const TriNode*, const T*,         \
+                                        const Ea*, const double*, double*, double*, int64_t);          \
+    template void launch_tri_bwd_sub<T>(hipStream_t, const TriPlan&, const TriNode*, const T*,         \
+                                        const int64_t*, const double*, double*);                       \
+    template void launch_tri_fwd_lvl<T>(hipStream_t, const TriTopLevel&, const TriPlan&, const TriNode*, \
+                                        const T*, const Ea*, const double*, double*, double*, int64_t); \
+    template void launch_tri_bwd_lvl<T>(hipStream_t, const TriTopLevel&, const TriPlan&, const TriNode*, \
+                                        const T*, const int64_t*, const double*, double*);
+BIDO_INST(double)
+BIDO_INST(float)
+#undef BIDO_INST
 
 }  // namespace bido

@@ -27,13 +27,25 @@ struct IonicConst {
     double dv, inv_dv, inv_tau_in, inv_tau_out, inv_tau_open, inv_tau_close, v_gate;
 };
 
-// One level (tree height) of a factor: work items of both sweeps.
-struct TriLevel {
-    TriItem* fwd_items = nullptr;   // device
-    int n_items = 0;
-    TriItem* bwd_items = nullptr;   // device
-    int n_bwd_items = 0;
-    size_t lds_bytes = 0;           // forward: max nI * 8
+// Execution plan of one factor's sweeps: the subtrees below the cut height
+// hc run in one launch (one workgroup walks a whole subtree), the levels
+// above it run one launch each.
+struct TriTopLevel {
+    TriItem* fwd = nullptr;   // device
+    int n_fwd = 0;
+    BwdItem* bwd = nullptr;   // device
+    int n_bwd = 0;
+    size_t lds_f = 0;         // forward: max column chunk * 8
+    size_t lds_b = 0;         // backward: max staged rows * 8
+};
+struct TriPlan {
+    int hc = -1;                  // subtree cut height (-1: no subtree phase)
+    int n_sub = 0;                // subtrees (workgroups of the subtree phase)
+    int32_t* sub_nodes = nullptr; // device: node ids grouped by subtree, by height
+    int32_t* sub_hoff = nullptr;  // device: n_sub x (hc+2) height offsets
+    int sub_maxw = 0;             // max nI below the cut
+    double* scratch = nullptr;    // backward partial sums
+    unsigned* counters = nullptr; // backward tile counters (zero between launches)
 };
 
 void launch_fill(hipStream_t s, int64_t n, double* x, double v);
@@ -58,10 +70,17 @@ void launch_p_update(hipStream_t s, int64_t n, const double* z, double* p, const
                      int flexible);
 
 template <typename T>
-void launch_tri_fwd(hipStream_t s, const TriLevel& L, const TriNode* nodes, const T* panel,
-                    const int2* ea, const double* b, double* y, double* upd, int64_t ground);
+void launch_tri_fwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
+                        const Ea* ea, const double* b, double* y, double* upd, int64_t ground);
 template <typename T>
-void launch_tri_bwd(hipStream_t s, const TriLevel& L, const TriNode* nodes, const T* panel,
-                    const int64_t* bidx, const double* y, double* x);
+void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
+                        const int64_t* bidx, const double* y, double* x);
+template <typename T>
+void launch_tri_fwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
+                        const T* panel_cm, const Ea* ea, const double* b, double* y, double* upd,
+                        int64_t ground);
+template <typename T>
+void launch_tri_bwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
+                        const T* panel, const int64_t* bidx, const double* y, double* x);
 
 }  // namespace bido

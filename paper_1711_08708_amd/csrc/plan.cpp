@@ -1,0 +1,425 @@
+// Execution plan of the hierarchical-Cholesky sweeps and its CPU emulation.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <stdexcept>
+
+namespace bido {
+namespace {
+
+int pow2_at_least(int n, int cap) {
+    int g = 1;
+    while (g < n && g < cap) g <<= 1;
+    return g;
+}
+
+int64_t panel_row_off(int64_t r, int64_t nI) {
+    return r < nI ? r * (r + 1) / 2 : nI * (nI + 1) / 2 + (r - nI) * nI;
+}
+
+}  // namespace
+
+bool build_plan(const Factor& f, FactorPlan& p, std::string& err) {
+    const NdTree& t = f.tree;
+    const int nn = (int)t.nodes.size();
+    p = FactorPlan();
+    p.n = f.n;
+    p.ground = f.ground;
+    p.height = t.height;
+    p.nodes.resize(nn);
+    int64_t poff = 0, boff = 0, uoff = 0, eoff = 0;
+    for (int id = 0; id < nn; ++id) {
+        const Front& fr = f.fronts[id];
+        TriNode& d = p.nodes[id];
+        d.off = fr.off;
+        d.nI = fr.nI;
+        d.nB = fr.nB;
+        d.panel = poff;
+        d.bidx = boff;
+        d.upd = uoff;
+        d.ea = eoff;
+        d.child[0] = t.nodes[id].child[0];
+        d.child[1] = t.nodes[id].child[1];
+        poff += (int64_t)fr.nI * (fr.nI + 1) / 2 + (int64_t)fr.nB * fr.nI;
+        boff += fr.nB;
+        uoff += fr.nB;
+        eoff += fr.nI + fr.nB;
+        p.max_nI = std::max(p.max_nI, fr.nI);
+    }
+    if (p.max_nI > PLAN_LDS_MAXW) {
+        err = "separator of " + std::to_string(p.max_nI) + " vertices exceeds the " +
+              std::to_string(PLAN_LDS_MAXW) + "-entry LDS staging limit";
+        return false;
+    }
+    p.upd_size = uoff;
+    p.panel.assign((size_t)poff, 0.0);
+    p.panel_cm.assign((size_t)poff, 0.0);
+    p.bidx.assign((size_t)std::max<int64_t>(boff, 1), 0);
+    p.ea.assign((size_t)std::max<int64_t>(eoff, 1), Ea{-1, -1});
+    for (int id = 0; id < nn; ++id) {
+        const Front& fr = f.fronts[id];
+        const TriNode& d = p.nodes[id];
+        const int nI = fr.nI;
+        std::vector<double> dense;
+        const std::vector<double>* P = &fr.P;
+        if (fr.compressed) {
+            // dense view of a compressed panel, rebuilt from its blocks
+            dense.assign((size_t)(nI + fr.nB) * nI, 0.0);
+            for (const auto& b : fr.dense)
+                for (int r = 0; r < b.nr; ++r)
+                    for (int c = 0; c < (b.lower_tri ? r + 1 : b.nc); ++c)
+                        dense[(size_t)(b.r0 + r) * nI + b.c0 + c] = b.D[(size_t)r * b.nc + c];
+            for (const auto& l : fr.lowrank)
+                for (int r = 0; r < l.nr; ++r)
+                    for (int c = 0; c < l.nc; ++c) {
+                        double s = 0.0;
+                        for (int k = 0; k < l.rank; ++k)
+                            s += l.U[(size_t)r * l.rank + k] * l.V[(size_t)c * l.rank + k];
+                        dense[(size_t)(l.r0 + r) * nI + l.c0 + c] = s;
+                    }
+            P = &dense;
+        }
+        int64_t o = d.panel;
+        for (int r = 0; r < nI + fr.nB; ++r) {
+            const int len = r < nI ? r + 1 : nI;
+            for (int c = 0; c < len; ++c) p.panel[o++] = (*P)[(size_t)r * nI + c];
+        }
+        o = d.panel;
+        for (int c = 0; c < nI; ++c)
+            for (int r = c; r < nI + fr.nB; ++r) p.panel_cm[o++] = (*P)[(size_t)r * nI + c];
+        for (int r = 0; r < fr.nB; ++r) p.bidx[d.bidx + r] = fr.B[r];
+        const NdNode& nd = t.nodes[id];
+        for (int c = 0; c < 2; ++c) {
+            const int ch = nd.child[c];
+            if (ch < 0) continue;
+            const Front& cf = f.fronts[ch];
+            for (int j = 0; j < cf.nB; ++j) {
+                const int64_t g = cf.B[j];
+                int pos;
+                if (g < nd.end) pos = (int)(g - nd.begin);
+                else pos = nI + (int)(std::lower_bound(fr.B.begin(), fr.B.end(), g) - fr.B.begin());
+                Ea& m = p.ea[d.ea + pos];
+                if (c == 0) m.a = j; else m.b = j;
+            }
+        }
+    }
+
+    // ---- subtree cut: largest height whose subtrees are numerous enough ----
+    const int H = t.height;
+    std::vector<std::vector<int>> by_h(H + 1);
+    for (int id = 0; id < nn; ++id) by_h[t.nodes[id].height].push_back(id);
+    std::vector<int> maxw_le(H + 1, 0), maxf_le(H + 1, 0);
+    for (int h = 0; h <= H; ++h) {
+        int m = h > 0 ? maxw_le[h - 1] : 0, mf = h > 0 ? maxf_le[h - 1] : 0;
+        for (int id : by_h[h]) {
+            m = std::max(m, f.fronts[id].nI);
+            mf = std::max(mf, f.fronts[id].nI + f.fronts[id].nB);
+        }
+        maxw_le[h] = m;
+        maxf_le[h] = mf;
+    }
+    auto is_root = [&](int id, int h) {
+        const NdNode& nd = t.nodes[id];
+        return nd.height <= h && (nd.parent < 0 || t.nodes[nd.parent].height > h);
+    };
+    auto roots_at = [&](int h) {
+        int r = 0;
+        for (int id = 0; id < nn; ++id) r += is_root(id, h);
+        return r;
+    };
+    int hc = -1;
+    for (int want : {256, 64, 16, 1}) {
+        for (int h = H; h >= 0 && hc < 0; --h)
+            if (maxw_le[h] <= PLAN_SUB_MAXW && maxf_le[h] <= PLAN_SUB_MAXF && roots_at(h) >= want) hc = h;
+        if (hc >= 0) break;
+    }
+    p.hc = hc;
+    if (hc >= 0) {
+        for (int rt = 0; rt < nn; ++rt) {
+            if (!is_root(rt, hc)) continue;
+            std::vector<std::vector<int>> byh(hc + 1);
+            std::vector<int> stack{rt};
+            while (!stack.empty()) {
+                const int id = stack.back();
+                stack.pop_back();
+                byh[t.nodes[id].height].push_back(id);
+                for (int c = 0; c < 2; ++c)
+                    if (t.nodes[id].child[c] >= 0) stack.push_back(t.nodes[id].child[c]);
+            }
+            for (int h = 0; h <= hc; ++h) {
+                p.sub_hoff.push_back((int32_t)p.sub_nodes.size());
+                for (int id : byh[h]) p.sub_nodes.push_back(id);
+            }
+            p.sub_hoff.push_back((int32_t)p.sub_nodes.size());
+            ++p.n_sub;
+        }
+        p.sub_maxw = maxw_le[hc];
+    }
+
+    // ---- level phases above the cut ------------------------------------------
+    std::vector<std::pair<size_t, size_t>> fspan, bspan;
+    struct LdsSz { size_t f, b; };
+    std::vector<LdsSz> lds;
+    for (int h = hc + 1; h <= H; ++h) {
+        const size_t f0 = p.fwd_items.size();
+        size_t ldsf = 0;
+        for (int id : by_h[h]) {
+            const Front& fr = f.fronts[id];
+            const int nI = fr.nI, nF = fr.nI + fr.nB;
+            if (nI == 0) continue;
+            for (int r0 = 0; r0 < nF; r0 += PLAN_FWD_ROWS) {
+                const int nrows = std::min(PLAN_FWD_ROWS, nF - r0);
+                // own rows only need the columns c <= r
+                const int cmax = r0 < nI ? std::min(nI, r0 + nrows) : nI;
+                const int nparts = (cmax + PLAN_FWD_COLS - 1) / PLAN_FWD_COLS;
+                const int64_t part0 = p.scratch_size;
+                for (int k = 0; k < nparts; ++k) {
+                    TriItem it{};
+                    it.node = id;
+                    it.r0 = r0;
+                    it.nrows = nrows;
+                    it.cs = k * PLAN_FWD_COLS;
+                    it.ce = std::min(cmax, it.cs + PLAN_FWD_COLS);
+                    it.nparts = nparts;
+                    it.tile = p.n_tiles;
+                    it.part = part0 + (int64_t)k * PLAN_FWD_ROWS;
+                    it.part0 = part0;
+                    p.fwd_items.push_back(it);
+                    ldsf = std::max(ldsf, (size_t)(it.ce - it.cs) * sizeof(double));
+                }
+                if (nparts > 1) p.scratch_size += (int64_t)nparts * PLAN_FWD_ROWS;
+                ++p.n_tiles;
+            }
+        }
+        fspan.push_back({f0, p.fwd_items.size() - f0});
+        lds.push_back({ldsf, 0});
+    }
+    for (int h = hc + 1; h <= H; ++h) {
+        const size_t b0 = p.bwd_items.size();
+        size_t ldsb = 0;
+        for (int id : by_h[h]) {
+            const Front& fr = f.fronts[id];
+            const int nI = fr.nI, nF = fr.nI + fr.nB;
+            if (nI == 0) continue;
+            const int W = pow2_at_least(std::min(nI, 64), 64);
+            const int RB = std::min(PLAN_BWD_MAXR, std::max(64, 8192 / W));
+            for (int c0 = 0; c0 < nI; c0 += W) {
+                const int nparts = (nF - c0 + RB - 1) / RB;
+                const int64_t part0 = p.scratch_size;
+                for (int k = 0; k < nparts; ++k) {
+                    BwdItem b{};
+                    b.node = id;
+                    b.c0 = c0;
+                    b.ncols = std::min(W, nI - c0);
+                    b.W = W;
+                    b.rs = c0 + k * RB;
+                    b.re = std::min(nF, b.rs + RB);
+                    b.nparts = nparts;
+                    b.tile = p.n_tiles;
+                    b.part = part0 + (int64_t)k * W;
+                    b.part0 = part0;
+                    p.bwd_items.push_back(b);
+                    ldsb = std::max(ldsb, (size_t)(b.re - b.rs) * sizeof(double));
+                }
+                if (nparts > 1) p.scratch_size += (int64_t)nparts * W;
+                ++p.n_tiles;
+            }
+        }
+        bspan.push_back({b0, p.bwd_items.size() - b0});
+        lds[h - hc - 1].b = ldsb;
+    }
+    for (size_t k = 0; k < fspan.size(); ++k)
+        p.spans.push_back({fspan[k].first, fspan[k].second, bspan[k].first, bspan[k].second,
+                           lds[k].f, lds[k].b});
+
+    // ---- algorithmic bytes per height ------------------------------------------
+    p.fwd_bytes64.assign(H + 1, 0.0);
+    p.bwd_bytes64.assign(H + 1, 0.0);
+    p.fwd_bytes32.assign(H + 1, 0.0);
+    p.bwd_bytes32.assign(H + 1, 0.0);
+    for (int h = 0; h <= H; ++h)
+        for (int id : by_h[h]) {
+            const Front& fr = f.fronts[id];
+            const double pe = (double)fr.nI * (fr.nI + 1) / 2 + (double)fr.nB * fr.nI;
+            double cb = 0.0;
+            for (int c = 0; c < 2; ++c)
+                if (t.nodes[id].child[c] >= 0) cb += f.fronts[t.nodes[id].child[c]].nB;
+            // forward: panel + b_t + extend-add maps + children's updates + y_t + c_t
+            const double fv = 8.0 * (fr.nI + (fr.nI + fr.nB) + cb + fr.nI + fr.nB);
+            // backward: panel + y_t + boundary ids + x_B + x_t
+            const double bv = 8.0 * (fr.nI + 2.0 * fr.nB + fr.nI);
+            p.fwd_bytes64[h] += 8.0 * pe + fv;
+            p.bwd_bytes64[h] += 8.0 * pe + bv;
+            p.fwd_bytes32[h] += 4.0 * pe + fv;
+            p.bwd_bytes32[h] += 4.0 * pe + bv;
+        }
+    for (int h = 0; h <= hc; ++h) {
+        p.sub_fwd_bytes64 += p.fwd_bytes64[h];
+        p.sub_bwd_bytes64 += p.bwd_bytes64[h];
+        p.sub_fwd_bytes32 += p.fwd_bytes32[h];
+        p.sub_bwd_bytes32 += p.bwd_bytes32[h];
+    }
+    p.meta_bytes = (int64_t)(p.nodes.size() * sizeof(TriNode) + p.bidx.size() * 8 + p.ea.size() * 8 +
+                             p.fwd_items.size() * sizeof(TriItem) + p.bwd_items.size() * sizeof(BwdItem));
+    if (p.scratch_size > (int64_t)1 << 31) { err = "plan scratch too large"; return false; }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// CPU emulation: the per-node work of each kernel, in launch order, with
+// bounds-checked accesses.
+// ---------------------------------------------------------------------------
+namespace {
+
+int64_t col_off(int64_t c, int64_t nI, int64_t nB) { return c * (nI + nB) - c * (c - 1) / 2; }
+
+struct Emu {
+    const FactorPlan& p;
+    const double* b;
+    std::vector<double> y, upd, x, scratch;
+    std::vector<unsigned> counters;
+    explicit Emu(const FactorPlan& pl, const double* bb)
+        : p(pl), b(bb), y(pl.n, std::nan("")), upd(std::max<int64_t>(pl.upd_size, 1), std::nan("")),
+          x(pl.n, std::nan("")), scratch(std::max<int64_t>(pl.scratch_size, 1), std::nan("")),
+          counters(std::max(pl.n_tiles, 1), 0u) {}
+
+    int64_t upd_of(int child) const { return child >= 0 ? p.nodes.at(child).upd : 0; }
+
+    double gather_w(const TriNode& nd, int i) const {
+        const int64_t u0 = upd_of(nd.child[0]), u1 = upd_of(nd.child[1]);
+        double v = b[nd.off + i];
+        const Ea m = p.ea.at(nd.ea + i);
+        if (m.a >= 0) v -= upd.at(u0 + m.a);
+        if (m.b >= 0) v -= upd.at(u1 + m.b);
+        return (nd.off + i == p.ground) ? 0.0 : v;
+    }
+
+    // sum over columns [cs, ce) of P(r, c) w(c) from the column-major copy
+    double row_part(const TriNode& nd, int r, int cs, int ce, const std::vector<double>& w) const {
+        const int cend = r < nd.nI ? std::min(ce, r + 1) : ce;
+        double s = 0.0;
+        for (int c = cs; c < cend; ++c)
+            s += p.panel_cm.at(nd.panel + col_off(c, nd.nI, nd.nB) + (r - c)) * w.at(c - cs);
+        return s;
+    }
+
+    void store_row(const TriNode& nd, int r, double s) {
+        if (r < nd.nI) {
+            y.at(nd.off + r) = s;
+        } else {
+            const Ea m = p.ea.at(nd.ea + r);
+            if (m.a >= 0) s += upd.at(upd_of(nd.child[0]) + m.a);
+            if (m.b >= 0) s += upd.at(upd_of(nd.child[1]) + m.b);
+            upd.at(nd.upd + (r - nd.nI)) = s;
+        }
+    }
+
+    double z_of(const TriNode& nd, int r) const {
+        return r < nd.nI ? y.at(nd.off + r) : -x.at(p.bidx.at(nd.bidx + (r - nd.nI)));
+    }
+
+    // sum over rows [rs, re) of P(r, c) z(r) from the row-major copy
+    double col_part(const TriNode& nd, int c, int rs, int re, const std::vector<double>& z, int z0) const {
+        const int nI = nd.nI;
+        double s = 0.0;
+        for (int r = std::max(rs, c); r < re; ++r)
+            s += p.panel.at(nd.panel + panel_row_off(r, nI) + c) * z.at(r - z0);
+        return s;
+    }
+
+    void fwd_sub() {
+        for (int s = 0; s < p.n_sub; ++s) {
+            const int32_t* hoff = &p.sub_hoff.at((size_t)s * (p.hc + 2));
+            for (int h = 0; h <= p.hc; ++h)
+                for (int k = hoff[h]; k < hoff[h + 1]; ++k) {
+                    const TriNode& nd = p.nodes.at(p.sub_nodes.at(k));
+                    if (nd.nI > PLAN_SUB_MAXW || nd.nI + nd.nB > PLAN_SUB_MAXF)
+                        throw std::runtime_error("subtree node too large");
+                    std::vector<double> w(nd.nI);
+                    for (int i = 0; i < nd.nI; ++i) w[i] = gather_w(nd, i);
+                    std::vector<double> out(nd.nI + nd.nB);
+                    for (int r = 0; r < nd.nI + nd.nB; ++r) out[r] = row_part(nd, r, 0, nd.nI, w);
+                    for (int r = 0; r < nd.nI + nd.nB; ++r) store_row(nd, r, out[r]);
+                }
+        }
+    }
+
+    void bwd_sub() {
+        for (int s = 0; s < p.n_sub; ++s) {
+            const int32_t* hoff = &p.sub_hoff.at((size_t)s * (p.hc + 2));
+            for (int h = p.hc; h >= 0; --h)
+                for (int k = hoff[h]; k < hoff[h + 1]; ++k) {
+                    const TriNode& nd = p.nodes.at(p.sub_nodes.at(k));
+                    const int nF = nd.nI + nd.nB;
+                    std::vector<double> z(nF);
+                    for (int r = 0; r < nF; ++r) z[r] = z_of(nd, r);
+                    for (int c = 0; c < nd.nI; ++c) x.at(nd.off + c) = col_part(nd, c, 0, nF, z, 0);
+                }
+        }
+    }
+
+    void fwd_lvl(const FactorPlan::Span& sp) {
+        for (size_t q = sp.f0; q < sp.f0 + sp.nf; ++q) {
+            const TriItem it = p.fwd_items.at(q);
+            const TriNode& nd = p.nodes.at(it.node);
+            if ((size_t)(it.ce - it.cs) * 8 > sp.lds_f) throw std::runtime_error("forward LDS too small");
+            if (it.nrows > PLAN_FWD_ROWS) throw std::runtime_error("forward row tile too large");
+            std::vector<double> w(it.ce - it.cs);
+            for (int i = it.cs; i < it.ce; ++i) w[i - it.cs] = gather_w(nd, i);
+            std::vector<double> s(PLAN_FWD_ROWS, 0.0);
+            for (int l = 0; l < it.nrows; ++l) s[l] = row_part(nd, it.r0 + l, it.cs, it.ce, w);
+            if (it.nparts == 1) {
+                for (int l = 0; l < it.nrows; ++l) store_row(nd, it.r0 + l, s[l]);
+                continue;
+            }
+            for (int l = 0; l < PLAN_FWD_ROWS; ++l) scratch.at(it.part + l) = s[l];
+            if (++counters.at(it.tile) == (unsigned)it.nparts) {
+                for (int l = 0; l < it.nrows; ++l) {
+                    double t = 0.0;
+                    for (int k = 0; k < it.nparts; ++k) t += scratch.at(it.part0 + (int64_t)k * PLAN_FWD_ROWS + l);
+                    store_row(nd, it.r0 + l, t);
+                }
+                counters.at(it.tile) = 0;
+            }
+        }
+    }
+
+    void bwd_lvl(const FactorPlan::Span& sp) {
+        for (size_t q = sp.b0; q < sp.b0 + sp.nb; ++q) {
+            const BwdItem it = p.bwd_items.at(q);
+            const TriNode& nd = p.nodes.at(it.node);
+            if ((size_t)(it.re - it.rs) * 8 > sp.lds_b) throw std::runtime_error("backward LDS too small");
+            std::vector<double> z(it.re - it.rs);
+            for (int r = it.rs; r < it.re; ++r) z[r - it.rs] = z_of(nd, r);
+            std::vector<double> s(it.W, 0.0);
+            for (int col = 0; col < it.ncols; ++col) s[col] = col_part(nd, it.c0 + col, it.rs, it.re, z, it.rs);
+            if (it.nparts == 1) {
+                for (int col = 0; col < it.ncols; ++col) x.at(nd.off + it.c0 + col) = s[col];
+                continue;
+            }
+            for (int col = 0; col < it.W; ++col) scratch.at(it.part + col) = s[col];
+            if (++counters.at(it.tile) == (unsigned)it.nparts) {
+                for (int col = 0; col < it.ncols; ++col) {
+                    double t = 0.0;
+                    for (int k = 0; k < it.nparts; ++k) t += scratch.at(it.part0 + (int64_t)k * it.W + col);
+                    x.at(nd.off + it.c0 + col) = t;
+                }
+                counters.at(it.tile) = 0;
+            }
+        }
+    }
+};
+
+}  // namespace
+
+void emulate_plan(const FactorPlan& p, const double* b, double* x) {
+    Emu e(p, b);
+    e.fwd_sub();
+    for (const auto& sp : p.spans) e.fwd_lvl(sp);
+    for (size_t k = p.spans.size(); k-- > 0;) e.bwd_lvl(p.spans[k]);
+    e.bwd_sub();
+    for (int64_t i = 0; i < p.n; ++i) x[i] = e.x[i];
+}
+
+}  // namespace bido

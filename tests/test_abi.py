@@ -131,3 +131,21 @@ def test_bad_inputs_are_rejected():
     no_heart["region"] = np.zeros_like(cfg["region"])
     with pytest.raises(B.BidoError):
         B.HostSetup(no_heart)
+
+
+@pytest.mark.parametrize("mk", [lambda: w.square2d(n=48), lambda: w.slab3d(n=12),
+                                lambda: w.thorax2d(n_target=40000, seed=12)])
+def test_device_plan_emulation_matches_host_factor(mk):
+    """The device execution plan of each factor (subtree phase, level phases
+    with split tiles) run by a bounds-checked CPU emulation of the sweep
+    kernels reproduces the host application of the same factor."""
+    import paper_1711_08708_amd as B
+    cfg = mk()
+    hs = B.HostSetup(cfg, eps_h=0.0)
+    for which, idx in ((B.FACTOR_P1, B.IDX_UPOS), (B.FACTOR_PK, B.IDX_VPOS)):
+        n = len(hs.index(idx))
+        b = np.random.default_rng(which).normal(size=n)
+        ref = hs.factor_apply(which, b)
+        emu = hs.factor_emulate(which, b)
+        assert np.isfinite(emu).all()
+        assert np.abs(emu - ref).max() <= 1e-13 * np.abs(ref).max()

@@ -65,7 +65,7 @@ def _check_solve(torch, cfg, method="auto", **params):
     lambda: w.square2d(n=48),           # the 2,401-vertex square (ragged leaves)
     lambda: w.thorax2d(n_target=3000, seed=11),
     lambda: w.slab3d(n=6),
-])
+], ids=["square5", "square48", "thorax3000", "slab6"])
 def test_solve_parity_exact_factor(torch, mk):
     _check_solve(torch, mk(), eps_h=0.0, tol=1e-12)
 
