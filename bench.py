@@ -38,7 +38,12 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the sampled parity check")
     ap.add_argument("--cpu-steps", type=int, default=2)
-    ap.add_argument("--variants", action="store_true", help="also time the mixed variant")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the mixed / learned / learned+mixed comparison")
+    ap.add_argument("--collect-steps", type=int, default=40,
+                    help="plain steps whose CG iterations provide training pairs")
+    ap.add_argument("--variant-steps", type=int, default=50)
+    ap.add_argument("--epochs", type=int, default=30)
     return ap.parse_args()
 
 
@@ -147,14 +152,51 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_steps)
 
-    if args.variants and prec == B.PREC_FP64:
-        solver.set_precision(B.PREC_MIXED)
-        v3, h3, u3 = [t.clone() for t in saved]
-        gs, ws, it3 = _timed_steps(torch, solver, (v3, h3, u3), n0, args.steps)
-        result["variants"] = {"mixed": {"steps_per_s": round(args.steps / ws, 3),
-                                        "cg_iterations_per_step": round(it3 / args.steps, 3)}}
-        solver.set_precision(B.PREC_FP64)
+    if not args.no_variants:
+        result["variants"] = _variants(torch, B, solver, args)
     print(json.dumps(result), flush=True)
+
+
+def _variants(torch, B, solver, args):
+    """Plain FP64 vs mixed vs learned vs learned+mixed on the same steps.
+
+    The learned correction is trained on pairs recorded during the first
+    `collect_steps` plain steps from rest; all four variants then run the
+    following `variant_steps` steps from the same saved state."""
+    out = {}
+    v, h, u = solver.state()
+    solver.set_precond(B.PRECOND_PLAIN)
+    solver.set_precision(B.PREC_FP64)
+    t0 = time.perf_counter()
+    col = solver.learn_collect(v, h, u, 0, args.collect_steps, max_samples=16 * args.collect_steps)
+    t_col = time.perf_counter() - t0
+    n_val = max(1, col["samples"] // 10)
+    ts = solver.learn_train(epochs=args.epochs, batch=8, lr=2e-3, seed=0, n_val=n_val)
+    out["training"] = {"collect_steps": args.collect_steps, "pairs": col["samples"],
+                       "collect_s": round(t_col, 3), "train_s": round(ts["seconds"], 3),
+                       "epochs": args.epochs, "loss_zero": round(ts["loss_zero"], 3),
+                       "loss_trained": round(ts["loss_last"], 3),
+                       "loss_zero_val": round(ts["loss_zero_val"], 3),
+                       "loss_val": round(ts["loss_val"], 3)}
+    saved = [t.clone() for t in (v, h, u)]
+    n1 = args.collect_steps
+    for name, prec, pc in (("plain_fp64", B.PREC_FP64, B.PRECOND_PLAIN),
+                           ("mixed", B.PREC_MIXED, B.PRECOND_PLAIN),
+                           ("learned_fp64", B.PREC_FP64, B.PRECOND_LEARNED),
+                           ("learned_mixed", B.PREC_MIXED, B.PRECOND_LEARNED)):
+        solver.set_precision(prec)
+        solver.set_precond(pc)
+        st = [t.clone() for t in saved]
+        _, ws, it = _timed_steps(torch, solver, st, n1, args.variant_steps)
+        out[name] = {"steps_per_s": round(args.variant_steps / ws, 3),
+                     "cg_iterations_per_step": round(it / args.variant_steps, 3)}
+    base = out["plain_fp64"]["steps_per_s"]
+    for name in ("mixed", "learned_fp64", "learned_mixed"):
+        out[name]["speedup_vs_plain"] = round(out[name]["steps_per_s"] / base, 3)
+    out["steps"] = [n1, n1 + args.variant_steps]
+    solver.set_precision(B.PREC_FP64)
+    solver.set_precond(B.PRECOND_PLAIN)
+    return out
 
 
 def _cpu_baseline(cfg, n_steps):

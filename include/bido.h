@@ -192,6 +192,56 @@ bido_status bido_set_solver(bido_ctx* ctx, double tol, int max_iter);
  * point for the triangular sweeps; the solve path does not call it.      */
 bido_status bido_inner_solve(bido_ctx* ctx, int which, const double* b, double* x);
 
+/* --- learned correction of the Schur-complement block (flexible CG) ----- *
+ * A two-layer message-passing network delta(t) on the heart vertices (the
+ * S_m pattern as graph, hidden width 32, BF16 weights and activations, FP32
+ * accumulation) is added to P_K^-1 t in the preconditioner of Def. 2.  It
+ * is trained on pairs (t_k, (V* - V_k) - Z2_k) that plain solves record.
+ * An untrained network outputs zero; an apply that is not a descent
+ * direction is redone without it (bido_stats.fallbacks).                  */
+/* Losses are per sample: r^T W r with r the error of the predicted
+ * correction in units of the RMS training target (the network's output
+ * unit) and W = K_m scaled to unit mean diagonal, the energy that the
+ * correction error leaves in the Schur-complement block.                 */
+typedef struct {
+    int samples, train_samples, epochs;
+    double loss_zero;       /* mean loss of the zero correction (training)   */
+    double loss_zero_val;   /* the same on the validation samples            */
+    double loss_first;      /* mean training loss before training            */
+    double loss_last;       /* mean training loss after training             */
+    double loss_val;        /* mean validation loss after training           */
+    double seconds;
+} bido_train_stats;
+
+/* BIDO_PRECOND_PLAIN or BIDO_PRECOND_LEARNED for later solves.            */
+bido_status bido_set_precond(bido_ctx* ctx, int precond);
+
+/* Run n_steps plain steps (as bido_run) recording training pairs, up to
+ * max_samples in total (device memory: 8 N_H bytes per sample).            */
+bido_status bido_learn_collect(bido_ctx* ctx, double* v, double* w, double* u, double dt,
+                               int64_t n0, int64_t n_steps, int max_samples, bido_stats* st);
+bido_status bido_learn_samples(const bido_ctx* ctx, int* n_samples);
+
+/* Adam on the FP32 master weights over the first (samples - n_val) pairs,
+ * mini-batches of `batch`, shuffled by `seed`; the last n_val pairs are
+ * held out for the validation loss.                                        */
+bido_status bido_learn_train(bido_ctx* ctx, int epochs, int batch, float lr, uint64_t seed,
+                             int n_val, bido_train_stats* st);
+
+/* FP32 master weights (3169 floats, layout W1s W1n b1 W2s W2n b2 w3 b3):
+ * dir 0 copies them to buf, dir 1 loads buf (and resets Adam and the output
+ * unit to 1).                                                             */
+bido_status bido_weights_io(bido_ctx* ctx, float* buf, int n, int dir);
+
+/* Check entry points (not used by the solve path).  gnn_eval: out = delta(t)
+ * for a device vector t in heart-local order.  gnn_loss_grad: for device
+ * inputs t/rms(t) and target/rms(t) (FP32, heart-local; rms(t) =
+ * |t|_2 / sqrt(N_H)) the loss r^T W r (r = o - y, W as above) and its
+ * gradient (host outputs), with the output unit 1.                        */
+bido_status bido_gnn_eval(bido_ctx* ctx, const double* t, double* out);
+bido_status bido_gnn_loss_grad(bido_ctx* ctx, const float* that, const float* y, double* loss,
+                               float* grad);
+
 /* Per-kernel profile: launches, summed event-timed duration [ms] and the
  * algorithmic bytes those launches must move (inputs read once, outputs
  * written once), aggregated by kernel class.                            */

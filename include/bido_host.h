@@ -25,9 +25,13 @@ typedef struct bido_host bido_host;
 #define BIDO_MAT_SI     1  /* S_i, heart-local numbering, N_H x N_H           */
 #define BIDO_MAT_SM     2  /* S_m, heart-local numbering                      */
 #define BIDO_MAT_LAMBDA 3  /* Lambda in the internal order (u then v)         */
+#define BIDO_MAT_GNN_AGG 4 /* neighbour weights of the learned correction,
+                              heart-local: |S_m,ij| / sum_k!=i |S_m,ik|, j != i */
 
 #define BIDO_VEC_M      0  /* lumped M, global numbering                      */
 #define BIDO_VEC_MH     1  /* lumped M_H, heart-local numbering               */
+#define BIDO_VEC_GNN_STATIC 2 /* static vertex features of the learned
+                                 correction, N_H x 15 row-major, heart-local  */
 
 #define BIDO_IDX_UPOS   0  /* global id -> internal u index                    */
 #define BIDO_IDX_VPOS   1  /* heart-local index -> internal v index            */

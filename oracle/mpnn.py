@@ -10,7 +10,7 @@ Graph: the heart vertices with the sparsity pattern of S_m (Sec. 5.2).
 Edge weights a_ij = |S_m,ij| / sum_{k != i} |S_m,ik| for j != i.
 
 Per-vertex input features (F = 16, zero padded):
-  0            t_i / |t|_2                       (the vector being corrected)
+  0            t_i / rms(t), rms(t) = |t|_2 / sqrt(N_H)   (the corrected vector)
   1..         mean over the incident heart elements of the entries of sigma_i
               then of sigma_e (2D: xx, xy, yy; 3D: xx, xy, xz, yy, yz, zz),
               divided by the largest diagonal conductivity value
@@ -19,9 +19,11 @@ Per-vertex input features (F = 16, zero padded):
 Network (hidden width 32, ReLU):
   m0 = A f,   h1 = relu(W1s f + W1n m0 + b1)
   m1 = A h1,  h2 = relu(W2s h1 + W2n m1 + b2)
-  o  = w3 . h2 + b3,     delta = |t|_2 * o
+  o  = w3 . h2 + b3,     delta = rms(t) * o
 
-Loss of one sample (t, target): sum_i (o_i - target_i / |t|)^2.
+Loss of one sample (t, target), with r = o - target / rms(t):
+  r^T W r,  W = K_m / mean(diag K_m)   (energy of the correction error)
+or r^T r when no weight matrix is given.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -98,7 +100,7 @@ def static_features(cfg, Sm):
     scale = max(np.max(cfg["sigma_i"]), np.max(cfg["sigma_e"]))
     acc /= scale
     # hop distance to the heart boundary over the S_m graph
-    G = sp.csr_matrix(Sm)
+    G = abs(sp.csr_matrix(Sm))
     b = heart_boundary_vertices(cfg)
     dist = csg.dijkstra(G, unweighted=True, indices=b, min_only=True)
     dist = dist / max(dist.max(), 1.0)
@@ -109,11 +111,12 @@ def static_features(cfg, Sm):
 
 
 def features(t, static):
-    nt = np.linalg.norm(t)
+    """Input features and rms(t) (the output scale of delta)."""
+    rms = np.linalg.norm(t) / np.sqrt(len(t))
     f = np.zeros((len(t), F))
-    f[:, 0] = t / nt if nt > 0 else 0.0
+    f[:, 0] = t / rms if rms > 0 else 0.0
     f[:, 1:] = static
-    return f, nt
+    return f, rms
 
 
 def forward(theta, A, f):
@@ -129,13 +132,20 @@ def forward(theta, A, f):
     return o, cache
 
 
-def loss_and_grad(theta, A, f, y):
-    """Loss sum_i (o_i - y_i)^2 and its gradient with respect to theta."""
+def energy_weight(Km):
+    """K_m scaled to unit mean diagonal: the norm of the training loss."""
+    Km = sp.csr_matrix(Km)
+    return Km / Km.diagonal().mean()
+
+
+def loss_and_grad(theta, A, f, y, W=None):
+    """Loss r^T W r (or r^T r), r = o - y, and its gradient w.r.t. theta."""
     p = unpack(theta)
     o, c = forward(theta, A, f)
     r = o - y
-    loss = float(r @ r)
-    do = 2.0 * r
+    Wr = r if W is None else W @ r
+    loss = float(r @ Wr)
+    do = 2.0 * Wr
     g = {}
     g["w3"] = c["h2"].T @ do
     g["b3"] = np.array([do.sum()])

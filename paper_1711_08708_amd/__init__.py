@@ -19,8 +19,8 @@ ERRORS = {-1: "BIDO_ERR_ARG", -2: "BIDO_ERR_DEVICE", -3: "BIDO_ERR_NOT_SPD",
           -6: "BIDO_ERR_RANGE", -7: "BIDO_ERR_STATE"}
 PREC_FP64, PREC_MIXED = 0, 1
 PRECOND_PLAIN, PRECOND_LEARNED = 0, 1
-MAT_S1, MAT_SI, MAT_SM, MAT_LAMBDA = 0, 1, 2, 3
-VEC_M, VEC_MH = 0, 1
+MAT_S1, MAT_SI, MAT_SM, MAT_LAMBDA, MAT_GNN_AGG = 0, 1, 2, 3, 4
+VEC_M, VEC_MH, VEC_GNN_STATIC = 0, 1, 2
 IDX_UPOS, IDX_VPOS, IDX_HEART = 0, 1, 2
 FACTOR_P1, FACTOR_PK = 0, 1
 
@@ -74,6 +74,19 @@ class Info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TrainStats(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int), ("train_samples", ctypes.c_int), ("epochs", ctypes.c_int),
+                ("loss_zero", ctypes.c_double), ("loss_zero_val", ctypes.c_double),
+                ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("loss_val", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+GNN_P = 3169
+
+
 class KProf(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
                 ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -102,6 +115,18 @@ ABI = {
     "bido_set_solver": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]),
     "bido_inner_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p]),
+    "bido_set_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "bido_learn_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
+                                          ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Stats)]),
+    "bido_learn_samples": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
+    "bido_learn_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                                        ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(TrainStats)]),
+    "bido_weights_io": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int,
+                                       ctypes.c_int]),
+    "bido_gnn_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bido_gnn_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)]),
     "bido_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KProf), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int)]),
@@ -269,6 +294,52 @@ class Solver:
     def inner_solve(self, which, b, x):
         n = self.N if which == FACTOR_P1 else self.NH
         _check(lib.bido_inner_solve(self.ctx, int(which), self._dev(b, n), self._dev(x, n)))
+
+    # ---- learned correction -------------------------------------------------
+    def set_precond(self, precond):
+        _check(lib.bido_set_precond(self.ctx, int(precond)))
+
+    def learn_collect(self, v, w, u, n0, n_steps, max_samples):
+        st = Stats()
+        _check(lib.bido_learn_collect(self.ctx, self._dev(v, self.NH), self._dev(w, self.NH),
+                                      self._dev(u, self.N), self.dt, int(n0), int(n_steps),
+                                      int(max_samples), ctypes.byref(st)))
+        n = ctypes.c_int()
+        _check(lib.bido_learn_samples(self.ctx, ctypes.byref(n)))
+        d = st.as_dict()
+        d["samples"] = n.value
+        return d
+
+    def learn_train(self, epochs=20, batch=8, lr=1e-3, seed=0, n_val=0):
+        ts = TrainStats()
+        _check(lib.bido_learn_train(self.ctx, int(epochs), int(batch), float(lr), int(seed), int(n_val),
+                                    ctypes.byref(ts)))
+        return ts.as_dict()
+
+    def weights(self):
+        buf = (ctypes.c_float * GNN_P)()
+        _check(lib.bido_weights_io(self.ctx, buf, GNN_P, 0))
+        return np.ctypeslib.as_array(buf).astype(np.float64).copy()
+
+    def set_weights(self, theta):
+        buf = (ctypes.c_float * GNN_P)(*np.asarray(theta, dtype=np.float32).tolist())
+        _check(lib.bido_weights_io(self.ctx, buf, GNN_P, 1))
+
+    def gnn_eval(self, t):
+        out = self.torch.zeros_like(t)
+        _check(lib.bido_gnn_eval(self.ctx, self._dev(t, self.NH), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def gnn_loss_grad(self, that, y):
+        torch = self.torch
+        for a in (that, y):
+            if not (a.is_cuda and a.dtype == torch.float32 and a.numel() == self.NH and a.is_contiguous()):
+                raise BidoError(-1, "expected contiguous float32 CUDA tensors of N_H entries")
+        loss = ctypes.c_double()
+        grad = (ctypes.c_float * GNN_P)()
+        _check(lib.bido_gnn_loss_grad(self.ctx, ctypes.c_void_p(that.data_ptr()),
+                                      ctypes.c_void_p(y.data_ptr()), ctypes.byref(loss), grad))
+        return loss.value, np.ctypeslib.as_array(grad).astype(np.float64).copy()
 
     def set_precision(self, precision):
         _check(lib.bido_set_precision(self.ctx, int(precision)))

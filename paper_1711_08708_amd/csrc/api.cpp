@@ -17,10 +17,12 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <random>
 #include <string>
 #include <vector>
 
 #include "../../include/bido.h"
+#include "gnn.h"
 #include "launch.h"
 #include "plan.h"
 #include "setup.h"
@@ -60,10 +62,10 @@ int pow2_at_least(int n, int cap) {
 
 // Kernel classes of the optional per-launch profiler.
 enum KClass { K_SPMV_LAMBDA = 0, K_PCG_UPDATE, K_COMBINE_DOT, K_P_UPDATE, K_TRI_FWD_SUB,
-              K_TRI_FWD_LVL, K_TRI_BWD_SUB, K_TRI_BWD_LVL, K_SPMV_CSR, K_IONIC, K_MISC, K_NCLASS };
+              K_TRI_FWD_LVL, K_TRI_BWD_SUB, K_TRI_BWD_LVL, K_SPMV_CSR, K_IONIC, K_GNN, K_MISC, K_NCLASS };
 const char* const kclass_name[K_NCLASS] = {"spmv_lambda", "pcg_update", "combine_dot", "p_update",
                                            "tri_fwd_sub", "tri_fwd_lvl", "tri_bwd_sub", "tri_bwd_lvl",
-                                           "spmv_csr", "ionic_rhs", "misc"};
+                                           "spmv_csr", "ionic_rhs", "gnn_infer", "misc"};
 
 // Per-launch HIP-event timing with the algorithmic bytes of each launch.
 struct Profiler {
@@ -193,6 +195,40 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd) {
     return BIDO_OK;
 }
 
+// Device state of the learned correction (see gnn.h).
+struct GnnState {
+    float* stat = nullptr;                 // N_H x 16 features, internal v order
+    GnnGraph A, At;                        // neighbour weights and their transpose
+    GnnGraph Wk;                           // K_m / mean diag: norm of the training loss
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    uint16_t* wbf = nullptr;               // BF16 working weights
+    GnnAct act;
+    float* partials = nullptr;
+    double* dloss = nullptr;
+    float *ft = nullptr, *fy = nullptr;    // check-entry buffers (internal order)
+    double* tz = nullptr;
+    // training samples: t/|t| and target/|t| (FP32), |t|^2 (FP64)
+    int max_samples = 0, n_samples = 0;
+    float *s_t = nullptr, *s_y = nullptr;
+    double* s_tn2 = nullptr;
+    double* pend = nullptr;                // V_k + Z2_k of the running solve
+    int max_pending = 64, n_pending = 0;
+    bool collecting = false;
+    int adam_step = 0;
+    float out_scale = 1.0f;                // output unit: RMS of the training targets
+    void release() {
+        for (void* b : {(void*)stat, (void*)A.ptr, (void*)A.col, (void*)A.val, (void*)At.ptr, (void*)At.col,
+                        (void*)At.val, (void*)Wk.ptr, (void*)Wk.col, (void*)Wk.val, (void*)act.res,
+                        (void*)act.zero, (void*)theta, (void*)m, (void*)v, (void*)grad, (void*)wbf,
+                        (void*)act.f, (void*)act.m0, (void*)act.h1, (void*)act.m1, (void*)act.h2,
+                        (void*)act.o, (void*)act.dout, (void*)act.dz2, (void*)act.g2, (void*)act.dz1,
+                        (void*)partials, (void*)dloss, (void*)ft, (void*)fy, (void*)tz, (void*)s_t,
+                        (void*)s_y, (void*)s_tn2, (void*)pend})
+            hipFree(b);
+        *this = GnnState();
+    }
+};
+
 }  // namespace
 
 struct bido_ctx {
@@ -215,11 +251,15 @@ struct bido_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<int64_t> heart_ids;
     Profiler prof;
+    GnnState gnn;
+    int precond = BIDO_PRECOND_PLAIN;
+    int fallbacks = 0;
 
     ~bido_ctx() {
         if (stream) hipStreamSynchronize(stream);
         p1.release();
         pk.release();
+        gnn.release();
         CsrHostView::release(lam);
         CsrHostView::release(avu);
         CsrHostView::release(auv);
@@ -309,10 +349,13 @@ void debug_check(bido_ctx* c, const char* name, const double* v, int64_t n) {
                  (long long)n, (long long)bad, (long long)first, mx);
 }
 
-// z = P_Lambda^-1 r  and  rho_new = r.z  (plus z.r_old for flexible CG)
-void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old) {
+// z = P_Lambda^-1 r  and  rho_new = r.z  (plus z.r_old for flexible CG).
+// learned: add the network's correction to Z2 (Schur-complement block);
+// collecting: record (t, V_k + Z2_k) for training targets.
+void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old, bool learned) {
     hipStream_t s = c->stream;
-    const int64_t N = c->N;
+    const int64_t N = c->N, NH = c->NH;
+    GnnState& g = c->gnn;
     debug_check(c, "r", r, c->n2);
     inner_solve(c, c->p1, r, c->tA);                                 // Z1 = P1^-1 R1
     debug_check(c, "Z1", c->tA, N);
@@ -321,6 +364,19 @@ void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old)
     debug_check(c, "t", c->tB, c->NH);
     inner_solve(c, c->pk, c->tB, z + N);                             // Z2 = PK^-1 (...)
     debug_check(c, "Z2", z + N, c->NH);
+    if (g.collecting && g.n_samples + g.n_pending < g.max_samples && g.n_pending < g.max_pending) {
+        const int k = g.n_samples + g.n_pending;
+        launch_dot_reduce(s, NH, c->tB, c->tB, c->rd, g.s_tn2 + k);
+        launch_gnn_store_sample(s, NH, c->tB, g.s_tn2 + k, g.s_t + (int64_t)k * NH);
+        launch_gnn_pending(s, NH, c->x + N, z + N, g.pend + (int64_t)g.n_pending * NH);
+        ++g.n_pending;
+    }
+    if (learned) {
+        PROF(c, K_MISC, 16.0 * NH, launch_dot_reduce(s, NH, c->tB, c->tB, c->rd, c->sc + S_TN2));
+        PROF(c, K_GNN, 200.0 * NH,
+             launch_gnn_forward(s, NH, c->tB, c->sc + S_TN2, g.stat, g.A, g.wbf, g.act, 0, z + N,
+                                g.out_scale));
+    }
     PROF(c, K_SPMV_CSR, csr_bytes(c->auv, c->NH),
          launch_spmv_csr(s, c->auv, c->spmv_group, z + N, nullptr, c->tC));   // Pi^T S_i Z2
     debug_check(c, "PiSZ2", c->tC, N);
@@ -336,12 +392,30 @@ bido_status read_scalars(bido_ctx* c) {
     return BIDO_OK;
 }
 
-// PCG on the internal vectors: x (initial guess in, solution out), Y.
+// PCG on the internal vectors: x (initial guess in, solution out), Y.  With a
+// nonlinear or inexact preconditioner (learned correction, mixed precision)
+// the direction update is the flexible (Polak-Ribiere) one.  A learned
+// apply that is not a descent direction (r.z <= 0) is redone without the
+// correction and counted as a fallback.
 bido_status pcg(bido_ctx* c, double tol, bido_stats* st) {
     hipStream_t s = c->stream;
     const int64_t n = c->n2;
-    const bool flexible = c->precision == BIDO_PREC_MIXED;
+    const bool learned = c->precond == BIDO_PRECOND_LEARNED && !c->gnn.collecting;
+    const bool flexible = c->precision == BIDO_PREC_MIXED || learned;
     double* r_old = flexible ? c->r_old : nullptr;
+    int fallbacks = 0;
+    auto apply = [&](const double* ro) -> bido_status {
+        precond_apply(c, c->r, c->z, ro, learned);
+        if (!learned) return BIDO_OK;
+        bido_status e2 = read_scalars(c);
+        if (e2) return e2;
+        const double rz = c->sc_host[S_RHO_NEW];
+        if (!(rz > 0.0) || !std::isfinite(rz)) {
+            ++fallbacks;
+            precond_apply(c, c->r, c->z, ro, false);
+        }
+        return BIDO_OK;
+    };
     PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n) + 8.0 * n,
          launch_spmv_lambda(s, c->lam, c->spmv_group, 1, c->x, c->Y, c->r, c->rd, c->sc));
     bido_status e = read_scalars(c);
@@ -352,7 +426,7 @@ bido_status pcg(bido_ctx* c, double tol, bido_stats* st) {
     bool conv = rel <= tol || yy == 0.0;
     if (yy == 0.0) launch_fill(s, n, c->x, 0.0);
     if (!conv) {
-        precond_apply(c, c->r, c->z, nullptr);
+        if ((e = apply(nullptr))) return e;
         PROF(c, K_P_UPDATE, 24.0 * n, launch_p_update(s, n, c->z, c->p, c->sc, 1, 0));
         for (it = 1; it <= c->params.max_iter; ++it) {
             PROF(c, K_MISC, 16.0, launch_copy_scalar(s, c->sc, S_RHO, S_RHO_NEW));
@@ -364,22 +438,38 @@ bido_status pcg(bido_ctx* c, double tol, bido_stats* st) {
             const double pq = c->sc_host[S_PQ], rho = c->sc_host[S_RHO];
             rel = std::sqrt(c->sc_host[S_RR] / yy);
             if (!(pq > 0.0) || !(rho > 0.0) || !std::isfinite(rel)) {
-                if (st) { st->iterations = it; st->rel_residual = rel; st->converged = 0; }
+                if (st) { st->iterations = it; st->rel_residual = rel; st->converged = 0; st->fallbacks = fallbacks; }
                 return fail(BIDO_ERR_NOT_SPD, "CG breakdown (p.Ap = " + std::to_string(pq) +
                                                   ", r.z = " + std::to_string(rho) + ")");
             }
             if (rel <= tol) { conv = true; break; }
-            precond_apply(c, c->r, c->z, r_old);
+            if ((e = apply(r_old))) return e;
             PROF(c, K_P_UPDATE, 24.0 * n, launch_p_update(s, n, c->z, c->p, c->sc, 0, flexible ? 1 : 0));
         }
         if (it > c->params.max_iter) it = c->params.max_iter;
     }
+    c->fallbacks += fallbacks;
     if (st) {
         st->iterations = it;
         st->rel_residual = rel;
         st->converged = conv ? 1 : 0;
+        st->fallbacks = fallbacks;
     }
     return conv ? BIDO_OK : fail(BIDO_ERR_NOT_CONVERGED, "tolerance not reached within max_iter");
+}
+
+// After a converged solve while collecting: targets (V* - V_k - Z2_k) / |t_k|.
+void finish_collection(bido_ctx* c, bool converged) {
+    GnnState& g = c->gnn;
+    if (!g.collecting) return;
+    if (converged)
+        for (int k = 0; k < g.n_pending; ++k) {
+            const int slot = g.n_samples + k;
+            launch_gnn_finish_targets(c->stream, c->NH, c->x + c->N, g.pend + (int64_t)k * c->NH,
+                                      g.s_tn2 + slot, g.s_y + (int64_t)slot * c->NH);
+        }
+    if (converged) g.n_samples += g.n_pending;
+    g.n_pending = 0;
 }
 
 IonicConst ionic_consts(const bido_ctx* c) {
@@ -409,11 +499,98 @@ bido_status step_once(bido_ctx* c, double* v, double* w, double* u, int64_t n, b
                       ionic_consts(c)));                               // Steps 1 and 3
     PROF(c, K_MISC, 8.0 * N, launch_fill(s, N, c->Y, 0.0));           // Y1 = 0
     bido_status e = pcg(c, c->params.tol, st);                         // Step 2
+    finish_collection(c, e == BIDO_OK);
     if (e && e != BIDO_ERR_NOT_CONVERGED) return e;
     PROF(c, K_MISC, 16.0 * N, launch_dot_reduce(s, N, c->m_int, c->x, c->rd, c->sc + S_MU));  // (M U, 1)
     PROF(c, K_MISC, 24.0 * N, launch_gather_out(s, N, c->u_pos, c->x, u, c->sc, S_MU, c->hs.msum));
     PROF(c, K_MISC, 24.0 * NH, launch_gather_out(s, NH, c->v_pos, c->x + N, v, c->sc, -1, 1.0));
     return e;
+}
+
+bido_status gnn_setup(bido_ctx* c) {
+    GnnState& g = c->gnn;
+    const HostSetup& hs = c->hs;
+    const int64_t NH = c->NH;
+    std::vector<float> stat((size_t)NH * GNN_F, 0.0f);
+    for (int64_t k = 0; k < NH; ++k)
+        for (int j = 1; j < GNN_F; ++j) stat[hs.v_pos[k] * GNN_F + j] = (float)hs.gnn_static[k * 15 + j - 1];
+    HIP_OK(upload(&g.stat, stat.data(), stat.size()));
+    // neighbour weights in internal order, and the transpose
+    const Csr& G = hs.gnn_agg;
+    std::vector<std::vector<std::pair<int32_t, float>>> rows(NH), trows(NH);
+    for (int64_t k = 0; k < NH; ++k)
+        for (int64_t p = G.ptr[k]; p < G.ptr[k + 1]; ++p) {
+            const int32_t i = (int32_t)hs.v_pos[k], j = (int32_t)hs.v_pos[G.col[p]];
+            rows[i].push_back({j, (float)G.val[p]});
+            trows[j].push_back({i, (float)G.val[p]});
+        }
+    auto up_graph = [&](std::vector<std::vector<std::pair<int32_t, float>>>& R, GnnGraph& out) -> bido_status {
+        std::vector<int64_t> ptr(NH + 1, 0);
+        std::vector<int32_t> col;
+        std::vector<float> val;
+        for (int64_t i = 0; i < NH; ++i) {
+            std::sort(R[i].begin(), R[i].end());
+            for (auto& e : R[i]) { col.push_back(e.first); val.push_back(e.second); }
+            ptr[i + 1] = (int64_t)col.size();
+        }
+        out.n = NH;
+        HIP_OK(upload(&out.ptr, ptr.data(), ptr.size()));
+        HIP_OK(upload(&out.col, col.data(), std::max<size_t>(col.size(), 1)));
+        HIP_OK(upload(&out.val, val.data(), std::max<size_t>(val.size(), 1)));
+        return BIDO_OK;
+    };
+    bido_status e;
+    if ((e = up_graph(rows, g.A))) return e;
+    if ((e = up_graph(trows, g.At))) return e;
+    // K_m = gamma M_H + S_m scaled to unit mean diagonal, internal order
+    {
+        const Csr& Sm = hs.A.Sm;
+        std::vector<std::vector<std::pair<int32_t, float>>> wrows(NH);
+        double dsum = 0.0;
+        for (int64_t k = 0; k < NH; ++k) dsum += hs.gamma * hs.A.mH[k];
+        for (int64_t k = 0; k < NH; ++k)
+            for (int64_t p = Sm.ptr[k]; p < Sm.ptr[k + 1]; ++p)
+                if (Sm.col[p] == k) dsum += Sm.val[p];
+        const double dmean = dsum / std::max<int64_t>(NH, 1);
+        for (int64_t k = 0; k < NH; ++k)
+            for (int64_t p = Sm.ptr[k]; p < Sm.ptr[k + 1]; ++p) {
+                double val = Sm.val[p] + (Sm.col[p] == k ? hs.gamma * hs.A.mH[k] : 0.0);
+                wrows[hs.v_pos[k]].push_back({(int32_t)hs.v_pos[Sm.col[p]], (float)(val / dmean)});
+            }
+        if ((e = up_graph(wrows, g.Wk))) return e;
+    }
+    // weights: fan-in scaled normal, zero biases; the readout starts at zero
+    // so that an untrained correction is exactly the plain preconditioner
+    std::vector<float> th(GNN_P, 0.0f);
+    std::mt19937_64 rng(12345);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (int k = 0; k < GNN_H * GNN_F; ++k) {
+        th[GNN_OFF_W1S + k] = (float)(nd(rng) / std::sqrt((double)GNN_F));
+        th[GNN_OFF_W1N + k] = (float)(nd(rng) / std::sqrt((double)GNN_F));
+    }
+    for (int k = 0; k < GNN_H * GNN_H; ++k) {
+        th[GNN_OFF_W2S + k] = (float)(nd(rng) / std::sqrt((double)GNN_H));
+        th[GNN_OFF_W2N + k] = (float)(nd(rng) / std::sqrt((double)GNN_H));
+    }
+    HIP_OK(upload(&g.theta, th.data(), th.size()));
+    for (float** b : {&g.m, &g.v, &g.grad}) {
+        HIP_OK(hipMalloc((void**)b, GNN_P * sizeof(float)));
+        HIP_OK(hipMemset(*b, 0, GNN_P * sizeof(float)));
+    }
+    HIP_OK(hipMalloc((void**)&g.wbf, GNN_P * sizeof(uint16_t)));
+    launch_gnn_to_bf16(c->stream, g.theta, g.wbf);
+    const int64_t nh = std::max<int64_t>(NH, 1);
+    for (uint16_t** b : {&g.act.f, &g.act.m0}) HIP_OK(hipMalloc((void**)b, nh * GNN_F * sizeof(uint16_t)));
+    for (uint16_t** b : {&g.act.h1, &g.act.m1, &g.act.h2}) HIP_OK(hipMalloc((void**)b, nh * GNN_H * sizeof(uint16_t)));
+    for (float** b : {&g.act.o, &g.act.dout, &g.act.res, &g.act.zero, &g.ft, &g.fy})
+        HIP_OK(hipMalloc((void**)b, nh * sizeof(float)));
+    HIP_OK(hipMemset(g.act.zero, 0, nh * sizeof(float)));
+    for (float** b : {&g.act.dz2, &g.act.g2, &g.act.dz1}) HIP_OK(hipMalloc((void**)b, nh * GNN_H * sizeof(float)));
+    const int64_t np = (int64_t)GNN_WG_BLOCKS * GNN_P + (nh * GNN_H + 255) / 256 + 256;
+    HIP_OK(hipMalloc((void**)&g.partials, np * sizeof(float)));
+    HIP_OK(hipMalloc((void**)&g.dloss, 4 * sizeof(double)));
+    HIP_OK(hipMalloc((void**)&g.tz, nh * sizeof(double)));
+    return BIDO_OK;
 }
 
 bool dt_matches(const bido_ctx* c, double dt) {
@@ -501,6 +678,8 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     HIP_OK(upload(&c->stim_loc, hs.stim_loc.data(), hs.stim_loc.size()));
     HIP_OK(hipEventCreate(&c->ev0));
     HIP_OK(hipEventCreate(&c->ev1));
+    if ((e = gnn_setup(c.get()))) return e;
+    c->precond = params->precond;
     HIP_OK(hipDeviceSynchronize());
     *out = c.release();
     return BIDO_OK;
@@ -589,6 +768,171 @@ bido_status bido_inner_solve(bido_ctx* c, int which, const double* b, double* x)
     return BIDO_OK;
 }
 
+bido_status bido_set_precond(bido_ctx* c, int precond) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    if (precond != BIDO_PRECOND_PLAIN && precond != BIDO_PRECOND_LEARNED) return fail(BIDO_ERR_ARG, "bad precond");
+    c->precond = precond;
+    return BIDO_OK;
+}
+
+bido_status bido_learn_collect(bido_ctx* c, double* v, double* w, double* u, double dt, int64_t n0,
+                               int64_t n_steps, int max_samples, bido_stats* st) {
+    if (!c || max_samples < 1) return fail(BIDO_ERR_ARG, "bad argument");
+    GnnState& g = c->gnn;
+    if (max_samples > g.max_samples) {
+        hipStreamSynchronize(c->stream);
+        float *nt = nullptr, *ny = nullptr;
+        double* nn = nullptr;
+        HIP_OK(hipMalloc((void**)&nt, (size_t)max_samples * c->NH * sizeof(float)));
+        HIP_OK(hipMalloc((void**)&ny, (size_t)max_samples * c->NH * sizeof(float)));
+        HIP_OK(hipMalloc((void**)&nn, (size_t)max_samples * sizeof(double)));
+        if (g.n_samples > 0) {
+            HIP_OK(hipMemcpy(nt, g.s_t, (size_t)g.n_samples * c->NH * sizeof(float), hipMemcpyDeviceToDevice));
+            HIP_OK(hipMemcpy(ny, g.s_y, (size_t)g.n_samples * c->NH * sizeof(float), hipMemcpyDeviceToDevice));
+            HIP_OK(hipMemcpy(nn, g.s_tn2, (size_t)g.n_samples * sizeof(double), hipMemcpyDeviceToDevice));
+        }
+        hipFree(g.s_t); hipFree(g.s_y); hipFree(g.s_tn2);
+        g.s_t = nt; g.s_y = ny; g.s_tn2 = nn;
+        g.max_samples = max_samples;
+    }
+    if (!g.pend) HIP_OK(hipMalloc((void**)&g.pend, (size_t)g.max_pending * std::max<int64_t>(c->NH, 1) * sizeof(double)));
+    g.collecting = true;
+    g.n_pending = 0;
+    bido_status e = bido_run(c, v, w, u, dt, n0, n_steps, st);
+    g.collecting = false;
+    return e;
+}
+
+bido_status bido_learn_samples(const bido_ctx* c, int* n_samples) {
+    if (!c || !n_samples) return fail(BIDO_ERR_ARG, "null argument");
+    *n_samples = c->gnn.n_samples;
+    return BIDO_OK;
+}
+
+bido_status bido_learn_train(bido_ctx* c, int epochs, int batch, float lr, uint64_t seed, int n_val,
+                             bido_train_stats* ts) {
+    if (!c || epochs < 0 || batch < 1 || !(lr > 0)) return fail(BIDO_ERR_ARG, "bad argument");
+    GnnState& g = c->gnn;
+    const int n_tr = g.n_samples - n_val;
+    if (n_val < 0 || n_tr < 1) return fail(BIDO_ERR_STATE, "not enough collected samples");
+    hipStream_t s = c->stream;
+    const int64_t NH = c->NH;
+    auto t0 = std::chrono::steady_clock::now();
+    double hl[4];
+    // loss of the zero correction on the training and validation sets; the
+    // network learns targets in units of their RMS per vertex (out_scale)
+    HIP_OK(hipMemsetAsync(g.dloss, 0, 4 * sizeof(double), s));
+    for (int k = 0; k < g.n_samples; ++k)
+        launch_gnn_sumsq(s, NH, g.s_y + (int64_t)k * NH, g.partials, g.dloss + (k < n_tr ? 0 : 1));
+    HIP_OK(hipMemcpyAsync(hl, g.dloss, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const double rms = std::sqrt(hl[0] / ((double)n_tr * std::max<int64_t>(NH, 1)));
+    g.out_scale = rms > 0 ? (float)rms : 1.0f;
+    const float yinv = 1.0f / g.out_scale;
+    HIP_OK(hipMemsetAsync(g.dloss, 0, 2 * sizeof(double), s));
+    for (int k = 0; k < g.n_samples; ++k)
+        launch_gnn_energy0(s, NH, g.s_y + (int64_t)k * NH, g.Wk, g.act, g.partials,
+                           g.dloss + (k < n_tr ? 0 : 1), yinv);
+    auto eval = [&](int k0, int k1, double* dst) {
+        for (int k = k0; k < k1; ++k) {
+            launch_gnn_forward_sample(s, NH, g.s_t + (int64_t)k * NH, g.stat, g.A, g.wbf, g.act);
+            launch_gnn_loss(s, NH, g.s_y + (int64_t)k * NH, g.Wk, g.act, g.partials, dst, yinv);
+        }
+    };
+    HIP_OK(hipMemsetAsync(g.dloss + 2, 0, 2 * sizeof(double), s));
+    eval(0, n_tr, g.dloss + 2);
+    HIP_OK(hipMemcpyAsync(hl, g.dloss, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (ts) {
+        std::memset(ts, 0, sizeof(*ts));
+        ts->samples = g.n_samples;
+        ts->train_samples = n_tr;
+        ts->loss_zero = hl[0] / n_tr;
+        ts->loss_zero_val = n_val ? hl[1] / n_val : 0.0;
+        ts->loss_first = hl[2] / n_tr;
+    }
+    std::mt19937_64 rng(seed);
+    std::vector<int> order(n_tr);
+    for (int k = 0; k < n_tr; ++k) order[k] = k;
+    for (int ep = 0; ep < epochs; ++ep) {
+        std::shuffle(order.begin(), order.end(), rng);
+        for (int b0 = 0; b0 < n_tr; b0 += batch) {
+            const int b1 = std::min(n_tr, b0 + batch);
+            HIP_OK(hipMemsetAsync(g.grad, 0, GNN_P * sizeof(float), s));
+            for (int q = b0; q < b1; ++q) {
+                const int k = order[q];
+                launch_gnn_forward_sample(s, NH, g.s_t + (int64_t)k * NH, g.stat, g.A, g.wbf, g.act);
+                launch_gnn_backward(s, NH, g.s_y + (int64_t)k * NH, g.Wk, g.At, g.wbf, g.act, g.partials,
+                                    g.grad, nullptr, yinv);
+            }
+            launch_gnn_adam(s, g.theta, g.m, g.v, g.grad, 1.0f / (float)(b1 - b0), lr, ++g.adam_step, g.wbf);
+        }
+    }
+    HIP_OK(hipMemsetAsync(g.dloss, 0, 4 * sizeof(double), s));
+    eval(0, n_tr, g.dloss + 2);
+    eval(n_tr, g.n_samples, g.dloss + 3);
+    HIP_OK(hipMemcpyAsync(hl, g.dloss, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (ts) {
+        ts->epochs = epochs;
+        ts->loss_last = hl[2] / n_tr;
+        ts->loss_val = n_val ? hl[3] / n_val : 0.0;
+        ts->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return BIDO_OK;
+}
+
+bido_status bido_weights_io(bido_ctx* c, float* buf, int n, int dir) {
+    if (!c || !buf || n != GNN_P || (dir != 0 && dir != 1)) return fail(BIDO_ERR_ARG, "bad argument");
+    GnnState& g = c->gnn;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (dir == 0) {
+        HIP_OK(hipMemcpy(buf, g.theta, GNN_P * sizeof(float), hipMemcpyDeviceToHost));
+    } else {
+        HIP_OK(hipMemcpy(g.theta, buf, GNN_P * sizeof(float), hipMemcpyHostToDevice));
+        HIP_OK(hipMemset(g.m, 0, GNN_P * sizeof(float)));
+        HIP_OK(hipMemset(g.v, 0, GNN_P * sizeof(float)));
+        g.adam_step = 0;
+        launch_gnn_to_bf16(c->stream, g.theta, g.wbf);
+        g.out_scale = 1.0f;
+        HIP_OK(hipStreamSynchronize(c->stream));
+    }
+    return BIDO_OK;
+}
+
+bido_status bido_gnn_eval(bido_ctx* c, const double* t, double* out) {
+    if (!c || !t || !out) return fail(BIDO_ERR_ARG, "null argument");
+    hipStream_t s = c->stream;
+    GnnState& g = c->gnn;
+    const int64_t NH = c->NH;
+    launch_scatter_in(s, NH, c->v_pos, t, c->tB);
+    launch_dot_reduce(s, NH, c->tB, c->tB, c->rd, c->sc + S_TN2);
+    launch_fill(s, NH, g.tz, 0.0);
+    launch_gnn_forward(s, NH, c->tB, c->sc + S_TN2, g.stat, g.A, g.wbf, g.act, 0, g.tz, g.out_scale);
+    launch_gather_out(s, NH, c->v_pos, g.tz, out, c->sc, -1, 1.0);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
+    return BIDO_OK;
+}
+
+bido_status bido_gnn_loss_grad(bido_ctx* c, const float* that, const float* y, double* loss, float* grad) {
+    if (!c || !that || !y || !loss || !grad) return fail(BIDO_ERR_ARG, "null argument");
+    hipStream_t s = c->stream;
+    GnnState& g = c->gnn;
+    const int64_t NH = c->NH;
+    launch_scatter_in_f(s, NH, c->v_pos, that, g.ft);
+    launch_scatter_in_f(s, NH, c->v_pos, y, g.fy);
+    HIP_OK(hipMemsetAsync(g.grad, 0, GNN_P * sizeof(float), s));
+    HIP_OK(hipMemsetAsync(g.dloss, 0, sizeof(double), s));
+    launch_gnn_forward_sample(s, NH, g.ft, g.stat, g.A, g.wbf, g.act);
+    launch_gnn_backward(s, NH, g.fy, g.Wk, g.At, g.wbf, g.act, g.partials, g.grad, g.dloss, 1.0f);
+    HIP_OK(hipMemcpyAsync(loss, g.dloss, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(grad, g.grad, GNN_P * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
+    return BIDO_OK;
+}
+
 bido_status bido_set_solver(bido_ctx* c, double tol, int max_iter) {
     if (!c) return fail(BIDO_ERR_ARG, "null context");
     if (tol > 0) c->params.tol = tol;
@@ -611,9 +955,11 @@ bido_status bido_run(bido_ctx* c, double* v, double* w, double* u, double dt, in
     HIP_OK(hipEventRecord(c->ev0, c->stream));
     bido_status e = BIDO_OK;
     int64_t total = 0;
+    int fb = 0;
     for (int64_t k = 0; k < n_steps; ++k) {
         e = step_once(c, v, w, u, n0 + k, &local);
         total += local.iterations;
+        fb += local.fallbacks;
         if (e) break;
     }
     HIP_OK(hipEventRecord(c->ev1, c->stream));
@@ -623,6 +969,7 @@ bido_status bido_run(bido_ctx* c, double* v, double* w, double* u, double dt, in
     if (st) {
         *st = local;
         st->total_iterations = total;
+        st->fallbacks = fb;
         st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     (void)ms;
@@ -649,6 +996,7 @@ bido_status bido_solve(bido_ctx* c, const double* rhs, double* x, double tol, bi
     launch_scatter_in(s, NH, c->v_pos, x + N, c->x + N);
     bido_stats local{};
     e = pcg(c, tol > 0 ? tol : c->params.tol, &local);
+    finish_collection(c, e == BIDO_OK);
     if (e && e != BIDO_ERR_NOT_CONVERGED) return e;
     launch_dot_reduce(s, N, c->m_int, c->x, c->rd, c->sc + S_MU);
     launch_gather_out(s, N, c->u_pos, c->x, x, c->sc, S_MU, c->hs.msum);

@@ -1,0 +1,388 @@
+// HIP kernels of the learned correction (see gnn.h): BF16 weights and
+// activations, FP32 accumulation, deterministic gradient reductions.
+#include <hip/hip_runtime.h>
+
+#include "gnn.h"
+
+namespace bido {
+namespace {
+
+constexpr int BLOCK = 256;
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ float bf2f(uint16_t u) { return __uint_as_float((uint32_t)u << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+unsigned blocks_for(int64_t threads) {
+    int64_t g = (threads + BLOCK - 1) / BLOCK;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// f[i][0] = t_i / rms(t) with rms(t) = sqrt(tn2 / n), f[i][1..15] = static features
+__global__ void k_input(int64_t n, const double* __restrict__ t, const double* __restrict__ tn2,
+                        const float* __restrict__ that, const float* __restrict__ stat,
+                        uint16_t* __restrict__ f) {
+    const int64_t id = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (id >= n * GNN_F) return;
+    const int64_t i = id / GNN_F;
+    const int j = (int)(id % GNN_F);
+    float v;
+    if (j == 0) {
+        if (that) {
+            v = that[i];
+        } else {
+            const double rms = sqrt(*tn2 / (double)n);
+            v = rms > 0.0 ? (float)(t[i] / rms) : 0.0f;
+        }
+    } else {
+        v = stat[i * GNN_F + j];
+    }
+    f[id] = f2bf(v);
+}
+
+// out_i = sum_j a_ij in_j  (W features per vertex)
+template <int W>
+__global__ void k_agg(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                      const float* __restrict__ val, const uint16_t* __restrict__ in,
+                      uint16_t* __restrict__ out) {
+    const int64_t id = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (id >= n * W) return;
+    const int64_t i = id / W;
+    const int k = (int)(id % W);
+    float s = 0.0f;
+    for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p) s += val[p] * bf2f(in[(int64_t)col[p] * W + k]);
+    out[id] = f2bf(s);
+}
+
+// h_i = relu(Ws x_i + Wn m_i + b); with READOUT also o_i = w3 . h_i + b3,
+// added (times rms(t) * out_scale) to z2 in inference mode.  8 vertices x 32 units
+// per block; weights staged in LDS.
+template <int IN, bool READOUT>
+__global__ __launch_bounds__(BLOCK) void k_layer(int64_t n, const uint16_t* __restrict__ x,
+                                                 const uint16_t* __restrict__ m,
+                                                 const uint16_t* __restrict__ wbf, int off_ws, int off_wn,
+                                                 int off_b, uint16_t* __restrict__ h, float* __restrict__ o,
+                                                 const double* __restrict__ tn2, double* __restrict__ z2,
+                                                 float out_scale) {
+    __shared__ float ws[GNN_H * IN], wn[GNN_H * IN], bb[GNN_H], w3[GNN_H];
+    __shared__ float xs[BLOCK / GNN_H][IN], ms[BLOCK / GNN_H][IN];
+    for (int k = threadIdx.x; k < GNN_H * IN; k += BLOCK) {
+        ws[k] = bf2f(wbf[off_ws + k]);
+        wn[k] = bf2f(wbf[off_wn + k]);
+    }
+    if (threadIdx.x < GNN_H) {
+        bb[threadIdx.x] = bf2f(wbf[off_b + threadIdx.x]);
+        w3[threadIdx.x] = bf2f(wbf[GNN_OFF_W3 + threadIdx.x]);
+    }
+    const int nl = threadIdx.x / GNN_H, a = threadIdx.x % GNN_H;
+    const int64_t i = blockIdx.x * (int64_t)(BLOCK / GNN_H) + nl;
+    for (int k = a; k < IN; k += GNN_H)
+        if (i < n) {
+            xs[nl][k] = bf2f(x[i * IN + k]);
+            ms[nl][k] = bf2f(m[i * IN + k]);
+        }
+    __syncthreads();
+    if (i >= n) return;   // whole 32-lane groups leave together
+    float z = bb[a];
+#pragma unroll 8
+    for (int k = 0; k < IN; ++k) z += ws[a * IN + k] * xs[nl][k] + wn[a * IN + k] * ms[nl][k];
+    const float hv = z > 0.0f ? z : 0.0f;
+    const uint16_t hb = f2bf(hv);
+    if (h) h[i * GNN_H + a] = hb;
+    if (READOUT) {
+        float s = w3[a] * bf2f(hb);
+#pragma unroll
+        for (int msk = GNN_H / 2; msk > 0; msk >>= 1) s += __shfl_xor(s, msk, WAVE);
+        if (a == 0) {
+            const float ov = s + bf2f(wbf[GNN_OFF_B3]);
+            if (o) o[i] = ov;
+            if (z2) z2[i] += sqrt(*tn2 / (double)n) * (double)out_scale * (double)ov;
+        }
+    }
+}
+
+// r_i = o_i - y_i * yinv
+__global__ void k_resid(int64_t n, const float* __restrict__ o, const float* __restrict__ y, float yinv,
+                        float* __restrict__ r) {
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (i < n) r[i] = o[i] - y[i] * yinv;
+}
+
+// energy-norm loss r^T W r: d o = 2 W r, per-block loss partials
+__global__ __launch_bounds__(BLOCK) void k_energy(int64_t n, const int64_t* __restrict__ wptr,
+                                                  const int32_t* __restrict__ wcol,
+                                                  const float* __restrict__ wval,
+                                                  const float* __restrict__ r, float* __restrict__ dout,
+                                                  float* __restrict__ loss_part) {
+    __shared__ float red[BLOCK];
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    float l = 0.0f;
+    if (i < n) {
+        float wr = 0.0f;
+        for (int64_t p = wptr[i]; p < wptr[i + 1]; ++p) wr += wval[p] * r[wcol[p]];
+        dout[i] = 2.0f * wr;
+        l = r[i] * wr;
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int k = BLOCK / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+// dz2 = d o_i * w3 * [h2 > 0]
+__global__ __launch_bounds__(BLOCK) void k_bwd_out(int64_t n, const float* __restrict__ dout,
+                                                   const uint16_t* __restrict__ h2,
+                                                   const uint16_t* __restrict__ wbf,
+                                                   float* __restrict__ dz2) {
+    const int64_t id = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    const int64_t i = id / GNN_H;
+    const int a = (int)(id % GNN_H);
+    if (i < n) dz2[id] = bf2f(h2[id]) > 0.0f ? dout[i] * bf2f(wbf[GNN_OFF_W3 + a]) : 0.0f;
+}
+
+// g_i = W2n^T dz2_i
+__global__ __launch_bounds__(BLOCK) void k_bwd_g(int64_t n, const float* __restrict__ dz2,
+                                                 const uint16_t* __restrict__ wbf, float* __restrict__ g) {
+    __shared__ float wn[GNN_H * GNN_H];
+    __shared__ float ds[BLOCK / GNN_H][GNN_H];
+    for (int k = threadIdx.x; k < GNN_H * GNN_H; k += BLOCK) wn[k] = bf2f(wbf[GNN_OFF_W2N + k]);
+    const int nl = threadIdx.x / GNN_H, k = threadIdx.x % GNN_H;
+    const int64_t i = blockIdx.x * (int64_t)(BLOCK / GNN_H) + nl;
+    if (i < n) ds[nl][k] = dz2[i * GNN_H + k];
+    __syncthreads();
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int a = 0; a < GNN_H; ++a) s += wn[a * GNN_H + k] * ds[nl][a];
+    g[i * GNN_H + k] = s;
+}
+
+// dh1_i = W2s^T dz2_i + sum_j (A^T)_ij g_j ;  dz1 = dh1 * [h1 > 0]
+__global__ __launch_bounds__(BLOCK) void k_bwd_hidden(int64_t n, const float* __restrict__ dz2,
+                                                      const float* __restrict__ g,
+                                                      const int64_t* __restrict__ tptr,
+                                                      const int32_t* __restrict__ tcol,
+                                                      const float* __restrict__ tval,
+                                                      const uint16_t* __restrict__ h1,
+                                                      const uint16_t* __restrict__ wbf,
+                                                      float* __restrict__ dz1) {
+    __shared__ float wsm[GNN_H * GNN_H];
+    __shared__ float ds[BLOCK / GNN_H][GNN_H];
+    for (int k = threadIdx.x; k < GNN_H * GNN_H; k += BLOCK) wsm[k] = bf2f(wbf[GNN_OFF_W2S + k]);
+    const int nl = threadIdx.x / GNN_H, k = threadIdx.x % GNN_H;
+    const int64_t i = blockIdx.x * (int64_t)(BLOCK / GNN_H) + nl;
+    if (i < n) ds[nl][k] = dz2[i * GNN_H + k];
+    __syncthreads();
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int a = 0; a < GNN_H; ++a) s += wsm[a * GNN_H + k] * ds[nl][a];
+    for (int64_t p = tptr[i]; p < tptr[i + 1]; ++p) s += tval[p] * g[(int64_t)tcol[p] * GNN_H + k];
+    dz1[i * GNN_H + k] = bf2f(h1[i * GNN_H + k]) > 0.0f ? s : 0.0f;
+}
+
+// Weight-gradient partials: block b sums over its vertex range
+//   P[b][off_w + a*IN + k] = sum_i G[i][a] X[i][k],   P[b][off_b + a] = sum_i G[i][a]
+// with GW rows of G per vertex (GW = 32, or 1 for the readout).
+template <int GW, int IN>
+__global__ void k_wgrad(int64_t n, const float* __restrict__ G, const uint16_t* __restrict__ X,
+                        float* __restrict__ part, int off_w, int off_b) {
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = blockIdx.x * per, i1 = min(n, i0 + per);
+    float* P = part + (int64_t)blockIdx.x * GNN_P;
+    for (int e = threadIdx.x; e < GW * IN; e += blockDim.x) {
+        const int a = e / IN, k = e % IN;
+        float s = 0.0f;
+        for (int64_t i = i0; i < i1; ++i) s += G[i * GW + a] * bf2f(X[i * IN + k]);
+        P[off_w + e] = s;
+    }
+    if (off_b >= 0)
+        for (int a = threadIdx.x; a < GW; a += blockDim.x) {
+            float s = 0.0f;
+            for (int64_t i = i0; i < i1; ++i) s += G[i * GW + a];
+            P[off_b + a] = s;
+        }
+}
+
+// sum of squares of a float vector into per-block partials
+__global__ void k_sumsq_f(int64_t n, const float* __restrict__ a, float* __restrict__ part) {
+    __shared__ float red[BLOCK];
+    float s = 0.0f;
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        s += a[i] * a[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = BLOCK / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// grad[p] += sum_b part[b][p] (fixed order); loss += sum of loss partials
+__global__ void k_reduce_grad(int nb, const float* __restrict__ part, float* __restrict__ grad,
+                              const float* __restrict__ loss_part, int nlp, double* loss) {
+    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    if (grad && p < GNN_P) {
+        float s = 0.0f;
+        for (int b = 0; b < nb; ++b) s += part[(int64_t)b * GNN_P + p];
+        grad[p] += s;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
+        double l = 0.0;
+        for (int b = 0; b < nlp; ++b) l += loss_part[b];
+        *loss += l;
+    }
+}
+
+__global__ void k_adam(float* theta, float* m, float* v, const float* grad, float scale, float lr,
+                       float c1, float c2, uint16_t* wbf) {
+    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= GNN_P) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float g = grad[p] * scale;
+    const float mm = b1 * m[p] + (1.0f - b1) * g;
+    const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    const float th = theta[p] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    theta[p] = th;
+    wbf[p] = f2bf(th);
+}
+
+__global__ void k_to_bf16(const float* theta, uint16_t* wbf) {
+    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    if (p < GNN_P) wbf[p] = f2bf(theta[p]);
+}
+
+__global__ void k_store_sample(int64_t n, const double* __restrict__ t, const double* __restrict__ tn2,
+                               float* __restrict__ that) {
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const double rms = sqrt(*tn2 / (double)n);
+    that[i] = rms > 0.0 ? (float)(t[i] / rms) : 0.0f;
+}
+
+__global__ void k_pending(int64_t n, const double* __restrict__ xv, const double* __restrict__ z2,
+                          double* __restrict__ d) {
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (i < n) d[i] = xv[i] + z2[i];
+}
+
+__global__ void k_finish_targets(int64_t n, const double* __restrict__ vstar, const double* __restrict__ d,
+                                 const double* __restrict__ tn2, float* __restrict__ y) {
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const double rms = sqrt(*tn2 / (double)n);
+    y[i] = rms > 0.0 ? (float)((vstar[i] - d[i]) / rms) : 0.0f;
+}
+
+void forward_common(hipStream_t s, int64_t n, const GnnGraph& A, const uint16_t* wbf, GnnAct& a, int mode,
+                    const double* tn2, double* z2, float out_scale) {
+    k_agg<GNN_F><<<blocks_for(n * GNN_F), BLOCK, 0, s>>>(n, A.ptr, A.col, A.val, a.f, a.m0);
+    const unsigned gb = blocks_for(n * GNN_H);
+    k_layer<GNN_F, false><<<gb, BLOCK, 0, s>>>(n, a.f, a.m0, wbf, GNN_OFF_W1S, GNN_OFF_W1N, GNN_OFF_B1, a.h1,
+                                               nullptr, nullptr, nullptr, 1.0f);
+    k_agg<GNN_H><<<blocks_for(n * GNN_H), BLOCK, 0, s>>>(n, A.ptr, A.col, A.val, a.h1, a.m1);
+    k_layer<GNN_H, true><<<gb, BLOCK, 0, s>>>(n, a.h1, a.m1, wbf, GNN_OFF_W2S, GNN_OFF_W2N, GNN_OFF_B2,
+                                              mode == 1 ? a.h2 : nullptr, mode == 1 ? a.o : nullptr,
+                                              tn2, mode == 0 ? z2 : nullptr, out_scale);
+}
+
+}  // namespace
+
+void launch_gnn_forward(hipStream_t s, int64_t n, const double* t, const double* tn2, const float* stat,
+                        const GnnGraph& A, const uint16_t* wbf, GnnAct& a, int mode, double* z2,
+                        float out_scale) {
+    if (n <= 0) return;
+    k_input<<<blocks_for(n * GNN_F), BLOCK, 0, s>>>(n, t, tn2, nullptr, stat, a.f);
+    forward_common(s, n, A, wbf, a, mode, tn2, z2, out_scale);
+}
+
+void launch_gnn_forward_sample(hipStream_t s, int64_t n, const float* that, const float* stat,
+                               const GnnGraph& A, const uint16_t* wbf, GnnAct& a) {
+    if (n <= 0) return;
+    k_input<<<blocks_for(n * GNN_F), BLOCK, 0, s>>>(n, nullptr, nullptr, that, stat, a.f);
+    forward_common(s, n, A, wbf, a, 1, nullptr, nullptr, 1.0f);
+}
+
+void launch_gnn_backward(hipStream_t s, int64_t n, const float* y, const GnnGraph& W, const GnnGraph& At,
+                         const uint16_t* wbf, GnnAct& a, float* partials, float* grad, double* loss,
+                         float yinv) {
+    if (n <= 0) return;
+    const unsigned gb = blocks_for(n * GNN_H);
+    const unsigned nb = blocks_for(n);
+    float* loss_part = partials + (int64_t)GNN_WG_BLOCKS * GNN_P;
+    k_resid<<<nb, BLOCK, 0, s>>>(n, a.o, y, yinv, a.res);
+    k_energy<<<nb, BLOCK, 0, s>>>(n, W.ptr, W.col, W.val, a.res, a.dout, loss_part);
+    k_bwd_out<<<gb, BLOCK, 0, s>>>(n, a.dout, a.h2, wbf, a.dz2);
+    k_bwd_g<<<gb, BLOCK, 0, s>>>(n, a.dz2, wbf, a.g2);
+    k_bwd_hidden<<<gb, BLOCK, 0, s>>>(n, a.dz2, a.g2, At.ptr, At.col, At.val, a.h1, wbf, a.dz1);
+    const int wb = GNN_WG_BLOCKS;
+    k_wgrad<1, GNN_H><<<wb, BLOCK, 0, s>>>(n, a.dout, a.h2, partials, GNN_OFF_W3, GNN_OFF_B3);
+    k_wgrad<GNN_H, GNN_H><<<wb, 1024, 0, s>>>(n, a.dz2, a.h1, partials, GNN_OFF_W2S, GNN_OFF_B2);
+    k_wgrad<GNN_H, GNN_H><<<wb, 1024, 0, s>>>(n, a.dz2, a.m1, partials, GNN_OFF_W2N, -1);
+    k_wgrad<GNN_H, GNN_F><<<wb, 512, 0, s>>>(n, a.dz1, a.f, partials, GNN_OFF_W1S, GNN_OFF_B1);
+    k_wgrad<GNN_H, GNN_F><<<wb, 512, 0, s>>>(n, a.dz1, a.m0, partials, GNN_OFF_W1N, -1);
+    k_reduce_grad<<<(GNN_P + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(GNN_WG_BLOCKS, partials, grad, loss_part,
+                                                                 (int)nb, loss);
+}
+
+void launch_gnn_loss(hipStream_t s, int64_t n, const float* y, const GnnGraph& W, GnnAct& a,
+                     float* partials, double* loss, float yinv) {
+    if (n <= 0) return;
+    const unsigned nb = blocks_for(n);
+    float* loss_part = partials + (int64_t)GNN_WG_BLOCKS * GNN_P;
+    k_resid<<<nb, BLOCK, 0, s>>>(n, a.o, y, yinv, a.res);
+    k_energy<<<nb, BLOCK, 0, s>>>(n, W.ptr, W.col, W.val, a.res, a.dout, loss_part);
+    k_reduce_grad<<<1, BLOCK, 0, s>>>(0, partials, nullptr, loss_part, (int)nb, loss);
+}
+
+void launch_gnn_sumsq(hipStream_t s, int64_t n, const float* y, float* partials, double* out) {
+    if (n <= 0) return;
+    float* lp = partials + (int64_t)GNN_WG_BLOCKS * GNN_P;
+    k_sumsq_f<<<256, BLOCK, 0, s>>>(n, y, lp);
+    k_reduce_grad<<<1, BLOCK, 0, s>>>(0, partials, nullptr, lp, 256, out);
+}
+
+void launch_gnn_energy0(hipStream_t s, int64_t n, const float* y, const GnnGraph& W, GnnAct& a,
+                        float* partials, double* out, float yinv) {
+    // loss of the zero output: (-y)^T W (-y)
+    if (n <= 0) return;
+    const unsigned nb = blocks_for(n);
+    float* loss_part = partials + (int64_t)GNN_WG_BLOCKS * GNN_P;
+    k_resid<<<nb, BLOCK, 0, s>>>(n, a.zero, y, yinv, a.res);
+    k_energy<<<nb, BLOCK, 0, s>>>(n, W.ptr, W.col, W.val, a.res, a.dout, loss_part);
+    k_reduce_grad<<<1, BLOCK, 0, s>>>(0, partials, nullptr, loss_part, (int)nb, out);
+}
+
+void launch_gnn_adam(hipStream_t s, float* theta, float* m, float* v, const float* grad, float scale,
+                     float lr, int step, uint16_t* wbf) {
+    const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+    k_adam<<<(GNN_P + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(theta, m, v, grad, scale, lr, c1, c2, wbf);
+}
+
+void launch_gnn_to_bf16(hipStream_t s, const float* theta, uint16_t* wbf) {
+    k_to_bf16<<<(GNN_P + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(theta, wbf);
+}
+
+void launch_gnn_store_sample(hipStream_t s, int64_t n, const double* t, const double* tn2, float* that) {
+    if (n > 0) k_store_sample<<<blocks_for(n), BLOCK, 0, s>>>(n, t, tn2, that);
+}
+
+void launch_gnn_finish_targets(hipStream_t s, int64_t n, const double* vstar, const double* d,
+                               const double* tn2, float* y) {
+    if (n > 0) k_finish_targets<<<blocks_for(n), BLOCK, 0, s>>>(n, vstar, d, tn2, y);
+}
+
+void launch_gnn_pending(hipStream_t s, int64_t n, const double* xv, const double* z2, double* d) {
+    if (n > 0) k_pending<<<blocks_for(n), BLOCK, 0, s>>>(n, xv, z2, d);
+}
+
+}  // namespace bido

@@ -46,6 +46,7 @@ bido_status bido_host_csr(const bido_host* h, int which, int64_t* n, int64_t* nn
         case BIDO_MAT_SI: a = &h->hs.A.Si; break;
         case BIDO_MAT_SM: a = &h->hs.A.Sm; break;
         case BIDO_MAT_LAMBDA: a = &h->hs.lam; break;
+        case BIDO_MAT_GNN_AGG: a = &h->hs.gnn_agg; break;
         default: return hfail(BIDO_ERR_ARG, "unknown matrix");
     }
     *n = a->n;
@@ -61,6 +62,7 @@ bido_status bido_host_vec(const bido_host* h, int which, int64_t* n, const doubl
     const std::vector<double>* v = nullptr;
     if (which == BIDO_VEC_M) v = &h->hs.A.m;
     else if (which == BIDO_VEC_MH) v = &h->hs.A.mH;
+    else if (which == BIDO_VEC_GNN_STATIC) v = &h->hs.gnn_static;
     else return hfail(BIDO_ERR_ARG, "unknown vector");
     *n = (int64_t)v->size();
     *data = v->data();

@@ -66,6 +66,7 @@ enum ScalarSlot {
     S_YY,           // |Y|^2 (adjacent to S_RR)
     S_MU,           // (M U, 1)
     S_Y1SUM,        // sum of Y_1 (range check)
+    S_TN2,          // |t|^2 of the learned correction's input
     S_COUNT = 32
 };
 

@@ -80,6 +80,13 @@ __global__ void k_scatter_in(int64_t n, const int64_t* __restrict__ pos,
         dst[pos[i]] = src[i];
 }
 
+// float variant
+__global__ void k_scatter_in_f(int64_t n, const int64_t* __restrict__ pos, const float* __restrict__ src,
+                               float* __restrict__ dst) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        dst[pos[i]] = src[i];
+}
+
 // dst[i] = src[pos[i]] - (shift ? *shift_num / shift_den : 0)
 __global__ void k_gather_out(int64_t n, const int64_t* __restrict__ pos,
                              const double* __restrict__ src, double* __restrict__ dst,
@@ -579,6 +586,10 @@ void launch_fill(hipStream_t s, int64_t n, double* x, double v) {
 void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst) {
     if (n <= 0) return;
     k_scatter_in<<<grid_for(n), BLOCK, 0, s>>>(n, pos, src, dst);
+}
+void launch_scatter_in_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst) {
+    if (n <= 0) return;
+    k_scatter_in_f<<<grid_for(n), BLOCK, 0, s>>>(n, pos, src, dst);
 }
 void launch_gather_out(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst,
                        const double* sc, int shift_slot, double shift_den) {

@@ -4,6 +4,7 @@
 #include "setup.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 
@@ -23,6 +24,101 @@ Csr add_diag(const Csr& a, const std::vector<double>& d, double scale) {
         if (!found) { b.n = -1; return b; }   // P1 matrices always store the diagonal
     }
     return b;
+}
+
+// Features of the learned correction (see setup.h).
+void gnn_inputs(const MeshIn& in, const Assembled& A, HostSetup& hs) {
+    const int d = A.dim, k = d + 1;
+    const int64_t NH = A.NH, E = in.n_elems;
+    const int nent = d == 2 ? 3 : 6;
+    static const int iu2[3][2] = {{0, 0}, {0, 1}, {1, 1}};
+    static const int iu3[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    hs.gnn_static.assign((size_t)NH * 15, 0.0);
+    std::vector<double> cnt(NH, 0.0);
+    double scale = 0.0;
+    for (int a = 0; a < d; ++a) scale = std::max(scale, std::max(in.sigma_i[a], in.sigma_e[a]));
+    std::vector<std::array<int32_t, 3>> facets;
+    facets.reserve((size_t)E * k);
+    for (int64_t e = 0; e < E; ++e) {
+        if (in.region[e] != 1) continue;
+        const double* Q = in.fibre + e * d * d;
+        double si[9], se[9];
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                double a = 0.0, b = 0.0;
+                for (int q = 0; q < d; ++q) {
+                    a += Q[i * d + q] * in.sigma_i[q] * Q[j * d + q];
+                    b += Q[i * d + q] * in.sigma_e[q] * Q[j * d + q];
+                }
+                si[i * d + j] = a;
+                se[i * d + j] = b;
+            }
+        double ent[12];
+        for (int q = 0; q < nent; ++q) {
+            const int i = d == 2 ? iu2[q][0] : iu3[q][0], j = d == 2 ? iu2[q][1] : iu3[q][1];
+            ent[q] = si[i * d + j];
+            ent[nent + q] = se[i * d + j];
+        }
+        const int32_t* v = in.elems + e * k;
+        for (int a = 0; a < k; ++a) {
+            const int64_t l = A.heart_loc[v[a]];
+            for (int q = 0; q < 2 * nent; ++q) hs.gnn_static[l * 15 + q] += ent[q];
+            cnt[l] += 1.0;
+        }
+        for (int skip = 0; skip < k; ++skip) {
+            std::array<int32_t, 3> f{-1, -1, -1};
+            int o = 0;
+            for (int a = 0; a < k; ++a)
+                if (a != skip) f[o++] = (int32_t)A.heart_loc[v[a]];
+            std::sort(f.begin(), f.begin() + o);
+            facets.push_back(f);
+        }
+    }
+    for (int64_t l = 0; l < NH; ++l)
+        for (int q = 0; q < 2 * nent; ++q) hs.gnn_static[l * 15 + q] /= (cnt[l] * scale);
+    // boundary of the heart sub-mesh: facets owned by one heart element
+    std::sort(facets.begin(), facets.end());
+    std::vector<int> dist(NH, -1);
+    std::vector<int64_t> queue;
+    for (size_t i = 0; i < facets.size();) {
+        size_t j = i;
+        while (j < facets.size() && facets[j] == facets[i]) ++j;
+        if (j - i == 1)
+            for (int a = 0; a < d; ++a) {
+                const int32_t l = facets[i][a];
+                if (dist[l] < 0) { dist[l] = 0; queue.push_back(l); }
+            }
+        i = j;
+    }
+    // hop distance over the S_m graph (breadth-first from the boundary)
+    const Csr& Sm = A.Sm;
+    for (size_t q = 0; q < queue.size(); ++q) {
+        const int64_t l = queue[q];
+        for (int64_t p = Sm.ptr[l]; p < Sm.ptr[l + 1]; ++p) {
+            const int32_t m = Sm.col[p];
+            if (dist[m] < 0) { dist[m] = dist[l] + 1; queue.push_back(m); }
+        }
+    }
+    int dmax = 1;
+    for (int64_t l = 0; l < NH; ++l) dmax = std::max(dmax, dist[l]);
+    for (int64_t l = 0; l < NH; ++l) hs.gnn_static[l * 15 + 2 * nent] = dist[l] < 0 ? 1.0 : (double)dist[l] / dmax;
+    // row-normalised |off-diagonal| pattern of S_m
+    Csr& G = hs.gnn_agg;
+    G.n = NH;
+    G.ptr.assign(NH + 1, 0);
+    G.col.clear();
+    G.val.clear();
+    for (int64_t l = 0; l < NH; ++l) {
+        double rs = 0.0;
+        for (int64_t p = Sm.ptr[l]; p < Sm.ptr[l + 1]; ++p)
+            if (Sm.col[p] != l) rs += std::fabs(Sm.val[p]);
+        for (int64_t p = Sm.ptr[l]; p < Sm.ptr[l + 1]; ++p)
+            if (Sm.col[p] != l && Sm.val[p] != 0.0) {
+                G.col.push_back(Sm.col[p]);
+                G.val.push_back(std::fabs(Sm.val[p]) / (rs > 0 ? rs : 1.0));
+            }
+        G.ptr[l + 1] = (int64_t)G.col.size();
+    }
 }
 
 }  // namespace
@@ -160,6 +256,7 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
     if (tissue->stim_mask)
         for (int64_t k = 0; k < NH; ++k)
             if (tissue->stim_mask[A.heart[k]]) hs.stim_loc[k] = tissue->stim_amp;
+    gnn_inputs(in, A, hs);
     hs.stim_n0 = std::llround(tissue->stim_t0 / P.dt);
     hs.stim_n1 = std::llround(tissue->stim_t1 / P.dt);
     hs.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -25,6 +25,11 @@ struct HostSetup {
     int64_t stim_n0 = 0, stim_n1 = 0;
     double gamma = 0.0;
     double msum = 0.0;
+    // learned correction: static vertex features (N_H x 15, heart-local order:
+    // averaged conductivity entries / max diagonal value, then the hop distance
+    // to the heart boundary / max) and the row-normalised |S_m| neighbour graph
+    std::vector<double> gnn_static;
+    Csr gnn_agg;
     double setup_seconds = 0.0;
 };
 

@@ -1,0 +1,126 @@
+"""GPU learned correction against the FP64 oracle network (oracle.mpnn).
+
+The device network runs in BF16 (weights and activations) with FP32
+accumulation, so forward values and gradients are compared at BF16
+tolerance after rounding the oracle's weights to BF16.  The corrected
+flexible CG must still reach the oracle's normalised solution at 1e-8."""
+import numpy as np
+import pytest
+
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _bf16(x):
+    """Round FP64 values to the nearest BF16 (ties to even), as FP64."""
+    f = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    f = (f + 0x7FFF + ((f >> 16) & 1)) >> 16
+    return (f.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def setup(torch):
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd, mpnn
+    cfg = w.thorax2d(n_target=6000, seed=21)
+    s = bd.System(cfg)
+    A = mpnn.aggregation_matrix(s.Sm)
+    st = mpnn.static_features(cfg, s.Sm)
+    solver = B.Solver(cfg, eps_h=0.0, tol=1e-12)
+    rng = np.random.default_rng(5)
+    theta = _bf16(mpnn.init_params(7) + np.concatenate(
+        [np.zeros(mpnn.N_PARAMS - 33), rng.normal(0, 0.2, 33)]))
+    return B, mpnn, s, A, st, solver, theta
+
+
+def test_forward_matches_oracle(torch, setup):
+    B, mpnn, s, A, st, solver, theta = setup
+    solver.set_weights(theta)
+    rng = np.random.default_rng(11)
+    t = rng.normal(size=s.NH)
+    d_gpu = solver.gnn_eval(torch.tensor(t, device="cuda")).cpu().numpy()
+    f, nt = mpnn.features(t, st)
+    o, _ = mpnn.forward(theta, A, f)
+    d_ref = nt * o
+    err = np.linalg.norm(d_gpu - d_ref) / np.linalg.norm(d_ref)
+    print(f"forward rel err {err:.2e}")
+    assert err < 3e-2
+
+
+def test_gradient_matches_oracle(torch, setup):
+    B, mpnn, s, A, st, solver, theta = setup
+    solver.set_weights(theta)
+    rng = np.random.default_rng(12)
+    t = rng.normal(size=s.NH)
+    that = (t / (np.linalg.norm(t) / np.sqrt(s.NH))).astype(np.float32)
+    y = (rng.normal(size=s.NH) * 0.5).astype(np.float32)
+    loss_g, grad_g = solver.gnn_loss_grad(torch.tensor(that, device="cuda"),
+                                          torch.tensor(y, device="cuda"))
+    f, _ = mpnn.features(t, st)
+    f[:, 0] = that
+    W = mpnn.energy_weight(s.gamma * np.diag(s.mH) + s.Sm.toarray())
+    loss_r, grad_r = mpnn.loss_and_grad(theta, A, f, y.astype(np.float64), W)
+    el = abs(loss_g - loss_r) / abs(loss_r)
+    eg = np.linalg.norm(grad_g - grad_r) / np.linalg.norm(grad_r)
+    print(f"loss rel err {el:.2e}, gradient rel err {eg:.2e}")
+    assert el < 3e-2 and eg < 6e-2
+
+
+def _solve_steps(torch, solver, s, state, n0, n_steps, learned):
+    import paper_1711_08708_amd as B
+    v, h, u = [x.clone() for x in state]
+    solver.set_precond(B.PRECOND_LEARNED if learned else B.PRECOND_PLAIN)
+    iters, worst, fb = [], 0.0, 0
+    for n in range(n0, n0 + n_steps):
+        Vn, hn = v.cpu().numpy().copy(), h.cpu().numpy().copy()
+        st = solver.step(v, h, u, n)
+        iters.append(st["iterations"])
+        fb += st["fallbacks"]
+        Uo, Vo, _ = s.step(Vn, hn, n)
+        Uo = s.to_global_u(Uo)
+        eu = np.linalg.norm(u.cpu().numpy() - Uo) / np.linalg.norm(Uo)
+        ev = np.linalg.norm(v.cpu().numpy() - Vo) / np.linalg.norm(Vo)
+        worst = max(worst, eu, ev)
+    return iters, worst, fb, (v, h, u)
+
+
+def test_collect_train_and_flexible_cg(torch, setup):
+    """Pairs recorded over plain steps train the network below the loss of
+    the zero correction; corrected flexible CG keeps 1e-8 parity."""
+    B, mpnn, s, A, st, solver, theta = setup
+    solver.set_weights(mpnn.init_params(3) * np.concatenate([np.ones(mpnn.N_PARAMS - 33), np.zeros(33)]))
+    solver.set_precond(B.PRECOND_PLAIN)
+    v, h, u = solver.state()
+    info = solver.learn_collect(v, h, u, 0, 12, max_samples=256)
+    print("collected", info["samples"], "pairs over 12 steps")
+    assert info["samples"] >= 24
+    ts = solver.learn_train(epochs=40, batch=4, lr=2e-3, seed=1, n_val=4)
+    print("train", ts)
+    assert ts["loss_last"] < ts["loss_first"]
+    assert ts["loss_last"] < ts["loss_zero"]
+    state = (v, h, u)
+    it_p, wp, _, _ = _solve_steps(torch, solver, s, state, 12, 6, learned=False)
+    it_l, wl, fb, _ = _solve_steps(torch, solver, s, state, 12, 6, learned=True)
+    print("iterations plain", it_p, "learned", it_l, "fallbacks", fb, "worst err", wp, wl)
+    assert wp <= 1e-8 and wl <= 1e-8
+
+
+def test_fallback_keeps_parity(torch, setup):
+    """A network with large random weights gives non-descent directions; the
+    solve falls back to the plain apply there and still converges."""
+    B, mpnn, s, A, st, solver, theta = setup
+    rng = np.random.default_rng(9)
+    solver.set_weights(rng.normal(0, 30.0, mpnn.N_PARAMS))
+    v, h, u = solver.state()
+    it, worst, fb, _ = _solve_steps(torch, solver, s, (v, h, u), 0, 3, learned=True)
+    print("iterations", it, "fallbacks", fb, "worst err", worst)
+    assert worst <= 1e-8

@@ -42,6 +42,23 @@ def test_gradient_matches_central_differences(graph):
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)), (k, fd, g[k])
 
 
+def test_energy_loss_gradient_matches_central_differences(graph):
+    """Same check with the energy-norm loss r^T W r, W = K_m / mean diag."""
+    s, A, st = graph
+    W = mpnn.energy_weight(s.gamma * np.diag(s.mH) + s.Sm.toarray())
+    rng = np.random.default_rng(4)
+    theta = mpnn.init_params(2)
+    f, _ = mpnn.features(rng.normal(size=s.NH), st)
+    y = rng.normal(size=s.NH)
+    loss, g = mpnn.loss_and_grad(theta, A, f, y, W)
+    assert loss > 0
+    for k in rng.choice(mpnn.N_PARAMS, size=40, replace=False):
+        e = np.zeros_like(theta)
+        e[k] = 1e-6
+        fd = (mpnn.loss_and_grad(theta + e, A, f, y, W)[0] - mpnn.loss_and_grad(theta - e, A, f, y, W)[0]) / 2e-6
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)), (k, fd, g[k])
+
+
 def test_linear_regime_equals_composed_map(graph):
     """With non-negative weights and inputs every ReLU is active, so the
     network is the affine map o = w3.(W2s h1 + W2n A h1 + b2) + b3 with
