@@ -160,9 +160,10 @@ def main():
 def _variants(torch, B, solver, args):
     """Plain FP64 vs mixed vs learned vs learned+mixed on the same steps.
 
-    The learned correction is trained on pairs recorded during the first
-    `collect_steps` plain steps from rest; all four variants then run the
-    following `variant_steps` steps from the same saved state."""
+    The learned Schur-complement stencil is trained on pairs recorded during
+    the first `collect_steps` plain steps from rest and K_m + C is factored;
+    all four variants then run the following `variant_steps` steps from the
+    same saved state."""
     out = {}
     v, h, u = solver.state()
     solver.set_precond(B.PRECOND_PLAIN)
@@ -171,19 +172,21 @@ def _variants(torch, B, solver, args):
     col = solver.learn_collect(v, h, u, 0, args.collect_steps, max_samples=16 * args.collect_steps)
     t_col = time.perf_counter() - t0
     n_val = max(1, col["samples"] // 10)
-    ts = solver.learn_train(epochs=args.epochs, batch=8, lr=2e-3, seed=0, n_val=n_val)
-    out["training"] = {"collect_steps": args.collect_steps, "pairs": col["samples"],
+    ts = solver.learn_train(kind=B.LEARN_STENCIL, epochs=args.epochs, batch=8, lr=2e-3, seed=0, n_val=n_val)
+    out["training"] = {"kind": "stencil", "collect_steps": args.collect_steps, "pairs": col["samples"],
                        "collect_s": round(t_col, 3), "train_s": round(ts["seconds"], 3),
+                       "refactor_s": round(ts["refactor_seconds"], 3), "spd": ts["spd"],
                        "epochs": args.epochs, "loss_zero": round(ts["loss_zero"], 3),
                        "loss_trained": round(ts["loss_last"], 3),
                        "loss_zero_val": round(ts["loss_zero_val"], 3),
                        "loss_val": round(ts["loss_val"], 3)}
     saved = [t.clone() for t in (v, h, u)]
     n1 = args.collect_steps
-    for name, prec, pc in (("plain_fp64", B.PREC_FP64, B.PRECOND_PLAIN),
-                           ("mixed", B.PREC_MIXED, B.PRECOND_PLAIN),
-                           ("learned_fp64", B.PREC_FP64, B.PRECOND_LEARNED),
-                           ("learned_mixed", B.PREC_MIXED, B.PRECOND_LEARNED)):
+    runs = [("plain_fp64", B.PREC_FP64, B.PRECOND_PLAIN), ("mixed", B.PREC_MIXED, B.PRECOND_PLAIN)]
+    if ts["spd"]:
+        runs += [("learned_fp64", B.PREC_FP64, B.PRECOND_LEARNED),
+                 ("learned_mixed", B.PREC_MIXED, B.PRECOND_LEARNED)]
+    for name, prec, pc in runs:
         solver.set_precision(prec)
         solver.set_precond(pc)
         st = [t.clone() for t in saved]
@@ -191,7 +194,7 @@ def _variants(torch, B, solver, args):
         out[name] = {"steps_per_s": round(args.variant_steps / ws, 3),
                      "cg_iterations_per_step": round(it / args.variant_steps, 3)}
     base = out["plain_fp64"]["steps_per_s"]
-    for name in ("mixed", "learned_fp64", "learned_mixed"):
+    for name in [r[0] for r in runs[1:]]:
         out[name]["speedup_vs_plain"] = round(out[name]["steps_per_s"] / base, 3)
     out["steps"] = [n1, n1 + args.variant_steps]
     solver.set_precision(B.PREC_FP64)

@@ -57,7 +57,11 @@ typedef int bido_status;
 #define BIDO_PREC_MIXED 1  /* preconditioner in FP32 (FP64 outer PCG)      */
 
 #define BIDO_PRECOND_PLAIN   0  /* block-LU / monodomain preconditioner    */
-#define BIDO_PRECOND_LEARNED 1  /* plus a learned correction, flexible CG  */
+#define BIDO_PRECOND_LEARNED 1  /* P_K from K_m + learned stencil C, FCG   */
+#define BIDO_PRECOND_LEARNED_ADDITIVE 2  /* P_K^-1 t + network(t), FCG     */
+
+#define BIDO_LEARN_STENCIL  0   /* train the Schur-complement stencil C     */
+#define BIDO_LEARN_ADDITIVE 1   /* train the additive correction network    */
 
 typedef struct bido_ctx bido_ctx;
 
@@ -192,17 +196,27 @@ bido_status bido_set_solver(bido_ctx* ctx, double tol, int max_iter);
  * point for the triangular sweeps; the solve path does not call it.      */
 bido_status bido_inner_solve(bido_ctx* ctx, int which, const double* b, double* x);
 
-/* --- learned correction of the Schur-complement block (flexible CG) ----- *
- * A two-layer message-passing network delta(t) on the heart vertices (the
- * S_m pattern as graph, hidden width 32, BF16 weights and activations, FP32
- * accumulation) is added to P_K^-1 t in the preconditioner of Def. 2.  It
- * is trained on pairs (t_k, (V* - V_k) - Z2_k) that plain solves record.
- * An untrained network outputs zero; an apply that is not a descent
- * direction is redone without it (bido_stats.fallbacks).                  */
-/* Losses are per sample: r^T W r with r the error of the predicted
- * correction in units of the RMS training target (the network's output
- * unit) and W = K_m scaled to unit mean diagonal, the energy that the
- * correction error leaves in the Schur-complement block.                 */
+/* --- learned correction of the monodomain preconditioner (flexible CG) -- *
+ * One two-layer message-passing network on the heart vertices (the S_m
+ * pattern as graph, hidden width 32, BF16 weights and activations, FP32
+ * accumulation), used in one of two ways:
+ *  - stencil (BIDO_LEARN_STENCIL / BIDO_PRECOND_LEARNED): fed the static
+ *    vertex features only, it gives embeddings h and the symmetric sparse
+ *    correction C_ij = dbar (sum_a w3_a h_ia h_ja + b3 [i==j]) on the S_m
+ *    pattern; trained so that (K_m + C) z*_k ~ t_k on pairs where
+ *    z*_k = V* - V_k is the exact Schur-complement solve of t_k that a
+ *    converged plain solve reveals; K_m + C is then factored (Sec. 5.3) and
+ *    replaces K_m in P_K (Sec. 5.2).  If K_m + C is not SPD the plain
+ *    factor stays.
+ *  - additive (BIDO_LEARN_ADDITIVE / BIDO_PRECOND_LEARNED_ADDITIVE): fed
+ *    t / rms(t) as an extra channel, its output delta(t) is added to
+ *    P_K^-1 t; trained on targets (V* - V_k) - Z2_k.  An apply that is not a
+ *    descent direction is redone without it (bido_stats.fallbacks).
+ * Pairs come from plain solves (bido_learn_collect).                       */
+/* Losses are per sample.  Stencil: |C^ zh - bh|^2 with zh = z* / rms(z*),
+ * bh = (t - K_m z*) / (dbar rms(z*)), C^ = C / dbar.  Additive: r^T W r,
+ * r the error of the predicted correction in units of the RMS target and
+ * W = K_m scaled to unit mean diagonal.                                   */
 typedef struct {
     int samples, train_samples, epochs;
     double loss_zero;       /* mean loss of the zero correction (training)   */
@@ -211,21 +225,24 @@ typedef struct {
     double loss_last;       /* mean training loss after training             */
     double loss_val;        /* mean validation loss after training           */
     double seconds;
+    int spd;                /* stencil: K_m + C factored (1) or not (0)       */
+    double refactor_seconds;
 } bido_train_stats;
 
-/* BIDO_PRECOND_PLAIN or BIDO_PRECOND_LEARNED for later solves.            */
+/* BIDO_PRECOND_* for later solves; BIDO_PRECOND_LEARNED needs a trained
+ * stencil (BIDO_ERR_STATE otherwise).                                      */
 bido_status bido_set_precond(bido_ctx* ctx, int precond);
 
 /* Run n_steps plain steps (as bido_run) recording training pairs, up to
- * max_samples in total (device memory: 8 N_H bytes per sample).            */
+ * max_samples in total (device memory: 16 N_H + 16 bytes per sample).            */
 bido_status bido_learn_collect(bido_ctx* ctx, double* v, double* w, double* u, double dt,
                                int64_t n0, int64_t n_steps, int max_samples, bido_stats* st);
 bido_status bido_learn_samples(const bido_ctx* ctx, int* n_samples);
 
-/* Adam on the FP32 master weights over the first (samples - n_val) pairs,
- * mini-batches of `batch`, shuffled by `seed`; the last n_val pairs are
- * held out for the validation loss.                                        */
-bido_status bido_learn_train(bido_ctx* ctx, int epochs, int batch, float lr, uint64_t seed,
+/* Train for `kind` (BIDO_LEARN_*): Adam on the FP32 master weights over the
+ * first (samples - n_val) pairs, mini-batches of `batch`, shuffled by
+ * `seed`; the last n_val pairs are held out for the validation loss.     */
+bido_status bido_learn_train(bido_ctx* ctx, int kind, int epochs, int batch, float lr, uint64_t seed,
                              int n_val, bido_train_stats* st);
 
 /* FP32 master weights (3169 floats, layout W1s W1n b1 W2s W2n b2 w3 b3):
@@ -240,6 +257,11 @@ bido_status bido_weights_io(bido_ctx* ctx, float* buf, int n, int dir);
  * gradient (host outputs), with the output unit 1.                        */
 bido_status bido_gnn_eval(bido_ctx* ctx, const double* t, double* out);
 bido_status bido_gnn_loss_grad(bido_ctx* ctx, const float* that, const float* y, double* loss,
+                               float* grad);
+/* stencil_check: with the current weights, for device FP32 vectors zh, bh in
+ * heart-local order: r = C^ zh - bh (device FP32, heart-local; may be NULL),
+ * the loss |r|^2 and its gradient (host; grad may be NULL).               */
+bido_status bido_stencil_check(bido_ctx* ctx, const float* zh, const float* bh, float* r, double* loss,
                                float* grad);
 
 /* Per-kernel profile: launches, summed event-timed duration [ms] and the

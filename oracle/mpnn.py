@@ -172,3 +172,72 @@ def init_params(seed):
             fan_in = shape[-1] if len(shape) > 1 else HID
             p[name] = rng.normal(0.0, 1.0 / np.sqrt(fan_in), size=shape)
     return pack(p)
+
+
+# ---------------------------------------------------------------------------
+# Learned Schur-complement stencil: K_m + C ~ K
+#
+# The network of this module, fed a constant first channel (f0 = 1) and the
+# static features, gives vertex embeddings h2.  On the sparsity pattern of
+# S_m the symmetric correction is
+#     C_ij = dbar * (sum_a w3_a h2_ia h2_ja + b3 [i == j])
+# with dbar the mean diagonal of K_m, so that K_m + C is a symmetric sparse
+# approximation of the Schur complement K of Prop. 2 (which K_m replaces
+# in Sec. 5.2).  Exact Schur-complement solves z* = K^-1 t are available
+# from converged solves (z* = V* - V_k for the residual t_k of iteration k),
+# hence the regression  C z*_k ~ t_k - K_m z*_k,  in units of dbar * rms(z*_k):
+#     loss = sum_k |C^ zh_k - bh_k|^2,  zh = z*/rms(z*),
+#     bh = (t - K_m z*) / (dbar rms(z*)),  C^ = C / dbar.
+# ---------------------------------------------------------------------------
+def static_input(static):
+    f = np.zeros((static.shape[0], F))
+    f[:, 0] = 1.0
+    f[:, 1:] = static
+    return f
+
+
+def stencil_values(theta, A, f, P):
+    """C^ on the pattern P (CSR, with diagonal); returns (values, cache)."""
+    p = unpack(theta)
+    _, c = forward(theta, A, f)
+    P = sp.csr_matrix(P)
+    rows = np.repeat(np.arange(P.shape[0]), np.diff(P.indptr))
+    cols = P.indices
+    h2 = c["h2"]
+    vals = np.einsum("ka,a,ka->k", h2[rows], p["w3"], h2[cols]) + p["b3"][0] * (rows == cols)
+    return vals, (c, rows, cols)
+
+
+def stencil_matrix(theta, A, f, P):
+    vals, (c, rows, cols) = stencil_values(theta, A, f, P)
+    return sp.csr_matrix((vals, (rows, cols)), shape=P.shape)
+
+
+def stencil_loss_and_grad(theta, A, f, P, Zh, Bh):
+    """Loss sum_k |C^ zh_k - bh_k|^2 over samples (rows of Zh, Bh) and its
+    gradient with respect to theta."""
+    p = unpack(theta)
+    vals, (c, rows, cols) = stencil_values(theta, A, f, P)
+    C = sp.csr_matrix((vals, (rows, cols)), shape=P.shape)
+    R = (C @ Zh.T).T - Bh                       # (samples, n)
+    loss = float(np.sum(R * R))
+    # d loss / d C_ij on the pattern
+    G = 2.0 * np.sum(R[:, rows] * Zh[:, cols], axis=0)
+    h2 = c["h2"]
+    g = {}
+    g["w3"] = np.einsum("k,ka,ka->a", G, h2[rows], h2[cols])
+    g["b3"] = np.array([np.sum(G[rows == cols])])
+    # d loss / d h2_i = sum_j G_ij w3 h2_j + sum_j G_ji w3 h2_j
+    dh2 = np.zeros_like(h2)
+    np.add.at(dh2, rows, G[:, None] * p["w3"] * h2[cols])
+    np.add.at(dh2, cols, G[:, None] * p["w3"] * h2[rows])
+    dz2 = dh2 * (c["z2"] > 0)
+    g["W2s"] = dz2.T @ c["h1"]
+    g["W2n"] = dz2.T @ c["m1"]
+    g["b2"] = dz2.sum(axis=0)
+    dh1 = dz2 @ p["W2s"] + A.T @ (dz2 @ p["W2n"])
+    dz1 = dh1 * (c["z1"] > 0)
+    g["W1s"] = dz1.T @ c["f"]
+    g["W1n"] = dz1.T @ c["m0"]
+    g["b1"] = dz1.sum(axis=0)
+    return loss, pack(g)

@@ -18,7 +18,8 @@ ERRORS = {-1: "BIDO_ERR_ARG", -2: "BIDO_ERR_DEVICE", -3: "BIDO_ERR_NOT_SPD",
           -4: "BIDO_ERR_NOT_CONVERGED", -5: "BIDO_ERR_DT_MISMATCH",
           -6: "BIDO_ERR_RANGE", -7: "BIDO_ERR_STATE"}
 PREC_FP64, PREC_MIXED = 0, 1
-PRECOND_PLAIN, PRECOND_LEARNED = 0, 1
+PRECOND_PLAIN, PRECOND_LEARNED, PRECOND_LEARNED_ADDITIVE = 0, 1, 2
+LEARN_STENCIL, LEARN_ADDITIVE = 0, 1
 MAT_S1, MAT_SI, MAT_SM, MAT_LAMBDA, MAT_GNN_AGG = 0, 1, 2, 3, 4
 VEC_M, VEC_MH, VEC_GNN_STATIC = 0, 1, 2
 IDX_UPOS, IDX_VPOS, IDX_HEART = 0, 1, 2
@@ -78,7 +79,8 @@ class TrainStats(ctypes.Structure):
     _fields_ = [("samples", ctypes.c_int), ("train_samples", ctypes.c_int), ("epochs", ctypes.c_int),
                 ("loss_zero", ctypes.c_double), ("loss_zero_val", ctypes.c_double),
                 ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
-                ("loss_val", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("loss_val", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("spd", ctypes.c_int), ("refactor_seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -120,12 +122,15 @@ ABI = {
                                           ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
                                           ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Stats)]),
     "bido_learn_samples": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
-    "bido_learn_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_float,
-                                        ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(TrainStats)]),
+    "bido_learn_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_float, ctypes.c_uint64, ctypes.c_int,
+                                        ctypes.POINTER(TrainStats)]),
     "bido_weights_io": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int,
                                        ctypes.c_int]),
     "bido_gnn_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "bido_gnn_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)]),
+    "bido_stencil_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)]),
     "bido_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KProf), ctypes.c_int,
@@ -310,10 +315,10 @@ class Solver:
         d["samples"] = n.value
         return d
 
-    def learn_train(self, epochs=20, batch=8, lr=1e-3, seed=0, n_val=0):
+    def learn_train(self, kind=LEARN_STENCIL, epochs=20, batch=8, lr=1e-3, seed=0, n_val=0):
         ts = TrainStats()
-        _check(lib.bido_learn_train(self.ctx, int(epochs), int(batch), float(lr), int(seed), int(n_val),
-                                    ctypes.byref(ts)))
+        _check(lib.bido_learn_train(self.ctx, int(kind), int(epochs), int(batch), float(lr), int(seed),
+                                    int(n_val), ctypes.byref(ts)))
         return ts.as_dict()
 
     def weights(self):
@@ -340,6 +345,20 @@ class Solver:
         _check(lib.bido_gnn_loss_grad(self.ctx, ctypes.c_void_p(that.data_ptr()),
                                       ctypes.c_void_p(y.data_ptr()), ctypes.byref(loss), grad))
         return loss.value, np.ctypeslib.as_array(grad).astype(np.float64).copy()
+
+    def stencil_check(self, zh, bh, grad=True):
+        """(r, loss, grad) of the learned stencil with the current weights:
+        r = C^ zh - bh (FP32 CUDA tensor), loss = |r|^2, grad = d loss / d theta."""
+        torch = self.torch
+        for a in (zh, bh):
+            if not (a.is_cuda and a.dtype == torch.float32 and a.numel() == self.NH and a.is_contiguous()):
+                raise BidoError(-1, "expected contiguous float32 CUDA tensors of N_H entries")
+        r = torch.empty_like(zh)
+        loss = ctypes.c_double()
+        g = (ctypes.c_float * GNN_P)() if grad else None
+        _check(lib.bido_stencil_check(self.ctx, ctypes.c_void_p(zh.data_ptr()), ctypes.c_void_p(bh.data_ptr()),
+                                      ctypes.c_void_p(r.data_ptr()), ctypes.byref(loss), g))
+        return r, loss.value, (np.ctypeslib.as_array(g).astype(np.float64).copy() if grad else None)
 
     def set_precision(self, precision):
         _check(lib.bido_set_precision(self.ctx, int(precision)))

@@ -216,6 +216,15 @@ struct GnnState {
     bool collecting = false;
     int adam_step = 0;
     float out_scale = 1.0f;                // output unit: RMS of the training targets
+    // learned Schur-complement stencil (K_m + C)
+    StencilPattern P;
+    StencilKm K;
+    double dbar = 1.0;                     // mean diagonal of K_m
+    float *cval = nullptr, *G = nullptr, *r = nullptr;
+    float *s_z = nullptr, *s_b = nullptr;  // samples z*/rms and (t - K_m z*)/(dbar rms)
+    double *s_zz = nullptr;
+    double *pend_t = nullptr, *pend_v = nullptr;
+    bool stencil_ready = false;
     void release() {
         for (void* b : {(void*)stat, (void*)A.ptr, (void*)A.col, (void*)A.val, (void*)At.ptr, (void*)At.col,
                         (void*)At.val, (void*)Wk.ptr, (void*)Wk.col, (void*)Wk.val, (void*)act.res,
@@ -252,6 +261,7 @@ struct bido_ctx {
     std::vector<int64_t> heart_ids;
     Profiler prof;
     GnnState gnn;
+    FactorDev pk_learned;             // factor of K_m + C (learned stencil)
     int precond = BIDO_PRECOND_PLAIN;
     int fallbacks = 0;
 
@@ -259,6 +269,7 @@ struct bido_ctx {
         if (stream) hipStreamSynchronize(stream);
         p1.release();
         pk.release();
+        pk_learned.release();
         gnn.release();
         CsrHostView::release(lam);
         CsrHostView::release(avu);
@@ -352,7 +363,8 @@ void debug_check(bido_ctx* c, const char* name, const double* v, int64_t n) {
 // z = P_Lambda^-1 r  and  rho_new = r.z  (plus z.r_old for flexible CG).
 // learned: add the network's correction to Z2 (Schur-complement block);
 // collecting: record (t, V_k + Z2_k) for training targets.
-void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old, bool learned) {
+void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old, bool learned,
+                   bool stencil = false) {
     hipStream_t s = c->stream;
     const int64_t N = c->N, NH = c->NH;
     GnnState& g = c->gnn;
@@ -362,13 +374,17 @@ void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old,
     PROF(c, K_SPMV_CSR, csr_bytes(c->avu, c->NH) + 8.0 * c->NH,
          launch_spmv_csr(s, c->avu, c->spmv_group, c->tA, r + N, c->tB));  // R2 - S_i Pi Z1
     debug_check(c, "t", c->tB, c->NH);
-    inner_solve(c, c->pk, c->tB, z + N);                             // Z2 = PK^-1 (...)
+    inner_solve(c, stencil ? c->pk_learned : c->pk, c->tB, z + N);  // Z2 = PK^-1 (...)
     debug_check(c, "Z2", z + N, c->NH);
     if (g.collecting && g.n_samples + g.n_pending < g.max_samples && g.n_pending < g.max_pending) {
         const int k = g.n_samples + g.n_pending;
         launch_dot_reduce(s, NH, c->tB, c->tB, c->rd, g.s_tn2 + k);
         launch_gnn_store_sample(s, NH, c->tB, g.s_tn2 + k, g.s_t + (int64_t)k * NH);
         launch_gnn_pending(s, NH, c->x + N, z + N, g.pend + (int64_t)g.n_pending * NH);
+        hipMemcpyAsync(g.pend_t + (int64_t)g.n_pending * NH, c->tB, NH * sizeof(double),
+                       hipMemcpyDeviceToDevice, s);
+        hipMemcpyAsync(g.pend_v + (int64_t)g.n_pending * NH, c->x + N, NH * sizeof(double),
+                       hipMemcpyDeviceToDevice, s);
         ++g.n_pending;
     }
     if (learned) {
@@ -400,19 +416,20 @@ bido_status read_scalars(bido_ctx* c) {
 bido_status pcg(bido_ctx* c, double tol, bido_stats* st) {
     hipStream_t s = c->stream;
     const int64_t n = c->n2;
-    const bool learned = c->precond == BIDO_PRECOND_LEARNED && !c->gnn.collecting;
-    const bool flexible = c->precision == BIDO_PREC_MIXED || learned;
+    const bool learned = c->precond == BIDO_PRECOND_LEARNED_ADDITIVE && !c->gnn.collecting;
+    const bool stencil = c->precond == BIDO_PRECOND_LEARNED && !c->gnn.collecting && c->gnn.stencil_ready;
+    const bool flexible = c->precision == BIDO_PREC_MIXED || learned || stencil;
     double* r_old = flexible ? c->r_old : nullptr;
     int fallbacks = 0;
     auto apply = [&](const double* ro) -> bido_status {
-        precond_apply(c, c->r, c->z, ro, learned);
-        if (!learned) return BIDO_OK;
+        precond_apply(c, c->r, c->z, ro, learned, stencil);
+        if (!learned && !stencil) return BIDO_OK;
         bido_status e2 = read_scalars(c);
         if (e2) return e2;
         const double rz = c->sc_host[S_RHO_NEW];
         if (!(rz > 0.0) || !std::isfinite(rz)) {
             ++fallbacks;
-            precond_apply(c, c->r, c->z, ro, false);
+            precond_apply(c, c->r, c->z, ro, false, false);
         }
         return BIDO_OK;
     };
@@ -465,8 +482,14 @@ void finish_collection(bido_ctx* c, bool converged) {
     if (converged)
         for (int k = 0; k < g.n_pending; ++k) {
             const int slot = g.n_samples + k;
-            launch_gnn_finish_targets(c->stream, c->NH, c->x + c->N, g.pend + (int64_t)k * c->NH,
-                                      g.s_tn2 + slot, g.s_y + (int64_t)slot * c->NH);
+            const int64_t NH = c->NH;
+            launch_gnn_finish_targets(c->stream, NH, c->x + c->N, g.pend + (int64_t)k * NH,
+                                      g.s_tn2 + slot, g.s_y + (int64_t)slot * NH);
+            // stencil pair: z* = V* - V_k, b = t_k - K_m z*
+            launch_gnn_sub(c->stream, NH, c->x + c->N, g.pend_v + (int64_t)k * NH, g.tz);
+            launch_dot_reduce(c->stream, NH, g.tz, g.tz, c->rd, g.s_zz + slot);
+            launch_stencil_sample(c->stream, NH, g.K, g.tz, g.s_zz + slot, g.pend_t + (int64_t)k * NH,
+                                  g.dbar, g.s_z + (int64_t)slot * NH, g.s_b + (int64_t)slot * NH);
         }
     if (converged) g.n_samples += g.n_pending;
     g.n_pending = 0;
@@ -542,6 +565,38 @@ bido_status gnn_setup(bido_ctx* c) {
     bido_status e;
     if ((e = up_graph(rows, g.A))) return e;
     if ((e = up_graph(trows, g.At))) return e;
+    // stored S_m pattern (= pattern of K_m) in internal order, and K_m itself
+    {
+        const Csr& Km = hs.km_int;
+        std::vector<int32_t> row(Km.nnz()), tpos(Km.nnz());
+        for (int64_t i = 0; i < NH; ++i)
+            for (int64_t p = Km.ptr[i]; p < Km.ptr[i + 1]; ++p) row[p] = (int32_t)i;
+        for (int64_t i = 0; i < NH; ++i)
+            for (int64_t p = Km.ptr[i]; p < Km.ptr[i + 1]; ++p) {
+                const int64_t j = Km.col[p];
+                const auto b = Km.col.begin() + Km.ptr[j], e = Km.col.begin() + Km.ptr[j + 1];
+                const auto it = std::lower_bound(b, e, (int32_t)i);
+                if (it == e || *it != (int32_t)i) return fail(BIDO_ERR_ARG, "S_m pattern is not symmetric");
+                tpos[p] = (int32_t)(it - Km.col.begin());
+            }
+        g.P.n = NH;
+        g.P.nnz = Km.nnz();
+        HIP_OK(upload(&g.P.ptr, Km.ptr.data(), Km.ptr.size()));
+        HIP_OK(upload(&g.P.col, Km.col.data(), std::max<size_t>(Km.col.size(), 1)));
+        HIP_OK(upload(&g.P.row, row.data(), std::max<size_t>(row.size(), 1)));
+        HIP_OK(upload(&g.P.tpos, tpos.data(), std::max<size_t>(tpos.size(), 1)));
+        HIP_OK(upload(&g.K.ptr, Km.ptr.data(), Km.ptr.size()));
+        HIP_OK(upload(&g.K.col, Km.col.data(), std::max<size_t>(Km.col.size(), 1)));
+        HIP_OK(upload(&g.K.val, Km.val.data(), std::max<size_t>(Km.val.size(), 1)));
+        double dsum = 0.0;
+        for (int64_t i = 0; i < NH; ++i)
+            for (int64_t p = Km.ptr[i]; p < Km.ptr[i + 1]; ++p)
+                if (Km.col[p] == i) dsum += Km.val[p];
+        g.dbar = dsum / std::max<int64_t>(NH, 1);
+        HIP_OK(hipMalloc((void**)&g.cval, std::max<int64_t>(Km.nnz(), 1) * sizeof(float)));
+        HIP_OK(hipMalloc((void**)&g.G, std::max<int64_t>(Km.nnz(), 1) * sizeof(float)));
+        HIP_OK(hipMalloc((void**)&g.r, std::max<int64_t>(NH, 1) * sizeof(float)));
+    }
     // K_m = gamma M_H + S_m scaled to unit mean diagonal, internal order
     {
         const Csr& Sm = hs.A.Sm;
@@ -679,7 +734,7 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     HIP_OK(hipEventCreate(&c->ev0));
     HIP_OK(hipEventCreate(&c->ev1));
     if ((e = gnn_setup(c.get()))) return e;
-    c->precond = params->precond;
+    c->precond = params->precond == BIDO_PRECOND_LEARNED_ADDITIVE ? params->precond : BIDO_PRECOND_PLAIN;
     HIP_OK(hipDeviceSynchronize());
     *out = c.release();
     return BIDO_OK;
@@ -770,7 +825,11 @@ bido_status bido_inner_solve(bido_ctx* c, int which, const double* b, double* x)
 
 bido_status bido_set_precond(bido_ctx* c, int precond) {
     if (!c) return fail(BIDO_ERR_ARG, "null context");
-    if (precond != BIDO_PRECOND_PLAIN && precond != BIDO_PRECOND_LEARNED) return fail(BIDO_ERR_ARG, "bad precond");
+    if (precond != BIDO_PRECOND_PLAIN && precond != BIDO_PRECOND_LEARNED &&
+        precond != BIDO_PRECOND_LEARNED_ADDITIVE)
+        return fail(BIDO_ERR_ARG, "bad precond");
+    if (precond == BIDO_PRECOND_LEARNED && !c->gnn.stencil_ready)
+        return fail(BIDO_ERR_STATE, "the learned stencil has not been trained (or K_m + C was not SPD)");
     c->precond = precond;
     return BIDO_OK;
 }
@@ -781,21 +840,33 @@ bido_status bido_learn_collect(bido_ctx* c, double* v, double* w, double* u, dou
     GnnState& g = c->gnn;
     if (max_samples > g.max_samples) {
         hipStreamSynchronize(c->stream);
-        float *nt = nullptr, *ny = nullptr;
-        double* nn = nullptr;
-        HIP_OK(hipMalloc((void**)&nt, (size_t)max_samples * c->NH * sizeof(float)));
-        HIP_OK(hipMalloc((void**)&ny, (size_t)max_samples * c->NH * sizeof(float)));
-        HIP_OK(hipMalloc((void**)&nn, (size_t)max_samples * sizeof(double)));
-        if (g.n_samples > 0) {
-            HIP_OK(hipMemcpy(nt, g.s_t, (size_t)g.n_samples * c->NH * sizeof(float), hipMemcpyDeviceToDevice));
-            HIP_OK(hipMemcpy(ny, g.s_y, (size_t)g.n_samples * c->NH * sizeof(float), hipMemcpyDeviceToDevice));
-            HIP_OK(hipMemcpy(nn, g.s_tn2, (size_t)g.n_samples * sizeof(double), hipMemcpyDeviceToDevice));
-        }
-        hipFree(g.s_t); hipFree(g.s_y); hipFree(g.s_tn2);
-        g.s_t = nt; g.s_y = ny; g.s_tn2 = nn;
+        auto grow = [&](float** buf) -> bido_status {
+            float* nb = nullptr;
+            HIP_OK(hipMalloc((void**)&nb, (size_t)max_samples * std::max<int64_t>(c->NH, 1) * sizeof(float)));
+            if (g.n_samples > 0)
+                HIP_OK(hipMemcpy(nb, *buf, (size_t)g.n_samples * c->NH * sizeof(float), hipMemcpyDeviceToDevice));
+            hipFree(*buf);
+            *buf = nb;
+            return BIDO_OK;
+        };
+        auto growd = [&](double** buf) -> bido_status {
+            double* nb = nullptr;
+            HIP_OK(hipMalloc((void**)&nb, (size_t)max_samples * sizeof(double)));
+            if (g.n_samples > 0)
+                HIP_OK(hipMemcpy(nb, *buf, (size_t)g.n_samples * sizeof(double), hipMemcpyDeviceToDevice));
+            hipFree(*buf);
+            *buf = nb;
+            return BIDO_OK;
+        };
+        bido_status e1;
+        for (float** b : {&g.s_t, &g.s_y, &g.s_z, &g.s_b})
+            if ((e1 = grow(b))) return e1;
+        for (double** b : {&g.s_tn2, &g.s_zz})
+            if ((e1 = growd(b))) return e1;
         g.max_samples = max_samples;
     }
-    if (!g.pend) HIP_OK(hipMalloc((void**)&g.pend, (size_t)g.max_pending * std::max<int64_t>(c->NH, 1) * sizeof(double)));
+    for (double** b : {&g.pend, &g.pend_t, &g.pend_v})
+        if (!*b) HIP_OK(hipMalloc((void**)b, (size_t)g.max_pending * std::max<int64_t>(c->NH, 1) * sizeof(double)));
     g.collecting = true;
     g.n_pending = 0;
     bido_status e = bido_run(c, v, w, u, dt, n0, n_steps, st);
@@ -809,12 +880,10 @@ bido_status bido_learn_samples(const bido_ctx* c, int* n_samples) {
     return BIDO_OK;
 }
 
-bido_status bido_learn_train(bido_ctx* c, int epochs, int batch, float lr, uint64_t seed, int n_val,
-                             bido_train_stats* ts) {
-    if (!c || epochs < 0 || batch < 1 || !(lr > 0)) return fail(BIDO_ERR_ARG, "bad argument");
+static bido_status train_additive(bido_ctx* c, int epochs, int batch, float lr, uint64_t seed, int n_val,
+                                  bido_train_stats* ts) {
     GnnState& g = c->gnn;
     const int n_tr = g.n_samples - n_val;
-    if (n_val < 0 || n_tr < 1) return fail(BIDO_ERR_STATE, "not enough collected samples");
     hipStream_t s = c->stream;
     const int64_t NH = c->NH;
     auto t0 = std::chrono::steady_clock::now();
@@ -882,6 +951,110 @@ bido_status bido_learn_train(bido_ctx* c, int epochs, int batch, float lr, uint6
     return BIDO_OK;
 }
 
+// Learned Schur-complement stencil: regression C z*_k ~ t_k - K_m z*_k over
+// the recorded pairs, then the factor of K_m + C replaces P_K in the learned
+// mode (the plain factor stays, and is kept if K_m + C is not SPD).
+static bido_status train_stencil(bido_ctx* c, int epochs, int batch, float lr, uint64_t seed, int n_val,
+                                 bido_train_stats* ts) {
+    GnnState& g = c->gnn;
+    const int n_tr = g.n_samples - n_val;
+    hipStream_t s = c->stream;
+    const int64_t NH = c->NH;
+    auto t0 = std::chrono::steady_clock::now();
+    double hl[4];
+    auto eval = [&](int k0, int k1, double* dst, bool zero_c) {
+        if (zero_c) HIP_OK(hipMemsetAsync(g.cval, 0, std::max<int64_t>(g.P.nnz, 1) * sizeof(float), s));
+        for (int k = k0; k < k1; ++k)
+            launch_stencil_sample_loss(s, g.P, g.cval, g.s_z + (int64_t)k * NH, g.s_b + (int64_t)k * NH, g.r,
+                                       nullptr, g.partials, dst);
+        return BIDO_OK;
+    };
+    HIP_OK(hipMemsetAsync(g.dloss, 0, 4 * sizeof(double), s));
+    eval(0, n_tr, g.dloss + 0, true);
+    eval(n_tr, g.n_samples, g.dloss + 1, true);
+    launch_gnn_embed(s, NH, g.stat, g.A, g.wbf, g.act);
+    launch_stencil_values(s, g.P, g.act.h2, g.wbf, g.cval);
+    eval(0, n_tr, g.dloss + 2, false);
+    HIP_OK(hipMemcpyAsync(hl, g.dloss, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (ts) {
+        std::memset(ts, 0, sizeof(*ts));
+        ts->samples = g.n_samples;
+        ts->train_samples = n_tr;
+        ts->loss_zero = hl[0] / n_tr;
+        ts->loss_zero_val = n_val ? hl[1] / n_val : 0.0;
+        ts->loss_first = hl[2] / n_tr;
+    }
+    std::mt19937_64 rng(seed);
+    std::vector<int> order(n_tr);
+    for (int k = 0; k < n_tr; ++k) order[k] = k;
+    for (int ep = 0; ep < epochs; ++ep) {
+        std::shuffle(order.begin(), order.end(), rng);
+        for (int b0 = 0; b0 < n_tr; b0 += batch) {
+            const int b1 = std::min(n_tr, b0 + batch);
+            launch_gnn_embed(s, NH, g.stat, g.A, g.wbf, g.act);
+            launch_stencil_values(s, g.P, g.act.h2, g.wbf, g.cval);
+            HIP_OK(hipMemsetAsync(g.G, 0, std::max<int64_t>(g.P.nnz, 1) * sizeof(float), s));
+            for (int q = b0; q < b1; ++q) {
+                const int k = order[q];
+                launch_stencil_sample_loss(s, g.P, g.cval, g.s_z + (int64_t)k * NH, g.s_b + (int64_t)k * NH,
+                                           g.r, g.G, g.partials, g.dloss + 3);
+            }
+            HIP_OK(hipMemsetAsync(g.grad, 0, GNN_P * sizeof(float), s));
+            launch_stencil_backward(s, g.P, g.At, g.G, g.wbf, g.act, g.partials, g.grad);
+            launch_gnn_adam(s, g.theta, g.m, g.v, g.grad, 1.0f / (float)(b1 - b0), lr, ++g.adam_step, g.wbf);
+        }
+    }
+    launch_gnn_embed(s, NH, g.stat, g.A, g.wbf, g.act);
+    launch_stencil_values(s, g.P, g.act.h2, g.wbf, g.cval);
+    HIP_OK(hipMemsetAsync(g.dloss, 0, 4 * sizeof(double), s));
+    eval(0, n_tr, g.dloss + 2, false);
+    eval(n_tr, g.n_samples, g.dloss + 3, false);
+    std::vector<float> cv(std::max<int64_t>(g.P.nnz, 1));
+    HIP_OK(hipMemcpyAsync(hl, g.dloss, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(cv.data(), g.cval, cv.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (ts) {
+        ts->epochs = epochs;
+        ts->loss_last = hl[2] / n_tr;
+        ts->loss_val = n_val ? hl[3] / n_val : 0.0;
+    }
+    // factor K_m + C on the host and upload it as the learned P_K
+    auto t1 = std::chrono::steady_clock::now();
+    Csr Kt = c->hs.km_int;
+    for (int64_t p = 0; p < Kt.nnz(); ++p) Kt.val[p] += g.dbar * (double)cv[p];
+    Factor f;
+    f.tree = c->hs.pk.tree;
+    std::string err;
+    const bool spd = multifrontal(Kt, f, -1, c->params.n_threads, err);
+    if (spd) {
+        c->pk_learned.release();
+        bido_status e = build_factor_dev(f, true, c->pk_learned);
+        if (e) return e;
+        for (FactorDev* fd : {&c->pk_learned}) {
+            HIP_OK(hipMemset(fd->ytmp, 0xFF, std::max<int64_t>(fd->n, 1) * sizeof(double)));
+            HIP_OK(hipMemset(fd->upd, 0xFF, std::max<int64_t>(fd->upd_size, 1) * sizeof(double)));
+        }
+    }
+    g.stencil_ready = spd;
+    if (ts) {
+        ts->spd = spd ? 1 : 0;
+        ts->refactor_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+        ts->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return BIDO_OK;
+}
+
+bido_status bido_learn_train(bido_ctx* c, int kind, int epochs, int batch, float lr, uint64_t seed, int n_val,
+                             bido_train_stats* ts) {
+    if (!c || epochs < 0 || batch < 1 || !(lr > 0)) return fail(BIDO_ERR_ARG, "bad argument");
+    const int n_tr = c->gnn.n_samples - n_val;
+    if (n_val < 0 || n_tr < 1) return fail(BIDO_ERR_STATE, "not enough collected samples");
+    if (kind == BIDO_LEARN_STENCIL) return train_stencil(c, epochs, batch, lr, seed, n_val, ts);
+    if (kind == BIDO_LEARN_ADDITIVE) return train_additive(c, epochs, batch, lr, seed, n_val, ts);
+    return fail(BIDO_ERR_ARG, "unknown learning target");
+}
+
 bido_status bido_weights_io(bido_ctx* c, float* buf, int n, int dir) {
     if (!c || !buf || n != GNN_P || (dir != 0 && dir != 1)) return fail(BIDO_ERR_ARG, "bad argument");
     GnnState& g = c->gnn;
@@ -928,6 +1101,29 @@ bido_status bido_gnn_loss_grad(bido_ctx* c, const float* that, const float* y, d
     launch_gnn_backward(s, NH, g.fy, g.Wk, g.At, g.wbf, g.act, g.partials, g.grad, g.dloss, 1.0f);
     HIP_OK(hipMemcpyAsync(loss, g.dloss, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_OK(hipMemcpyAsync(grad, g.grad, GNN_P * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
+    return BIDO_OK;
+}
+
+bido_status bido_stencil_check(bido_ctx* c, const float* zh, const float* bh, float* r, double* loss,
+                               float* grad) {
+    if (!c || !zh || !bh || !loss) return fail(BIDO_ERR_ARG, "null argument");
+    hipStream_t s = c->stream;
+    GnnState& g = c->gnn;
+    const int64_t NH = c->NH;
+    launch_scatter_in_f(s, NH, c->v_pos, zh, g.ft);
+    launch_scatter_in_f(s, NH, c->v_pos, bh, g.fy);
+    HIP_OK(hipMemsetAsync(g.grad, 0, GNN_P * sizeof(float), s));
+    HIP_OK(hipMemsetAsync(g.dloss, 0, sizeof(double), s));
+    HIP_OK(hipMemsetAsync(g.G, 0, std::max<int64_t>(g.P.nnz, 1) * sizeof(float), s));
+    launch_gnn_embed(s, NH, g.stat, g.A, g.wbf, g.act);
+    launch_stencil_values(s, g.P, g.act.h2, g.wbf, g.cval);
+    launch_stencil_sample_loss(s, g.P, g.cval, g.ft, g.fy, g.r, g.G, g.partials, g.dloss);
+    if (grad) launch_stencil_backward(s, g.P, g.At, g.G, g.wbf, g.act, g.partials, g.grad);
+    if (r) launch_gather_f(s, NH, c->v_pos, g.r, r);
+    HIP_OK(hipMemcpyAsync(loss, g.dloss, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (grad) HIP_OK(hipMemcpyAsync(grad, g.grad, GNN_P * sizeof(float), hipMemcpyDeviceToHost, s));
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(s));
     return BIDO_OK;

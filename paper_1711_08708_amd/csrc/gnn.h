@@ -29,6 +29,20 @@ struct GnnGraph {                 // row-normalised neighbour weights (internal 
     float* val = nullptr;
 };
 
+struct StencilPattern {           // stored pattern of S_m, internal v order
+    int64_t n = 0, nnz = 0;
+    int64_t* ptr = nullptr;
+    int32_t* col = nullptr;
+    int32_t* row = nullptr;       // row of each entry
+    int32_t* tpos = nullptr;      // entry of the transposed position
+};
+
+struct StencilKm {                // K_m = gamma M_H + S_m, FP64, internal v order
+    int64_t* ptr = nullptr;
+    int32_t* col = nullptr;
+    double* val = nullptr;
+};
+
 struct GnnAct {                   // activations of one forward pass
     uint16_t *f = nullptr, *m0 = nullptr, *h1 = nullptr, *m1 = nullptr, *h2 = nullptr;  // bf16
     float* o = nullptr;
@@ -61,6 +75,21 @@ void launch_gnn_energy0(hipStream_t s, int64_t n, const float* y, const GnnGraph
 void launch_gnn_adam(hipStream_t s, float* theta, float* m, float* v, const float* grad, float scale,
                      float lr, int step, uint16_t* wbf);
 void launch_gnn_to_bf16(hipStream_t s, const float* theta, uint16_t* wbf);
+
+// learned Schur-complement stencil (K_m + C, Sec. 5.2): embeddings from the
+// static features, stencil values, per-sample residual/loss (G += dloss/dC
+// when G is given), backward from G to the weight gradient, sample targets
+void launch_gnn_embed(hipStream_t s, int64_t n, const float* stat, const GnnGraph& A, const uint16_t* wbf,
+                      GnnAct& a);
+void launch_stencil_values(hipStream_t s, const StencilPattern& P, const uint16_t* h2, const uint16_t* wbf,
+                           float* cval);
+void launch_stencil_sample_loss(hipStream_t s, const StencilPattern& P, const float* cval, const float* zh,
+                                const float* bh, float* r, float* G, float* partials, double* loss);
+void launch_stencil_backward(hipStream_t s, const StencilPattern& P, const GnnGraph& At, const float* G,
+                             const uint16_t* wbf, GnnAct& a, float* partials, float* grad);
+void launch_gnn_sub(hipStream_t s, int64_t n, const double* a, const double* b, double* out);
+void launch_stencil_sample(hipStream_t s, int64_t n, const StencilKm& K, const double* z, const double* zz,
+                           const double* t, double dbar, float* zh, float* bh);
 void launch_gnn_store_sample(hipStream_t s, int64_t n, const double* t, const double* tn2, float* that);
 void launch_gnn_finish_targets(hipStream_t s, int64_t n, const double* vstar, const double* d,
                                const double* tn2, float* y);

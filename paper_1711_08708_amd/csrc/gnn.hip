@@ -35,6 +35,8 @@ __global__ void k_input(int64_t n, const double* __restrict__ t, const double* _
     if (j == 0) {
         if (that) {
             v = that[i];
+        } else if (!t) {
+            v = 1.0f;                      // embedding mode: constant channel
         } else {
             const double rms = sqrt(*tn2 / (double)n);
             v = rms > 0.0 ? (float)(t[i] / rms) : 0.0f;
@@ -362,10 +364,162 @@ void launch_gnn_energy0(hipStream_t s, int64_t n, const float* y, const GnnGraph
     k_reduce_grad<<<1, BLOCK, 0, s>>>(0, partials, nullptr, loss_part, (int)nb, out);
 }
 
+// ---------------------------------------------------------------------------
+// Learned Schur-complement stencil C^_p = sum_a w3_a h2_ia h2_ja + b3 [i==j]
+// on the stored pattern of S_m (entry p = (row[p], col[p]), tpos[p] = index
+// of (col[p], row[p])).
+// ---------------------------------------------------------------------------
+__global__ void k_cvals(int64_t nnz, const int32_t* __restrict__ row, const int32_t* __restrict__ col,
+                        const uint16_t* __restrict__ h2, const uint16_t* __restrict__ wbf,
+                        float* __restrict__ cval) {
+    __shared__ float w3[GNN_H];
+    if (threadIdx.x < GNN_H) w3[threadIdx.x] = bf2f(wbf[GNN_OFF_W3 + threadIdx.x]);
+    __syncthreads();
+    const int64_t p = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (p >= nnz) return;
+    const int64_t i = row[p], j = col[p];
+    float s = (i == j) ? bf2f(wbf[GNN_OFF_B3]) : 0.0f;
+#pragma unroll 8
+    for (int a = 0; a < GNN_H; ++a) s += w3[a] * bf2f(h2[i * GNN_H + a]) * bf2f(h2[j * GNN_H + a]);
+    cval[p] = s;
+}
+
+// r = C^ z - b, loss partial |r|^2
+__global__ __launch_bounds__(BLOCK) void k_cspmv(int64_t n, const int64_t* __restrict__ ptr,
+                                                 const int32_t* __restrict__ col, const float* __restrict__ cval,
+                                                 const float* __restrict__ z, const float* __restrict__ b,
+                                                 float* __restrict__ r, float* __restrict__ loss_part) {
+    __shared__ float red[BLOCK];
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    float l = 0.0f;
+    if (i < n) {
+        float s = -b[i];
+        for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p) s += cval[p] * z[col[p]];
+        r[i] = s;
+        l = s * s;
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int k = BLOCK / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+// G_p += 2 r_i z_j
+__global__ void k_gacc(int64_t nnz, const int32_t* __restrict__ row, const int32_t* __restrict__ col,
+                       const float* __restrict__ r, const float* __restrict__ z, float* __restrict__ G) {
+    const int64_t p = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (p < nnz) G[p] += 2.0f * r[row[p]] * z[col[p]];
+}
+
+// dz2_ia = [h2_ia > 0] w3_a sum_{p in row i} (G_p + G_tpos[p]) h2_{col p, a}
+__global__ __launch_bounds__(BLOCK) void k_dh2(int64_t n, const int64_t* __restrict__ ptr,
+                                               const int32_t* __restrict__ col, const int32_t* __restrict__ tpos,
+                                               const float* __restrict__ G, const uint16_t* __restrict__ h2,
+                                               const uint16_t* __restrict__ wbf, float* __restrict__ dz2) {
+    const int64_t id = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    const int64_t i = id / GNN_H;
+    const int a = (int)(id % GNN_H);
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p)
+        s += (G[p] + G[tpos[p]]) * bf2f(h2[(int64_t)col[p] * GNN_H + a]);
+    dz2[id] = bf2f(h2[id]) > 0.0f ? s * bf2f(wbf[GNN_OFF_W3 + a]) : 0.0f;
+}
+
+// partials of d/dw3_a = sum_p G_p h2_ia h2_ja and d/db3 = sum_{diag} G_p
+__global__ void k_w3grad(int64_t nnz, const int32_t* __restrict__ row, const int32_t* __restrict__ col,
+                         const float* __restrict__ G, const uint16_t* __restrict__ h2, float* __restrict__ part) {
+    const int64_t per = (nnz + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = blockIdx.x * per, p1 = min(nnz, p0 + per);
+    float* P = part + (int64_t)blockIdx.x * GNN_P;
+    for (int a = threadIdx.x; a <= GNN_H; a += blockDim.x) {
+        float s = 0.0f;
+        for (int64_t p = p0; p < p1; ++p) {
+            const int64_t i = row[p], j = col[p];
+            if (a < GNN_H) s += G[p] * bf2f(h2[i * GNN_H + a]) * bf2f(h2[j * GNN_H + a]);
+            else if (i == j) s += G[p];
+        }
+        P[a < GNN_H ? GNN_OFF_W3 + a : GNN_OFF_B3] = s;
+    }
+}
+
+// zero-correction loss |b|^2 and the samples of one solve:
+// zh = z / rms(z), bh = (t - K_m z) / (dbar rms(z)), z = V* - V_k
+__global__ void k_stencil_sample(int64_t n, const int64_t* __restrict__ kptr, const int32_t* __restrict__ kcol,
+                                 const double* __restrict__ kval, const double* __restrict__ z,
+                                 const double* __restrict__ zz, const double* __restrict__ t, double dbar,
+                                 float* __restrict__ zh, float* __restrict__ bh) {
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const double rms = sqrt(*zz / (double)n);
+    double kz = 0.0;
+    for (int64_t p = kptr[i]; p < kptr[i + 1]; ++p) kz += kval[p] * z[kcol[p]];
+    zh[i] = rms > 0.0 ? (float)(z[i] / rms) : 0.0f;
+    bh[i] = rms > 0.0 ? (float)((t[i] - kz) / (dbar * rms)) : 0.0f;
+}
+
+__global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (i < n) out[i] = a[i] - b[i];
+}
+
 void launch_gnn_adam(hipStream_t s, float* theta, float* m, float* v, const float* grad, float scale,
                      float lr, int step, uint16_t* wbf) {
     const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
     k_adam<<<(GNN_P + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(theta, m, v, grad, scale, lr, c1, c2, wbf);
+}
+
+void launch_gnn_embed(hipStream_t s, int64_t n, const float* stat, const GnnGraph& A, const uint16_t* wbf,
+                      GnnAct& a) {
+    if (n <= 0) return;
+    k_input<<<blocks_for(n * GNN_F), BLOCK, 0, s>>>(n, nullptr, nullptr, nullptr, stat, a.f);
+    forward_common(s, n, A, wbf, a, 1, nullptr, nullptr, 1.0f);
+}
+
+void launch_stencil_values(hipStream_t s, const StencilPattern& P, const uint16_t* h2, const uint16_t* wbf,
+                           float* cval) {
+    if (P.nnz > 0) k_cvals<<<blocks_for(P.nnz), BLOCK, 0, s>>>(P.nnz, P.row, P.col, h2, wbf, cval);
+}
+
+void launch_stencil_sample_loss(hipStream_t s, const StencilPattern& P, const float* cval, const float* zh,
+                                const float* bh, float* r, float* G, float* partials, double* loss) {
+    const int64_t n = P.n;
+    if (n <= 0) return;
+    const unsigned nb = blocks_for(n);
+    float* loss_part = partials + (int64_t)GNN_WG_BLOCKS * GNN_P;
+    k_cspmv<<<nb, BLOCK, 0, s>>>(n, P.ptr, P.col, cval, zh, bh, r, loss_part);
+    if (G) k_gacc<<<blocks_for(P.nnz), BLOCK, 0, s>>>(P.nnz, P.row, P.col, r, zh, G);
+    k_reduce_grad<<<1, BLOCK, 0, s>>>(0, partials, nullptr, loss_part, (int)nb, loss);
+}
+
+void launch_stencil_backward(hipStream_t s, const StencilPattern& P, const GnnGraph& At, const float* G,
+                             const uint16_t* wbf, GnnAct& a, float* partials, float* grad) {
+    const int64_t n = P.n;
+    if (n <= 0) return;
+    const unsigned gb = blocks_for(n * GNN_H);
+    const int wb = GNN_WG_BLOCKS;
+    k_dh2<<<gb, BLOCK, 0, s>>>(n, P.ptr, P.col, P.tpos, G, a.h2, wbf, a.dz2);
+    k_w3grad<<<wb, 64, 0, s>>>(P.nnz, P.row, P.col, G, a.h2, partials);
+    k_bwd_g<<<gb, BLOCK, 0, s>>>(n, a.dz2, wbf, a.g2);
+    k_bwd_hidden<<<gb, BLOCK, 0, s>>>(n, a.dz2, a.g2, At.ptr, At.col, At.val, a.h1, wbf, a.dz1);
+    k_wgrad<GNN_H, GNN_H><<<wb, 1024, 0, s>>>(n, a.dz2, a.h1, partials, GNN_OFF_W2S, GNN_OFF_B2);
+    k_wgrad<GNN_H, GNN_H><<<wb, 1024, 0, s>>>(n, a.dz2, a.m1, partials, GNN_OFF_W2N, -1);
+    k_wgrad<GNN_H, GNN_F><<<wb, 512, 0, s>>>(n, a.dz1, a.f, partials, GNN_OFF_W1S, GNN_OFF_B1);
+    k_wgrad<GNN_H, GNN_F><<<wb, 512, 0, s>>>(n, a.dz1, a.m0, partials, GNN_OFF_W1N, -1);
+    k_reduce_grad<<<(GNN_P + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(wb, partials, grad, nullptr, 0, nullptr);
+}
+
+void launch_gnn_sub(hipStream_t s, int64_t n, const double* a, const double* b, double* out) {
+    if (n > 0) k_sub<<<blocks_for(n), BLOCK, 0, s>>>(n, a, b, out);
+}
+
+void launch_stencil_sample(hipStream_t s, int64_t n, const StencilKm& K, const double* z, const double* zz,
+                           const double* t, double dbar, float* zh, float* bh) {
+    if (n > 0) k_stencil_sample<<<blocks_for(n), BLOCK, 0, s>>>(n, K.ptr, K.col, K.val, z, zz, t, dbar, zh, bh);
 }
 
 void launch_gnn_to_bf16(hipStream_t s, const float* theta, uint16_t* wbf) {

@@ -87,6 +87,12 @@ __global__ void k_scatter_in_f(int64_t n, const int64_t* __restrict__ pos, const
         dst[pos[i]] = src[i];
 }
 
+__global__ void k_gather_f(int64_t n, const int64_t* __restrict__ pos, const float* __restrict__ src,
+                           float* __restrict__ dst) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        dst[i] = src[pos[i]];
+}
+
 // dst[i] = src[pos[i]] - (shift ? *shift_num / shift_den : 0)
 __global__ void k_gather_out(int64_t n, const int64_t* __restrict__ pos,
                              const double* __restrict__ src, double* __restrict__ dst,
@@ -590,6 +596,10 @@ void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const doubl
 void launch_scatter_in_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst) {
     if (n <= 0) return;
     k_scatter_in_f<<<grid_for(n), BLOCK, 0, s>>>(n, pos, src, dst);
+}
+void launch_gather_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst) {
+    if (n <= 0) return;
+    k_gather_f<<<grid_for(n), BLOCK, 0, s>>>(n, pos, src, dst);
 }
 void launch_gather_out(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst,
                        const double* sc, int shift_slot, double shift_den) {

@@ -51,6 +51,7 @@ struct TriPlan {
 void launch_fill(hipStream_t s, int64_t n, double* x, double v);
 void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst);
 void launch_scatter_in_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst);
+void launch_gather_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst);
 void launch_gather_out(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst,
                        const double* sc, int shift_slot, double shift_den);
 void launch_dot_reduce(hipStream_t s, int64_t n, const double* a, const double* b, Reduce rd, double* out);

@@ -170,6 +170,7 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
     Csr Km = add_diag(A.Sm, A.mH, hs.gamma);
     if (Km.n < 0) { err = "missing diagonal in S_m"; return false; }
     Csr Kmp = permute(Km, tk.perm, tk.iperm);
+    hs.km_int = Kmp;
     const int nth = P.n_threads;
     if (!multifrontal(S1p, hs.p1, N - 1, nth, err)) { err = "P_1: " + err; return false; }
     if (!multifrontal(Kmp, hs.pk, -1, nth, err)) { err = "P_K: " + err; return false; }

@@ -30,6 +30,7 @@ struct HostSetup {
     // to the heart boundary / max) and the row-normalised |S_m| neighbour graph
     std::vector<double> gnn_static;
     Csr gnn_agg;
+    Csr km_int;                    // K_m = gamma M_H + S_m in internal v order
     double setup_seconds = 0.0;
 };
 

@@ -1,9 +1,10 @@
-"""GPU learned correction against the FP64 oracle network (oracle.mpnn).
+"""GPU learned corrections against the FP64 oracle network (oracle.mpnn).
 
 The device network runs in BF16 (weights and activations) with FP32
-accumulation, so forward values and gradients are compared at BF16
-tolerance after rounding the oracle's weights to BF16.  The corrected
-flexible CG must still reach the oracle's normalised solution at 1e-8."""
+accumulation, so forward values, stencil values and gradients are compared
+at BF16 tolerance after rounding the oracle's weights to BF16.  The
+corrected flexible CG (learned stencil or additive correction) must still
+reach the oracle's normalised solution at 1e-8."""
 import numpy as np
 import pytest
 
@@ -75,10 +76,31 @@ def test_gradient_matches_oracle(torch, setup):
     assert el < 3e-2 and eg < 6e-2
 
 
+def test_stencil_matches_oracle(torch, setup):
+    """C^ zh - bh, its squared norm and the weight gradient against the
+    oracle's stencil regression (static-feature embedding, f0 = 1)."""
+    B, mpnn, s, A, st, solver, theta = setup
+    solver.set_weights(theta)
+    rng = np.random.default_rng(13)
+    zh = rng.normal(size=s.NH).astype(np.float32)
+    bh = (rng.normal(size=s.NH) * 0.3).astype(np.float32)
+    r_g, loss_g, grad_g = solver.stencil_check(torch.tensor(zh, device="cuda"), torch.tensor(bh, device="cuda"))
+    f = mpnn.static_input(st)
+    C = mpnn.stencil_matrix(theta, A, f, s.Sm)
+    r_o = C @ zh.astype(np.float64) - bh
+    loss_o, grad_o = mpnn.stencil_loss_and_grad(theta, A, f, s.Sm, zh[None, :].astype(np.float64),
+                                                bh[None, :].astype(np.float64))
+    er = np.linalg.norm(r_g.cpu().numpy() - r_o) / np.linalg.norm(r_o)
+    el = abs(loss_g - loss_o) / loss_o
+    eg = np.linalg.norm(grad_g - grad_o) / np.linalg.norm(grad_o)
+    print(f"stencil residual rel err {er:.2e}, loss {el:.2e}, gradient {eg:.2e}")
+    assert er < 3e-2 and el < 3e-2 and eg < 6e-2
+
+
 def _solve_steps(torch, solver, s, state, n0, n_steps, learned):
     import paper_1711_08708_amd as B
     v, h, u = [x.clone() for x in state]
-    solver.set_precond(B.PRECOND_LEARNED if learned else B.PRECOND_PLAIN)
+    solver.set_precond(learned if learned else B.PRECOND_PLAIN)
     iters, worst, fb = [], 0.0, 0
     for n in range(n0, n0 + n_steps):
         Vn, hn = v.cpu().numpy().copy(), h.cpu().numpy().copy()
@@ -93,9 +115,8 @@ def _solve_steps(torch, solver, s, state, n0, n_steps, learned):
     return iters, worst, fb, (v, h, u)
 
 
-def test_collect_train_and_flexible_cg(torch, setup):
-    """Pairs recorded over plain steps train the network below the loss of
-    the zero correction; corrected flexible CG keeps 1e-8 parity."""
+@pytest.fixture(scope="module")
+def collected(torch, setup):
     B, mpnn, s, A, st, solver, theta = setup
     solver.set_weights(mpnn.init_params(3) * np.concatenate([np.ones(mpnn.N_PARAMS - 33), np.zeros(33)]))
     solver.set_precond(B.PRECOND_PLAIN)
@@ -103,14 +124,38 @@ def test_collect_train_and_flexible_cg(torch, setup):
     info = solver.learn_collect(v, h, u, 0, 12, max_samples=256)
     print("collected", info["samples"], "pairs over 12 steps")
     assert info["samples"] >= 24
-    ts = solver.learn_train(epochs=40, batch=4, lr=2e-3, seed=1, n_val=4)
-    print("train", ts)
+    return (v, h, u)
+
+
+def test_learned_stencil_and_flexible_cg(torch, setup, collected):
+    """The stencil regression goes below the loss of C = 0; K_m + C stays
+    SPD and is factored; flexible CG with it keeps 1e-8 parity."""
+    B, mpnn, s, A, st, solver, theta = setup
+    with pytest.raises(B.BidoError):
+        solver.set_precond(B.PRECOND_LEARNED)      # not trained yet
+    ts = solver.learn_train(kind=B.LEARN_STENCIL, epochs=30, batch=4, lr=2e-3, seed=1, n_val=4)
+    print("train stencil", ts)
+    assert ts["loss_last"] < ts["loss_first"] and ts["loss_last"] < ts["loss_zero"]
+    assert ts["spd"] == 1
+    it_p, wp, _, _ = _solve_steps(torch, solver, s, collected, 12, 6, learned=0)
+    it_l, wl, fb, _ = _solve_steps(torch, solver, s, collected, 12, 6, learned=B.PRECOND_LEARNED)
+    print("iterations plain", it_p, "stencil", it_l, "worst err", wp, wl)
+    assert wp <= 1e-8 and wl <= 1e-8
+    assert fb == 0
+
+
+def test_learned_additive_and_flexible_cg(torch, setup, collected):
+    """Additive correction: training goes below the zero correction's loss;
+    corrected flexible CG keeps 1e-8 parity."""
+    B, mpnn, s, A, st, solver, theta = setup
+    solver.set_weights(mpnn.init_params(3) * np.concatenate([np.ones(mpnn.N_PARAMS - 33), np.zeros(33)]))
+    ts = solver.learn_train(kind=B.LEARN_ADDITIVE, epochs=40, batch=4, lr=2e-3, seed=1, n_val=4)
+    print("train additive", ts)
     assert ts["loss_last"] < ts["loss_first"]
     assert ts["loss_last"] < ts["loss_zero"]
-    state = (v, h, u)
-    it_p, wp, _, _ = _solve_steps(torch, solver, s, state, 12, 6, learned=False)
-    it_l, wl, fb, _ = _solve_steps(torch, solver, s, state, 12, 6, learned=True)
-    print("iterations plain", it_p, "learned", it_l, "fallbacks", fb, "worst err", wp, wl)
+    it_p, wp, _, _ = _solve_steps(torch, solver, s, collected, 12, 6, learned=0)
+    it_l, wl, fb, _ = _solve_steps(torch, solver, s, collected, 12, 6, learned=B.PRECOND_LEARNED_ADDITIVE)
+    print("iterations plain", it_p, "additive", it_l, "fallbacks", fb, "worst err", wp, wl)
     assert wp <= 1e-8 and wl <= 1e-8
 
 
@@ -121,6 +166,6 @@ def test_fallback_keeps_parity(torch, setup):
     rng = np.random.default_rng(9)
     solver.set_weights(rng.normal(0, 30.0, mpnn.N_PARAMS))
     v, h, u = solver.state()
-    it, worst, fb, _ = _solve_steps(torch, solver, s, (v, h, u), 0, 3, learned=True)
+    it, worst, fb, _ = _solve_steps(torch, solver, s, (v, h, u), 0, 3, learned=B.PRECOND_LEARNED_ADDITIVE)
     print("iterations", it, "fallbacks", fb, "worst err", worst)
     assert worst <= 1e-8

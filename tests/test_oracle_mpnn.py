@@ -101,3 +101,44 @@ def test_boundary_distance_feature():
     assert st[centre, dcol] == st[:, dcol].max() == 1.0
     # conductivity features: first column is sigma_i xx / max diagonal value
     assert 0 < st[:, 0].max() <= 1.0
+
+
+def test_stencil_is_symmetric_and_gradient_matches_fd(graph):
+    """The learned stencil C is symmetric on the S_m pattern; the gradient of
+    the regression loss matches central differences."""
+    s, A, st = graph
+    P = s.Sm
+    f = mpnn.static_input(st)
+    rng = np.random.default_rng(6)
+    theta = mpnn.init_params(4)
+    theta[-33:] = rng.normal(0, 0.3, 33)
+    C = mpnn.stencil_matrix(theta, A, f, P).toarray()
+    np.testing.assert_allclose(C, C.T, atol=1e-14)
+    Pc = P.tocsr()
+    stored = set(zip(np.repeat(np.arange(Pc.shape[0]), np.diff(Pc.indptr)).tolist(), Pc.indices.tolist()))
+    assert set(zip(*np.nonzero(C))) <= stored     # C lives on the stored S_m pattern
+    Zh = rng.normal(size=(3, s.NH))
+    Bh = rng.normal(size=(3, s.NH)) * 0.1
+    loss, g = mpnn.stencil_loss_and_grad(theta, A, f, P, Zh, Bh)
+    for k in rng.choice(mpnn.N_PARAMS, size=50, replace=False):
+        e = np.zeros_like(theta)
+        e[k] = 1e-6
+        fd = (mpnn.stencil_loss_and_grad(theta + e, A, f, P, Zh, Bh)[0]
+              - mpnn.stencil_loss_and_grad(theta - e, A, f, P, Zh, Bh)[0]) / 2e-6
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)), (k, fd, g[k])
+
+
+def test_stencil_regression_recovers_a_known_correction():
+    """If the targets come from K_m + C0 with C0 a constant multiple of the
+    identity, the loss of the network that outputs that multiple is zero."""
+    s = bd.System(w.square2d(n=10))
+    A = mpnn.aggregation_matrix(s.Sm)
+    f = mpnn.static_input(mpnn.static_features(s.cfg, s.Sm))
+    p = {name: np.zeros(shape) for name, shape in mpnn.PARAM_SHAPES}
+    p["b3"] = np.array([0.05])
+    theta = mpnn.pack(p)
+    rng = np.random.default_rng(1)
+    Zh = rng.normal(size=(2, s.NH))
+    Bh = 0.05 * Zh                      # C^ = 0.05 I exactly
+    loss, _ = mpnn.stencil_loss_and_grad(theta, A, f, s.Sm, Zh, Bh)
+    assert loss < 1e-24
