@@ -78,6 +78,14 @@ bido_status bido_host_factor_emulate(const bido_host* h, int which, const double
 bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n_sub, int* n_levels,
                                   int64_t* n_fwd_items, int64_t* n_bwd_items);
 
+/* Dense top of that plan: the tree nodes of height >= top_h are solved as
+ * one product with the explicit inverse of their Schur complement (the
+ * Cholesky factor of Sec. 5.3 restricted to the top separators, inverted
+ * once at set-up); n_top vertices, `seconds` of host time to invert.
+ * top_h = tree height + 1 means no dense top.  The cut comes from a cost
+ * model; environment BIDO_TOP_H forces it.                                */
+bido_status bido_host_factor_top(const bido_host* h, int which, int* top_h, int64_t* n_top, double* seconds);
+
 #ifdef __cplusplus
 }
 #endif

@@ -156,6 +156,8 @@ ABI = {
     "bido_host_factor_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                              _c_i64_p, _c_i64_p]),
+    "bido_host_factor_top": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _c_i64_p,
+                                            ctypes.POINTER(ctypes.c_double)]),
     "bido_host_factor_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p,
                                               _c_double_p]),
 }
@@ -458,6 +460,12 @@ class HostSetup:
                                          ctypes.byref(nl), ctypes.byref(nf), ctypes.byref(nb)), host=True)
         return dict(hc=hc.value, n_sub=ns.value, n_levels=nl.value, n_fwd_items=nf.value,
                     n_bwd_items=nb.value)
+
+    def factor_top(self, which):
+        th, nt, sec = ctypes.c_int(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib.bido_host_factor_top(self.h, which, ctypes.byref(th), ctypes.byref(nt), ctypes.byref(sec)),
+               host=True)
+        return dict(top_h=th.value, n_top=nt.value, seconds=sec.value)
 
     def factor_apply(self, which, b):
         b = _arr(b, np.float64)

@@ -62,10 +62,11 @@ int pow2_at_least(int n, int cap) {
 
 // Kernel classes of the optional per-launch profiler.
 enum KClass { K_SPMV_LAMBDA = 0, K_PCG_UPDATE, K_COMBINE_DOT, K_P_UPDATE, K_TRI_FWD_SUB,
-              K_TRI_FWD_LVL, K_TRI_BWD_SUB, K_TRI_BWD_LVL, K_SPMV_CSR, K_IONIC, K_GNN, K_MISC, K_NCLASS };
+              K_TRI_FWD_LVL, K_TRI_BWD_SUB, K_TRI_BWD_LVL, K_TRI_TOP, K_SPMV_CSR, K_IONIC, K_GNN, K_MISC,
+              K_NCLASS };
 const char* const kclass_name[K_NCLASS] = {"spmv_lambda", "pcg_update", "combine_dot", "p_update",
                                            "tri_fwd_sub", "tri_fwd_lvl", "tri_bwd_sub", "tri_bwd_lvl",
-                                           "spmv_csr", "ionic_rhs", "gnn_infer", "misc"};
+                                           "tri_top", "spmv_csr", "ionic_rhs", "gnn_infer", "misc"};
 
 // Per-launch HIP-event timing with the algorithmic bytes of each launch.
 struct Profiler {
@@ -100,6 +101,11 @@ struct FactorDev {
     double* ytmp = nullptr;
     TriItem* items = nullptr;
     BwdItem* bitems = nullptr;
+    double* top_inv64 = nullptr;    // dense top S_top^-1 (n_top x n_top)
+    float* top_inv32 = nullptr;
+    double top_bytes64 = 0, top_bytes32 = 0;
+    int top_h = 0;
+    double top_seconds = 0;
     TriPlan plan;
     std::vector<TriTopLevel> top;                   // heights hc+1 .. height
     std::vector<double> fwd_bytes64, bwd_bytes64;   // algorithmic bytes per height (FP64 panel)
@@ -116,6 +122,9 @@ struct FactorDev {
         hipFree(ea); hipFree(bidx);
         hipFree(upd); hipFree(ytmp); hipFree(items); hipFree(bitems);
         hipFree(plan.sub_nodes); hipFree(plan.sub_hoff); hipFree(plan.scratch); hipFree(plan.counters);
+        hipFree(top_inv64); hipFree(top_inv32); top_inv64 = nullptr; top_inv32 = nullptr;
+        hipFree((void*)plan.top_pos); hipFree((void*)plan.top_gptr); hipFree((void*)plan.top_gsrc);
+        hipFree(plan.top_w);
         nodes = nullptr; panel64 = nullptr; panel32 = nullptr; panel64_cm = nullptr; panel32_cm = nullptr;
         ea = nullptr; bidx = nullptr;
         upd = nullptr; ytmp = nullptr; items = nullptr; bitems = nullptr;
@@ -138,10 +147,10 @@ struct CsrHostView {
     }
 };
 
-bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd) {
+bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_threads = 0) {
     FactorPlan p;
     std::string err;
-    if (!build_plan(f, p, err)) return fail(BIDO_ERR_ARG, err);
+    if (!build_plan(f, p, err, n_threads)) return fail(BIDO_ERR_ARG, err);
     fd.n = p.n;
     fd.ground = p.ground;
     fd.height = p.height;
@@ -172,6 +181,25 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd) {
     HIP_OK(hipMemset(fd.plan.counters, 0, std::max(p.n_tiles, 1) * sizeof(unsigned)));
     HIP_OK(hipMalloc((void**)&fd.upd, std::max<int64_t>(p.upd_size, 1) * sizeof(double)));
     HIP_OK(hipMalloc((void**)&fd.ytmp, std::max<int64_t>(p.n, 1) * sizeof(double)));
+    fd.top_h = p.top_h;
+    fd.top_seconds = p.top_seconds;
+    fd.plan.n_top = p.n_top;
+    if (p.n_top > 0) {
+        int64_t* pos = nullptr; int32_t* gptr = nullptr; int64_t* gsrc = nullptr;
+        HIP_OK(upload(&pos, p.top_pos.data(), p.top_pos.size()));
+        HIP_OK(upload(&gptr, p.top_gptr.data(), p.top_gptr.size()));
+        HIP_OK(upload(&gsrc, p.top_gsrc.data(), p.top_gsrc.size()));
+        fd.plan.top_pos = pos; fd.plan.top_gptr = gptr; fd.plan.top_gsrc = gsrc;
+        HIP_OK(hipMalloc((void**)&fd.plan.top_w, p.n_top * sizeof(double)));
+        HIP_OK(upload(&fd.top_inv64, p.top_inv.data(), p.top_inv.size()));
+        if (want32) {
+            std::vector<float> i32(p.top_inv.begin(), p.top_inv.end());
+            HIP_OK(upload(&fd.top_inv32, i32.data(), i32.size()));
+        }
+        const double nt = (double)p.n_top, vec = 8.0 * (3 * nt) + 16.0 * (double)p.top_gsrc.size();
+        fd.top_bytes64 = 8.0 * nt * nt + vec;
+        fd.top_bytes32 = 4.0 * nt * nt + vec;
+    }
     fd.top.clear();
     for (const auto& sp : p.spans) {
         TriTopLevel L;
@@ -305,6 +333,10 @@ double csr_bytes(const CsrDev& a, int64_t ncols_read) {
     return 12.0 * a.nnz + 8.0 * (a.n + 1) + 8.0 * ncols_read + 8.0 * a.n;
 }
 
+template <typename T> const T* top_inv(const FactorDev& f);
+template <> const double* top_inv<double>(const FactorDev& f) { return f.top_inv64; }
+template <> const float* top_inv<float>(const FactorDev& f) { return f.top_inv32; }
+
 template <typename T>
 void tri_solve(bido_ctx* c, const FactorDev& f, const T* panel, const T* panel_cm, const double* in,
                double* out) {
@@ -319,6 +351,8 @@ void tri_solve(bido_ctx* c, const FactorDev& f, const T* panel, const T* panel_c
              launch_tri_fwd_lvl<T>(s, f.top[k], f.plan, f.nodes, panel_cm, f.ea, in, f.ytmp, f.upd,
                                    f.ground));
     }
+    PROF(c, K_TRI_TOP, f32 ? f.top_bytes32 : f.top_bytes64,
+         launch_tri_top<T>(s, f.plan, top_inv<T>(f), in, f.upd, f.ground, out));
     for (size_t k = f.top.size(); k-- > 0;) {
         const int h = hc + 1 + (int)k;
         PROF(c, K_TRI_BWD_LVL, f32 ? f.bwd_bytes32[h] : f.bwd_bytes64[h],
@@ -703,8 +737,8 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     if ((e = CsrHostView::up(hs.lam, c->lam))) return e;
     if ((e = CsrHostView::up(hs.avu, c->avu))) return e;
     if ((e = CsrHostView::up(hs.auv, c->auv))) return e;
-    if ((e = build_factor_dev(hs.p1, true, c->p1))) return e;
-    if ((e = build_factor_dev(hs.pk, true, c->pk))) return e;
+    if ((e = build_factor_dev(hs.p1, true, c->p1, hs.params.n_threads))) return e;
+    if ((e = build_factor_dev(hs.pk, true, c->pk, hs.params.n_threads))) return e;
     const int64_t n2 = c->n2;
     for (double** b : {&c->x, &c->r, &c->z, &c->p, &c->q, &c->Y, &c->r_old})
         HIP_OK(hipMalloc((void**)b, n2 * sizeof(double)));
@@ -761,7 +795,7 @@ bido_status bido_get_info(const bido_ctx* c, bido_info* info) {
     info->launches_per_sweep_p1 = (int)c->p1.top.size() + (c->p1.plan.n_sub > 0);
     info->launches_per_sweep_pk = (int)c->pk.top.size() + (c->pk.plan.n_sub > 0);
     info->lowrank_blocks = c->hs.p1.n_lowrank() + c->hs.pk.n_lowrank();
-    info->setup_seconds = c->hs.setup_seconds;
+    info->setup_seconds = c->hs.setup_seconds + c->p1.top_seconds + c->pk.top_seconds;
     info->ground_index = (int)c->p1.ground;
     return BIDO_OK;
 }
@@ -1029,7 +1063,7 @@ static bido_status train_stencil(bido_ctx* c, int epochs, int batch, float lr, u
     const bool spd = multifrontal(Kt, f, -1, c->params.n_threads, err);
     if (spd) {
         c->pk_learned.release();
-        bido_status e = build_factor_dev(f, true, c->pk_learned);
+        bido_status e = build_factor_dev(f, true, c->pk_learned, c->params.n_threads);
         if (e) return e;
         for (FactorDev* fd : {&c->pk_learned}) {
             HIP_OK(hipMemset(fd->ytmp, 0xFF, std::max<int64_t>(fd->n, 1) * sizeof(double)));

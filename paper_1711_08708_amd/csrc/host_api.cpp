@@ -125,7 +125,7 @@ bido_status bido_host_factor_emulate(const bido_host* h, int which, const double
     if (!f) return hfail(BIDO_ERR_ARG, "unknown factor");
     bido::FactorPlan p;
     std::string err;
-    if (!bido::build_plan(*f, p, err)) return hfail(BIDO_ERR_ARG, err);
+    if (!bido::build_plan(*f, p, err, h->hs.params.n_threads)) return hfail(BIDO_ERR_ARG, err);
     try {
         bido::emulate_plan(p, b, x);
     } catch (const std::exception& e) {
@@ -147,6 +147,19 @@ bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n
     if (n_levels) *n_levels = (int)p.spans.size();
     if (n_fwd_items) *n_fwd_items = (int64_t)p.fwd_items.size();
     if (n_bwd_items) *n_bwd_items = (int64_t)p.bwd_items.size();
+    return BIDO_OK;
+}
+
+bido_status bido_host_factor_top(const bido_host* h, int which, int* top_h, int64_t* n_top, double* seconds) {
+    if (!h) return hfail(BIDO_ERR_ARG, "null argument");
+    const bido::Factor* f = which == BIDO_FACTOR_P1 ? &h->hs.p1 : which == BIDO_FACTOR_PK ? &h->hs.pk : nullptr;
+    if (!f) return hfail(BIDO_ERR_ARG, "unknown factor");
+    bido::FactorPlan p;
+    std::string err;
+    if (!bido::build_plan(*f, p, err, h->hs.params.n_threads)) return hfail(BIDO_ERR_ARG, err);
+    if (top_h) *top_h = p.top_h;
+    if (n_top) *n_top = p.n_top;
+    if (seconds) *seconds = p.top_seconds;
     return BIDO_OK;
 }
 

@@ -575,6 +575,44 @@ __global__ __launch_bounds__(BLOCK) void k_tri_bwd_lvl(const TriNode* __restrict
     if (threadIdx.x == 0) counters[it.tile] = 0u;
 }
 
+// Dense top: w_top[k] = b[pos[k]] - sum of the bottom roots' updates at k.
+__global__ void k_top_gather(int64_t n, const int64_t* __restrict__ pos, const int32_t* __restrict__ gptr,
+                             const int64_t* __restrict__ gsrc, const double* __restrict__ b,
+                             const double* __restrict__ upd, int64_t ground, double* __restrict__ w) {
+    const int64_t k = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (k >= n) return;
+    const int64_t g = pos[k];
+    double v = b[g];
+    for (int32_t q = gptr[k]; q < gptr[k + 1]; ++q) v -= upd[gsrc[q]];
+    w[k] = g == ground ? 0.0 : v;
+}
+
+// x[pos[i]] = sum_j inv[i][j] w[j]: one wave per row, w staged in LDS,
+// eight independent loads in flight per lane.
+constexpr int TOP_ROWS = BLOCK / WAVE;
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_top_gemv(int64_t n, const T* __restrict__ inv,
+                                                    const double* __restrict__ w,
+                                                    const int64_t* __restrict__ pos, double* __restrict__ x) {
+    extern __shared__ double ws[];
+    for (int64_t j = threadIdx.x; j < n; j += BLOCK) ws[j] = w[j];
+    __syncthreads();
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int64_t row = blockIdx.x * (int64_t)TOP_ROWS + wave;
+    if (row >= n) return;
+    const T* a = inv + row * n;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t j = lane;
+    for (; j + 7 * WAVE < n; j += 8 * WAVE) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += (double)a[j + k * WAVE] * ws[j + k * WAVE];
+    }
+    for (int k = 0; j < n; j += WAVE, ++k) acc[k] += (double)a[j] * ws[j];
+    double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    for (int m = WAVE / 2; m > 0; m >>= 1) s += __shfl_xor(s, m, WAVE);
+    if (lane == 0) x[pos[row]] = s;
+}
+
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
@@ -666,6 +704,17 @@ void launch_p_update(hipStream_t s, int64_t n, const double* z, double* p, const
 }
 
 template <typename T>
+void launch_tri_top(hipStream_t s, const TriPlan& P, const T* inv, const double* b, const double* upd,
+                    int64_t ground, double* x) {
+    const int64_t n = P.n_top;
+    if (n <= 0) return;
+    k_top_gather<<<(unsigned)((n + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(n, P.top_pos, P.top_gptr, P.top_gsrc, b,
+                                                                        upd, ground, P.top_w);
+    k_top_gemv<T><<<(unsigned)((n + TOP_ROWS - 1) / TOP_ROWS), BLOCK, n * sizeof(double), s>>>(
+        n, inv, P.top_w, P.top_pos, x);
+}
+
+template <typename T>
 void launch_tri_fwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel_cm,
                         const Ea* ea, const double* b, double* y, double* upd, int64_t ground) {
     if (P.n_sub == 0) return;
@@ -701,7 +750,9 @@ void launch_tri_bwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, c
     template void launch_tri_fwd_lvl<T>(hipStream_t, const TriTopLevel&, const TriPlan&, const TriNode*, \
                                         const T*, const Ea*, const double*, double*, double*, int64_t); \
     template void launch_tri_bwd_lvl<T>(hipStream_t, const TriTopLevel&, const TriPlan&, const TriNode*, \
-                                        const T*, const int64_t*, const double*, double*);
+                                        const T*, const int64_t*, const double*, double*);               \
+    template void launch_tri_top<T>(hipStream_t, const TriPlan&, const T*, const double*, const double*, \
+                                    int64_t, double*);
 BIDO_INST(double)
 BIDO_INST(float)
 #undef BIDO_INST

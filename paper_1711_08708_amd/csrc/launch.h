@@ -46,6 +46,12 @@ struct TriPlan {
     int sub_maxw = 0;             // max nI below the cut
     double* scratch = nullptr;    // backward partial sums
     unsigned* counters = nullptr; // backward tile counters (zero between launches)
+    // dense top (n_top = 0: none): x[top_pos] = S_top^-1 w_top
+    int64_t n_top = 0;
+    const int64_t* top_pos = nullptr;
+    const int32_t* top_gptr = nullptr;
+    const int64_t* top_gsrc = nullptr;
+    double* top_w = nullptr;
 };
 
 void launch_fill(hipStream_t s, int64_t n, double* x, double v);
@@ -64,6 +70,11 @@ void launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode, con
 void launch_spmv_csr(hipStream_t s, const CsrDev& A, int group, const double* x, const double* b,
                      double* y);
 void launch_copy_scalar(hipStream_t s, double* sc, int dst, int src);
+// dense top of a sweep: gather w_top from b and the bottom roots' updates,
+// then x[top_pos] = S_top^-1 w_top (inv: n_top x n_top row-major)
+template <typename T>
+void launch_tri_top(hipStream_t s, const TriPlan& P, const T* inv, const double* b, const double* upd,
+                    int64_t ground, double* x);
 void launch_pcg_update(hipStream_t s, int64_t n, double* x, double* r, double* r_old, const double* p,
                        const double* q, Reduce rd, double* sc);
 void launch_combine_dot(hipStream_t s, int64_t n1, int64_t n, double* z, const double* a, const double* b,

@@ -1,8 +1,12 @@
 // Execution plan of the hierarchical-Cholesky sweeps and its CPU emulation.
 #include "plan.h"
 
+#include <omp.h>
+
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <stdexcept>
 
 namespace bido {
@@ -18,9 +22,131 @@ int64_t panel_row_off(int64_t r, int64_t nI) {
     return r < nI ? r * (r + 1) / 2 : nI * (nI + 1) / 2 + (r - nI) * nI;
 }
 
+int env_limit(const char* name, int def, int lo, int hi) {
+    const char* e = std::getenv(name);
+    if (!e || !*e) return def;
+    return std::max(lo, std::min(hi, std::atoi(e)));
+}
+
+// Row-major dense (nI+nB) x nI view of a panel (rebuilt from its blocks when
+// the panel is held in compressed form).
+const double* dense_panel(const Front& fr, std::vector<double>& buf) {
+    if (!fr.compressed) return fr.P.data();
+    const int nI = fr.nI;
+    buf.assign((size_t)(nI + fr.nB) * nI, 0.0);
+    for (const auto& b : fr.dense)
+        for (int r = 0; r < b.nr; ++r)
+            for (int c = 0; c < (b.lower_tri ? r + 1 : b.nc); ++c)
+                buf[(size_t)(b.r0 + r) * nI + b.c0 + c] = b.D[(size_t)r * b.nc + c];
+    for (const auto& l : fr.lowrank)
+        for (int r = 0; r < l.nr; ++r)
+            for (int c = 0; c < l.nc; ++c) {
+                double s = 0.0;
+                for (int k = 0; k < l.rank; ++k) s += l.U[(size_t)r * l.rank + k] * l.V[(size_t)c * l.rank + k];
+                buf[(size_t)(l.r0 + r) * nI + l.c0 + c] = s;
+            }
+    return buf.data();
+}
+
+// S_top^-1 column by column: the sweeps of the top fronts applied to unit
+// vectors e_j (top numbering), in blocks of TB columns.  The forward sweep of
+// column j only reaches the fronts whose top subtree holds j (post-order
+// numbering makes that a contiguous range per front); the backward sweep
+// reaches every top front.
+void top_inverse(const Factor& f, const std::vector<int>& top, const std::vector<int32_t>& tmap,
+                 int64_t ntop, std::vector<double>& inv, int n_threads) {
+    constexpr int TB = 32;
+    const int nt = (int)top.size();
+    std::vector<std::vector<double>> dbuf(nt);
+    std::vector<const double*> P(nt);
+    std::vector<int64_t> sb(nt), eb(nt);          // top-subtree range [sb, eb) per front
+    std::vector<int> local(f.fronts.size(), -1);
+    for (int q = 0; q < nt; ++q) {
+        const Front& fr = f.fronts[top[q]];
+        P[q] = dense_panel(fr, dbuf[q]);
+        local[top[q]] = q;
+        eb[q] = tmap[fr.off] + fr.nI;
+        sb[q] = tmap[fr.off];
+        for (int c = 0; c < 2; ++c) {
+            const int ch = f.tree.nodes[top[q]].child[c];
+            if (ch >= 0 && local[ch] >= 0) sb[q] = std::min(sb[q], sb[local[ch]]);
+        }
+    }
+    inv.assign((size_t)ntop * ntop, 0.0);
+    const int64_t nblk = (ntop + TB - 1) / TB;
+#pragma omp parallel num_threads(n_threads > 0 ? n_threads : omp_get_max_threads())
+    {
+        std::vector<double> acc((size_t)ntop * TB), Y((size_t)ntop * TB), X((size_t)ntop * TB), W, O;
+#pragma omp for schedule(dynamic)
+        for (int64_t blk = 0; blk < nblk; ++blk) {
+            const int64_t j0 = blk * TB, j1 = std::min<int64_t>(ntop, j0 + TB);
+            const int m = (int)(j1 - j0);
+            std::fill(acc.begin(), acc.end(), 0.0);
+            std::fill(Y.begin(), Y.end(), 0.0);
+            for (int q = 0; q < nt; ++q) {
+                if (j1 <= sb[q] || j0 >= eb[q]) continue;   // no column of the block reaches it
+                const Front& fr = f.fronts[top[q]];
+                const int nI = fr.nI, nF = nI + fr.nB;
+                W.assign((size_t)nI * TB, 0.0);
+                for (int i = 0; i < nI; ++i) {
+                    const int64_t g = fr.off + i, ti = tmap[g];
+                    if (g == f.ground) continue;
+                    for (int k = 0; k < m; ++k)
+                        W[(size_t)i * TB + k] = (ti == j0 + k ? 1.0 : 0.0) - acc[(size_t)ti * TB + k];
+                }
+                O.assign((size_t)nF * TB, 0.0);
+                for (int r = 0; r < nF; ++r) {
+                    double* o = &O[(size_t)r * TB];
+                    const double* pr = P[q] + (size_t)r * nI;
+                    const int len = r < nI ? r + 1 : nI;
+                    for (int c = 0; c < len; ++c) {
+                        const double a = pr[c];
+                        const double* w = &W[(size_t)c * TB];
+                        for (int k = 0; k < TB; ++k) o[k] += a * w[k];
+                    }
+                }
+                for (int i = 0; i < nI; ++i)
+                    std::copy(&O[(size_t)i * TB], &O[(size_t)i * TB] + TB, &Y[(size_t)tmap[fr.off + i] * TB]);
+                for (int r = 0; r < fr.nB; ++r) {
+                    double* a = &acc[(size_t)tmap[fr.B[r]] * TB];
+                    const double* o = &O[(size_t)(nI + r) * TB];
+                    for (int k = 0; k < TB; ++k) a[k] += o[k];
+                }
+            }
+            for (int q = nt - 1; q >= 0; --q) {
+                const Front& fr = f.fronts[top[q]];
+                const int nI = fr.nI, nF = nI + fr.nB;
+                W.assign((size_t)nF * TB, 0.0);
+                for (int i = 0; i < nI; ++i)
+                    std::copy(&Y[(size_t)tmap[fr.off + i] * TB], &Y[(size_t)tmap[fr.off + i] * TB] + TB,
+                              &W[(size_t)i * TB]);
+                for (int r = 0; r < fr.nB; ++r) {
+                    const double* xb = &X[(size_t)tmap[fr.B[r]] * TB];
+                    for (int k = 0; k < TB; ++k) W[(size_t)(nI + r) * TB + k] = -xb[k];
+                }
+                O.assign((size_t)nI * TB, 0.0);
+                for (int r = 0; r < nF; ++r) {
+                    const double* pr = P[q] + (size_t)r * nI;
+                    const double* z = &W[(size_t)r * TB];
+                    const int len = r < nI ? r + 1 : nI;
+                    for (int c = 0; c < len; ++c) {
+                        const double a = pr[c];
+                        double* o = &O[(size_t)c * TB];
+                        for (int k = 0; k < TB; ++k) o[k] += a * z[k];
+                    }
+                }
+                for (int i = 0; i < nI; ++i)
+                    std::copy(&O[(size_t)i * TB], &O[(size_t)i * TB] + TB, &X[(size_t)tmap[fr.off + i] * TB]);
+            }
+            for (int64_t i = 0; i < ntop; ++i)
+                for (int k = 0; k < m; ++k) inv[(size_t)i * ntop + j0 + k] = X[(size_t)i * TB + k];
+        }
+    }
+}
+
 }  // namespace
 
-bool build_plan(const Factor& f, FactorPlan& p, std::string& err) {
+bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads) {
     const NdTree& t = f.tree;
     const int nn = (int)t.nodes.size();
     p = FactorPlan();
@@ -157,11 +283,82 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err) {
         p.sub_maxw = maxw_le[hc];
     }
 
+    // ---- dense top: cut height by a cost model -----------------------------------
+    // A level of the sweeps costs about one forward and one backward launch
+    // of dependent memory latency (or its panel bytes at level-phase
+    // bandwidth when larger); the dense top costs two launches plus n_top^2
+    // FP64 entries at streaming bandwidth.  Environment BIDO_TOP_H forces the
+    // cut (a value above the tree height switches the dense top off).
+    {
+        constexpr double T_FWD = 10e-6, T_BWD = 25e-6, BW_LVL = 2.0e12, T_TOP = 10e-6, BW_TOP = 4.5e12;
+        int best = H + 1;
+        double best_cost = 0.0, saved = 0.0;
+        int64_t cum = 0;
+        for (int h = H; h > hc; --h) {
+            double pb = 0.0;
+            for (int id : by_h[h]) {
+                cum += f.fronts[id].nI;
+                pb += 8.0 * ((double)f.fronts[id].nI * (f.fronts[id].nI + 1) / 2 +
+                             (double)f.fronts[id].nB * f.fronts[id].nI);
+            }
+            if (cum > PLAN_TOP_MAX) break;
+            saved += std::max(T_FWD, pb / BW_LVL) + std::max(T_BWD, pb / BW_LVL);
+            const double cost = T_TOP + 8.0 * (double)cum * (double)cum / BW_TOP - saved;
+            if (cost < best_cost) { best_cost = cost; best = h; }
+        }
+        const char* e = std::getenv("BIDO_TOP_H");
+        if (e && *e) best = std::max(hc + 1, std::min(H + 1, std::atoi(e)));
+        p.top_h = best;
+    }
+    const int top_h = p.top_h;
+    if (top_h <= H) {
+        auto t0 = std::chrono::steady_clock::now();
+        std::vector<int> top;
+        for (int id = 0; id < nn; ++id)
+            if (t.nodes[id].height >= top_h) top.push_back(id);     // post-order
+        std::vector<int32_t> tmap(f.n, -1);
+        int64_t nt = 0;
+        for (int id : top)
+            for (int i = 0; i < f.fronts[id].nI; ++i) {
+                tmap[f.fronts[id].off + i] = (int32_t)nt++;
+                p.top_pos.push_back(f.fronts[id].off + i);
+            }
+        if (nt > PLAN_TOP_MAX) { err = "dense top too large"; return false; }
+        p.n_top = nt;
+        // bottom roots: the update vector of each one covers its boundary,
+        // which lies in the top
+        std::vector<std::vector<int64_t>> lists(nt);
+        for (int id = 0; id < nn; ++id) {
+            const NdNode& nd = t.nodes[id];
+            if (nd.height >= top_h || nd.parent < 0 || t.nodes[nd.parent].height < top_h) continue;
+            const Front& fr = f.fronts[id];
+            for (int r = 0; r < fr.nB; ++r) {
+                const int32_t ti = tmap[fr.B[r]];
+                if (ti < 0) { err = "boundary of a bottom root outside the top"; return false; }
+                lists[ti].push_back(p.nodes[id].upd + r);
+            }
+        }
+        p.top_gptr.assign(nt + 1, 0);
+        for (int64_t k = 0; k < nt; ++k) {
+            p.top_gptr[k + 1] = p.top_gptr[k] + (int32_t)lists[k].size();
+            for (int64_t src : lists[k]) p.top_gsrc.push_back(src);
+        }
+        if (p.top_gsrc.empty()) p.top_gsrc.push_back(0);
+        top_inverse(f, top, tmap, nt, p.top_inv, n_threads);
+        p.top_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
     // ---- level phases above the cut ------------------------------------------
+    // Work-item limits: columns per forward item and rows per backward item.
+    // Splitting a tile over several items exposes more workgroups but needs a
+    // cross-workgroup combine (device-scope fence), so the limits are tunable
+    // (environment BIDO_FWD_COLS, BIDO_BWD_MAXR) within the LDS staging bound.
+    const int fwd_cols = env_limit("BIDO_FWD_COLS", PLAN_FWD_COLS, 32, PLAN_LDS_DOUBLES);
+    const int bwd_maxr = env_limit("BIDO_BWD_MAXR", PLAN_BWD_MAXR, 64, PLAN_LDS_DOUBLES);
     std::vector<std::pair<size_t, size_t>> fspan, bspan;
     struct LdsSz { size_t f, b; };
     std::vector<LdsSz> lds;
-    for (int h = hc + 1; h <= H; ++h) {
+    for (int h = hc + 1; h < top_h; ++h) {
         const size_t f0 = p.fwd_items.size();
         size_t ldsf = 0;
         for (int id : by_h[h]) {
@@ -172,15 +369,15 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err) {
                 const int nrows = std::min(PLAN_FWD_ROWS, nF - r0);
                 // own rows only need the columns c <= r
                 const int cmax = r0 < nI ? std::min(nI, r0 + nrows) : nI;
-                const int nparts = (cmax + PLAN_FWD_COLS - 1) / PLAN_FWD_COLS;
+                const int nparts = (cmax + fwd_cols - 1) / fwd_cols;
                 const int64_t part0 = p.scratch_size;
                 for (int k = 0; k < nparts; ++k) {
                     TriItem it{};
                     it.node = id;
                     it.r0 = r0;
                     it.nrows = nrows;
-                    it.cs = k * PLAN_FWD_COLS;
-                    it.ce = std::min(cmax, it.cs + PLAN_FWD_COLS);
+                    it.cs = k * fwd_cols;
+                    it.ce = std::min(cmax, it.cs + fwd_cols);
                     it.nparts = nparts;
                     it.tile = p.n_tiles;
                     it.part = part0 + (int64_t)k * PLAN_FWD_ROWS;
@@ -195,7 +392,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err) {
         fspan.push_back({f0, p.fwd_items.size() - f0});
         lds.push_back({ldsf, 0});
     }
-    for (int h = hc + 1; h <= H; ++h) {
+    for (int h = hc + 1; h < top_h; ++h) {
         const size_t b0 = p.bwd_items.size();
         size_t ldsb = 0;
         for (int id : by_h[h]) {
@@ -203,7 +400,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err) {
             const int nI = fr.nI, nF = fr.nI + fr.nB;
             if (nI == 0) continue;
             const int W = pow2_at_least(std::min(nI, 64), 64);
-            const int RB = std::min(PLAN_BWD_MAXR, std::max(64, 8192 / W));
+            const int RB = bwd_maxr == PLAN_BWD_MAXR ? std::min(PLAN_BWD_MAXR, std::max(64, 8192 / W)) : bwd_maxr;
             for (int c0 = 0; c0 < nI; c0 += W) {
                 const int nparts = (nF - c0 + RB - 1) / RB;
                 const int64_t part0 = p.scratch_size;
@@ -385,6 +582,23 @@ struct Emu {
         }
     }
 
+    // dense top: w_top = b - updates of the bottom roots, x_top = S_top^-1 w_top
+    void top() {
+        const int64_t nt = p.n_top;
+        if (nt == 0) return;
+        std::vector<double> w(nt);
+        for (int64_t k = 0; k < nt; ++k) {
+            double v = b[p.top_pos.at(k)];
+            for (int32_t q = p.top_gptr.at(k); q < p.top_gptr.at(k + 1); ++q) v -= upd.at(p.top_gsrc.at(q));
+            w[k] = p.top_pos[k] == p.ground ? 0.0 : v;
+        }
+        for (int64_t i = 0; i < nt; ++i) {
+            double s = 0.0;
+            for (int64_t j = 0; j < nt; ++j) s += p.top_inv.at((size_t)i * nt + j) * w[j];
+            x.at(p.top_pos[i]) = s;
+        }
+    }
+
     void bwd_lvl(const FactorPlan::Span& sp) {
         for (size_t q = sp.b0; q < sp.b0 + sp.nb; ++q) {
             const BwdItem it = p.bwd_items.at(q);
@@ -417,6 +631,7 @@ void emulate_plan(const FactorPlan& p, const double* b, double* x) {
     Emu e(p, b);
     e.fwd_sub();
     for (const auto& sp : p.spans) e.fwd_lvl(sp);
+    e.top();
     for (size_t k = p.spans.size(); k-- > 0;) e.bwd_lvl(p.spans[k]);
     e.bwd_sub();
     for (int64_t i = 0; i < p.n; ++i) x[i] = e.x[i];

@@ -30,6 +30,15 @@ struct FactorPlan {
     std::vector<Span> spans;
     int64_t scratch_size = 0;           // partial sums of split tiles
     int n_tiles = 0;                    // completion counters (forward + backward)
+    // dense top: the nodes of height >= top_h are replaced by x_top = S_top^-1 w_top,
+    // S_top the Schur complement of their vertices (top_h = height + 1: none)
+    int top_h = 0;
+    int64_t n_top = 0;
+    std::vector<int64_t> top_pos;       // top index -> vertex (tree order)
+    std::vector<int32_t> top_gptr;      // top index -> [gptr, gptr+1) in top_gsrc
+    std::vector<int64_t> top_gsrc;      // update-workspace entries of the bottom roots
+    std::vector<double> top_inv;        // S_top^-1, n_top x n_top row-major
+    double top_seconds = 0.0;           // host time spent on S_top^-1
     // algorithmic bytes per height (panel at 8 or 4 bytes per entry)
     std::vector<double> fwd_bytes64, bwd_bytes64, fwd_bytes32, bwd_bytes32;
     double sub_fwd_bytes64 = 0, sub_bwd_bytes64 = 0, sub_fwd_bytes32 = 0, sub_bwd_bytes32 = 0;
@@ -43,8 +52,11 @@ constexpr int PLAN_LDS_MAXW = 1 << 20; // (no own-size limit in the level phases
 constexpr int PLAN_FWD_ROWS = 64;      // forward row tile (one row per lane)
 constexpr int PLAN_FWD_COLS = 128;     // forward column chunk per work item (4 waves)
 constexpr int PLAN_BWD_MAXR = 512;     // backward rows per work item (LDS staging)
+constexpr int PLAN_LDS_DOUBLES = 4096; // bound of the LDS staging per level item
+constexpr int PLAN_TOP_MAX = 6144;     // max n_top (w_top staged in LDS, FP64)
 
-bool build_plan(const Factor& f, FactorPlan& p, std::string& err);
+// n_threads: host threads for S_top^-1 (<= 0: OpenMP default).
+bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads = 0);
 
 // CPU emulation of the sweep kernels over the plan: x = (L L^T)^-1 b.
 void emulate_plan(const FactorPlan& p, const double* b, double* x);

@@ -133,6 +133,34 @@ def test_bad_inputs_are_rejected():
         B.HostSetup(no_heart)
 
 
+@pytest.mark.parametrize("mk", [lambda: w.thorax2d(n_target=3000, seed=2), lambda: w.slab3d(n=10),
+                                lambda: w.square2d(n=48)], ids=["thorax3000", "slab10", "square48"])
+def test_dense_top_at_every_cut(mk, monkeypatch):
+    """Forcing the dense top at every possible cut height (down to the
+    lowest level above the subtree phase) leaves the sweep result unchanged:
+    S_top^-1 is the inverse of the Schur complement of the top vertices."""
+    import paper_1711_08708_amd as B
+    cfg = mk()
+    hs = B.HostSetup(cfg, eps_h=0.0)
+    for which, idx in ((B.FACTOR_P1, B.IDX_UPOS), (B.FACTOR_PK, B.IDX_VPOS)):
+        n = len(hs.index(idx))
+        b = np.random.default_rng(3 + which).normal(size=n)
+        ref = hs.factor_apply(which, b)
+        hc = hs.factor_plan(which)["hc"]
+        H = hs.factor_stats(which)["height"]
+        cuts = []
+        for th in range(hc + 1, H + 2):
+            monkeypatch.setenv("BIDO_TOP_H", str(th))
+            top = hs.factor_top(which)
+            assert top["top_h"] == th
+            emu = hs.factor_emulate(which, b)
+            assert np.isfinite(emu).all()
+            assert np.abs(emu - ref).max() <= 1e-12 * np.abs(ref).max(), (which, th)
+            cuts.append((th, top["n_top"]))
+        print(which, "hc", hc, "height", H, "cuts (top_h, n_top)", cuts)
+        assert cuts[-1][1] == 0 and (len(cuts) == 1 or cuts[0][1] > 0)
+
+
 @pytest.mark.parametrize("mk", [lambda: w.square2d(n=48), lambda: w.slab3d(n=12),
                                 lambda: w.thorax2d(n_target=40000, seed=12)])
 def test_device_plan_emulation_matches_host_factor(mk):
