@@ -280,8 +280,9 @@ struct bido_ctx {
     FactorDev p1, pk;
     double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *Y = nullptr;
     double *tA = nullptr, *tB = nullptr, *tC = nullptr, *tD = nullptr, *r_old = nullptr;
-    double* sc = nullptr;
+    double* sc = nullptr;        // scalar slots, then the PCG partial regions
     double* sc_host = nullptr;   // pinned
+    unsigned nb_rz = 0;          // partials of r.z written by the latest apply
     Reduce rd;
     int64_t *u_pos = nullptr, *v_pos = nullptr;
     double *m_int = nullptr, *mh_loc = nullptr, *stim_loc = nullptr;
@@ -433,13 +434,20 @@ void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old,
     inner_solve(c, c->p1, c->tC, c->tD);                             // P1^-1 Pi^T S_i Z2
     debug_check(c, "W", c->tD, N);
     PROF(c, K_COMBINE_DOT, 8.0 * (3 * N + c->NH + c->n2 * (r_old ? 2 : 1)),
-         launch_combine_dot(s, N, c->n2, z, c->tA, c->tD, r, r_old, c->rd, c->sc));
+         c->nb_rz = launch_combine_dot(s, N, c->n2, z, c->tA, c->tD, r, r_old, c->sc));
 }
 
-bido_status read_scalars(bido_ctx* c) {
-    HIP_OK(hipMemcpyAsync(c->sc_host, c->sc, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+// Copy the scalar slots and the partial regions below `regions` to the host.
+bido_status read_scalars(bido_ctx* c, int regions = 0) {
+    HIP_OK(hipMemcpyAsync(c->sc_host, c->sc, pp_offset(regions) * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     return BIDO_OK;
+}
+double host_partials(const bido_ctx* c, int region, unsigned nb) {
+    double s = 0.0;
+    for (unsigned b = 0; b < nb; ++b) s += c->sc_host[pp_offset(region) + b];
+    return s;
 }
 
 // PCG on the internal vectors: x (initial guess in, solution out), Y.  With a
@@ -458,44 +466,50 @@ bido_status pcg(bido_ctx* c, double tol, bido_stats* st) {
     auto apply = [&](const double* ro) -> bido_status {
         precond_apply(c, c->r, c->z, ro, learned, stencil);
         if (!learned && !stencil) return BIDO_OK;
-        bido_status e2 = read_scalars(c);
+        bido_status e2 = read_scalars(c, PP_RZ + 1);
         if (e2) return e2;
-        const double rz = c->sc_host[S_RHO_NEW];
+        const double rz = host_partials(c, PP_RZ, c->nb_rz);
         if (!(rz > 0.0) || !std::isfinite(rz)) {
             ++fallbacks;
             precond_apply(c, c->r, c->z, ro, false, false);
         }
         return BIDO_OK;
     };
+    unsigned nb = 0;
     PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n) + 8.0 * n,
-         launch_spmv_lambda(s, c->lam, c->spmv_group, 1, c->x, c->Y, c->r, c->rd, c->sc));
-    bido_status e = read_scalars(c);
+         nb = launch_spmv_lambda(s, c->lam, c->spmv_group, 1, c->x, c->Y, c->r, c->sc));
+    bido_status e = read_scalars(c, PP_YY + 1);
     if (e) return e;
-    const double yy = c->sc_host[S_YY];
-    double rel = yy > 0 ? std::sqrt(c->sc_host[S_RR] / yy) : 0.0;
+    const double yy = host_partials(c, PP_YY, nb);
+    double rel = yy > 0 ? std::sqrt(host_partials(c, PP_RR, nb) / yy) : 0.0;
     int it = 0;
     bool conv = rel <= tol || yy == 0.0;
     if (yy == 0.0) launch_fill(s, n, c->x, 0.0);
+    // r.z of the current direction alternates between two slots, so that the
+    // direction update never overwrites the value its other blocks read
+    int rho = S_RHO;
     if (!conv) {
         if ((e = apply(nullptr))) return e;
-        PROF(c, K_P_UPDATE, 24.0 * n, launch_p_update(s, n, c->z, c->p, c->sc, 1, 0));
+        PROF(c, K_P_UPDATE, 24.0 * n, launch_p_update(s, n, c->z, c->p, c->sc, c->nb_rz, 1, 0, rho, rho));
         for (it = 1; it <= c->params.max_iter; ++it) {
-            PROF(c, K_MISC, 16.0, launch_copy_scalar(s, c->sc, S_RHO, S_RHO_NEW));
             PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n),
-                 launch_spmv_lambda(s, c->lam, c->spmv_group, 0, c->p, nullptr, c->q, c->rd, c->sc));
+                 nb = launch_spmv_lambda(s, c->lam, c->spmv_group, 0, c->p, nullptr, c->q, c->sc));
             PROF(c, K_PCG_UPDATE, (r_old ? 56.0 : 48.0) * n,
-                 launch_pcg_update(s, n, c->x, c->r, r_old, c->p, c->q, c->rd, c->sc));
-            if ((e = read_scalars(c))) return e;
-            const double pq = c->sc_host[S_PQ], rho = c->sc_host[S_RHO];
-            rel = std::sqrt(c->sc_host[S_RR] / yy);
-            if (!(pq > 0.0) || !(rho > 0.0) || !std::isfinite(rel)) {
+                 nb = launch_pcg_update(s, n, c->x, c->r, r_old, c->p, c->q, c->sc, nb, rho));
+            if ((e = read_scalars(c, PP_RR + 1))) return e;
+            const double pq = c->sc_host[S_PQ], rz = c->sc_host[rho];
+            rel = std::sqrt(host_partials(c, PP_RR, nb) / yy);
+            if (!(pq > 0.0) || !(rz > 0.0) || !std::isfinite(rel)) {
                 if (st) { st->iterations = it; st->rel_residual = rel; st->converged = 0; st->fallbacks = fallbacks; }
                 return fail(BIDO_ERR_NOT_SPD, "CG breakdown (p.Ap = " + std::to_string(pq) +
-                                                  ", r.z = " + std::to_string(rho) + ")");
+                                                  ", r.z = " + std::to_string(rz) + ")");
             }
             if (rel <= tol) { conv = true; break; }
             if ((e = apply(r_old))) return e;
-            PROF(c, K_P_UPDATE, 24.0 * n, launch_p_update(s, n, c->z, c->p, c->sc, 0, flexible ? 1 : 0));
+            const int next = rho == S_RHO ? S_RHO_NEW : S_RHO;
+            PROF(c, K_P_UPDATE, 24.0 * n,
+                 launch_p_update(s, n, c->z, c->p, c->sc, c->nb_rz, 0, flexible ? 1 : 0, rho, next));
+            rho = next;
         }
         if (it > c->params.max_iter) it = c->params.max_iter;
     }
@@ -744,19 +758,19 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
         HIP_OK(hipMalloc((void**)b, n2 * sizeof(double)));
     for (double** b : {&c->tA, &c->tC, &c->tD}) HIP_OK(hipMalloc((void**)b, c->N * sizeof(double)));
     HIP_OK(hipMalloc((void**)&c->tB, std::max<int64_t>(c->NH, 1) * sizeof(double)));
-    HIP_OK(hipMalloc((void**)&c->sc, S_COUNT * sizeof(double)));
+    HIP_OK(hipMalloc((void**)&c->sc, pp_offset(PP_COUNT) * sizeof(double)));
     // Work vectors start as NaN (all-ones bit pattern): a kernel that reads
     // one before writing it shows up in every result instead of by chance.
     for (double* b : {c->x, c->r, c->z, c->p, c->q, c->Y, c->r_old})
         HIP_OK(hipMemset(b, 0xFF, n2 * sizeof(double)));
     for (double* b : {c->tA, c->tC, c->tD}) HIP_OK(hipMemset(b, 0xFF, c->N * sizeof(double)));
     HIP_OK(hipMemset(c->tB, 0xFF, std::max<int64_t>(c->NH, 1) * sizeof(double)));
-    HIP_OK(hipMemset(c->sc, 0xFF, S_COUNT * sizeof(double)));
+    HIP_OK(hipMemset(c->sc, 0xFF, pp_offset(PP_COUNT) * sizeof(double)));
     for (FactorDev* f : {&c->p1, &c->pk}) {
         HIP_OK(hipMemset(f->ytmp, 0xFF, std::max<int64_t>(f->n, 1) * sizeof(double)));
         HIP_OK(hipMemset(f->upd, 0xFF, std::max<int64_t>(f->upd_size, 1) * sizeof(double)));
     }
-    HIP_OK(hipHostMalloc((void**)&c->sc_host, S_COUNT * sizeof(double), hipHostMallocDefault));
+    HIP_OK(hipHostMalloc((void**)&c->sc_host, pp_offset(PP_COUNT) * sizeof(double), hipHostMallocDefault));
     HIP_OK(hipMalloc((void**)&c->rd.partials, 2 * c->rd.max_blocks * sizeof(double)));
     HIP_OK(hipMalloc((void**)&c->rd.counter, sizeof(unsigned)));
     HIP_OK(hipMemset(c->rd.counter, 0, sizeof(unsigned)));

@@ -67,7 +67,17 @@ enum ScalarSlot {
     S_MU,           // (M U, 1)
     S_Y1SUM,        // sum of Y_1 (range check)
     S_TN2,          // |t|^2 of the learned correction's input
+    S_ALPHA,        // step length of the latest PCG update
     S_COUNT = 32
 };
+
+// Per-block partial sums of the PCG reductions, stored right after the
+// scalar slots in the same device buffer: region k holds at most PP_MAX
+// block partials.  The kernel that needs a total sums the partials itself
+// (every block in the same order), so no reduction needs a device-scope
+// fence; the host sums the regions it reads.
+enum PartialRegion { PP_RR = 0, PP_YY, PP_RZ, PP_ZRO, PP_PQ, PP_COUNT };
+constexpr int PP_MAX = 1024;
+constexpr int64_t pp_offset(int region) { return S_COUNT + (int64_t)region * PP_MAX; }
 
 }  // namespace bido

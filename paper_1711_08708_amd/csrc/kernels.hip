@@ -151,16 +151,15 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
-// mode 0: q = A p, partial p.q            (reduction slot S_PQ)
-// mode 1: r = y - A x, partials |r|^2, |y|^2 (slots S_RR, S_YY)
+// mode 0: q = A p, block partial of p.q            (region PP_PQ)
+// mode 1: r = y - A x, block partials of |r|^2, |y|^2 (PP_RR, PP_YY)
 template <int G, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_spmv_lambda(int64_t n, const int64_t* __restrict__ ptr,
                                                        const int32_t* __restrict__ col,
                                                        const double* __restrict__ val,
                                                        const double* __restrict__ x,
                                                        const double* __restrict__ y,
-                                                       double* __restrict__ out, double* partials,
-                                                       unsigned* counter, double* sc) {
+                                                       double* __restrict__ out, double* __restrict__ pp) {
     __shared__ double sh[BLOCK / WAVE];
     const int lane = threadIdx.x % G;
     const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
@@ -184,12 +183,13 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lambda(int64_t n, const int64_t*
     }
     acc0 = block_sum(acc0, sh);
     if (MODE == 0) {
-        double part[1] = {acc0};
-        finish_reduce<1>(part, partials, counter, sc + S_PQ, sh);
+        if (threadIdx.x == 0) pp[pp_offset(PP_PQ) + blockIdx.x] = acc0;
     } else {
         acc1 = block_sum(acc1, sh);
-        double part[2] = {acc0, acc1};
-        finish_reduce<2>(part, partials, counter, sc + S_RR, sh);  // S_RR, S_YY adjacent
+        if (threadIdx.x == 0) {
+            pp[pp_offset(PP_RR) + blockIdx.x] = acc0;
+            pp[pp_offset(PP_YY) + blockIdx.x] = acc1;
+        }
     }
 }
 
@@ -215,19 +215,24 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_csr(int64_t n, const int64_t* __
 // ---------------------------------------------------------------------------
 // PCG vector recurrences
 // ---------------------------------------------------------------------------
-// rho <- rho_new (start of an iteration is marked by the caller)
-__global__ void k_copy_scalar(double* sc, int dst, int src) { sc[dst] = sc[src]; }
+// Sum of nb block partials, in the same order in every block.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nb, double* sh) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += BLOCK) s += part[b];
+    return block_sum(s, sh);
+}
 
-// alpha = rho / pq ; x += alpha p ; r -= alpha q ; |r|^2
+// alpha = rho / p.q (p.q from the SpMV's nb_pq partials); x += alpha p ;
+// r -= alpha q ; block partials of |r|^2.  Block 0 records p.q and alpha.
 __global__ __launch_bounds__(BLOCK) void k_pcg_update(int64_t n, double* __restrict__ x,
                                                       double* __restrict__ r,
                                                       double* __restrict__ r_old,
                                                       const double* __restrict__ p,
                                                       const double* __restrict__ q,
-                                                      double* partials, unsigned* counter,
-                                                      double* sc) {
+                                                      double* __restrict__ pp, int nb_pq, int rho_slot) {
     __shared__ double sh[BLOCK / WAVE];
-    const double alpha = sc[S_RHO] / sc[S_PQ];
+    const double pq = sum_partials(pp + pp_offset(PP_PQ), nb_pq, sh);
+    const double alpha = pp[rho_slot] / pq;
     double acc = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
         x[i] += alpha * p[i];
@@ -237,19 +242,23 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_update(int64_t n, double* __restr
         acc += ri * ri;
     }
     acc = block_sum(acc, sh);
-    double part[1] = {acc};
-    finish_reduce<1>(part, partials, counter, sc + S_RR, sh);
+    if (threadIdx.x == 0) {
+        pp[pp_offset(PP_RR) + blockIdx.x] = acc;
+        if (blockIdx.x == 0) {
+            pp[S_PQ] = pq;
+            pp[S_ALPHA] = alpha;
+        }
+    }
 }
 
-// z1 = a - b over the first n1 entries (z2 already in place); rho_new = r.z;
-// with flexible CG also z.r_old (slot S_ZR_OLD) when r_old is given.
+// z1 = a - b over the first n1 entries (z2 already in place); block
+// partials of r.z (PP_RZ) and, with flexible CG, of r_old.z (PP_ZRO).
 __global__ __launch_bounds__(BLOCK) void k_combine_dot(int64_t n1, int64_t n, double* __restrict__ z,
                                                        const double* __restrict__ a,
                                                        const double* __restrict__ b,
                                                        const double* __restrict__ r,
                                                        const double* __restrict__ r_old,
-                                                       double* partials, unsigned* counter,
-                                                       double* sc) {
+                                                       double* __restrict__ pp) {
     __shared__ double sh[BLOCK / WAVE];
     double acc = 0.0, acc2 = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
@@ -264,28 +273,27 @@ __global__ __launch_bounds__(BLOCK) void k_combine_dot(int64_t n1, int64_t n, do
         if (r_old) acc2 += r_old[i] * zi;
     }
     acc = block_sum(acc, sh);
-    if (r_old) {
-        acc2 = block_sum(acc2, sh);
-        double part[2] = {acc, acc2};
-        finish_reduce<2>(part, partials, counter, sc + S_RHO_NEW, sh);  // S_RHO_NEW, S_ZR_OLD
-    } else {
-        double part[1] = {acc};
-        finish_reduce<1>(part, partials, counter, sc + S_RHO_NEW, sh);
+    if (r_old) acc2 = block_sum(acc2, sh);
+    if (threadIdx.x == 0) {
+        pp[pp_offset(PP_RZ) + blockIdx.x] = acc;
+        if (r_old) pp[pp_offset(PP_ZRO) + blockIdx.x] = acc2;
     }
 }
 
-// beta = rho_new / rho (or from flexible-CG slots), p = z + beta p
-__global__ void k_p_update(int64_t n, const double* __restrict__ z, double* __restrict__ p,
-                           const double* __restrict__ sc, int first, int flexible) {
+// rho_new = r.z (summed from nb partials); beta = rho_new / rho_old, or the
+// flexible (Polak-Ribiere) (r.z - r_old.z) / rho_old; p = z + beta p.  Block
+// 0 stores rho_new in slot rho_new_slot (never the slot read here).
+__global__ __launch_bounds__(BLOCK) void k_p_update(int64_t n, const double* __restrict__ z, double* __restrict__ p,
+                                                    double* __restrict__ pp, int nb, int first, int flexible,
+                                                    int rho_old_slot, int rho_new_slot) {
+    __shared__ double sh[BLOCK / WAVE];
+    const double rz = sum_partials(pp + pp_offset(PP_RZ), nb, sh);
     double beta = 0.0;
     if (!first) {
-        if (flexible) {
-            // Polak-Ribiere form: beta = (z.r - z.r_old) / rho_old
-            beta = (sc[S_RHO_NEW] - sc[S_ZR_OLD]) / sc[S_RHO];
-        } else {
-            beta = sc[S_RHO_NEW] / sc[S_RHO];
-        }
+        const double zro = flexible ? sum_partials(pp + pp_offset(PP_ZRO), nb, sh) : 0.0;
+        beta = (rz - zro) / pp[rho_old_slot];
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) pp[rho_new_slot] = rz;
     // the first direction is z itself: p may hold stale bits (0 * NaN = NaN)
     for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
         p[i] = first ? z[i] : z[i] + beta * p[i];
@@ -658,21 +666,20 @@ void launch_ionic(hipStream_t s, int64_t nh, const double* v, double* h, const d
     k_ionic_rhs<<<grid_for(nh), BLOCK, 0, s>>>(nh, v, h, stim, stim_on, mh, pos, y2, x2, c);
 }
 
-void launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode, const double* x,
-                        const double* y, double* out, Reduce rd, double* sc) {
-    const unsigned g = grid_for(A.n * group, BLOCK * 2, rd.max_blocks);
-#define BIDO_SPMV_CASE(G)                                                                       \
-    if (group == G) {                                                                           \
-        if (mode == 0)                                                                          \
-            k_spmv_lambda<G, 0><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, y, out,        \
-                                                     rd.partials, rd.counter, sc);              \
-        else                                                                                    \
-            k_spmv_lambda<G, 1><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, y, out,        \
-                                                     rd.partials, rd.counter, sc);              \
-        return;                                                                                 \
+unsigned launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode, const double* x,
+                            const double* y, double* out, double* pp) {
+    const unsigned g = grid_for(A.n * group, BLOCK * 2, PP_MAX);
+#define BIDO_SPMV_CASE(G)                                                                               \
+    if (group == G) {                                                                                   \
+        if (mode == 0)                                                                                  \
+            k_spmv_lambda<G, 0><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, y, out, pp);           \
+        else                                                                                            \
+            k_spmv_lambda<G, 1><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, y, out, pp);           \
+        return g;                                                                                       \
     }
     BIDO_SPMV_CASE(4) BIDO_SPMV_CASE(8) BIDO_SPMV_CASE(16) BIDO_SPMV_CASE(32)
 #undef BIDO_SPMV_CASE
+    return 0;
 }
 
 void launch_spmv_csr(hipStream_t s, const CsrDev& A, int group, const double* x, const double* b,
@@ -685,22 +692,21 @@ void launch_spmv_csr(hipStream_t s, const CsrDev& A, int group, const double* x,
     else k_spmv_csr<32><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, b, y);
 }
 
-void launch_copy_scalar(hipStream_t s, double* sc, int dst, int src) {
-    k_copy_scalar<<<1, 1, 0, s>>>(sc, dst, src);
+unsigned launch_pcg_update(hipStream_t s, int64_t n, double* x, double* r, double* r_old, const double* p,
+                           const double* q, double* pp, unsigned nb_pq, int rho_slot) {
+    const unsigned g = grid_for(n, BLOCK * 4, PP_MAX);
+    k_pcg_update<<<g, BLOCK, 0, s>>>(n, x, r, r_old, p, q, pp, (int)nb_pq, rho_slot);
+    return g;
 }
-void launch_pcg_update(hipStream_t s, int64_t n, double* x, double* r, double* r_old, const double* p,
-                       const double* q, Reduce rd, double* sc) {
-    k_pcg_update<<<grid_for(n, BLOCK * 4, rd.max_blocks), BLOCK, 0, s>>>(n, x, r, r_old, p, q,
-                                                                          rd.partials, rd.counter, sc);
+unsigned launch_combine_dot(hipStream_t s, int64_t n1, int64_t n, double* z, const double* a, const double* b,
+                            const double* r, const double* r_old, double* pp) {
+    const unsigned g = grid_for(n, BLOCK * 4, PP_MAX);
+    k_combine_dot<<<g, BLOCK, 0, s>>>(n1, n, z, a, b, r, r_old, pp);
+    return g;
 }
-void launch_combine_dot(hipStream_t s, int64_t n1, int64_t n, double* z, const double* a, const double* b,
-                        const double* r, const double* r_old, Reduce rd, double* sc) {
-    k_combine_dot<<<grid_for(n, BLOCK * 4, rd.max_blocks), BLOCK, 0, s>>>(n1, n, z, a, b, r, r_old,
-                                                                           rd.partials, rd.counter, sc);
-}
-void launch_p_update(hipStream_t s, int64_t n, const double* z, double* p, const double* sc, int first,
-                     int flexible) {
-    k_p_update<<<grid_for(n), BLOCK, 0, s>>>(n, z, p, sc, first, flexible);
+void launch_p_update(hipStream_t s, int64_t n, const double* z, double* p, double* pp, unsigned nb_rz, int first,
+                     int flexible, int rho_old_slot, int rho_new_slot) {
+    k_p_update<<<grid_for(n), BLOCK, 0, s>>>(n, z, p, pp, (int)nb_rz, first, flexible, rho_old_slot, rho_new_slot);
 }
 
 template <typename T>

@@ -65,22 +65,22 @@ void launch_shift(hipStream_t s, int64_t n, double* x, const double* sc, int slo
 void launch_ionic(hipStream_t s, int64_t nh, const double* v, double* h, const double* stim,
                   double stim_on, const double* mh, const int64_t* pos, double* y2, double* x2,
                   const IonicConst& c);
-void launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode, const double* x,
-                        const double* y, double* out, Reduce rd, double* sc);
+// Each returns its grid size: the number of block partials it wrote.
+unsigned launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode, const double* x,
+                            const double* y, double* out, double* pp);
 void launch_spmv_csr(hipStream_t s, const CsrDev& A, int group, const double* x, const double* b,
                      double* y);
-void launch_copy_scalar(hipStream_t s, double* sc, int dst, int src);
 // dense top of a sweep: gather w_top from b and the bottom roots' updates,
 // then x[top_pos] = S_top^-1 w_top (inv: n_top x n_top row-major)
 template <typename T>
 void launch_tri_top(hipStream_t s, const TriPlan& P, const T* inv, const double* b, const double* upd,
                     int64_t ground, double* x);
-void launch_pcg_update(hipStream_t s, int64_t n, double* x, double* r, double* r_old, const double* p,
-                       const double* q, Reduce rd, double* sc);
-void launch_combine_dot(hipStream_t s, int64_t n1, int64_t n, double* z, const double* a, const double* b,
-                        const double* r, const double* r_old, Reduce rd, double* sc);
-void launch_p_update(hipStream_t s, int64_t n, const double* z, double* p, const double* sc, int first,
-                     int flexible);
+unsigned launch_pcg_update(hipStream_t s, int64_t n, double* x, double* r, double* r_old, const double* p,
+                           const double* q, double* pp, unsigned nb_pq, int rho_slot);
+unsigned launch_combine_dot(hipStream_t s, int64_t n1, int64_t n, double* z, const double* a, const double* b,
+                            const double* r, const double* r_old, double* pp);
+void launch_p_update(hipStream_t s, int64_t n, const double* z, double* p, double* pp, unsigned nb_rz, int first,
+                     int flexible, int rho_old_slot, int rho_new_slot);
 
 template <typename T>
 void launch_tri_fwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
