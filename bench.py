@@ -44,7 +44,43 @@ def _parse():
                     help="plain steps whose CG iterations provide training pairs")
     ap.add_argument("--variant-steps", type=int, default=50)
     ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (counter calibration)")
     return ap.parse_args()
+
+
+COPY_BYTES = 256 << 20
+
+
+def _calibrate_copy():
+    """A plain device-to-device copy of known size, for scaling the HBM
+    byte counters (FETCH_SIZE, WRITE_SIZE) of a profiler run."""
+    import torch
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 3}))
+
+
+def _traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none or the kernel source changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t:
+        return None
+    src = os.path.join(ROOT, "paper_1711_08708_amd", "csrc", "kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(1):
+        return None
+    return float(t.group(1))
 
 
 def _timed_steps(torch, solver, state, n0, k):
@@ -70,6 +106,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.calibrate_copy:
+        _calibrate_copy()
+        return
     import numpy as np
     import torch
 
@@ -114,7 +153,7 @@ def main():
     total_ms = sum(p["ms"] for p in prof.values())
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
+                "traffic": _traffic(dom_name, cfg["name"], args.precision),
                 "launches": dom["launches"], "avg_launch_us": round(dom["ms"] * 1e3 / dom["launches"], 2),
                 "bytes_per_launch": round(dom["bytes"] / dom["launches"]),
                 "step_bytes": round(total_bytes / args.steps),
