@@ -44,6 +44,9 @@ def _parse():
                     help="plain steps whose CG iterations provide training pairs")
     ap.add_argument("--variant-steps", type=int, default=50)
     ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch-streams", type=int, default=8, help="streams of the batch (batch64)")
+    ap.add_argument("--batch-learned", action="store_true",
+                    help="batch64: train the learned stencil of every slice first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy three times (counter calibration)")
     return ap.parse_args()
@@ -108,6 +111,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         _calibrate_copy()
+        return
+    if args.config == "batch64":
+        _bench_batch(args)
         return
     import numpy as np
     import torch
@@ -239,6 +245,102 @@ def _variants(torch, B, solver, args):
     solver.set_precision(B.PREC_FP64)
     solver.set_precond(B.PRECOND_PLAIN)
     return out
+
+
+def _gen_slice(kw):
+    import workloads as w
+    return w.thorax2d(**kw)
+
+
+def _bench_batch(args):
+    """64 independent thorax-like slices (vertex counts log-uniform in
+    [20k, 300k], seeded sites and conductivity scales) stepped together;
+    the value is slice-steps per second of the whole batch."""
+    import concurrent.futures as cf
+
+    import numpy as np
+    import torch
+
+    import paper_1711_08708_amd as B
+    import workloads as w
+
+    torch.cuda.set_device(0)
+    prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
+    kws = w.make_config("batch64")
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        cfgs = list(ex.map(_gen_slice, kws))
+    t_mesh = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    solvers = [B.Solver(c, tol=args.tol, precision=prec) for c in cfgs]
+    t_setup = time.perf_counter() - t0
+    n_nodes = sum(s.N for s in solvers)
+    print(f"[bench] batch64: {len(solvers)} slices, {n_nodes} vertices, meshes {t_mesh:.1f}s, "
+          f"set-up {t_setup:.1f}s", file=sys.stderr, flush=True)
+    sample = [int(np.argmin([s.N for s in solvers])), int(np.argmax([s.N for s in solvers]))]
+    keep = {k: cfgs[k] for k in sample}
+    del cfgs
+    training = None
+    if args.batch_learned:
+        t0 = time.perf_counter()
+        spd = 0
+        for sv in solvers:
+            v, h, u = sv.state()
+            col = sv.learn_collect(v, h, u, 0, args.collect_steps, max_samples=16 * args.collect_steps)
+            n_val = max(1, col["samples"] // 10)
+            ts = sv.learn_train(kind=B.LEARN_STENCIL, epochs=args.epochs, batch=8, lr=2e-3, seed=0, n_val=n_val)
+            spd += ts["spd"]
+            if ts["spd"]:
+                sv.set_precond(B.PRECOND_LEARNED)
+        training = {"collect_steps": args.collect_steps, "epochs": args.epochs, "spd_slices": spd,
+                    "seconds": round(time.perf_counter() - t0, 1)}
+    batch = B.Batch(solvers, n_streams=args.batch_streams)
+    states = [s.state() for s in solvers]
+    batch.run(states, 0, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot, per = batch.run(states, args.warmup, args.steps - 1)
+    before = {k: (states[k][0].cpu().numpy().copy(), states[k][1].cpu().numpy().copy()) for k in sample}
+    tot2, per2 = batch.run(states, args.warmup + args.steps - 1, 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    S = len(solvers)
+    n_last = args.warmup + args.steps - 1
+    result = {
+        "metric": METRIC, "value": round(S * args.steps / wall, 3), "unit": "slice-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == B.PREC_FP64 else "f64+f32", "data": "synthetic",
+        "config": {"workload": f"batch64: {S} thorax-like slices, {n_nodes} vertices in total, "
+                               f"vertex counts log-uniform in [20k, 300k], lockstep PCG per slice",
+                   "slices": S, "total_nodes": n_nodes, "precision": args.precision, "tol": args.tol,
+                   "streams": args.batch_streams, "learned": bool(args.batch_learned),
+                   "mean_iterations_per_slice_step": round((tot["total_iterations"] + tot2["total_iterations"])
+                                                           / (S * args.steps), 3),
+                   "max_iterations_per_step": max(tot["iterations"], tot2["iterations"]),
+                   "mesh_s": round(t_mesh, 1), "setup_s": round(t_setup, 1)},
+    }
+    if training:
+        result["config"]["training"] = training
+    from oracle import bidomain as bd
+    par = {}
+    for k in sample:
+        sy = bd.System(keep[k])
+        Uo, Vo, _ = sy.step(before[k][0], before[k][1], n_last)
+        Uo = sy.to_global_u(Uo)
+        U, V = states[k][2].cpu().numpy(), states[k][0].cpu().numpy()
+        par[keep[k]["name"]] = {"e_u": float(np.linalg.norm(U - Uo) / np.linalg.norm(Uo)),
+                                "e_v": float(np.linalg.norm(V - Vo) / np.linalg.norm(Vo))}
+    result["parity"] = {"step": n_last, "slices": par}
+    if not args.no_cpu:
+        k = sample[0]
+        cb = _cpu_baseline(keep[k], args.cpu_steps)
+        cb["value"] = round(cb["value"], 5)
+        cb["unit"] = "slice-steps/s"
+        cb["sample"] = "smallest slice: " + cb["sample"]
+        result["cpu_baseline"] = cb
+    batch.close()
+    print(json.dumps(result), flush=True)
 
 
 def _cpu_baseline(cfg, n_steps):

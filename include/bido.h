@@ -264,6 +264,29 @@ bido_status bido_gnn_loss_grad(bido_ctx* ctx, const float* that, const float* y,
 bido_status bido_stencil_check(bido_ctx* ctx, const float* zh, const float* bh, float* r, double* loss,
                                float* grad);
 
+/* --- batched execution of independent slices ---------------------------- *
+ * A batch runs bido_run on many contexts at once (Sec. 3.2 for each slice,
+ * each with its own PCG scalars and stopping test).  The contexts keep their
+ * settings (precision, preconditioner); while they belong to the batch their
+ * launches go to the batch's own streams (n_streams of them, <= 0: up to 8;
+ * default priority), packed by size, and the host waits once per PCG phase
+ * for all slices.  The contexts must live on the current device, may not be
+ * listed twice or belong to another batch (BIDO_ERR_STATE), and must not be
+ * used on their own until bido_batch_destroy gives them back.  `stream` is
+ * the caller's stream (a hipStream_t): bido_batch_run waits for it and makes it wait for the
+ * batch.  The additive learned mode is refused (BIDO_ERR_STATE).          */
+typedef struct bido_batch bido_batch;
+bido_status bido_batch_create(bido_ctx* const* ctxs, int n_ctx, int n_streams, void* stream,
+                              bido_batch** out);
+/* v[i], w[i], u[i]: device state of slice i as for bido_run.  per_ctx (host
+ * array of n_ctx, may be NULL): the last step's statistics of each slice with
+ * its summed iterations; total: the largest per-step iteration count
+ * (iterations), the sum over slices and steps (total_iterations), the worst
+ * final residual, wall time.  Returns the first error of any slice.       */
+bido_status bido_batch_run(bido_batch* b, double* const* v, double* const* w, double* const* u, double dt,
+                           int64_t n0, int64_t n_steps, bido_stats* per_ctx, bido_stats* total);
+void bido_batch_destroy(bido_batch* b);
+
 /* Per-kernel profile: launches, summed event-timed duration [ms] and the
  * algorithmic bytes those launches must move (inputs read once, outputs
  * written once), aggregated by kernel class.                            */

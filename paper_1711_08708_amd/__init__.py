@@ -132,6 +132,13 @@ ABI = {
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)]),
     "bido_stencil_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)]),
+    "bido_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "bido_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(Stats),
+                                      ctypes.POINTER(Stats)]),
+    "bido_batch_destroy": (None, [ctypes.c_void_p]),
     "bido_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KProf), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int)]),
@@ -382,6 +389,54 @@ class Solver:
         if getattr(self, "ctx", None):
             lib.bido_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent slices (Solver objects on one device) stepped together.
+
+    While the batch exists the solvers run on its streams and must not be
+    used on their own; close() gives them back."""
+
+    def __init__(self, solvers, n_streams=0, stream=None):
+        import torch
+        self.torch = torch
+        self.solvers = list(solvers)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s.ctx.value for s in self.solvers])
+        b = ctypes.c_void_p()
+        _check(lib.bido_batch_create(arr, len(self.solvers), int(n_streams), ctypes.c_void_p(stream.cuda_stream),
+                                     ctypes.byref(b)))
+        self.b = b
+
+    def run(self, states, n0, n_steps, check=True):
+        """states: one (v, w, u) tuple of device tensors per solver.  Returns
+        (total, per_slice) statistics dicts."""
+        S = len(self.solvers)
+        if len(states) != S:
+            raise BidoError(-1, "one state per solver expected")
+        v = (ctypes.c_void_p * S)(*[sv._dev(st[0], sv.NH).value for sv, st in zip(self.solvers, states)])
+        w = (ctypes.c_void_p * S)(*[sv._dev(st[1], sv.NH).value for sv, st in zip(self.solvers, states)])
+        u = (ctypes.c_void_p * S)(*[sv._dev(st[2], sv.N).value for sv, st in zip(self.solvers, states)])
+        per = (Stats * S)()
+        tot = Stats()
+        code = lib.bido_batch_run(self.b, v, w, u, self.solvers[0].dt, int(n0), int(n_steps), per,
+                                  ctypes.byref(tot))
+        if check:
+            _check(code)
+        return tot.as_dict(), [p.as_dict() for p in per]
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib.bido_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -283,6 +283,7 @@ struct bido_ctx {
     double* sc = nullptr;        // scalar slots, then the PCG partial regions
     double* sc_host = nullptr;   // pinned
     unsigned nb_rz = 0;          // partials of r.z written by the latest apply
+    bool batched = false;        // owned by a bido_batch (runs on its stream)
     Reduce rd;
     int64_t *u_pos = nullptr, *v_pos = nullptr;
     double *m_int = nullptr, *mh_loc = nullptr, *stim_loc = nullptr;
@@ -450,77 +451,133 @@ double host_partials(const bido_ctx* c, int region, unsigned nb) {
     return s;
 }
 
-// PCG on the internal vectors: x (initial guess in, solution out), Y.  With a
-// nonlinear or inexact preconditioner (learned correction, mixed precision)
-// the direction update is the flexible (Polak-Ribiere) one.  A learned
-// apply that is not a descent direction (r.z <= 0) is redone without the
-// correction and counted as a fallback.
-bido_status pcg(bido_ctx* c, double tol, bido_stats* st) {
+// PCG on the internal vectors: x (initial guess in, solution out), Y, run as
+// a sequence of phases so that a batch of contexts can advance in lockstep.
+// Each phase ends with an asynchronous copy of the scalar slots and the
+// partials the host needs; pcg_advance runs once that copy has landed.
+// With a nonlinear or inexact preconditioner (learned correction, mixed
+// precision) the direction update is the flexible (Polak-Ribiere) one.  A
+// learned additive apply that is not a descent direction (r.z <= 0) is redone
+// without the correction and counted as a fallback.
+struct PcgRun {
+    double tol = 0.0, yy = 0.0, rel = 0.0;
+    int it = 0;                 // completed updates x += alpha p
+    int rho = S_RHO;            // slot of r.z of the current direction
+    int fallbacks = 0;
+    unsigned nb = 0;            // partials written by the latest reduction
+    bool learned = false, stencil = false, flexible = false;
+    bool started = false, done = false, conv = false;
+    double* r_old = nullptr;
+    bido_status status = BIDO_OK;
+    std::string err;
+};
+
+void copy_scalars_async(bido_ctx* c, int regions) {
+    hipMemcpyAsync(c->sc_host, c->sc, pp_offset(regions) * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+}
+
+bido_status pcg_apply(bido_ctx* c, PcgRun& ps, const double* ro) {
+    precond_apply(c, c->r, c->z, ro, ps.learned, ps.stencil);
+    if (!ps.learned) return BIDO_OK;
+    bido_status e = read_scalars(c, PP_RZ + 1);
+    if (e) return e;
+    const double rz = host_partials(c, PP_RZ, c->nb_rz);
+    if (!(rz > 0.0) || !std::isfinite(rz)) {
+        ++ps.fallbacks;
+        precond_apply(c, c->r, c->z, ro, false, false);
+    }
+    return BIDO_OK;
+}
+
+// q = Lambda p, x += alpha p, r -= alpha q; copy |r|^2 partials and p.q
+void pcg_tail(bido_ctx* c, PcgRun& ps) {
     hipStream_t s = c->stream;
     const int64_t n = c->n2;
-    const bool learned = c->precond == BIDO_PRECOND_LEARNED_ADDITIVE && !c->gnn.collecting;
-    const bool stencil = c->precond == BIDO_PRECOND_LEARNED && !c->gnn.collecting && c->gnn.stencil_ready;
-    const bool flexible = c->precision == BIDO_PREC_MIXED || learned || stencil;
-    double* r_old = flexible ? c->r_old : nullptr;
-    int fallbacks = 0;
-    auto apply = [&](const double* ro) -> bido_status {
-        precond_apply(c, c->r, c->z, ro, learned, stencil);
-        if (!learned && !stencil) return BIDO_OK;
-        bido_status e2 = read_scalars(c, PP_RZ + 1);
-        if (e2) return e2;
-        const double rz = host_partials(c, PP_RZ, c->nb_rz);
-        if (!(rz > 0.0) || !std::isfinite(rz)) {
-            ++fallbacks;
-            precond_apply(c, c->r, c->z, ro, false, false);
-        }
-        return BIDO_OK;
-    };
     unsigned nb = 0;
+    PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n),
+         nb = launch_spmv_lambda(s, c->lam, c->spmv_group, 0, c->p, nullptr, c->q, c->sc));
+    PROF(c, K_PCG_UPDATE, (ps.r_old ? 56.0 : 48.0) * n,
+         ps.nb = launch_pcg_update(s, n, c->x, c->r, ps.r_old, c->p, c->q, c->sc, nb, ps.rho));
+    copy_scalars_async(c, PP_RR + 1);
+}
+
+// r0 = Y - Lambda x0; copy |r|^2 and |Y|^2 partials
+void pcg_start(bido_ctx* c, PcgRun& ps, double tol) {
+    ps = PcgRun();
+    ps.tol = tol;
+    ps.learned = c->precond == BIDO_PRECOND_LEARNED_ADDITIVE && !c->gnn.collecting;
+    ps.stencil = c->precond == BIDO_PRECOND_LEARNED && !c->gnn.collecting && c->gnn.stencil_ready;
+    ps.flexible = c->precision == BIDO_PREC_MIXED || ps.learned || ps.stencil;
+    ps.r_old = ps.flexible ? c->r_old : nullptr;
+    const int64_t n = c->n2;
     PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n) + 8.0 * n,
-         nb = launch_spmv_lambda(s, c->lam, c->spmv_group, 1, c->x, c->Y, c->r, c->sc));
-    bido_status e = read_scalars(c, PP_YY + 1);
-    if (e) return e;
-    const double yy = host_partials(c, PP_YY, nb);
-    double rel = yy > 0 ? std::sqrt(host_partials(c, PP_RR, nb) / yy) : 0.0;
-    int it = 0;
-    bool conv = rel <= tol || yy == 0.0;
-    if (yy == 0.0) launch_fill(s, n, c->x, 0.0);
-    // r.z of the current direction alternates between two slots, so that the
-    // direction update never overwrites the value its other blocks read
-    int rho = S_RHO;
-    if (!conv) {
-        if ((e = apply(nullptr))) return e;
-        PROF(c, K_P_UPDATE, 24.0 * n, launch_p_update(s, n, c->z, c->p, c->sc, c->nb_rz, 1, 0, rho, rho));
-        for (it = 1; it <= c->params.max_iter; ++it) {
-            PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n),
-                 nb = launch_spmv_lambda(s, c->lam, c->spmv_group, 0, c->p, nullptr, c->q, c->sc));
-            PROF(c, K_PCG_UPDATE, (r_old ? 56.0 : 48.0) * n,
-                 nb = launch_pcg_update(s, n, c->x, c->r, r_old, c->p, c->q, c->sc, nb, rho));
-            if ((e = read_scalars(c, PP_RR + 1))) return e;
-            const double pq = c->sc_host[S_PQ], rz = c->sc_host[rho];
-            rel = std::sqrt(host_partials(c, PP_RR, nb) / yy);
-            if (!(pq > 0.0) || !(rz > 0.0) || !std::isfinite(rel)) {
-                if (st) { st->iterations = it; st->rel_residual = rel; st->converged = 0; st->fallbacks = fallbacks; }
-                return fail(BIDO_ERR_NOT_SPD, "CG breakdown (p.Ap = " + std::to_string(pq) +
-                                                  ", r.z = " + std::to_string(rz) + ")");
-            }
-            if (rel <= tol) { conv = true; break; }
-            if ((e = apply(r_old))) return e;
-            const int next = rho == S_RHO ? S_RHO_NEW : S_RHO;
-            PROF(c, K_P_UPDATE, 24.0 * n,
-                 launch_p_update(s, n, c->z, c->p, c->sc, c->nb_rz, 0, flexible ? 1 : 0, rho, next));
-            rho = next;
+         ps.nb = launch_spmv_lambda(c->stream, c->lam, c->spmv_group, 1, c->x, c->Y, c->r, c->sc));
+    copy_scalars_async(c, PP_YY + 1);
+}
+
+// Decide on the scalars of the latest phase and launch the next one.
+void pcg_advance(bido_ctx* c, PcgRun& ps) {
+    hipStream_t s = c->stream;
+    const int64_t n = c->n2;
+    auto finish = [&](bool conv, bido_status st, const std::string& msg) {
+        ps.done = true;
+        ps.conv = conv;
+        ps.status = st;
+        ps.err = msg;
+    };
+    bido_status e;
+    if (!ps.started) {
+        ps.started = true;
+        ps.yy = host_partials(c, PP_YY, ps.nb);
+        ps.rel = ps.yy > 0 ? std::sqrt(host_partials(c, PP_RR, ps.nb) / ps.yy) : 0.0;
+        if (ps.yy == 0.0) {
+            launch_fill(s, n, c->x, 0.0);
+            return finish(true, BIDO_OK, "");
         }
-        if (it > c->params.max_iter) it = c->params.max_iter;
+        if (ps.rel <= ps.tol) return finish(true, BIDO_OK, "");
+        if ((e = pcg_apply(c, ps, nullptr))) return finish(false, e, "device error");
+        PROF(c, K_P_UPDATE, 24.0 * n, launch_p_update(s, n, c->z, c->p, c->sc, c->nb_rz, 1, 0, ps.rho, ps.rho));
+        ps.it = 1;
+        return pcg_tail(c, ps);
     }
-    c->fallbacks += fallbacks;
+    const double pq = c->sc_host[S_PQ], rz = c->sc_host[ps.rho];
+    ps.rel = std::sqrt(host_partials(c, PP_RR, ps.nb) / ps.yy);
+    if (!(pq > 0.0) || !(rz > 0.0) || !std::isfinite(ps.rel))
+        return finish(false, BIDO_ERR_NOT_SPD,
+                      "CG breakdown (p.Ap = " + std::to_string(pq) + ", r.z = " + std::to_string(rz) + ")");
+    if (ps.rel <= ps.tol) return finish(true, BIDO_OK, "");
+    if (ps.it >= c->params.max_iter)
+        return finish(false, BIDO_ERR_NOT_CONVERGED, "tolerance not reached within max_iter");
+    if ((e = pcg_apply(c, ps, ps.r_old))) return finish(false, e, "device error");
+    // r.z alternates between two slots, so that the direction update never
+    // overwrites the value its other blocks read
+    const int next = ps.rho == S_RHO ? S_RHO_NEW : S_RHO;
+    PROF(c, K_P_UPDATE, 24.0 * n,
+         launch_p_update(s, n, c->z, c->p, c->sc, c->nb_rz, 0, ps.flexible ? 1 : 0, ps.rho, next));
+    ps.rho = next;
+    ++ps.it;
+    pcg_tail(c, ps);
+}
+
+bido_status pcg_result(bido_ctx* c, const PcgRun& ps, bido_stats* st) {
+    c->fallbacks += ps.fallbacks;
     if (st) {
-        st->iterations = it;
-        st->rel_residual = rel;
-        st->converged = conv ? 1 : 0;
-        st->fallbacks = fallbacks;
+        st->iterations = ps.it;
+        st->rel_residual = ps.rel;
+        st->converged = ps.conv ? 1 : 0;
+        st->fallbacks = ps.fallbacks;
     }
-    return conv ? BIDO_OK : fail(BIDO_ERR_NOT_CONVERGED, "tolerance not reached within max_iter");
+    return ps.status ? fail(ps.status, ps.err) : BIDO_OK;
+}
+
+bido_status pcg(bido_ctx* c, double tol, bido_stats* st) {
+    PcgRun ps;
+    pcg_start(c, ps, tol);
+    while (!ps.done) {
+        HIP_OK(hipStreamSynchronize(c->stream));
+        pcg_advance(c, ps);
+    }
+    return pcg_result(c, ps, st);
 }
 
 // After a converged solve while collecting: targets (V* - V_k - Z2_k) / |t_k|.
@@ -560,7 +617,8 @@ IonicConst ionic_consts(const bido_ctx* c) {
 }
 
 // one time step on device arrays (no sync, no timing)
-bido_status step_once(bido_ctx* c, double* v, double* w, double* u, int64_t n, bido_stats* st) {
+// Steps 1 and 3 on the device and the start of Step 2 (no wait).
+void step_begin(bido_ctx* c, double* v, double* w, double* u, int64_t n, PcgRun& ps) {
     hipStream_t s = c->stream;
     const int64_t N = c->N, NH = c->NH;
     PROF(c, K_MISC, 24.0 * N, launch_scatter_in(s, N, c->u_pos, u, c->x));   // X0 = (U^n, V^n)
@@ -569,13 +627,30 @@ bido_status step_once(bido_ctx* c, double* v, double* w, double* u, int64_t n, b
          launch_ionic(s, NH, v, w, c->stim_loc, on, c->mh_loc, c->v_pos, c->Y + N, c->x + N,
                       ionic_consts(c)));                               // Steps 1 and 3
     PROF(c, K_MISC, 8.0 * N, launch_fill(s, N, c->Y, 0.0));           // Y1 = 0
-    bido_status e = pcg(c, c->params.tol, st);                         // Step 2
+    pcg_start(c, ps, c->params.tol);                                   // Step 2
+}
+
+// After Step 2: normalisation (M U, 1) = 0 and the write-back of U, V.
+bido_status step_end(bido_ctx* c, double* v, double* u, const PcgRun& ps, bido_stats* st) {
+    hipStream_t s = c->stream;
+    const int64_t N = c->N, NH = c->NH;
+    bido_status e = pcg_result(c, ps, st);
     finish_collection(c, e == BIDO_OK);
     if (e && e != BIDO_ERR_NOT_CONVERGED) return e;
     PROF(c, K_MISC, 16.0 * N, launch_dot_reduce(s, N, c->m_int, c->x, c->rd, c->sc + S_MU));  // (M U, 1)
     PROF(c, K_MISC, 24.0 * N, launch_gather_out(s, N, c->u_pos, c->x, u, c->sc, S_MU, c->hs.msum));
     PROF(c, K_MISC, 24.0 * NH, launch_gather_out(s, NH, c->v_pos, c->x + N, v, c->sc, -1, 1.0));
     return e;
+}
+
+bido_status step_once(bido_ctx* c, double* v, double* w, double* u, int64_t n, bido_stats* st) {
+    PcgRun ps;
+    step_begin(c, v, w, u, n, ps);
+    while (!ps.done) {
+        HIP_OK(hipStreamSynchronize(c->stream));
+        pcg_advance(c, ps);
+    }
+    return step_end(c, v, u, ps, st);
 }
 
 bido_status gnn_setup(bido_ctx* c) {
@@ -789,6 +864,157 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
 }
 
 void bido_destroy(bido_ctx* ctx) { delete ctx; }
+
+// ---------------------------------------------------------------------------
+// Batched execution of independent slices: every context advances Steps 1-3
+// in lockstep.  The slices' launches go to a few streams of the batch (the
+// slices are packed onto them by size, largest first), so that small,
+// latency-bound slices overlap on the device; the host waits once per PCG
+// phase for the whole batch instead of once per slice.
+// ---------------------------------------------------------------------------
+struct bido_batch {
+    std::vector<bido_ctx*> ctx;
+    std::vector<hipStream_t> saved;    // the contexts' own streams
+    std::vector<hipStream_t> own;      // the batch's streams
+    std::vector<hipEvent_t> done;
+    hipEvent_t start = nullptr;
+    hipStream_t stream = nullptr;      // caller's stream
+    ~bido_batch() {
+        for (size_t i = 0; i < ctx.size(); ++i) {
+            ctx[i]->stream = saved[i];
+            ctx[i]->batched = false;
+        }
+        for (hipStream_t s : own) hipStreamDestroy(s);
+        for (hipEvent_t e : done) hipEventDestroy(e);
+        if (start) hipEventDestroy(start);
+    }
+};
+
+bido_status bido_batch_create(bido_ctx* const* ctxs, int n_ctx, int n_streams, void* stream,
+                              bido_batch** out) {
+    if (!ctxs || n_ctx < 1 || !out) return fail(BIDO_ERR_ARG, "null argument or empty batch");
+    *out = nullptr;
+    for (int i = 0; i < n_ctx; ++i) {
+        if (!ctxs[i]) return fail(BIDO_ERR_ARG, "null context");
+        if (ctxs[i]->batched) return fail(BIDO_ERR_STATE, "context already in a batch");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(BIDO_ERR_ARG, "context listed twice");
+    }
+    auto b = std::make_unique<bido_batch>();
+    const int K = n_streams > 0 ? std::min(n_streams, n_ctx) : std::min(n_ctx, 8);
+    b->stream = (hipStream_t)stream;
+    HIP_OK(hipEventCreateWithFlags(&b->start, hipEventDisableTiming));
+    for (int k = 0; k < K; ++k) {
+        hipStream_t st;
+        HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        b->own.push_back(st);
+        hipEvent_t ev;
+        HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        b->done.push_back(ev);
+    }
+    // largest slices first, each to the least loaded stream
+    std::vector<int> order(n_ctx);
+    for (int i = 0; i < n_ctx; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int c) { return ctxs[a]->n2 > ctxs[c]->n2; });
+    std::vector<int64_t> load(K, 0);
+    std::vector<int> which(n_ctx);
+    for (int i : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        which[i] = k;
+        load[k] += ctxs[i]->n2;
+    }
+    for (int i = 0; i < n_ctx; ++i) {
+        b->ctx.push_back(ctxs[i]);
+        b->saved.push_back(ctxs[i]->stream);
+        ctxs[i]->stream = b->own[which[i]];
+        ctxs[i]->batched = true;
+    }
+    *out = b.release();
+    return BIDO_OK;
+}
+
+void bido_batch_destroy(bido_batch* b) {
+    if (!b) return;
+    for (hipStream_t s : b->own) hipStreamSynchronize(s);
+    delete b;
+}
+
+bido_status bido_batch_run(bido_batch* b, double* const* v, double* const* w, double* const* u, double dt,
+                           int64_t n0, int64_t n_steps, bido_stats* per_ctx, bido_stats* total) {
+    if (!b || !v || !w || !u || n_steps < 0) return fail(BIDO_ERR_ARG, "null argument");
+    const int S = (int)b->ctx.size();
+    for (int i = 0; i < S; ++i) {
+        bido_ctx* c = b->ctx[i];
+        if (!v[i] || !w[i] || !u[i]) return fail(BIDO_ERR_ARG, "null state pointer");
+        if (!dt_matches(c, dt)) return fail(BIDO_ERR_DT_MISMATCH, "dt differs from the factored time step");
+        if (c->precond == BIDO_PRECOND_LEARNED_ADDITIVE)
+            return fail(BIDO_ERR_STATE, "the additive learned mode needs a host check inside the apply; "
+                                        "not available in a batch");
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    HIP_OK(hipEventRecord(b->start, b->stream));
+    for (hipStream_t s : b->own) HIP_OK(hipStreamWaitEvent(s, b->start, 0));
+    std::vector<PcgRun> ps(S);
+    std::vector<bido_stats> last(S);
+    std::vector<int64_t> tot(S, 0);
+    std::vector<int> fb(S, 0);
+    int max_it = 0;
+    bido_status err = BIDO_OK;
+    bool all_conv = true;
+    double worst = 0.0;
+    for (int64_t k = 0; k < n_steps && !err; ++k) {
+        const int64_t n = n0 + k;
+        for (int i = 0; i < S; ++i) step_begin(b->ctx[i], v[i], w[i], u[i], n, ps[i]);
+        for (;;) {
+            for (hipStream_t s : b->own) HIP_OK(hipStreamSynchronize(s));
+            int active = 0;
+            for (int i = 0; i < S; ++i)
+                if (!ps[i].done) {
+                    pcg_advance(b->ctx[i], ps[i]);
+                    active += !ps[i].done;
+                }
+            if (active == 0) break;
+        }
+        for (int i = 0; i < S; ++i) {
+            const bido_status e = step_end(b->ctx[i], v[i], u[i], ps[i], &last[i]);
+            tot[i] += last[i].iterations;
+            fb[i] += last[i].fallbacks;
+            max_it = std::max(max_it, last[i].iterations);
+            worst = std::max(worst, last[i].rel_residual);
+            all_conv = all_conv && last[i].converged;
+            if (e && e != BIDO_ERR_NOT_CONVERGED && !err) err = e;
+            if (e == BIDO_ERR_NOT_CONVERGED && !err) err = e;
+        }
+    }
+    for (size_t k = 0; k < b->own.size(); ++k) {
+        HIP_OK(hipEventRecord(b->done[k], b->own[k]));
+        HIP_OK(hipStreamWaitEvent(b->stream, b->done[k], 0));
+        HIP_OK(hipStreamSynchronize(b->own[k]));
+    }
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int64_t all = 0;
+    int all_fb = 0;
+    for (int i = 0; i < S; ++i) {
+        all += tot[i];
+        all_fb += fb[i];
+        if (per_ctx) {
+            per_ctx[i] = last[i];
+            per_ctx[i].total_iterations = tot[i];
+            per_ctx[i].fallbacks = fb[i];
+            per_ctx[i].ms = ms;
+        }
+    }
+    if (total) {
+        std::memset(total, 0, sizeof(*total));
+        total->iterations = max_it;
+        total->converged = all_conv ? 1 : 0;
+        total->rel_residual = worst;
+        total->ms = ms;
+        total->fallbacks = all_fb;
+        total->total_iterations = all;
+    }
+    return err;
+}
 
 bido_status bido_get_info(const bido_ctx* c, bido_info* info) {
     if (!c || !info) return fail(BIDO_ERR_ARG, "null argument");

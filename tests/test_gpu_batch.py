@@ -1,0 +1,87 @@
+"""Batched execution of independent slices (bido_batch_*).
+
+Each slice of a batch runs the same kernels in the same order as on its
+own, with its own PCG scalars, so a batch must reproduce the per-slice runs
+bit for bit; the last step of every slice is also checked against the FP64
+oracle at 1e-8."""
+import numpy as np
+import pytest
+
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _slices():
+    return [w.thorax2d(n_target=3000, seed=31), w.thorax2d(n_target=6000, seed=32, sigma_scale=0.8),
+            w.square2d(n=24, seed=3), w.thorax2d(n_target=1500, seed=33, sigma_scale=1.2)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_matches_single_slices_and_oracle(torch, precision):
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd
+    prec = B.PREC_MIXED if precision == "mixed" else B.PREC_FP64
+    cfgs = _slices()
+    n_steps = 12
+    # reference: each slice alone
+    ref = []
+    for cfg in cfgs:
+        s = B.Solver(cfg, tol=1e-12, precision=prec)
+        v, h, u = s.state()
+        s.run(v, h, u, 0, n_steps)
+        ref.append((v.cpu().numpy(), h.cpu().numpy(), u.cpu().numpy()))
+        s.close()
+    solvers = [B.Solver(cfg, tol=1e-12, precision=prec) for cfg in cfgs]
+    batch = B.Batch(solvers, n_streams=3)
+    states = [s.state() for s in solvers]
+    tot, per = batch.run(states, 0, n_steps - 1)
+    before = [(st[0].cpu().numpy().copy(), st[1].cpu().numpy().copy()) for st in states]
+    tot2, per2 = batch.run(states, n_steps - 1, 1)
+    print(precision, "iterations per slice (last step)", [p["iterations"] for p in per2],
+          "batch max", tot["iterations"], "total", tot["total_iterations"] + tot2["total_iterations"])
+    assert tot["converged"] == 1 and tot2["converged"] == 1
+    for k, (cfg, st) in enumerate(zip(cfgs, states)):
+        v, h, u = [t.cpu().numpy() for t in st]
+        # bit-identical to the slice run on its own
+        assert np.array_equal(v, ref[k][0]) and np.array_equal(h, ref[k][1]) and np.array_equal(u, ref[k][2]), k
+        # last step against the oracle
+        sy = bd.System(cfg)
+        Uo, Vo, _ = sy.step(before[k][0], before[k][1], n_steps - 1)
+        Uo = sy.to_global_u(Uo)
+        eu = np.linalg.norm(u - Uo) / np.linalg.norm(Uo)
+        ev = np.linalg.norm(v - Vo) / np.linalg.norm(Vo)
+        print(f"  slice {k} ({cfg['name']}): e_u {eu:.2e} e_v {ev:.2e}")
+        assert eu <= 1e-8 and ev <= 1e-8
+    batch.close()
+    for s in solvers:
+        s.close()
+
+
+def test_batch_refusals(torch):
+    import paper_1711_08708_amd as B
+    cfgs = _slices()[:2]
+    a, b = [B.Solver(cfg, tol=1e-10) for cfg in cfgs]
+    with pytest.raises(B.BidoError):
+        B.Batch([a, a])                      # listed twice
+    bt = B.Batch([a, b])
+    with pytest.raises(B.BidoError):
+        B.Batch([b])                         # already in a batch
+    a.set_precond(B.PRECOND_LEARNED_ADDITIVE)
+    states = [a.state(), b.state()]
+    with pytest.raises(B.BidoError):
+        bt.run(states, 0, 1)                 # additive learned mode needs host checks
+    bt.close()
+    a.set_precond(B.PRECOND_PLAIN)
+    v, h, u = a.state()
+    a.run(v, h, u, 0, 2)                     # usable on its own again
+    a.close()
+    b.close()
