@@ -44,7 +44,7 @@ def _parse():
                     help="plain steps whose CG iterations provide training pairs")
     ap.add_argument("--variant-steps", type=int, default=50)
     ap.add_argument("--epochs", type=int, default=30)
-    ap.add_argument("--batch-streams", type=int, default=8, help="streams of the batch (batch64)")
+    ap.add_argument("--batch-streams", type=int, default=4, help="streams of the batch (batch64)")
     ap.add_argument("--batch-learned", action="store_true",
                     help="batch64: train the learned stencil of every slice first")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -264,11 +264,23 @@ bido_status bido_gnn_loss_grad(bido_ctx* ctx, const float* that, const float* y,
 bido_status bido_stencil_check(bido_ctx* ctx, const float* zh, const float* bh, float* r, double* loss,
                                float* grad);
 
+/* HIP graphs: bido_step / bido_run / bido_batch_run can replay one captured
+ * graph per PCG iteration (preconditioner apply, direction update, SpMV,
+ * PCG update, copy of the scalars) instead of launching its kernels one by
+ * one; graphs are captured on first use and again after a change of
+ * precision or preconditioner.  on = 1: always, 0: never, -1 (default):
+ * only while the context belongs to a batch (where the many small launches
+ * of its slices make them pay; a single large context runs faster eager).
+ * Steps run on a stream of the context ordered after and before the
+ * caller's stream.  Profiling, sample collection and the additive learned
+ * mode run eagerly.  Results are the same bit for bit either way.        */
+bido_status bido_set_graphs(bido_ctx* ctx, int on);
+
 /* --- batched execution of independent slices ---------------------------- *
  * A batch runs bido_run on many contexts at once (Sec. 3.2 for each slice,
  * each with its own PCG scalars and stopping test).  The contexts keep their
  * settings (precision, preconditioner); while they belong to the batch their
- * launches go to the batch's own streams (n_streams of them, <= 0: up to 8;
+ * launches go to the batch's own streams (n_streams of them, <= 0: up to 4;
  * default priority), packed by size, and the host waits once per PCG phase
  * for all slices.  The contexts must live on the current device, may not be
  * listed twice or belong to another batch (BIDO_ERR_STATE), and must not be

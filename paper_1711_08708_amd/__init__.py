@@ -118,6 +118,7 @@ ABI = {
     "bido_inner_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p]),
     "bido_set_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "bido_set_graphs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_learn_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
                                           ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Stats)]),
@@ -368,6 +369,10 @@ class Solver:
         _check(lib.bido_stencil_check(self.ctx, ctypes.c_void_p(zh.data_ptr()), ctypes.c_void_p(bh.data_ptr()),
                                       ctypes.c_void_p(r.data_ptr()), ctypes.byref(loss), g))
         return r, loss.value, (np.ctypeslib.as_array(g).astype(np.float64).copy() if grad else None)
+
+    def set_graphs(self, on):
+        """True: always replay captured graphs, False: never, None: only in a batch."""
+        _check(lib.bido_set_graphs(self.ctx, -1 if on is None else (1 if on else 0)))
 
     def set_precision(self, precision):
         _check(lib.bido_set_precision(self.ctx, int(precision)))

@@ -284,6 +284,19 @@ struct bido_ctx {
     double* sc_host = nullptr;   // pinned
     unsigned nb_rz = 0;          // partials of r.z written by the latest apply
     bool batched = false;        // owned by a bido_batch (runs on its stream)
+    // HIP graphs of one PCG iteration's launch sequence (preconditioner apply,
+    // direction update, SpMV, PCG update, scalar copy): [0] the first
+    // iteration, [1] and [2] the later ones by the slot of r.z they read
+    hipStream_t work = nullptr;  // capturable stream for bido_run
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int graph_mode = -1;         // 1 on, 0 off, -1 only inside a batch
+    hipGraphExec_t gx[3] = {nullptr, nullptr, nullptr};
+    unsigned gx_nb[3] = {0, 0, 0}, gx_nbrz[3] = {0, 0, 0};
+    const void* gx_key[4] = {nullptr, nullptr, nullptr, nullptr};
+    void drop_graphs() {
+        for (auto& g : gx)
+            if (g) { hipGraphExecDestroy(g); g = nullptr; }
+    }
     Reduce rd;
     int64_t *u_pos = nullptr, *v_pos = nullptr;
     double *m_int = nullptr, *mh_loc = nullptr, *stim_loc = nullptr;
@@ -312,6 +325,10 @@ struct bido_ctx {
         if (sc_host) hipHostFree(sc_host);
         if (ev0) hipEventDestroy(ev0);
         if (ev1) hipEventDestroy(ev1);
+        drop_graphs();
+        if (ev_in) hipEventDestroy(ev_in);
+        if (ev_out) hipEventDestroy(ev_out);
+        if (work) hipStreamDestroy(work);
     }
 };
 
@@ -515,9 +532,82 @@ void pcg_start(bido_ctx* c, PcgRun& ps, double tol) {
     copy_scalars_async(c, PP_YY + 1);
 }
 
+// The launch sequences between two host checks: the first iteration (apply
+// to r0, p = z, update) and a later one (apply, direction update, update).
+void seq_first(bido_ctx* c, PcgRun& ps) {
+    const int64_t n = c->n2;
+    pcg_apply(c, ps, nullptr);
+    PROF(c, K_P_UPDATE, 24.0 * n, launch_p_update(c->stream, n, c->z, c->p, c->sc, c->nb_rz, 1, 0, ps.rho, ps.rho));
+    ps.it = 1;
+    pcg_tail(c, ps);
+}
+void seq_iter(bido_ctx* c, PcgRun& ps) {
+    const int64_t n = c->n2;
+    pcg_apply(c, ps, ps.r_old);
+    // r.z alternates between two slots, so that the direction update never
+    // overwrites the value its other blocks read
+    const int next = ps.rho == S_RHO ? S_RHO_NEW : S_RHO;
+    PROF(c, K_P_UPDATE, 24.0 * n,
+         launch_p_update(c->stream, n, c->z, c->p, c->sc, c->nb_rz, 0, ps.flexible ? 1 : 0, ps.rho, next));
+    ps.rho = next;
+    ++ps.it;
+    pcg_tail(c, ps);
+}
+
+// Replay (capturing it first if needed) the graph of a sequence.  Returns
+// false when the sequence has to run eagerly: graphs off, profiling, sample
+// collection or the additive learned mode (host checks inside the apply),
+// or a stream that cannot be captured.
+bool seq_graph(bido_ctx* c, PcgRun& ps, int variant) {
+    const bool on = c->graph_mode > 0 || (c->graph_mode < 0 && c->batched);
+    if (!on || c->prof.on || c->gnn.collecting || ps.learned || !c->stream || debug_on()) return false;
+    const void* key[4] = {(const void*)(intptr_t)(c->precision + 1), (const void*)(intptr_t)(ps.stencil ? 2 : 1),
+                          c->pk_learned.nodes, ps.r_old};
+    if (!std::equal(key, key + 4, c->gx_key)) {
+        c->drop_graphs();
+        std::copy(key, key + 4, c->gx_key);
+    }
+    if (!c->gx[variant]) {
+        PcgRun tmp = ps;
+        if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            c->graph_mode = 0;
+            return false;
+        }
+        if (variant == 0) seq_first(c, tmp); else seq_iter(c, tmp);
+        hipGraph_t g = nullptr;
+        hipError_t e1 = hipStreamEndCapture(c->stream, &g);
+        hipGraphExec_t x = nullptr;
+        hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&x, g, nullptr, nullptr, 0) : e1;
+        if (g) hipGraphDestroy(g);
+        if (e2 != hipSuccess) {
+            (void)hipGetLastError();
+            c->graph_mode = 0;
+            return false;
+        }
+        c->gx[variant] = x;
+        c->gx_nb[variant] = tmp.nb;
+        c->gx_nbrz[variant] = c->nb_rz;
+    }
+    if (hipGraphLaunch(c->gx[variant], c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        c->drop_graphs();
+        c->graph_mode = 0;
+        return false;
+    }
+    ps.nb = c->gx_nb[variant];
+    c->nb_rz = c->gx_nbrz[variant];
+    if (variant == 0) {
+        ps.it = 1;
+    } else {
+        ps.rho = ps.rho == S_RHO ? S_RHO_NEW : S_RHO;
+        ++ps.it;
+    }
+    return true;
+}
+
 // Decide on the scalars of the latest phase and launch the next one.
 void pcg_advance(bido_ctx* c, PcgRun& ps) {
-    hipStream_t s = c->stream;
     const int64_t n = c->n2;
     auto finish = [&](bool conv, bido_status st, const std::string& msg) {
         ps.done = true;
@@ -525,20 +615,17 @@ void pcg_advance(bido_ctx* c, PcgRun& ps) {
         ps.status = st;
         ps.err = msg;
     };
-    bido_status e;
     if (!ps.started) {
         ps.started = true;
         ps.yy = host_partials(c, PP_YY, ps.nb);
         ps.rel = ps.yy > 0 ? std::sqrt(host_partials(c, PP_RR, ps.nb) / ps.yy) : 0.0;
         if (ps.yy == 0.0) {
-            launch_fill(s, n, c->x, 0.0);
+            launch_fill(c->stream, n, c->x, 0.0);
             return finish(true, BIDO_OK, "");
         }
         if (ps.rel <= ps.tol) return finish(true, BIDO_OK, "");
-        if ((e = pcg_apply(c, ps, nullptr))) return finish(false, e, "device error");
-        PROF(c, K_P_UPDATE, 24.0 * n, launch_p_update(s, n, c->z, c->p, c->sc, c->nb_rz, 1, 0, ps.rho, ps.rho));
-        ps.it = 1;
-        return pcg_tail(c, ps);
+        if (!seq_graph(c, ps, 0)) seq_first(c, ps);
+        return;
     }
     const double pq = c->sc_host[S_PQ], rz = c->sc_host[ps.rho];
     ps.rel = std::sqrt(host_partials(c, PP_RR, ps.nb) / ps.yy);
@@ -548,15 +635,7 @@ void pcg_advance(bido_ctx* c, PcgRun& ps) {
     if (ps.rel <= ps.tol) return finish(true, BIDO_OK, "");
     if (ps.it >= c->params.max_iter)
         return finish(false, BIDO_ERR_NOT_CONVERGED, "tolerance not reached within max_iter");
-    if ((e = pcg_apply(c, ps, ps.r_old))) return finish(false, e, "device error");
-    // r.z alternates between two slots, so that the direction update never
-    // overwrites the value its other blocks read
-    const int next = ps.rho == S_RHO ? S_RHO_NEW : S_RHO;
-    PROF(c, K_P_UPDATE, 24.0 * n,
-         launch_p_update(s, n, c->z, c->p, c->sc, c->nb_rz, 0, ps.flexible ? 1 : 0, ps.rho, next));
-    ps.rho = next;
-    ++ps.it;
-    pcg_tail(c, ps);
+    if (!seq_graph(c, ps, ps.rho == S_RHO ? 1 : 2)) seq_iter(c, ps);
 }
 
 bido_status pcg_result(bido_ctx* c, const PcgRun& ps, bido_stats* st) {
@@ -856,6 +935,9 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     HIP_OK(upload(&c->stim_loc, hs.stim_loc.data(), hs.stim_loc.size()));
     HIP_OK(hipEventCreate(&c->ev0));
     HIP_OK(hipEventCreate(&c->ev1));
+    HIP_OK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    HIP_OK(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
     if ((e = gnn_setup(c.get()))) return e;
     c->precond = params->precond == BIDO_PRECOND_LEARNED_ADDITIVE ? params->precond : BIDO_PRECOND_PLAIN;
     HIP_OK(hipDeviceSynchronize());
@@ -883,6 +965,7 @@ struct bido_batch {
         for (size_t i = 0; i < ctx.size(); ++i) {
             ctx[i]->stream = saved[i];
             ctx[i]->batched = false;
+            ctx[i]->drop_graphs();
         }
         for (hipStream_t s : own) hipStreamDestroy(s);
         for (hipEvent_t e : done) hipEventDestroy(e);
@@ -901,7 +984,7 @@ bido_status bido_batch_create(bido_ctx* const* ctxs, int n_ctx, int n_streams, v
             if (ctxs[j] == ctxs[i]) return fail(BIDO_ERR_ARG, "context listed twice");
     }
     auto b = std::make_unique<bido_batch>();
-    const int K = n_streams > 0 ? std::min(n_streams, n_ctx) : std::min(n_ctx, 8);
+    const int K = n_streams > 0 ? std::min(n_streams, n_ctx) : std::min(n_ctx, 4);
     b->stream = (hipStream_t)stream;
     HIP_OK(hipEventCreateWithFlags(&b->start, hipEventDisableTiming));
     for (int k = 0; k < K; ++k) {
@@ -928,6 +1011,7 @@ bido_status bido_batch_create(bido_ctx* const* ctxs, int n_ctx, int n_streams, v
         b->saved.push_back(ctxs[i]->stream);
         ctxs[i]->stream = b->own[which[i]];
         ctxs[i]->batched = true;
+        ctxs[i]->drop_graphs();
     }
     *out = b.release();
     return BIDO_OK;
@@ -1403,6 +1487,13 @@ bido_status bido_stencil_check(bido_ctx* c, const float* zh, const float* bh, fl
     return BIDO_OK;
 }
 
+bido_status bido_set_graphs(bido_ctx* c, int on) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    c->drop_graphs();
+    c->graph_mode = on < 0 ? -1 : (on != 0);
+    return BIDO_OK;
+}
+
 bido_status bido_set_solver(bido_ctx* c, double tol, int max_iter) {
     if (!c) return fail(BIDO_ERR_ARG, "null context");
     if (tol > 0) c->params.tol = tol;
@@ -1422,6 +1513,14 @@ bido_status bido_run(bido_ctx* c, double* v, double* w, double* u, double dt, in
         return fail(BIDO_ERR_DT_MISMATCH, "dt differs from the factored time step");
     bido_stats local{};
     auto t0 = std::chrono::steady_clock::now();
+    // steps run on the context's own (capturable) stream, ordered after and
+    // before the caller's stream by events
+    hipStream_t user = c->stream;
+    if (!c->batched) {
+        HIP_OK(hipEventRecord(c->ev_in, user));
+        HIP_OK(hipStreamWaitEvent(c->work, c->ev_in, 0));
+        c->stream = c->work;
+    }
     HIP_OK(hipEventRecord(c->ev0, c->stream));
     bido_status e = BIDO_OK;
     int64_t total = 0;
@@ -1433,6 +1532,11 @@ bido_status bido_run(bido_ctx* c, double* v, double* w, double* u, double dt, in
         if (e) break;
     }
     HIP_OK(hipEventRecord(c->ev1, c->stream));
+    if (!c->batched) {
+        c->stream = user;
+        HIP_OK(hipEventRecord(c->ev_out, c->work));
+        HIP_OK(hipStreamWaitEvent(user, c->ev_out, 0));
+    }
     HIP_OK(hipStreamSynchronize(c->stream));
     float ms = 0.f;
     hipEventElapsedTime(&ms, c->ev0, c->ev1);

@@ -32,10 +32,12 @@ def test_batch_matches_single_slices_and_oracle(torch, precision):
     prec = B.PREC_MIXED if precision == "mixed" else B.PREC_FP64
     cfgs = _slices()
     n_steps = 12
-    # reference: each slice alone
+    # reference: each slice alone, every kernel launched eagerly (the batch
+    # replays captured graphs)
     ref = []
     for cfg in cfgs:
         s = B.Solver(cfg, tol=1e-12, precision=prec)
+        s.set_graphs(False)
         v, h, u = s.state()
         s.run(v, h, u, 0, n_steps)
         ref.append((v.cpu().numpy(), h.cpu().numpy(), u.cpu().numpy()))
@@ -85,3 +87,25 @@ def test_batch_refusals(torch):
     a.run(v, h, u, 0, 2)                     # usable on its own again
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replays_match_eager_launches(torch, precision):
+    """The captured per-iteration graphs, replayed many times with eager
+    work (Steps 1 and 3, normalisation) and host waits in between, give the
+    same trajectory bit for bit as launching every kernel eagerly."""
+    import paper_1711_08708_amd as B
+    prec = B.PREC_MIXED if precision == "mixed" else B.PREC_FP64
+    cfg = w.thorax2d(n_target=6000, seed=41)
+    out = []
+    for graphs in (False, True):
+        s = B.Solver(cfg, tol=1e-12, precision=prec)
+        s.set_graphs(graphs)
+        v, h, u = s.state()
+        its = [s.step(v, h, u, n)["iterations"] for n in range(15)]
+        out.append(([t.cpu().numpy() for t in (v, h, u)], its))
+        s.close()
+    print(precision, "iterations", out[1][1])
+    assert out[0][1] == out[1][1]
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
