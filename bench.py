@@ -173,9 +173,10 @@ def main():
         "ms_per_step": round(wall_s * 1e3 / args.steps, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == B.PREC_FP64 else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": f"{cfg['name']}: 2D thorax-like slice, {solver.N} vertices "
-                               f"({solver.NH} heart), semi-implicit bidomain step, block-LU/"
-                               f"monodomain PCG, {args.precision} preconditioner",
+        "config": {"workload": f"{cfg['name']}: " + (
+                       f"2D thorax-like slice, {solver.N} vertices ({solver.NH} heart)" if cfg["dim"] == 2 else
+                       f"3D orthotropic slab, {solver.N} vertices (isolated heart)") +
+                       f", semi-implicit bidomain step, block-LU/monodomain PCG, {args.precision} preconditioner",
                    "n_nodes": solver.N, "n_heart": solver.NH, "dt_ms": cfg["dt"],
                    "tol": args.tol, "eps_h": args.eps, "precision": args.precision,
                    "first_step": n0, "cg_iterations_per_step": round(iters / args.steps, 3),

@@ -83,7 +83,8 @@ bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n
  * Cholesky factor of Sec. 5.3 restricted to the top separators, inverted
  * once at set-up); n_top vertices, `seconds` of host time to invert.
  * top_h = tree height + 1 means no dense top.  The cut comes from a cost
- * model; environment BIDO_TOP_H forces it.                                */
+ * model; environment BIDO_TOP_H forces it (raised as far as the bound of
+ * the top size requires).                                                */
 bido_status bido_host_factor_top(const bido_host* h, int which, int* top_h, int64_t* n_top, double* seconds);
 
 #ifdef __cplusplus

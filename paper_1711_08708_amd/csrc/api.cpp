@@ -101,6 +101,8 @@ struct FactorDev {
     double* ytmp = nullptr;
     TriItem* items = nullptr;
     BwdItem* bitems = nullptr;
+    TriItem* fcomb = nullptr;
+    BwdItem* bcomb = nullptr;
     double* top_inv64 = nullptr;    // dense top S_top^-1 (n_top x n_top)
     float* top_inv32 = nullptr;
     double top_bytes64 = 0, top_bytes32 = 0;
@@ -121,7 +123,8 @@ struct FactorDev {
         hipFree(nodes); hipFree(panel64); hipFree(panel32); hipFree(panel64_cm); hipFree(panel32_cm);
         hipFree(ea); hipFree(bidx);
         hipFree(upd); hipFree(ytmp); hipFree(items); hipFree(bitems);
-        hipFree(plan.sub_nodes); hipFree(plan.sub_hoff); hipFree(plan.scratch); hipFree(plan.counters);
+        hipFree(plan.sub_nodes); hipFree(plan.sub_hoff); hipFree(plan.scratch);
+        hipFree(fcomb); hipFree(bcomb); fcomb = nullptr; bcomb = nullptr;
         hipFree(top_inv64); hipFree(top_inv32); top_inv64 = nullptr; top_inv32 = nullptr;
         hipFree((void*)plan.top_pos); hipFree((void*)plan.top_gptr); hipFree((void*)plan.top_gsrc);
         hipFree(plan.top_w);
@@ -177,8 +180,8 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
     HIP_OK(upload(&fd.plan.sub_nodes, p.sub_nodes.data(), p.sub_nodes.size()));
     HIP_OK(upload(&fd.plan.sub_hoff, p.sub_hoff.data(), p.sub_hoff.size()));
     HIP_OK(hipMalloc((void**)&fd.plan.scratch, std::max<int64_t>(p.scratch_size, 1) * sizeof(double)));
-    HIP_OK(hipMalloc((void**)&fd.plan.counters, std::max(p.n_tiles, 1) * sizeof(unsigned)));
-    HIP_OK(hipMemset(fd.plan.counters, 0, std::max(p.n_tiles, 1) * sizeof(unsigned)));
+    HIP_OK(upload(&fd.fcomb, p.fwd_comb.data(), p.fwd_comb.size()));   // empty: no combine launch
+    HIP_OK(upload(&fd.bcomb, p.bwd_comb.data(), p.bwd_comb.size()));
     HIP_OK(hipMalloc((void**)&fd.upd, std::max<int64_t>(p.upd_size, 1) * sizeof(double)));
     HIP_OK(hipMalloc((void**)&fd.ytmp, std::max<int64_t>(p.n, 1) * sizeof(double)));
     fd.top_h = p.top_h;
@@ -209,6 +212,10 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
         L.n_bwd = (int)sp.nb;
         L.lds_f = sp.lds_f;
         L.lds_b = sp.lds_b;
+        L.fcomb = fd.fcomb + sp.cf0;
+        L.n_fcomb = (int)sp.ncf;
+        L.bcomb = fd.bcomb + sp.cb0;
+        L.n_bcomb = (int)sp.ncb;
         fd.top.push_back(L);
     }
     fd.fwd_bytes64 = p.fwd_bytes64;

@@ -480,8 +480,8 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __rest
 }
 
 // Level phase, forward: item = (64-row tile, column chunk) of one node.  The
-// four waves split the chunk's columns; partial sums over split chunks are
-// combined by the last item of the tile to finish.
+// four waves split the chunk's columns.  A tile split over several chunks
+// leaves its partial sums in scratch for the combine launch of the level.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_tri_fwd_lvl(const TriNode* __restrict__ nodes,
                                                        const TriItem* __restrict__ items,
@@ -490,10 +490,9 @@ __global__ __launch_bounds__(BLOCK) void k_tri_fwd_lvl(const TriNode* __restrict
                                                        const double* __restrict__ b,
                                                        double* __restrict__ y,
                                                        double* upd, int64_t ground,
-                                                       double* scratch, unsigned* counters) {
+                                                       double* __restrict__ scratch) {
     extern __shared__ double w[];
     __shared__ double red[BLOCK / WAVE][FWD_ROWS];
-    __shared__ bool last;
     const TriItem it = items[blockIdx.x];
     const TriNode nd = nodes[it.node];
     const int64_t u0 = child_upd(nodes, nd.child[0]), u1 = child_upd(nodes, nd.child[1]);
@@ -515,37 +514,41 @@ __global__ __launch_bounds__(BLOCK) void k_tri_fwd_lvl(const TriNode* __restrict
     for (int k = 0; k < nw; ++k) tot += red[k][lane];
     if (it.nparts == 1) {
         if (lane < it.nrows) store_row(nd, r, tot, ea, y, upd, u0, u1);
-        return;
+    } else {
+        scratch[it.part + lane] = tot;
     }
-    scratch[it.part + lane] = tot;
-    __threadfence();
-    if (lane == 0) last = atomicAdd(&counters[it.tile], 1u) == (unsigned)(it.nparts - 1);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    if (!last) return;
-    __threadfence();
-    if (lane < it.nrows) {
-        double t = 0.0;
-        for (int k = 0; k < it.nparts; ++k) t += scratch[it.part0 + (int64_t)k * FWD_ROWS + lane];
-        store_row(nd, r, t, ea, y, upd, u0, u1);
-    }
-    if (lane == 0) counters[it.tile] = 0u;
+}
+
+// Combine launch of a forward level: one wave per split tile sums the parts
+// in order (deterministic) and finishes its rows.
+__global__ __launch_bounds__(BLOCK) void k_tri_fwd_comb(const TriNode* __restrict__ nodes,
+                                                        const TriItem* __restrict__ comb, int ncomb,
+                                                        const Ea* __restrict__ ea, double* __restrict__ y,
+                                                        double* upd, const double* __restrict__ scratch) {
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int q = blockIdx.x * (BLOCK / WAVE) + wave;
+    if (q >= ncomb) return;
+    const TriItem it = comb[q];
+    if (lane >= it.nrows) return;
+    const TriNode nd = nodes[it.node];
+    const int64_t u0 = child_upd(nodes, nd.child[0]), u1 = child_upd(nodes, nd.child[1]);
+    double t = 0.0;
+    for (int k = 0; k < it.nparts; ++k) t += scratch[it.part0 + (int64_t)k * FWD_ROWS + lane];
+    store_row(nd, it.r0 + lane, t, ea, y, upd, u0, u1);
 }
 
 // Level phase, backward: item = (column tile, row range) of one node; z for
-// the row range is staged in LDS first.
+// the row range is staged in LDS first.  A tile split over several row
+// ranges leaves its partial sums in scratch for the combine launch.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_tri_bwd_lvl(const TriNode* __restrict__ nodes,
                                                        const BwdItem* __restrict__ items,
                                                        const T* __restrict__ panel,
                                                        const int64_t* __restrict__ bidx,
                                                        const double* __restrict__ y,
-                                                       double* x, double* scratch,
-                                                       unsigned* counters) {
+                                                       double* x, double* __restrict__ scratch) {
     extern __shared__ double z[];
     __shared__ double red[BLOCK];
-    __shared__ bool last;
     const BwdItem it = items[blockIdx.x];
     const TriNode nd = nodes[it.node];
     const int nI = nd.nI;
@@ -561,26 +564,27 @@ __global__ __launch_bounds__(BLOCK) void k_tri_bwd_lvl(const TriNode* __restrict
     if (col < it.ncols) acc = col_part<T>(P, nI, c, max(it.rs, it.c0) + st, it.re, S, z, it.rs);
     red[threadIdx.x] = acc;
     __syncthreads();
+    if (threadIdx.x >= W) return;
     double s = 0.0;
-    if (threadIdx.x < W)
-        for (int k = 0; k < S; ++k) s += red[k * W + threadIdx.x];
+    for (int k = 0; k < S; ++k) s += red[k * W + threadIdx.x];
     if (it.nparts == 1) {
         if (threadIdx.x < it.ncols) x[nd.off + c] = s;
-        return;
+    } else {
+        scratch[it.part + threadIdx.x] = s;
     }
-    if (threadIdx.x < W) scratch[it.part + threadIdx.x] = s;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&counters[it.tile], 1u) == (unsigned)(it.nparts - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (threadIdx.x < it.ncols) {
-        double t = 0.0;
-        for (int k = 0; k < it.nparts; ++k) t += scratch[it.part0 + (int64_t)k * W + threadIdx.x];
-        x[nd.off + c] = t;
-    }
-    if (threadIdx.x == 0) counters[it.tile] = 0u;
+}
+
+// Combine launch of a backward level: one wave per split column tile.
+__global__ __launch_bounds__(WAVE) void k_tri_bwd_comb(const TriNode* __restrict__ nodes,
+                                                       const BwdItem* __restrict__ comb,
+                                                       double* __restrict__ x, const double* __restrict__ scratch) {
+    const BwdItem it = comb[blockIdx.x];
+    const int col = threadIdx.x;
+    if (col >= it.ncols) return;
+    const TriNode nd = nodes[it.node];
+    double t = 0.0;
+    for (int k = 0; k < it.nparts; ++k) t += scratch[it.part0 + (int64_t)k * it.W + col];
+    x[nd.off + it.c0 + col] = t;
 }
 
 // Dense top: w_top[k] = b[pos[k]] - sum of the bottom roots' updates at k.
@@ -738,14 +742,17 @@ void launch_tri_fwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, c
                         const T* panel_cm, const Ea* ea, const double* b, double* y, double* upd,
                         int64_t ground) {
     if (L.n_fwd == 0) return;
-    k_tri_fwd_lvl<T><<<L.n_fwd, BLOCK, L.lds_f, s>>>(nodes, L.fwd, panel_cm, ea, b, y, upd, ground,
-                                                     P.scratch, P.counters);
+    k_tri_fwd_lvl<T><<<L.n_fwd, BLOCK, L.lds_f, s>>>(nodes, L.fwd, panel_cm, ea, b, y, upd, ground, P.scratch);
+    if (L.n_fcomb > 0)
+        k_tri_fwd_comb<<<(L.n_fcomb + BLOCK / WAVE - 1) / (BLOCK / WAVE), BLOCK, 0, s>>>(nodes, L.fcomb, L.n_fcomb,
+                                                                                       ea, y, upd, P.scratch);
 }
 template <typename T>
 void launch_tri_bwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
                         const T* panel, const int64_t* bidx, const double* y, double* x) {
     if (L.n_bwd == 0) return;
-    k_tri_bwd_lvl<T><<<L.n_bwd, BLOCK, L.lds_b, s>>>(nodes, L.bwd, panel, bidx, y, x, P.scratch, P.counters);
+    k_tri_bwd_lvl<T><<<L.n_bwd, BLOCK, L.lds_b, s>>>(nodes, L.bwd, panel, bidx, y, x, P.scratch);
+    if (L.n_bcomb > 0) k_tri_bwd_comb<<<L.n_bcomb, WAVE, 0, s>>>(nodes, L.bcomb, x, P.scratch);
 }
 
 #define BIDO_INST(T)                                                                                   \

@@ -37,6 +37,10 @@ struct TriTopLevel {
     int n_bwd = 0;
     size_t lds_f = 0;         // forward: max column chunk * 8
     size_t lds_b = 0;         // backward: max staged rows * 8
+    TriItem* fcomb = nullptr; // device: split forward tiles (combine launch)
+    int n_fcomb = 0;
+    BwdItem* bcomb = nullptr; // device: split backward tiles
+    int n_bcomb = 0;
 };
 struct TriPlan {
     int hc = -1;                  // subtree cut height (-1: no subtree phase)
@@ -44,8 +48,7 @@ struct TriPlan {
     int32_t* sub_nodes = nullptr; // device: node ids grouped by subtree, by height
     int32_t* sub_hoff = nullptr;  // device: n_sub x (hc+2) height offsets
     int sub_maxw = 0;             // max nI below the cut
-    double* scratch = nullptr;    // backward partial sums
-    unsigned* counters = nullptr; // backward tile counters (zero between launches)
+    double* scratch = nullptr;    // partial sums of split tiles
     // dense top (n_top = 0: none): x[top_pos] = S_top^-1 w_top
     int64_t n_top = 0;
     const int64_t* top_pos = nullptr;

@@ -291,7 +291,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads)
     // cut (a value above the tree height switches the dense top off).
     {
         constexpr double T_FWD = 10e-6, T_BWD = 25e-6, BW_LVL = 2.0e12, T_TOP = 10e-6, BW_TOP = 4.5e12;
-        int best = H + 1;
+        int best = H + 1, lowest = H + 1;
         double best_cost = 0.0, saved = 0.0;
         int64_t cum = 0;
         for (int h = H; h > hc; --h) {
@@ -302,12 +302,14 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads)
                              (double)f.fronts[id].nB * f.fronts[id].nI);
             }
             if (cum > PLAN_TOP_MAX) break;
+            lowest = h;
             saved += std::max(T_FWD, pb / BW_LVL) + std::max(T_BWD, pb / BW_LVL);
             const double cost = T_TOP + 8.0 * (double)cum * (double)cum / BW_TOP - saved;
             if (cost < best_cost) { best_cost = cost; best = h; }
         }
+        // a forced cut is raised as far as the top-size bound requires
         const char* e = std::getenv("BIDO_TOP_H");
-        if (e && *e) best = std::max(hc + 1, std::min(H + 1, std::atoi(e)));
+        if (e && *e) best = std::max(lowest, std::min(H + 1, std::atoi(e)));
         p.top_h = best;
     }
     const int top_h = p.top_h;
@@ -355,11 +357,11 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads)
     // (environment BIDO_FWD_COLS, BIDO_BWD_MAXR) within the LDS staging bound.
     const int fwd_cols = env_limit("BIDO_FWD_COLS", PLAN_FWD_COLS, 32, PLAN_LDS_DOUBLES);
     const int bwd_maxr = env_limit("BIDO_BWD_MAXR", PLAN_BWD_MAXR, 64, PLAN_LDS_DOUBLES);
-    std::vector<std::pair<size_t, size_t>> fspan, bspan;
+    std::vector<std::pair<size_t, size_t>> fspan, bspan, fcspan, bcspan;
     struct LdsSz { size_t f, b; };
     std::vector<LdsSz> lds;
     for (int h = hc + 1; h < top_h; ++h) {
-        const size_t f0 = p.fwd_items.size();
+        const size_t f0 = p.fwd_items.size(), fc0 = p.fwd_comb.size();
         size_t ldsf = 0;
         for (int id : by_h[h]) {
             const Front& fr = f.fronts[id];
@@ -383,6 +385,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads)
                     it.part = part0 + (int64_t)k * PLAN_FWD_ROWS;
                     it.part0 = part0;
                     p.fwd_items.push_back(it);
+                    if (k == 0 && nparts > 1) p.fwd_comb.push_back(it);
                     ldsf = std::max(ldsf, (size_t)(it.ce - it.cs) * sizeof(double));
                 }
                 if (nparts > 1) p.scratch_size += (int64_t)nparts * PLAN_FWD_ROWS;
@@ -390,10 +393,11 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads)
             }
         }
         fspan.push_back({f0, p.fwd_items.size() - f0});
+        fcspan.push_back({fc0, p.fwd_comb.size() - fc0});
         lds.push_back({ldsf, 0});
     }
     for (int h = hc + 1; h < top_h; ++h) {
-        const size_t b0 = p.bwd_items.size();
+        const size_t b0 = p.bwd_items.size(), bc0 = p.bwd_comb.size();
         size_t ldsb = 0;
         for (int id : by_h[h]) {
             const Front& fr = f.fronts[id];
@@ -417,6 +421,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads)
                     b.part = part0 + (int64_t)k * W;
                     b.part0 = part0;
                     p.bwd_items.push_back(b);
+                    if (k == 0 && nparts > 1) p.bwd_comb.push_back(b);
                     ldsb = std::max(ldsb, (size_t)(b.re - b.rs) * sizeof(double));
                 }
                 if (nparts > 1) p.scratch_size += (int64_t)nparts * W;
@@ -424,11 +429,13 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads)
             }
         }
         bspan.push_back({b0, p.bwd_items.size() - b0});
+        bcspan.push_back({bc0, p.bwd_comb.size() - bc0});
         lds[h - hc - 1].b = ldsb;
     }
     for (size_t k = 0; k < fspan.size(); ++k)
         p.spans.push_back({fspan[k].first, fspan[k].second, bspan[k].first, bspan[k].second,
-                           lds[k].f, lds[k].b});
+                           lds[k].f, lds[k].b, fcspan[k].first, fcspan[k].second, bcspan[k].first,
+                           bcspan[k].second});
 
     // ---- algorithmic bytes per height ------------------------------------------
     p.fwd_bytes64.assign(H + 1, 0.0);
@@ -475,11 +482,9 @@ struct Emu {
     const FactorPlan& p;
     const double* b;
     std::vector<double> y, upd, x, scratch;
-    std::vector<unsigned> counters;
     explicit Emu(const FactorPlan& pl, const double* bb)
         : p(pl), b(bb), y(pl.n, std::nan("")), upd(std::max<int64_t>(pl.upd_size, 1), std::nan("")),
-          x(pl.n, std::nan("")), scratch(std::max<int64_t>(pl.scratch_size, 1), std::nan("")),
-          counters(std::max(pl.n_tiles, 1), 0u) {}
+          x(pl.n, std::nan("")), scratch(std::max<int64_t>(pl.scratch_size, 1), std::nan("")) {}
 
     int64_t upd_of(int child) const { return child >= 0 ? p.nodes.at(child).upd : 0; }
 
@@ -571,13 +576,15 @@ struct Emu {
                 continue;
             }
             for (int l = 0; l < PLAN_FWD_ROWS; ++l) scratch.at(it.part + l) = s[l];
-            if (++counters.at(it.tile) == (unsigned)it.nparts) {
-                for (int l = 0; l < it.nrows; ++l) {
-                    double t = 0.0;
-                    for (int k = 0; k < it.nparts; ++k) t += scratch.at(it.part0 + (int64_t)k * PLAN_FWD_ROWS + l);
-                    store_row(nd, it.r0 + l, t);
-                }
-                counters.at(it.tile) = 0;
+        }
+        // combine launch: one entry per split tile
+        for (size_t q = sp.cf0; q < sp.cf0 + sp.ncf; ++q) {
+            const TriItem it = p.fwd_comb.at(q);
+            const TriNode& nd = p.nodes.at(it.node);
+            for (int l = 0; l < it.nrows; ++l) {
+                double t = 0.0;
+                for (int k = 0; k < it.nparts; ++k) t += scratch.at(it.part0 + (int64_t)k * PLAN_FWD_ROWS + l);
+                store_row(nd, it.r0 + l, t);
             }
         }
     }
@@ -613,13 +620,14 @@ struct Emu {
                 continue;
             }
             for (int col = 0; col < it.W; ++col) scratch.at(it.part + col) = s[col];
-            if (++counters.at(it.tile) == (unsigned)it.nparts) {
-                for (int col = 0; col < it.ncols; ++col) {
-                    double t = 0.0;
-                    for (int k = 0; k < it.nparts; ++k) t += scratch.at(it.part0 + (int64_t)k * it.W + col);
-                    x.at(nd.off + it.c0 + col) = t;
-                }
-                counters.at(it.tile) = 0;
+        }
+        for (size_t q = sp.cb0; q < sp.cb0 + sp.ncb; ++q) {
+            const BwdItem it = p.bwd_comb.at(q);
+            const TriNode& nd = p.nodes.at(it.node);
+            for (int col = 0; col < it.ncols; ++col) {
+                double t = 0.0;
+                for (int k = 0; k < it.nparts; ++k) t += scratch.at(it.part0 + (int64_t)k * it.W + col);
+                x.at(nd.off + it.c0 + col) = t;
             }
         }
     }

@@ -26,10 +26,14 @@ struct FactorPlan {
     // level phases (heights hc+1 .. height)
     std::vector<TriItem> fwd_items;
     std::vector<BwdItem> bwd_items;
-    struct Span { size_t f0, nf, b0, nb, lds_f, lds_b; };
+    // split tiles (more than one item) are summed by a combine launch after
+    // their level: one entry (the tile's first item) per split tile
+    std::vector<TriItem> fwd_comb;
+    std::vector<BwdItem> bwd_comb;
+    struct Span { size_t f0, nf, b0, nb, lds_f, lds_b, cf0, ncf, cb0, ncb; };
     std::vector<Span> spans;
     int64_t scratch_size = 0;           // partial sums of split tiles
-    int n_tiles = 0;                    // completion counters (forward + backward)
+    int n_tiles = 0;                    // tiles (forward + backward)
     // dense top: the nodes of height >= top_h are replaced by x_top = S_top^-1 w_top,
     // S_top the Schur complement of their vertices (top_h = height + 1: none)
     int top_h = 0;

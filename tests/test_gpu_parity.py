@@ -65,7 +65,8 @@ def _check_solve(torch, cfg, method="auto", **params):
     lambda: w.square2d(n=48),           # the 2,401-vertex square (ragged leaves)
     lambda: w.thorax2d(n_target=3000, seed=11),
     lambda: w.slab3d(n=6),
-], ids=["square5", "square48", "thorax3000", "slab6"])
+    lambda: w.slab3d(n=14),             # 3,375 vertices: oracle by Jacobi-CG
+], ids=["square5", "square48", "thorax3000", "slab6", "slab14"])
 def test_solve_parity_exact_factor(torch, mk):
     _check_solve(torch, mk(), eps_h=0.0, tol=1e-12)
 
@@ -120,6 +121,49 @@ def test_thorax200k_solve_parity(torch):
     """Full-size thorax slice (about 200k vertices): the normalised solution
     of one step's system matches the oracle's sparse direct solve."""
     _check_solve(torch, w.make_config("thorax200k"), eps_h=0.0, tol=1e-12)
+
+
+def test_slab64_full_size_residual(torch):
+    """Full-size 3D slab (274,625 vertices, mixed precision as in its
+    configuration): the GPU step's solution satisfies the linear system to
+    the requested tolerance when its residual is recomputed on the host
+    with Lambda from the set-up (an independent SciPy product), and U is
+    normalised ((M U, 1) = 0)."""
+    import scipy.sparse as sp
+    import paper_1711_08708_amd as B
+    cfg = w.make_config("slab64")
+    solver = B.Solver(cfg, eps_h=0.0, tol=1e-10, precision=B.PREC_MIXED)
+    hs = B.HostSetup(cfg)
+    rng = np.random.default_rng(5)
+    N, NH = solver.N, solver.NH
+    v0 = rng.uniform(0, 100, NH)
+    h0 = rng.uniform(0, 1, NH)
+    v = torch.tensor(v0, device="cuda")
+    h = torch.tensor(h0, device="cuda")
+    u = torch.zeros(N, dtype=torch.float64, device="cuda")
+    st = solver.step(v, h, u, 0)
+    print("slab64 mixed step:", st)
+    assert st["converged"] == 1
+    # right-hand side of Step 1 from the host vectors (internal order)
+    upos, vpos = hs.index(B.IDX_UPOS), hs.index(B.IDX_VPOS)
+    L = hs.csr(B.MAT_LAMBDA)
+    mh = hs.vec(B.VEC_MH)
+    gamma = cfg["chi"] * cfg["cm"] / cfg["dt"]
+    vt = v0 / 100.0
+    iion = cfg["cm"] * 100.0 * (-h0 * vt * vt * (1 - vt) / 0.3 + vt / 6.0)
+    ist = cfg["stim_amp"] * cfg["stim_mask"][solver.heart_nodes].astype(float)
+    Y = np.zeros(N + NH)
+    Y[N + vpos] = mh * (gamma * v0 - cfg["chi"] * (iion - ist))
+    X = np.zeros(N + NH)
+    X[upos] = u.cpu().numpy()
+    X[N + vpos] = v.cpu().numpy()
+    rel = np.linalg.norm(L @ X - Y) / np.linalg.norm(Y)
+    m = hs.vec(B.VEC_M)                    # global numbering, as u
+    ug = u.cpu().numpy()
+    mean = (m * ug).sum() / m.sum()
+    print(f"host residual {rel:.2e}, (M U,1)/(M 1,1) = {mean:.2e}")
+    assert rel <= 1e-9
+    assert abs(mean) <= 1e-12 * np.abs(ug).max()
 
 
 def test_range_and_dt_errors(torch):

@@ -49,3 +49,32 @@ def test_inner_solve_matches_host(torch, name, which):
     print(f"  max rel diff {err:.2e}", flush=True)
     assert np.isfinite(x).all()
     assert err < 1e-12
+
+
+@pytest.mark.parametrize("name", ["thorax40k", "slab10", "square48"])
+@pytest.mark.parametrize("which", [0, 1])
+def test_dense_top_at_lowest_cut(torch, name, which, monkeypatch):
+    """The dense top forced down to the lowest cut it can take (every level
+    phase replaced, or as many as fit the top-size bound) still reproduces
+    the host factor on the device."""
+    import paper_1711_08708_amd as B
+    cfg = CASES[name]()
+    hs = B.HostSetup(cfg, eps_h=0.0)
+    hc = hs.factor_plan(which)["hc"]
+    H = hs.factor_stats(which)["height"]
+    monkeypatch.setenv("BIDO_TOP_H", str(hc + 1))   # raised to the lowest admissible cut
+    top = hs.factor_top(which)
+    cut = top["top_h"]
+    if cut > H:
+        pytest.skip("no admissible dense top")
+    print(f"{name} factor {which}: cut {cut} (hc {hc}, height {H}), n_top {top['n_top']}", flush=True)
+    solver = B.Solver(cfg, eps_h=0.0)        # plans are built with the forced cut
+    n = solver.N if which == 0 else solver.NH
+    b = np.random.default_rng(2).normal(size=n)
+    ref = hs.factor_apply(which, b)
+    xd = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    solver.inner_solve(which, torch.tensor(b, device="cuda"), xd)
+    x = xd.cpu().numpy()
+    err = np.abs(x - ref).max() / np.abs(ref).max()
+    print(f"  max rel diff {err:.2e}", flush=True)
+    assert np.isfinite(x).all() and err < 1e-12
