@@ -381,23 +381,48 @@ __device__ __forceinline__ double row_part(const T* __restrict__ Pc, int nI, int
     return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
+// Offset of row r in a packed row-major panel, in 32-bit arithmetic (a
+// single node's panel stays far below 2^31 entries).
+__device__ __forceinline__ int row_off32(int r, int nI) {
+    return r < nI ? (r * (r + 1)) >> 1 : ((nI * (nI + 1)) >> 1) + (r - nI) * nI;
+}
+
 // sum over rows r = r0, r0+S, ... < re of P(r, c) z[r - z0] (row-major copy),
 // skipping the unstored entries c > r of the triangle.  All lanes of a wave
-// walk the same rows, so each row is read as one contiguous segment.
+// walk the same rows, so each row is read as one contiguous segment.  S is a
+// power of two (2^lgS); row offsets advance by additions only: in the
+// triangle off(r+S) = off(r) + S r + S(S+1)/2, below it off(r+S) = off(r) + S nI.
 template <typename T>
 __device__ __forceinline__ double col_part(const T* __restrict__ P, int nI, int c, int r0, int re, int S,
                                            const double* z, int z0) {
+    const int lgS = __ffs(S) - 1;
+    const int SS = (S * (S + 1)) >> 1;
     double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int r = r0;
-    for (; r + 7 * S < re; r += 8 * S) {
+    int off = row_off32(r, nI);
+    const int te = min(re, nI);
+    for (; r + 7 * S < te; r += 8 * S) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int rr = r + k * S;
-            if (rr >= nI || c <= rr) a[k] += (double)P[panel_row_off(rr, nI) + c] * z[rr - z0];
+        for (int q = 0; q < 8; ++q) {
+            const int rr = r + q * S;
+            if (c <= rr) a[q] += (double)P[off + c] * z[rr - z0];
+            off = rr + S <= nI ? off + (rr << lgS) + SS : row_off32(rr + S, nI);
         }
     }
-    for (int k = 0; r < re; r += S, ++k)
-        if (r >= nI || c <= r) a[k] += (double)P[panel_row_off(r, nI) + c] * z[r - z0];
+    for (; r < te; r += S) {
+        if (c <= r) a[0] += (double)P[off + c] * z[r - z0];
+        off = r + S <= nI ? off + (r << lgS) + SS : row_off32(r + S, nI);
+    }
+    const int step = S * nI;
+    for (; r + 7 * S < re; r += 8 * S) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] += (double)P[off + q * step + c] * z[r + q * S - z0];
+        off += 8 * step;
+    }
+    for (; r < re; r += S) {
+        a[1] += (double)P[off + c] * z[r - z0];
+        off += step;
+    }
     return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
