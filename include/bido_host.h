@@ -84,8 +84,13 @@ bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n
  * once at set-up); n_top vertices, `seconds` of host time to invert.
  * top_h = tree height + 1 means no dense top.  The cut comes from a cost
  * model; environment BIDO_TOP_H forces it (raised as far as the bound of
- * the top size requires).                                                */
-bido_status bido_host_factor_top(const bido_host* h, int which, int* top_h, int64_t* n_top, double* seconds);
+ * the top size requires).  With eps_h > 0 the inverse is held in
+ * hierarchical low-rank form (the top vertices in geometric bisection
+ * order, off-diagonal blocks truncated by rank-revealing QR at relative
+ * accuracy eps_h, Sec. 5.3): stored_entries counts its values, max_rank its
+ * largest block rank (-1 when dense).                                    */
+bido_status bido_host_factor_top(const bido_host* h, int which, int* top_h, int64_t* n_top, double* seconds,
+                                 int64_t* stored_entries, int* max_rank);
 
 #ifdef __cplusplus
 }

@@ -165,7 +165,7 @@ ABI = {
                                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                              _c_i64_p, _c_i64_p]),
     "bido_host_factor_top": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _c_i64_p,
-                                            ctypes.POINTER(ctypes.c_double)]),
+                                            ctypes.POINTER(ctypes.c_double), _c_i64_p, ctypes.POINTER(ctypes.c_int)]),
     "bido_host_factor_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p,
                                               _c_double_p]),
 }
@@ -523,9 +523,11 @@ class HostSetup:
 
     def factor_top(self, which):
         th, nt, sec = ctypes.c_int(), ctypes.c_int64(), ctypes.c_double()
-        _check(lib.bido_host_factor_top(self.h, which, ctypes.byref(th), ctypes.byref(nt), ctypes.byref(sec)),
-               host=True)
-        return dict(top_h=th.value, n_top=nt.value, seconds=sec.value)
+        st, mr = ctypes.c_int64(), ctypes.c_int()
+        _check(lib.bido_host_factor_top(self.h, which, ctypes.byref(th), ctypes.byref(nt), ctypes.byref(sec),
+                                        ctypes.byref(st), ctypes.byref(mr)), host=True)
+        return dict(top_h=th.value, n_top=nt.value, seconds=sec.value, stored_entries=st.value,
+                    max_rank=mr.value)
 
     def factor_apply(self, which, b):
         b = _arr(b, np.float64)

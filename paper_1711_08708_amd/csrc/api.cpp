@@ -126,6 +126,8 @@ struct FactorDev {
         hipFree(plan.sub_nodes); hipFree(plan.sub_hoff); hipFree(plan.scratch);
         hipFree(fcomb); hipFree(bcomb); fcomb = nullptr; bcomb = nullptr;
         hipFree(top_inv64); hipFree(top_inv32); top_inv64 = nullptr; top_inv32 = nullptr;
+        hipFree((void*)plan.hblocks); hipFree((void*)plan.hleaves); hipFree((void*)plan.hanc);
+        hipFree((void*)plan.hcols); hipFree(plan.ht);
         hipFree((void*)plan.top_pos); hipFree((void*)plan.top_gptr); hipFree((void*)plan.top_gsrc);
         hipFree(plan.top_w);
         nodes = nullptr; panel64 = nullptr; panel32 = nullptr; panel64_cm = nullptr; panel32_cm = nullptr;
@@ -194,14 +196,29 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
         HIP_OK(upload(&gsrc, p.top_gsrc.data(), p.top_gsrc.size()));
         fd.plan.top_pos = pos; fd.plan.top_gptr = gptr; fd.plan.top_gsrc = gsrc;
         HIP_OK(hipMalloc((void**)&fd.plan.top_w, p.n_top * sizeof(double)));
-        HIP_OK(upload(&fd.top_inv64, p.top_inv.data(), p.top_inv.size()));
+        const std::vector<double>& vals = p.top_hodlr ? p.hodlr.val : p.top_inv;
+        HIP_OK(upload(&fd.top_inv64, vals.data(), vals.size()));
         if (want32) {
-            std::vector<float> i32(p.top_inv.begin(), p.top_inv.end());
+            std::vector<float> i32(vals.begin(), vals.end());
             HIP_OK(upload(&fd.top_inv32, i32.data(), i32.size()));
         }
-        const double nt = (double)p.n_top, vec = 8.0 * (3 * nt) + 16.0 * (double)p.top_gsrc.size();
-        fd.top_bytes64 = 8.0 * nt * nt + vec;
-        fd.top_bytes32 = 4.0 * nt * nt + vec;
+        double vec = 8.0 * (3.0 * p.n_top) + 16.0 * (double)p.top_gsrc.size();
+        if (p.top_hodlr) {
+            const Hodlr& hd = p.hodlr;
+            HodlrBlock* hb = nullptr; HodlrLeaf* hl = nullptr; int32_t* ha = nullptr; int32_t* hc = nullptr;
+            HIP_OK(upload(&hb, hd.blocks.data(), hd.blocks.size()));
+            HIP_OK(upload(&hl, hd.leaves.data(), hd.leaves.size()));
+            HIP_OK(upload(&ha, hd.anc.data(), hd.anc.size()));
+            HIP_OK(upload(&hc, p.hodlr_cols.data(), p.hodlr_cols.size()));
+            fd.plan.hblocks = hb; fd.plan.hleaves = hl; fd.plan.hanc = ha; fd.plan.hcols = hc;
+            fd.plan.n_hblocks = (int)hd.blocks.size();
+            fd.plan.n_hleaves = (int)hd.leaves.size();
+            fd.plan.n_hcols = (int)p.hodlr_cols.size();
+            HIP_OK(hipMalloc((void**)&fd.plan.ht, hd.t_size * sizeof(double)));
+            vec += 8.0 * 2.0 * (double)hd.t_size;
+        }
+        fd.top_bytes64 = 8.0 * (double)vals.size() + vec;
+        fd.top_bytes32 = 4.0 * (double)vals.size() + vec;
     }
     fd.top.clear();
     for (const auto& sp : p.spans) {

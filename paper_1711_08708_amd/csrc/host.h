@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+#include "kernels.h"
+
 namespace bido {
 
 // Compressed sparse rows with int64 row pointers and int32 columns.
@@ -111,6 +113,10 @@ struct Factor {
     int64_t ground = -1;             // grounded index (new order) or -1
     NdTree tree;
     std::vector<Front> fronts;       // indexed like tree.nodes
+    // hierarchical compression (eps = 0: exact); vertex coordinates in tree order
+    double eps = 0.0, eta = 2.0;
+    int dim = 0;
+    std::vector<double> xyz;
     int64_t dense_entries() const;
     int64_t stored_entries() const;  // after compression
     int64_t n_lowrank() const;
@@ -121,10 +127,32 @@ struct Factor {
 bool multifrontal(const Csr& a, Factor& f, int64_t ground, int n_threads,
                   std::string& err);
 
-// Hierarchical compression of every panel at relative accuracy eps with
-// admissibility parameter eta, using the vertex coordinates (tree order).
+// Record the compression accuracy eps and the vertex coordinates (tree order)
+// of a factor; the execution plan then holds the inverse of the top
+// separators' Schur complement in hierarchical low-rank form at eps.
 void compress(Factor& f, const double* xyz, int dim, double eps, double eta,
               int n_threads);
+
+// Rank-revealing QR truncation: B (m x n row-major, leading dimension ld)
+// ~ U V^T, U (m x k) and V (n x k) column-major, stopping at the first pivot
+// below eps times the first one.
+void rrqr_lowrank(const double* B, int64_t ld, int m, int n, double eps, std::vector<double>& U,
+                  std::vector<double>& V, int& k);
+
+struct Hodlr {
+    int64_t n = 0, t_size = 1;
+    int max_rank = 0;
+    std::vector<HodlrBlock> blocks;
+    std::vector<HodlrLeaf> leaves;
+    std::vector<int32_t> anc;
+    std::vector<double> val;
+};
+// Recursive geometric bisection order of n points (leaves of <= leaf points).
+void hodlr_order(int64_t n, const double* xyz, int dim, int leaf, std::vector<int64_t>& ord);
+// Hierarchical form of the symmetric n x n row-major A (bisection order).
+void hodlr_build(const std::vector<double>& A, int64_t n, double eps, int leaf, int n_threads, Hodlr& h);
+// y = A w from the hierarchical form.
+void hodlr_apply(const Hodlr& h, const double* w, double* y);
 
 // Host application of the factor (test hook): x = (L L^T)^-1 b with the
 // grounded entry fixed to zero.  Uses the compressed form when present.

@@ -150,7 +150,8 @@ bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n
     return BIDO_OK;
 }
 
-bido_status bido_host_factor_top(const bido_host* h, int which, int* top_h, int64_t* n_top, double* seconds) {
+bido_status bido_host_factor_top(const bido_host* h, int which, int* top_h, int64_t* n_top, double* seconds,
+                                 int64_t* stored_entries, int* max_rank) {
     if (!h) return hfail(BIDO_ERR_ARG, "null argument");
     const bido::Factor* f = which == BIDO_FACTOR_P1 ? &h->hs.p1 : which == BIDO_FACTOR_PK ? &h->hs.pk : nullptr;
     if (!f) return hfail(BIDO_ERR_ARG, "unknown factor");
@@ -160,6 +161,8 @@ bido_status bido_host_factor_top(const bido_host* h, int which, int* top_h, int6
     if (top_h) *top_h = p.top_h;
     if (n_top) *n_top = p.n_top;
     if (seconds) *seconds = p.top_seconds;
+    if (stored_entries) *stored_entries = p.top_hodlr ? (int64_t)p.hodlr.val.size() : p.n_top * p.n_top;
+    if (max_rank) *max_rank = p.top_hodlr ? p.hodlr.max_rank : -1;
     return BIDO_OK;
 }
 

@@ -56,6 +56,24 @@ struct BwdItem {
     int64_t part0;       // scratch offset of the tile's first part
 };
 
+// Hierarchical (off-diagonal low-rank) form of a symmetric matrix in a
+// bisection order: block b couples rows [a, m) with columns [m, e) as
+// U V^T (U: (m-a) x k, V: (e-m) x k, both column-major at offsets u, v of the
+// value array); its transpose couples [m, e) with [a, m).  t is the offset
+// of the block's projections V^T w[m:e) and U^T w[a:m) (k each).
+struct HodlrBlock {
+    int32_t a, m, e, k;
+    int64_t u, v;
+    int32_t t, pad;
+};
+// Leaf rows [a, e): dense diagonal block (column-major at offset d) and the
+// list anc[anc .. anc+nanc) of its ancestor blocks, each coded 2*block +
+// (1 if the leaf lies in the block's second half).
+struct HodlrLeaf {
+    int32_t a, e, nanc, anc;
+    int64_t d;
+};
+
 // Scalars of the PCG recurrences, resident on the device.
 enum ScalarSlot {
     S_RHO = 0,      // r^T z of the current search direction

@@ -650,6 +650,88 @@ __global__ __launch_bounds__(BLOCK) void k_top_gemv(int64_t n, const T* __restri
     if (lane == 0) x[pos[row]] = s;
 }
 
+// Hierarchical top, projections: one wave per column of every block,
+// t[b.t + j] = V[:, j]^T w[m:e) (j < k) or U[:, j-k]^T w[a:m).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_hodlr_proj(const HodlrBlock* __restrict__ blocks,
+                                                      const int32_t* __restrict__ cols, int ncols,
+                                                      const T* __restrict__ val, const double* __restrict__ w,
+                                                      double* __restrict__ t) {
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int q = blockIdx.x * (BLOCK / WAVE) + wave;
+    if (q >= ncols) return;
+    const int code = cols[q];
+    const HodlrBlock b = blocks[code >> 16];
+    const int j = code & 0xffff;
+    const bool first = j < b.k;
+    const int len = first ? b.e - b.m : b.m - b.a;
+    const T* col = val + (first ? b.v : b.u) + (int64_t)(first ? j : j - b.k) * len;
+    const double* ws = w + (first ? b.m : b.a);
+    double a[4] = {0, 0, 0, 0};
+    int r = lane;
+    for (; r + 3 * WAVE < len; r += 4 * WAVE) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] += (double)col[r + u * WAVE] * ws[r + u * WAVE];
+    }
+    for (; r < len; r += WAVE) a[0] += (double)col[r] * ws[r];
+    double s = wave_sum((a[0] + a[1]) + (a[2] + a[3]));
+    if (lane == 0) t[b.t + j] = s;
+}
+
+// Hierarchical top, rows of one leaf (<= 64): the four waves split the
+// terms (the dense diagonal block, then the leaf's ancestor blocks), one
+// lane per row; x[pos[row]] = sum of the terms.
+constexpr int HODLR_LEAF = 64;
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_hodlr_apply(const HodlrLeaf* __restrict__ leaves,
+                                                       const HodlrBlock* __restrict__ blocks,
+                                                       const int32_t* __restrict__ anc, const T* __restrict__ val,
+                                                       const double* __restrict__ w, const double* __restrict__ t,
+                                                       const int64_t* __restrict__ pos, double* __restrict__ x) {
+    __shared__ double ws[HODLR_LEAF];
+    __shared__ double part[BLOCK / WAVE][HODLR_LEAF];
+    const HodlrLeaf lf = leaves[blockIdx.x];
+    const int len = lf.e - lf.a;
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    if (threadIdx.x < len) ws[threadIdx.x] = w[lf.a + threadIdx.x];
+    __syncthreads();
+    double a[4] = {0, 0, 0, 0};
+    if (lane < len) {
+        for (int q = wave; q <= lf.nanc; q += BLOCK / WAVE) {
+            if (q == 0) {
+                const T* D = val + lf.d + lane;
+                int j = 0;
+                for (; j + 3 < len; j += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) a[u] += (double)D[(int64_t)(j + u) * len] * ws[j + u];
+                }
+                for (; j < len; ++j) a[0] += (double)D[(int64_t)j * len] * ws[j];
+                continue;
+            }
+            const int code = anc[lf.anc + q - 1];
+            const HodlrBlock b = blocks[code >> 1];
+            const bool upper = (code & 1) == 0;        // leaf rows in [a, m): U (V^T w[m:e))
+            const int rows = upper ? b.m - b.a : b.e - b.m;
+            const int r = lf.a + lane - (upper ? b.a : b.m);
+            const T* M = val + (upper ? b.u : b.v) + r;
+            const double* tt = t + b.t + (upper ? 0 : b.k);
+            int c = 0;
+            for (; c + 3 < b.k; c += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a[u] += (double)M[(int64_t)(c + u) * rows] * tt[c + u];
+            }
+            for (; c < b.k; ++c) a[0] += (double)M[(int64_t)c * rows] * tt[c];
+        }
+    }
+    part[wave][lane] = (a[0] + a[1]) + (a[2] + a[3]);
+    __syncthreads();
+    if (wave == 0 && lane < len) {
+        double s = 0.0;
+        for (int k = 0; k < BLOCK / WAVE; ++k) s += part[k][lane];
+        x[pos[lf.a + lane]] = s;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
@@ -745,6 +827,14 @@ void launch_tri_top(hipStream_t s, const TriPlan& P, const T* inv, const double*
     if (n <= 0) return;
     k_top_gather<<<(unsigned)((n + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(n, P.top_pos, P.top_gptr, P.top_gsrc, b,
                                                                         upd, ground, P.top_w);
+    if (P.n_hleaves > 0) {
+        if (P.n_hcols > 0)
+            k_hodlr_proj<T><<<(unsigned)((P.n_hcols + BLOCK / WAVE - 1) / (BLOCK / WAVE)), BLOCK, 0, s>>>(
+                P.hblocks, P.hcols, P.n_hcols, inv, P.top_w, P.ht);
+        k_hodlr_apply<T><<<(unsigned)P.n_hleaves, BLOCK, 0, s>>>(P.hleaves, P.hblocks, P.hanc, inv, P.top_w, P.ht,
+                                                                 P.top_pos, x);
+        return;
+    }
     k_top_gemv<T><<<(unsigned)((n + TOP_ROWS - 1) / TOP_ROWS), BLOCK, n * sizeof(double), s>>>(
         n, inv, P.top_w, P.top_pos, x);
 }

@@ -55,6 +55,13 @@ struct TriPlan {
     const int32_t* top_gptr = nullptr;
     const int64_t* top_gsrc = nullptr;
     double* top_w = nullptr;
+    // hierarchical top (n_hblocks > 0 or n_hleaves > 0): S_top^-1 as low-rank blocks
+    int n_hblocks = 0, n_hleaves = 0, n_hcols = 0;
+    const HodlrBlock* hblocks = nullptr;
+    const HodlrLeaf* hleaves = nullptr;
+    const int32_t* hanc = nullptr;
+    const int32_t* hcols = nullptr;
+    double* ht = nullptr;         // projections, 2k per block
 };
 
 void launch_fill(hipStream_t s, int64_t n, double* x, double v);
@@ -74,7 +81,8 @@ unsigned launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode,
 void launch_spmv_csr(hipStream_t s, const CsrDev& A, int group, const double* x, const double* b,
                      double* y);
 // dense top of a sweep: gather w_top from b and the bottom roots' updates,
-// then x[top_pos] = S_top^-1 w_top (inv: n_top x n_top row-major)
+// then x[top_pos] = S_top^-1 w_top (inv: n_top x n_top row-major, or the
+// value array of the hierarchical form)
 template <typename T>
 void launch_tri_top(hipStream_t s, const TriPlan& P, const T* inv, const double* b, const double* upd,
                     int64_t ground, double* x);

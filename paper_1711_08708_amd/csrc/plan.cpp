@@ -347,6 +347,39 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads)
         }
         if (p.top_gsrc.empty()) p.top_gsrc.push_back(0);
         top_inverse(f, top, tmap, nt, p.top_inv, n_threads);
+        if (f.eps > 0.0 && f.dim > 0 && (int64_t)f.xyz.size() >= f.n * f.dim) {
+            // hierarchical form: bisection order of the top vertices, then
+            // low-rank off-diagonal blocks at relative accuracy eps
+            std::vector<double> xt((size_t)nt * f.dim);
+            for (int64_t k = 0; k < nt; ++k)
+                for (int d = 0; d < f.dim; ++d) xt[k * f.dim + d] = f.xyz[p.top_pos[k] * f.dim + d];
+            std::vector<int64_t> ord;
+            hodlr_order(nt, xt.data(), f.dim, PLAN_HODLR_LEAF, ord);
+            std::vector<double> Ap((size_t)nt * nt);
+            for (int64_t i = 0; i < nt; ++i)
+                for (int64_t j = 0; j < nt; ++j) Ap[(size_t)i * nt + j] = p.top_inv[(size_t)ord[i] * nt + ord[j]];
+            std::vector<int64_t> pos(nt);
+            std::vector<int32_t> gptr(nt + 1, 0);
+            std::vector<int64_t> gsrc;
+            for (int64_t i = 0; i < nt; ++i) {
+                pos[i] = p.top_pos[ord[i]];
+                for (int32_t q = p.top_gptr[ord[i]]; q < p.top_gptr[ord[i] + 1]; ++q) gsrc.push_back(p.top_gsrc[q]);
+                gptr[i + 1] = (int32_t)gsrc.size();
+            }
+            if (gsrc.empty()) gsrc.push_back(0);
+            p.top_pos.swap(pos);
+            p.top_gptr.swap(gptr);
+            p.top_gsrc.swap(gsrc);
+            hodlr_build(Ap, nt, f.eps, PLAN_HODLR_LEAF, n_threads, p.hodlr);
+            std::vector<double>().swap(p.top_inv);
+            p.top_hodlr = true;
+            for (size_t b = 0; b < p.hodlr.blocks.size(); ++b)
+                for (int j = 0; j < 2 * p.hodlr.blocks[b].k; ++j) p.hodlr_cols.push_back((int32_t)((b << 16) | j));
+            if (p.hodlr.blocks.size() >= (1u << 15) || p.hodlr.max_rank >= (1 << 15)) {
+                err = "hierarchical top too large";
+                return false;
+            }
+        }
         p.top_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
 
@@ -598,6 +631,12 @@ struct Emu {
             double v = b[p.top_pos.at(k)];
             for (int32_t q = p.top_gptr.at(k); q < p.top_gptr.at(k + 1); ++q) v -= upd.at(p.top_gsrc.at(q));
             w[k] = p.top_pos[k] == p.ground ? 0.0 : v;
+        }
+        if (p.top_hodlr) {
+            std::vector<double> y(nt);
+            hodlr_apply(p.hodlr, w.data(), y.data());
+            for (int64_t i = 0; i < nt; ++i) x.at(p.top_pos[i]) = y[i];
+            return;
         }
         for (int64_t i = 0; i < nt; ++i) {
             double s = 0.0;

@@ -41,7 +41,10 @@ struct FactorPlan {
     std::vector<int64_t> top_pos;       // top index -> vertex (tree order)
     std::vector<int32_t> top_gptr;      // top index -> [gptr, gptr+1) in top_gsrc
     std::vector<int64_t> top_gsrc;      // update-workspace entries of the bottom roots
-    std::vector<double> top_inv;        // S_top^-1, n_top x n_top row-major
+    std::vector<double> top_inv;        // S_top^-1, n_top x n_top row-major (exact mode)
+    bool top_hodlr = false;             // S_top^-1 in hierarchical low-rank form instead
+    Hodlr hodlr;                        // (top indices then in bisection order)
+    std::vector<int32_t> hodlr_cols;    // projection columns: block << 16 | column
     double top_seconds = 0.0;           // host time spent on S_top^-1
     // algorithmic bytes per height (panel at 8 or 4 bytes per entry)
     std::vector<double> fwd_bytes64, bwd_bytes64, fwd_bytes32, bwd_bytes32;
@@ -58,6 +61,7 @@ constexpr int PLAN_FWD_COLS = 128;     // forward column chunk per work item (4 
 constexpr int PLAN_BWD_MAXR = 512;     // backward rows per work item (LDS staging)
 constexpr int PLAN_LDS_DOUBLES = 4096; // bound of the LDS staging per level item
 constexpr int PLAN_TOP_MAX = 6144;     // max n_top (w_top staged in LDS, FP64)
+constexpr int PLAN_HODLR_LEAF = 64;    // leaf size of the hierarchical top
 
 // n_threads: host threads for S_top^-1 (<= 0: OpenMP default).
 bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads = 0);

@@ -178,3 +178,47 @@ def test_device_plan_emulation_matches_host_factor(mk):
         emu = hs.factor_emulate(which, b)
         assert np.isfinite(emu).all()
         assert np.abs(emu - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("mk", [lambda: w.thorax2d(n_target=6000, seed=3), lambda: w.slab3d(n=12)],
+                         ids=["thorax6000", "slab12"])
+def test_hierarchical_top_accuracy(mk, monkeypatch):
+    """With eps_h > 0 the inverse of the top separators' Schur complement is
+    held in hierarchical low-rank form (Sec. 5.3).  The emulated inner solve
+    then differs from the exact factor by an amount that shrinks with eps,
+    and the storage shrinks as eps grows."""
+    import paper_1711_08708_amd as B
+    cfg = mk()
+    monkeypatch.setenv("BIDO_TOP_H", "0")             # lowest admissible cut: largest top
+    exact = B.HostSetup(cfg, eps_h=0.0)
+    n = len(exact.index(B.IDX_UPOS))
+    b = np.random.default_rng(9).normal(size=n)
+    ref = exact.factor_apply(B.FACTOR_P1, b)
+    dense = exact.factor_top(B.FACTOR_P1)
+    rows = []
+    for eps in (1e-12, 1e-8, 1e-5, 1e-3):
+        hs = B.HostSetup(cfg, eps_h=eps)
+        top = hs.factor_top(B.FACTOR_P1)
+        emu = hs.factor_emulate(B.FACTOR_P1, b)
+        err = np.linalg.norm(emu - ref) / np.linalg.norm(ref)
+        rows.append((eps, err, top["stored_entries"], top["max_rank"]))
+    print("n_top", dense["n_top"], "dense entries", dense["stored_entries"])
+    for r in rows:
+        print("  eps %.0e  rel err %.2e  stored %d  max rank %d" % r)
+    assert rows[0][1] < 1e-9
+    for (e0, r0, s0, _), (e1, r1, s1, _) in zip(rows, rows[1:]):
+        assert r1 >= r0 * 0.5 and s1 <= s0
+    assert rows[-1][2] < dense["stored_entries"]
+    for eps, err, _, _ in rows:
+        assert err <= 1e3 * eps + 1e-12
+
+
+def test_hierarchical_top_is_compressed():
+    """At eps_h = 1e-6 the hierarchical top stores fewer values than the
+    dense inverse, with low-rank blocks of positive rank."""
+    import paper_1711_08708_amd as B
+    cfg = w.thorax2d(n_target=6000, seed=3)
+    hs = B.HostSetup(cfg, eps_h=1e-6)
+    top = hs.factor_top(B.FACTOR_P1)
+    assert top["max_rank"] > 0
+    assert top["stored_entries"] < top["n_top"] ** 2

@@ -71,6 +71,14 @@ def test_solve_parity_exact_factor(torch, mk):
     _check_solve(torch, mk(), eps_h=0.0, tol=1e-12)
 
 
+@pytest.mark.parametrize("eps", [1e-8, 1e-4])
+def test_solve_parity_hierarchical_top(torch, eps):
+    """Inexact inner solves (hierarchical top at eps_h) change the iteration
+    count, never the solution: parity at 1e-8 holds."""
+    st, _ = _check_solve(torch, w.thorax2d(n_target=6000, seed=13), eps_h=eps, tol=1e-12)
+    print("iterations at eps", eps, st["iterations"])
+
+
 def test_exact_factor_iteration_count_matches_dense_block_lu(torch):
     """With exact inner factors the GPU preconditioner is the block-LU of
     Def. 2 with P_1 = grounded S_1 and P_K = K_m exactly, so its iteration

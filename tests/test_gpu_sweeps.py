@@ -78,3 +78,30 @@ def test_dense_top_at_lowest_cut(torch, name, which, monkeypatch):
     err = np.abs(x - ref).max() / np.abs(ref).max()
     print(f"  max rel diff {err:.2e}", flush=True)
     assert np.isfinite(x).all() and err < 1e-12
+
+
+@pytest.mark.parametrize("name", ["thorax40k", "slab10"])
+@pytest.mark.parametrize("eps", [1e-10, 1e-4])
+def test_hierarchical_top_matches_emulation(torch, name, eps, monkeypatch):
+    """With eps_h > 0 the top inverse is applied in hierarchical low-rank
+    form; the device application equals the CPU emulation of the same plan
+    to rounding, and stays within about eps of the exact factor."""
+    import paper_1711_08708_amd as B
+    monkeypatch.setenv("BIDO_TOP_H", "0")     # lowest admissible cut: the largest top
+    cfg = CASES[name]()
+    hs = B.HostSetup(cfg, eps_h=eps)
+    solver = B.Solver(cfg, eps_h=eps)
+    for which in (0, 1):
+        n = solver.N if which == 0 else solver.NH
+        b = np.random.default_rng(4 + which).normal(size=n)
+        emu = hs.factor_emulate(which, b)
+        exact = hs.factor_apply(which, b)
+        xd = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        solver.inner_solve(which, torch.tensor(b, device="cuda"), xd)
+        x = xd.cpu().numpy()
+        e_emu = np.abs(x - emu).max() / np.abs(emu).max()
+        e_ex = np.linalg.norm(x - exact) / np.linalg.norm(exact)
+        print(f"{name} eps {eps:.0e} factor {which}: top {hs.factor_top(which)}, vs emulation {e_emu:.2e}, "
+              f"vs exact {e_ex:.2e}", flush=True)
+        assert np.isfinite(x).all() and e_emu < 1e-12
+        assert e_ex <= 1e3 * eps + 1e-12
