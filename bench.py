@@ -33,7 +33,8 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="thorax200k")
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--eps", type=float, default=0.0)
+    ap.add_argument("--eps", type=float, default=1e-8,
+                    help="accuracy of the hierarchical top of the inner solves (0: exact)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the sampled parity check")
@@ -273,7 +274,7 @@ def _bench_batch(args):
         cfgs = list(ex.map(_gen_slice, kws))
     t_mesh = time.perf_counter() - t0
     t0 = time.perf_counter()
-    solvers = [B.Solver(c, tol=args.tol, precision=prec) for c in cfgs]
+    solvers = [B.Solver(c, tol=args.tol, eps_h=args.eps, precision=prec) for c in cfgs]
     t_setup = time.perf_counter() - t0
     n_nodes = sum(s.N for s in solvers)
     print(f"[bench] batch64: {len(solvers)} slices, {n_nodes} vertices, meshes {t_mesh:.1f}s, "

@@ -678,18 +678,25 @@ __global__ __launch_bounds__(BLOCK) void k_hodlr_proj(const HodlrBlock* __restri
     if (lane == 0) t[b.t + j] = s;
 }
 
-// Hierarchical top, rows of one leaf (<= 64): the four waves split the
-// terms (the dense diagonal block, then the leaf's ancestor blocks), one
-// lane per row; x[pos[row]] = sum of the terms.
+// Hierarchical top, rows of one leaf (<= 64), one lane per row: the terms
+// (the dense diagonal block, then the leaf's ancestor blocks) are cut into
+// chunks of 16 columns dealt round-robin to the 16 waves of the workgroup;
+// x[pos[row]] = sum of the chunks (reduced in LDS, fixed order).
 constexpr int HODLR_LEAF = 64;
+constexpr int HODLR_BLOCK = 1024;
+constexpr int HODLR_NW = HODLR_BLOCK / WAVE;
+constexpr int HODLR_CHUNK = 16;
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_hodlr_apply(const HodlrLeaf* __restrict__ leaves,
-                                                       const HodlrBlock* __restrict__ blocks,
-                                                       const int32_t* __restrict__ anc, const T* __restrict__ val,
-                                                       const double* __restrict__ w, const double* __restrict__ t,
-                                                       const int64_t* __restrict__ pos, double* __restrict__ x) {
+__global__ __launch_bounds__(HODLR_BLOCK) void k_hodlr_apply(const HodlrLeaf* __restrict__ leaves,
+                                                             const HodlrBlock* __restrict__ blocks,
+                                                             const int32_t* __restrict__ anc,
+                                                             const T* __restrict__ val,
+                                                             const double* __restrict__ w,
+                                                             const double* __restrict__ t,
+                                                             const int64_t* __restrict__ pos,
+                                                             double* __restrict__ x) {
     __shared__ double ws[HODLR_LEAF];
-    __shared__ double part[BLOCK / WAVE][HODLR_LEAF];
+    __shared__ double part[HODLR_NW][HODLR_LEAF];
     const HodlrLeaf lf = leaves[blockIdx.x];
     const int len = lf.e - lf.a;
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
@@ -697,37 +704,47 @@ __global__ __launch_bounds__(BLOCK) void k_hodlr_apply(const HodlrLeaf* __restri
     __syncthreads();
     double a[4] = {0, 0, 0, 0};
     if (lane < len) {
-        for (int q = wave; q <= lf.nanc; q += BLOCK / WAVE) {
-            if (q == 0) {
-                const T* D = val + lf.d + lane;
-                int j = 0;
-                for (; j + 3 < len; j += 4) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) a[u] += (double)D[(int64_t)(j + u) * len] * ws[j + u];
-                }
-                for (; j < len; ++j) a[0] += (double)D[(int64_t)j * len] * ws[j];
-                continue;
+        int u = 0;
+        for (int j0 = 0; j0 < len; j0 += HODLR_CHUNK, ++u) {
+            if (u % HODLR_NW != wave) continue;
+            const T* D = val + lf.d + lane;
+            const int j1 = min(len, j0 + HODLR_CHUNK);
+            int j = j0;
+            for (; j + 3 < j1; j += 4) {
+                a[0] += (double)D[(int64_t)j * len] * ws[j];
+                a[1] += (double)D[(int64_t)(j + 1) * len] * ws[j + 1];
+                a[2] += (double)D[(int64_t)(j + 2) * len] * ws[j + 2];
+                a[3] += (double)D[(int64_t)(j + 3) * len] * ws[j + 3];
             }
-            const int code = anc[lf.anc + q - 1];
+            for (; j < j1; ++j) a[0] += (double)D[(int64_t)j * len] * ws[j];
+        }
+        for (int q = 0; q < lf.nanc; ++q) {
+            const int code = anc[lf.anc + q];
             const HodlrBlock b = blocks[code >> 1];
             const bool upper = (code & 1) == 0;        // leaf rows in [a, m): U (V^T w[m:e))
             const int rows = upper ? b.m - b.a : b.e - b.m;
             const int r = lf.a + lane - (upper ? b.a : b.m);
             const T* M = val + (upper ? b.u : b.v) + r;
             const double* tt = t + b.t + (upper ? 0 : b.k);
-            int c = 0;
-            for (; c + 3 < b.k; c += 4) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) a[u] += (double)M[(int64_t)(c + u) * rows] * tt[c + u];
+            for (int c0 = 0; c0 < b.k; c0 += HODLR_CHUNK, ++u) {
+                if (u % HODLR_NW != wave) continue;
+                const int c1 = min(b.k, c0 + HODLR_CHUNK);
+                int c = c0;
+                for (; c + 3 < c1; c += 4) {
+                    a[0] += (double)M[(int64_t)c * rows] * tt[c];
+                    a[1] += (double)M[(int64_t)(c + 1) * rows] * tt[c + 1];
+                    a[2] += (double)M[(int64_t)(c + 2) * rows] * tt[c + 2];
+                    a[3] += (double)M[(int64_t)(c + 3) * rows] * tt[c + 3];
+                }
+                for (; c < c1; ++c) a[0] += (double)M[(int64_t)c * rows] * tt[c];
             }
-            for (; c < b.k; ++c) a[0] += (double)M[(int64_t)c * rows] * tt[c];
         }
     }
     part[wave][lane] = (a[0] + a[1]) + (a[2] + a[3]);
     __syncthreads();
     if (wave == 0 && lane < len) {
         double s = 0.0;
-        for (int k = 0; k < BLOCK / WAVE; ++k) s += part[k][lane];
+        for (int k = 0; k < HODLR_NW; ++k) s += part[k][lane];
         x[pos[lf.a + lane]] = s;
     }
 }
@@ -831,8 +848,8 @@ void launch_tri_top(hipStream_t s, const TriPlan& P, const T* inv, const double*
         if (P.n_hcols > 0)
             k_hodlr_proj<T><<<(unsigned)((P.n_hcols + BLOCK / WAVE - 1) / (BLOCK / WAVE)), BLOCK, 0, s>>>(
                 P.hblocks, P.hcols, P.n_hcols, inv, P.top_w, P.ht);
-        k_hodlr_apply<T><<<(unsigned)P.n_hleaves, BLOCK, 0, s>>>(P.hleaves, P.hblocks, P.hanc, inv, P.top_w, P.ht,
-                                                                 P.top_pos, x);
+        k_hodlr_apply<T><<<(unsigned)P.n_hleaves, HODLR_BLOCK, 0, s>>>(P.hleaves, P.hblocks, P.hanc, inv, P.top_w,
+                                                                       P.ht, P.top_pos, x);
         return;
     }
     k_top_gemv<T><<<(unsigned)((n + TOP_ROWS - 1) / TOP_ROWS), BLOCK, n * sizeof(double), s>>>(
