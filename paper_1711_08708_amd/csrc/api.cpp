@@ -123,7 +123,7 @@ struct FactorDev {
         hipFree(nodes); hipFree(panel64); hipFree(panel32); hipFree(panel64_cm); hipFree(panel32_cm);
         hipFree(ea); hipFree(bidx);
         hipFree(upd); hipFree(ytmp); hipFree(items); hipFree(bitems);
-        hipFree(plan.sub_nodes); hipFree(plan.sub_hoff); hipFree(plan.scratch);
+        hipFree(plan.sub_nodes); hipFree(plan.sub_tn); hipFree(plan.sub_hoff); hipFree(plan.scratch);
         hipFree(fcomb); hipFree(bcomb); fcomb = nullptr; bcomb = nullptr;
         hipFree(top_inv64); hipFree(top_inv32); top_inv64 = nullptr; top_inv32 = nullptr;
         hipFree((void*)plan.hblocks); hipFree((void*)plan.hleaves); hipFree((void*)plan.hanc);
@@ -180,6 +180,7 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
     fd.plan.n_sub = p.n_sub;
     fd.plan.sub_maxw = p.sub_maxw;
     HIP_OK(upload(&fd.plan.sub_nodes, p.sub_nodes.data(), p.sub_nodes.size()));
+    HIP_OK(upload(&fd.plan.sub_tn, p.sub_tn.data(), p.sub_tn.size()));
     HIP_OK(upload(&fd.plan.sub_hoff, p.sub_hoff.data(), p.sub_hoff.size()));
     HIP_OK(hipMalloc((void**)&fd.plan.scratch, std::max<int64_t>(p.scratch_size, 1) * sizeof(double)));
     HIP_OK(upload(&fd.fcomb, p.fwd_comb.data(), p.fwd_comb.size()));   // empty: no combine launch

@@ -18,6 +18,7 @@ struct TriNode {
     int64_t bidx;    // offset of B(t) in the boundary index array
     int64_t upd;     // offset of the update vector c_t in the workspace
     int64_t ea;      // offset of the extend-add map (nI + nB entries)
+    int64_t u0, u1;  // update offsets of the two children (0 when absent)
     int32_t nI, nB;
     int32_t child[2];
 };

@@ -327,10 +327,6 @@ __device__ __forceinline__ int pow2_ceil64(int n) {
     return g;
 }
 
-__device__ __forceinline__ int64_t child_upd(const TriNode* __restrict__ nodes, int c) {
-    return c >= 0 ? nodes[c].upd : 0;
-}
-
 // w_t[i] = b[off+i] - children's updates at own position i (ground -> 0)
 __device__ __forceinline__ double gather_w(const TriNode& nd, int i, const Ea* __restrict__ ea,
                                            const double* __restrict__ b, const double* upd,
@@ -429,8 +425,7 @@ __device__ __forceinline__ double col_part(const T* __restrict__ P, int nI, int 
 // Subtree phase, forward: workgroup s walks its subtree from the leaves up;
 // each node is handled by one wave, one panel row per lane.
 template <typename T>
-__global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __restrict__ nodes,
-                                                           const int32_t* __restrict__ sub_nodes,
+__global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __restrict__ sub_tn,
                                                            const int32_t* __restrict__ sub_hoff, int hc,
                                                            const T* __restrict__ panel_cm,
                                                            const Ea* __restrict__ ea,
@@ -443,8 +438,8 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __rest
     double* w = wbuf[wave];
     for (int h = 0; h <= hc; ++h) {
         for (int k = hoff[h] + wave; k < hoff[h + 1]; k += SUB_NW) {
-            const TriNode nd = nodes[sub_nodes[k]];
-            const int64_t u0 = child_upd(nodes, nd.child[0]), u1 = child_upd(nodes, nd.child[1]);
+            const TriNode nd = sub_tn[__builtin_amdgcn_readfirstlane(k)];   // wave-uniform
+            const int64_t u0 = nd.u0, u1 = nd.u1;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_wave_barrier();
             for (int i = lane; i < nd.nI; i += WAVE) w[i] = gather_w(nd, i, ea, b, upd, u0, u1, ground);
@@ -462,42 +457,77 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __rest
     }
 }
 
-// Subtree phase, backward: heights from the subtree root down; one wave per
-// node: z = [y_t ; -x_B] staged in LDS, lanes own columns (and row streams
-// when the node has fewer than 64 columns).
+// Subtree phase, backward: heights from the subtree root down, z = [y_t ;
+// -x_B] staged in LDS.  One node per wave (lanes own columns, plus row
+// streams when the node has fewer than 64 columns), except at a height with
+// few nodes of which one is large: there the nodes are done one by one by
+// the whole workgroup, W columns times 1024/W row streams, partial sums
+// reduced in LDS.
+constexpr int SUB_COOP_MIN = 6000;    // nI * (nI + nB) of a large node
 template <typename T>
-__global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __restrict__ nodes,
-                                                           const int32_t* __restrict__ sub_nodes,
+__global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __restrict__ sub_tn,
                                                            const int32_t* __restrict__ sub_hoff, int hc,
                                                            const T* __restrict__ panel,
                                                            const int64_t* __restrict__ bidx,
                                                            const double* __restrict__ y,
                                                            double* x) {
     __shared__ double zbuf[SUB_NW][SUB_MAXF];
+    __shared__ double redb[SUB_BLOCK];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int32_t* hoff = sub_hoff + (size_t)blockIdx.x * (hc + 2);
     double* z = zbuf[wave];
     for (int h = hc; h >= 0; --h) {
-        for (int k = hoff[h] + wave; k < hoff[h + 1]; k += SUB_NW) {
-            const TriNode nd = nodes[sub_nodes[k]];
-            const int nI = nd.nI, nF = nd.nI + nd.nB;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            for (int r = lane; r < nF; r += WAVE) z[r] = r < nI ? y[nd.off + r] : -x[bidx[nd.bidx + (r - nI)]];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            const T* P = panel + nd.panel;
-            for (int cb = 0; cb < nI; cb += WAVE) {
-                const int ncols = min(WAVE, nI - cb);
-                const int W = pow2_ceil64(ncols);
-                const int S = WAVE / W;
-                const int col = lane % W, st = lane / W;
-                const int c = cb + col;
-                double acc = 0.0;
-                if (col < ncols) acc = col_part<T>(P, nI, c, cb + st, nF, S, z, 0);
-                for (int m = W; m < WAVE; m <<= 1) acc += __shfl_xor(acc, m, WAVE);
-                if (st == 0 && col < ncols) x[nd.off + c] = acc;
+        const int k0 = hoff[h], k1 = hoff[h + 1];
+        bool coop = false;
+        if (2 * (k1 - k0) < SUB_NW)
+            for (int k = k0; k < k1; ++k) coop |= sub_tn[k].nI * (sub_tn[k].nI + sub_tn[k].nB) >= SUB_COOP_MIN;
+        if (!coop) {
+            for (int k = k0 + wave; k < k1; k += SUB_NW) {
+                const TriNode nd = sub_tn[__builtin_amdgcn_readfirstlane(k)];   // wave-uniform
+                const int nI = nd.nI, nF = nd.nI + nd.nB;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                for (int r = lane; r < nF; r += WAVE) z[r] = r < nI ? y[nd.off + r] : -x[bidx[nd.bidx + (r - nI)]];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const T* P = panel + nd.panel;
+                for (int cb = 0; cb < nI; cb += WAVE) {
+                    const int ncols = min(WAVE, nI - cb);
+                    const int W = pow2_ceil64(ncols);
+                    const int S = WAVE / W;
+                    const int col = lane % W, st = lane / W;
+                    const int c = cb + col;
+                    double acc = 0.0;
+                    if (col < ncols) acc = col_part<T>(P, nI, c, cb + st, nF, S, z, 0);
+                    for (int m = W; m < WAVE; m <<= 1) acc += __shfl_xor(acc, m, WAVE);
+                    if (st == 0 && col < ncols) x[nd.off + c] = acc;
+                }
+            }
+        } else {
+            double* zsh = zbuf[0];
+            for (int k = k0; k < k1; ++k) {
+                const TriNode nd = sub_tn[k];
+                const int nI = nd.nI, nF = nd.nI + nd.nB;
+                for (int r = threadIdx.x; r < nF; r += SUB_BLOCK)
+                    zsh[r] = r < nI ? y[nd.off + r] : -x[bidx[nd.bidx + (r - nI)]];
+                __syncthreads();
+                const T* P = panel + nd.panel;
+                for (int cb = 0; cb < nI; cb += WAVE) {
+                    const int ncols = min(WAVE, nI - cb);
+                    const int W = pow2_ceil64(ncols);
+                    const int S = SUB_BLOCK / W;
+                    const int col = threadIdx.x % W, st = threadIdx.x / W;
+                    const int c = cb + col;
+                    redb[threadIdx.x] = col < ncols ? col_part<T>(P, nI, c, cb + st, nF, S, zsh, 0) : 0.0;
+                    __syncthreads();
+                    if (threadIdx.x < ncols) {
+                        double t = 0.0;
+                        for (int q = 0; q < S; ++q) t += redb[q * W + threadIdx.x];
+                        x[nd.off + c] = t;
+                    }
+                    __syncthreads();
+                }
             }
         }
         __syncthreads();
@@ -520,7 +550,7 @@ __global__ __launch_bounds__(BLOCK) void k_tri_fwd_lvl(const TriNode* __restrict
     __shared__ double red[BLOCK / WAVE][FWD_ROWS];
     const TriItem it = items[blockIdx.x];
     const TriNode nd = nodes[it.node];
-    const int64_t u0 = child_upd(nodes, nd.child[0]), u1 = child_upd(nodes, nd.child[1]);
+    const int64_t u0 = nd.u0, u1 = nd.u1;
     const int ncol = it.ce - it.cs;
     for (int i = threadIdx.x; i < ncol; i += BLOCK) w[i] = gather_w(nd, it.cs + i, ea, b, upd, u0, u1, ground);
     __syncthreads();
@@ -556,7 +586,7 @@ __global__ __launch_bounds__(BLOCK) void k_tri_fwd_comb(const TriNode* __restric
     const TriItem it = comb[q];
     if (lane >= it.nrows) return;
     const TriNode nd = nodes[it.node];
-    const int64_t u0 = child_upd(nodes, nd.child[0]), u1 = child_upd(nodes, nd.child[1]);
+    const int64_t u0 = nd.u0, u1 = nd.u1;
     double t = 0.0;
     for (int k = 0; k < it.nparts; ++k) t += scratch[it.part0 + (int64_t)k * FWD_ROWS + lane];
     store_row(nd, it.r0 + lane, t, ea, y, upd, u0, u1);
@@ -860,14 +890,13 @@ template <typename T>
 void launch_tri_fwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel_cm,
                         const Ea* ea, const double* b, double* y, double* upd, int64_t ground) {
     if (P.n_sub == 0) return;
-    k_tri_fwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(nodes, P.sub_nodes, P.sub_hoff, P.hc, panel_cm, ea, b,
-                                                   y, upd, ground);
+    k_tri_fwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel_cm, ea, b, y, upd, ground);
 }
 template <typename T>
 void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
                         const int64_t* bidx, const double* y, double* x) {
     if (P.n_sub == 0) return;
-    k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(nodes, P.sub_nodes, P.sub_hoff, P.hc, panel, bidx, y, x);
+    k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel, bidx, y, x);
 }
 template <typename T>
 void launch_tri_fwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,

@@ -46,6 +46,7 @@ struct TriPlan {
     int hc = -1;                  // subtree cut height (-1: no subtree phase)
     int n_sub = 0;                // subtrees (workgroups of the subtree phase)
     int32_t* sub_nodes = nullptr; // device: node ids grouped by subtree, by height
+    TriNode* sub_tn = nullptr;    // device: the same nodes' records, in that order
     int32_t* sub_hoff = nullptr;  // device: n_sub x (hc+2) height offsets
     int sub_maxw = 0;             // max nI below the cut
     double* scratch = nullptr;    // partial sums of split tiles

@@ -179,6 +179,11 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads)
         return false;
     }
     p.upd_size = uoff;
+    for (int id = 0; id < nn; ++id) {
+        TriNode& d = p.nodes[id];
+        d.u0 = d.child[0] >= 0 ? p.nodes[d.child[0]].upd : 0;
+        d.u1 = d.child[1] >= 0 ? p.nodes[d.child[1]].upd : 0;
+    }
     p.panel.assign((size_t)poff, 0.0);
     p.panel_cm.assign((size_t)poff, 0.0);
     p.bidx.assign((size_t)std::max<int64_t>(boff, 1), 0);
@@ -282,6 +287,8 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads)
         }
         p.sub_maxw = maxw_le[hc];
     }
+    p.sub_tn.clear();
+    for (int id : p.sub_nodes) p.sub_tn.push_back(p.nodes[id]);
 
     // ---- dense top: cut height by a cost model -----------------------------------
     // A level of the sweeps costs about one forward and one backward launch
@@ -522,7 +529,9 @@ struct Emu {
     int64_t upd_of(int child) const { return child >= 0 ? p.nodes.at(child).upd : 0; }
 
     double gather_w(const TriNode& nd, int i) const {
-        const int64_t u0 = upd_of(nd.child[0]), u1 = upd_of(nd.child[1]);
+        if (nd.u0 != upd_of(nd.child[0]) || nd.u1 != upd_of(nd.child[1]))
+            throw std::runtime_error("children's update offsets");
+        const int64_t u0 = nd.u0, u1 = nd.u1;
         double v = b[nd.off + i];
         const Ea m = p.ea.at(nd.ea + i);
         if (m.a >= 0) v -= upd.at(u0 + m.a);
@@ -544,8 +553,8 @@ struct Emu {
             y.at(nd.off + r) = s;
         } else {
             const Ea m = p.ea.at(nd.ea + r);
-            if (m.a >= 0) s += upd.at(upd_of(nd.child[0]) + m.a);
-            if (m.b >= 0) s += upd.at(upd_of(nd.child[1]) + m.b);
+            if (m.a >= 0) s += upd.at(nd.u0 + m.a);
+            if (m.b >= 0) s += upd.at(nd.u1 + m.b);
             upd.at(nd.upd + (r - nd.nI)) = s;
         }
     }
@@ -568,7 +577,7 @@ struct Emu {
             const int32_t* hoff = &p.sub_hoff.at((size_t)s * (p.hc + 2));
             for (int h = 0; h <= p.hc; ++h)
                 for (int k = hoff[h]; k < hoff[h + 1]; ++k) {
-                    const TriNode& nd = p.nodes.at(p.sub_nodes.at(k));
+                    const TriNode& nd = p.sub_tn.at(k);
                     if (nd.nI > PLAN_SUB_MAXW || nd.nI + nd.nB > PLAN_SUB_MAXF)
                         throw std::runtime_error("subtree node too large");
                     std::vector<double> w(nd.nI);
@@ -585,7 +594,7 @@ struct Emu {
             const int32_t* hoff = &p.sub_hoff.at((size_t)s * (p.hc + 2));
             for (int h = p.hc; h >= 0; --h)
                 for (int k = hoff[h]; k < hoff[h + 1]; ++k) {
-                    const TriNode& nd = p.nodes.at(p.sub_nodes.at(k));
+                    const TriNode& nd = p.sub_tn.at(k);
                     const int nF = nd.nI + nd.nB;
                     std::vector<double> z(nF);
                     for (int r = 0; r < nF; ++r) z[r] = z_of(nd, r);

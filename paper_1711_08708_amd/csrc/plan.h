@@ -23,6 +23,7 @@ struct FactorPlan {
     // subtree phase
     int hc = -1, n_sub = 0, sub_maxw = 0;
     std::vector<int32_t> sub_nodes, sub_hoff;
+    std::vector<TriNode> sub_tn;        // node records in sub_nodes order
     // level phases (heights hc+1 .. height)
     std::vector<TriItem> fwd_items;
     std::vector<BwdItem> bwd_items;

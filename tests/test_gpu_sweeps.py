@@ -24,6 +24,7 @@ CASES = {
     "square48": lambda: w.square2d(n=48),
     "slab6": lambda: w.slab3d(n=6),
     "slab10": lambda: w.slab3d(n=10),
+    "slab16": lambda: w.slab3d(n=16),
     "thorax3000": lambda: w.thorax2d(n_target=3000, seed=11),
     "thorax40k": lambda: w.thorax2d(n_target=40000, seed=12),
 }
