@@ -45,6 +45,7 @@ def _parse():
                     help="plain steps whose CG iterations provide training pairs")
     ap.add_argument("--variant-steps", type=int, default=50)
     ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuning of the inner-solve plans")
     ap.add_argument("--batch-streams", type=int, default=4, help="streams of the batch (batch64)")
     ap.add_argument("--batch-learned", action="store_true",
                     help="batch64: train the learned stencil of every slice first")
@@ -128,6 +129,7 @@ def main():
     t_setup = time.perf_counter()
     solver = B.Solver(cfg, tol=args.tol, eps_h=args.eps, precision=prec)
     t_setup = time.perf_counter() - t_setup
+    tune = None if args.no_tune else solver.autotune()
     info = solver.info
     print(f"[bench] {cfg['name']}: N={solver.N} N_H={solver.NH} setup {t_setup:.2f}s "
           f"P1 {info['bytes_p1']/1e6:.1f} MB PK {info['bytes_pk']/1e6:.1f} MB", file=sys.stderr,
@@ -181,7 +183,12 @@ def main():
                    "n_nodes": solver.N, "n_heart": solver.NH, "dt_ms": cfg["dt"],
                    "tol": args.tol, "eps_h": args.eps, "precision": args.precision,
                    "first_step": n0, "cg_iterations_per_step": round(iters / args.steps, 3),
-                   "setup_s": round(t_setup, 2)},
+                   "setup_s": round(t_setup, 2),
+                   "tune": None if tune is None else {
+                       "seconds": round(tune["seconds"], 2), "candidates": tune["candidates"],
+                       "us_before": [round(x, 1) for x in tune["us_before"]],
+                       "us_after": [round(x, 1) for x in tune["us_after"]],
+                       "top_h": tune["top_h"], "fwd_cols": tune["fwd_cols"], "bwd_rows": tune["bwd_rows"]}},
         "roofline": roofline,
         "kernels": kernels,
     }

@@ -264,6 +264,24 @@ bido_status bido_gnn_loss_grad(bido_ctx* ctx, const float* that, const float* y,
 bido_status bido_stencil_check(bido_ctx* ctx, const float* zh, const float* bh, float* r, double* loss,
                                float* grad);
 
+/* Autotuning of the inner-solve plans: for P_1 and P_K, candidate plans
+ * (the first height of the top one or two levels either side of the cost
+ * model's choice, then forward column chunks of 64/128/256 and backward row
+ * ranges of 256/1024 or the default) are built, their triangular solves are
+ * timed on the device (`reps` back-to-back solves, <= 0: 10) and the fastest
+ * plan is kept.  Results do not change beyond rounding.  Synchronises the
+ * stream; not for a context in a batch (BIDO_ERR_STATE).                  */
+typedef struct {
+    int candidates;          /* plans built and timed                         */
+    double seconds;          /* host time of the whole tuning                 */
+    double us_before[2];     /* P_1, P_K solve time with the initial plans    */
+    double us_after[2];      /* ... with the chosen plans                     */
+    int top_h[2];            /* chosen first height of the top                */
+    int fwd_cols[2];         /* chosen forward column chunk                   */
+    int bwd_rows[2];         /* chosen backward row range (0: default)        */
+} bido_tune_report;
+bido_status bido_autotune(bido_ctx* ctx, int reps, bido_tune_report* report);
+
 /* HIP graphs: bido_step / bido_run / bido_batch_run can replay one captured
  * graph per PCG iteration (preconditioner apply, direction update, SpMV,
  * PCG update, copy of the scalars) instead of launching its kernels one by

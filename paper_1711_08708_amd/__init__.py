@@ -89,6 +89,16 @@ class TrainStats(ctypes.Structure):
 GNN_P = 3169
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int), ("seconds", ctypes.c_double),
+                ("us_before", ctypes.c_double * 2), ("us_after", ctypes.c_double * 2),
+                ("top_h", ctypes.c_int * 2), ("fwd_cols", ctypes.c_int * 2), ("bwd_rows", ctypes.c_int * 2)]
+
+    def as_dict(self):
+        return {k: (list(getattr(self, k)) if k not in ("candidates", "seconds") else getattr(self, k))
+                for k, _ in self._fields_}
+
+
 class KProf(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
                 ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -119,6 +129,7 @@ ABI = {
                                         ctypes.c_void_p]),
     "bido_set_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_set_graphs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "bido_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(TuneReport)]),
     "bido_learn_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
                                           ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Stats)]),
@@ -369,6 +380,12 @@ class Solver:
         _check(lib.bido_stencil_check(self.ctx, ctypes.c_void_p(zh.data_ptr()), ctypes.c_void_p(bh.data_ptr()),
                                       ctypes.c_void_p(r.data_ptr()), ctypes.byref(loss), g))
         return r, loss.value, (np.ctypeslib.as_array(g).astype(np.float64).copy() if grad else None)
+
+    def autotune(self, reps=10):
+        """Time candidate plans of the inner solves on the device and keep the fastest."""
+        r = TuneReport()
+        _check(lib.bido_autotune(self.ctx, int(reps), ctypes.byref(r)))
+        return r.as_dict()
 
     def set_graphs(self, on):
         """True: always replay captured graphs, False: never, None: only in a batch."""

@@ -108,6 +108,7 @@ struct FactorDev {
     double top_bytes64 = 0, top_bytes32 = 0;
     int top_h = 0;
     double top_seconds = 0;
+    PlanOptions opts;               // the options of the current plan
     TriPlan plan;
     std::vector<TriTopLevel> top;                   // heights hc+1 .. height
     std::vector<double> fwd_bytes64, bwd_bytes64;   // algorithmic bytes per height (FP64 panel)
@@ -152,10 +153,12 @@ struct CsrHostView {
     }
 };
 
-bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_threads = 0) {
+bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_threads = 0,
+                             const PlanOptions* opt = nullptr) {
     FactorPlan p;
     std::string err;
-    if (!build_plan(f, p, err, n_threads)) return fail(BIDO_ERR_ARG, err);
+    if (!build_plan(f, p, err, n_threads, opt)) return fail(BIDO_ERR_ARG, err);
+    fd.opts = p.used;
     fd.n = p.n;
     fd.ground = p.ground;
     fd.height = p.height;
@@ -932,6 +935,8 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     if ((e = CsrHostView::up(hs.auv, c->auv))) return e;
     if ((e = build_factor_dev(hs.p1, true, c->p1, hs.params.n_threads))) return e;
     if ((e = build_factor_dev(hs.pk, true, c->pk, hs.params.n_threads))) return e;
+    hs.p1.clear_top_cache();
+    hs.pk.clear_top_cache();
     const int64_t n2 = c->n2;
     for (double** b : {&c->x, &c->r, &c->z, &c->p, &c->q, &c->Y, &c->r_old})
         HIP_OK(hipMalloc((void**)b, n2 * sizeof(double)));
@@ -1509,6 +1514,75 @@ bido_status bido_stencil_check(bido_ctx* c, const float* zh, const float* bh, fl
     if (grad) HIP_OK(hipMemcpyAsync(grad, g.grad, GNN_P * sizeof(float), hipMemcpyDeviceToHost, s));
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(s));
+    return BIDO_OK;
+}
+
+// Mean time of one application of factor f over `reps` back-to-back solves
+// on the context's stream [ms].
+double time_factor(bido_ctx* c, const FactorDev& f, const double* in, double* out, int reps) {
+    inner_solve(c, f, in, out);
+    hipEventRecord(c->ev0, c->stream);
+    for (int r = 0; r < reps; ++r) inner_solve(c, f, in, out);
+    hipEventRecord(c->ev1, c->stream);
+    hipEventSynchronize(c->ev1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    return ms / reps;
+}
+
+bido_status bido_autotune(bido_ctx* c, int reps, bido_tune_report* rep) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    if (c->batched) return fail(BIDO_ERR_STATE, "context belongs to a batch");
+    reps = reps > 0 ? reps : 10;
+    auto t0 = std::chrono::steady_clock::now();
+    bido_tune_report r{};
+    const int nth = c->hs.params.n_threads;
+    for (int which = 0; which < 2; ++which) {
+        FactorDev& cur = which == 0 ? c->p1 : c->pk;
+        const Factor& f = which == 0 ? c->hs.p1 : c->hs.pk;
+        launch_fill(c->stream, cur.n, c->r, 1.0);
+        double best = time_factor(c, cur, c->r, c->z, reps);
+        r.us_before[which] = best * 1e3;
+        auto attempt = [&](PlanOptions o) {
+            FactorDev cand;
+            if (build_factor_dev(f, true, cand, nth, &o) == BIDO_OK) {
+                ++r.candidates;
+                const double ms = time_factor(c, cand, c->r, c->z, reps);
+                if (ms < 0.98 * best) {
+                    best = ms;
+                    std::swap(cur, cand);
+                }
+            }
+            cand.release();
+        };
+        // the cut first, with the present tiles; then the tiles at the best cut
+        const PlanOptions start = cur.opts;
+        for (int d : {-2, -1, 1, 2}) {
+            PlanOptions o = start;
+            o.top_h = start.top_h + d;
+            if (o.top_h >= 0) attempt(o);
+        }
+        const PlanOptions at = cur.opts;
+        for (int fc : {64, 128, 256})
+            for (int br : {0, 256, 1024}) {
+                PlanOptions o = at;
+                o.fwd_cols = fc;
+                o.bwd_rows = br;
+                if (o.fwd_cols == at.fwd_cols && o.bwd_rows == at.bwd_rows) continue;
+                attempt(o);
+            }
+        f.clear_top_cache();
+        HIP_OK(hipMemset(cur.ytmp, 0xFF, std::max<int64_t>(cur.n, 1) * sizeof(double)));
+        HIP_OK(hipMemset(cur.upd, 0xFF, std::max<int64_t>(cur.upd_size, 1) * sizeof(double)));
+        r.us_after[which] = best * 1e3;
+        r.top_h[which] = cur.opts.top_h;
+        r.fwd_cols[which] = cur.opts.fwd_cols;
+        r.bwd_rows[which] = cur.opts.bwd_rows;
+    }
+    c->drop_graphs();
+    HIP_OK(hipStreamSynchronize(c->stream));
+    r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = r;
     return BIDO_OK;
 }
 

@@ -3,6 +3,8 @@
 // the inner-solve factors.  Pure C++ (no HIP); compiled into libbido.so.
 #pragma once
 #include <cstdint>
+#include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -108,6 +110,32 @@ struct Front {
     std::vector<LowRank> lowrank;
 };
 
+struct Hodlr {
+    int64_t n = 0, t_size = 1;
+    int max_rank = 0;
+    std::vector<HodlrBlock> blocks;
+    std::vector<HodlrLeaf> leaves;
+    std::vector<int32_t> anc;
+    std::vector<double> val;
+};
+
+// The top of a factor's execution plan for one cut height: its vertices
+// (tree order), the bottom roots' update entries to gather, and S_top^-1,
+// dense or in hierarchical form (then in bisection order, with the list of
+// projection columns).
+struct TopPart {
+    double eps = 0.0;
+    int64_t n_top = 0;
+    std::vector<int64_t> pos;
+    std::vector<int32_t> gptr;
+    std::vector<int64_t> gsrc;
+    std::vector<double> inv;
+    bool hodlr = false;
+    Hodlr hd;
+    std::vector<int32_t> cols;
+    double seconds = 0.0;
+};
+
 struct Factor {
     int64_t n = 0;
     int64_t ground = -1;             // grounded index (new order) or -1
@@ -117,6 +145,10 @@ struct Factor {
     double eps = 0.0, eta = 2.0;
     int dim = 0;
     std::vector<double> xyz;
+    // tops of earlier plans, by cut height (plans built again while tuning
+    // reuse them); clear_top_cache() frees them
+    mutable std::map<int, std::shared_ptr<const TopPart>> top_cache;
+    void clear_top_cache() const { top_cache.clear(); }
     int64_t dense_entries() const;
     int64_t stored_entries() const;  // after compression
     int64_t n_lowrank() const;
@@ -139,14 +171,6 @@ void compress(Factor& f, const double* xyz, int dim, double eps, double eta,
 void rrqr_lowrank(const double* B, int64_t ld, int m, int n, double eps, std::vector<double>& U,
                   std::vector<double>& V, int& k);
 
-struct Hodlr {
-    int64_t n = 0, t_size = 1;
-    int max_rank = 0;
-    std::vector<HodlrBlock> blocks;
-    std::vector<HodlrLeaf> leaves;
-    std::vector<int32_t> anc;
-    std::vector<double> val;
-};
 // Recursive geometric bisection order of n points (leaves of <= leaf points).
 void hodlr_order(int64_t n, const double* xyz, int dim, int leaf, std::vector<int64_t>& ord);
 // Hierarchical form of the symmetric n x n row-major A (bisection order).

@@ -146,7 +146,8 @@ void top_inverse(const Factor& f, const std::vector<int>& top, const std::vector
 
 }  // namespace
 
-bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads) {
+bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads, const PlanOptions* opt) {
+    const PlanOptions o = opt ? *opt : PlanOptions();
     const NdTree& t = f.tree;
     const int nn = (int)t.nodes.size();
     p = FactorPlan();
@@ -316,78 +317,99 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads)
         }
         // a forced cut is raised as far as the top-size bound requires
         const char* e = std::getenv("BIDO_TOP_H");
-        if (e && *e) best = std::max(lowest, std::min(H + 1, std::atoi(e)));
+        if (o.top_h >= 0) best = std::max(lowest, std::min(H + 1, o.top_h));
+        else if (e && *e) best = std::max(lowest, std::min(H + 1, std::atoi(e)));
         p.top_h = best;
+        p.used.top_h = best;
     }
     const int top_h = p.top_h;
     if (top_h <= H) {
-        auto t0 = std::chrono::steady_clock::now();
-        std::vector<int> top;
-        for (int id = 0; id < nn; ++id)
-            if (t.nodes[id].height >= top_h) top.push_back(id);     // post-order
-        std::vector<int32_t> tmap(f.n, -1);
-        int64_t nt = 0;
-        for (int id : top)
-            for (int i = 0; i < f.fronts[id].nI; ++i) {
-                tmap[f.fronts[id].off + i] = (int32_t)nt++;
-                p.top_pos.push_back(f.fronts[id].off + i);
+        std::shared_ptr<const TopPart> tp;
+        auto hit = f.top_cache.find(top_h);
+        if (hit != f.top_cache.end() && hit->second->eps == f.eps) tp = hit->second;
+        if (!tp) {
+            auto t0 = std::chrono::steady_clock::now();
+            auto np = std::make_shared<TopPart>();
+            TopPart& T = *np;
+            T.eps = f.eps;
+            std::vector<int> top;
+            for (int id = 0; id < nn; ++id)
+                if (t.nodes[id].height >= top_h) top.push_back(id);     // post-order
+            std::vector<int32_t> tmap(f.n, -1);
+            int64_t nt = 0;
+            for (int id : top)
+                for (int i = 0; i < f.fronts[id].nI; ++i) {
+                    tmap[f.fronts[id].off + i] = (int32_t)nt++;
+                    T.pos.push_back(f.fronts[id].off + i);
+                }
+            if (nt > PLAN_TOP_MAX) { err = "dense top too large"; return false; }
+            T.n_top = nt;
+            // bottom roots: the update vector of each one covers its boundary,
+            // which lies in the top
+            std::vector<std::vector<int64_t>> lists(nt);
+            for (int id = 0; id < nn; ++id) {
+                const NdNode& nd = t.nodes[id];
+                if (nd.height >= top_h || nd.parent < 0 || t.nodes[nd.parent].height < top_h) continue;
+                const Front& fr = f.fronts[id];
+                for (int r = 0; r < fr.nB; ++r) {
+                    const int32_t ti = tmap[fr.B[r]];
+                    if (ti < 0) { err = "boundary of a bottom root outside the top"; return false; }
+                    lists[ti].push_back(p.nodes[id].upd + r);
+                }
             }
-        if (nt > PLAN_TOP_MAX) { err = "dense top too large"; return false; }
-        p.n_top = nt;
-        // bottom roots: the update vector of each one covers its boundary,
-        // which lies in the top
-        std::vector<std::vector<int64_t>> lists(nt);
-        for (int id = 0; id < nn; ++id) {
-            const NdNode& nd = t.nodes[id];
-            if (nd.height >= top_h || nd.parent < 0 || t.nodes[nd.parent].height < top_h) continue;
-            const Front& fr = f.fronts[id];
-            for (int r = 0; r < fr.nB; ++r) {
-                const int32_t ti = tmap[fr.B[r]];
-                if (ti < 0) { err = "boundary of a bottom root outside the top"; return false; }
-                lists[ti].push_back(p.nodes[id].upd + r);
+            T.gptr.assign(nt + 1, 0);
+            for (int64_t k = 0; k < nt; ++k) {
+                T.gptr[k + 1] = T.gptr[k] + (int32_t)lists[k].size();
+                for (int64_t src : lists[k]) T.gsrc.push_back(src);
             }
+            if (T.gsrc.empty()) T.gsrc.push_back(0);
+            top_inverse(f, top, tmap, nt, T.inv, n_threads);
+            if (f.eps > 0.0 && f.dim > 0 && (int64_t)f.xyz.size() >= f.n * f.dim) {
+                // hierarchical form: bisection order of the top vertices, then
+                // low-rank off-diagonal blocks at relative accuracy eps
+                std::vector<double> xt((size_t)nt * f.dim);
+                for (int64_t k = 0; k < nt; ++k)
+                    for (int d = 0; d < f.dim; ++d) xt[k * f.dim + d] = f.xyz[T.pos[k] * f.dim + d];
+                std::vector<int64_t> ord;
+                hodlr_order(nt, xt.data(), f.dim, PLAN_HODLR_LEAF, ord);
+                std::vector<double> Ap((size_t)nt * nt);
+                for (int64_t a = 0; a < nt; ++a)
+                    for (int64_t b = 0; b < nt; ++b) Ap[(size_t)a * nt + b] = T.inv[(size_t)ord[a] * nt + ord[b]];
+                std::vector<int64_t> pos(nt);
+                std::vector<int32_t> gptr(nt + 1, 0);
+                std::vector<int64_t> gsrc;
+                for (int64_t a = 0; a < nt; ++a) {
+                    pos[a] = T.pos[ord[a]];
+                    for (int32_t q = T.gptr[ord[a]]; q < T.gptr[ord[a] + 1]; ++q) gsrc.push_back(T.gsrc[q]);
+                    gptr[a + 1] = (int32_t)gsrc.size();
+                }
+                if (gsrc.empty()) gsrc.push_back(0);
+                T.pos.swap(pos);
+                T.gptr.swap(gptr);
+                T.gsrc.swap(gsrc);
+                hodlr_build(Ap, nt, f.eps, PLAN_HODLR_LEAF, n_threads, T.hd);
+                std::vector<double>().swap(T.inv);
+                T.hodlr = true;
+                for (size_t b = 0; b < T.hd.blocks.size(); ++b)
+                    for (int j = 0; j < 2 * T.hd.blocks[b].k; ++j) T.cols.push_back((int32_t)((b << 16) | j));
+                if (T.hd.blocks.size() >= (1u << 15) || T.hd.max_rank >= (1 << 15)) {
+                    err = "hierarchical top too large";
+                    return false;
+                }
+            }
+            T.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            f.top_cache[top_h] = np;
+            tp = np;
         }
-        p.top_gptr.assign(nt + 1, 0);
-        for (int64_t k = 0; k < nt; ++k) {
-            p.top_gptr[k + 1] = p.top_gptr[k] + (int32_t)lists[k].size();
-            for (int64_t src : lists[k]) p.top_gsrc.push_back(src);
-        }
-        if (p.top_gsrc.empty()) p.top_gsrc.push_back(0);
-        top_inverse(f, top, tmap, nt, p.top_inv, n_threads);
-        if (f.eps > 0.0 && f.dim > 0 && (int64_t)f.xyz.size() >= f.n * f.dim) {
-            // hierarchical form: bisection order of the top vertices, then
-            // low-rank off-diagonal blocks at relative accuracy eps
-            std::vector<double> xt((size_t)nt * f.dim);
-            for (int64_t k = 0; k < nt; ++k)
-                for (int d = 0; d < f.dim; ++d) xt[k * f.dim + d] = f.xyz[p.top_pos[k] * f.dim + d];
-            std::vector<int64_t> ord;
-            hodlr_order(nt, xt.data(), f.dim, PLAN_HODLR_LEAF, ord);
-            std::vector<double> Ap((size_t)nt * nt);
-            for (int64_t i = 0; i < nt; ++i)
-                for (int64_t j = 0; j < nt; ++j) Ap[(size_t)i * nt + j] = p.top_inv[(size_t)ord[i] * nt + ord[j]];
-            std::vector<int64_t> pos(nt);
-            std::vector<int32_t> gptr(nt + 1, 0);
-            std::vector<int64_t> gsrc;
-            for (int64_t i = 0; i < nt; ++i) {
-                pos[i] = p.top_pos[ord[i]];
-                for (int32_t q = p.top_gptr[ord[i]]; q < p.top_gptr[ord[i] + 1]; ++q) gsrc.push_back(p.top_gsrc[q]);
-                gptr[i + 1] = (int32_t)gsrc.size();
-            }
-            if (gsrc.empty()) gsrc.push_back(0);
-            p.top_pos.swap(pos);
-            p.top_gptr.swap(gptr);
-            p.top_gsrc.swap(gsrc);
-            hodlr_build(Ap, nt, f.eps, PLAN_HODLR_LEAF, n_threads, p.hodlr);
-            std::vector<double>().swap(p.top_inv);
-            p.top_hodlr = true;
-            for (size_t b = 0; b < p.hodlr.blocks.size(); ++b)
-                for (int j = 0; j < 2 * p.hodlr.blocks[b].k; ++j) p.hodlr_cols.push_back((int32_t)((b << 16) | j));
-            if (p.hodlr.blocks.size() >= (1u << 15) || p.hodlr.max_rank >= (1 << 15)) {
-                err = "hierarchical top too large";
-                return false;
-            }
-        }
-        p.top_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        p.n_top = tp->n_top;
+        p.top_pos = tp->pos;
+        p.top_gptr = tp->gptr;
+        p.top_gsrc = tp->gsrc;
+        p.top_inv = tp->inv;
+        p.top_hodlr = tp->hodlr;
+        p.hodlr = tp->hd;
+        p.hodlr_cols = tp->cols;
+        p.top_seconds = tp->seconds;
     }
 
     // ---- level phases above the cut ------------------------------------------
@@ -395,8 +417,12 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads)
     // Splitting a tile over several items exposes more workgroups but needs a
     // cross-workgroup combine (device-scope fence), so the limits are tunable
     // (environment BIDO_FWD_COLS, BIDO_BWD_MAXR) within the LDS staging bound.
-    const int fwd_cols = env_limit("BIDO_FWD_COLS", PLAN_FWD_COLS, 32, PLAN_LDS_DOUBLES);
-    const int bwd_maxr = env_limit("BIDO_BWD_MAXR", PLAN_BWD_MAXR, 64, PLAN_LDS_DOUBLES);
+    const int fwd_cols = o.fwd_cols > 0 ? std::max(32, std::min(PLAN_LDS_DOUBLES, o.fwd_cols))
+                                        : env_limit("BIDO_FWD_COLS", PLAN_FWD_COLS, 32, PLAN_LDS_DOUBLES);
+    const int bwd_maxr = o.bwd_rows > 0 ? std::max(64, std::min(PLAN_LDS_DOUBLES, o.bwd_rows))
+                                        : env_limit("BIDO_BWD_MAXR", PLAN_BWD_MAXR, 64, PLAN_LDS_DOUBLES);
+    p.used.fwd_cols = fwd_cols;
+    p.used.bwd_rows = bwd_maxr == PLAN_BWD_MAXR ? 0 : bwd_maxr;
     std::vector<std::pair<size_t, size_t>> fspan, bspan, fcspan, bcspan;
     struct LdsSz { size_t f, b; };
     std::vector<LdsSz> lds;

@@ -10,6 +10,15 @@
 
 namespace bido {
 
+// Work-item shapes and the top cut; values <= 0 (top_h < 0) take the
+// defaults (environment BIDO_FWD_COLS / BIDO_BWD_MAXR / BIDO_TOP_H, else the
+// built-in sizes and the cost model of the cut).
+struct PlanOptions {
+    int fwd_cols = 0;   // columns per forward level item
+    int bwd_rows = 0;   // rows per backward level item (0: 8192 / tile width, at most 512)
+    int top_h = -1;     // first height of the top (raised to fit the top-size bound)
+};
+
 struct FactorPlan {
     int64_t n = 0, ground = -1;
     int height = 0;
@@ -51,6 +60,7 @@ struct FactorPlan {
     std::vector<double> fwd_bytes64, bwd_bytes64, fwd_bytes32, bwd_bytes32;
     double sub_fwd_bytes64 = 0, sub_bwd_bytes64 = 0, sub_fwd_bytes32 = 0, sub_bwd_bytes32 = 0;
     int64_t meta_bytes = 0;
+    PlanOptions used;                   // the options the plan was built with
 };
 
 // Limits and tile sizes the kernels rely on.
@@ -65,7 +75,8 @@ constexpr int PLAN_TOP_MAX = 6144;     // max n_top (w_top staged in LDS, FP64)
 constexpr int PLAN_HODLR_LEAF = 64;    // leaf size of the hierarchical top
 
 // n_threads: host threads for S_top^-1 (<= 0: OpenMP default).
-bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads = 0);
+bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads = 0,
+                const PlanOptions* opt = nullptr);
 
 // CPU emulation of the sweep kernels over the plan: x = (L L^T)^-1 b.
 void emulate_plan(const FactorPlan& p, const double* b, double* x);

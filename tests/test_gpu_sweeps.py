@@ -106,3 +106,24 @@ def test_hierarchical_top_matches_emulation(torch, name, eps, monkeypatch):
               f"vs exact {e_ex:.2e}", flush=True)
         assert np.isfinite(x).all() and e_emu < 1e-12
         assert e_ex <= 1e3 * eps + 1e-12
+
+
+def test_autotune_keeps_the_factor(torch):
+    """The autotuner times candidate plans on the device and keeps the
+    fastest; the inner solves still reproduce the host factor."""
+    import paper_1711_08708_amd as B
+    cfg = CASES["thorax40k"]()
+    hs = B.HostSetup(cfg, eps_h=0.0)
+    solver = B.Solver(cfg, eps_h=0.0)
+    rep = solver.autotune(reps=3)
+    print("autotune:", rep, flush=True)
+    assert rep["candidates"] > 0
+    assert all(a <= b * 1.05 for a, b in zip(rep["us_after"], rep["us_before"]))
+    for which in (0, 1):
+        n = solver.N if which == 0 else solver.NH
+        b = np.random.default_rng(6 + which).normal(size=n)
+        ref = hs.factor_apply(which, b)
+        xd = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        solver.inner_solve(which, torch.tensor(b, device="cuda"), xd)
+        x = xd.cpu().numpy()
+        assert np.isfinite(x).all() and np.abs(x - ref).max() / np.abs(ref).max() < 1e-12
