@@ -109,3 +109,24 @@ def test_monodomain_is_an_approximation(blocks):
     x, it, hist = bl.pcg(s.Lam, Y, bl.block_prec(b, P1, bl.chol_solver(Km)), tol=1e-10)
     assert 1 < it < 20
     assert bd.rel_err(s.normalise(x), s.solve_dense(Y)) < 1e-8
+
+
+def test_iterations_stay_bounded_under_refinement():
+    """Sec. 5 and 6: with exact P_1 and P_K = K_m the preconditioned
+    spectrum does not depend on the mesh size, so the PCG iteration count of
+    the block-LU / monodomain preconditioner stays flat (up to a log factor)
+    while the mesh is refined 4x per direction."""
+    its = []
+    for n in (12, 24, 48):
+        s = bd.System(w.square2d(n=n, seed=0))
+        b = bl.dense_blocks(s)
+        P1 = bl.grounded_solver(b["S1"])
+        PK = bl.chol_solver(bl.K_monodomain(b))
+        rng = np.random.default_rng(3)
+        Y = s.rhs(rng.uniform(0, 100, b["NH"]), rng.uniform(0, 1, b["NH"]), 0)
+        _, it, _ = bl.pcg(s.Lam, Y, bl.block_prec(b, P1, PK), tol=1e-10)
+        its.append(it)
+    print("iterations for n = 12, 24, 48:", its)
+    lg = np.log([13 * 13, 25 * 25, 49 * 49])
+    assert max(its) <= (lg[-1] / lg[0]) ** 2 * min(its)
+    assert its[-1] <= its[0] + 3
