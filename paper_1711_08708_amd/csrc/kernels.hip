@@ -352,29 +352,49 @@ __device__ __forceinline__ void store_row(const TriNode& nd, int r, double s, co
     }
 }
 
+// Independent loads in flight per lane in the sweeps' inner loops.
+constexpr int SWEEP_ILP = 8;
+__device__ __forceinline__ double sum_ilp(const double (&a)[SWEEP_ILP]) {
+    double s[SWEEP_ILP / 2];
+#pragma unroll
+    for (int k = 0; k < SWEEP_ILP / 2; ++k) s[k] = a[2 * k] + a[2 * k + 1];
+#pragma unroll
+    for (int w = SWEEP_ILP / 4; w >= 1; w >>= 1)
+#pragma unroll
+        for (int k = 0; k < w; ++k) s[k] = s[2 * k] + s[2 * k + 1];
+    return s[0];
+}
+
 // sum_{c in [cs, ce), c <= r if r < nI} P(r, c) w[c - cs]   (column-major copy).
 // Entry (r, c) sits at col_off(c) + r - c; moving to column c+1 adds
-// nI + nB - c - 1.  Eight independent accumulators keep eight loads in flight.
+// nI + nB - c - 1.  SWEEP_ILP independent accumulators keep that many loads
+// in flight.
 template <typename T>
 __device__ __forceinline__ double row_part(const T* __restrict__ Pc, int nI, int nB, int r, int cs,
                                            int ce, const double* w) {
     const int cend = r < nI ? min(ce, r + 1) : ce;
     const int nF = nI + nB;
     int64_t off = panel_col_off(cs, nI, nB) + (r - cs);
-    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int c = cs;
-    for (; c + 8 <= cend; c += 8) {
+    double a[SWEEP_ILP];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < SWEEP_ILP; ++k) a[k] = 0.0;
+    int c = cs;
+    for (; c + SWEEP_ILP <= cend; c += SWEEP_ILP) {
+#pragma unroll
+        for (int k = 0; k < SWEEP_ILP; ++k) {
             a[k] += (double)Pc[off] * w[c + k - cs];
             off += nF - (c + k) - 1;
         }
     }
-    for (int k = 0; c < cend; ++c, ++k) {
-        a[k] += (double)Pc[off] * w[c - cs];
-        off += nF - c - 1;
+    // remainder (< SWEEP_ILP columns): predicated, one accumulator each
+#pragma unroll
+    for (int k = 0; k < SWEEP_ILP - 1; ++k) {
+        if (c + k < cend) {
+            a[k] += (double)Pc[off] * w[c + k - cs];
+            off += nF - (c + k) - 1;
+        }
     }
-    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    return sum_ilp(a);
 }
 
 // Offset of row r in a packed row-major panel, in 32-bit arithmetic (a
@@ -393,33 +413,39 @@ __device__ __forceinline__ double col_part(const T* __restrict__ P, int nI, int 
                                            const double* z, int z0) {
     const int lgS = __ffs(S) - 1;
     const int SS = (S * (S + 1)) >> 1;
-    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double a[SWEEP_ILP];
+#pragma unroll
+    for (int k = 0; k < SWEEP_ILP; ++k) a[k] = 0.0;
     int r = r0;
     int off = row_off32(r, nI);
     const int te = min(re, nI);
-    for (; r + 7 * S < te; r += 8 * S) {
+    for (; r + (SWEEP_ILP - 1) * S < te; r += SWEEP_ILP * S) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < SWEEP_ILP; ++q) {
             const int rr = r + q * S;
             if (c <= rr) a[q] += (double)P[off + c] * z[rr - z0];
             off = rr + S <= nI ? off + (rr << lgS) + SS : row_off32(rr + S, nI);
         }
     }
-    for (; r < te; r += S) {
-        if (c <= r) a[0] += (double)P[off + c] * z[r - z0];
-        off = r + S <= nI ? off + (r << lgS) + SS : row_off32(r + S, nI);
-    }
-    const int step = S * nI;
-    for (; r + 7 * S < re; r += 8 * S) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) a[q] += (double)P[off + q * step + c] * z[r + q * S - z0];
-        off += 8 * step;
+    for (int q = 0; q < SWEEP_ILP - 1; ++q) {
+        const int rr = r + q * S;
+        if (rr < te) {
+            if (c <= rr) a[q] += (double)P[off + c] * z[rr - z0];
+            off = rr + S <= nI ? off + (rr << lgS) + SS : row_off32(rr + S, nI);
+        }
     }
-    for (; r < re; r += S) {
-        a[1] += (double)P[off + c] * z[r - z0];
-        off += step;
+    if (r < te) r += ((te - r + S - 1) >> lgS) << lgS;   // first row of the sequence at or past te
+    const int step = S * nI;
+    for (; r + (SWEEP_ILP - 1) * S < re; r += SWEEP_ILP * S) {
+#pragma unroll
+        for (int q = 0; q < SWEEP_ILP; ++q) a[q] += (double)P[off + q * step + c] * z[r + q * S - z0];
+        off += SWEEP_ILP * step;
     }
-    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+#pragma unroll
+    for (int q = 0; q < SWEEP_ILP - 1; ++q)
+        if (r + q * S < re) a[q] += (double)P[off + q * step + c] * z[r + q * S - z0];
+    return sum_ilp(a);
 }
 
 // Subtree phase, forward: workgroup s walks its subtree from the leaves up;
