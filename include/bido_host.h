@@ -78,6 +78,14 @@ bido_status bido_host_factor_emulate(const bido_host* h, int which, const double
 bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n_sub, int* n_levels,
                                   int64_t* n_fwd_items, int64_t* n_bwd_items);
 
+/* Test hook for batches of independent slices: a host object whose factors
+ * are the forests of the slices' factors (the factors of the block-diagonal
+ * union), slice s at offset O_s = sum_{t<s} (N_t + N_H,t): P_1 on
+ * [O_s, O_s + N_s), P_K on [O_s + N_s, O_s + N_s + N_H,s), vectors of
+ * sum_s (N_s + N_H,s) entries.  Only the bido_host_factor_* entry points
+ * apply to it; free it with bido_host_free.                               */
+bido_status bido_host_merge(const bido_host* const* hs, int n, bido_host** out);
+
 /* Dense top of that plan: the tree nodes of height >= top_h are solved as
  * one product with the explicit inverse of their Schur complement (the
  * Cholesky factor of Sec. 5.3 restricted to the top separators, inverted

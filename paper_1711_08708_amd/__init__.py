@@ -175,6 +175,8 @@ ABI = {
     "bido_host_factor_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                              _c_i64_p, _c_i64_p]),
+    "bido_host_merge": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_void_p)]),
     "bido_host_factor_top": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _c_i64_p,
                                             ctypes.POINTER(ctypes.c_double), _c_i64_p, ctypes.POINTER(ctypes.c_int)]),
     "bido_host_factor_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p,
@@ -479,6 +481,19 @@ class HostSetup:
                                    ctypes.byref(self.params), ctypes.byref(h)), host=True)
         del keep
         self.h = h
+
+    @classmethod
+    def merged(cls, parts):
+        """Host object of the forest of the parts' factors (test hook): slice s
+        at offset sum_{t<s} (N_t + N_H,t), P_1 first, then P_K."""
+        obj = cls.__new__(cls)
+        arr = (ctypes.c_void_p * len(parts))(*[p.h.value for p in parts])
+        h = ctypes.c_void_p()
+        _check(lib.bido_host_merge(arr, len(parts), ctypes.byref(h)), host=True)
+        obj.h = h
+        obj.parts = list(parts)
+        obj.params = parts[0].params
+        return obj
 
     def csr(self, which):
         import scipy.sparse as sp

@@ -130,6 +130,7 @@ struct FactorDev {
         hipFree((void*)plan.hblocks); hipFree((void*)plan.hleaves); hipFree((void*)plan.hanc);
         hipFree((void*)plan.hcols); hipFree(plan.ht);
         hipFree((void*)plan.top_pos); hipFree((void*)plan.top_gptr); hipFree((void*)plan.top_gsrc);
+        hipFree((void*)plan.top_zero);
         hipFree(plan.top_w);
         nodes = nullptr; panel64 = nullptr; panel32 = nullptr; panel64_cm = nullptr; panel32_cm = nullptr;
         ea = nullptr; bidx = nullptr;
@@ -194,8 +195,10 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
     fd.top_seconds = p.top_seconds;
     fd.plan.n_top = p.n_top;
     if (p.n_top > 0) {
-        int64_t* pos = nullptr; int32_t* gptr = nullptr; int64_t* gsrc = nullptr;
+        int64_t* pos = nullptr; int32_t* gptr = nullptr; int64_t* gsrc = nullptr; uint8_t* zero = nullptr;
         HIP_OK(upload(&pos, p.top_pos.data(), p.top_pos.size()));
+        HIP_OK(upload(&zero, p.top_zero.data(), p.top_zero.size()));
+        fd.plan.top_zero = zero;
         HIP_OK(upload(&gptr, p.top_gptr.data(), p.top_gptr.size()));
         HIP_OK(upload(&gsrc, p.top_gsrc.data(), p.top_gsrc.size()));
         fd.plan.top_pos = pos; fd.plan.top_gptr = gptr; fd.plan.top_gsrc = gsrc;
@@ -391,15 +394,14 @@ void tri_solve(bido_ctx* c, const FactorDev& f, const T* panel, const T* panel_c
     const bool f32 = sizeof(T) == 4;
     const int hc = f.plan.hc;
     PROF(c, K_TRI_FWD_SUB, f32 ? f.sub_fwd_bytes32 : f.sub_fwd_bytes64,
-         launch_tri_fwd_sub<T>(s, f.plan, f.nodes, panel_cm, f.ea, in, f.ytmp, f.upd, f.ground));
+         launch_tri_fwd_sub<T>(s, f.plan, f.nodes, panel_cm, f.ea, in, f.ytmp, f.upd));
     for (size_t k = 0; k < f.top.size(); ++k) {
         const int h = hc + 1 + (int)k;
         PROF(c, K_TRI_FWD_LVL, f32 ? f.fwd_bytes32[h] : f.fwd_bytes64[h],
-             launch_tri_fwd_lvl<T>(s, f.top[k], f.plan, f.nodes, panel_cm, f.ea, in, f.ytmp, f.upd,
-                                   f.ground));
+             launch_tri_fwd_lvl<T>(s, f.top[k], f.plan, f.nodes, panel_cm, f.ea, in, f.ytmp, f.upd));
     }
     PROF(c, K_TRI_TOP, f32 ? f.top_bytes32 : f.top_bytes64,
-         launch_tri_top<T>(s, f.plan, top_inv<T>(f), in, f.upd, f.ground, out));
+         launch_tri_top<T>(s, f.plan, top_inv<T>(f), in, f.upd, out));
     for (size_t k = f.top.size(); k-- > 0;) {
         const int h = hc + 1 + (int)k;
         PROF(c, K_TRI_BWD_LVL, f32 ? f.bwd_bytes32[h] : f.bwd_bytes64[h],

@@ -139,6 +139,7 @@ struct TopPart {
 struct Factor {
     int64_t n = 0;
     int64_t ground = -1;             // grounded index (new order) or -1
+    std::vector<int64_t> grounds;    // every grounded index (several in a merged forest)
     NdTree tree;
     std::vector<Front> fronts;       // indexed like tree.nodes
     // hierarchical compression (eps = 0: exact); vertex coordinates in tree order
@@ -177,6 +178,11 @@ void hodlr_order(int64_t n, const double* xyz, int dim, int leaf, std::vector<in
 void hodlr_build(const std::vector<double>& A, int64_t n, double eps, int leaf, int n_threads, Hodlr& h);
 // y = A w from the hierarchical form.
 void hodlr_apply(const Hodlr& h, const double* w, double* y);
+
+// Factor of a block-diagonal matrix from the factors of its blocks: block s
+// at indices [offs[s], offs[s] + n_s) of n_total; the trees become a forest.
+void merge_factors(const std::vector<const Factor*>& fs, const std::vector<int64_t>& offs, int64_t n_total,
+                   Factor& out);
 
 // Host application of the factor (test hook): x = (L L^T)^-1 b with the
 // grounded entry fixed to zero.  Uses the compressed form when present.

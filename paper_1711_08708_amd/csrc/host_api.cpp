@@ -150,6 +150,28 @@ bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n
     return BIDO_OK;
 }
 
+bido_status bido_host_merge(const bido_host* const* hs, int n, bido_host** out) {
+    if (!hs || n < 1 || !out) return hfail(BIDO_ERR_ARG, "null argument");
+    auto m = std::make_unique<bido_host>();
+    std::vector<const bido::Factor*> f1, fk;
+    std::vector<int64_t> o1, ok;
+    int64_t off = 0;
+    for (int s = 0; s < n; ++s) {
+        if (!hs[s]) return hfail(BIDO_ERR_ARG, "null host set-up");
+        const bido::HostSetup& h = hs[s]->hs;
+        f1.push_back(&h.p1);
+        fk.push_back(&h.pk);
+        o1.push_back(off);
+        ok.push_back(off + h.A.N);
+        off += h.A.N + h.A.NH;
+    }
+    bido::merge_factors(f1, o1, off, m->hs.p1);
+    bido::merge_factors(fk, ok, off, m->hs.pk);
+    m->hs.params = hs[0]->hs.params;
+    *out = m.release();
+    return BIDO_OK;
+}
+
 bido_status bido_host_factor_top(const bido_host* h, int which, int* top_h, int64_t* n_top, double* seconds,
                                  int64_t* stored_entries, int* max_rank) {
     if (!h) return hfail(BIDO_ERR_ARG, "null argument");

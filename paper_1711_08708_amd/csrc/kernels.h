@@ -21,6 +21,8 @@ struct TriNode {
     int64_t u0, u1;  // update offsets of the two children (0 when absent)
     int32_t nI, nB;
     int32_t child[2];
+    int32_t gi;      // own index of a grounded vertex (its entry is fixed to 0), or -1
+    int32_t pad;
 };
 
 // Extend-add map entry: position in each child's update vector (-1: none).

@@ -330,12 +330,12 @@ __device__ __forceinline__ int pow2_ceil64(int n) {
 // w_t[i] = b[off+i] - children's updates at own position i (ground -> 0)
 __device__ __forceinline__ double gather_w(const TriNode& nd, int i, const Ea* __restrict__ ea,
                                            const double* __restrict__ b, const double* upd,
-                                           int64_t u0, int64_t u1, int64_t ground) {
+                                           int64_t u0, int64_t u1) {
     double v = b[nd.off + i];
     const Ea m = ea[nd.ea + i];
     if (m.a >= 0) v -= upd[u0 + m.a];
     if (m.b >= 0) v -= upd[u1 + m.b];
-    return (nd.off + i == ground) ? 0.0 : v;
+    return i == nd.gi ? 0.0 : v;
 }
 
 // store row r of P_t w_t: own rows to y, boundary rows (plus the children's
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __rest
                                                            const Ea* __restrict__ ea,
                                                            const double* __restrict__ b,
                                                            double* __restrict__ y,
-                                                           double* upd, int64_t ground) {
+                                                           double* upd) {
     __shared__ double wbuf[SUB_NW][SUB_MAXW];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int32_t* hoff = sub_hoff + (size_t)blockIdx.x * (hc + 2);
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __rest
             const int64_t u0 = nd.u0, u1 = nd.u1;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_wave_barrier();
-            for (int i = lane; i < nd.nI; i += WAVE) w[i] = gather_w(nd, i, ea, b, upd, u0, u1, ground);
+            for (int i = lane; i < nd.nI; i += WAVE) w[i] = gather_w(nd, i, ea, b, upd, u0, u1);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -570,15 +570,14 @@ __global__ __launch_bounds__(BLOCK) void k_tri_fwd_lvl(const TriNode* __restrict
                                                        const Ea* __restrict__ ea,
                                                        const double* __restrict__ b,
                                                        double* __restrict__ y,
-                                                       double* upd, int64_t ground,
-                                                       double* __restrict__ scratch) {
+                                                       double* upd, double* __restrict__ scratch) {
     extern __shared__ double w[];
     __shared__ double red[BLOCK / WAVE][FWD_ROWS];
     const TriItem it = items[blockIdx.x];
     const TriNode nd = nodes[it.node];
     const int64_t u0 = nd.u0, u1 = nd.u1;
     const int ncol = it.ce - it.cs;
-    for (int i = threadIdx.x; i < ncol; i += BLOCK) w[i] = gather_w(nd, it.cs + i, ea, b, upd, u0, u1, ground);
+    for (int i = threadIdx.x; i < ncol; i += BLOCK) w[i] = gather_w(nd, it.cs + i, ea, b, upd, u0, u1);
     __syncthreads();
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int nw = BLOCK / WAVE;
@@ -671,13 +670,14 @@ __global__ __launch_bounds__(WAVE) void k_tri_bwd_comb(const TriNode* __restrict
 // Dense top: w_top[k] = b[pos[k]] - sum of the bottom roots' updates at k.
 __global__ void k_top_gather(int64_t n, const int64_t* __restrict__ pos, const int32_t* __restrict__ gptr,
                              const int64_t* __restrict__ gsrc, const double* __restrict__ b,
-                             const double* __restrict__ upd, int64_t ground, double* __restrict__ w) {
+                             const double* __restrict__ upd, const uint8_t* __restrict__ zero,
+                             double* __restrict__ w) {
     const int64_t k = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
     if (k >= n) return;
     const int64_t g = pos[k];
     double v = b[g];
     for (int32_t q = gptr[k]; q < gptr[k + 1]; ++q) v -= upd[gsrc[q]];
-    w[k] = g == ground ? 0.0 : v;
+    w[k] = zero[k] ? 0.0 : v;
 }
 
 // x[pos[i]] = sum_j inv[i][j] w[j]: one wave per row, w staged in LDS,
@@ -895,11 +895,11 @@ void launch_p_update(hipStream_t s, int64_t n, const double* z, double* p, doubl
 
 template <typename T>
 void launch_tri_top(hipStream_t s, const TriPlan& P, const T* inv, const double* b, const double* upd,
-                    int64_t ground, double* x) {
+                    double* x) {
     const int64_t n = P.n_top;
     if (n <= 0) return;
     k_top_gather<<<(unsigned)((n + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(n, P.top_pos, P.top_gptr, P.top_gsrc, b,
-                                                                        upd, ground, P.top_w);
+                                                                        upd, P.top_zero, P.top_w);
     if (P.n_hleaves > 0) {
         if (P.n_hcols > 0)
             k_hodlr_proj<T><<<(unsigned)((P.n_hcols + BLOCK / WAVE - 1) / (BLOCK / WAVE)), BLOCK, 0, s>>>(
@@ -914,9 +914,9 @@ void launch_tri_top(hipStream_t s, const TriPlan& P, const T* inv, const double*
 
 template <typename T>
 void launch_tri_fwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel_cm,
-                        const Ea* ea, const double* b, double* y, double* upd, int64_t ground) {
+                        const Ea* ea, const double* b, double* y, double* upd) {
     if (P.n_sub == 0) return;
-    k_tri_fwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel_cm, ea, b, y, upd, ground);
+    k_tri_fwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel_cm, ea, b, y, upd);
 }
 template <typename T>
 void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
@@ -926,10 +926,9 @@ void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, c
 }
 template <typename T>
 void launch_tri_fwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
-                        const T* panel_cm, const Ea* ea, const double* b, double* y, double* upd,
-                        int64_t ground) {
+                        const T* panel_cm, const Ea* ea, const double* b, double* y, double* upd) {
     if (L.n_fwd == 0) return;
-    k_tri_fwd_lvl<T><<<L.n_fwd, BLOCK, L.lds_f, s>>>(nodes, L.fwd, panel_cm, ea, b, y, upd, ground, P.scratch);
+    k_tri_fwd_lvl<T><<<L.n_fwd, BLOCK, L.lds_f, s>>>(nodes, L.fwd, panel_cm, ea, b, y, upd, P.scratch);
     if (L.n_fcomb > 0)
         k_tri_fwd_comb<<<(L.n_fcomb + BLOCK / WAVE - 1) / (BLOCK / WAVE), BLOCK, 0, s>>>(nodes, L.fcomb, L.n_fcomb,
                                                                                        ea, y, upd, P.scratch);
@@ -944,15 +943,15 @@ void launch_tri_bwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, c
 
 #define BIDO_INST(T)                                                                                   \
     template void launch_tri_fwd_sub<T>(hipStream_t, const TriPlan&, const TriNode*, const T*,         \
-                                        const Ea*, const double*, double*, double*, int64_t);          \
+                                        const Ea*, const double*, double*, double*);                   \
     template void launch_tri_bwd_sub<T>(hipStream_t, const TriPlan&, const TriNode*, const T*,         \
                                         const int64_t*, const double*, double*);                       \
     template void launch_tri_fwd_lvl<T>(hipStream_t, const TriTopLevel&, const TriPlan&, const TriNode*, \
-                                        const T*, const Ea*, const double*, double*, double*, int64_t); \
+                                        const T*, const Ea*, const double*, double*, double*);           \
     template void launch_tri_bwd_lvl<T>(hipStream_t, const TriTopLevel&, const TriPlan&, const TriNode*, \
                                         const T*, const int64_t*, const double*, double*);               \
     template void launch_tri_top<T>(hipStream_t, const TriPlan&, const T*, const double*, const double*, \
-                                    int64_t, double*);
+                                    double*);
 BIDO_INST(double)
 BIDO_INST(float)
 #undef BIDO_INST

@@ -53,6 +53,7 @@ struct TriPlan {
     // dense top (n_top = 0: none): x[top_pos] = S_top^-1 w_top
     int64_t n_top = 0;
     const int64_t* top_pos = nullptr;
+    const uint8_t* top_zero = nullptr;
     const int32_t* top_gptr = nullptr;
     const int64_t* top_gsrc = nullptr;
     double* top_w = nullptr;
@@ -86,7 +87,7 @@ void launch_spmv_csr(hipStream_t s, const CsrDev& A, int group, const double* x,
 // value array of the hierarchical form)
 template <typename T>
 void launch_tri_top(hipStream_t s, const TriPlan& P, const T* inv, const double* b, const double* upd,
-                    int64_t ground, double* x);
+                    double* x);
 unsigned launch_pcg_update(hipStream_t s, int64_t n, double* x, double* r, double* r_old, const double* p,
                            const double* q, double* pp, unsigned nb_pq, int rho_slot);
 unsigned launch_combine_dot(hipStream_t s, int64_t n1, int64_t n, double* z, const double* a, const double* b,
@@ -96,14 +97,13 @@ void launch_p_update(hipStream_t s, int64_t n, const double* z, double* p, doubl
 
 template <typename T>
 void launch_tri_fwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
-                        const Ea* ea, const double* b, double* y, double* upd, int64_t ground);
+                        const Ea* ea, const double* b, double* y, double* upd);
 template <typename T>
 void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
                         const int64_t* bidx, const double* y, double* x);
 template <typename T>
 void launch_tri_fwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
-                        const T* panel_cm, const Ea* ea, const double* b, double* y, double* upd,
-                        int64_t ground);
+                        const T* panel_cm, const Ea* ea, const double* b, double* y, double* upd);
 template <typename T>
 void launch_tri_bwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
                         const T* panel, const int64_t* bidx, const double* y, double* x);

@@ -97,6 +97,8 @@ bool multifrontal(const Csr& a0, Factor& f, int64_t ground, int n_threads,
     const int nn = (int)t.nodes.size();
     f.n = a.n;
     f.ground = ground;
+    f.grounds.clear();
+    if (ground >= 0) f.grounds.push_back(ground);
     f.fronts.assign(nn, Front());
 
     // ---- symbolic: boundary sets, children first (post-order) -----------
@@ -306,12 +308,14 @@ void panel_apply_t(const Front& fr, const double* z, double* out) {
 void host_solve(const Factor& f, const double* b, double* x) {
     const int64_t n = f.n;
     std::vector<double> acc(n, 0.0), y(n, 0.0), w, out;
+    std::vector<char> gnd(n, 0);
+    for (int64_t g : f.grounds) gnd[g] = 1;
     for (const Front& fr : f.fronts) {   // post-order
         w.resize(fr.nI);
         out.resize(fr.nI + fr.nB);
         for (int i = 0; i < fr.nI; ++i) {
             int64_t g = fr.off + i;
-            w[i] = (g == f.ground) ? 0.0 : b[g] - acc[g];
+            w[i] = gnd[g] ? 0.0 : b[g] - acc[g];
         }
         panel_apply(fr, w.data(), out.data());
         for (int i = 0; i < fr.nI; ++i) y[fr.off + i] = out[i];
@@ -327,6 +331,56 @@ void host_solve(const Factor& f, const double* b, double* x) {
         panel_apply_t(fr, w.data(), out.data());
         for (int i = 0; i < fr.nI; ++i) x[fr.off + i] = out[i];
     }
+}
+
+}  // namespace bido
+
+namespace bido {
+
+// Disjoint union of factors (the factor of a block-diagonal matrix): factor
+// s occupies indices [offs[s], offs[s] + n_s) of an index space of n_total
+// entries (indices outside every factor are never touched); tree nodes and
+// boundary indices are shifted and the trees become one forest.
+void merge_factors(const std::vector<const Factor*>& fs, const std::vector<int64_t>& offs, int64_t n_total,
+                   Factor& out) {
+    out = Factor();
+    out.n = n_total;
+    out.ground = -1;
+    out.eps = fs.empty() ? 0.0 : fs[0]->eps;
+    out.eta = fs.empty() ? 2.0 : fs[0]->eta;
+    out.dim = fs.empty() ? 0 : fs[0]->dim;
+    bool coords = out.dim > 0;
+    for (const Factor* f : fs) coords = coords && f->dim == out.dim && (int64_t)f->xyz.size() >= f->n * f->dim;
+    if (coords) out.xyz.assign((size_t)n_total * out.dim, 0.0);
+    else out.dim = 0;
+    int node_off = 0;
+    for (size_t s = 0; s < fs.size(); ++s) {
+        const Factor& f = *fs[s];
+        const int64_t o = offs[s];
+        for (int64_t g : f.grounds) out.grounds.push_back(g + o);
+        if (coords)
+            for (int64_t i = 0; i < f.n * f.dim; ++i) out.xyz[o * f.dim + i] = f.xyz[i];
+        for (const NdNode& nd : f.tree.nodes) {
+            NdNode m = nd;
+            m.begin += o;
+            m.end += o;
+            m.sub_begin += o;
+            if (m.parent >= 0) m.parent += node_off;
+            for (int& ch : m.child)
+                if (ch >= 0) ch += node_off;
+            out.tree.nodes.push_back(m);
+        }
+        for (const Front& fr : f.fronts) {
+            Front m = fr;
+            m.node += node_off;
+            m.off += o;
+            for (int64_t& b : m.B) b += o;
+            out.fronts.push_back(std::move(m));
+        }
+        out.tree.height = std::max(out.tree.height, f.tree.height);
+        node_off += (int)f.tree.nodes.size();
+    }
+    out.tree.root = -1;
 }
 
 }  // namespace bido

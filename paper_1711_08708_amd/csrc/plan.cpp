@@ -73,6 +73,8 @@ void top_inverse(const Factor& f, const std::vector<int>& top, const std::vector
         }
     }
     inv.assign((size_t)ntop * ntop, 0.0);
+    std::vector<char> gnd(f.n, 0);
+    for (int64_t g : f.grounds) gnd[g] = 1;
     const int64_t nblk = (ntop + TB - 1) / TB;
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : omp_get_max_threads())
     {
@@ -90,7 +92,7 @@ void top_inverse(const Factor& f, const std::vector<int>& top, const std::vector
                 W.assign((size_t)nI * TB, 0.0);
                 for (int i = 0; i < nI; ++i) {
                     const int64_t g = fr.off + i, ti = tmap[g];
-                    if (g == f.ground) continue;
+                    if (gnd[g]) continue;
                     for (int k = 0; k < m; ++k)
                         W[(size_t)i * TB + k] = (ti == j0 + k ? 1.0 : 0.0) - acc[(size_t)ti * TB + k];
                 }
@@ -184,6 +186,9 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
         TriNode& d = p.nodes[id];
         d.u0 = d.child[0] >= 0 ? p.nodes[d.child[0]].upd : 0;
         d.u1 = d.child[1] >= 0 ? p.nodes[d.child[1]].upd : 0;
+        d.gi = -1;
+        for (int64_t g : f.grounds)
+            if (g >= d.off && g < d.off + d.nI) d.gi = (int32_t)(g - d.off);
     }
     p.panel.assign((size_t)poff, 0.0);
     p.panel_cm.assign((size_t)poff, 0.0);
@@ -291,20 +296,34 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     p.sub_tn.clear();
     for (int id : p.sub_nodes) p.sub_tn.push_back(p.nodes[id]);
 
-    // ---- dense top: cut height by a cost model -----------------------------------
+    // ---- top: cut height by a cost model -------------------------------------
     // A level of the sweeps costs about one forward and one backward launch
     // of dependent memory latency (or its panel bytes at level-phase
-    // bandwidth when larger); the dense top costs two launches plus n_top^2
-    // FP64 entries at streaming bandwidth.  Environment BIDO_TOP_H forces the
-    // cut (a value above the tree height switches the dense top off).
-    {
+    // bandwidth when larger); the top costs two launches plus n_top^2 FP64
+    // entries at streaming bandwidth.  A forest (the factor of several
+    // independent blocks) gets one cut per tree and one hierarchical top per
+    // tree, concatenated.  Environment BIDO_TOP_H forces a single tree's cut
+    // (a value above the tree height switches the top off).
+    std::vector<int> root_of(nn, -1), roots;
+    for (int id = nn - 1; id >= 0; --id) {
+        const int par = t.nodes[id].parent;
+        root_of[id] = par < 0 ? id : root_of[par];
+        if (par < 0) roots.push_back(id);
+    }
+    std::reverse(roots.begin(), roots.end());
+    const bool forest = roots.size() > 1;
+    // cost-model cut of the tree rooted at r (heights of its own nodes)
+    auto model_cut = [&](int r, int& lowest) {
         constexpr double T_FWD = 10e-6, T_BWD = 25e-6, BW_LVL = 2.0e12, T_TOP = 10e-6, BW_TOP = 4.5e12;
-        int best = H + 1, lowest = H + 1;
+        const int Hr = t.nodes[r].height;
+        int best = Hr + 1;
+        lowest = Hr + 1;
         double best_cost = 0.0, saved = 0.0;
         int64_t cum = 0;
-        for (int h = H; h > hc; --h) {
+        for (int h = Hr; h > hc; --h) {
             double pb = 0.0;
             for (int id : by_h[h]) {
+                if (root_of[id] != r) continue;
                 cum += f.fronts[id].nI;
                 pb += 8.0 * ((double)f.fronts[id].nI * (f.fronts[id].nI + 1) / 2 +
                              (double)f.fronts[id].nB * f.fronts[id].nI);
@@ -315,94 +334,176 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
             const double cost = T_TOP + 8.0 * (double)cum * (double)cum / BW_TOP - saved;
             if (cost < best_cost) { best_cost = cost; best = h; }
         }
+        return best;
+    };
+    std::vector<int> cut_of(nn, H + 1);      // first top height of each node's tree
+    if (!forest) {
+        int lowest = H + 1;
+        int best = roots.empty() ? H + 1 : model_cut(roots[0], lowest);
+        if (roots.empty()) lowest = H + 1;
         // a forced cut is raised as far as the top-size bound requires
         const char* e = std::getenv("BIDO_TOP_H");
         if (o.top_h >= 0) best = std::max(lowest, std::min(H + 1, o.top_h));
         else if (e && *e) best = std::max(lowest, std::min(H + 1, std::atoi(e)));
+        for (int id = 0; id < nn; ++id) cut_of[id] = best;
         p.top_h = best;
-        p.used.top_h = best;
+    } else {
+        std::vector<int> rc(nn, H + 1);
+        for (int r : roots) {
+            int lowest;
+            rc[r] = model_cut(r, lowest);
+        }
+        for (int id = 0; id < nn; ++id) cut_of[id] = rc[root_of[id]];
+        p.top_h = -1;
     }
-    const int top_h = p.top_h;
-    if (top_h <= H) {
-        std::shared_ptr<const TopPart> tp;
-        auto hit = f.top_cache.find(top_h);
-        if (hit != f.top_cache.end() && hit->second->eps == f.eps) tp = hit->second;
-        if (!tp) {
-            auto t0 = std::chrono::steady_clock::now();
-            auto np = std::make_shared<TopPart>();
-            TopPart& T = *np;
-            T.eps = f.eps;
+    p.used.top_h = p.top_h;
+    std::vector<char> is_top(nn, 0);
+    for (int id = 0; id < nn; ++id) is_top[id] = t.nodes[id].height >= cut_of[id];
+
+    // the top of the nodes `top` (post-order): vertices, gather lists of the
+    // bottom roots, S_top^-1 (hierarchical when eps > 0 or `hier`)
+    auto build_top = [&](const std::vector<int>& top, bool hier, TopPart& T) -> bool {
+        auto t0 = std::chrono::steady_clock::now();
+        T.eps = f.eps;
+        std::vector<int32_t> tmap(f.n, -1);
+        int64_t nt = 0;
+        for (int id : top)
+            for (int i = 0; i < f.fronts[id].nI; ++i) {
+                tmap[f.fronts[id].off + i] = (int32_t)nt++;
+                T.pos.push_back(f.fronts[id].off + i);
+            }
+        if (nt > PLAN_TOP_MAX) { err = "dense top too large"; return false; }
+        T.n_top = nt;
+        std::vector<char> intop(nn, 0);
+        for (int id : top) intop[id] = 1;
+        // bottom roots: the update vector of each one covers its boundary,
+        // which lies in the top
+        std::vector<std::vector<int64_t>> lists(nt);
+        for (int id = 0; id < nn; ++id) {
+            const NdNode& nd = t.nodes[id];
+            if (intop[id] || nd.parent < 0 || !intop[nd.parent]) continue;
+            const Front& fr = f.fronts[id];
+            for (int r = 0; r < fr.nB; ++r) {
+                const int32_t ti = tmap[fr.B[r]];
+                if (ti < 0) { err = "boundary of a bottom root outside the top"; return false; }
+                lists[ti].push_back(p.nodes[id].upd + r);
+            }
+        }
+        T.gptr.assign(nt + 1, 0);
+        for (int64_t k = 0; k < nt; ++k) {
+            T.gptr[k + 1] = T.gptr[k] + (int32_t)lists[k].size();
+            for (int64_t src : lists[k]) T.gsrc.push_back(src);
+        }
+        if (T.gsrc.empty()) T.gsrc.push_back(0);
+        top_inverse(f, top, tmap, nt, T.inv, n_threads);
+        if ((f.eps > 0.0 || hier) && f.dim > 0 && (int64_t)f.xyz.size() >= f.n * f.dim) {
+            // hierarchical form: bisection order of the top vertices, then
+            // low-rank off-diagonal blocks at relative accuracy eps
+            std::vector<double> xt((size_t)nt * f.dim);
+            for (int64_t k = 0; k < nt; ++k)
+                for (int d = 0; d < f.dim; ++d) xt[k * f.dim + d] = f.xyz[T.pos[k] * f.dim + d];
+            std::vector<int64_t> ord;
+            hodlr_order(nt, xt.data(), f.dim, PLAN_HODLR_LEAF, ord);
+            std::vector<double> Ap((size_t)nt * nt);
+            for (int64_t a = 0; a < nt; ++a)
+                for (int64_t b = 0; b < nt; ++b) Ap[(size_t)a * nt + b] = T.inv[(size_t)ord[a] * nt + ord[b]];
+            std::vector<int64_t> pos(nt);
+            std::vector<int32_t> gptr(nt + 1, 0);
+            std::vector<int64_t> gsrc;
+            for (int64_t a = 0; a < nt; ++a) {
+                pos[a] = T.pos[ord[a]];
+                for (int32_t q = T.gptr[ord[a]]; q < T.gptr[ord[a] + 1]; ++q) gsrc.push_back(T.gsrc[q]);
+                gptr[a + 1] = (int32_t)gsrc.size();
+            }
+            if (gsrc.empty()) gsrc.push_back(0);
+            T.pos.swap(pos);
+            T.gptr.swap(gptr);
+            T.gsrc.swap(gsrc);
+            hodlr_build(Ap, nt, f.eps, PLAN_HODLR_LEAF, n_threads, T.hd);
+            std::vector<double>().swap(T.inv);
+            T.hodlr = true;
+            for (size_t b = 0; b < T.hd.blocks.size(); ++b)
+                for (int j = 0; j < 2 * T.hd.blocks[b].k; ++j) T.cols.push_back((int32_t)((b << 16) | j));
+        }
+        T.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return true;
+    };
+    // append top part B to A (hierarchical forms; indices shifted)
+    auto append_top = [](TopPart& A, const TopPart& B) {
+        const int64_t to = A.n_top, go = (int64_t)A.gsrc.size();
+        const int64_t vo = (int64_t)A.hd.val.size(), ao = (int64_t)A.hd.anc.size();
+        const int32_t bo = (int32_t)A.hd.blocks.size(), tso = (int32_t)(A.n_top ? A.hd.t_size : 0);
+        for (int64_t v : B.pos) A.pos.push_back(v);
+        if (A.gptr.empty()) A.gptr.push_back(0);
+        for (size_t k = 1; k < B.gptr.size(); ++k) A.gptr.push_back((int32_t)(B.gptr[k] + go));
+        for (int64_t v : B.gsrc) A.gsrc.push_back(v);
+        for (HodlrBlock hb : B.hd.blocks) {
+            hb.a += (int32_t)to; hb.m += (int32_t)to; hb.e += (int32_t)to;
+            hb.u += vo; hb.v += vo; hb.t += tso;
+            A.hd.blocks.push_back(hb);
+        }
+        for (HodlrLeaf lf : B.hd.leaves) {
+            lf.a += (int32_t)to; lf.e += (int32_t)to; lf.d += vo; lf.anc += (int32_t)ao;
+            A.hd.leaves.push_back(lf);
+        }
+        for (int32_t c : B.hd.anc) A.hd.anc.push_back(c + 2 * bo);
+        A.hd.val.insert(A.hd.val.end(), B.hd.val.begin(), B.hd.val.end());
+        for (int32_t c : B.cols) A.cols.push_back(c + (bo << 16));
+        A.hd.t_size = tso + B.hd.t_size;
+        A.hd.max_rank = std::max(A.hd.max_rank, B.hd.max_rank);
+        A.hd.n += B.hd.n;
+        A.n_top += B.n_top;
+        A.seconds += B.seconds;
+        A.hodlr = true;
+    };
+    std::shared_ptr<const TopPart> tp;
+    if (!forest) {
+        const int top_h = p.top_h;
+        if (top_h <= H) {
+            auto hit = f.top_cache.find(top_h);
+            if (hit != f.top_cache.end() && hit->second->eps == f.eps) tp = hit->second;
+            if (!tp) {
+                auto np = std::make_shared<TopPart>();
+                std::vector<int> top;
+                for (int id = 0; id < nn; ++id)
+                    if (is_top[id]) top.push_back(id);     // post-order
+                if (!build_top(top, false, *np)) return false;
+                f.top_cache[top_h] = np;
+                tp = np;
+            }
+        }
+    } else {
+        auto np = std::make_shared<TopPart>();
+        np->eps = f.eps;
+        np->gptr.push_back(0);
+        for (int r : roots) {
             std::vector<int> top;
             for (int id = 0; id < nn; ++id)
-                if (t.nodes[id].height >= top_h) top.push_back(id);     // post-order
-            std::vector<int32_t> tmap(f.n, -1);
-            int64_t nt = 0;
-            for (int id : top)
-                for (int i = 0; i < f.fronts[id].nI; ++i) {
-                    tmap[f.fronts[id].off + i] = (int32_t)nt++;
-                    T.pos.push_back(f.fronts[id].off + i);
-                }
-            if (nt > PLAN_TOP_MAX) { err = "dense top too large"; return false; }
-            T.n_top = nt;
-            // bottom roots: the update vector of each one covers its boundary,
-            // which lies in the top
-            std::vector<std::vector<int64_t>> lists(nt);
-            for (int id = 0; id < nn; ++id) {
-                const NdNode& nd = t.nodes[id];
-                if (nd.height >= top_h || nd.parent < 0 || t.nodes[nd.parent].height < top_h) continue;
-                const Front& fr = f.fronts[id];
-                for (int r = 0; r < fr.nB; ++r) {
-                    const int32_t ti = tmap[fr.B[r]];
-                    if (ti < 0) { err = "boundary of a bottom root outside the top"; return false; }
-                    lists[ti].push_back(p.nodes[id].upd + r);
-                }
-            }
-            T.gptr.assign(nt + 1, 0);
-            for (int64_t k = 0; k < nt; ++k) {
-                T.gptr[k + 1] = T.gptr[k] + (int32_t)lists[k].size();
-                for (int64_t src : lists[k]) T.gsrc.push_back(src);
-            }
-            if (T.gsrc.empty()) T.gsrc.push_back(0);
-            top_inverse(f, top, tmap, nt, T.inv, n_threads);
-            if (f.eps > 0.0 && f.dim > 0 && (int64_t)f.xyz.size() >= f.n * f.dim) {
-                // hierarchical form: bisection order of the top vertices, then
-                // low-rank off-diagonal blocks at relative accuracy eps
-                std::vector<double> xt((size_t)nt * f.dim);
-                for (int64_t k = 0; k < nt; ++k)
-                    for (int d = 0; d < f.dim; ++d) xt[k * f.dim + d] = f.xyz[T.pos[k] * f.dim + d];
-                std::vector<int64_t> ord;
-                hodlr_order(nt, xt.data(), f.dim, PLAN_HODLR_LEAF, ord);
-                std::vector<double> Ap((size_t)nt * nt);
-                for (int64_t a = 0; a < nt; ++a)
-                    for (int64_t b = 0; b < nt; ++b) Ap[(size_t)a * nt + b] = T.inv[(size_t)ord[a] * nt + ord[b]];
-                std::vector<int64_t> pos(nt);
-                std::vector<int32_t> gptr(nt + 1, 0);
-                std::vector<int64_t> gsrc;
-                for (int64_t a = 0; a < nt; ++a) {
-                    pos[a] = T.pos[ord[a]];
-                    for (int32_t q = T.gptr[ord[a]]; q < T.gptr[ord[a] + 1]; ++q) gsrc.push_back(T.gsrc[q]);
-                    gptr[a + 1] = (int32_t)gsrc.size();
-                }
-                if (gsrc.empty()) gsrc.push_back(0);
-                T.pos.swap(pos);
-                T.gptr.swap(gptr);
-                T.gsrc.swap(gsrc);
-                hodlr_build(Ap, nt, f.eps, PLAN_HODLR_LEAF, n_threads, T.hd);
-                std::vector<double>().swap(T.inv);
-                T.hodlr = true;
-                for (size_t b = 0; b < T.hd.blocks.size(); ++b)
-                    for (int j = 0; j < 2 * T.hd.blocks[b].k; ++j) T.cols.push_back((int32_t)((b << 16) | j));
-                if (T.hd.blocks.size() >= (1u << 15) || T.hd.max_rank >= (1 << 15)) {
-                    err = "hierarchical top too large";
-                    return false;
-                }
-            }
-            T.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-            f.top_cache[top_h] = np;
+                if (is_top[id] && root_of[id] == r) top.push_back(id);
+            if (top.empty()) continue;
+            TopPart T;
+            if (!build_top(top, true, T)) return false;
+            if (!T.hodlr) { err = "a forest needs vertex coordinates for its tops"; return false; }
+            append_top(*np, T);
+        }
+        if (np->n_top > 0) {
+            if (np->gsrc.empty()) np->gsrc.push_back(0);
             tp = np;
+        }
+    }
+    if (tp) {
+        if (tp->hodlr && (tp->hd.blocks.size() >= (1u << 15) || tp->hd.max_rank >= (1 << 15))) {
+            err = "hierarchical top too large";
+            return false;
         }
         p.n_top = tp->n_top;
         p.top_pos = tp->pos;
+        p.top_zero.assign(tp->n_top, 0);
+        {
+            std::vector<char> gnd(f.n, 0);
+            for (int64_t g : f.grounds) gnd[g] = 1;
+            for (int64_t k = 0; k < tp->n_top; ++k) p.top_zero[k] = gnd[tp->pos[k]] ? 1 : 0;
+        }
         p.top_gptr = tp->gptr;
         p.top_gsrc = tp->gsrc;
         p.top_inv = tp->inv;
@@ -426,10 +527,14 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     std::vector<std::pair<size_t, size_t>> fspan, bspan, fcspan, bcspan;
     struct LdsSz { size_t f, b; };
     std::vector<LdsSz> lds;
-    for (int h = hc + 1; h < top_h; ++h) {
+    int Hl = hc;                            // highest level with non-top nodes
+    for (int id = 0; id < nn; ++id)
+        if (!is_top[id] && t.nodes[id].height > Hl) Hl = t.nodes[id].height;
+    for (int h = hc + 1; h <= Hl; ++h) {
         const size_t f0 = p.fwd_items.size(), fc0 = p.fwd_comb.size();
         size_t ldsf = 0;
         for (int id : by_h[h]) {
+            if (is_top[id]) continue;
             const Front& fr = f.fronts[id];
             const int nI = fr.nI, nF = fr.nI + fr.nB;
             if (nI == 0) continue;
@@ -462,10 +567,11 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
         fcspan.push_back({fc0, p.fwd_comb.size() - fc0});
         lds.push_back({ldsf, 0});
     }
-    for (int h = hc + 1; h < top_h; ++h) {
+    for (int h = hc + 1; h <= Hl; ++h) {
         const size_t b0 = p.bwd_items.size(), bc0 = p.bwd_comb.size();
         size_t ldsb = 0;
         for (int id : by_h[h]) {
+            if (is_top[id]) continue;
             const Front& fr = f.fronts[id];
             const int nI = fr.nI, nF = fr.nI + fr.nB;
             if (nI == 0) continue;
@@ -510,6 +616,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     p.bwd_bytes32.assign(H + 1, 0.0);
     for (int h = 0; h <= H; ++h)
         for (int id : by_h[h]) {
+            if (is_top[id]) continue;
             const Front& fr = f.fronts[id];
             const double pe = (double)fr.nI * (fr.nI + 1) / 2 + (double)fr.nB * fr.nI;
             double cb = 0.0;
@@ -562,7 +669,7 @@ struct Emu {
         const Ea m = p.ea.at(nd.ea + i);
         if (m.a >= 0) v -= upd.at(u0 + m.a);
         if (m.b >= 0) v -= upd.at(u1 + m.b);
-        return (nd.off + i == p.ground) ? 0.0 : v;
+        return i == nd.gi ? 0.0 : v;
     }
 
     // sum over columns [cs, ce) of P(r, c) w(c) from the column-major copy
@@ -665,7 +772,7 @@ struct Emu {
         for (int64_t k = 0; k < nt; ++k) {
             double v = b[p.top_pos.at(k)];
             for (int32_t q = p.top_gptr.at(k); q < p.top_gptr.at(k + 1); ++q) v -= upd.at(p.top_gsrc.at(q));
-            w[k] = p.top_pos[k] == p.ground ? 0.0 : v;
+            w[k] = p.top_zero.at(k) ? 0.0 : v;
         }
         if (p.top_hodlr) {
             std::vector<double> y(nt);

@@ -49,6 +49,7 @@ struct FactorPlan {
     int top_h = 0;
     int64_t n_top = 0;
     std::vector<int64_t> top_pos;       // top index -> vertex (tree order)
+    std::vector<uint8_t> top_zero;      // 1 at the grounded top entries
     std::vector<int32_t> top_gptr;      // top index -> [gptr, gptr+1) in top_gsrc
     std::vector<int64_t> top_gsrc;      // update-workspace entries of the bottom roots
     std::vector<double> top_inv;        // S_top^-1, n_top x n_top row-major (exact mode)

@@ -174,7 +174,7 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
     const int nth = P.n_threads;
     if (!multifrontal(S1p, hs.p1, N - 1, nth, err)) { err = "P_1: " + err; return false; }
     if (!multifrontal(Kmp, hs.pk, -1, nth, err)) { err = "P_K: " + err; return false; }
-    if (P.eps_h > 0.0) {
+    {   // coordinates (tree order) and the accuracy of the hierarchical top
         std::vector<double> x1((size_t)N * d), xk((size_t)NH * d);
         for (int64_t p = 0; p < N; ++p)
             for (int a = 0; a < d; ++a) x1[p * d + a] = mesh->xyz[t1.perm[p] * d + a];

@@ -222,3 +222,32 @@ def test_hierarchical_top_is_compressed():
     top = hs.factor_top(B.FACTOR_P1)
     assert top["max_rank"] > 0
     assert top["stored_entries"] < top["n_top"] ** 2
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-6])
+def test_forest_of_slices_emulates_each_slice(eps):
+    """The factor of a batch of independent slices is the forest of their
+    factors; its device plan (one subtree phase, merged level phases, one
+    hierarchical top per tree) run by the CPU emulation gives, on every
+    slice's range, that slice's own inner solve (exact, or within about eps
+    for the hierarchical tops)."""
+    import paper_1711_08708_amd as B
+    cfgs = [w.thorax2d(n_target=3000, seed=31), w.thorax2d(n_target=6000, seed=32, sigma_scale=0.8),
+            w.square2d(n=24, seed=3), w.thorax2d(n_target=1500, seed=33)]
+    parts = [B.HostSetup(c, eps_h=eps) for c in cfgs]
+    merged = B.HostSetup.merged(parts)
+    sizes = [(len(p.index(B.IDX_UPOS)), len(p.index(B.IDX_VPOS))) for p in parts]
+    ntot = sum(a + b for a, b in sizes)
+    rng = np.random.default_rng(12)
+    for which in (B.FACTOR_P1, B.FACTOR_PK):
+        b = rng.normal(size=ntot)
+        emu = merged.factor_emulate(which, b)
+        print("forest plan", which, merged.factor_plan(which), merged.factor_top(which))
+        off = 0
+        for p, (N, NH) in zip(parts, sizes):
+            lo, n = (off, N) if which == B.FACTOR_P1 else (off + N, NH)
+            ref = p.factor_apply(which, b[lo:lo + n])
+            err = np.abs(emu[lo:lo + n] - ref).max() / np.abs(ref).max()
+            assert np.isfinite(emu[lo:lo + n]).all()
+            assert err <= 1e-11 + 1e3 * eps, (which, err)
+            off += N + NH
