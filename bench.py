@@ -46,7 +46,10 @@ def _parse():
     ap.add_argument("--variant-steps", type=int, default=50)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuning of the inner-solve plans")
-    ap.add_argument("--batch-streams", type=int, default=4, help="streams of the batch (batch64)")
+    ap.add_argument("--batch-streams", type=int, default=4, help="streams of the batch (batch64, --batch-mode streams)")
+    ap.add_argument("--batch-mode", choices=["fused", "streams"], default="fused",
+                    help="batch64: one union PCG for all slices (fused) or lockstep slices on streams; "
+                         "the learned stencil runs on streams")
     ap.add_argument("--batch-learned", action="store_true",
                     help="batch64: train the learned stencil of every slice first")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -303,7 +306,10 @@ def _bench_batch(args):
                 sv.set_precond(B.PRECOND_LEARNED)
         training = {"collect_steps": args.collect_steps, "epochs": args.epochs, "spd_slices": spd,
                     "seconds": round(time.perf_counter() - t0, 1)}
-    batch = B.Batch(solvers, n_streams=args.batch_streams)
+    mode = "streams" if args.batch_learned else args.batch_mode
+    t0 = time.perf_counter()
+    batch = B.Batch(solvers, n_streams=args.batch_streams, fused=mode == "fused")
+    t_batch = time.perf_counter() - t0
     states = [s.state() for s in solvers]
     batch.run(states, 0, args.warmup)
     torch.cuda.synchronize()
@@ -321,9 +327,10 @@ def _bench_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == B.PREC_FP64 else "f64+f32", "data": "synthetic",
         "config": {"workload": f"batch64: {S} thorax-like slices, {n_nodes} vertices in total, "
-                               f"vertex counts log-uniform in [20k, 300k], lockstep PCG per slice",
+                               f"vertex counts log-uniform in [20k, 300k], PCG per slice",
                    "slices": S, "total_nodes": n_nodes, "precision": args.precision, "tol": args.tol,
-                   "streams": args.batch_streams, "learned": bool(args.batch_learned),
+                   "mode": mode, "streams": args.batch_streams if mode == "streams" else 1,
+                   "learned": bool(args.batch_learned), "batch_setup_s": round(t_batch, 1),
                    "mean_iterations_per_slice_step": round((tot["total_iterations"] + tot2["total_iterations"])
                                                            / (S * args.steps), 3),
                    "max_iterations_per_step": max(tot["iterations"], tot2["iterations"]),

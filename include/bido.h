@@ -317,6 +317,30 @@ bido_status bido_batch_run(bido_batch* b, double* const* v, double* const* w, do
                            int64_t n0, int64_t n_steps, bido_stats* per_ctx, bido_stats* total);
 void bido_batch_destroy(bido_batch* b);
 
+/* Fused batch (same run and destroy calls).  The slices' vectors, Lambda,
+ * S_i Pi, Pi^T S_i and their P1 and PK factors are laid side by side in one
+ * union (slice s at the sum of the earlier slices' N + N_H, u rows first),
+ * so that each phase of the PCG iteration of Sec. 3.2 is one launch for all
+ * slices: segmented vector kernels keep alpha, beta and r.z per slice, the
+ * stopping test is per slice and a slice that has met it is frozen (alpha =
+ * beta = 0) while the others iterate; the inner solves sweep the forest of
+ * all slices' elimination trees level by level, each tree with the top cut
+ * of its own plan.  Steps 1 and 3 and the normalisation stay per slice.
+ * Needs the plain preconditioner and one precision for all slices, and
+ * refuses contexts already in a batch (BIDO_ERR_STATE).  Set-up merges the
+ * host factors and uploads a second copy of them (the contexts keep
+ * theirs); results agree with the slices run alone up to rounding order.
+ * The contexts' U/V work vectors alias the union while in the batch.     */
+bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stream, bido_batch** out);
+/* Fused batch only: replay captured graphs of the PCG iterations (on != 0,
+ * the default) or launch every kernel eagerly (BIDO_ERR_STATE for a batch
+ * of streams, whose contexts follow bido_set_graphs).                    */
+bido_status bido_batch_set_graphs(bido_batch* b, int on);
+/* fused: 1 for a fused batch; n_union: its union length (sum of N + N_H);
+ * setup_seconds: host and upload time of bido_batch_create_fused.  Any
+ * output may be NULL.                                                    */
+bido_status bido_batch_info(const bido_batch* b, int* fused, int64_t* n_union, double* setup_seconds);
+
 /* Per-kernel profile: launches, summed event-timed duration [ms] and the
  * algorithmic bytes those launches must move (inputs read once, outputs
  * written once), aggregated by kernel class.                            */

@@ -83,7 +83,10 @@ bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n
  * union), slice s at offset O_s = sum_{t<s} (N_t + N_H,t): P_1 on
  * [O_s, O_s + N_s), P_K on [O_s + N_s, O_s + N_s + N_H,s), vectors of
  * sum_s (N_s + N_H,s) entries.  Only the bido_host_factor_* entry points
- * apply to it; free it with bido_host_free.                               */
+ * apply to it; free it with bido_host_free.  A tree whose slice's own plan
+ * already holds a hierarchical top of the same cut (any earlier
+ * bido_host_factor_* call on that slice with eps_h > 0) takes it over
+ * instead of inverting again, so the slices' objects must outlive this one.*/
 bido_status bido_host_merge(const bido_host* const* hs, int n, bido_host** out);
 
 /* Dense top of that plan: the tree nodes of height >= top_h are solved as

@@ -151,6 +151,11 @@ ABI = {
                                       ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(Stats),
                                       ctypes.POINTER(Stats)]),
     "bido_batch_destroy": (None, [ctypes.c_void_p]),
+    "bido_batch_create_fused": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p,
+                                               ctypes.POINTER(ctypes.c_void_p)]),
+    "bido_batch_set_graphs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "bido_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "bido_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KProf), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int)]),
@@ -425,9 +430,12 @@ class Batch:
     """Independent slices (Solver objects on one device) stepped together.
 
     While the batch exists the solvers run on its streams and must not be
-    used on their own; close() gives them back."""
+    used on their own; close() gives them back.  fused=True lays the slices
+    side by side in one union and runs each PCG phase as one launch for all
+    of them (bido_batch_create_fused); otherwise the slices are spread over
+    n_streams streams."""
 
-    def __init__(self, solvers, n_streams=0, stream=None):
+    def __init__(self, solvers, n_streams=0, stream=None, fused=False):
         import torch
         self.torch = torch
         self.solvers = list(solvers)
@@ -436,9 +444,22 @@ class Batch:
         self.stream = stream
         arr = (ctypes.c_void_p * len(self.solvers))(*[s.ctx.value for s in self.solvers])
         b = ctypes.c_void_p()
-        _check(lib.bido_batch_create(arr, len(self.solvers), int(n_streams), ctypes.c_void_p(stream.cuda_stream),
-                                     ctypes.byref(b)))
+        if fused:
+            _check(lib.bido_batch_create_fused(arr, len(self.solvers), ctypes.c_void_p(stream.cuda_stream),
+                                               ctypes.byref(b)))
+        else:
+            _check(lib.bido_batch_create(arr, len(self.solvers), int(n_streams),
+                                         ctypes.c_void_p(stream.cuda_stream), ctypes.byref(b)))
         self.b = b
+
+    def set_graphs(self, on):
+        """Fused batches: replay captured iteration graphs (default) or not."""
+        _check(lib.bido_batch_set_graphs(self.b, 1 if on else 0))
+
+    def info(self):
+        f, n, t = ctypes.c_int(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib.bido_batch_info(self.b, ctypes.byref(f), ctypes.byref(n), ctypes.byref(t)))
+        return {"fused": bool(f.value), "n_union": n.value, "setup_seconds": t.value}
 
     def run(self, states, n0, n_steps, check=True):
         """states: one (v, w, u) tuple of device tensors per solver.  Returns

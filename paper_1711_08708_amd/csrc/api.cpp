@@ -90,6 +90,7 @@ struct Profiler {
 struct FactorDev {
     int64_t n = 0, ground = -1;
     int height = 0;
+    int lvl0 = 0;                   // height of the first level phase
     TriNode* nodes = nullptr;
     double* panel64 = nullptr;      // row-major copy (backward sweep)
     float* panel32 = nullptr;
@@ -181,6 +182,7 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
     HIP_OK(upload(&fd.items, p.fwd_items.data(), p.fwd_items.size()));
     HIP_OK(upload(&fd.bitems, p.bwd_items.data(), p.bwd_items.size()));
     fd.plan.hc = p.hc;
+    fd.lvl0 = p.lvl0;
     fd.plan.n_sub = p.n_sub;
     fd.plan.sub_maxw = p.sub_maxw;
     HIP_OK(upload(&fd.plan.sub_nodes, p.sub_nodes.data(), p.sub_nodes.size()));
@@ -387,23 +389,22 @@ template <typename T> const T* top_inv(const FactorDev& f);
 template <> const double* top_inv<double>(const FactorDev& f) { return f.top_inv64; }
 template <> const float* top_inv<float>(const FactorDev& f) { return f.top_inv32; }
 
-template <typename T>
-void tri_solve(bido_ctx* c, const FactorDev& f, const T* panel, const T* panel_cm, const double* in,
-               double* out) {
+// C: a context or a fused batch (stream, profiler, precision)
+template <typename T, typename C>
+void tri_solve(C* c, const FactorDev& f, const T* panel, const T* panel_cm, const double* in, double* out) {
     hipStream_t s = c->stream;
     const bool f32 = sizeof(T) == 4;
-    const int hc = f.plan.hc;
     PROF(c, K_TRI_FWD_SUB, f32 ? f.sub_fwd_bytes32 : f.sub_fwd_bytes64,
          launch_tri_fwd_sub<T>(s, f.plan, f.nodes, panel_cm, f.ea, in, f.ytmp, f.upd));
     for (size_t k = 0; k < f.top.size(); ++k) {
-        const int h = hc + 1 + (int)k;
+        const int h = f.lvl0 + (int)k;
         PROF(c, K_TRI_FWD_LVL, f32 ? f.fwd_bytes32[h] : f.fwd_bytes64[h],
              launch_tri_fwd_lvl<T>(s, f.top[k], f.plan, f.nodes, panel_cm, f.ea, in, f.ytmp, f.upd));
     }
     PROF(c, K_TRI_TOP, f32 ? f.top_bytes32 : f.top_bytes64,
          launch_tri_top<T>(s, f.plan, top_inv<T>(f), in, f.upd, out));
     for (size_t k = f.top.size(); k-- > 0;) {
-        const int h = hc + 1 + (int)k;
+        const int h = f.lvl0 + (int)k;
         PROF(c, K_TRI_BWD_LVL, f32 ? f.bwd_bytes32[h] : f.bwd_bytes64[h],
              launch_tri_bwd_lvl<T>(s, f.top[k], f.plan, f.nodes, panel, f.bidx, f.ytmp, out));
     }
@@ -411,7 +412,8 @@ void tri_solve(bido_ctx* c, const FactorDev& f, const T* panel, const T* panel_c
          launch_tri_bwd_sub<T>(s, f.plan, f.nodes, panel, f.bidx, f.ytmp, out));
 }
 
-void inner_solve(bido_ctx* c, const FactorDev& f, const double* in, double* out) {
+template <typename C>
+void inner_solve(C* c, const FactorDev& f, const double* in, double* out) {
     if (c->precision == BIDO_PREC_MIXED && f.panel32)
         tri_solve<float>(c, f, f.panel32, f.panel32_cm, in, out);
     else
@@ -725,9 +727,8 @@ IonicConst ionic_consts(const bido_ctx* c) {
     return k;
 }
 
-// one time step on device arrays (no sync, no timing)
-// Steps 1 and 3 on the device and the start of Step 2 (no wait).
-void step_begin(bido_ctx* c, double* v, double* w, double* u, int64_t n, PcgRun& ps) {
+// Steps 1 and 3 on the device: X0 = (U^n, V^n) and the right-hand side Y.
+void step_prepare(bido_ctx* c, double* v, double* w, double* u, int64_t n) {
     hipStream_t s = c->stream;
     const int64_t N = c->N, NH = c->NH;
     PROF(c, K_MISC, 24.0 * N, launch_scatter_in(s, N, c->u_pos, u, c->x));   // X0 = (U^n, V^n)
@@ -736,19 +737,28 @@ void step_begin(bido_ctx* c, double* v, double* w, double* u, int64_t n, PcgRun&
          launch_ionic(s, NH, v, w, c->stim_loc, on, c->mh_loc, c->v_pos, c->Y + N, c->x + N,
                       ionic_consts(c)));                               // Steps 1 and 3
     PROF(c, K_MISC, 8.0 * N, launch_fill(s, N, c->Y, 0.0));           // Y1 = 0
+}
+
+// Steps 1 and 3 and the start of Step 2 (no wait).
+void step_begin(bido_ctx* c, double* v, double* w, double* u, int64_t n, PcgRun& ps) {
+    step_prepare(c, v, w, u, n);
     pcg_start(c, ps, c->params.tol);                                   // Step 2
 }
 
 // After Step 2: normalisation (M U, 1) = 0 and the write-back of U, V.
-bido_status step_end(bido_ctx* c, double* v, double* u, const PcgRun& ps, bido_stats* st) {
+void step_write(bido_ctx* c, double* v, double* u) {
     hipStream_t s = c->stream;
     const int64_t N = c->N, NH = c->NH;
-    bido_status e = pcg_result(c, ps, st);
-    finish_collection(c, e == BIDO_OK);
-    if (e && e != BIDO_ERR_NOT_CONVERGED) return e;
     PROF(c, K_MISC, 16.0 * N, launch_dot_reduce(s, N, c->m_int, c->x, c->rd, c->sc + S_MU));  // (M U, 1)
     PROF(c, K_MISC, 24.0 * N, launch_gather_out(s, N, c->u_pos, c->x, u, c->sc, S_MU, c->hs.msum));
     PROF(c, K_MISC, 24.0 * NH, launch_gather_out(s, NH, c->v_pos, c->x + N, v, c->sc, -1, 1.0));
+}
+
+bido_status step_end(bido_ctx* c, double* v, double* u, const PcgRun& ps, bido_stats* st) {
+    bido_status e = pcg_result(c, ps, st);
+    finish_collection(c, e == BIDO_OK);
+    if (e && e != BIDO_ERR_NOT_CONVERGED) return e;
+    step_write(c, v, u);
     return e;
 }
 
@@ -884,6 +894,267 @@ bool dt_matches(const bido_ctx* c, double dt) {
     return std::fabs(dt - c->params.dt) <= 1e-12 * std::fabs(c->params.dt);
 }
 
+// ---------------------------------------------------------------------------
+// Fused batch: the slices side by side in one union vector (slice s at
+// off[s], its u rows then its v rows), one block-diagonal Lambda, S_i Pi and
+// Pi^T S_i, and the merged forests of the slices' P1 and PK factors.  Each
+// PCG phase is one launch sequence for all slices; the scalars and the
+// stopping test stay per slice, and a finished slice is frozen
+// (alpha = beta = 0) while the others go on.
+// ---------------------------------------------------------------------------
+constexpr int64_t SEG_ROWS = 1024;   // rows per block of the segmented kernels
+
+enum { FR_RR = 0, FR_YY, FR_PQ, FR_RZ, FR_ZRO, FR_COUNT };
+
+struct FusedBatch {
+    hipStream_t stream = nullptr;
+    Profiler prof;
+    int precision = BIDO_PREC_FP64;
+    int spmv_group = 8;
+    bool graphs = true;
+    int S = 0;
+    int64_t n = 0;
+    std::vector<int64_t> off, n2;
+    CsrDev lam, avu, auv;
+    FactorDev p1, pk;
+    SegTable T, Tu, Tv;
+    std::vector<void*> tables;          // device arrays of the three tables
+    std::vector<SegSlice> slices;       // T's slices (host copy)
+    double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *Y = nullptr;
+    double *tA = nullptr, *tB = nullptr, *tC = nullptr, *tD = nullptr, *r_old = nullptr;
+    double* sc = nullptr;               // r.z (2 slots of S), p.q (S), then FR_COUNT partial regions
+    double* sc_host = nullptr;          // pinned
+    uint8_t *done = nullptr, *done_host = nullptr;
+    hipGraphExec_t gx[3] = {nullptr, nullptr, nullptr};
+    double setup_seconds = 0.0;
+
+    int64_t region(int k) const { return 3 * (int64_t)S + (int64_t)k * T.nblocks; }
+    double* part(int k) const { return sc + region(k); }
+    double host_sum(int k, int s) const {
+        double a = 0.0;
+        for (int b = slices[s].b0; b < slices[s].b1; ++b) a += sc_host[region(k) + b];
+        return a;
+    }
+    bool flexible() const { return precision == BIDO_PREC_MIXED; }
+    void drop_graphs() {
+        for (auto& g : gx)
+            if (g) { hipGraphExecDestroy(g); g = nullptr; }
+    }
+    ~FusedBatch() {
+        if (stream) hipStreamSynchronize(stream);
+        drop_graphs();
+        p1.release();
+        pk.release();
+        CsrHostView::release(lam);
+        CsrHostView::release(avu);
+        CsrHostView::release(auv);
+        for (void* t : tables) hipFree(t);
+        for (double* b : {x, r, z, p, q, Y, tA, tB, tC, tD, r_old, sc}) hipFree(b);
+        hipFree(done);
+        if (sc_host) hipHostFree(sc_host);
+        if (done_host) hipHostFree(done_host);
+        if (stream) hipStreamDestroy(stream);
+    }
+};
+
+// Blocks of at most SEG_ROWS rows over the row range [start[s], start[s] +
+// len[s]) of every slice.
+void seg_layout(const std::vector<int64_t>& start, const std::vector<int64_t>& len, const std::vector<int64_t>& base,
+                const std::vector<int64_t>& nu, std::vector<SegBlock>& blk, std::vector<SegSlice>& sl) {
+    blk.clear();
+    sl.assign(start.size(), SegSlice{});
+    for (size_t s = 0; s < start.size(); ++s) {
+        sl[s].base = base[s];
+        sl[s].nu = nu[s];
+        sl[s].b0 = (int32_t)blk.size();
+        for (int64_t r = start[s]; r < start[s] + len[s]; r += SEG_ROWS)
+            blk.push_back({r, std::min(r + SEG_ROWS, start[s] + len[s]), (int32_t)s, 0});
+        sl[s].b1 = (int32_t)blk.size();
+    }
+}
+
+bido_status seg_upload(FusedBatch* F, const std::vector<SegBlock>& blk, const std::vector<SegSlice>& sl,
+                       SegTable& T) {
+    SegBlock* db = nullptr;
+    SegSlice* ds = nullptr;
+    HIP_OK(upload(&db, blk.data(), blk.size()));
+    F->tables.push_back(db);
+    HIP_OK(upload(&ds, sl.data(), sl.size()));
+    F->tables.push_back(ds);
+    T.nblocks = (int)blk.size();
+    T.blk = db;
+    T.sl = ds;
+    return BIDO_OK;
+}
+
+// Block-diagonal union of CSR blocks: block s at rows row_off[s] and columns
+// col_off[s]; rows outside every block are empty.
+bido_status union_csr(const std::vector<const Csr*>& parts, const std::vector<int64_t>& row_off,
+                      const std::vector<int64_t>& col_off, int64_t n, CsrDev& d) {
+    Csr u;
+    u.n = n;
+    u.ptr.assign(n + 1, 0);
+    int64_t nnz = 0;
+    for (const Csr* a : parts) nnz += a->nnz();
+    u.col.reserve(nnz);
+    u.val.reserve(nnz);
+    std::vector<int64_t> order(parts.size());
+    for (size_t s = 0; s < parts.size(); ++s) order[s] = (int64_t)s;
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return row_off[a] < row_off[b]; });
+    int64_t row = 0;
+    for (int64_t s : order) {
+        const Csr& a = *parts[s];
+        if (row_off[s] < row || row_off[s] + a.n > n) return fail(BIDO_ERR_ARG, "overlapping union blocks");
+        for (; row < row_off[s]; ++row) u.ptr[row + 1] = (int64_t)u.col.size();
+        for (int64_t i = 0; i < a.n; ++i, ++row) {
+            for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) {
+                u.col.push_back((int32_t)(a.col[k] + col_off[s]));
+                u.val.push_back(a.val[k]);
+            }
+            u.ptr[row + 1] = (int64_t)u.col.size();
+        }
+    }
+    for (; row < n; ++row) u.ptr[row + 1] = (int64_t)u.col.size();
+    if (u.col.empty()) {                     // keep the device arrays non-null
+        u.col.push_back(0);
+        u.val.push_back(0.0);
+    }
+    return CsrHostView::up(u, d);
+}
+
+// z = P^-1 r for all slices (the same steps as precond_apply) and the
+// partials of r.z (and r_old.z)
+void fused_apply(FusedBatch* F, bool with_old) {
+    hipStream_t s = F->stream;
+    inner_solve(F, F->p1, F->r, F->tA);                                               // Z1 = P1^-1 R1
+    launch_seg_csr(s, F->Tv, F->avu, F->spmv_group, F->tA, F->r, F->tB);               // R2 - S_i Pi Z1
+    inner_solve(F, F->pk, F->tB, F->z);                                                // Z2 = PK^-1 (...)
+    launch_seg_csr(s, F->Tu, F->auv, F->spmv_group, F->z, nullptr, F->tC);             // Pi^T S_i Z2
+    inner_solve(F, F->p1, F->tC, F->tD);                                               // P1^-1 Pi^T S_i Z2
+    launch_seg_combine(s, F->T, F->z, F->tA, F->tD, F->r, with_old ? F->r_old : nullptr, F->part(FR_RZ),
+                       F->part(FR_ZRO));
+}
+
+// q = Lambda p, x += alpha p, r -= alpha q (alpha from r.z in slot `rho`);
+// copy the scalars and the |r|^2 partials
+void fused_tail(FusedBatch* F, int rho) {
+    hipStream_t s = F->stream;
+    const int S = F->S;
+    launch_seg_spmv(s, F->T, F->lam, F->spmv_group, 0, F->p, nullptr, F->q, F->part(FR_PQ), nullptr);
+    launch_seg_pcg_update(s, F->T, F->x, F->r, F->flexible() ? F->r_old : nullptr, F->p, F->q, F->part(FR_PQ),
+                          F->part(FR_RR), F->sc + (int64_t)rho * S, F->done, F->sc + 2 * (int64_t)S);
+    hipMemcpyAsync(F->sc_host, F->sc, F->region(FR_RR + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+}
+
+// variant 0: the first iteration (p = z, r.z into slot 0); 1 and 2: a later
+// one reading r.z from slot 0 or 1 and writing the other slot
+void fused_seq(FusedBatch* F, int variant) {
+    const int S = F->S;
+    if (variant == 0) {
+        fused_apply(F, false);
+        launch_seg_p_update(F->stream, F->T, F->z, F->p, F->part(FR_RZ), nullptr, 1, 0, nullptr, F->sc, F->done);
+        fused_tail(F, 0);
+        return;
+    }
+    const int rho = variant - 1, next = 1 - rho;
+    const bool flex = F->flexible();
+    fused_apply(F, flex);
+    launch_seg_p_update(F->stream, F->T, F->z, F->p, F->part(FR_RZ), F->part(FR_ZRO), 0, flex ? 1 : 0,
+                        F->sc + (int64_t)rho * S, F->sc + (int64_t)next * S, F->done);
+    fused_tail(F, next);
+}
+
+bido_status fused_launch(FusedBatch* F, int variant) {
+    if (!F->graphs || F->prof.on || debug_on()) {
+        fused_seq(F, variant);
+        return BIDO_OK;
+    }
+    if (!F->gx[variant]) {
+        HIP_OK(hipStreamBeginCapture(F->stream, hipStreamCaptureModeThreadLocal));
+        fused_seq(F, variant);
+        hipGraph_t g = nullptr;
+        HIP_OK(hipStreamEndCapture(F->stream, &g));
+        hipGraphExec_t x = nullptr;
+        const hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        HIP_OK(e);
+        F->gx[variant] = x;
+    }
+    HIP_OK(hipGraphLaunch(F->gx[variant], F->stream));
+    return BIDO_OK;
+}
+
+struct SliceRun {
+    double yy = 0.0, rel = 0.0;
+    int it = 0;
+    bool done = false, conv = false;
+    bido_status status = BIDO_OK;
+    std::string err;
+};
+
+// Step 2 for all slices of a fused batch (Steps 1 and 3 already launched):
+// PCG from the present x with per-slice stopping tests.
+bido_status fused_pcg(FusedBatch* F, const std::vector<bido_ctx*>& ctx, std::vector<SliceRun>& sr) {
+    const int S = F->S;
+    hipStream_t s = F->stream;
+    launch_seg_spmv(s, F->T, F->lam, F->spmv_group, 1, F->x, F->Y, F->r, F->part(FR_RR), F->part(FR_YY));
+    HIP_OK(hipMemcpyAsync(F->sc_host, F->sc, F->region(FR_YY + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    sr.assign(S, SliceRun());
+    int active = 0;
+    for (int i = 0; i < S; ++i) {
+        SliceRun& q = sr[i];
+        q.yy = F->host_sum(FR_YY, i);
+        q.rel = q.yy > 0 ? std::sqrt(F->host_sum(FR_RR, i) / q.yy) : 0.0;
+        if (q.yy == 0.0) {
+            launch_fill(s, F->n2[i], F->x + F->off[i], 0.0);
+            q.done = q.conv = true;
+        } else if (q.rel <= ctx[i]->params.tol) {
+            q.done = q.conv = true;
+        }
+        F->done_host[i] = q.done ? 1 : 0;
+        active += !q.done;
+    }
+    int rho = 0;
+    bool first = true;
+    while (active > 0) {
+        HIP_OK(hipMemcpyAsync(F->done, F->done_host, S, hipMemcpyHostToDevice, s));
+        bido_status e;
+        if (first) {
+            e = fused_launch(F, 0);
+        } else {
+            e = fused_launch(F, rho == 0 ? 1 : 2);
+            rho = 1 - rho;
+        }
+        if (e) return e;
+        first = false;
+        for (int i = 0; i < S; ++i) sr[i].it += !sr[i].done;
+        HIP_OK(hipStreamSynchronize(s));
+        active = 0;
+        for (int i = 0; i < S; ++i) {
+            SliceRun& q = sr[i];
+            if (q.done) continue;
+            const double pq = F->sc_host[2 * (int64_t)S + i], rz = F->sc_host[(int64_t)rho * S + i];
+            q.rel = std::sqrt(F->host_sum(FR_RR, i) / q.yy);
+            if (!(pq > 0.0) || !(rz > 0.0) || !std::isfinite(q.rel)) {
+                q.done = true;
+                q.status = BIDO_ERR_NOT_SPD;
+                q.err = "CG breakdown (p.Ap = " + std::to_string(pq) + ", r.z = " + std::to_string(rz) + ")";
+            } else if (q.rel <= ctx[i]->params.tol) {
+                q.done = q.conv = true;
+            } else if (q.it >= ctx[i]->params.max_iter) {
+                q.done = true;
+                q.status = BIDO_ERR_NOT_CONVERGED;
+                q.err = "tolerance not reached within max_iter";
+            }
+            F->done_host[i] = q.done ? 1 : 0;
+            active += !q.done;
+        }
+    }
+    return BIDO_OK;
+}
+
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -937,8 +1208,8 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     if ((e = CsrHostView::up(hs.auv, c->auv))) return e;
     if ((e = build_factor_dev(hs.p1, true, c->p1, hs.params.n_threads))) return e;
     if ((e = build_factor_dev(hs.pk, true, c->pk, hs.params.n_threads))) return e;
-    hs.p1.clear_top_cache();
-    hs.pk.clear_top_cache();
+    hs.p1.trim_top_cache(c->p1.top_h);      // a fused batch reuses hierarchical tops
+    hs.pk.trim_top_cache(c->pk.top_h);
     const int64_t n2 = c->n2;
     for (double** b : {&c->x, &c->r, &c->z, &c->p, &c->q, &c->Y, &c->r_old})
         HIP_OK(hipMalloc((void**)b, n2 * sizeof(double)));
@@ -993,12 +1264,21 @@ struct bido_batch {
     std::vector<hipEvent_t> done;
     hipEvent_t start = nullptr;
     hipStream_t stream = nullptr;      // caller's stream
+    std::unique_ptr<FusedBatch> fused; // fused batch (then no own streams)
+    std::vector<double*> saved_x, saved_Y;
     ~bido_batch() {
+        if (fused) fused->drop_graphs();
         for (size_t i = 0; i < ctx.size(); ++i) {
+            if (fused) hipStreamSynchronize(ctx[i]->stream);
             ctx[i]->stream = saved[i];
             ctx[i]->batched = false;
             ctx[i]->drop_graphs();
+            if (i < saved_x.size()) {
+                ctx[i]->x = saved_x[i];
+                ctx[i]->Y = saved_Y[i];
+            }
         }
+        fused.reset();
         for (hipStream_t s : own) hipStreamDestroy(s);
         for (hipEvent_t e : done) hipEventDestroy(e);
         if (start) hipEventDestroy(start);
@@ -1049,10 +1329,214 @@ bido_status bido_batch_create(bido_ctx* const* ctxs, int n_ctx, int n_streams, v
     return BIDO_OK;
 }
 
+bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stream, bido_batch** out) {
+    if (!ctxs || n_ctx < 1 || !out) return fail(BIDO_ERR_ARG, "null argument or empty batch");
+    *out = nullptr;
+    for (int i = 0; i < n_ctx; ++i) {
+        if (!ctxs[i]) return fail(BIDO_ERR_ARG, "null context");
+        if (ctxs[i]->batched) return fail(BIDO_ERR_STATE, "context already in a batch");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(BIDO_ERR_ARG, "context listed twice");
+        if (ctxs[i]->precond != BIDO_PRECOND_PLAIN || ctxs[i]->gnn.collecting)
+            return fail(BIDO_ERR_STATE, "a fused batch runs the plain preconditioner only");
+        if (ctxs[i]->precision != ctxs[0]->precision)
+            return fail(BIDO_ERR_STATE, "a fused batch needs one precision for all slices");
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    auto b = std::make_unique<bido_batch>();
+    b->stream = (hipStream_t)stream;
+    HIP_OK(hipEventCreateWithFlags(&b->start, hipEventDisableTiming));
+    hipEvent_t ev;
+    HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    b->done.push_back(ev);
+    auto F = std::make_unique<FusedBatch>();
+    const int S = n_ctx;
+    F->S = S;
+    F->precision = ctxs[0]->precision;
+    F->spmv_group = ctxs[0]->spmv_group;
+    int64_t n = 0;
+    int big = 0;
+    for (int i = 0; i < S; ++i) {
+        F->off.push_back(n);
+        F->n2.push_back(ctxs[i]->n2);
+        n += ctxs[i]->n2;
+        if (ctxs[i]->n2 > ctxs[big]->n2) big = i;
+        F->spmv_group = std::max(F->spmv_group, ctxs[i]->spmv_group);
+    }
+    if (n >= INT32_MAX) return fail(BIDO_ERR_ARG, "fused batch too large for 32-bit column indices");
+    F->n = n;
+    std::vector<const Csr*> lam, avu, auv;
+    std::vector<int64_t> o, ou, ov;
+    for (int i = 0; i < S; ++i) {
+        lam.push_back(&ctxs[i]->hs.lam);
+        avu.push_back(&ctxs[i]->hs.avu);
+        auv.push_back(&ctxs[i]->hs.auv);
+        o.push_back(F->off[i]);
+        ov.push_back(F->off[i] + ctxs[i]->N);
+    }
+    bido_status e;
+    if ((e = union_csr(lam, o, o, n, F->lam))) return e;
+    if ((e = union_csr(avu, ov, o, n, F->avu))) return e;
+    if ((e = union_csr(auv, o, ov, n, F->auv))) return e;
+    {
+        // merged forests; each tree keeps the cut of its own plan (and its
+        // hierarchical top), the tiles are those of the largest slice
+        std::vector<const Factor*> f1, fk;
+        for (int i = 0; i < S; ++i) {
+            f1.push_back(&ctxs[i]->hs.p1);
+            fk.push_back(&ctxs[i]->hs.pk);
+        }
+        const bool want32 = F->precision == BIDO_PREC_MIXED;
+        const int nth = ctxs[0]->hs.params.n_threads;
+        Factor m;
+        merge_factors(f1, o, n, m);
+        for (int i = 0; i < S; ++i) m.part_top_h[i] = ctxs[i]->p1.top_h;
+        PlanOptions op = ctxs[big]->p1.opts;
+        op.top_h = -1;
+        if ((e = build_factor_dev(m, want32, F->p1, nth, &op))) return e;
+        m = Factor();
+        merge_factors(fk, ov, n, m);
+        for (int i = 0; i < S; ++i) m.part_top_h[i] = ctxs[i]->pk.top_h;
+        op = ctxs[big]->pk.opts;
+        op.top_h = -1;
+        if ((e = build_factor_dev(m, want32, F->pk, nth, &op))) return e;
+    }
+    {
+        std::vector<int64_t> nu, nh, len;
+        for (int i = 0; i < S; ++i) {
+            nu.push_back(ctxs[i]->N);
+            nh.push_back(ctxs[i]->NH);
+        }
+        std::vector<SegBlock> blk;
+        std::vector<SegSlice> sl;
+        seg_layout(o, F->n2, o, nu, blk, sl);
+        if ((e = seg_upload(F.get(), blk, sl, F->T))) return e;
+        F->slices = sl;
+        seg_layout(o, nu, o, nu, blk, sl);
+        if ((e = seg_upload(F.get(), blk, sl, F->Tu))) return e;
+        seg_layout(ov, nh, o, nu, blk, sl);
+        if ((e = seg_upload(F.get(), blk, sl, F->Tv))) return e;
+    }
+    for (double** v : {&F->x, &F->r, &F->z, &F->p, &F->q, &F->Y, &F->tA, &F->tB, &F->tC, &F->tD, &F->r_old}) {
+        HIP_OK(hipMalloc((void**)v, std::max<int64_t>(n, 1) * sizeof(double)));
+        HIP_OK(hipMemset(*v, 0xFF, std::max<int64_t>(n, 1) * sizeof(double)));
+    }
+    const int64_t nsc = F->region(FR_COUNT);
+    HIP_OK(hipMalloc((void**)&F->sc, nsc * sizeof(double)));
+    HIP_OK(hipMemset(F->sc, 0xFF, nsc * sizeof(double)));
+    HIP_OK(hipHostMalloc((void**)&F->sc_host, nsc * sizeof(double), hipHostMallocDefault));
+    HIP_OK(hipMalloc((void**)&F->done, S));
+    HIP_OK(hipHostMalloc((void**)&F->done_host, S, hipHostMallocDefault));
+    for (FactorDev* f : {&F->p1, &F->pk}) {
+        HIP_OK(hipMemset(f->ytmp, 0xFF, std::max<int64_t>(f->n, 1) * sizeof(double)));
+        HIP_OK(hipMemset(f->upd, 0xFF, std::max<int64_t>(f->upd_size, 1) * sizeof(double)));
+    }
+    HIP_OK(hipStreamCreateWithFlags(&F->stream, hipStreamNonBlocking));
+    HIP_OK(hipDeviceSynchronize());
+    for (int i = 0; i < S; ++i) {
+        bido_ctx* c = ctxs[i];
+        b->ctx.push_back(c);
+        b->saved.push_back(c->stream);
+        b->saved_x.push_back(c->x);
+        b->saved_Y.push_back(c->Y);
+        c->stream = F->stream;
+        c->x = F->x + F->off[i];
+        c->Y = F->Y + F->off[i];
+        c->batched = true;
+        c->drop_graphs();
+    }
+    F->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    b->fused = std::move(F);
+    *out = b.release();
+    return BIDO_OK;
+}
+
+bido_status bido_batch_set_graphs(bido_batch* b, int on) {
+    if (!b) return fail(BIDO_ERR_ARG, "null batch");
+    if (!b->fused) return fail(BIDO_ERR_STATE, "not a fused batch (its contexts' bido_set_graphs applies)");
+    b->fused->drop_graphs();
+    b->fused->graphs = on != 0;
+    return BIDO_OK;
+}
+
+bido_status bido_batch_info(const bido_batch* b, int* fused, int64_t* n_union, double* setup_seconds) {
+    if (!b) return fail(BIDO_ERR_ARG, "null batch");
+    if (fused) *fused = b->fused ? 1 : 0;
+    if (n_union) *n_union = b->fused ? b->fused->n : 0;
+    if (setup_seconds) *setup_seconds = b->fused ? b->fused->setup_seconds : 0.0;
+    return BIDO_OK;
+}
+
 void bido_batch_destroy(bido_batch* b) {
     if (!b) return;
     for (hipStream_t s : b->own) hipStreamSynchronize(s);
     delete b;
+}
+
+static bido_status fused_run(bido_batch* b, double* const* v, double* const* w, double* const* u, int64_t n0,
+                             int64_t n_steps, bido_stats* per_ctx, bido_stats* total) {
+    FusedBatch* F = b->fused.get();
+    const int S = (int)b->ctx.size();
+    for (int i = 0; i < S; ++i) {
+        const bido_ctx* c = b->ctx[i];
+        if (c->precond != BIDO_PRECOND_PLAIN || c->precision != F->precision || c->gnn.collecting)
+            return fail(BIDO_ERR_STATE, "a slice of the fused batch changed its preconditioner or precision");
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    HIP_OK(hipEventRecord(b->start, b->stream));
+    HIP_OK(hipStreamWaitEvent(F->stream, b->start, 0));
+    std::vector<SliceRun> sr;
+    std::vector<int64_t> tot(S, 0);
+    std::vector<int> last_it(S, 0);
+    int max_it = 0;
+    bido_status err = BIDO_OK;
+    std::string err_msg;
+    for (int64_t k = 0; k < n_steps && !err; ++k) {
+        const int64_t n = n0 + k;
+        for (int i = 0; i < S; ++i) step_prepare(b->ctx[i], v[i], w[i], u[i], n);
+        const bido_status e = fused_pcg(F, b->ctx, sr);
+        if (e) return e;
+        for (int i = 0; i < S; ++i) {
+            tot[i] += sr[i].it;
+            last_it[i] = sr[i].it;
+            max_it = std::max(max_it, sr[i].it);
+            if (sr[i].status && !err) {
+                err = sr[i].status;
+                err_msg = "slice " + std::to_string(i) + ": " + sr[i].err;
+            }
+            if (!sr[i].status || sr[i].status == BIDO_ERR_NOT_CONVERGED) step_write(b->ctx[i], v[i], u[i]);
+        }
+    }
+    HIP_OK(hipEventRecord(b->done[0], F->stream));
+    HIP_OK(hipStreamWaitEvent(b->stream, b->done[0], 0));
+    HIP_OK(hipStreamSynchronize(F->stream));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int64_t all = 0;
+    bool all_conv = true;
+    double worst = 0.0;
+    for (int i = 0; i < S; ++i) {
+        all += tot[i];
+        const bool conv = !sr.empty() && sr[i].conv;
+        all_conv = all_conv && (n_steps == 0 || conv);
+        if (!sr.empty()) worst = std::max(worst, sr[i].rel);
+        if (per_ctx) {
+            std::memset(&per_ctx[i], 0, sizeof(per_ctx[i]));
+            per_ctx[i].iterations = last_it[i];
+            per_ctx[i].rel_residual = sr.empty() ? 0.0 : sr[i].rel;
+            per_ctx[i].converged = conv ? 1 : 0;
+            per_ctx[i].total_iterations = tot[i];
+            per_ctx[i].ms = ms;
+        }
+    }
+    if (total) {
+        std::memset(total, 0, sizeof(*total));
+        total->iterations = max_it;
+        total->converged = all_conv ? 1 : 0;
+        total->rel_residual = worst;
+        total->ms = ms;
+        total->total_iterations = all;
+    }
+    return err ? fail(err, err_msg) : BIDO_OK;
 }
 
 bido_status bido_batch_run(bido_batch* b, double* const* v, double* const* w, double* const* u, double dt,
@@ -1067,6 +1551,7 @@ bido_status bido_batch_run(bido_batch* b, double* const* v, double* const* w, do
             return fail(BIDO_ERR_STATE, "the additive learned mode needs a host check inside the apply; "
                                         "not available in a batch");
     }
+    if (b->fused) return fused_run(b, v, w, u, n0, n_steps, per_ctx, total);
     auto t0 = std::chrono::steady_clock::now();
     HIP_OK(hipEventRecord(b->start, b->stream));
     for (hipStream_t s : b->own) HIP_OK(hipStreamWaitEvent(s, b->start, 0));
@@ -1573,7 +2058,7 @@ bido_status bido_autotune(bido_ctx* c, int reps, bido_tune_report* rep) {
                 if (o.fwd_cols == at.fwd_cols && o.bwd_rows == at.bwd_rows) continue;
                 attempt(o);
             }
-        f.clear_top_cache();
+        f.trim_top_cache(cur.top_h);
         HIP_OK(hipMemset(cur.ytmp, 0xFF, std::max<int64_t>(cur.n, 1) * sizeof(double)));
         HIP_OK(hipMemset(cur.upd, 0xFF, std::max<int64_t>(cur.upd_size, 1) * sizeof(double)));
         r.us_after[which] = best * 1e3;

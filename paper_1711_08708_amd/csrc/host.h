@@ -150,6 +150,18 @@ struct Factor {
     // reuse them); clear_top_cache() frees them
     mutable std::map<int, std::shared_ptr<const TopPart>> top_cache;
     void clear_top_cache() const { top_cache.clear(); }
+    // keep only the hierarchical top of cut `keep` (small; a merged forest
+    // reuses it)
+    void trim_top_cache(int keep) const {
+        for (auto it = top_cache.begin(); it != top_cache.end();)
+            it = (it->first == keep && it->second->hodlr) ? std::next(it) : top_cache.erase(it);
+    }
+    // merged forest: the factors it was built from (only read while they
+    // live), their index offsets, first node ids and the top cut of each
+    // (-1: the cost model's)
+    std::vector<const Factor*> parts;
+    std::vector<int64_t> part_off;
+    std::vector<int> part_node0, part_top_h;
     int64_t dense_entries() const;
     int64_t stored_entries() const;  // after compression
     int64_t n_lowrank() const;

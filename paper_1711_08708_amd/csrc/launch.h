@@ -66,6 +66,23 @@ struct TriPlan {
     double* ht = nullptr;         // projections, 2k per block
 };
 
+// Row ranges of a batch of independent slices held in one union vector:
+// block b works on rows [r0, r1) of slice `slice`; slice s owns blocks
+// [b0, b1), starts at union row `base` and has `nu` rows of its first part.
+struct SegBlock {
+    int64_t r0, r1;
+    int32_t slice, pad;
+};
+struct SegSlice {
+    int64_t base, nu;
+    int32_t b0, b1;
+};
+struct SegTable {
+    int nblocks = 0;
+    const SegBlock* blk = nullptr;   // device
+    const SegSlice* sl = nullptr;    // device
+};
+
 void launch_fill(hipStream_t s, int64_t n, double* x, double v);
 void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst);
 void launch_scatter_in_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst);
@@ -107,5 +124,21 @@ void launch_tri_fwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, c
 template <typename T>
 void launch_tri_bwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
                         const T* panel, const int64_t* bidx, const double* y, double* x);
+
+// Segmented PCG kernels of a batch (batch.hip).  Scalars are per slice:
+// rho[s], done[s] (1: frozen), pq_out[s], rho_new[s]; partial regions have
+// one entry per block of the table.
+void launch_seg_spmv(hipStream_t s, const SegTable& T, const CsrDev& A, int group, int mode, const double* x,
+                     const double* y, double* out, double* part0, double* part1);
+void launch_seg_csr(hipStream_t s, const SegTable& T, const CsrDev& A, int group, const double* x, const double* b,
+                    double* y);
+void launch_seg_pcg_update(hipStream_t s, const SegTable& T, double* x, double* r, double* r_old, const double* p,
+                           const double* q, const double* part_pq, double* part_rr, const double* rho,
+                           const uint8_t* done, double* pq_out);
+void launch_seg_combine(hipStream_t s, const SegTable& T, double* z, const double* a, const double* b,
+                        const double* r, const double* r_old, double* part_rz, double* part_zro);
+void launch_seg_p_update(hipStream_t s, const SegTable& T, const double* z, double* p, const double* part_rz,
+                         const double* part_zro, int first, int flexible, const double* rho_old, double* rho_new,
+                         const uint8_t* done);
 
 }  // namespace bido

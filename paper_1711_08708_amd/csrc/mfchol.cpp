@@ -357,6 +357,11 @@ void merge_factors(const std::vector<const Factor*>& fs, const std::vector<int64
     for (size_t s = 0; s < fs.size(); ++s) {
         const Factor& f = *fs[s];
         const int64_t o = offs[s];
+        out.parts.push_back(&f);
+        out.part_off.push_back(o);
+        out.part_node0.push_back(node_off);
+        // a single cached top names the cut the slice's own plan uses
+        out.part_top_h.push_back(f.top_cache.size() == 1 ? f.top_cache.begin()->first : -1);
         for (int64_t g : f.grounds) out.grounds.push_back(g + o);
         if (coords)
             for (int64_t i = 0; i < f.n * f.dim; ++i) out.xyz[o * f.dim + i] = f.xyz[i];

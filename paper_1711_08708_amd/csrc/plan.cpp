@@ -242,39 +242,57 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
         }
     }
 
-    // ---- subtree cut: largest height whose subtrees are numerous enough ----
+    // ---- subtree cut: per tree, the largest height whose subtrees are numerous
+    // enough (a merged forest keeps each tree's own cut)
     const int H = t.height;
     std::vector<std::vector<int>> by_h(H + 1);
     for (int id = 0; id < nn; ++id) by_h[t.nodes[id].height].push_back(id);
-    std::vector<int> maxw_le(H + 1, 0), maxf_le(H + 1, 0);
-    for (int h = 0; h <= H; ++h) {
-        int m = h > 0 ? maxw_le[h - 1] : 0, mf = h > 0 ? maxf_le[h - 1] : 0;
-        for (int id : by_h[h]) {
-            m = std::max(m, f.fronts[id].nI);
-            mf = std::max(mf, f.fronts[id].nI + f.fronts[id].nB);
+    std::vector<int> root_of(nn, -1), roots;
+    for (int id = nn - 1; id >= 0; --id) {
+        const int par = t.nodes[id].parent;
+        root_of[id] = par < 0 ? id : root_of[par];
+        if (par < 0) roots.push_back(id);
+    }
+    std::reverse(roots.begin(), roots.end());
+    const bool forest = roots.size() > 1;
+    std::vector<int> hc_of(nn, -1);
+    {
+        std::vector<std::vector<int>> members(nn);
+        for (int id = 0; id < nn; ++id) members[root_of[id]].push_back(id);
+        for (int r : roots) {
+            const int Hr = t.nodes[r].height;
+            std::vector<int> mw(Hr + 1, 0), mf(Hr + 1, 0), nroots(Hr + 2, 0);
+            for (int id : members[r]) {
+                const int h = t.nodes[id].height;
+                mw[h] = std::max(mw[h], f.fronts[id].nI);
+                mf[h] = std::max(mf[h], f.fronts[id].nI + f.fronts[id].nB);
+                // id is a subtree root for every cut in [its height, its parent's height)
+                const int hp = t.nodes[id].parent < 0 ? Hr + 1 : t.nodes[t.nodes[id].parent].height;
+                nroots[h] += 1;
+                nroots[hp] -= 1;
+            }
+            for (int h = 1; h <= Hr; ++h) {
+                mw[h] = std::max(mw[h], mw[h - 1]);
+                mf[h] = std::max(mf[h], mf[h - 1]);
+                nroots[h] += nroots[h - 1];
+            }
+            int cut = -1;
+            for (int want : {256, 64, 16, 1}) {
+                for (int h = Hr; h >= 0 && cut < 0; --h)
+                    if (mw[h] <= PLAN_SUB_MAXW && mf[h] <= PLAN_SUB_MAXF && nroots[h] >= want) cut = h;
+                if (cut >= 0) break;
+            }
+            for (int id : members[r]) hc_of[id] = cut;
         }
-        maxw_le[h] = m;
-        maxf_le[h] = mf;
     }
-    auto is_root = [&](int id, int h) {
-        const NdNode& nd = t.nodes[id];
-        return nd.height <= h && (nd.parent < 0 || t.nodes[nd.parent].height > h);
-    };
-    auto roots_at = [&](int h) {
-        int r = 0;
-        for (int id = 0; id < nn; ++id) r += is_root(id, h);
-        return r;
-    };
+    auto in_sub = [&](int id) { return t.nodes[id].height <= hc_of[id]; };
     int hc = -1;
-    for (int want : {256, 64, 16, 1}) {
-        for (int h = H; h >= 0 && hc < 0; --h)
-            if (maxw_le[h] <= PLAN_SUB_MAXW && maxf_le[h] <= PLAN_SUB_MAXF && roots_at(h) >= want) hc = h;
-        if (hc >= 0) break;
-    }
+    for (int id = 0; id < nn; ++id) hc = std::max(hc, hc_of[id]);
     p.hc = hc;
     if (hc >= 0) {
         for (int rt = 0; rt < nn; ++rt) {
-            if (!is_root(rt, hc)) continue;
+            const NdNode& nr = t.nodes[rt];
+            if (!in_sub(rt) || (nr.parent >= 0 && in_sub(nr.parent))) continue;
             std::vector<std::vector<int>> byh(hc + 1);
             std::vector<int> stack{rt};
             while (!stack.empty()) {
@@ -291,7 +309,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
             p.sub_hoff.push_back((int32_t)p.sub_nodes.size());
             ++p.n_sub;
         }
-        p.sub_maxw = maxw_le[hc];
+        for (int id : p.sub_nodes) p.sub_maxw = std::max(p.sub_maxw, f.fronts[id].nI);
     }
     p.sub_tn.clear();
     for (int id : p.sub_nodes) p.sub_tn.push_back(p.nodes[id]);
@@ -304,14 +322,13 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     // independent blocks) gets one cut per tree and one hierarchical top per
     // tree, concatenated.  Environment BIDO_TOP_H forces a single tree's cut
     // (a value above the tree height switches the top off).
-    std::vector<int> root_of(nn, -1), roots;
-    for (int id = nn - 1; id >= 0; --id) {
-        const int par = t.nodes[id].parent;
-        root_of[id] = par < 0 ? id : root_of[par];
-        if (par < 0) roots.push_back(id);
-    }
-    std::reverse(roots.begin(), roots.end());
-    const bool forest = roots.size() > 1;
+    // part of a merged forest that holds node id (-1: none recorded)
+    auto part_of = [&](int id) {
+        int k = -1;
+        for (size_t q = 0; q < f.parts.size() && q < f.part_node0.size(); ++q)
+            if (f.part_node0[q] <= id) k = (int)q;
+        return k < (int)f.part_top_h.size() && k < (int)f.part_off.size() ? k : -1;
+    };
     // cost-model cut of the tree rooted at r (heights of its own nodes)
     auto model_cut = [&](int r, int& lowest) {
         constexpr double T_FWD = 10e-6, T_BWD = 25e-6, BW_LVL = 2.0e12, T_TOP = 10e-6, BW_TOP = 4.5e12;
@@ -320,7 +337,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
         lowest = Hr + 1;
         double best_cost = 0.0, saved = 0.0;
         int64_t cum = 0;
-        for (int h = Hr; h > hc; --h) {
+        for (int h = Hr; h > hc_of[r]; --h) {
             double pb = 0.0;
             for (int id : by_h[h]) {
                 if (root_of[id] != r) continue;
@@ -348,10 +365,14 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
         for (int id = 0; id < nn; ++id) cut_of[id] = best;
         p.top_h = best;
     } else {
+        // a merged forest may carry each tree's cut (the one its own plan uses)
         std::vector<int> rc(nn, H + 1);
         for (int r : roots) {
             int lowest;
             rc[r] = model_cut(r, lowest);
+            const int k = part_of(r);
+            if (k >= 0 && f.part_top_h[k] >= 0)
+                rc[r] = std::max(lowest, std::min(t.nodes[r].height + 1, f.part_top_h[k]));
         }
         for (int id = 0; id < nn; ++id) cut_of[id] = rc[root_of[id]];
         p.top_h = -1;
@@ -360,20 +381,12 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     std::vector<char> is_top(nn, 0);
     for (int id = 0; id < nn; ++id) is_top[id] = t.nodes[id].height >= cut_of[id];
 
-    // the top of the nodes `top` (post-order): vertices, gather lists of the
-    // bottom roots, S_top^-1 (hierarchical when eps > 0 or `hier`)
-    auto build_top = [&](const std::vector<int>& top, bool hier, TopPart& T) -> bool {
-        auto t0 = std::chrono::steady_clock::now();
-        T.eps = f.eps;
-        std::vector<int32_t> tmap(f.n, -1);
-        int64_t nt = 0;
-        for (int id : top)
-            for (int i = 0; i < f.fronts[id].nI; ++i) {
-                tmap[f.fronts[id].off + i] = (int32_t)nt++;
-                T.pos.push_back(f.fronts[id].off + i);
-            }
-        if (nt > PLAN_TOP_MAX) { err = "dense top too large"; return false; }
-        T.n_top = nt;
+    // top index of each vertex (-1 elsewhere); reset after each use
+    std::vector<int32_t> tmap(f.n, -1);
+    // gather lists of the bottom roots below the nodes `top` into T (top
+    // indices from tmap)
+    auto gather_lists = [&](const std::vector<int>& top, TopPart& T) -> bool {
+        const int64_t nt = T.n_top;
         std::vector<char> intop(nn, 0);
         for (int id : top) intop[id] = 1;
         // bottom roots: the update vector of each one covers its boundary,
@@ -390,12 +403,65 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
             }
         }
         T.gptr.assign(nt + 1, 0);
+        T.gsrc.clear();
         for (int64_t k = 0; k < nt; ++k) {
             T.gptr[k + 1] = T.gptr[k] + (int32_t)lists[k].size();
             for (int64_t src : lists[k]) T.gsrc.push_back(src);
         }
         if (T.gsrc.empty()) T.gsrc.push_back(0);
-        top_inverse(f, top, tmap, nt, T.inv, n_threads);
+        return true;
+    };
+    // a merged tree whose own plan holds a hierarchical top of the same cut:
+    // take its vertices (shifted by the tree's offset, same order) and its
+    // hierarchical form; only the gather lists are rebuilt
+    auto reuse_top = [&](const std::vector<int>& top, const TopPart& src, int64_t off, TopPart& T) -> bool {
+        int64_t cnt = 0;
+        for (int id : top) cnt += f.fronts[id].nI;
+        if (!src.hodlr || src.n_top != cnt) return false;
+        bool ok = true;
+        for (int64_t k = 0; k < src.n_top && ok; ++k) {
+            const int64_t v = src.pos[k] + off;
+            ok = v >= 0 && v < f.n && tmap[v] < 0;
+            if (ok) tmap[v] = (int32_t)k;
+        }
+        for (int id : top)
+            for (int i = 0; i < f.fronts[id].nI && ok; ++i) ok = tmap[f.fronts[id].off + i] >= 0;
+        if (ok) {
+            T = TopPart();
+            T.eps = src.eps;
+            T.n_top = src.n_top;
+            T.pos.resize(src.n_top);
+            for (int64_t k = 0; k < src.n_top; ++k) T.pos[k] = src.pos[k] + off;
+            T.hodlr = true;
+            T.hd = src.hd;
+            T.cols = src.cols;
+            ok = gather_lists(top, T);
+        }
+        for (int64_t k = 0; k < src.n_top; ++k) {
+            const int64_t v = src.pos[k] + off;
+            if (v >= 0 && v < f.n) tmap[v] = -1;
+        }
+        return ok;
+    };
+
+    // the top of the nodes `top` (post-order): vertices, gather lists of the
+    // bottom roots, S_top^-1 (hierarchical when eps > 0 or `hier`)
+    auto build_top = [&](const std::vector<int>& top, bool hier, TopPart& T) -> bool {
+        auto t0 = std::chrono::steady_clock::now();
+        T.eps = f.eps;
+        int64_t nt = 0;
+        for (int id : top)
+            for (int i = 0; i < f.fronts[id].nI; ++i) {
+                tmap[f.fronts[id].off + i] = (int32_t)nt++;
+                T.pos.push_back(f.fronts[id].off + i);
+            }
+        T.n_top = nt;
+        bool ok = nt <= PLAN_TOP_MAX;
+        if (!ok) err = "dense top too large";
+        if (ok) ok = gather_lists(top, T);
+        if (ok) top_inverse(f, top, tmap, nt, T.inv, n_threads);
+        for (int64_t v : T.pos) tmap[v] = -1;
+        if (!ok) return false;
         if ((f.eps > 0.0 || hier) && f.dim > 0 && (int64_t)f.xyz.size() >= f.n * f.dim) {
             // hierarchical form: bisection order of the top vertices, then
             // low-rank off-diagonal blocks at relative accuracy eps
@@ -482,7 +548,14 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
                 if (is_top[id] && root_of[id] == r) top.push_back(id);
             if (top.empty()) continue;
             TopPart T;
-            if (!build_top(top, true, T)) return false;
+            const int k = part_of(r);
+            bool reused = false;
+            if (k >= 0) {
+                auto hit = f.parts[k]->top_cache.find(cut_of[r]);
+                if (hit != f.parts[k]->top_cache.end() && hit->second->eps == f.eps)
+                    reused = reuse_top(top, *hit->second, f.part_off[k], T);
+            }
+            if (!reused && !build_top(top, true, T)) return false;
             if (!T.hodlr) { err = "a forest needs vertex coordinates for its tops"; return false; }
             append_top(*np, T);
         }
@@ -516,7 +589,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     // ---- level phases above the cut ------------------------------------------
     // Work-item limits: columns per forward item and rows per backward item.
     // Splitting a tile over several items exposes more workgroups but needs a
-    // cross-workgroup combine (device-scope fence), so the limits are tunable
+    // combine launch after the level, so the limits are tunable
     // (environment BIDO_FWD_COLS, BIDO_BWD_MAXR) within the LDS staging bound.
     const int fwd_cols = o.fwd_cols > 0 ? std::max(32, std::min(PLAN_LDS_DOUBLES, o.fwd_cols))
                                         : env_limit("BIDO_FWD_COLS", PLAN_FWD_COLS, 32, PLAN_LDS_DOUBLES);
@@ -527,14 +600,19 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     std::vector<std::pair<size_t, size_t>> fspan, bspan, fcspan, bcspan;
     struct LdsSz { size_t f, b; };
     std::vector<LdsSz> lds;
-    int Hl = hc;                            // highest level with non-top nodes
+    // level heights lvl0 .. Hl: the nodes neither in the subtree phase nor in the top
+    int lvl0 = H + 1;
+    for (int r : roots) lvl0 = std::min(lvl0, hc_of[r] + 1);
+    if (roots.empty()) lvl0 = 0;
+    p.lvl0 = lvl0;
+    int Hl = lvl0 - 1;
     for (int id = 0; id < nn; ++id)
-        if (!is_top[id] && t.nodes[id].height > Hl) Hl = t.nodes[id].height;
-    for (int h = hc + 1; h <= Hl; ++h) {
+        if (!is_top[id] && !in_sub(id) && t.nodes[id].height > Hl) Hl = t.nodes[id].height;
+    for (int h = lvl0; h <= Hl; ++h) {
         const size_t f0 = p.fwd_items.size(), fc0 = p.fwd_comb.size();
         size_t ldsf = 0;
         for (int id : by_h[h]) {
-            if (is_top[id]) continue;
+            if (is_top[id] || in_sub(id)) continue;
             const Front& fr = f.fronts[id];
             const int nI = fr.nI, nF = fr.nI + fr.nB;
             if (nI == 0) continue;
@@ -567,11 +645,11 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
         fcspan.push_back({fc0, p.fwd_comb.size() - fc0});
         lds.push_back({ldsf, 0});
     }
-    for (int h = hc + 1; h <= Hl; ++h) {
+    for (int h = lvl0; h <= Hl; ++h) {
         const size_t b0 = p.bwd_items.size(), bc0 = p.bwd_comb.size();
         size_t ldsb = 0;
         for (int id : by_h[h]) {
-            if (is_top[id]) continue;
+            if (is_top[id] || in_sub(id)) continue;
             const Front& fr = f.fronts[id];
             const int nI = fr.nI, nF = fr.nI + fr.nB;
             if (nI == 0) continue;
@@ -602,7 +680,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
         }
         bspan.push_back({b0, p.bwd_items.size() - b0});
         bcspan.push_back({bc0, p.bwd_comb.size() - bc0});
-        lds[h - hc - 1].b = ldsb;
+        lds[h - lvl0].b = ldsb;
     }
     for (size_t k = 0; k < fspan.size(); ++k)
         p.spans.push_back({fspan[k].first, fspan[k].second, bspan[k].first, bspan[k].second,
@@ -626,17 +704,18 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
             const double fv = 8.0 * (fr.nI + (fr.nI + fr.nB) + cb + fr.nI + fr.nB);
             // backward: panel + y_t + boundary ids + x_B + x_t
             const double bv = 8.0 * (fr.nI + 2.0 * fr.nB + fr.nI);
+            if (in_sub(id)) {
+                p.sub_fwd_bytes64 += 8.0 * pe + fv;
+                p.sub_bwd_bytes64 += 8.0 * pe + bv;
+                p.sub_fwd_bytes32 += 4.0 * pe + fv;
+                p.sub_bwd_bytes32 += 4.0 * pe + bv;
+                continue;
+            }
             p.fwd_bytes64[h] += 8.0 * pe + fv;
             p.bwd_bytes64[h] += 8.0 * pe + bv;
             p.fwd_bytes32[h] += 4.0 * pe + fv;
             p.bwd_bytes32[h] += 4.0 * pe + bv;
         }
-    for (int h = 0; h <= hc; ++h) {
-        p.sub_fwd_bytes64 += p.fwd_bytes64[h];
-        p.sub_bwd_bytes64 += p.bwd_bytes64[h];
-        p.sub_fwd_bytes32 += p.fwd_bytes32[h];
-        p.sub_bwd_bytes32 += p.bwd_bytes32[h];
-    }
     p.meta_bytes = (int64_t)(p.nodes.size() * sizeof(TriNode) + p.bidx.size() * 8 + p.ea.size() * 8 +
                              p.fwd_items.size() * sizeof(TriItem) + p.bwd_items.size() * sizeof(BwdItem));
     if (p.scratch_size > (int64_t)1 << 31) { err = "plan scratch too large"; return false; }

@@ -30,10 +30,12 @@ struct FactorPlan {
     int64_t upd_size = 0;               // update workspace entries
     int max_nI = 0;
     // subtree phase
-    int hc = -1, n_sub = 0, sub_maxw = 0;
+    int hc = -1, n_sub = 0, sub_maxw = 0;  // hc: the highest subtree cut of any tree
     std::vector<int32_t> sub_nodes, sub_hoff;
     std::vector<TriNode> sub_tn;        // node records in sub_nodes order
-    // level phases (heights hc+1 .. height)
+    // level phases: span k covers height lvl0 + k (heights above each tree's
+    // subtree cut, below its top)
+    int lvl0 = 0;
     std::vector<TriItem> fwd_items;
     std::vector<BwdItem> bwd_items;
     // split tiles (more than one item) are summed by a combine launch after

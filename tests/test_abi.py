@@ -251,3 +251,31 @@ def test_forest_of_slices_emulates_each_slice(eps):
             assert np.isfinite(emu[lo:lo + n]).all()
             assert err <= 1e-11 + 1e3 * eps, (which, err)
             off += N + NH
+
+
+def test_forest_takes_over_each_slice_hierarchical_top():
+    """A merged tree whose slice already built its hierarchical top at the
+    same cut reuses it (no second inversion: zero host seconds for the
+    forest's tops) and then sweeps exactly like that slice's own plan."""
+    import paper_1711_08708_amd as B
+    eps = 1e-6
+    cfgs = [w.thorax2d(n_target=3000, seed=31), w.thorax2d(n_target=6000, seed=32, sigma_scale=0.8),
+            w.thorax2d(n_target=1500, seed=33)]
+    parts = [B.HostSetup(c, eps_h=eps) for c in cfgs]
+    sizes = [(len(p.index(B.IDX_UPOS)), len(p.index(B.IDX_VPOS))) for p in parts]
+    ntot = sum(a + b for a, b in sizes)
+    rng = np.random.default_rng(5)
+    for which in (B.FACTOR_P1, B.FACTOR_PK):
+        b = rng.normal(size=ntot)
+        refs, off = [], 0
+        for p, (N, NH) in zip(parts, sizes):
+            lo, n = (off, N) if which == B.FACTOR_P1 else (off + N, NH)
+            refs.append((lo, n, p.factor_emulate(which, b[lo:lo + n])))   # builds the slice's top
+            off += N + NH
+        merged = B.HostSetup.merged(parts)
+        top = merged.factor_top(which)
+        assert top["n_top"] > 0 and top["seconds"] == 0.0, top
+        emu = merged.factor_emulate(which, b)
+        for lo, n, ref in refs:
+            err = np.abs(emu[lo:lo + n] - ref).max() / np.abs(ref).max()
+            assert err <= 1e-13, (which, err)

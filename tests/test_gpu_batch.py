@@ -109,3 +109,118 @@ def test_graph_replays_match_eager_launches(torch, precision):
     assert out[0][1] == out[1][1]
     for a, b in zip(out[0][0], out[1][0]):
         assert np.array_equal(a, b)
+
+
+def _single_runs(B, cfgs, prec, n_steps):
+    out = []
+    for cfg in cfgs:
+        s = B.Solver(cfg, tol=1e-12, precision=prec)
+        s.set_graphs(False)
+        v, h, u = s.state()
+        its = [s.step(v, h, u, n)["iterations"] for n in range(n_steps)]
+        out.append(((v.cpu().numpy(), h.cpu().numpy(), u.cpu().numpy()), its))
+        s.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_batch_matches_single_slices_and_oracle(torch, precision):
+    """One union PCG over all slices (segmented vector kernels with per-slice
+    scalars, merged forests of the factors) follows each slice's own solve:
+    same iteration counts within one, states within 1e-9 of the slice run
+    alone (only the rounding order of the reductions differs), last step
+    against the FP64 oracle at 1e-8."""
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd
+    prec = B.PREC_MIXED if precision == "mixed" else B.PREC_FP64
+    cfgs = _slices() + [w.square2d(n=6, seed=4)]        # plus a one-block slice
+    n_steps = 12
+    ref = _single_runs(B, cfgs, prec, n_steps)
+    solvers = [B.Solver(cfg, tol=1e-12, precision=prec) for cfg in cfgs]
+    batch = B.Batch(solvers, fused=True)
+    info = batch.info()
+    print(precision, "fused union", info)
+    assert info["fused"] and info["n_union"] == sum(s.N + s.NH for s in solvers)
+    states = [s.state() for s in solvers]
+    its = []
+    for n in range(n_steps - 1):
+        tot, per = batch.run(states, n, 1)
+        assert tot["converged"] == 1
+        its.append([p["iterations"] for p in per])
+    before = [(st[0].cpu().numpy().copy(), st[1].cpu().numpy().copy()) for st in states]
+    tot, per = batch.run(states, n_steps - 1, 1)
+    its.append([p["iterations"] for p in per])
+    for k, (cfg, st) in enumerate(zip(cfgs, states)):
+        v, h, u = [t.cpu().numpy() for t in st]
+        fused_its = [row[k] for row in its]
+        print(f"  slice {k} ({cfg['name']}): iterations fused {fused_its} alone {ref[k][1]}")
+        assert all(abs(a - b) <= 1 for a, b in zip(fused_its, ref[k][1]))
+        for a, b in zip((v, h, u), ref[k][0]):
+            assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b), k
+        sy = bd.System(cfg)
+        Uo, Vo, _ = sy.step(before[k][0], before[k][1], n_steps - 1)
+        Uo = sy.to_global_u(Uo)
+        eu = np.linalg.norm(u - Uo) / np.linalg.norm(Uo)
+        ev = np.linalg.norm(v - Vo) / np.linalg.norm(Vo)
+        print(f"    e_u {eu:.2e} e_v {ev:.2e}")
+        assert eu <= 1e-8 and ev <= 1e-8
+    batch.close()
+    # the contexts work on their own again, on their own vectors
+    v, h, u = solvers[0].state()
+    assert solvers[0].step(v, h, u, 0)["converged"] == 1
+    for s in solvers:
+        s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_graph_replays_match_eager(torch, precision):
+    """The fused batch's captured iteration graphs, replayed with the per-slice
+    step kernels and host checks between them, give the eager trajectory bit
+    for bit."""
+    import paper_1711_08708_amd as B
+    prec = B.PREC_MIXED if precision == "mixed" else B.PREC_FP64
+    cfgs = _slices()[:3]
+    out = []
+    for graphs in (False, True):
+        solvers = [B.Solver(cfg, tol=1e-12, precision=prec) for cfg in cfgs]
+        batch = B.Batch(solvers, fused=True)
+        batch.set_graphs(graphs)
+        states = [s.state() for s in solvers]
+        its = [[p["iterations"] for p in batch.run(states, n, 1)[1]] for n in range(8)]
+        out.append(([[t.cpu().numpy() for t in st] for st in states], its))
+        batch.close()
+        for s in solvers:
+            s.close()
+    assert out[0][1] == out[1][1]
+    for a, b in zip(out[0][0], out[1][0]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_fused_batch_refusals(torch):
+    import paper_1711_08708_amd as B
+    cfgs = _slices()[:2]
+    a = B.Solver(cfgs[0], tol=1e-10)
+    b = B.Solver(cfgs[1], tol=1e-10, precision=B.PREC_MIXED)
+    with pytest.raises(B.BidoError):
+        B.Batch([a, b], fused=True)          # two precisions
+    b.close()
+    b = B.Solver(cfgs[1], tol=1e-10)
+    with pytest.raises(B.BidoError):
+        B.Batch([a, a], fused=True)          # listed twice
+    a.set_precond(B.PRECOND_LEARNED_ADDITIVE)
+    with pytest.raises(B.BidoError):
+        B.Batch([a, b], fused=True)          # plain preconditioner only
+    a.set_precond(B.PRECOND_PLAIN)
+    bt = B.Batch([a, b], fused=True)
+    with pytest.raises(B.BidoError):
+        B.Batch([b], fused=True)             # already in a batch
+    a.set_precision(B.PREC_MIXED)
+    with pytest.raises(B.BidoError):
+        bt.run([a.state(), b.state()], 0, 1)  # precision changed inside the batch
+    bt.close()
+    a.set_precision(B.PREC_FP64)
+    v, h, u = a.state()
+    a.run(v, h, u, 0, 2)
+    a.close()
+    b.close()
