@@ -7,6 +7,7 @@
 #include <omp.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <numeric>
 #include <stdexcept>
@@ -25,9 +26,10 @@ void compress(Factor& f, const double* xyz, int dim, double eps, double eta, int
 
 // B (m x n, row-major, leading dimension ld) ~ U V^T with U (m x k) and
 // V (n x k) column-major: Householder QR with column pivoting, stopped at the
-// first pivot |R_jj| <= eps |R_00|.
+// first pivot |R_jj| <= max(eps |R_00|, abs_tol) (a block far below the
+// matrix it belongs to gets rank 0 instead of a basis of rounding noise).
 void rrqr_lowrank(const double* B, int64_t ld, int m, int n, double eps, std::vector<double>& U,
-                  std::vector<double>& V, int& k) {
+                  std::vector<double>& V, int& k, double abs_tol) {
     std::vector<double> A((size_t)m * n);          // column-major work copy
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < n; ++j) A[(size_t)j * m + i] = B[(size_t)i * ld + j];
@@ -46,7 +48,7 @@ void rrqr_lowrank(const double* B, int64_t ld, int m, int n, double eps, std::ve
         const int p = (int)(std::max_element(nrm.begin() + j, nrm.end()) - nrm.begin());
         const double np = std::sqrt(nrm[p]);
         if (j == 0) r00 = np;
-        if (np == 0.0 || np <= eps * r00) break;
+        if (!(np > abs_tol) || np <= eps * r00 || !std::isfinite(np)) break;
         if (p != j) {
             std::swap_ranges(A.begin() + (size_t)j * m, A.begin() + (size_t)(j + 1) * m, A.begin() + (size_t)p * m);
             std::swap(nrm[j], nrm[p]);
@@ -150,10 +152,15 @@ void hodlr_build(const std::vector<double>& A, int64_t n, double eps, int leaf, 
     std::vector<std::vector<double>> Us(nb), Vs(nb);
     std::vector<int> ks(nb, 0);
     (void)n_threads;
+    // blocks are truncated relative to themselves, but never below eps (at
+    // least the square of the machine epsilon) times the largest entry
+    double scale = 0.0;
+    for (double v : A) scale = std::max(scale, std::fabs(v));
+    const double abs_tol = std::max(eps, DBL_EPSILON * DBL_EPSILON) * scale;
     for (int b = 0; b < nb; ++b) {
         const Node& nd = internal[b];
         rrqr_lowrank(&A[(size_t)nd.a * n + nd.m], n, (int)(nd.m - nd.a), (int)(nd.e - nd.m), eps, Us[b], Vs[b],
-                     ks[b]);
+                     ks[b], abs_tol);
     }
     int64_t toff = 0;
     for (int b = 0; b < nb; ++b) {

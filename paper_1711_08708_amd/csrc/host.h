@@ -180,9 +180,9 @@ void compress(Factor& f, const double* xyz, int dim, double eps, double eta,
 
 // Rank-revealing QR truncation: B (m x n row-major, leading dimension ld)
 // ~ U V^T, U (m x k) and V (n x k) column-major, stopping at the first pivot
-// below eps times the first one.
+// below eps times the first one or below abs_tol.
 void rrqr_lowrank(const double* B, int64_t ld, int m, int n, double eps, std::vector<double>& U,
-                  std::vector<double>& V, int& k);
+                  std::vector<double>& V, int& k, double abs_tol = 0.0);
 
 // Recursive geometric bisection order of n points (leaves of <= leaf points).
 void hodlr_order(int64_t n, const double* xyz, int dim, int leaf, std::vector<int64_t>& ord);

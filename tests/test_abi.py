@@ -279,3 +279,23 @@ def test_forest_takes_over_each_slice_hierarchical_top():
         for lo, n, ref in refs:
             err = np.abs(emu[lo:lo + n] - ref).max() / np.abs(ref).max()
             assert err <= 1e-13, (which, err)
+
+
+def test_hierarchical_top_with_a_decoupled_block():
+    """The heart of this slice falls into two parts, so the inverse of its
+    top Schur complement has an off-diagonal block that is zero up to
+    rounding (entries near 1e-162).  Truncation relative to that block alone
+    would keep a full-rank basis of underflowing noise (NaN in the sweep);
+    the block must get rank 0 and the sweep stay accurate."""
+    import paper_1711_08708_amd as B
+    cfg = w.thorax2d(n_target=32084, seed=1007, sigma_scale=0.7472320903063928)
+    hs = B.HostSetup(cfg, eps_h=1e-8)
+    n = len(hs.index(B.IDX_VPOS))
+    b = np.random.default_rng(7).normal(size=n)
+    ref = hs.factor_apply(B.FACTOR_PK, b)
+    emu = hs.factor_emulate(B.FACTOR_PK, b)
+    top = hs.factor_top(B.FACTOR_PK)
+    print("top", top)
+    assert np.isfinite(emu).all()
+    assert np.abs(emu - ref).max() <= 1e-6 * np.abs(ref).max()
+    assert top["stored_entries"] < top["n_top"] ** 2 // 4
