@@ -10,6 +10,8 @@
 //   mean_*              normalisation (M U, 1) = 0 of Prop. 1
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "kernels.h"
 #include "launch.h"
 
@@ -386,13 +388,20 @@ __device__ __forceinline__ double row_part(const T* __restrict__ Pc, int nI, int
             off += nF - (c + k) - 1;
         }
     }
-    // remainder (< SWEEP_ILP columns): predicated, one accumulator each
+    // remainder (< SWEEP_ILP columns): every lane issues all its loads at
+    // once (a finished lane reads the panel's first entry and drops it), so
+    // the tail costs one memory latency instead of one per column
+    int64_t offs[SWEEP_ILP - 1];
 #pragma unroll
     for (int k = 0; k < SWEEP_ILP - 1; ++k) {
-        if (c + k < cend) {
-            a[k] += (double)Pc[off] * w[c + k - cs];
-            off += nF - (c + k) - 1;
-        }
+        offs[k] = off;
+        off += nF - (c + k) - 1;
+    }
+#pragma unroll
+    for (int k = 0; k < SWEEP_ILP - 1; ++k) {
+        const bool ok = c + k < cend;
+        const double v = (double)Pc[ok ? offs[k] : 0] * w[ok ? c + k - cs : 0];
+        a[k] += v * (ok ? 1.0 : 0.0);      // (a select would let the load sink into a branch)
     }
     return sum_ilp(a);
 }
@@ -419,21 +428,33 @@ __device__ __forceinline__ double col_part(const T* __restrict__ P, int nI, int 
     int r = r0;
     int off = row_off32(r, nI);
     const int te = min(re, nI);
+    // triangle: the loads are unconditional (entry (rr, c > rr) is not
+    // stored, but off + c still lies inside the triangle) and the unstored
+    // products are dropped, so all SWEEP_ILP loads are in flight together
     for (; r + (SWEEP_ILP - 1) * S < te; r += SWEEP_ILP * S) {
 #pragma unroll
         for (int q = 0; q < SWEEP_ILP; ++q) {
             const int rr = r + q * S;
-            if (c <= rr) a[q] += (double)P[off + c] * z[rr - z0];
+            const double v = (double)P[off + c] * z[rr - z0];
+            a[q] += c <= rr ? v : 0.0;
             off = rr + S <= nI ? off + (rr << lgS) + SS : row_off32(rr + S, nI);
         }
+    }
+    // triangle tail: rows past te read the panel's first entry, dropped
+    int offs[SWEEP_ILP - 1];
+#pragma unroll
+    for (int q = 0; q < SWEEP_ILP - 1; ++q) {
+        const int rr = r + q * S;
+        offs[q] = off;
+        const int nxt = rr + S <= nI ? off + (rr << lgS) + SS : row_off32(rr + S, nI);
+        off = rr < te ? nxt : off;
     }
 #pragma unroll
     for (int q = 0; q < SWEEP_ILP - 1; ++q) {
         const int rr = r + q * S;
-        if (rr < te) {
-            if (c <= rr) a[q] += (double)P[off + c] * z[rr - z0];
-            off = rr + S <= nI ? off + (rr << lgS) + SS : row_off32(rr + S, nI);
-        }
+        const bool ok = rr < te;
+        const double v = (double)P[ok ? offs[q] + c : 0] * z[ok ? rr - z0 : 0];
+        a[q] += v * (ok && c <= rr ? 1.0 : 0.0);
     }
     if (r < te) r += ((te - r + S - 1) >> lgS) << lgS;   // first row of the sequence at or past te
     const int step = S * nI;
@@ -443,8 +464,11 @@ __device__ __forceinline__ double col_part(const T* __restrict__ P, int nI, int 
         off += SWEEP_ILP * step;
     }
 #pragma unroll
-    for (int q = 0; q < SWEEP_ILP - 1; ++q)
-        if (r + q * S < re) a[q] += (double)P[off + q * step + c] * z[r + q * S - z0];
+    for (int q = 0; q < SWEEP_ILP - 1; ++q) {
+        const bool ok = r + q * S < re;
+        const double v = (double)P[ok ? off + q * step + c : 0] * z[ok ? r + q * S - z0 : 0];
+        a[q] += v * (ok ? 1.0 : 0.0);
+    }
     return sum_ilp(a);
 }
 
@@ -489,14 +513,14 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __rest
 // few nodes of which one is large: there the nodes are done one by one by
 // the whole workgroup, W columns times 1024/W row streams, partial sums
 // reduced in LDS.
-constexpr int SUB_COOP_MIN = 6000;    // nI * (nI + nB) of a large node
+constexpr int SUB_COOP_MIN = 6000;    // nI * (nI + nB) of a large node (default)
 template <typename T>
 __global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __restrict__ sub_tn,
                                                            const int32_t* __restrict__ sub_hoff, int hc,
                                                            const T* __restrict__ panel,
                                                            const int64_t* __restrict__ bidx,
                                                            const double* __restrict__ y,
-                                                           double* x) {
+                                                           double* x, int coop_min) {
     __shared__ double zbuf[SUB_NW][SUB_MAXF];
     __shared__ double redb[SUB_BLOCK];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
@@ -506,7 +530,7 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __rest
         const int k0 = hoff[h], k1 = hoff[h + 1];
         bool coop = false;
         if (2 * (k1 - k0) < SUB_NW)
-            for (int k = k0; k < k1; ++k) coop |= sub_tn[k].nI * (sub_tn[k].nI + sub_tn[k].nB) >= SUB_COOP_MIN;
+            for (int k = k0; k < k1; ++k) coop |= sub_tn[k].nI * (sub_tn[k].nI + sub_tn[k].nB) >= coop_min;
         if (!coop) {
             for (int k = k0 + wave; k < k1; k += SUB_NW) {
                 const TriNode nd = sub_tn[__builtin_amdgcn_readfirstlane(k)];   // wave-uniform
@@ -922,7 +946,11 @@ template <typename T>
 void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
                         const int64_t* bidx, const double* y, double* x) {
     if (P.n_sub == 0) return;
-    k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel, bidx, y, x);
+    static const int coop_min = [] {
+        const char* e = std::getenv("BIDO_COOP_MIN");
+        return e && *e ? std::atoi(e) : SUB_COOP_MIN;
+    }();
+    k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel, bidx, y, x, coop_min);
 }
 template <typename T>
 void launch_tri_fwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,

@@ -256,6 +256,9 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     std::reverse(roots.begin(), roots.end());
     const bool forest = roots.size() > 1;
     std::vector<int> hc_of(nn, -1);
+    // cap of every tree's cut (environment BIDO_SUB_H when not given)
+    const char* esub = std::getenv("BIDO_SUB_H");
+    const int sub_cap = o.sub_h >= 0 ? o.sub_h : (esub && *esub ? std::atoi(esub) : -1);
     {
         std::vector<std::vector<int>> members(nn);
         for (int id = 0; id < nn; ++id) members[root_of[id]].push_back(id);
@@ -282,6 +285,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
                     if (mw[h] <= PLAN_SUB_MAXW && mf[h] <= PLAN_SUB_MAXF && nroots[h] >= want) cut = h;
                 if (cut >= 0) break;
             }
+            if (sub_cap >= 0) cut = std::min(cut, sub_cap);
             for (int id : members[r]) hc_of[id] = cut;
         }
     }
@@ -378,6 +382,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
         p.top_h = -1;
     }
     p.used.top_h = p.top_h;
+    p.used.sub_h = sub_cap;
     std::vector<char> is_top(nn, 0);
     for (int id = 0; id < nn; ++id) is_top[id] = t.nodes[id].height >= cut_of[id];
 

@@ -17,6 +17,7 @@ struct PlanOptions {
     int fwd_cols = 0;   // columns per forward level item
     int bwd_rows = 0;   // rows per backward level item (0: 8192 / tile width, at most 512)
     int top_h = -1;     // first height of the top (raised to fit the top-size bound)
+    int sub_h = -1;     // highest subtree cut of any tree (< 0: the size rule alone)
 };
 
 struct FactorPlan {

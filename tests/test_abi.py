@@ -299,3 +299,32 @@ def test_hierarchical_top_with_a_decoupled_block():
     assert np.isfinite(emu).all()
     assert np.abs(emu - ref).max() <= 1e-6 * np.abs(ref).max()
     assert top["stored_entries"] < top["n_top"] ** 2 // 4
+
+
+@pytest.mark.parametrize("sub_h", ["0", "1", "2"])
+def test_capped_subtree_cut_emulates_each_slice(sub_h, monkeypatch):
+    """Capping every tree's subtree cut (more of the sweep in level phases,
+    tops chosen again where a tree had none) leaves the forest an exact
+    solve of every slice (eps_h = 0: tops exact up to rounding)."""
+    import paper_1711_08708_amd as B
+    cfgs = [w.thorax2d(n_target=3000, seed=31), w.thorax2d(n_target=6000, seed=32, sigma_scale=0.8),
+            w.square2d(n=24, seed=3)]
+    parts = [B.HostSetup(c, eps_h=0.0) for c in cfgs]
+    sizes = [(len(p.index(B.IDX_UPOS)), len(p.index(B.IDX_VPOS))) for p in parts]
+    ntot = sum(a + b for a, b in sizes)
+    rng = np.random.default_rng(11)
+    for which in (B.FACTOR_P1, B.FACTOR_PK):
+        b = rng.normal(size=ntot)
+        refs, off = [], 0
+        for p, (N, NH) in zip(parts, sizes):
+            lo, n = (off, N) if which == B.FACTOR_P1 else (off + N, NH)
+            refs.append((lo, n, p.factor_apply(which, b[lo:lo + n])))
+            off += N + NH
+        monkeypatch.setenv("BIDO_SUB_H", sub_h)
+        merged = B.HostSetup.merged(parts)
+        plan = merged.factor_plan(which)
+        emu = merged.factor_emulate(which, b)
+        monkeypatch.delenv("BIDO_SUB_H")
+        assert plan["hc"] <= int(sub_h)
+        for lo, n, ref in refs:
+            assert np.abs(emu[lo:lo + n] - ref).max() <= 1e-11 * np.abs(ref).max()
