@@ -192,6 +192,7 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
     HIP_OK(upload(&fd.fcomb, p.fwd_comb.data(), p.fwd_comb.size()));   // empty: no combine launch
     HIP_OK(upload(&fd.bcomb, p.bwd_comb.data(), p.bwd_comb.size()));
     HIP_OK(hipMalloc((void**)&fd.upd, std::max<int64_t>(p.upd_size, 1) * sizeof(double)));
+    HIP_OK(hipMemset(fd.upd, 0, sizeof(double)));                    // the 0.0 entry
     HIP_OK(hipMalloc((void**)&fd.ytmp, std::max<int64_t>(p.n, 1) * sizeof(double)));
     fd.top_h = p.top_h;
     fd.top_seconds = p.top_seconds;
@@ -254,6 +255,16 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
     fd.sub_bwd_bytes32 = p.sub_bwd_bytes32;
     fd.meta_bytes = p.meta_bytes;
     return BIDO_OK;
+}
+
+// Work vectors of a factor's sweeps start as NaN (all-ones bits), so that a
+// read before a write shows up in every result; entry 0 of the update
+// workspace is the 0.0 the sweeps read for a missing child update.
+hipError_t poison_workspace(const FactorDev& f) {
+    hipError_t e = hipMemset(f.ytmp, 0xFF, std::max<int64_t>(f.n, 1) * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(f.upd, 0xFF, std::max<int64_t>(f.upd_size, 1) * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(f.upd, 0, sizeof(double));
+    return e;
 }
 
 // Device state of the learned correction (see gnn.h).
@@ -1224,8 +1235,7 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     HIP_OK(hipMemset(c->tB, 0xFF, std::max<int64_t>(c->NH, 1) * sizeof(double)));
     HIP_OK(hipMemset(c->sc, 0xFF, pp_offset(PP_COUNT) * sizeof(double)));
     for (FactorDev* f : {&c->p1, &c->pk}) {
-        HIP_OK(hipMemset(f->ytmp, 0xFF, std::max<int64_t>(f->n, 1) * sizeof(double)));
-        HIP_OK(hipMemset(f->upd, 0xFF, std::max<int64_t>(f->upd_size, 1) * sizeof(double)));
+        HIP_OK(poison_workspace(*f));
     }
     HIP_OK(hipHostMalloc((void**)&c->sc_host, pp_offset(PP_COUNT) * sizeof(double), hipHostMallocDefault));
     HIP_OK(hipMalloc((void**)&c->rd.partials, 2 * c->rd.max_blocks * sizeof(double)));
@@ -1432,8 +1442,7 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
     HIP_OK(hipMalloc((void**)&F->done, S));
     HIP_OK(hipHostMalloc((void**)&F->done_host, S, hipHostMallocDefault));
     for (FactorDev* f : {&F->p1, &F->pk}) {
-        HIP_OK(hipMemset(f->ytmp, 0xFF, std::max<int64_t>(f->n, 1) * sizeof(double)));
-        HIP_OK(hipMemset(f->upd, 0xFF, std::max<int64_t>(f->upd_size, 1) * sizeof(double)));
+        HIP_OK(poison_workspace(*f));
     }
     HIP_OK(hipStreamCreateWithFlags(&F->stream, hipStreamNonBlocking));
     HIP_OK(hipDeviceSynchronize());
@@ -1911,8 +1920,7 @@ static bido_status train_stencil(bido_ctx* c, int epochs, int batch, float lr, u
         bido_status e = build_factor_dev(f, true, c->pk_learned, c->params.n_threads);
         if (e) return e;
         for (FactorDev* fd : {&c->pk_learned}) {
-            HIP_OK(hipMemset(fd->ytmp, 0xFF, std::max<int64_t>(fd->n, 1) * sizeof(double)));
-            HIP_OK(hipMemset(fd->upd, 0xFF, std::max<int64_t>(fd->upd_size, 1) * sizeof(double)));
+            HIP_OK(poison_workspace(*fd));
         }
     }
     g.stencil_ready = spd;
@@ -2063,8 +2071,7 @@ bido_status bido_autotune(bido_ctx* c, int reps, bido_tune_report* rep) {
                 attempt(o);
             }
         f.trim_top_cache(cur.top_h);
-        HIP_OK(hipMemset(cur.ytmp, 0xFF, std::max<int64_t>(cur.n, 1) * sizeof(double)));
-        HIP_OK(hipMemset(cur.upd, 0xFF, std::max<int64_t>(cur.upd_size, 1) * sizeof(double)));
+        HIP_OK(poison_workspace(cur));
         r.us_after[which] = best * 1e3;
         r.top_h[which] = cur.opts.top_h;
         r.fwd_cols[which] = cur.opts.fwd_cols;

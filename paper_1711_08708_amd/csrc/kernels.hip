@@ -329,29 +329,67 @@ __device__ __forceinline__ int pow2_ceil64(int n) {
     return g;
 }
 
-// w_t[i] = b[off+i] - children's updates at own position i (ground -> 0)
-__device__ __forceinline__ double gather_w(const TriNode& nd, int i, const Ea* __restrict__ ea,
-                                           const double* __restrict__ b, const double* upd,
-                                           int64_t u0, int64_t u1) {
-    double v = b[nd.off + i];
-    const Ea m = ea[nd.ea + i];
-    if (m.a >= 0) v -= upd[u0 + m.a];
-    if (m.b >= 0) v -= upd[u1 + m.b];
-    return i == nd.gi ? 0.0 : v;
+// Staging steps issue every load before using any: entry 0 of the update
+// workspace is always 0.0 (no node's update vector starts there) and stands in
+// for a missing child update, the boundary index array ends with a spare
+// entry, lanes past the end of a range reread its last entry, and their
+// results go to a spare LDS slot.  A staging step then costs two memory
+// latencies (indices, then values) instead of two per element.
+
+// w[i - ibase] = b[off+i] - children's updates at own position i (ground ->
+// 0), for i = i0 + t + stride k < i1 (k < K)
+template <int K>
+__device__ __forceinline__ void stage_w(const TriNode& nd, int t, int stride, int i0, int i1, int ibase,
+                                        const Ea* __restrict__ ea, const double* __restrict__ b,
+                                        const double* upd, int64_t u0, int64_t u1, double* w, int spare) {
+    if (i1 <= i0) return;
+    Ea m[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) m[k] = ea[nd.ea + min(i0 + t + stride * k, i1 - 1)];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = i0 + t + stride * k, ic = min(i, i1 - 1);
+        const double v = b[nd.off + ic] - upd[m[k].a >= 0 ? u0 + m[k].a : 0] - upd[m[k].b >= 0 ? u1 + m[k].b : 0];
+        w[i < i1 ? i - ibase : spare] = v * (ic == nd.gi ? 0.0 : 1.0);
+    }
 }
 
-// store row r of P_t w_t: own rows to y, boundary rows (plus the children's
-// updates there) to the update vector of the node
-__device__ __forceinline__ void store_row(const TriNode& nd, int r, double s, const Ea* __restrict__ ea,
-                                          double* __restrict__ y, double* upd, int64_t u0, int64_t u1) {
-    if (r < nd.nI) {
-        y[nd.off + r] = s;
-    } else {
-        const Ea m = ea[nd.ea + r];
-        if (m.a >= 0) s += upd[u0 + m.a];
-        if (m.b >= 0) s += upd[u1 + m.b];
-        upd[nd.upd + (r - nd.nI)] = s;
+// z[r - zbase] = y_t[r] (own rows) or -x[B(t)[r - nI]] (boundary rows), for
+// r = r0 + t + stride k < r1 (k < K)
+template <int K>
+__device__ __forceinline__ void stage_z(const TriNode& nd, int t, int stride, int r0, int r1, int zbase,
+                                        const int64_t* __restrict__ bidx, const double* __restrict__ y,
+                                        const double* x, double* z, int spare) {
+    if (r1 <= r0) return;
+    const int nI = nd.nI;
+    int64_t xi[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int rc = min(r0 + t + stride * k, r1 - 1);
+        xi[k] = bidx[nd.bidx + (rc >= nI ? rc - nI : 0)];
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int r = r0 + t + stride * k, rc = min(r, r1 - 1);
+        const double v = *(rc < nI ? y + nd.off + rc : x + xi[k]);
+        z[r < r1 ? r - zbase : spare] = rc < nI ? v : -v;
+    }
+}
+
+// the children's updates at row r of P_t w_t (0.0 for own rows), loaded
+// ahead of the row's products
+__device__ __forceinline__ double row_add(const TriNode& nd, int r, const Ea* __restrict__ ea, const double* upd,
+                                          int64_t u0, int64_t u1) {
+    const Ea m = ea[nd.ea + r];
+    const bool bnd = r >= nd.nI;
+    return upd[bnd && m.a >= 0 ? u0 + m.a : 0] + upd[bnd && m.b >= 0 ? u1 + m.b : 0];
+}
+
+// store row r of P_t w_t (its additions included): own rows to y, boundary
+// rows to the update vector of the node
+__device__ __forceinline__ void store_row(const TriNode& nd, int r, double s, double* __restrict__ y, double* upd) {
+    if (r < nd.nI) y[nd.off + r] = s;
+    else upd[nd.upd + (r - nd.nI)] = s;
 }
 
 // Independent loads in flight per lane in the sweeps' inner loops.
@@ -482,7 +520,7 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __rest
                                                            const double* __restrict__ b,
                                                            double* __restrict__ y,
                                                            double* upd) {
-    __shared__ double wbuf[SUB_NW][SUB_MAXW];
+    __shared__ double wbuf[SUB_NW][SUB_MAXW + 1];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int32_t* hoff = sub_hoff + (size_t)blockIdx.x * (hc + 2);
     double* w = wbuf[wave];
@@ -492,15 +530,16 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __rest
             const int64_t u0 = nd.u0, u1 = nd.u1;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_wave_barrier();
-            for (int i = lane; i < nd.nI; i += WAVE) w[i] = gather_w(nd, i, ea, b, upd, u0, u1);
+            stage_w<SUB_MAXW / WAVE>(nd, lane, WAVE, 0, nd.nI, 0, ea, b, upd, u0, u1, w, SUB_MAXW);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             const T* Pc = panel_cm + nd.panel;
             const int nF = nd.nI + nd.nB;
             for (int r = lane; r < nF; r += WAVE) {
+                const double add = row_add(nd, r, ea, upd, u0, u1);
                 const double s = row_part<T>(Pc, nd.nI, nd.nB, r, 0, nd.nI, w);
-                store_row(nd, r, s, ea, y, upd, u0, u1);
+                store_row(nd, r, s + add, y, upd);
             }
         }
         __syncthreads();
@@ -521,7 +560,7 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __rest
                                                            const int64_t* __restrict__ bidx,
                                                            const double* __restrict__ y,
                                                            double* x, int coop_min) {
-    __shared__ double zbuf[SUB_NW][SUB_MAXF];
+    __shared__ double zbuf[SUB_NW][SUB_MAXF + 1];
     __shared__ double redb[SUB_BLOCK];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int32_t* hoff = sub_hoff + (size_t)blockIdx.x * (hc + 2);
@@ -537,7 +576,7 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __rest
                 const int nI = nd.nI, nF = nd.nI + nd.nB;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 __builtin_amdgcn_wave_barrier();
-                for (int r = lane; r < nF; r += WAVE) z[r] = r < nI ? y[nd.off + r] : -x[bidx[nd.bidx + (r - nI)]];
+                stage_z<SUB_MAXF / WAVE>(nd, lane, WAVE, 0, nF, 0, bidx, y, x, z, SUB_MAXF);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -559,8 +598,8 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __rest
             for (int k = k0; k < k1; ++k) {
                 const TriNode nd = sub_tn[k];
                 const int nI = nd.nI, nF = nd.nI + nd.nB;
-                for (int r = threadIdx.x; r < nF; r += SUB_BLOCK)
-                    zsh[r] = r < nI ? y[nd.off + r] : -x[bidx[nd.bidx + (r - nI)]];
+                stage_z<(SUB_MAXF + SUB_BLOCK - 1) / SUB_BLOCK>(nd, threadIdx.x, SUB_BLOCK, 0, nF, 0, bidx, y, x, zsh,
+                                                                 SUB_MAXF);
                 __syncthreads();
                 const T* P = panel + nd.panel;
                 for (int cb = 0; cb < nI; cb += WAVE) {
@@ -594,20 +633,22 @@ __global__ __launch_bounds__(BLOCK) void k_tri_fwd_lvl(const TriNode* __restrict
                                                        const Ea* __restrict__ ea,
                                                        const double* __restrict__ b,
                                                        double* __restrict__ y,
-                                                       double* upd, double* __restrict__ scratch) {
-    extern __shared__ double w[];
+                                                       double* upd, double* __restrict__ scratch, int spare) {
+    extern __shared__ double w[];   // the item's columns, then the spare slot
     __shared__ double red[BLOCK / WAVE][FWD_ROWS];
     const TriItem it = items[blockIdx.x];
     const TriNode nd = nodes[it.node];
     const int64_t u0 = nd.u0, u1 = nd.u1;
     const int ncol = it.ce - it.cs;
-    for (int i = threadIdx.x; i < ncol; i += BLOCK) w[i] = gather_w(nd, it.cs + i, ea, b, upd, u0, u1);
-    __syncthreads();
+    for (int i0 = it.cs; i0 < it.ce; i0 += 2 * BLOCK)
+        stage_w<2>(nd, threadIdx.x, BLOCK, i0, it.ce, it.cs, ea, b, upd, u0, u1, w, spare);
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int r = it.r0 + lane;
+    const double add = wave == 0 && it.nparts == 1 && lane < it.nrows ? row_add(nd, r, ea, upd, u0, u1) : 0.0;
+    __syncthreads();
     const int nw = BLOCK / WAVE;
     const int per = (ncol + nw - 1) / nw;
     const int c0 = it.cs + wave * per, c1 = min(it.ce, c0 + per);
-    const int r = it.r0 + lane;
     double s = 0.0;
     if (lane < it.nrows && c0 < c1)
         s = row_part<T>(panel_cm + nd.panel, nd.nI, nd.nB, r, c0, c1, w + (c0 - it.cs));
@@ -617,7 +658,7 @@ __global__ __launch_bounds__(BLOCK) void k_tri_fwd_lvl(const TriNode* __restrict
     double tot = 0.0;
     for (int k = 0; k < nw; ++k) tot += red[k][lane];
     if (it.nparts == 1) {
-        if (lane < it.nrows) store_row(nd, r, tot, ea, y, upd, u0, u1);
+        if (lane < it.nrows) store_row(nd, r, tot + add, y, upd);
     } else {
         scratch[it.part + lane] = tot;
     }
@@ -635,10 +676,10 @@ __global__ __launch_bounds__(BLOCK) void k_tri_fwd_comb(const TriNode* __restric
     const TriItem it = comb[q];
     if (lane >= it.nrows) return;
     const TriNode nd = nodes[it.node];
-    const int64_t u0 = nd.u0, u1 = nd.u1;
+    const double add = row_add(nd, it.r0 + lane, ea, upd, nd.u0, nd.u1);
     double t = 0.0;
     for (int k = 0; k < it.nparts; ++k) t += scratch[it.part0 + (int64_t)k * FWD_ROWS + lane];
-    store_row(nd, it.r0 + lane, t, ea, y, upd, u0, u1);
+    store_row(nd, it.r0 + lane, t + add, y, upd);
 }
 
 // Level phase, backward: item = (column tile, row range) of one node; z for
@@ -650,14 +691,14 @@ __global__ __launch_bounds__(BLOCK) void k_tri_bwd_lvl(const TriNode* __restrict
                                                        const T* __restrict__ panel,
                                                        const int64_t* __restrict__ bidx,
                                                        const double* __restrict__ y,
-                                                       double* x, double* __restrict__ scratch) {
-    extern __shared__ double z[];
+                                                       double* x, double* __restrict__ scratch, int spare) {
+    extern __shared__ double z[];   // the item's rows, then the spare slot
     __shared__ double red[BLOCK];
     const BwdItem it = items[blockIdx.x];
     const TriNode nd = nodes[it.node];
     const int nI = nd.nI;
-    for (int r = it.rs + threadIdx.x; r < it.re; r += BLOCK)
-        z[r - it.rs] = r < nI ? y[nd.off + r] : -x[bidx[nd.bidx + (r - nI)]];
+    for (int r0 = it.rs; r0 < it.re; r0 += 2 * BLOCK)
+        stage_z<2>(nd, threadIdx.x, BLOCK, r0, it.re, it.rs, bidx, y, x, z, spare);
     __syncthreads();
     const int W = it.W;
     const int col = threadIdx.x % W, st = threadIdx.x / W;
@@ -956,7 +997,8 @@ template <typename T>
 void launch_tri_fwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
                         const T* panel_cm, const Ea* ea, const double* b, double* y, double* upd) {
     if (L.n_fwd == 0) return;
-    k_tri_fwd_lvl<T><<<L.n_fwd, BLOCK, L.lds_f, s>>>(nodes, L.fwd, panel_cm, ea, b, y, upd, P.scratch);
+    k_tri_fwd_lvl<T><<<L.n_fwd, BLOCK, L.lds_f + sizeof(double), s>>>(nodes, L.fwd, panel_cm, ea, b, y, upd,
+                                                                      P.scratch, (int)(L.lds_f / sizeof(double)));
     if (L.n_fcomb > 0)
         k_tri_fwd_comb<<<(L.n_fcomb + BLOCK / WAVE - 1) / (BLOCK / WAVE), BLOCK, 0, s>>>(nodes, L.fcomb, L.n_fcomb,
                                                                                        ea, y, upd, P.scratch);
@@ -965,7 +1007,8 @@ template <typename T>
 void launch_tri_bwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
                         const T* panel, const int64_t* bidx, const double* y, double* x) {
     if (L.n_bwd == 0) return;
-    k_tri_bwd_lvl<T><<<L.n_bwd, BLOCK, L.lds_b, s>>>(nodes, L.bwd, panel, bidx, y, x, P.scratch);
+    k_tri_bwd_lvl<T><<<L.n_bwd, BLOCK, L.lds_b + sizeof(double), s>>>(nodes, L.bwd, panel, bidx, y, x, P.scratch,
+                                                                      (int)(L.lds_b / sizeof(double)));
     if (L.n_bcomb > 0) k_tri_bwd_comb<<<L.n_bcomb, WAVE, 0, s>>>(nodes, L.bcomb, x, P.scratch);
 }
 
