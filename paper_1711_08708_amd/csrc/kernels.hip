@@ -10,8 +10,6 @@
 //   mean_*              normalisation (M U, 1) = 0 of Prop. 1
 #include <hip/hip_runtime.h>
 
-#include <cstdlib>
-
 #include "kernels.h"
 #include "launch.h"
 
@@ -510,8 +508,107 @@ __device__ __forceinline__ double col_part(const T* __restrict__ P, int nI, int 
     return sum_ilp(a);
 }
 
-// Subtree phase, forward: workgroup s walks its subtree from the leaves up;
-// each node is handled by one wave, one panel row per lane.
+// Subtree phases: workgroup s walks its subtree one height at a time, each
+// wave taking whole nodes.  In the forward phase a height with 8 or fewer
+// nodes (the upper ones of a subtree) gives every node a group of
+// g = 16 / (nodes) waves (rounded down to a power of two) that split its
+// rows.  (The backward phase stays one wave per node: its upper nodes are
+// thin, a few columns over many rows that the row streams of one wave
+// already cover, and a group's reductions cost more than they save.)
+
+// waves per node at a height with n < SUB_NW nodes
+__device__ __forceinline__ int sub_group(int n) {
+    int g = SUB_NW;
+    while (g * n > SUB_NW) g >>= 1;
+    return g;
+}
+
+// The node records and index maps a wave needs at a height do not depend on
+// the heights before it, so they are loaded before the barrier that ends the
+// previous height; after it only the values that do (x of the ancestors,
+// the children's updates) remain to be fetched.
+constexpr int SUB_KW = SUB_MAXW / WAVE;   // columns of w per lane (one wave per node)
+constexpr int SUB_KF = SUB_MAXF / WAVE;   // rows of z per lane
+
+// this wave's share of height h of a subtree: its first node k (-1: none),
+// the group size g and the thread's index t within the group
+struct SubSlot {
+    int k, g, t;
+};
+__device__ __forceinline__ SubSlot fwd_slot(const int32_t* hoff, int h, int wave, int lane) {
+    const int k0 = hoff[h], n = hoff[h + 1] - k0;
+    SubSlot sl;
+    if (n > SUB_NW / 2) {
+        sl.g = 1;
+        sl.t = lane;
+        sl.k = wave < n ? k0 + wave : -1;
+    } else {
+        sl.g = n > 0 ? sub_group(n) : 1;
+        const int grp = wave / sl.g;
+        sl.t = (wave % sl.g) * WAVE + lane;
+        sl.k = grp < n ? k0 + grp : -1;
+    }
+    return sl;
+}
+
+struct FwdPre {
+    TriNode nd;
+    Ea mw[SUB_KW];   // maps of the thread's columns of w (stride g * WAVE)
+    Ea mr;           // map of the thread's first row
+};
+__device__ __forceinline__ void fwd_load(const TriNode* __restrict__ sub_tn, const Ea* __restrict__ ea, int k,
+                                         int t, int stride, FwdPre& p) {
+    p.nd = sub_tn[__builtin_amdgcn_readfirstlane(k)];
+    const int nI = p.nd.nI, nF = nI + p.nd.nB;
+#pragma unroll
+    for (int q = 0; q < SUB_KW; ++q) p.mw[q] = ea[p.nd.ea + max(0, min(t + stride * q, nI - 1))];
+    p.mr = ea[p.nd.ea + max(0, min(t, nF - 1))];
+}
+// w from prefetched maps: w[i] = b[off+i] - children's updates (ground -> 0)
+__device__ __forceinline__ void stage_w_pre(const FwdPre& p, int t, int stride, int kmax,
+                                            const double* __restrict__ b, const double* upd, double* w) {
+    const TriNode& nd = p.nd;
+    if (nd.nI <= 0) return;
+#pragma unroll
+    for (int q = 0; q < SUB_KW; ++q) {
+        if (q >= kmax) break;
+        const int i = t + stride * q, ic = min(i, nd.nI - 1);
+        const double v = b[nd.off + ic] - upd[p.mw[q].a >= 0 ? nd.u0 + p.mw[q].a : 0] -
+                         upd[p.mw[q].b >= 0 ? nd.u1 + p.mw[q].b : 0];
+        w[i < nd.nI ? i : SUB_MAXW] = v * (ic == nd.gi ? 0.0 : 1.0);
+    }
+}
+
+struct BwdPre {
+    TriNode nd;
+    int64_t xi[SUB_KF];   // boundary indices of the lane's rows
+};
+__device__ __forceinline__ void bwd_load(const TriNode* __restrict__ sub_tn, const int64_t* __restrict__ bidx, int k,
+                                         int lane, BwdPre& p) {
+    p.nd = sub_tn[__builtin_amdgcn_readfirstlane(k)];
+    const int nI = p.nd.nI, nF = nI + p.nd.nB;
+#pragma unroll
+    for (int q = 0; q < SUB_KF; ++q) {
+        const int rc = max(0, min(lane + WAVE * q, nF - 1));
+        p.xi[q] = bidx[p.nd.bidx + (rc >= nI ? rc - nI : 0)];
+    }
+}
+// z = [y_t ; -x_B] from prefetched indices
+__device__ __forceinline__ void stage_z_pre(const BwdPre& p, int lane, const double* __restrict__ y,
+                                            const double* x, double* z) {
+    const TriNode& nd = p.nd;
+    const int nI = nd.nI, nF = nI + nd.nB;
+    if (nF <= 0) return;
+#pragma unroll
+    for (int q = 0; q < SUB_KF; ++q) {
+        const int r = lane + WAVE * q, rc = min(r, nF - 1);
+        const double v = *(rc < nI ? y + nd.off + rc : x + p.xi[q]);
+        z[r < nF ? r : SUB_MAXF] = rc < nI ? v : -v;
+    }
+}
+
+// Forward: [y_t ; c_t] = P_t w_t, one panel row per thread of the node's
+// waves (rows need no reduction).
 template <typename T>
 __global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __restrict__ sub_tn,
                                                            const int32_t* __restrict__ sub_hoff, int hc,
@@ -523,101 +620,108 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __rest
     __shared__ double wbuf[SUB_NW][SUB_MAXW + 1];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int32_t* hoff = sub_hoff + (size_t)blockIdx.x * (hc + 2);
-    double* w = wbuf[wave];
+    FwdPre pre;
+    SubSlot sl = fwd_slot(hoff, 0, wave, lane);
+    if (sl.k >= 0) fwd_load(sub_tn, ea, sl.k, sl.t, sl.g * WAVE, pre);
     for (int h = 0; h <= hc; ++h) {
-        for (int k = hoff[h] + wave; k < hoff[h + 1]; k += SUB_NW) {
-            const TriNode nd = sub_tn[__builtin_amdgcn_readfirstlane(k)];   // wave-uniform
-            const int64_t u0 = nd.u0, u1 = nd.u1;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            stage_w<SUB_MAXW / WAVE>(nd, lane, WAVE, 0, nd.nI, 0, ea, b, upd, u0, u1, w, SUB_MAXW);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        const int k0 = hoff[h], k1 = hoff[h + 1], n = k1 - k0;
+        const int stride = sl.g * WAVE;
+        const int kmax = (SUB_MAXW + stride - 1) / stride;
+        if (n > SUB_NW / 2) {
+            double* w = wbuf[wave];
+            for (int k = k0 + wave; k < k1; k += SUB_NW) {
+                if (k != sl.k) fwd_load(sub_tn, ea, k, lane, WAVE, pre);
+                const TriNode& nd = pre.nd;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                stage_w_pre(pre, lane, WAVE, SUB_KW, b, upd, w);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const T* Pc = panel_cm + nd.panel;
+                const int nF = nd.nI + nd.nB;
+                for (int r = lane; r < nF; r += WAVE) {
+                    const Ea m = r == lane ? pre.mr : ea[nd.ea + r];
+                    const bool bnd = r >= nd.nI;
+                    const double add = upd[bnd && m.a >= 0 ? nd.u0 + m.a : 0] + upd[bnd && m.b >= 0 ? nd.u1 + m.b : 0];
+                    const double s = row_part<T>(Pc, nd.nI, nd.nB, r, 0, nd.nI, w);
+                    store_row(nd, r, s + add, y, upd);
+                }
+            }
+        } else if (sl.k >= 0) {
+            const int grp = wave / sl.g;
+            double* w = wbuf[grp * sl.g];
+            stage_w_pre(pre, sl.t, stride, kmax, b, upd, w);
+        }
+        if (n > 0 && n <= SUB_NW / 2) __syncthreads();   // the group's w is staged
+        if (n > 0 && n <= SUB_NW / 2 && sl.k >= 0) {
+            const TriNode& nd = pre.nd;
+            const double* w = wbuf[(wave / sl.g) * sl.g];
             const T* Pc = panel_cm + nd.panel;
             const int nF = nd.nI + nd.nB;
-            for (int r = lane; r < nF; r += WAVE) {
-                const double add = row_add(nd, r, ea, upd, u0, u1);
+            for (int r = sl.t; r < nF; r += stride) {
+                const Ea m = r == sl.t ? pre.mr : ea[nd.ea + r];
+                const bool bnd = r >= nd.nI;
+                const double add = upd[bnd && m.a >= 0 ? nd.u0 + m.a : 0] + upd[bnd && m.b >= 0 ? nd.u1 + m.b : 0];
                 const double s = row_part<T>(Pc, nd.nI, nd.nB, r, 0, nd.nI, w);
                 store_row(nd, r, s + add, y, upd);
             }
+        }
+        // records and maps of the next height, ahead of the barrier
+        if (h < hc) {
+            sl = fwd_slot(hoff, h + 1, wave, lane);
+            if (sl.k >= 0) fwd_load(sub_tn, ea, sl.k, sl.t, sl.g * WAVE, pre);
         }
         __syncthreads();
     }
 }
 
-// Subtree phase, backward: heights from the subtree root down, z = [y_t ;
-// -x_B] staged in LDS.  One node per wave (lanes own columns, plus row
-// streams when the node has fewer than 64 columns), except at a height with
-// few nodes of which one is large: there the nodes are done one by one by
-// the whole workgroup, W columns times 1024/W row streams, partial sums
-// reduced in LDS.
-constexpr int SUB_COOP_MIN = 6000;    // nI * (nI + nB) of a large node (default)
+// Backward: x_t = P_t^T [y_t ; -x_B], z staged in LDS.  Lanes own columns
+// (blocks of up to 64); a block of W < 64 columns splits the rows into
+// 64 / W streams, summed across the wave.
 template <typename T>
 __global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __restrict__ sub_tn,
                                                            const int32_t* __restrict__ sub_hoff, int hc,
                                                            const T* __restrict__ panel,
                                                            const int64_t* __restrict__ bidx,
                                                            const double* __restrict__ y,
-                                                           double* x, int coop_min) {
+                                                           double* x) {
     __shared__ double zbuf[SUB_NW][SUB_MAXF + 1];
-    __shared__ double redb[SUB_BLOCK];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int32_t* hoff = sub_hoff + (size_t)blockIdx.x * (hc + 2);
     double* z = zbuf[wave];
+    BwdPre pre;
+    int kp = hoff[hc] + wave;
+    if (kp < hoff[hc + 1]) bwd_load(sub_tn, bidx, kp, lane, pre);
     for (int h = hc; h >= 0; --h) {
         const int k0 = hoff[h], k1 = hoff[h + 1];
-        bool coop = false;
-        if (2 * (k1 - k0) < SUB_NW)
-            for (int k = k0; k < k1; ++k) coop |= sub_tn[k].nI * (sub_tn[k].nI + sub_tn[k].nB) >= coop_min;
-        if (!coop) {
-            for (int k = k0 + wave; k < k1; k += SUB_NW) {
-                const TriNode nd = sub_tn[__builtin_amdgcn_readfirstlane(k)];   // wave-uniform
-                const int nI = nd.nI, nF = nd.nI + nd.nB;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-                stage_z<SUB_MAXF / WAVE>(nd, lane, WAVE, 0, nF, 0, bidx, y, x, z, SUB_MAXF);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                const T* P = panel + nd.panel;
-                for (int cb = 0; cb < nI; cb += WAVE) {
-                    const int ncols = min(WAVE, nI - cb);
-                    const int W = pow2_ceil64(ncols);
-                    const int S = WAVE / W;
-                    const int col = lane % W, st = lane / W;
-                    const int c = cb + col;
-                    double acc = 0.0;
-                    if (col < ncols) acc = col_part<T>(P, nI, c, cb + st, nF, S, z, 0);
-                    for (int m = W; m < WAVE; m <<= 1) acc += __shfl_xor(acc, m, WAVE);
-                    if (st == 0 && col < ncols) x[nd.off + c] = acc;
-                }
+        for (int k = k0 + wave; k < k1; k += SUB_NW) {
+            if (k != kp) bwd_load(sub_tn, bidx, k, lane, pre);
+            const TriNode& nd = pre.nd;
+            const int nI = nd.nI, nF = nd.nI + nd.nB;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            stage_z_pre(pre, lane, y, x, z);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const T* P = panel + nd.panel;
+            for (int cb = 0; cb < nI; cb += WAVE) {
+                const int ncols = min(WAVE, nI - cb);
+                const int W = pow2_ceil64(ncols);
+                const int S = WAVE / W;
+                const int col = lane % W, st = lane / W;
+                const int c = cb + col;
+                double acc = 0.0;
+                if (col < ncols) acc = col_part<T>(P, nI, c, cb + st, nF, S, z, 0);
+                for (int m = W; m < WAVE; m <<= 1) acc += __shfl_xor(acc, m, WAVE);
+                if (st == 0 && col < ncols) x[nd.off + c] = acc;
             }
-        } else {
-            double* zsh = zbuf[0];
-            for (int k = k0; k < k1; ++k) {
-                const TriNode nd = sub_tn[k];
-                const int nI = nd.nI, nF = nd.nI + nd.nB;
-                stage_z<(SUB_MAXF + SUB_BLOCK - 1) / SUB_BLOCK>(nd, threadIdx.x, SUB_BLOCK, 0, nF, 0, bidx, y, x, zsh,
-                                                                 SUB_MAXF);
-                __syncthreads();
-                const T* P = panel + nd.panel;
-                for (int cb = 0; cb < nI; cb += WAVE) {
-                    const int ncols = min(WAVE, nI - cb);
-                    const int W = pow2_ceil64(ncols);
-                    const int S = SUB_BLOCK / W;
-                    const int col = threadIdx.x % W, st = threadIdx.x / W;
-                    const int c = cb + col;
-                    redb[threadIdx.x] = col < ncols ? col_part<T>(P, nI, c, cb + st, nF, S, zsh, 0) : 0.0;
-                    __syncthreads();
-                    if (threadIdx.x < ncols) {
-                        double t = 0.0;
-                        for (int q = 0; q < S; ++q) t += redb[q * W + threadIdx.x];
-                        x[nd.off + c] = t;
-                    }
-                    __syncthreads();
-                }
-            }
+        }
+        // record and boundary indices of the next height, ahead of the barrier
+        if (h > 0) {
+            kp = hoff[h - 1] + wave;
+            if (kp < hoff[h]) bwd_load(sub_tn, bidx, kp, lane, pre);
         }
         __syncthreads();
     }
@@ -987,11 +1091,7 @@ template <typename T>
 void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
                         const int64_t* bidx, const double* y, double* x) {
     if (P.n_sub == 0) return;
-    static const int coop_min = [] {
-        const char* e = std::getenv("BIDO_COOP_MIN");
-        return e && *e ? std::atoi(e) : SUB_COOP_MIN;
-    }();
-    k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel, bidx, y, x, coop_min);
+    k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel, bidx, y, x);
 }
 template <typename T>
 void launch_tri_fwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,

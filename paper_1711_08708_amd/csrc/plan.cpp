@@ -158,7 +158,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     p.height = t.height;
     p.nodes.resize(nn);
     // update workspace entry 0 stays 0.0 (read in place of a missing child's
-    // update); the boundary index array ends with one spare entry
+    // update); the boundary index and extend-add arrays end with a spare entry
     int64_t poff = 0, boff = 0, uoff = 1, eoff = 0;
     for (int id = 0; id < nn; ++id) {
         const Front& fr = f.fronts[id];
@@ -195,7 +195,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     p.panel.assign((size_t)poff, 0.0);
     p.panel_cm.assign((size_t)poff, 0.0);
     p.bidx.assign((size_t)boff + 1, 0);
-    p.ea.assign((size_t)std::max<int64_t>(eoff, 1), Ea{-1, -1});
+    p.ea.assign((size_t)eoff + 1, Ea{-1, -1});        // (plus a spare entry)
     for (int id = 0; id < nn; ++id) {
         const Front& fr = f.fronts[id];
         const TriNode& d = p.nodes[id];
