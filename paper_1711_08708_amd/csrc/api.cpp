@@ -243,6 +243,7 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
         L.n_fcomb = (int)sp.ncf;
         L.bcomb = fd.bcomb + sp.cb0;
         L.n_bcomb = (int)sp.ncb;
+        L.bwd_nt = p.bwd_wide ? PLAN_BWD_WIDE : 256;
         fd.top.push_back(L);
     }
     fd.fwd_bytes64 = p.fwd_bytes64;
@@ -2063,13 +2064,15 @@ bido_status bido_autotune(bido_ctx* c, int reps, bido_tune_report* rep) {
         }
         const PlanOptions at = cur.opts;
         for (int fc : {64, 128, 256})
-            for (int br : {0, 256, 1024}) {
-                PlanOptions o = at;
-                o.fwd_cols = fc;
-                o.bwd_rows = br;
-                if (o.fwd_cols == at.fwd_cols && o.bwd_rows == at.bwd_rows) continue;
-                attempt(o);
-            }
+            for (int wide : {1, 0})
+                for (int br : {0, wide ? 1024 : 256}) {
+                    PlanOptions o = at;
+                    o.fwd_cols = fc;
+                    o.bwd_rows = br;
+                    o.bwd_wide = wide;
+                    if (o.fwd_cols == at.fwd_cols && o.bwd_rows == at.bwd_rows && o.bwd_wide == at.bwd_wide) continue;
+                    attempt(o);
+                }
         f.trim_top_cache(cur.top_h);
         HIP_OK(poison_workspace(cur));
         r.us_after[which] = best * 1e3;

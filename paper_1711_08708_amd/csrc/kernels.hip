@@ -10,6 +10,9 @@
 //   mean_*              normalisation (M U, 1) = 0 of Prop. 1
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
+
 #include "kernels.h"
 #include "launch.h"
 
@@ -685,8 +688,9 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __rest
                                                            const T* __restrict__ panel,
                                                            const int64_t* __restrict__ bidx,
                                                            const double* __restrict__ y,
-                                                           double* x) {
+                                                           double* x, int group_max) {
     __shared__ double zbuf[SUB_NW][SUB_MAXF + 1];
+    __shared__ double red[SUB_NW][WAVE];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int32_t* hoff = sub_hoff + (size_t)blockIdx.x * (hc + 2);
     double* z = zbuf[wave];
@@ -694,7 +698,54 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __rest
     int kp = hoff[hc] + wave;
     if (kp < hoff[hc + 1]) bwd_load(sub_tn, bidx, kp, lane, pre);
     for (int h = hc; h >= 0; --h) {
-        const int k0 = hoff[h], k1 = hoff[h + 1];
+        const int k0 = hoff[h], k1 = hoff[h + 1], n = k1 - k0;
+        if (n > 0 && n <= group_max) {
+            // g waves per node: row streams spread over the group, partial
+            // column sums reduced across the wave, then across the group
+            const int g = sub_group(n), grp = wave / g, wg = wave % g;
+            const bool active = grp < n;
+            const int lead = grp * g < SUB_NW ? grp * g : 0;
+            double* zg = zbuf[lead];
+            TriNode nd{};
+            if (active) {
+                nd = sub_tn[__builtin_amdgcn_readfirstlane(k0 + grp)];
+                const int t = wg * WAVE + lane, nF = nd.nI + nd.nB;
+                if (g == 2) stage_z<SUB_MAXF / (2 * WAVE)>(nd, t, 2 * WAVE, 0, nF, 0, bidx, y, x, zg, SUB_MAXF);
+                else if (g == 4) stage_z<(SUB_MAXF + 4 * WAVE - 1) / (4 * WAVE)>(nd, t, 4 * WAVE, 0, nF, 0, bidx, y, x,
+                                                                                  zg, SUB_MAXF);
+                else stage_z<(SUB_MAXF + 8 * WAVE - 1) / (8 * WAVE)>(nd, t, g * WAVE, 0, nF, 0, bidx, y, x, zg,
+                                                                      SUB_MAXF);
+            }
+            int ncb = 0;
+            for (int k = k0; k < k1; ++k) ncb = max(ncb, (sub_tn[k].nI + WAVE - 1) / WAVE);
+            __syncthreads();
+            const int nI = nd.nI, nF = nd.nI + nd.nB;
+            const T* P = panel + nd.panel;
+            for (int cb = 0; cb < ncb * WAVE; cb += WAVE) {
+                const bool on = active && cb < nI;
+                const int ncols = on ? min(WAVE, nI - cb) : 1;
+                const int W = pow2_ceil64(ncols);
+                const int Sw = WAVE / W, S = g * Sw;
+                const int col = lane % W, st = wg * Sw + lane / W;
+                double acc = 0.0;
+                if (on && col < ncols) acc = col_part<T>(P, nI, cb + col, cb + st, nF, S, zg, 0);
+                for (int m = W; m < WAVE; m <<= 1) acc += __shfl_xor(acc, m, WAVE);
+                if (lane < W) red[wave][lane] = acc;
+                __syncthreads();
+                if (on && wg == 0 && lane < ncols) {
+                    double sum = 0.0;
+                    for (int q = 0; q < g; ++q) sum += red[lead + q][lane];
+                    x[nd.off + cb + lane] = sum;
+                }
+                __syncthreads();
+            }
+            if (h > 0) {
+                kp = hoff[h - 1] + wave;
+                if (kp < hoff[h]) bwd_load(sub_tn, bidx, kp, lane, pre);
+            }
+            __syncthreads();
+            continue;
+        }
         for (int k = k0 + wave; k < k1; k += SUB_NW) {
             if (k != kp) bwd_load(sub_tn, bidx, k, lane, pre);
             const TriNode& nd = pre.nd;
@@ -789,24 +840,24 @@ __global__ __launch_bounds__(BLOCK) void k_tri_fwd_comb(const TriNode* __restric
 // Level phase, backward: item = (column tile, row range) of one node; z for
 // the row range is staged in LDS first.  A tile split over several row
 // ranges leaves its partial sums in scratch for the combine launch.
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_tri_bwd_lvl(const TriNode* __restrict__ nodes,
-                                                       const BwdItem* __restrict__ items,
-                                                       const T* __restrict__ panel,
-                                                       const int64_t* __restrict__ bidx,
-                                                       const double* __restrict__ y,
-                                                       double* x, double* __restrict__ scratch, int spare) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_tri_bwd_lvl(const TriNode* __restrict__ nodes,
+                                                    const BwdItem* __restrict__ items,
+                                                    const T* __restrict__ panel,
+                                                    const int64_t* __restrict__ bidx,
+                                                    const double* __restrict__ y,
+                                                    double* x, double* __restrict__ scratch, int spare) {
     extern __shared__ double z[];   // the item's rows, then the spare slot
-    __shared__ double red[BLOCK];
+    __shared__ double red[NT];
     const BwdItem it = items[blockIdx.x];
     const TriNode nd = nodes[it.node];
     const int nI = nd.nI;
-    for (int r0 = it.rs; r0 < it.re; r0 += 2 * BLOCK)
-        stage_z<2>(nd, threadIdx.x, BLOCK, r0, it.re, it.rs, bidx, y, x, z, spare);
+    for (int r0 = it.rs; r0 < it.re; r0 += 2 * NT)
+        stage_z<2>(nd, threadIdx.x, NT, r0, it.re, it.rs, bidx, y, x, z, spare);
     __syncthreads();
     const int W = it.W;
     const int col = threadIdx.x % W, st = threadIdx.x / W;
-    const int S = BLOCK / W;
+    const int S = NT / W;
     const int c = it.c0 + col;
     const T* P = panel + nd.panel;
     double acc = 0.0;
@@ -1091,7 +1142,11 @@ template <typename T>
 void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
                         const int64_t* bidx, const double* y, double* x) {
     if (P.n_sub == 0) return;
-    k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel, bidx, y, x);
+    static const int group_max = [] {
+        const char* e = std::getenv("BIDO_BWD_GROUP_MAXN");
+        return e && *e ? std::max(0, std::min(SUB_NW / 2, std::atoi(e))) : 2;
+    }();
+    k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel, bidx, y, x, group_max);
 }
 template <typename T>
 void launch_tri_fwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
@@ -1107,8 +1162,12 @@ template <typename T>
 void launch_tri_bwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
                         const T* panel, const int64_t* bidx, const double* y, double* x) {
     if (L.n_bwd == 0) return;
-    k_tri_bwd_lvl<T><<<L.n_bwd, BLOCK, L.lds_b + sizeof(double), s>>>(nodes, L.bwd, panel, bidx, y, x, P.scratch,
-                                                                      (int)(L.lds_b / sizeof(double)));
+    const size_t lds = L.lds_b + sizeof(double);
+    const int spare = (int)(L.lds_b / sizeof(double));
+    if (L.bwd_nt == 1024)
+        k_tri_bwd_lvl<T, 1024><<<L.n_bwd, 1024, lds, s>>>(nodes, L.bwd, panel, bidx, y, x, P.scratch, spare);
+    else
+        k_tri_bwd_lvl<T, BLOCK><<<L.n_bwd, BLOCK, lds, s>>>(nodes, L.bwd, panel, bidx, y, x, P.scratch, spare);
     if (L.n_bcomb > 0) k_tri_bwd_comb<<<L.n_bcomb, WAVE, 0, s>>>(nodes, L.bcomb, x, P.scratch);
 }
 

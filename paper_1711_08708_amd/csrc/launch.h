@@ -41,6 +41,7 @@ struct TriTopLevel {
     int n_fcomb = 0;
     BwdItem* bcomb = nullptr; // device: split backward tiles
     int n_bcomb = 0;
+    int bwd_nt = 256;         // threads of a backward item (256 or 1024)
 };
 struct TriPlan {
     int hc = -1;                  // subtree cut height (-1: no subtree phase)

@@ -604,6 +604,11 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
                                         : env_limit("BIDO_BWD_MAXR", PLAN_BWD_MAXR, 64, PLAN_LDS_DOUBLES);
     p.used.fwd_cols = fwd_cols;
     p.used.bwd_rows = bwd_maxr == PLAN_BWD_MAXR ? 0 : bwd_maxr;
+    {
+        const char* ew = std::getenv("BIDO_BWD_WIDE");
+        p.bwd_wide = o.bwd_wide >= 0 ? o.bwd_wide != 0 : (ew && *ew ? std::atoi(ew) != 0 : true);
+        p.used.bwd_wide = p.bwd_wide ? 1 : 0;
+    }
     std::vector<std::pair<size_t, size_t>> fspan, bspan, fcspan, bcspan;
     struct LdsSz { size_t f, b; };
     std::vector<LdsSz> lds;
@@ -661,7 +666,10 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
             const int nI = fr.nI, nF = fr.nI + fr.nB;
             if (nI == 0) continue;
             const int W = pow2_at_least(std::min(nI, 64), 64);
-            const int RB = bwd_maxr == PLAN_BWD_MAXR ? std::min(PLAN_BWD_MAXR, std::max(64, 8192 / W)) : bwd_maxr;
+            // wide items take a whole column tile (up to the LDS staging bound)
+            const int RB = p.bwd_wide ? (o.bwd_rows > 0 ? bwd_maxr : PLAN_LDS_DOUBLES)
+                           : bwd_maxr == PLAN_BWD_MAXR ? std::min(PLAN_BWD_MAXR, std::max(64, 8192 / W))
+                                                       : bwd_maxr;
             for (int c0 = 0; c0 < nI; c0 += W) {
                 const int nparts = (nF - c0 + RB - 1) / RB;
                 const int64_t part0 = p.scratch_size;

@@ -18,6 +18,9 @@ struct PlanOptions {
     int bwd_rows = 0;   // rows per backward level item (0: 8192 / tile width, at most 512)
     int top_h = -1;     // first height of the top (raised to fit the top-size bound)
     int sub_h = -1;     // highest subtree cut of any tree (< 0: the size rule alone)
+    int bwd_wide = -1;  // backward level items of 1024 threads over whole column tiles
+                        // (1), of 256 threads over row ranges (0); < 0: environment
+                        // BIDO_BWD_WIDE, else 1
 };
 
 struct FactorPlan {
@@ -44,6 +47,7 @@ struct FactorPlan {
     std::vector<TriItem> fwd_comb;
     std::vector<BwdItem> bwd_comb;
     struct Span { size_t f0, nf, b0, nb, lds_f, lds_b, cf0, ncf, cb0, ncb; };
+    bool bwd_wide = false;              // backward level items of 1024 threads
     std::vector<Span> spans;
     int64_t scratch_size = 0;           // partial sums of split tiles
     int n_tiles = 0;                    // tiles (forward + backward)
@@ -73,7 +77,8 @@ constexpr int PLAN_SUB_MAXF = 384;     // panel rows of a node in the subtree ph
 constexpr int PLAN_LDS_MAXW = 1 << 20; // (no own-size limit in the level phases)
 constexpr int PLAN_FWD_ROWS = 64;      // forward row tile (one row per lane)
 constexpr int PLAN_FWD_COLS = 128;     // forward column chunk per work item (4 waves)
-constexpr int PLAN_BWD_MAXR = 512;     // backward rows per work item (LDS staging)
+constexpr int PLAN_BWD_MAXR = 512;     // backward rows per 256-thread work item (LDS staging)
+constexpr int PLAN_BWD_WIDE = 1024;    // threads of a wide backward work item
 constexpr int PLAN_LDS_DOUBLES = 4096; // bound of the LDS staging per level item
 constexpr int PLAN_TOP_MAX = 6144;     // max n_top (w_top staged in LDS, FP64)
 constexpr int PLAN_HODLR_LEAF = 64;    // leaf size of the hierarchical top
