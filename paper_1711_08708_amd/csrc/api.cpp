@@ -1039,12 +1039,12 @@ bido_status union_csr(const std::vector<const Csr*>& parts, const std::vector<in
 void fused_apply(FusedBatch* F, bool with_old) {
     hipStream_t s = F->stream;
     inner_solve(F, F->p1, F->r, F->tA);                                               // Z1 = P1^-1 R1
-    launch_seg_csr(s, F->Tv, F->avu, F->spmv_group, F->tA, F->r, F->tB);               // R2 - S_i Pi Z1
+    launch_seg_csr(s, F->Tv, F->avu, F->spmv_group, F->tA, F->r, F->tB, F->done);      // R2 - S_i Pi Z1
     inner_solve(F, F->pk, F->tB, F->z);                                                // Z2 = PK^-1 (...)
-    launch_seg_csr(s, F->Tu, F->auv, F->spmv_group, F->z, nullptr, F->tC);             // Pi^T S_i Z2
+    launch_seg_csr(s, F->Tu, F->auv, F->spmv_group, F->z, nullptr, F->tC, F->done);    // Pi^T S_i Z2
     inner_solve(F, F->p1, F->tC, F->tD);                                               // P1^-1 Pi^T S_i Z2
     launch_seg_combine(s, F->T, F->z, F->tA, F->tD, F->r, with_old ? F->r_old : nullptr, F->part(FR_RZ),
-                       F->part(FR_ZRO));
+                       F->part(FR_ZRO), F->done);
 }
 
 // q = Lambda p, x += alpha p, r -= alpha q (alpha from r.z in slot `rho`);
@@ -1052,7 +1052,7 @@ void fused_apply(FusedBatch* F, bool with_old) {
 void fused_tail(FusedBatch* F, int rho) {
     hipStream_t s = F->stream;
     const int S = F->S;
-    launch_seg_spmv(s, F->T, F->lam, F->spmv_group, 0, F->p, nullptr, F->q, F->part(FR_PQ), nullptr);
+    launch_seg_spmv(s, F->T, F->lam, F->spmv_group, 0, F->p, nullptr, F->q, F->part(FR_PQ), nullptr, F->done);
     launch_seg_pcg_update(s, F->T, F->x, F->r, F->flexible() ? F->r_old : nullptr, F->p, F->q, F->part(FR_PQ),
                           F->part(FR_RR), F->sc + (int64_t)rho * S, F->done, F->sc + 2 * (int64_t)S);
     hipMemcpyAsync(F->sc_host, F->sc, F->region(FR_RR + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -1109,7 +1109,7 @@ struct SliceRun {
 bido_status fused_pcg(FusedBatch* F, const std::vector<bido_ctx*>& ctx, std::vector<SliceRun>& sr) {
     const int S = F->S;
     hipStream_t s = F->stream;
-    launch_seg_spmv(s, F->T, F->lam, F->spmv_group, 1, F->x, F->Y, F->r, F->part(FR_RR), F->part(FR_YY));
+    launch_seg_spmv(s, F->T, F->lam, F->spmv_group, 1, F->x, F->Y, F->r, F->part(FR_RR), F->part(FR_YY), nullptr);
     HIP_OK(hipMemcpyAsync(F->sc_host, F->sc, F->region(FR_YY + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     sr.assign(S, SliceRun());
@@ -1446,6 +1446,9 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
         HIP_OK(poison_workspace(*f));
     }
     HIP_OK(hipStreamCreateWithFlags(&F->stream, hipStreamNonBlocking));
+    HIP_OK(hipMemset(F->done, 0, S));
+    F->p1.plan.skip = F->done;         // the sweeps leave frozen slices' trees alone
+    F->pk.plan.skip = F->done;
     HIP_OK(hipDeviceSynchronize());
     for (int i = 0; i < S; ++i) {
         bido_ctx* c = ctxs[i];

@@ -2,8 +2,8 @@
 // vector (slice s at [base[s], base[s] + n2_s), u rows first): each block
 // works on a row range of one slice, and every scalar of the recurrences
 // (p.q, r.z, alpha, beta) is a per-slice sum of that slice's block partials,
-// formed in the same order by every block that needs it.  A slice whose
-// stopping test is met is frozen (alpha = beta = 0).
+// formed in the same order by every block that needs it.  The blocks of a
+// slice whose stopping test is met (done[s]) leave its vectors alone.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -50,9 +50,10 @@ __global__ __launch_bounds__(BB) void k_seg_spmv(SegTable T, const int64_t* __re
                                                  const int32_t* __restrict__ col, const double* __restrict__ val,
                                                  const double* __restrict__ x, const double* __restrict__ y,
                                                  double* __restrict__ out, double* __restrict__ part0,
-                                                 double* __restrict__ part1) {
+                                                 double* __restrict__ part1, const uint8_t* __restrict__ done) {
     __shared__ double sh[BB / BW];
     const SegBlock bk = T.blk[blockIdx.x];
+    if (done && done[bk.slice]) return;
     const int64_t r0 = bk.r0, r1 = bk.r1;
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
@@ -86,8 +87,9 @@ template <int G>
 __global__ __launch_bounds__(BB) void k_seg_csr(SegTable T, const int64_t* __restrict__ ptr,
                                                 const int32_t* __restrict__ col, const double* __restrict__ val,
                                                 const double* __restrict__ x, const double* __restrict__ b,
-                                                double* __restrict__ y) {
+                                                double* __restrict__ y, const uint8_t* __restrict__ done) {
     const SegBlock bk = T.blk[blockIdx.x];
+    if (done && done[bk.slice]) return;
     const int lane = threadIdx.x % G;
     for (int64_t r = bk.r0 + threadIdx.x / G; r < bk.r1; r += BB / G) {
         double s = 0.0;
@@ -107,9 +109,10 @@ __global__ __launch_bounds__(BB) void k_seg_pcg_update(SegTable T, double* __res
     __shared__ double sh[BB / BW];
     const SegBlock bk = T.blk[blockIdx.x];
     const int s = bk.slice;
+    if (done[s]) return;                 // frozen: x, r and its partials stay as they are
     const SegSlice sl = T.sl[s];
     const double pq = slice_sum(part_pq, sl.b0, sl.b1, sh);
-    const double alpha = done[s] ? 0.0 : rho[s] / pq;
+    const double alpha = rho[s] / pq;
     if ((int)blockIdx.x == sl.b0 && threadIdx.x == 0) pq_out[s] = pq;
     double acc = 0.0;
     for (int64_t i = bk.r0 + threadIdx.x; i < bk.r1; i += BB) {
@@ -128,9 +131,10 @@ __global__ __launch_bounds__(BB) void k_seg_pcg_update(SegTable T, double* __res
 __global__ __launch_bounds__(BB) void k_seg_combine(SegTable T, double* __restrict__ z, const double* __restrict__ a,
                                                     const double* __restrict__ bb, const double* __restrict__ r,
                                                     const double* __restrict__ r_old, double* __restrict__ part_rz,
-                                                    double* __restrict__ part_zro) {
+                                                    double* __restrict__ part_zro, const uint8_t* __restrict__ done) {
     __shared__ double sh[BB / BW];
     const SegBlock bk = T.blk[blockIdx.x];
+    if (done[bk.slice]) return;
     const SegSlice sl = T.sl[bk.slice];
     const int64_t uend = sl.base + sl.nu;
     double acc = 0.0, acc2 = 0.0;
@@ -163,12 +167,13 @@ __global__ __launch_bounds__(BB) void k_seg_p_update(SegTable T, const double* _
     __shared__ double sh[BB / BW];
     const SegBlock bk = T.blk[blockIdx.x];
     const int s = bk.slice;
+    if (done[s]) return;
     const SegSlice sl = T.sl[s];
     const double rz = slice_sum(part_rz, sl.b0, sl.b1, sh);
     double beta = 0.0;
     if (!first) {
         const double zro = flexible ? slice_sum(part_zro, sl.b0, sl.b1, sh) : 0.0;
-        if (!done[s]) beta = (rz - zro) / rho_old[s];
+        beta = (rz - zro) / rho_old[s];
     }
     if ((int)blockIdx.x == sl.b0 && threadIdx.x == 0) rho_new[s] = rz;
     // the first direction is z itself: p may hold stale bits (0 * NaN = NaN)
@@ -178,28 +183,28 @@ __global__ __launch_bounds__(BB) void k_seg_p_update(SegTable T, const double* _
 }  // namespace
 
 void launch_seg_spmv(hipStream_t s, const SegTable& T, const CsrDev& A, int group, int mode, const double* x,
-                     const double* y, double* out, double* part0, double* part1) {
+                     const double* y, double* out, double* part0, double* part1, const uint8_t* done) {
     if (T.nblocks <= 0) return;
 #define BIDO_SEG_CASE(G)                                                                                     \
     if (group == G) {                                                                                        \
         if (mode == 0)                                                                                       \
-            k_seg_spmv<G, 0><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, y, out, part0, part1);     \
+            k_seg_spmv<G, 0><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, y, out, part0, part1, done); \
         else                                                                                                 \
-            k_seg_spmv<G, 1><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, y, out, part0, part1);     \
+            k_seg_spmv<G, 1><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, y, out, part0, part1, done); \
         return;                                                                                              \
     }
     BIDO_SEG_CASE(4) BIDO_SEG_CASE(8) BIDO_SEG_CASE(16)
 #undef BIDO_SEG_CASE
-    if (mode == 0) k_seg_spmv<32, 0><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, y, out, part0, part1);
-    else k_seg_spmv<32, 1><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, y, out, part0, part1);
+    if (mode == 0) k_seg_spmv<32, 0><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, y, out, part0, part1, done);
+    else k_seg_spmv<32, 1><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, y, out, part0, part1, done);
 }
 void launch_seg_csr(hipStream_t s, const SegTable& T, const CsrDev& A, int group, const double* x, const double* b,
-                    double* y) {
+                    double* y, const uint8_t* done) {
     if (T.nblocks <= 0) return;
-    if (group == 4) k_seg_csr<4><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, b, y);
-    else if (group == 8) k_seg_csr<8><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, b, y);
-    else if (group == 16) k_seg_csr<16><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, b, y);
-    else k_seg_csr<32><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, b, y);
+    if (group == 4) k_seg_csr<4><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, b, y, done);
+    else if (group == 8) k_seg_csr<8><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, b, y, done);
+    else if (group == 16) k_seg_csr<16><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, b, y, done);
+    else k_seg_csr<32><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, b, y, done);
 }
 void launch_seg_pcg_update(hipStream_t s, const SegTable& T, double* x, double* r, double* r_old, const double* p,
                            const double* q, const double* part_pq, double* part_rr, const double* rho,
@@ -208,9 +213,10 @@ void launch_seg_pcg_update(hipStream_t s, const SegTable& T, double* x, double* 
     k_seg_pcg_update<<<T.nblocks, BB, 0, s>>>(T, x, r, r_old, p, q, part_pq, part_rr, rho, done, pq_out);
 }
 void launch_seg_combine(hipStream_t s, const SegTable& T, double* z, const double* a, const double* b,
-                        const double* r, const double* r_old, double* part_rz, double* part_zro) {
+                        const double* r, const double* r_old, double* part_rz, double* part_zro,
+                        const uint8_t* done) {
     if (T.nblocks <= 0) return;
-    k_seg_combine<<<T.nblocks, BB, 0, s>>>(T, z, a, b, r, r_old, part_rz, part_zro);
+    k_seg_combine<<<T.nblocks, BB, 0, s>>>(T, z, a, b, r, r_old, part_rz, part_zro, done);
 }
 void launch_seg_p_update(hipStream_t s, const SegTable& T, const double* z, double* p, const double* part_rz,
                          const double* part_zro, int first, int flexible, const double* rho_old, double* rho_new,

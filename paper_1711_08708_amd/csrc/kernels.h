@@ -22,7 +22,7 @@ struct TriNode {
     int32_t nI, nB;
     int32_t child[2];
     int32_t gi;      // own index of a grounded vertex (its entry is fixed to 0), or -1
-    int32_t pad;
+    int32_t tree;    // slice of a merged forest the node belongs to (0 otherwise)
 };
 
 // Extend-add map entry: position in each child's update vector (-1: none).

@@ -619,10 +619,11 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_fwd_sub(const TriNode* __rest
                                                            const Ea* __restrict__ ea,
                                                            const double* __restrict__ b,
                                                            double* __restrict__ y,
-                                                           double* upd) {
+                                                           double* upd, const uint8_t* __restrict__ skip) {
     __shared__ double wbuf[SUB_NW][SUB_MAXW + 1];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int32_t* hoff = sub_hoff + (size_t)blockIdx.x * (hc + 2);
+    if (skip && skip[sub_tn[hoff[0]].tree]) return;   // a frozen slice of a batch
     FwdPre pre;
     SubSlot sl = fwd_slot(hoff, 0, wave, lane);
     if (sl.k >= 0) fwd_load(sub_tn, ea, sl.k, sl.t, sl.g * WAVE, pre);
@@ -688,11 +689,13 @@ __global__ __launch_bounds__(SUB_BLOCK) void k_tri_bwd_sub(const TriNode* __rest
                                                            const T* __restrict__ panel,
                                                            const int64_t* __restrict__ bidx,
                                                            const double* __restrict__ y,
-                                                           double* x, int group_max) {
+                                                           double* x, int group_max,
+                                                           const uint8_t* __restrict__ skip) {
     __shared__ double zbuf[SUB_NW][SUB_MAXF + 1];
     __shared__ double red[SUB_NW][WAVE];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int32_t* hoff = sub_hoff + (size_t)blockIdx.x * (hc + 2);
+    if (skip && skip[sub_tn[hoff[0]].tree]) return;   // a frozen slice of a batch
     double* z = zbuf[wave];
     BwdPre pre;
     int kp = hoff[hc] + wave;
@@ -788,11 +791,13 @@ __global__ __launch_bounds__(BLOCK) void k_tri_fwd_lvl(const TriNode* __restrict
                                                        const Ea* __restrict__ ea,
                                                        const double* __restrict__ b,
                                                        double* __restrict__ y,
-                                                       double* upd, double* __restrict__ scratch, int spare) {
+                                                       double* upd, double* __restrict__ scratch, int spare,
+                                                       const uint8_t* __restrict__ skip) {
     extern __shared__ double w[];   // the item's columns, then the spare slot
     __shared__ double red[BLOCK / WAVE][FWD_ROWS];
     const TriItem it = items[blockIdx.x];
     const TriNode nd = nodes[it.node];
+    if (skip && skip[nd.tree]) return;
     const int64_t u0 = nd.u0, u1 = nd.u1;
     const int ncol = it.ce - it.cs;
     for (int i0 = it.cs; i0 < it.ce; i0 += 2 * BLOCK)
@@ -824,13 +829,15 @@ __global__ __launch_bounds__(BLOCK) void k_tri_fwd_lvl(const TriNode* __restrict
 __global__ __launch_bounds__(BLOCK) void k_tri_fwd_comb(const TriNode* __restrict__ nodes,
                                                         const TriItem* __restrict__ comb, int ncomb,
                                                         const Ea* __restrict__ ea, double* __restrict__ y,
-                                                        double* upd, const double* __restrict__ scratch) {
+                                                        double* upd, const double* __restrict__ scratch,
+                                                        const uint8_t* __restrict__ skip) {
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int q = blockIdx.x * (BLOCK / WAVE) + wave;
     if (q >= ncomb) return;
     const TriItem it = comb[q];
     if (lane >= it.nrows) return;
     const TriNode nd = nodes[it.node];
+    if (skip && skip[nd.tree]) return;
     const double add = row_add(nd, it.r0 + lane, ea, upd, nd.u0, nd.u1);
     double t = 0.0;
     for (int k = 0; k < it.nparts; ++k) t += scratch[it.part0 + (int64_t)k * FWD_ROWS + lane];
@@ -846,11 +853,13 @@ __global__ __launch_bounds__(NT) void k_tri_bwd_lvl(const TriNode* __restrict__ 
                                                     const T* __restrict__ panel,
                                                     const int64_t* __restrict__ bidx,
                                                     const double* __restrict__ y,
-                                                    double* x, double* __restrict__ scratch, int spare) {
+                                                    double* x, double* __restrict__ scratch, int spare,
+                                                    const uint8_t* __restrict__ skip) {
     extern __shared__ double z[];   // the item's rows, then the spare slot
     __shared__ double red[NT];
     const BwdItem it = items[blockIdx.x];
     const TriNode nd = nodes[it.node];
+    if (skip && skip[nd.tree]) return;
     const int nI = nd.nI;
     for (int r0 = it.rs; r0 < it.re; r0 += 2 * NT)
         stage_z<2>(nd, threadIdx.x, NT, r0, it.re, it.rs, bidx, y, x, z, spare);
@@ -877,11 +886,13 @@ __global__ __launch_bounds__(NT) void k_tri_bwd_lvl(const TriNode* __restrict__ 
 // Combine launch of a backward level: one wave per split column tile.
 __global__ __launch_bounds__(WAVE) void k_tri_bwd_comb(const TriNode* __restrict__ nodes,
                                                        const BwdItem* __restrict__ comb,
-                                                       double* __restrict__ x, const double* __restrict__ scratch) {
+                                                       double* __restrict__ x, const double* __restrict__ scratch,
+                                                       const uint8_t* __restrict__ skip) {
     const BwdItem it = comb[blockIdx.x];
     const int col = threadIdx.x;
     if (col >= it.ncols) return;
     const TriNode nd = nodes[it.node];
+    if (skip && skip[nd.tree]) return;
     double t = 0.0;
     for (int k = 0; k < it.nparts; ++k) t += scratch[it.part0 + (int64_t)k * it.W + col];
     x[nd.off + it.c0 + col] = t;
@@ -1136,7 +1147,7 @@ template <typename T>
 void launch_tri_fwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel_cm,
                         const Ea* ea, const double* b, double* y, double* upd) {
     if (P.n_sub == 0) return;
-    k_tri_fwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel_cm, ea, b, y, upd);
+    k_tri_fwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel_cm, ea, b, y, upd, P.skip);
 }
 template <typename T>
 void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
@@ -1146,17 +1157,19 @@ void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, c
         const char* e = std::getenv("BIDO_BWD_GROUP_MAXN");
         return e && *e ? std::max(0, std::min(SUB_NW / 2, std::atoi(e))) : 2;
     }();
-    k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel, bidx, y, x, group_max);
+    k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel, bidx, y, x, group_max,
+                                                   P.skip);
 }
 template <typename T>
 void launch_tri_fwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
                         const T* panel_cm, const Ea* ea, const double* b, double* y, double* upd) {
     if (L.n_fwd == 0) return;
     k_tri_fwd_lvl<T><<<L.n_fwd, BLOCK, L.lds_f + sizeof(double), s>>>(nodes, L.fwd, panel_cm, ea, b, y, upd,
-                                                                      P.scratch, (int)(L.lds_f / sizeof(double)));
+                                                                      P.scratch, (int)(L.lds_f / sizeof(double)),
+                                                                      P.skip);
     if (L.n_fcomb > 0)
         k_tri_fwd_comb<<<(L.n_fcomb + BLOCK / WAVE - 1) / (BLOCK / WAVE), BLOCK, 0, s>>>(nodes, L.fcomb, L.n_fcomb,
-                                                                                       ea, y, upd, P.scratch);
+                                                                                       ea, y, upd, P.scratch, P.skip);
 }
 template <typename T>
 void launch_tri_bwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, const TriNode* nodes,
@@ -1165,10 +1178,10 @@ void launch_tri_bwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, c
     const size_t lds = L.lds_b + sizeof(double);
     const int spare = (int)(L.lds_b / sizeof(double));
     if (L.bwd_nt == 1024)
-        k_tri_bwd_lvl<T, 1024><<<L.n_bwd, 1024, lds, s>>>(nodes, L.bwd, panel, bidx, y, x, P.scratch, spare);
+        k_tri_bwd_lvl<T, 1024><<<L.n_bwd, 1024, lds, s>>>(nodes, L.bwd, panel, bidx, y, x, P.scratch, spare, P.skip);
     else
-        k_tri_bwd_lvl<T, BLOCK><<<L.n_bwd, BLOCK, lds, s>>>(nodes, L.bwd, panel, bidx, y, x, P.scratch, spare);
-    if (L.n_bcomb > 0) k_tri_bwd_comb<<<L.n_bcomb, WAVE, 0, s>>>(nodes, L.bcomb, x, P.scratch);
+        k_tri_bwd_lvl<T, BLOCK><<<L.n_bwd, BLOCK, lds, s>>>(nodes, L.bwd, panel, bidx, y, x, P.scratch, spare, P.skip);
+    if (L.n_bcomb > 0) k_tri_bwd_comb<<<L.n_bcomb, WAVE, 0, s>>>(nodes, L.bcomb, x, P.scratch, P.skip);
 }
 
 #define BIDO_INST(T)                                                                                   \

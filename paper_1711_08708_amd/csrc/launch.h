@@ -51,6 +51,7 @@ struct TriPlan {
     int32_t* sub_hoff = nullptr;  // device: n_sub x (hc+2) height offsets
     int sub_maxw = 0;             // max nI below the cut
     double* scratch = nullptr;    // partial sums of split tiles
+    const uint8_t* skip = nullptr; // device, per tree of a merged forest: 1 = leave its nodes alone
     // dense top (n_top = 0: none): x[top_pos] = S_top^-1 w_top
     int64_t n_top = 0;
     const int64_t* top_pos = nullptr;
@@ -127,17 +128,19 @@ void launch_tri_bwd_lvl(hipStream_t s, const TriTopLevel& L, const TriPlan& P, c
                         const T* panel, const int64_t* bidx, const double* y, double* x);
 
 // Segmented PCG kernels of a batch (batch.hip).  Scalars are per slice:
-// rho[s], done[s] (1: frozen), pq_out[s], rho_new[s]; partial regions have
-// one entry per block of the table.
+// rho[s], done[s] (1: frozen; its blocks do nothing, except in the residual
+// SpMV of mode 1, which passes done = null), pq_out[s], rho_new[s]; partial
+// regions have one entry per block of the table.
 void launch_seg_spmv(hipStream_t s, const SegTable& T, const CsrDev& A, int group, int mode, const double* x,
-                     const double* y, double* out, double* part0, double* part1);
+                     const double* y, double* out, double* part0, double* part1, const uint8_t* done);
 void launch_seg_csr(hipStream_t s, const SegTable& T, const CsrDev& A, int group, const double* x, const double* b,
-                    double* y);
+                    double* y, const uint8_t* done);
 void launch_seg_pcg_update(hipStream_t s, const SegTable& T, double* x, double* r, double* r_old, const double* p,
                            const double* q, const double* part_pq, double* part_rr, const double* rho,
                            const uint8_t* done, double* pq_out);
 void launch_seg_combine(hipStream_t s, const SegTable& T, double* z, const double* a, const double* b,
-                        const double* r, const double* r_old, double* part_rz, double* part_zro);
+                        const double* r, const double* r_old, double* part_rz, double* part_zro,
+                        const uint8_t* done);
 void launch_seg_p_update(hipStream_t s, const SegTable& T, const double* z, double* p, const double* part_rz,
                          const double* part_zro, int first, int flexible, const double* rho_old, double* rho_new,
                          const uint8_t* done);

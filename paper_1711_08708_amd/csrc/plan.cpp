@@ -257,6 +257,14 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     }
     std::reverse(roots.begin(), roots.end());
     const bool forest = roots.size() > 1;
+    // part of a merged forest that holds node id (-1: none recorded)
+    auto part_of = [&](int id) {
+        int k = -1;
+        for (size_t q = 0; q < f.parts.size() && q < f.part_node0.size(); ++q)
+            if (f.part_node0[q] <= id) k = (int)q;
+        return k < (int)f.part_top_h.size() && k < (int)f.part_off.size() ? k : -1;
+    };
+    for (int id = 0; id < nn; ++id) p.nodes[id].tree = std::max(0, part_of(root_of[id]));
     std::vector<int> hc_of(nn, -1);
     // cap of every tree's cut (environment BIDO_SUB_H when not given)
     const char* esub = std::getenv("BIDO_SUB_H");
@@ -328,13 +336,6 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     // independent blocks) gets one cut per tree and one hierarchical top per
     // tree, concatenated.  Environment BIDO_TOP_H forces a single tree's cut
     // (a value above the tree height switches the top off).
-    // part of a merged forest that holds node id (-1: none recorded)
-    auto part_of = [&](int id) {
-        int k = -1;
-        for (size_t q = 0; q < f.parts.size() && q < f.part_node0.size(); ++q)
-            if (f.part_node0[q] <= id) k = (int)q;
-        return k < (int)f.part_top_h.size() && k < (int)f.part_off.size() ? k : -1;
-    };
     // cost-model cut of the tree rooted at r (heights of its own nodes)
     auto model_cut = [&](int r, int& lowest) {
         constexpr double T_FWD = 10e-6, T_BWD = 25e-6, BW_LVL = 2.0e12, T_TOP = 10e-6, BW_TOP = 4.5e12;
