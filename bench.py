@@ -46,6 +46,8 @@ def _parse():
     ap.add_argument("--variant-steps", type=int, default=50)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuning of the inner-solve plans")
+    ap.add_argument("--graphs", type=int, default=-1, choices=[-1, 0, 1],
+                    help="replay captured iteration graphs: 1 always, 0 never, -1 the library default")
     ap.add_argument("--batch-streams", type=int, default=4, help="streams of the batch (batch64, --batch-mode streams)")
     ap.add_argument("--batch-mode", choices=["fused", "streams"], default="fused",
                     help="batch64: one union PCG for all slices (fused) or lockstep slices on streams; "
@@ -133,6 +135,8 @@ def main():
     solver = B.Solver(cfg, tol=args.tol, eps_h=args.eps, precision=prec)
     t_setup = time.perf_counter() - t_setup
     tune = None if args.no_tune else solver.autotune()
+    if args.graphs >= 0:
+        solver.set_graphs(bool(args.graphs))
     info = solver.info
     print(f"[bench] {cfg['name']}: N={solver.N} N_H={solver.NH} setup {t_setup:.2f}s "
           f"P1 {info['bytes_p1']/1e6:.1f} MB PK {info['bytes_pk']/1e6:.1f} MB", file=sys.stderr,

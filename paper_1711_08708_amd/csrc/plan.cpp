@@ -290,7 +290,9 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
                 nroots[h] += nroots[h - 1];
             }
             int cut = -1;
-            for (int want : {256, 64, 16, 1}) {
+            const char* ew = std::getenv("BIDO_SUB_WANT");
+            const int want0 = ew && *ew ? std::max(1, std::atoi(ew)) : 256;
+            for (int want : {want0, 64, 16, 1}) {
                 for (int h = Hr; h >= 0 && cut < 0; --h)
                     if (mw[h] <= PLAN_SUB_MAXW && mf[h] <= PLAN_SUB_MAXF && nroots[h] >= want) cut = h;
                 if (cut >= 0) break;
