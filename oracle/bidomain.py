@@ -11,6 +11,22 @@ Sec. 3.2 (scheme and resolution algorithm): with gamma = chi*c/dt,
 Vertices are reordered heart-first (assumption H1), so that Pi is the
 truncation to the first N_H entries and Pi^T the zero padding.
 
+Crank-Nicolson (the remark on the time discretisation after Prop. 3: another
+scheme changes only Step 1 and the definition of K).  Reading: the diffusion
+terms of the parabolic row are averaged over t^n and t^{n+1}, the reaction
+stays explicit and the elliptic row holds at t^{n+1}:
+
+  gamma M_H (V^{n+1} - V^n) + 1/2 S_i (V + Pi U)^{n+1} + 1/2 S_i (V + Pi U)^n
+      = - chi M_H (I_ion(V^n, W^n) - I_st^n);
+
+times 2 this is the system above with gamma replaced by 2 gamma (in Lambda
+and in K) and
+
+  Y = [0 ; M_H (2 gamma V^n - 2 chi (I_ion - I_st)) - S_i (V^n + Pi U^n)].
+
+`reaction=False` drops I_ion and I_st (the linear problem, for the
+convergence-order pins).
+
 Prop. 1: Lambda is symmetric positive semi-definite with kernel
 1_Omega x {0}; for Y in its range the solution with (M U, 1) = 0 is unique,
 obtained from any solution by U <- U - alpha 1 with
@@ -34,8 +50,12 @@ from . import fem, ionic
 class System:
     """Assembled bidomain system for one mesh and one time step."""
 
-    def __init__(self, cfg, dt=None):
+    def __init__(self, cfg, dt=None, scheme="euler", reaction=True):
+        if scheme not in ("euler", "cn"):
+            raise ValueError("scheme is 'euler' or 'cn'")
         self.cfg = cfg
+        self.scheme = scheme
+        self.reaction = reaction
         a = fem.assemble(cfg)
         self.N, self.NH = a["N"], a["NH"]
         self.hn = a["hn"]
@@ -48,6 +68,8 @@ class System:
         self.chi, self.cm = cfg["chi"], cfg["cm"]
         self.dt = cfg["dt"] if dt is None else dt
         self.gamma = self.chi * self.cm / self.dt
+        # the coefficient of M_H in Lambda and K: gamma (Euler), 2 gamma (CN)
+        self.gamma_eff = self.gamma * (2.0 if scheme == "cn" else 1.0)
         P = self.perm
         self.S1 = a["S1"][P][:, P].tocsr()
         self.Se = a["Se"][P][:, P].tocsr()
@@ -57,7 +79,7 @@ class System:
         Pi_T = sp.vstack([sp.identity(NH, format="csr"),
                           sp.csr_matrix((N - NH, NH))]).tocsr()
         self.PiT = Pi_T
-        g = self.gamma
+        g = self.gamma_eff
         self.Lam = sp.bmat([[self.S1, Pi_T @ self.Si],
                             [self.Si @ Pi_T.T, g * sp.diags(self.mH) + self.Si]],
                            format="csr")
@@ -80,15 +102,21 @@ class System:
         amp = self.cfg["stim_amp"] if self.n0 <= n < self.n1 else 0.0
         return np.where(self.stim_h, amp, 0.0)
 
-    def rhs(self, V, h, n):
-        """Step 1: the right-hand side Y (heart-first order)."""
-        Iion = ionic.i_ion(V, h, self.cm)
-        Y2 = self.mH * (self.gamma * V - self.chi * (Iion - self.i_stim(n)))
+    def rhs(self, V, h, n, U=None):
+        """Step 1: the right-hand side Y (heart-first order).  Crank-Nicolson
+        also needs U^n (heart-first order; constants do not matter, S_i 1 = 0)."""
+        src = ionic.i_ion(V, h, self.cm) - self.i_stim(n) if self.reaction else np.zeros(self.NH)
+        if self.scheme == "euler":
+            Y2 = self.mH * (self.gamma * V - self.chi * src)
+        else:
+            if U is None:
+                raise ValueError("the Crank-Nicolson right-hand side needs U^n")
+            Y2 = self.mH * (2.0 * self.gamma * V - 2.0 * self.chi * src) - self.Si @ (V + U[:self.NH])
         return np.concatenate([np.zeros(self.N), Y2])
 
     def gate(self, V, h):
         """Step 3, forward Euler on the old state."""
-        return h + self.dt * ionic.gate_rate(V, h)
+        return h + self.dt * ionic.gate_rate(V, h) if self.reaction else h
 
     # ---- normalisation (Prop. 1) ---------------------------------------
     def normalise(self, X):
@@ -165,8 +193,9 @@ class System:
 
     # ---- a full time step ------------------------------------------------
     def step(self, V, h, n, method="auto", U0=None):
-        """Advance (V^n, h^n) -> (U^{n+1}, V^{n+1}, h^{n+1})."""
-        Y = self.rhs(V, h, n)
+        """Advance (V^n, h^n) -> (U^{n+1}, V^{n+1}, h^{n+1}).  U0: U^n in
+        heart-first order (initial guess; required by Crank-Nicolson)."""
+        Y = self.rhs(V, h, n, U0)
         x0 = None
         if U0 is not None:
             x0 = np.concatenate([U0, V])

@@ -113,3 +113,53 @@ def test_gate_relaxation():
                 h = h + dt * ionic.gate_rate(np.array([V]), h)
             errs.append(abs(h[0] - exact(T)))
         assert errs[1] < 0.6 * errs[0] and errs[1] < 1e-3
+
+
+def _bump_state(s):
+    """A smooth transmembrane bump on the heart and the potential U that the
+    elliptic row (S_1 U + Pi^T S_i V = 0) gives it, normalised."""
+    xy = s.cfg["xyz"][s.hn]
+    c = xy.mean(axis=0)
+    V = 60.0 * np.exp(-np.sum((xy - c) ** 2, axis=1) / 4.0)
+    rhs = -(s.PiT @ (s.Si @ V))
+    U = np.linalg.lstsq(s.S1.toarray(), rhs, rcond=None)[0]
+    U -= (s.m @ U) / s.m.sum()
+    return U, V
+
+
+@pytest.mark.parametrize("scheme,order", [("euler", 1.0), ("cn", 2.0)])
+def test_time_scheme_orders(scheme, order):
+    """Without the reaction terms the problem is linear; from a smooth state
+    the backward-Euler scheme of Sec. 3.2 converges at order 1 in dt and the
+    Crank-Nicolson reading at order 2 (errors against a CN run at dt/16)."""
+    cfg = w.square2d(n=8)
+    T = 2.0
+
+    def run(dt, sch):
+        s = bd.System(cfg, dt=dt, scheme=sch, reaction=False)
+        U, V = _bump_state(s)
+        h = np.ones(s.NH)
+        for n in range(int(round(T / dt))):
+            U, V, h = s.step(V, h, n, method="dense", U0=U)
+        return V
+
+    ref = run(0.2 / 16, "cn")
+    errs = [np.linalg.norm(run(dt, scheme) - ref) for dt in (0.2, 0.1, 0.05)]
+    rates = [np.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    print(scheme, "errors", errs, "rates", rates)
+    assert all(abs(r - order) < 0.25 for r in rates), rates
+
+
+def test_cn_rest_and_constants():
+    """Crank-Nicolson keeps rest at rest, and a constant V with U = 0 (a
+    state the elliptic row admits) is stationary without reaction."""
+    cfg = w.square2d(n=12)
+    s = bd.System(cfg, scheme="cn")
+    U, V1, h1 = s.step(np.zeros(s.NH), np.ones(s.NH), n=10**6, U0=np.zeros(s.N))
+    assert np.abs(U).max() < 1e-13 and np.abs(V1).max() < 1e-13
+    lin = bd.System(cfg, scheme="cn", reaction=False)
+    c = 12.5
+    U, V1, _ = lin.step(np.full(lin.NH, c), np.ones(lin.NH), 0, U0=np.zeros(lin.N))
+    np.testing.assert_allclose(V1, c, rtol=1e-12)
+    assert np.abs(U).max() < 1e-10
+    assert abs(lin.gamma_eff - 2.0 * lin.gamma) < 1e-12 * lin.gamma
