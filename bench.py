@@ -36,6 +36,8 @@ def _parse():
     ap.add_argument("--eps", type=float, default=1e-8,
                     help="accuracy of the hierarchical top of the inner solves (0: exact)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--scheme", default="euler", choices=["euler", "cn"],
+                    help="time scheme: semi-implicit (Sec. 3.2) or Crank-Nicolson")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the sampled parity check")
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -132,7 +134,8 @@ def main():
     cfg = w.make_config(args.config)
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
     t_setup = time.perf_counter()
-    solver = B.Solver(cfg, tol=args.tol, eps_h=args.eps, precision=prec)
+    scheme = B.SCHEME_CN if args.scheme == "cn" else B.SCHEME_EULER
+    solver = B.Solver(cfg, tol=args.tol, eps_h=args.eps, precision=prec, scheme=scheme)
     t_setup = time.perf_counter() - t_setup
     tune = None if args.no_tune else solver.autotune()
     if args.graphs >= 0:
@@ -159,7 +162,7 @@ def main():
     last_state = None
     for n in range(n0, n0 + args.steps):
         if n == n0 + args.steps - 1:
-            last_state = [t.cpu().numpy().copy() for t in (v2, h2)]
+            last_state = [t.cpu().numpy().copy() for t in (v2, h2, u2)]
         solver.step(v2, h2, u2, n)
     prof = solver.profile_read()
     solver.profile(False)
@@ -186,7 +189,9 @@ def main():
         "config": {"workload": f"{cfg['name']}: " + (
                        f"2D thorax-like slice, {solver.N} vertices ({solver.NH} heart)" if cfg["dim"] == 2 else
                        f"3D orthotropic slab, {solver.N} vertices (isolated heart)") +
-                       f", semi-implicit bidomain step, block-LU/monodomain PCG, {args.precision} preconditioner",
+                       (", Crank-Nicolson" if args.scheme == "cn" else ", semi-implicit") +
+                       f" bidomain step, block-LU/monodomain PCG, {args.precision} preconditioner",
+                   "scheme": args.scheme,
                    "n_nodes": solver.N, "n_heart": solver.NH, "dt_ms": cfg["dt"],
                    "tol": args.tol, "eps_h": args.eps, "precision": args.precision,
                    "first_step": n0, "cg_iterations_per_step": round(iters / args.steps, 3),
@@ -202,8 +207,8 @@ def main():
 
     if not args.no_parity and last_state is not None:
         from oracle import bidomain as bd
-        s = bd.System(cfg)
-        Uo, Vo, _ = s.step(last_state[0], last_state[1], n0 + args.steps - 1)
+        s = bd.System(cfg, scheme=args.scheme)
+        Uo, Vo, _ = s.step(last_state[0], last_state[1], n0 + args.steps - 1, U0=s.from_global_u(last_state[2]))
         Uo = s.to_global_u(Uo)
         U, V = u2.cpu().numpy(), v2.cpu().numpy()
         result["parity"] = {"step": n0 + args.steps - 1,
@@ -211,7 +216,7 @@ def main():
                             "e_v": float(np.linalg.norm(V - Vo) / np.linalg.norm(Vo))}
 
     if not args.no_cpu:
-        result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_steps)
+        result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_steps, args.scheme)
 
     if not args.no_variants:
         result["variants"] = _variants(torch, B, solver, args)
@@ -272,6 +277,8 @@ def _bench_batch(args):
     """64 independent thorax-like slices (vertex counts log-uniform in
     [20k, 300k], seeded sites and conductivity scales) stepped together;
     the value is slice-steps per second of the whole batch."""
+    if args.scheme != "euler":
+        raise SystemExit("batch64 runs the semi-implicit scheme of its configuration (no --scheme)")
     import concurrent.futures as cf
 
     import numpy as np
@@ -363,19 +370,20 @@ def _bench_batch(args):
     print(json.dumps(result), flush=True)
 
 
-def _cpu_baseline(cfg, n_steps):
+def _cpu_baseline(cfg, n_steps, scheme="euler"):
     """Oracle steps from rest on the host (sparse direct solve per step)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import bidomain as bd
     with threadpool_limits(limits=1):
-        s = bd.System(cfg)
+        s = bd.System(cfg, scheme=scheme)
         V = np.zeros(s.NH)
         h = np.ones(s.NH)
+        U = np.zeros(s.N)
         t0 = time.perf_counter()
         for n in range(n_steps):
-            U, V, h = s.step(V, h, n)
+            U, V, h = s.step(V, h, n, U0=U)
         el = time.perf_counter() - t0
     return {"value": round(n_steps / el, 5), "unit": "steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_steps} steps of {cfg['name']} from rest (FP64 NumPy/SciPy oracle: "

@@ -104,7 +104,18 @@ typedef struct {
     int precond;       /* BIDO_PRECOND_*                                      */
     int ionic;         /* 0 = Mitchell-Schaeffer (one gate per vertex)       */
     int n_threads;     /* host threads for set-up; 0 = library default       */
+    int scheme;        /* BIDO_SCHEME_*: time discretisation                 */
 } bido_params;
+
+/* Time schemes.  EULER: the semi-implicit scheme of Sec. 3.2 (backward
+ * Euler on the diffusion, reaction explicit).  CN: Crank-Nicolson on the
+ * diffusion terms of the parabolic row with the reaction explicit (the
+ * remark on the time discretisation after Prop. 3: only Step 1 and K
+ * change): Lambda and K_m take 2 gamma instead of gamma, and Step 1 becomes
+ * Y_2 = M_H (2 gamma V^n - 2 chi (I_ion - I_st)) - S_i (V^n + Pi U^n), so a
+ * step reads U^n as well as V^n (both from the state arrays).            */
+#define BIDO_SCHEME_EULER 0
+#define BIDO_SCHEME_CN 1
 
 typedef struct {
     int iterations;        /* PCG iterations of the (last) solve            */
@@ -135,7 +146,7 @@ typedef struct {
 const char* bido_last_error(void);
 
 /* Fill *p with the defaults (chi 200, cm 1, dt 0.1, eps 1e-3, eta 2,
- * tol 1e-10, leaf 64, max_iter 200, FP64, plain, MS).                     */
+ * tol 1e-10, leaf 64, max_iter 200, FP64, plain, MS, semi-implicit Euler). */
 void bido_default_params(bido_params* p);
 
 /* Assemble S_1, S_i, S_m and the lumped M, M_H from the mesh (Sec. 3.1,

@@ -19,6 +19,7 @@ ERRORS = {-1: "BIDO_ERR_ARG", -2: "BIDO_ERR_DEVICE", -3: "BIDO_ERR_NOT_SPD",
           -6: "BIDO_ERR_RANGE", -7: "BIDO_ERR_STATE"}
 PREC_FP64, PREC_MIXED = 0, 1
 PRECOND_PLAIN, PRECOND_LEARNED, PRECOND_LEARNED_ADDITIVE = 0, 1, 2
+SCHEME_EULER, SCHEME_CN = 0, 1
 LEARN_STENCIL, LEARN_ADDITIVE = 0, 1
 MAT_S1, MAT_SI, MAT_SM, MAT_LAMBDA, MAT_GNN_AGG = 0, 1, 2, 3, 4
 VEC_M, VEC_MH, VEC_GNN_STATIC = 0, 1, 2
@@ -48,7 +49,8 @@ class Params(ctypes.Structure):
     _fields_ = [("chi", ctypes.c_double), ("cm", ctypes.c_double), ("dt", ctypes.c_double),
                 ("eps_h", ctypes.c_double), ("eta", ctypes.c_double), ("tol", ctypes.c_double),
                 ("leaf", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
-                ("precond", ctypes.c_int), ("ionic", ctypes.c_int), ("n_threads", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("ionic", ctypes.c_int), ("n_threads", ctypes.c_int),
+                ("scheme", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

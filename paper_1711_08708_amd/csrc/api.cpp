@@ -736,6 +736,7 @@ IonicConst ionic_consts(const bido_ctx* c) {
     k.inv_tau_open = 1.0 / 120.0;
     k.inv_tau_close = 1.0 / 150.0;
     k.v_gate = 0.13;
+    k.scale = c->params.scheme == BIDO_SCHEME_CN ? 2.0 : 1.0;
     return k;
 }
 
@@ -745,8 +746,22 @@ void step_prepare(bido_ctx* c, double* v, double* w, double* u, int64_t n) {
     const int64_t N = c->N, NH = c->NH;
     PROF(c, K_MISC, 24.0 * N, launch_scatter_in(s, N, c->u_pos, u, c->x));   // X0 = (U^n, V^n)
     const double on = (n >= c->hs.stim_n0 && n < c->hs.stim_n1) ? 1.0 : 0.0;
+    const double* sub = nullptr;
+    if (c->params.scheme == BIDO_SCHEME_CN) {
+        // Crank-Nicolson: S_i (V^n + Pi U^n) = (Lambda X^n)_v - 2 gamma M_H V^n,
+        // so Y_2 = 2 M_H (2 gamma V^n - chi (I_ion - I_st)) - (Lambda X^n)_v
+        // with 2 gamma the coefficient of M_H in Lambda
+        PROF(c, K_MISC, 24.0 * NH, launch_scatter_in(s, NH, c->v_pos, v, c->x + N));
+        CsrDev rows = c->lam;                    // the v rows of Lambda
+        rows.n = NH;
+        rows.ptr = c->lam.ptr + N;
+        rows.nnz = c->hs.lam.ptr[c->n2] - c->hs.lam.ptr[N];
+        PROF(c, K_SPMV_CSR, csr_bytes(rows, c->n2),
+             launch_spmv_csr(s, rows, c->spmv_group, c->x, nullptr, c->tB));
+        sub = c->tB;
+    }
     PROF(c, K_IONIC, 64.0 * NH,
-         launch_ionic(s, NH, v, w, c->stim_loc, on, c->mh_loc, c->v_pos, c->Y + N, c->x + N,
+         launch_ionic(s, NH, v, w, c->stim_loc, on, c->mh_loc, c->v_pos, c->Y + N, c->x + N, sub,
                       ionic_consts(c)));                               // Steps 1 and 3
     PROF(c, K_MISC, 8.0 * N, launch_fill(s, N, c->Y, 0.0));           // Y1 = 0
 }
@@ -1191,6 +1206,7 @@ void bido_default_params(bido_params* p) {
     p->precond = BIDO_PRECOND_PLAIN;
     p->ionic = 0;
     p->n_threads = 0;
+    p->scheme = BIDO_SCHEME_EULER;
 }
 
 bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const bido_params* params,

@@ -130,14 +130,15 @@ __global__ void k_shift(int64_t n, double* x, const double* sc, int slot, double
 __global__ void k_ionic_rhs(int64_t nh, const double* __restrict__ v, double* __restrict__ h,
                             const double* __restrict__ stim, double stim_on,
                             const double* __restrict__ mh, const int64_t* __restrict__ pos,
-                            double* __restrict__ y2, double* __restrict__ x2, IonicConst c) {
+                            double* __restrict__ y2, double* __restrict__ x2,
+                            const double* __restrict__ sub, IonicConst c) {
     for (int64_t k = blockIdx.x * (int64_t)BLOCK + threadIdx.x; k < nh; k += (int64_t)gridDim.x * BLOCK) {
         const double V = v[k], hk = h[k];
         const double vt = V * c.inv_dv;
         const double iion = c.cm * c.dv * (-hk * vt * vt * (1.0 - vt) * c.inv_tau_in + vt * c.inv_tau_out);
         const double ist = stim[k] * stim_on;
         const int64_t p = pos[k];
-        y2[p] = mh[k] * (c.gamma * V - c.chi * (iion - ist));
+        y2[p] = c.scale * mh[k] * (c.gamma * V - c.chi * (iion - ist)) - (sub ? sub[p] : 0.0);
         x2[p] = V;
         const double g = (vt < c.v_gate) ? (1.0 - hk) * c.inv_tau_open : -hk * c.inv_tau_close;
         h[k] = hk + c.dt * g;
@@ -1076,9 +1077,9 @@ void launch_shift(hipStream_t s, int64_t n, double* x, const double* sc, int slo
 }
 void launch_ionic(hipStream_t s, int64_t nh, const double* v, double* h, const double* stim,
                   double stim_on, const double* mh, const int64_t* pos, double* y2, double* x2,
-                  const IonicConst& c) {
+                  const double* sub, const IonicConst& c) {
     if (nh <= 0) return;
-    k_ionic_rhs<<<grid_for(nh), BLOCK, 0, s>>>(nh, v, h, stim, stim_on, mh, pos, y2, x2, c);
+    k_ionic_rhs<<<grid_for(nh), BLOCK, 0, s>>>(nh, v, h, stim, stim_on, mh, pos, y2, x2, sub, c);
 }
 
 unsigned launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode, const double* x,

@@ -25,6 +25,7 @@ struct Reduce {
 struct IonicConst {
     double gamma, chi, cm, dt;
     double dv, inv_dv, inv_tau_in, inv_tau_out, inv_tau_open, inv_tau_close, v_gate;
+    double scale;   // 1 (semi-implicit), 2 (Crank-Nicolson: the system times 2)
 };
 
 // Execution plan of one factor's sweeps: the subtrees below the cut height
@@ -93,9 +94,11 @@ void launch_gather_out(hipStream_t s, int64_t n, const int64_t* pos, const doubl
                        const double* sc, int shift_slot, double shift_den);
 void launch_dot_reduce(hipStream_t s, int64_t n, const double* a, const double* b, Reduce rd, double* out);
 void launch_shift(hipStream_t s, int64_t n, double* x, const double* sc, int slot, double den);
+// y2[pos] = scale M_H (gamma V - chi (I_ion - I_st)) - sub[pos] (sub may be
+// null), x2[pos] = V, gates advanced
 void launch_ionic(hipStream_t s, int64_t nh, const double* v, double* h, const double* stim,
                   double stim_on, const double* mh, const int64_t* pos, double* y2, double* x2,
-                  const IonicConst& c);
+                  const double* sub, const IonicConst& c);
 // Each returns its grid size: the number of block partials it wrote.
 unsigned launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode, const double* x,
                             const double* y, double* out, double* pp);

@@ -133,6 +133,7 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
     if (P.ionic != 0) { err = "only the Mitchell-Schaeffer model (ionic = 0) is built in"; return false; }
     if (P.precision != BIDO_PREC_FP64 && P.precision != BIDO_PREC_MIXED) { err = "bad precision"; return false; }
     if (P.precond != BIDO_PRECOND_PLAIN && P.precond != BIDO_PRECOND_LEARNED) { err = "bad precond"; return false; }
+    if (P.scheme != BIDO_SCHEME_EULER && P.scheme != BIDO_SCHEME_CN) { err = "bad time scheme"; return false; }
 #ifdef _OPENMP
     if (P.n_threads > 0) omp_set_num_threads(P.n_threads);
 #endif
@@ -152,7 +153,9 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
     const Assembled& A = hs.A;
     const int64_t N = A.N, NH = A.NH;
     const int d = A.dim;
-    hs.gamma = P.chi * P.cm / P.dt;
+    // the coefficient of M_H in Lambda and K_m: gamma = chi cm / dt for the
+    // semi-implicit scheme, 2 gamma for Crank-Nicolson (the system times 2)
+    hs.gamma = P.chi * P.cm / P.dt * (P.scheme == BIDO_SCHEME_CN ? 2.0 : 1.0);
 
     // orderings: nested dissection of S_1 (u) and of K_m (v)
     nested_dissection(A.S1, mesh->xyz, d, P.leaf, hs.p1.tree);

@@ -111,10 +111,10 @@ def test_graph_replays_match_eager_launches(torch, precision):
         assert np.array_equal(a, b)
 
 
-def _single_runs(B, cfgs, prec, n_steps):
+def _single_runs(B, cfgs, prec, n_steps, **kw):
     out = []
     for cfg in cfgs:
-        s = B.Solver(cfg, tol=1e-12, precision=prec)
+        s = B.Solver(cfg, tol=1e-12, precision=prec, **kw)
         s.set_graphs(False)
         v, h, u = s.state()
         its = [s.step(v, h, u, n)["iterations"] for n in range(n_steps)]
@@ -224,3 +224,22 @@ def test_fused_batch_refusals(torch):
     a.run(v, h, u, 0, 2)
     a.close()
     b.close()
+
+
+def test_fused_batch_crank_nicolson(torch):
+    """A fused batch of Crank-Nicolson slices follows each slice run alone."""
+    import paper_1711_08708_amd as B
+    cfgs = _slices()[:3]
+    n_steps = 8
+    ref = _single_runs(B, cfgs, B.PREC_FP64, n_steps, scheme=B.SCHEME_CN)
+    solvers = [B.Solver(cfg, tol=1e-12, scheme=B.SCHEME_CN) for cfg in cfgs]
+    batch = B.Batch(solvers, fused=True)
+    states = [s.state() for s in solvers]
+    its = [[p["iterations"] for p in batch.run(states, n, 1)[1]] for n in range(n_steps)]
+    for k, st in enumerate(states):
+        print(k, "iterations fused", [row[k] for row in its], "alone", ref[k][1])
+        for a, b in zip([t.cpu().numpy() for t in st], ref[k][0]):
+            assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b), k
+    batch.close()
+    for s in solvers:
+        s.close()

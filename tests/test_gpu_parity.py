@@ -125,6 +125,34 @@ def test_step_trajectory_square48(torch):
     print("square48 worst per-step error", worst)
 
 
+@pytest.mark.parametrize("mk,eps,n_steps", [(lambda: w.make_config("square48"), 0.0, 20),
+                                             (lambda: w.thorax2d(n_target=3000, seed=11), 1e-8, 12)],
+                         ids=["square48", "thorax3000"])
+def test_crank_nicolson_trajectory(torch, mk, eps, n_steps):
+    """Crank-Nicolson steps (Lambda and K_m with 2 gamma; Step 1 reads U^n
+    through the v rows of Lambda): every step's U^{n+1}, V^{n+1} match the
+    oracle's Crank-Nicolson step from the same U^n, V^n, h^n."""
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd
+    cfg = mk()
+    s = bd.System(cfg, scheme="cn")
+    solver = B.Solver(cfg, eps_h=eps, tol=1e-12, scheme=B.SCHEME_CN)
+    v, h, u = solver.state()
+    worst = 0.0
+    for n in range(n_steps):
+        Vn = v.cpu().numpy().copy()
+        hn = h.cpu().numpy().copy()
+        Un = s.from_global_u(u.cpu().numpy())
+        st = solver.step(v, h, u, n)
+        assert st["converged"] == 1
+        Uo_p, Vo, ho = s.step(Vn, hn, n, U0=Un)
+        eu, ev = _errs(u.cpu().numpy(), v.cpu().numpy(), s.to_global_u(Uo_p), Vo)
+        worst = max(worst, eu, ev)
+        assert eu <= TOL_PARITY and ev <= TOL_PARITY, (n, eu, ev)
+        assert np.abs(h.cpu().numpy() - ho).max() <= 1e-14
+    print(cfg["name"], "Crank-Nicolson worst per-step error", worst, "iterations", st["iterations"])
+
+
 def test_thorax200k_solve_parity(torch):
     """Full-size thorax slice (about 200k vertices): the normalised solution
     of one step's system matches the oracle's sparse direct solve."""
