@@ -1418,18 +1418,16 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
         Factor m;
         merge_factors(f1, o, n, m);
         for (int i = 0; i < S; ++i) m.part_top_h[i] = ctxs[i]->p1.top_h;
-        const char* es = std::getenv("BIDO_FUSED_SUB_H");
-        const int sub_h = es && *es ? std::atoi(es) : -1;
         PlanOptions op = ctxs[big]->p1.opts;
         op.top_h = -1;
-        op.sub_h = sub_h;
+        op.sub_h = -1;
         if ((e = build_factor_dev(m, want32, F->p1, nth, &op))) return e;
         m = Factor();
         merge_factors(fk, ov, n, m);
         for (int i = 0; i < S; ++i) m.part_top_h[i] = ctxs[i]->pk.top_h;
         op = ctxs[big]->pk.opts;
         op.top_h = -1;
-        op.sub_h = sub_h;
+        op.sub_h = -1;
         if ((e = build_factor_dev(m, want32, F->pk, nth, &op))) return e;
     }
     {

@@ -32,14 +32,15 @@ struct Ea {
 
 // Forward work item of one level above the subtree cut: rows
 // [r0, r0+nrows) (nrows <= 64) of the panel of `node`, columns [cs, ce).
-// Items that split a row tile's columns write 64 partial sums each; the last
-// one to finish sums the parts in order and stores the rows.
+// Items that split a row tile's columns write 64 partial sums each to
+// scratch; the combine launch after the level sums the parts in order and
+// stores the rows.
 struct TriItem {
     int32_t node;
     int32_t r0, nrows;
     int32_t cs, ce;
     int32_t nparts;      // items of this row tile
-    int32_t tile;        // completion counter of the tile
+    int32_t tile;        // index of the tile (plan bookkeeping)
     int32_t pad;
     int64_t part;        // scratch offset of this item's partial sums
     int64_t part0;       // scratch offset of the tile's first part
@@ -47,14 +48,14 @@ struct TriItem {
 
 // Backward work item of one level above the subtree cut: columns
 // [c0, c0+ncols) of the panel of `node`, rows [rs, re).  Items that share a
-// column tile write W partial sums each; the last one to finish sums the
-// parts in order (deterministic) and writes x.
+// column tile write W partial sums each to scratch; the combine launch after
+// the level sums the parts in order (deterministic) and writes x.
 struct BwdItem {
     int32_t node;
     int32_t c0, ncols, W;
     int32_t rs, re;
     int32_t nparts;      // items of this column tile
-    int32_t tile;        // completion counter of the tile
+    int32_t tile;        // index of the tile (plan bookkeeping)
     int64_t part;        // scratch offset of this item's partial sums
     int64_t part0;       // scratch offset of the tile's first part
 };

@@ -1,13 +1,18 @@
 // HIP kernels for gfx950 (CDNA4, 64-lane wavefronts).
 //
-//   tri_fwd / tri_bwd   level sweeps of the hierarchical-Cholesky solves
-//                       (inner solves P_1^-1, P_K^-1 of Def. 2, Sec. 5.3)
+//   tri_*               sweeps of the multifrontal Cholesky inner solves
+//                       P_1^-1, P_K^-1 (Def. 2, Sec. 5.3): subtree phase,
+//                       level phases with their combine launches, top
+//                       (dense or hierarchical inverse of the top Schur
+//                       complement)
 //   spmv_*              Lambda products (Sec. 3.2, eq. (system)) and the
 //                       S_i Pi / Pi^T S_i products of the preconditioner
-//   pcg_*               FP64 CG recurrences with fused, deterministic dot
-//                       products (the last block reduces the partials)
+//   pcg_*, p_update,    FP64 CG recurrences; each reduction leaves one partial
+//   combine_dot         per block and the kernel that needs the total sums
+//                       the partials itself, in a fixed order (no fences)
 //   ionic_rhs           Steps 1 and 3 of the resolution algorithm
-//   mean_*              normalisation (M U, 1) = 0 of Prop. 1
+//   dot_reduce,         normalisation (M U, 1) = 0 of Prop. 1 (the last
+//   gather_out          block reduces: once per step)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

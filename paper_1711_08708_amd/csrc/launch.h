@@ -15,7 +15,7 @@ struct CsrDev {
     double* val = nullptr;
 };
 
-// partial-sum scratch of the fused reductions (last block reduces)
+// partial-sum scratch of k_dot_reduce (the last block reduces)
 struct Reduce {
     double* partials = nullptr;   // 2 * max_blocks doubles
     unsigned* counter = nullptr;
