@@ -243,3 +243,36 @@ def test_fused_batch_crank_nicolson(torch):
     batch.close()
     for s in solvers:
         s.close()
+
+
+def test_fused_batch64_sampled_slices_full_size(torch):
+    """batch64 at full size, in the fused configuration the bench times: the
+    smallest and the largest of its 64 slices plus two others (one of them
+    with a heart in two parts), 3 steps in one fused batch, each slice's last
+    step against the FP64 oracle at 1e-8."""
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd
+    kws = w.make_config("batch64")
+    sizes = [kw["n_target"] for kw in kws]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 20})
+    cfgs = [w.thorax2d(**kws[k]) for k in pick]
+    solvers = [B.Solver(cfg, tol=1e-10, eps_h=1e-8) for cfg in cfgs]
+    batch = B.Batch(solvers, fused=True)
+    states = [s.state() for s in solvers]
+    batch.run(states, 0, 2)
+    before = [(st[0].cpu().numpy().copy(), st[1].cpu().numpy().copy()) for st in states]
+    tot, per = batch.run(states, 2, 1)
+    assert tot["converged"] == 1
+    for k, (cfg, st) in enumerate(zip(cfgs, states)):
+        sy = bd.System(cfg)
+        Uo, Vo, _ = sy.step(before[k][0], before[k][1], 2)
+        Uo = sy.to_global_u(Uo)
+        u, v = st[2].cpu().numpy(), st[0].cpu().numpy()
+        eu = np.linalg.norm(u - Uo) / np.linalg.norm(Uo)
+        ev = np.linalg.norm(v - Vo) / np.linalg.norm(Vo)
+        print(f"  batch64 slice {pick[k]} ({cfg['name']}): iterations {per[k]['iterations']} "
+              f"e_u {eu:.2e} e_v {ev:.2e}")
+        assert eu <= 1e-8 and ev <= 1e-8
+    batch.close()
+    for s in solvers:
+        s.close()
