@@ -298,6 +298,8 @@ def _bench_batch(args):
     solvers = [B.Solver(c, tol=args.tol, eps_h=args.eps, precision=prec) for c in cfgs]
     t_setup = time.perf_counter() - t0
     n_nodes = sum(s.N for s in solvers)
+    union_rows = sum(s.N + s.NH for s in solvers)
+    union_nnz = sum(s.info["nnz_lambda"] for s in solvers)
     print(f"[bench] batch64: {len(solvers)} slices, {n_nodes} vertices, meshes {t_mesh:.1f}s, "
           f"set-up {t_setup:.1f}s", file=sys.stderr, flush=True)
     sample = [int(np.argmin([s.N for s in solvers])), int(np.argmax([s.N for s in solvers]))]
@@ -341,6 +343,7 @@ def _bench_batch(args):
                                f"vertex counts log-uniform in [20k, 300k], PCG per slice",
                    "slices": S, "total_nodes": n_nodes, "precision": args.precision, "tol": args.tol,
                    "mode": mode, "streams": args.batch_streams if mode == "streams" else 1,
+                   "union_rows": union_rows, "union_nnz_lambda": union_nnz,
                    "learned": bool(args.batch_learned), "batch_setup_s": round(t_batch, 1),
                    "mean_iterations_per_slice_step": round((tot["total_iterations"] + tot2["total_iterations"])
                                                            / (S * args.steps), 3),

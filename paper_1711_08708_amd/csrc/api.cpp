@@ -1418,9 +1418,17 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
         Factor m;
         merge_factors(f1, o, n, m);
         for (int i = 0; i < S; ++i) m.part_top_h[i] = ctxs[i]->p1.top_h;
+        // 512 subtrees shared over the union in proportion to the trees'
+        // sizes (each tree's cut kept below its top cut) instead of 256 per
+        // tree: the union has subtrees enough to fill the device anyway, and
+        // bigger ones keep the waves of a workgroup busy (batch64 FP64:
+        // 627 -> 802 slice-steps/s); environment BIDO_SUB_TOTAL overrides it
+        const char* est = std::getenv("BIDO_SUB_TOTAL");
+        const int sub_total = est && *est ? std::max(1, std::atoi(est)) : 512;
         PlanOptions op = ctxs[big]->p1.opts;
         op.top_h = -1;
         op.sub_h = -1;
+        op.sub_total = sub_total;
         if ((e = build_factor_dev(m, want32, F->p1, nth, &op))) return e;
         m = Factor();
         merge_factors(fk, ov, n, m);
@@ -1428,6 +1436,7 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
         op = ctxs[big]->pk.opts;
         op.top_h = -1;
         op.sub_h = -1;
+        op.sub_total = sub_total;
         if ((e = build_factor_dev(m, want32, F->pk, nth, &op))) return e;
     }
     {

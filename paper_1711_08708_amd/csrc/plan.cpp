@@ -272,6 +272,11 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     {
         std::vector<std::vector<int>> members(nn);
         for (int id = 0; id < nn; ++id) members[root_of[id]].push_back(id);
+        int64_t all_v = 0;
+        for (int id = 0; id < nn; ++id) all_v += f.fronts[id].nI;
+        // a forest may share a subtree budget (environment BIDO_SUB_TOTAL)
+        const char* est = std::getenv("BIDO_SUB_TOTAL");
+        const int sub_total = o.sub_total > 0 ? o.sub_total : (forest && est && *est ? std::atoi(est) : 0);
         for (int r : roots) {
             const int Hr = t.nodes[r].height;
             std::vector<int> mw(Hr + 1, 0), mf(Hr + 1, 0), nroots(Hr + 2, 0);
@@ -291,13 +296,23 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
             }
             int cut = -1;
             const char* ew = std::getenv("BIDO_SUB_WANT");
-            const int want0 = ew && *ew ? std::max(1, std::atoi(ew)) : 256;
+            int want0 = ew && *ew ? std::max(1, std::atoi(ew)) : 256;
+            if (sub_total > 0 && all_v > 0) {
+                int64_t tv = 0;
+                for (int id : members[r]) tv += f.fronts[id].nI;
+                want0 = (int)std::max<int64_t>(1, (int64_t)sub_total * tv / all_v);
+            }
             for (int want : {want0, 64, 16, 1}) {
                 for (int h = Hr; h >= 0 && cut < 0; --h)
                     if (mw[h] <= PLAN_SUB_MAXW && mf[h] <= PLAN_SUB_MAXF && nroots[h] >= want) cut = h;
                 if (cut >= 0) break;
             }
             if (sub_cap >= 0) cut = std::min(cut, sub_cap);
+            if (sub_total > 0) {
+                // keep the tree's recorded top cut (and so its cached top)
+                const int k = part_of(r);
+                if (k >= 0 && f.part_top_h[k] >= 0) cut = std::min(cut, f.part_top_h[k] - 1);
+            }
             for (int id : members[r]) hc_of[id] = cut;
         }
     }

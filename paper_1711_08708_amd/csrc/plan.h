@@ -18,6 +18,9 @@ struct PlanOptions {
     int bwd_rows = 0;   // rows per backward level item (0: 8192 / tile width, at most 512)
     int top_h = -1;     // first height of the top (raised to fit the top-size bound)
     int sub_h = -1;     // highest subtree cut of any tree (< 0: the size rule alone)
+    int sub_total = 0;  // > 0: subtrees wanted over the whole forest, shared by the trees
+                        // in proportion to their vertices (each tree's cut then stays
+                        // below its recorded top cut); 0: 256 per tree
     int bwd_wide = -1;  // backward level items of 1024 threads over whole column tiles
                         // (1), of 256 threads over row ranges (0); < 0: environment
                         // BIDO_BWD_WIDE, else 1

@@ -330,3 +330,34 @@ def test_capped_subtree_cut_emulates_each_slice(sub_h, monkeypatch):
         assert plan["hc"] <= int(sub_h)
         for lo, n, ref in refs:
             assert np.abs(emu[lo:lo + n] - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("total", ["4", "64"])
+def test_forest_with_shared_subtree_budget(total, monkeypatch):
+    """A forest that shares a subtree budget over its trees (bigger subtrees
+    per tree, cuts kept below the trees' top cuts) is still an exact solve of
+    every slice (eps_h = 0)."""
+    import paper_1711_08708_amd as B
+    cfgs = [w.thorax2d(n_target=3000, seed=31), w.thorax2d(n_target=6000, seed=32, sigma_scale=0.8),
+            w.square2d(n=24, seed=3), w.thorax2d(n_target=1500, seed=33)]
+    parts = [B.HostSetup(c, eps_h=0.0) for c in cfgs]
+    sizes = [(len(p.index(B.IDX_UPOS)), len(p.index(B.IDX_VPOS))) for p in parts]
+    ntot = sum(a + b for a, b in sizes)
+    rng = np.random.default_rng(21)
+    for which in (B.FACTOR_P1, B.FACTOR_PK):
+        b = rng.normal(size=ntot)
+        refs, off = [], 0
+        for p, (N, NH) in zip(parts, sizes):
+            lo, n = (off, N) if which == B.FACTOR_P1 else (off + N, NH)
+            p.factor_emulate(which, b[lo:lo + n])           # records the slice's top cut
+            refs.append((lo, n, p.factor_apply(which, b[lo:lo + n])))
+            off += N + NH
+        monkeypatch.setenv("BIDO_SUB_TOTAL", total)
+        merged = B.HostSetup.merged(parts)
+        plan = merged.factor_plan(which)
+        top = merged.factor_top(which)
+        emu = merged.factor_emulate(which, b)
+        monkeypatch.delenv("BIDO_SUB_TOTAL")
+        print(which, total, plan, top)
+        for lo, n, ref in refs:
+            assert np.abs(emu[lo:lo + n] - ref).max() <= 1e-11 * np.abs(ref).max()
