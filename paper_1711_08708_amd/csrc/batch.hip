@@ -8,6 +8,7 @@
 
 #include "kernels.h"
 #include "launch.h"
+#include "rows.h"
 
 namespace bido {
 namespace {
@@ -37,12 +38,6 @@ __device__ __forceinline__ double slice_sum(const double* __restrict__ part, int
     return bsum(s, sh);
 }
 
-template <int G>
-__device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-    return v;
-}
 
 // mode 0: q = A p, partials p.q;  mode 1: r = y - A x, partials |r|^2, |y|^2
 template <int G, int MODE>
@@ -54,23 +49,36 @@ __global__ __launch_bounds__(BB) void k_seg_spmv(SegTable T, const int64_t* __re
     __shared__ double sh[BB / BW];
     const SegBlock bk = T.blk[blockIdx.x];
     if (done && done[bk.slice]) return;
+    constexpr int RU = SPMV_RU, NG = BB / G;
     const int64_t r0 = bk.r0, r1 = bk.r1;
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
     double acc0 = 0.0, acc1 = 0.0;
-    for (int64_t r = r0 + grp; r < r1; r += BB / G) {
-        double s = 0.0;
-        for (int64_t q = ptr[r] + lane; q < ptr[r + 1]; q += G) s += val[q] * x[col[q]];
-        s = gsum<G>(s);
+    for (int64_t rb = r0 + grp; rb < r1; rb += RU * NG) {
+        int64_t row[RU];
+        bool ok[RU];
+        double own[RU];   // x[row] (p.q) or y[row] (residual), loaded with the rows
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            row[u] = rb + u * NG;
+            ok[u] = row[u] < r1;
+            own[u] = (MODE == 0 ? x : y)[ok[u] ? row[u] : rb];
+        }
+        double s[RU];
+        csr_rows<G, RU>(ptr, col, val, x, row, ok, lane, s);
         if (lane == 0) {
-            if (MODE == 0) {
-                out[r] = s;
-                acc0 += s * x[r];
-            } else {
-                const double rv = y[r] - s;
-                out[r] = rv;
-                acc0 += rv * rv;
-                acc1 += y[r] * y[r];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (!ok[u]) continue;
+                if (MODE == 0) {
+                    out[row[u]] = s[u];
+                    acc0 += s[u] * own[u];
+                } else {
+                    const double rv = own[u] - s[u];
+                    out[row[u]] = rv;
+                    acc0 += rv * rv;
+                    acc1 += own[u] * own[u];
+                }
             }
         }
     }
@@ -90,12 +98,25 @@ __global__ __launch_bounds__(BB) void k_seg_csr(SegTable T, const int64_t* __res
                                                 double* __restrict__ y, const uint8_t* __restrict__ done) {
     const SegBlock bk = T.blk[blockIdx.x];
     if (done && done[bk.slice]) return;
+    constexpr int RU = SPMV_RU, NG = BB / G;
     const int lane = threadIdx.x % G;
-    for (int64_t r = bk.r0 + threadIdx.x / G; r < bk.r1; r += BB / G) {
-        double s = 0.0;
-        for (int64_t q = ptr[r] + lane; q < ptr[r + 1]; q += G) s += val[q] * x[col[q]];
-        s = gsum<G>(s);
-        if (lane == 0) y[r] = b ? b[r] - s : s;
+    for (int64_t rb = bk.r0 + threadIdx.x / G; rb < bk.r1; rb += RU * NG) {
+        int64_t row[RU];
+        bool ok[RU];
+        double bv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            row[u] = rb + u * NG;
+            ok[u] = row[u] < bk.r1;
+            bv[u] = b ? b[ok[u] ? row[u] : rb] : 0.0;
+        }
+        double s[RU];
+        csr_rows<G, RU>(ptr, col, val, x, row, ok, lane, s);
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+                if (ok[u]) y[row[u]] = b ? bv[u] - s[u] : s[u];
+        }
     }
 }
 

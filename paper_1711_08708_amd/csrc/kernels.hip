@@ -20,6 +20,7 @@
 
 #include "kernels.h"
 #include "launch.h"
+#include "rows.h"
 
 namespace bido {
 
@@ -153,12 +154,6 @@ __global__ void k_ionic_rhs(int64_t nh, const double* __restrict__ v, double* __
 // ---------------------------------------------------------------------------
 // Lambda products.  Rows handled by groups of G lanes.
 // ---------------------------------------------------------------------------
-template <int G>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
 
 // mode 0: q = A p, block partial of p.q            (region PP_PQ)
 // mode 1: r = y - A x, block partials of |r|^2, |y|^2 (PP_RR, PP_YY)
@@ -170,23 +165,36 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lambda(int64_t n, const int64_t*
                                                        const double* __restrict__ y,
                                                        double* __restrict__ out, double* __restrict__ pp) {
     __shared__ double sh[BLOCK / WAVE];
+    constexpr int RU = SPMV_RU;
     const int lane = threadIdx.x % G;
     const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
     const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
     double acc0 = 0.0, acc1 = 0.0;
-    for (int64_t r = gid; r < n; r += ngroups) {
-        double s = 0.0;
-        for (int64_t p = ptr[r] + lane; p < ptr[r + 1]; p += G) s += val[p] * x[col[p]];
-        s = group_sum<G>(s);
+    for (int64_t rb = gid; rb < n; rb += RU * ngroups) {
+        int64_t row[RU];
+        bool ok[RU];
+        double own[RU];   // x[row] (p.q) or y[row] (residual), loaded with the rows
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            row[u] = rb + u * ngroups;
+            ok[u] = row[u] < n;
+            own[u] = (MODE == 0 ? x : y)[ok[u] ? row[u] : rb];
+        }
+        double s[RU];
+        csr_rows<G, RU>(ptr, col, val, x, row, ok, lane, s);
         if (lane == 0) {
-            if (MODE == 0) {
-                out[r] = s;
-                acc0 += s * x[r];
-            } else {
-                const double rv = y[r] - s;
-                out[r] = rv;
-                acc0 += rv * rv;
-                acc1 += y[r] * y[r];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (!ok[u]) continue;
+                if (MODE == 0) {
+                    out[row[u]] = s[u];
+                    acc0 += s[u] * own[u];
+                } else {
+                    const double rv = own[u] - s[u];
+                    out[row[u]] = rv;
+                    acc0 += rv * rv;
+                    acc1 += own[u] * own[u];
+                }
             }
         }
     }
@@ -202,7 +210,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lambda(int64_t n, const int64_t*
     }
 }
 
-// y = b - A x  (b may be null: y = A x), rows of a CSR block
+// y = b - A x  (b may be null: y = A x), rows of a CSR block (one row per
+// group at a time: Pi^T S_i has mostly empty rows, the torso vertices)
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_spmv_csr(int64_t n, const int64_t* __restrict__ ptr,
                                                     const int32_t* __restrict__ col,
@@ -216,7 +225,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_csr(int64_t n, const int64_t* __
     for (int64_t r = gid; r < n; r += ngroups) {
         double s = 0.0;
         for (int64_t p = ptr[r] + lane; p < ptr[r + 1]; p += G) s += val[p] * x[col[p]];
-        s = group_sum<G>(s);
+        s = lane_group_sum<G>(s);
         if (lane == 0) y[r] = b ? b[r] - s : s;
     }
 }
