@@ -38,6 +38,10 @@ def _parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--scheme", default="euler", choices=["euler", "cn"],
                     help="time scheme: semi-implicit (Sec. 3.2) or Crank-Nicolson")
+    ap.add_argument("--pk", default="cholesky", choices=["cholesky", "chebyshev"],
+                    help="P_K inside the block-LU preconditioner: the factor of K_m, or "
+                         "Chebyshev-accelerated Jacobi steps on K_m")
+    ap.add_argument("--pk-steps", type=int, default=3, help="Chebyshev steps of --pk chebyshev")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the sampled parity check")
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -138,6 +142,8 @@ def main():
     solver = B.Solver(cfg, tol=args.tol, eps_h=args.eps, precision=prec, scheme=scheme)
     t_setup = time.perf_counter() - t_setup
     tune = None if args.no_tune else solver.autotune()
+    if args.pk == "chebyshev":
+        solver.set_pk(B.PK_CHEBYSHEV, args.pk_steps)
     if args.graphs >= 0:
         solver.set_graphs(bool(args.graphs))
     info = solver.info
@@ -190,8 +196,9 @@ def main():
                        f"2D thorax-like slice, {solver.N} vertices ({solver.NH} heart)" if cfg["dim"] == 2 else
                        f"3D orthotropic slab, {solver.N} vertices (isolated heart)") +
                        (", Crank-Nicolson" if args.scheme == "cn" else ", semi-implicit") +
-                       f" bidomain step, block-LU/monodomain PCG, {args.precision} preconditioner",
-                   "scheme": args.scheme,
+                       f" bidomain step, block-LU/monodomain PCG, {args.precision} preconditioner" +
+                       (f", Chebyshev P_K ({args.pk_steps} steps)" if args.pk == "chebyshev" else ""),
+                   "scheme": args.scheme, "pk": solver.pk(),
                    "n_nodes": solver.N, "n_heart": solver.NH, "dt_ms": cfg["dt"],
                    "tol": args.tol, "eps_h": args.eps, "precision": args.precision,
                    "first_step": n0, "cg_iterations_per_step": round(iters / args.steps, 3),
@@ -224,11 +231,12 @@ def main():
 
 
 def _variants(torch, B, solver, args):
-    """Plain FP64 vs mixed vs learned vs learned+mixed on the same steps.
+    """Plain FP64 vs mixed vs learned vs learned+mixed on the same steps, and
+    the factored P_K against the Chebyshev one (FP64 and mixed).
 
     The learned Schur-complement stencil is trained on pairs recorded during
     the first `collect_steps` plain steps from rest and K_m + C is factored;
-    all four variants then run the following `variant_steps` steps from the
+    every variant then runs the following `variant_steps` steps from the
     same saved state."""
     out = {}
     v, h, u = solver.state()
@@ -248,13 +256,18 @@ def _variants(torch, B, solver, args):
                        "loss_val": round(ts["loss_val"], 3)}
     saved = [t.clone() for t in (v, h, u)]
     n1 = args.collect_steps
-    runs = [("plain_fp64", B.PREC_FP64, B.PRECOND_PLAIN), ("mixed", B.PREC_MIXED, B.PRECOND_PLAIN)]
+    main_pk = solver.pk()
+    chol, cheb = B.PK_CHOLESKY, B.PK_CHEBYSHEV
+    runs = [("plain_fp64", B.PREC_FP64, B.PRECOND_PLAIN, chol), ("mixed", B.PREC_MIXED, B.PRECOND_PLAIN, chol),
+            ("chebyshev_pk_fp64", B.PREC_FP64, B.PRECOND_PLAIN, cheb),
+            ("chebyshev_pk_mixed", B.PREC_MIXED, B.PRECOND_PLAIN, cheb)]
     if ts["spd"]:
-        runs += [("learned_fp64", B.PREC_FP64, B.PRECOND_LEARNED),
-                 ("learned_mixed", B.PREC_MIXED, B.PRECOND_LEARNED)]
-    for name, prec, pc in runs:
+        runs += [("learned_fp64", B.PREC_FP64, B.PRECOND_LEARNED, chol),
+                 ("learned_mixed", B.PREC_MIXED, B.PRECOND_LEARNED, chol)]
+    for name, prec, pc, pk in runs:
         solver.set_precision(prec)
         solver.set_precond(pc)
+        solver.set_pk(pk, args.pk_steps)
         st = [t.clone() for t in saved]
         _, ws, it = _timed_steps(torch, solver, st, n1, args.variant_steps)
         out[name] = {"steps_per_s": round(args.variant_steps / ws, 3),
@@ -263,8 +276,10 @@ def _variants(torch, B, solver, args):
     for name in [r[0] for r in runs[1:]]:
         out[name]["speedup_vs_plain"] = round(out[name]["steps_per_s"] / base, 3)
     out["steps"] = [n1, n1 + args.variant_steps]
+    out["chebyshev_pk_steps"] = args.pk_steps
     solver.set_precision(B.PREC_FP64)
     solver.set_precond(B.PRECOND_PLAIN)
+    solver.set_pk(main_pk["kind"], max(1, main_pk["steps"]), main_pk["lo"], main_pk["hi"])
     return out
 
 

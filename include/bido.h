@@ -207,6 +207,33 @@ bido_status bido_set_solver(bido_ctx* ctx, double tol, int max_iter);
  * point for the triangular sweeps; the solve path does not call it.      */
 bido_status bido_inner_solve(bido_ctx* ctx, int which, const double* b, double* x);
 
+/* --- alternative P_K (Sec. 5.3: P_1 and P_K are free choices) ----------- *
+ * P_K ~ K_m = gamma M_H + S_m (Sec. 5.2) inside P_Lambda (Def. 2) is either
+ * the hierarchical Cholesky factor of K_m (BIDO_PK_CHOLESKY, the default)
+ * or `steps` steps of the Chebyshev acceleration of the Jacobi iteration on
+ * K_m from z_0 = 0 (BIDO_PK_CHEBYSHEV): with D = diag K_m and the interval
+ * [lo, hi] holding the spectrum of D^-1 K_m, the error of each eigencomponent
+ * lambda is multiplied by T_steps((hi + lo - 2 lambda) / (hi - lo)) /
+ * T_steps((hi + lo) / (hi - lo)).  The apply is symmetric positive definite
+ * whenever the spectrum lies below lo + hi, so plain CG stays valid; it
+ * runs in FP64 in both precisions and costs one product with K_m per step
+ * after the first.  lo = hi = 0 estimates the interval on the host
+ * (BIDO_PK_LANCZOS_STEPS Lanczos steps on D^-1/2 K_m D^-1/2, the top Ritz
+ * value raised by 5 %, clamped to the rigorous bounds min gamma m_i / K_ii
+ * and Gershgorin).  The first Chebyshev call uploads K_m (12 bytes per
+ * entry) and three N_H work vectors.  Errors: BIDO_ERR_ARG for a bad kind,
+ * steps outside [1, BIDO_PK_MAX_STEPS] or an interval other than
+ * 0 < lo < hi (or both 0); BIDO_ERR_STATE inside a batch.  Synchronises the
+ * stream; captured step graphs are rebuilt.  A fused batch refuses
+ * contexts that use the Chebyshev P_K.                                    */
+#define BIDO_PK_CHOLESKY  0
+#define BIDO_PK_CHEBYSHEV 1
+#define BIDO_PK_MAX_STEPS 64
+#define BIDO_PK_LANCZOS_STEPS 20
+bido_status bido_set_pk(bido_ctx* ctx, int kind, int steps, double lo, double hi);
+/* The current choice: kind, steps and interval (0 for the factor).        */
+bido_status bido_get_pk(const bido_ctx* ctx, int* kind, int* steps, double* lo, double* hi);
+
 /* --- learned correction of the monodomain preconditioner (flexible CG) -- *
  * One two-layer message-passing network on the heart vertices (the S_m
  * pattern as graph, hidden width 32, BF16 weights and activations, FP32

@@ -27,6 +27,7 @@ typedef struct bido_host bido_host;
 #define BIDO_MAT_LAMBDA 3  /* Lambda in the internal order (u then v)         */
 #define BIDO_MAT_GNN_AGG 4 /* neighbour weights of the learned correction,
                               heart-local: |S_m,ij| / sum_k!=i |S_m,ik|, j != i */
+#define BIDO_MAT_KM     5  /* K_m = gamma M_H + S_m, internal v order         */
 
 #define BIDO_VEC_M      0  /* lumped M, global numbering                      */
 #define BIDO_VEC_MH     1  /* lumped M_H, heart-local numbering               */
@@ -51,6 +52,12 @@ void bido_host_free(bido_host* h);
 bido_status bido_host_csr(const bido_host* h, int which, int64_t* n, int64_t* nnz,
                           const int64_t** ptr, const int32_t** col, const double** val);
 bido_status bido_host_vec(const bido_host* h, int which, int64_t* n, const double** data);
+
+/* Spectral interval of the Chebyshev P_K (bido_set_pk with lo = hi = 0):
+ * out[0..6) = the interval used (lo, hi), the extreme Ritz values of
+ * `lanczos_steps` Lanczos steps on D^-1/2 K_m D^-1/2, and the rigorous
+ * bounds (min gamma m_i / K_ii, Gershgorin).                              */
+bido_status bido_host_pk_interval(const bido_host* h, int lanczos_steps, double* out);
 bido_status bido_host_index(const bido_host* h, int which, int64_t* n, const int64_t** data);
 
 /* Sizes of a factor: entries uncompressed / as stored, low-rank blocks,

@@ -20,8 +20,10 @@ ERRORS = {-1: "BIDO_ERR_ARG", -2: "BIDO_ERR_DEVICE", -3: "BIDO_ERR_NOT_SPD",
 PREC_FP64, PREC_MIXED = 0, 1
 PRECOND_PLAIN, PRECOND_LEARNED, PRECOND_LEARNED_ADDITIVE = 0, 1, 2
 SCHEME_EULER, SCHEME_CN = 0, 1
+PK_CHOLESKY, PK_CHEBYSHEV = 0, 1
+PK_MAX_STEPS, PK_LANCZOS_STEPS = 64, 20
 LEARN_STENCIL, LEARN_ADDITIVE = 0, 1
-MAT_S1, MAT_SI, MAT_SM, MAT_LAMBDA, MAT_GNN_AGG = 0, 1, 2, 3, 4
+MAT_S1, MAT_SI, MAT_SM, MAT_LAMBDA, MAT_GNN_AGG, MAT_KM = 0, 1, 2, 3, 4, 5
 VEC_M, VEC_MH, VEC_GNN_STATIC = 0, 1, 2
 IDX_UPOS, IDX_VPOS, IDX_HEART = 0, 1, 2
 FACTOR_P1, FACTOR_PK = 0, 1
@@ -130,6 +132,10 @@ ABI = {
     "bido_inner_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p]),
     "bido_set_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "bido_set_pk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_double]),
+    "bido_get_pk": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                   _c_double_p, _c_double_p]),
     "bido_set_graphs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(TuneReport)]),
     "bido_learn_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -170,6 +176,7 @@ ABI = {
                                      ctypes.POINTER(_c_double_p)]),
     "bido_host_vec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p,
                                      ctypes.POINTER(_c_double_p)]),
+    "bido_host_pk_interval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p]),
     "bido_host_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p,
                                        ctypes.POINTER(_c_i64_p)]),
     "bido_host_factor_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p, _c_i64_p,
@@ -329,6 +336,18 @@ class Solver:
     def inner_solve(self, which, b, x):
         n = self.N if which == FACTOR_P1 else self.NH
         _check(lib.bido_inner_solve(self.ctx, int(which), self._dev(b, n), self._dev(x, n)))
+
+    def set_pk(self, kind, steps=3, lo=0.0, hi=0.0):
+        """P_K by its factor (PK_CHOLESKY) or by `steps` Chebyshev-accelerated
+        Jacobi steps on K_m over [lo, hi] (0, 0: estimated by the library)."""
+        _check(lib.bido_set_pk(self.ctx, int(kind), int(steps), float(lo), float(hi)))
+
+    def pk(self):
+        kind, steps = ctypes.c_int(), ctypes.c_int()
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        _check(lib.bido_get_pk(self.ctx, ctypes.byref(kind), ctypes.byref(steps), ctypes.byref(lo),
+                               ctypes.byref(hi)))
+        return dict(kind=kind.value, steps=steps.value, lo=lo.value, hi=hi.value)
 
     # ---- learned correction -------------------------------------------------
     def set_precond(self, precond):
@@ -529,6 +548,12 @@ class HostSetup:
         c = np.ctypeslib.as_array(col, shape=(nnz.value,)).copy() if nnz.value else np.zeros(0, np.int32)
         v = np.ctypeslib.as_array(val, shape=(nnz.value,)).copy() if nnz.value else np.zeros(0)
         return sp.csr_matrix((v, c, p), shape=(n.value, n.value))
+
+    def pk_interval(self, lanczos_steps=PK_LANCZOS_STEPS):
+        out = (ctypes.c_double * 6)()
+        _check(lib.bido_host_pk_interval(self.h, int(lanczos_steps), out), host=True)
+        keys = ("lo", "hi", "ritz_lo", "ritz_hi", "bound_lo", "bound_hi")
+        return dict(zip(keys, list(out)))
 
     def vec(self, which):
         n = ctypes.c_int64()

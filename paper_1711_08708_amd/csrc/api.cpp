@@ -63,10 +63,11 @@ int pow2_at_least(int n, int cap) {
 // Kernel classes of the optional per-launch profiler.
 enum KClass { K_SPMV_LAMBDA = 0, K_PCG_UPDATE, K_COMBINE_DOT, K_P_UPDATE, K_TRI_FWD_SUB,
               K_TRI_FWD_LVL, K_TRI_BWD_SUB, K_TRI_BWD_LVL, K_TRI_TOP, K_SPMV_CSR, K_IONIC, K_GNN, K_MISC,
-              K_NCLASS };
+              K_CHEB, K_NCLASS };
 const char* const kclass_name[K_NCLASS] = {"spmv_lambda", "pcg_update", "combine_dot", "p_update",
                                            "tri_fwd_sub", "tri_fwd_lvl", "tri_bwd_sub", "tri_bwd_lvl",
-                                           "tri_top", "spmv_csr", "ionic_rhs", "gnn_infer", "misc"};
+                                           "tri_top", "spmv_csr", "ionic_rhs", "gnn_infer", "misc",
+                                           "pk_chebyshev"};
 
 // Per-launch HIP-event timing with the algorithmic bytes of each launch.
 struct Profiler {
@@ -352,6 +353,13 @@ struct bido_ctx {
     FactorDev pk_learned;             // factor of K_m + C (learned stencil)
     int precond = BIDO_PRECOND_PLAIN;
     int fallbacks = 0;
+    // P_K ~ K_m: the factor `pk`, or Chebyshev-accelerated Jacobi on K_m
+    int pk_kind = BIDO_PK_CHOLESKY;
+    int cheb_steps = 0;
+    double cheb_lo = 0.0, cheb_hi = 0.0;
+    ChebCoef cheb;
+    CsrDev km;                        // K_m, internal v order (uploaded on first use)
+    double *km_dinv = nullptr, *ch_r = nullptr, *ch_d[2] = {nullptr, nullptr};
 
     ~bido_ctx() {
         if (stream) hipStreamSynchronize(stream);
@@ -362,7 +370,10 @@ struct bido_ctx {
         CsrHostView::release(lam);
         CsrHostView::release(avu);
         CsrHostView::release(auv);
-        for (double* b : {x, r, z, p, q, Y, tA, tB, tC, tD, r_old, sc, m_int, mh_loc, stim_loc}) hipFree(b);
+        CsrHostView::release(km);
+        for (double* b : {x, r, z, p, q, Y, tA, tB, tC, tD, r_old, sc, m_int, mh_loc, stim_loc, km_dinv, ch_r,
+                          ch_d[0], ch_d[1]})
+            hipFree(b);
         hipFree(rd.partials);
         hipFree(rd.counter);
         hipFree(u_pos);
@@ -432,6 +443,26 @@ void inner_solve(C* c, const FactorDev& f, const double* in, double* out) {
         tri_solve<double>(c, f, f.panel64, f.panel64_cm, in, out);
 }
 
+// Z2 = P_K^-1 t: the factor of K_m, or `cheb_steps` steps of the Chebyshev
+// acceleration of the Jacobi iteration on K_m (always FP64; z_0 = 0).
+void pk_solve(bido_ctx* c, const double* in, double* out) {
+    if (c->pk_kind != BIDO_PK_CHEBYSHEV) {
+        inner_solve(c, c->pk, in, out);
+        return;
+    }
+    hipStream_t s = c->stream;
+    const int64_t n = c->NH;
+    const double step_bytes = 12.0 * c->km.nnz + 8.0 * (n + 1) + 8.0 * 8 * n;
+    PROF(c, K_CHEB, 32.0 * n, launch_cheb_init(s, n, in, c->km_dinv, c->cheb.inv_theta, c->ch_d[0], out));
+    for (int k = 1; k < c->cheb_steps; ++k) {
+        const bool last = k + 1 == c->cheb_steps;
+        PROF(c, K_CHEB, last ? step_bytes - 16.0 * n : step_bytes,
+             launch_cheb_step(s, c->km, c->spmv_group, c->km_dinv, k == 1 ? in : c->ch_r, c->ch_r,
+                              c->ch_d[(k - 1) & 1], c->ch_d[k & 1], out, c->cheb.c1[k - 1], c->cheb.c2[k - 1],
+                              last));
+    }
+}
+
 // Opt-in check (environment BIDO_DEBUG=1): report the first non-finite
 // intermediate vector of a preconditioner apply on stderr.
 bool debug_on() {
@@ -471,7 +502,8 @@ void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old,
     PROF(c, K_SPMV_CSR, csr_bytes(c->avu, c->NH) + 8.0 * c->NH,
          launch_spmv_csr(s, c->avu, c->spmv_group, c->tA, r + N, c->tB));  // R2 - S_i Pi Z1
     debug_check(c, "t", c->tB, c->NH);
-    inner_solve(c, stencil ? c->pk_learned : c->pk, c->tB, z + N);  // Z2 = PK^-1 (...)
+    if (stencil) inner_solve(c, c->pk_learned, c->tB, z + N);        // Z2 = PK^-1 (...)
+    else pk_solve(c, c->tB, z + N);
     debug_check(c, "Z2", z + N, c->NH);
     if (g.collecting && g.n_samples + g.n_pending < g.max_samples && g.n_pending < g.max_pending) {
         const int k = g.n_samples + g.n_pending;
@@ -1366,6 +1398,8 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
             if (ctxs[j] == ctxs[i]) return fail(BIDO_ERR_ARG, "context listed twice");
         if (ctxs[i]->precond != BIDO_PRECOND_PLAIN || ctxs[i]->gnn.collecting)
             return fail(BIDO_ERR_STATE, "a fused batch runs the plain preconditioner only");
+        if (ctxs[i]->pk_kind != BIDO_PK_CHOLESKY)
+            return fail(BIDO_ERR_STATE, "a fused batch applies P_K by its factor only");
         if (ctxs[i]->precision != ctxs[0]->precision)
             return fail(BIDO_ERR_STATE, "a fused batch needs one precision for all slices");
     }
@@ -1732,9 +1766,64 @@ bido_status bido_profile_read(bido_ctx* c, bido_kprof* out, int cap, int* n) {
 
 bido_status bido_inner_solve(bido_ctx* c, int which, const double* b, double* x) {
     if (!c || !b || !x || (which != 0 && which != 1)) return fail(BIDO_ERR_ARG, "bad argument");
-    inner_solve(c, which == 0 ? c->p1 : c->pk, b, x);
+    if (which == 0) inner_solve(c, c->p1, b, x);
+    else pk_solve(c, b, x);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(c->stream));
+    return BIDO_OK;
+}
+
+bido_status bido_set_pk(bido_ctx* c, int kind, int steps, double lo, double hi) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    if (kind != BIDO_PK_CHOLESKY && kind != BIDO_PK_CHEBYSHEV) return fail(BIDO_ERR_ARG, "bad P_K kind");
+    if (c->batched) return fail(BIDO_ERR_STATE, "context is in a batch");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->drop_graphs();
+    if (kind == BIDO_PK_CHOLESKY) {
+        c->pk_kind = kind;
+        return BIDO_OK;
+    }
+    if (steps < 1 || steps > BIDO_PK_MAX_STEPS) return fail(BIDO_ERR_ARG, "Chebyshev steps out of range");
+    if (!(lo >= 0.0) || !(hi >= 0.0) || (lo == 0.0) != (hi == 0.0) || (lo > 0.0 && !(hi > lo)))
+        return fail(BIDO_ERR_ARG, "bad Chebyshev interval (0 < lo < hi, or both 0 to estimate)");
+    const Csr& K = c->hs.km_int;
+    if (K.n != c->NH) return fail(BIDO_ERR_STATE, "K_m is not available");
+    if (lo == 0.0) {
+        std::vector<double> gm(c->NH);
+        for (int64_t l = 0; l < c->NH; ++l) gm[c->hs.v_pos[l]] = c->hs.gamma * c->hs.mh_loc[l];
+        ChebInterval iv;
+        std::string err;
+        if (!chebyshev_interval(K, gm, BIDO_PK_LANCZOS_STEPS, iv, err)) return fail(BIDO_ERR_ARG, err);
+        lo = iv.lo;
+        hi = iv.hi;
+    }
+    if (!c->km.ptr && c->NH > 0) {
+        if (bido_status e = CsrHostView::up(K, c->km)) return e;
+        std::vector<double> dinv(c->NH, 0.0);
+        for (int64_t i = 0; i < c->NH; ++i)
+            for (int64_t p = K.ptr[i]; p < K.ptr[i + 1]; ++p)
+                if (K.col[p] == i) dinv[i] += K.val[p];
+        for (auto& x : dinv) {
+            if (!(x > 0.0)) return fail(BIDO_ERR_NOT_SPD, "K_m has a non-positive diagonal entry");
+            x = 1.0 / x;
+        }
+        HIP_OK(upload(&c->km_dinv, dinv.data(), dinv.size()));
+        for (double** b : {&c->ch_r, &c->ch_d[0], &c->ch_d[1]}) HIP_OK(hipMalloc((void**)b, c->NH * sizeof(double)));
+    }
+    c->pk_kind = kind;
+    c->cheb_steps = steps;
+    c->cheb_lo = lo;
+    c->cheb_hi = hi;
+    c->cheb = chebyshev_coefficients(lo, hi, steps);
+    return BIDO_OK;
+}
+
+bido_status bido_get_pk(const bido_ctx* c, int* kind, int* steps, double* lo, double* hi) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    if (kind) *kind = c->pk_kind;
+    if (steps) *steps = c->pk_kind == BIDO_PK_CHEBYSHEV ? c->cheb_steps : 0;
+    if (lo) *lo = c->pk_kind == BIDO_PK_CHEBYSHEV ? c->cheb_lo : 0.0;
+    if (hi) *hi = c->pk_kind == BIDO_PK_CHEBYSHEV ? c->cheb_hi : 0.0;
     return BIDO_OK;
 }
 

@@ -200,4 +200,17 @@ void merge_factors(const std::vector<const Factor*>& fs, const std::vector<int64
 // grounded entry fixed to zero.  Uses the compressed form when present.
 void host_solve(const Factor& f, const double* b, double* x);
 
+// Chebyshev-accelerated Jacobi iteration for P_K ~ K_m (chebyshev.cpp).
+// Interval for the spectrum of D^-1 K (D = diag K): rigorous bounds
+// [min gamma m_i / K_ii, Gershgorin] (gm = gamma M_H in the order of K),
+// the extreme Ritz values of `lanczos_steps` Lanczos steps, and the interval
+// used: [max(bound_lo, ritz_lo), min(bound_hi, 1.05 ritz_hi)].
+struct ChebInterval { double lo = 0, hi = 0, ritz_lo = 0, ritz_hi = 0, bound_lo = 0, bound_hi = 0; };
+bool chebyshev_interval(const Csr& K, const std::vector<double>& gm, int lanczos_steps, ChebInterval& out,
+                        std::string& err);
+// Step coefficients on [lo, hi]: d_0 = inv_theta D^-1 t, then for k >= 1
+// d_k = c1[k-1] d_{k-1} + c2[k-1] D^-1 r_k (steps - 1 entries).
+struct ChebCoef { double inv_theta = 0; std::vector<double> c1, c2; };
+ChebCoef chebyshev_coefficients(double lo, double hi, int steps);
+
 }  // namespace bido

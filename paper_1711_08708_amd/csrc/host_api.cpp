@@ -1,4 +1,5 @@
 // Host-only inspection entry points (include/bido_host.h).
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -47,6 +48,7 @@ bido_status bido_host_csr(const bido_host* h, int which, int64_t* n, int64_t* nn
         case BIDO_MAT_SM: a = &h->hs.A.Sm; break;
         case BIDO_MAT_LAMBDA: a = &h->hs.lam; break;
         case BIDO_MAT_GNN_AGG: a = &h->hs.gnn_agg; break;
+        case BIDO_MAT_KM: a = &h->hs.km_int; break;
         default: return hfail(BIDO_ERR_ARG, "unknown matrix");
     }
     *n = a->n;
@@ -54,6 +56,19 @@ bido_status bido_host_csr(const bido_host* h, int which, int64_t* n, int64_t* nn
     *ptr = a->ptr.data();
     *col = a->col.data();
     *val = a->val.data();
+    return BIDO_OK;
+}
+
+bido_status bido_host_pk_interval(const bido_host* h, int lanczos_steps, double* out) {
+    if (!h || !out || lanczos_steps < 1) return hfail(BIDO_ERR_ARG, "bad argument");
+    const bido::HostSetup& hs = h->hs;
+    std::vector<double> gm(hs.km_int.n, 0.0);
+    for (size_t l = 0; l < hs.mh_loc.size(); ++l) gm[hs.v_pos[l]] = hs.gamma * hs.mh_loc[l];
+    bido::ChebInterval iv;
+    std::string err;
+    if (!bido::chebyshev_interval(hs.km_int, gm, lanczos_steps, iv, err)) return hfail(BIDO_ERR_ARG, err);
+    const double v[6] = {iv.lo, iv.hi, iv.ritz_lo, iv.ritz_hi, iv.bound_lo, iv.bound_hi};
+    std::copy(v, v + 6, out);
     return BIDO_OK;
 }
 

@@ -231,6 +231,68 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_csr(int64_t n, const int64_t* __
 }
 
 // ---------------------------------------------------------------------------
+// P_K by Chebyshev acceleration of the Jacobi iteration on K_m (z_0 = 0):
+// d_0 = z = D^-1 t / theta, then per step r -= K_m d, d <- c1 d + c2 D^-1 r,
+// z += d (coefficients from the spectral interval, set up on the host)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_cheb_init(int64_t n, const double* __restrict__ t,
+                                                     const double* __restrict__ dinv, double inv_theta,
+                                                     double* __restrict__ d, double* __restrict__ z) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        const double v = inv_theta * dinv[i] * t[i];
+        d[i] = v;
+        z[i] = v;
+    }
+}
+
+// r = r_in - K dp ; dn = c1 dp + c2 D^-1 r ; z += dn.  r_in and r may be one
+// array (a row reads and writes only its own entry); dp and dn differ, since
+// other rows gather dp.  The last step writes z only.
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_cheb_step(int64_t n, const int64_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ val,
+                                                     const double* __restrict__ dinv, const double* r_in,
+                                                     double* r, const double* __restrict__ dp,
+                                                     double* __restrict__ dn, double* __restrict__ z,
+                                                     double c1, double c2, int last) {
+    constexpr int RU = SPMV_RU;
+    const int lane = threadIdx.x % G;
+    const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
+    const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
+    for (int64_t rb = gid; rb < n; rb += RU * ngroups) {
+        int64_t row[RU];
+        bool ok[RU];
+        double rv[RU], dv[RU], di[RU], zv[RU];   // the rows' own entries, loaded with the rows
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            row[u] = rb + u * ngroups;
+            ok[u] = row[u] < n;
+            const int64_t i = ok[u] ? row[u] : rb;
+            rv[u] = r_in[i];
+            dv[u] = dp[i];
+            di[u] = dinv[i];
+            zv[u] = z[i];
+        }
+        double s[RU];
+        csr_rows<G, RU>(ptr, col, val, dp, row, ok, lane, s);
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (!ok[u]) continue;
+                const double rn = rv[u] - s[u];
+                const double d = c1 * dv[u] + c2 * di[u] * rn;
+                z[row[u]] = zv[u] + d;
+                if (!last) {
+                    r[row[u]] = rn;
+                    dn[row[u]] = d;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // PCG vector recurrences
 // ---------------------------------------------------------------------------
 // Sum of nb block partials, in the same order in every block.
@@ -1120,6 +1182,25 @@ void launch_spmv_csr(hipStream_t s, const CsrDev& A, int group, const double* x,
     else if (group == 8) k_spmv_csr<8><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, b, y);
     else if (group == 16) k_spmv_csr<16><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, b, y);
     else k_spmv_csr<32><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, b, y);
+}
+
+void launch_cheb_init(hipStream_t s, int64_t n, const double* t, const double* dinv, double inv_theta, double* d,
+                      double* z) {
+    if (n <= 0) return;
+    k_cheb_init<<<grid_for(n), BLOCK, 0, s>>>(n, t, dinv, inv_theta, d, z);
+}
+void launch_cheb_step(hipStream_t s, const CsrDev& K, int group, const double* dinv, const double* r_in, double* r,
+                      const double* dp, double* dn, double* z, double c1, double c2, bool last) {
+    if (K.n <= 0) return;
+    const unsigned g = grid_for(K.n * group, BLOCK * 2, 4096);
+#define BIDO_CHEB_CASE(G)                                                                                   \
+    if (group == G) {                                                                                       \
+        k_cheb_step<G><<<g, BLOCK, 0, s>>>(K.n, K.ptr, K.col, K.val, dinv, r_in, r, dp, dn, z, c1, c2,      \
+                                           last ? 1 : 0);                                                   \
+        return;                                                                                             \
+    }
+    BIDO_CHEB_CASE(4) BIDO_CHEB_CASE(8) BIDO_CHEB_CASE(16) BIDO_CHEB_CASE(32)
+#undef BIDO_CHEB_CASE
 }
 
 unsigned launch_pcg_update(hipStream_t s, int64_t n, double* x, double* r, double* r_old, const double* p,

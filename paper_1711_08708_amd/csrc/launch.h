@@ -104,6 +104,13 @@ unsigned launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode,
                             const double* y, double* out, double* pp);
 void launch_spmv_csr(hipStream_t s, const CsrDev& A, int group, const double* x, const double* b,
                      double* y);
+// P_K by Chebyshev-accelerated Jacobi on K_m: d = z = inv_theta D^-1 t, then
+// per step r = r_in - K dp, dn = c1 dp + c2 D^-1 r, z += dn (r, dn not
+// written on the last step; r_in may equal r; dp and dn must differ)
+void launch_cheb_init(hipStream_t s, int64_t n, const double* t, const double* dinv, double inv_theta, double* d,
+                      double* z);
+void launch_cheb_step(hipStream_t s, const CsrDev& K, int group, const double* dinv, const double* r_in, double* r,
+                      const double* dp, double* dn, double* z, double c1, double c2, bool last);
 // dense top of a sweep: gather w_top from b and the bottom roots' updates,
 // then x[top_pos] = S_top^-1 w_top (inv: n_top x n_top row-major, or the
 // value array of the hierarchical form)

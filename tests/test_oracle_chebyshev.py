@@ -1,0 +1,164 @@
+"""Pins of the polynomial P_K (Chebyshev acceleration of the Jacobi iteration
+on K_m; Sec. 5.3 leaves P_K free) and of the library's host interval.
+
+The oracle builds the polynomial from its closed form; these tests pin it
+to the trigonometric definition of T_m, to the one-step special case (a
+scaled Jacobi step), to the classical error bound 1 / T_m(theta / delta) in
+the energy norm, to symmetry and definiteness of the operator, and to the
+exact solve as the step count grows.  The host interval of the library is
+checked against dense eigenvalues the oracle computes itself."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as w
+from oracle import bidomain as bd
+from oracle import blocklu as bl
+from oracle import chebyshev as ch
+
+
+def _km(cfg):
+    s = bd.System(cfg)
+    K = (s.gamma_eff * sp.diags(s.mH) + s.Sm).tocsr()
+    return s, K
+
+
+def _spectrum(K):
+    d = K.diagonal()
+    Ds = sp.diags(1.0 / np.sqrt(d))
+    return np.linalg.eigvalsh((Ds @ K @ Ds).toarray())
+
+
+@pytest.fixture(scope="module")
+def square48():
+    return _km(w.square2d(n=48))
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 8])
+def test_residual_polynomial_is_scaled_chebyshev(m):
+    lo, hi = 0.37, 1.9
+    th, de = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    lam = np.linspace(0.0, 2.6, 101)
+    R = ch.residual_polynomial(lo, hi, m)(lam)
+    ref = ch.chebyshev_t(m, (th - lam) / de) / ch.chebyshev_t(m, np.array([th / de]))[0]
+    assert abs(R[0] - 1.0) < 1e-13                       # R_m(0) = 1
+    assert np.abs(R - ref).max() < 1e-11
+    q = np.polynomial.Polynomial(ch.q_polynomial(lo, hi, m))
+    assert np.abs(1.0 - lam * q(lam) - ref).max() < 1e-11
+    # on [lo, hi] |R_m| <= 1 / T_m(theta / delta), reached at the m + 1 extrema
+    inside = (lam >= lo) & (lam <= hi)
+    assert np.abs(R[inside]).max() <= 1.0 / np.cosh(m * np.arccosh(th / de)) * (1 + 1e-12)
+
+
+def test_one_step_is_a_scaled_jacobi_step(square48):
+    _, K = square48
+    t = np.random.default_rng(0).normal(size=K.shape[0])
+    lo, hi = 0.6, 1.4
+    z = ch.chebyshev_jacobi(K, t, lo, hi, 1)
+    assert np.allclose(z, t / K.diagonal() / (0.5 * (lo + hi)), rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("m", [2, 3, 5])
+def test_energy_error_bound_on_km(square48, m):
+    """With [lo, hi] the exact extreme eigenvalues of D^-1 K_m, the energy
+    error of z_m is at most that of z_0 = 0 divided by T_m(theta / delta)."""
+    _, K = square48
+    ev = _spectrum(K)
+    lo, hi = ev[0], ev[-1]
+    th, de = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    bound = 1.0 / np.cosh(m * np.arccosh(th / de))
+    rng = np.random.default_rng(m)
+    x_exact_solve = bl.chol_solver(K.toarray())
+    for _ in range(3):
+        t = rng.normal(size=K.shape[0])
+        x = x_exact_solve(t)
+        e = ch.chebyshev_jacobi(K, t, lo, hi, m) - x
+        en = np.sqrt(e @ (K @ e)) / np.sqrt(x @ (K @ x))
+        assert en <= bound * (1 + 1e-9), (en, bound)
+
+
+@pytest.mark.parametrize("m", [2, 3, 4])
+def test_operator_symmetric_positive_definite(square48, m):
+    """t -> z is q(A) D^-1 = D^-1/2 q(B) D^-1/2 with B symmetric: a symmetric
+    operator, positive definite while the spectrum stays below lo + hi;
+    the eigenvalues of P K lie in [1 - 1/T_m, 1 + 1/T_m] on an exact
+    interval."""
+    _, K = square48
+    n = K.shape[0]
+    ev = _spectrum(K)
+    lo, hi = ev[0], ev[-1]
+    Z = np.column_stack([ch.chebyshev_jacobi(K, e, lo, hi, m) for e in np.eye(n)])
+    assert np.abs(Z - Z.T).max() <= 1e-12 * np.abs(Z).max()
+    assert np.linalg.eigvalsh(0.5 * (Z + Z.T)).min() > 0
+    th, de = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    b = 1.0 / np.cosh(m * np.arccosh(th / de))
+    Kd = K.toarray()
+    L = np.linalg.cholesky(Kd)
+    mu = np.linalg.eigvalsh(L.T @ Z @ L)                 # spectrum of Z K
+    assert mu.min() >= 1 - b - 1e-10 and mu.max() <= 1 + b + 1e-10
+    # a deliberately short interval (hi below the spectrum's top, still
+    # lambda_max < lo + hi) keeps the operator definite
+    Z2 = np.column_stack([ch.chebyshev_jacobi(K, e, lo, 0.8 * ev[-1], m) for e in np.eye(n)])
+    assert ev[-1] < lo + 0.8 * ev[-1]
+    assert np.linalg.eigvalsh(0.5 * (Z2 + Z2.T)).min() > 0
+
+
+def test_many_steps_approach_the_solve(square48):
+    _, K = square48
+    ev = _spectrum(K)
+    t = np.random.default_rng(3).normal(size=K.shape[0])
+    x = bl.chol_solver(K.toarray())(t)
+    z = ch.chebyshev_jacobi(K, t, ev[0], ev[-1], 10)
+    assert np.linalg.norm(z - x) / np.linalg.norm(x) < 1e-7
+
+
+def test_block_lu_with_polynomial_pk_converges_to_the_solution():
+    """Def. 2 with P_1 exact (grounded) and the polynomial P_K: PCG reaches
+    the unique normalised solution, in at most two iterations more than
+    with the exact K_m solve."""
+    cfg = w.square2d(n=48)
+    s = bd.System(cfg)
+    b = bl.dense_blocks(s)
+    K = bl.K_monodomain(b)
+    Ks = sp.csr_matrix(K)
+    ev = _spectrum(Ks)
+    P1 = bl.grounded_solver(b["S1"])
+    A = s.Lam.toarray()
+    rng = np.random.default_rng(4)
+    Y = s.rhs(rng.uniform(0, 100, s.NH), rng.uniform(0, 1, s.NH), 0)
+    Xo = s.solve(Y)
+    its = {}
+    for name, PK in (("exact", bl.chol_solver(K)),
+                     ("cheb3", lambda t: ch.chebyshev_jacobi(Ks, t, ev[0], 1.05 * ev[-1], 3))):
+        X, it, _ = bl.pcg(A, Y, bl.block_prec(b, P1, PK), tol=1e-12)
+        X1 = X[:s.N] - (s.m @ X[:s.N]) / s.m.sum()
+        Xn = np.concatenate([X1, X[s.N:]])
+        assert np.linalg.norm(Xn - Xo) / np.linalg.norm(Xo) < 1e-9
+        its[name] = it
+    assert its["cheb3"] <= its["exact"] + 2, its
+
+
+@pytest.mark.parametrize("mk", [lambda: w.square2d(n=48), lambda: w.thorax2d(n_target=3000, seed=11),
+                                lambda: w.slab3d(n=8)], ids=["square48", "thorax3000", "slab8"])
+def test_host_interval_brackets_the_spectrum(mk):
+    """The library's host interval (Lanczos + rigorous bounds) against the
+    oracle's own dense eigenvalues of D^-1/2 K_m D^-1/2: the rigorous bounds
+    enclose the spectrum, the Ritz values lie inside it, the interval's top
+    covers lambda_max and definiteness (lambda_max < lo + hi) holds."""
+    import paper_1711_08708_amd as B
+    cfg = mk()
+    _, K = _km(cfg)
+    ev = _spectrum(K)
+    hs = B.HostSetup(cfg)
+    iv = hs.pk_interval()
+    tol = 1e-10 * ev[-1]
+    assert iv["bound_lo"] <= ev[0] + tol and iv["bound_hi"] >= ev[-1] - tol
+    assert ev[0] - tol <= iv["ritz_lo"] <= iv["ritz_hi"] <= ev[-1] + tol
+    assert iv["hi"] >= ev[-1] - tol
+    assert ev[-1] < iv["lo"] + iv["hi"]
+    assert iv["lo"] == max(iv["bound_lo"], iv["ritz_lo"])
+    # the host K_m is the oracle's K_m up to the internal v order
+    Kh = hs.csr(B.MAT_KM)
+    vpos = hs.index(B.IDX_VPOS)
+    P = sp.csr_matrix((np.ones(len(vpos)), (vpos, np.arange(len(vpos)))), shape=Kh.shape)
+    assert abs(P @ K @ P.T - Kh).max() <= 1e-12 * abs(K).max()
