@@ -13,4 +13,6 @@ Modules
   blocklu   dense block-LU algebra of Sec. 4 (Prop. 2, Rem. 1, Prop. 3) and
             the block preconditioner of Def. 2 with the monodomain K_m
   mpnn      FP64 message-passing network used as the learned correction
+  chebyshev polynomial P_K (Chebyshev acceleration of the Jacobi iteration
+            on K_m, one of the free choices of Sec. 5.3) from its closed form
 """
