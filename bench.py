@@ -311,6 +311,9 @@ def _bench_batch(args):
     t_mesh = time.perf_counter() - t0
     t0 = time.perf_counter()
     solvers = [B.Solver(c, tol=args.tol, eps_h=args.eps, precision=prec) for c in cfgs]
+    if args.pk == "chebyshev":
+        for sv in solvers:
+            sv.set_pk(B.PK_CHEBYSHEV, args.pk_steps)
     t_setup = time.perf_counter() - t0
     n_nodes = sum(s.N for s in solvers)
     union_rows = sum(s.N + s.NH for s in solvers)
@@ -358,6 +361,7 @@ def _bench_batch(args):
                                f"vertex counts log-uniform in [20k, 300k], PCG per slice",
                    "slices": S, "total_nodes": n_nodes, "precision": args.precision, "tol": args.tol,
                    "mode": mode, "streams": args.batch_streams if mode == "streams" else 1,
+                   "pk": args.pk if args.pk == "cholesky" else f"chebyshev ({args.pk_steps} steps)",
                    "union_rows": union_rows, "union_nnz_lambda": union_nnz,
                    "learned": bool(args.batch_learned), "batch_setup_s": round(t_batch, 1),
                    "mean_iterations_per_slice_step": round((tot["total_iterations"] + tot2["total_iterations"])

@@ -224,8 +224,10 @@ bido_status bido_inner_solve(bido_ctx* ctx, int which, const double* b, double* 
  * entry) and three N_H work vectors.  Errors: BIDO_ERR_ARG for a bad kind,
  * steps outside [1, BIDO_PK_MAX_STEPS] or an interval other than
  * 0 < lo < hi (or both 0); BIDO_ERR_STATE inside a batch.  Synchronises the
- * stream; captured step graphs are rebuilt.  A fused batch refuses
- * contexts that use the Chebyshev P_K.                                    */
+ * stream; captured step graphs are rebuilt.  A fused batch takes the
+ * choice of its slices (all must agree on the kind and the step count;
+ * each keeps its own interval) and runs the steps as segmented launches
+ * over the union.                                                        */
 #define BIDO_PK_CHOLESKY  0
 #define BIDO_PK_CHEBYSHEV 1
 #define BIDO_PK_MAX_STEPS 64
@@ -364,8 +366,9 @@ void bido_batch_destroy(bido_batch* b);
  * beta = 0) while the others iterate; the inner solves sweep the forest of
  * all slices' elimination trees level by level, each tree with the top cut
  * of its own plan.  Steps 1 and 3 and the normalisation stay per slice.
- * Needs the plain preconditioner and one precision for all slices, and
- * refuses contexts already in a batch (BIDO_ERR_STATE).  Set-up merges the
+ * Needs the plain preconditioner, one precision and one P_K choice
+ * (bido_set_pk) for all slices, and refuses contexts already in a batch
+ * (BIDO_ERR_STATE).  Set-up merges the
  * host factors and uploads a second copy of them (the contexts keep
  * theirs); results agree with the slices run alone up to rounding order.
  * The contexts' U/V work vectors alias the union while in the batch.     */

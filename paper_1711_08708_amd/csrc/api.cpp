@@ -986,6 +986,14 @@ struct FusedBatch {
     uint8_t *done = nullptr, *done_host = nullptr;
     hipGraphExec_t gx[3] = {nullptr, nullptr, nullptr};
     double setup_seconds = 0.0;
+    // P_K by Chebyshev-accelerated Jacobi on the union K_m (one step count
+    // for all slices, each slice with its own interval): cheb holds
+    // inv_theta[S], then c1[S], c2[S] for each step after the first
+    int pk_kind = BIDO_PK_CHOLESKY;
+    int cheb_steps = 0;
+    int64_t nv = 0;                     // v rows of all slices
+    CsrDev km;
+    double *km_dinv = nullptr, *cheb = nullptr, *ch_r = nullptr, *ch_d[2] = {nullptr, nullptr};
 
     int64_t region(int k) const { return 3 * (int64_t)S + (int64_t)k * T.nblocks; }
     double* part(int k) const { return sc + region(k); }
@@ -1007,8 +1015,10 @@ struct FusedBatch {
         CsrHostView::release(lam);
         CsrHostView::release(avu);
         CsrHostView::release(auv);
+        CsrHostView::release(km);
         for (void* t : tables) hipFree(t);
-        for (double* b : {x, r, z, p, q, Y, tA, tB, tC, tD, r_old, sc}) hipFree(b);
+        for (double* b : {x, r, z, p, q, Y, tA, tB, tC, tD, r_old, sc, km_dinv, cheb, ch_r, ch_d[0], ch_d[1]})
+            hipFree(b);
         hipFree(done);
         if (sc_host) hipHostFree(sc_host);
         if (done_host) hipHostFree(done_host);
@@ -1081,13 +1091,31 @@ bido_status union_csr(const std::vector<const Csr*>& parts, const std::vector<in
     return CsrHostView::up(u, d);
 }
 
+// Z2 = P_K^-1 t on the v rows of every active slice by Chebyshev steps
+// (the same recurrence as pk_solve, with per-slice coefficients)
+void fused_pk_cheb(FusedBatch* F, const double* in, double* out) {
+    hipStream_t s = F->stream;
+    const int S = F->S;
+    const double nv = (double)F->nv, step_bytes = 12.0 * F->km.nnz + 8.0 * nv + 64.0 * nv;
+    PROF(F, K_CHEB, 32.0 * nv,
+         launch_seg_cheb_init(s, F->Tv, in, F->km_dinv, F->cheb, F->ch_d[0], out, F->done));
+    for (int k = 1; k < F->cheb_steps; ++k) {
+        const double* c1 = F->cheb + (int64_t)S * (1 + 2 * (k - 1));
+        const bool last = k + 1 == F->cheb_steps;
+        PROF(F, K_CHEB, last ? step_bytes - 16.0 * nv : step_bytes,
+             launch_seg_cheb_step(s, F->Tv, F->km, F->spmv_group, F->km_dinv, k == 1 ? in : F->ch_r, F->ch_r,
+                                  F->ch_d[(k - 1) & 1], F->ch_d[k & 1], out, c1, c1 + S, last, F->done));
+    }
+}
+
 // z = P^-1 r for all slices (the same steps as precond_apply) and the
 // partials of r.z (and r_old.z)
 void fused_apply(FusedBatch* F, bool with_old) {
     hipStream_t s = F->stream;
     inner_solve(F, F->p1, F->r, F->tA);                                               // Z1 = P1^-1 R1
     launch_seg_csr(s, F->Tv, F->avu, F->spmv_group, F->tA, F->r, F->tB, F->done);      // R2 - S_i Pi Z1
-    inner_solve(F, F->pk, F->tB, F->z);                                                // Z2 = PK^-1 (...)
+    if (F->pk_kind == BIDO_PK_CHEBYSHEV) fused_pk_cheb(F, F->tB, F->z);                // Z2 = PK^-1 (...)
+    else inner_solve(F, F->pk, F->tB, F->z);
     launch_seg_csr(s, F->Tu, F->auv, F->spmv_group, F->z, nullptr, F->tC, F->done);    // Pi^T S_i Z2
     inner_solve(F, F->p1, F->tC, F->tD);                                               // P1^-1 Pi^T S_i Z2
     launch_seg_combine(s, F->T, F->z, F->tA, F->tD, F->r, with_old ? F->r_old : nullptr, F->part(FR_RZ),
@@ -1398,8 +1426,9 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
             if (ctxs[j] == ctxs[i]) return fail(BIDO_ERR_ARG, "context listed twice");
         if (ctxs[i]->precond != BIDO_PRECOND_PLAIN || ctxs[i]->gnn.collecting)
             return fail(BIDO_ERR_STATE, "a fused batch runs the plain preconditioner only");
-        if (ctxs[i]->pk_kind != BIDO_PK_CHOLESKY)
-            return fail(BIDO_ERR_STATE, "a fused batch applies P_K by its factor only");
+        if (ctxs[i]->pk_kind != ctxs[0]->pk_kind ||
+            (ctxs[i]->pk_kind == BIDO_PK_CHEBYSHEV && ctxs[i]->cheb_steps != ctxs[0]->cheb_steps))
+            return fail(BIDO_ERR_STATE, "a fused batch needs one P_K choice (kind, Chebyshev steps) for all slices");
         if (ctxs[i]->precision != ctxs[0]->precision)
             return fail(BIDO_ERR_STATE, "a fused batch needs one precision for all slices");
     }
@@ -1439,6 +1468,37 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
     if ((e = union_csr(lam, o, o, n, F->lam))) return e;
     if ((e = union_csr(avu, ov, o, n, F->avu))) return e;
     if ((e = union_csr(auv, o, ov, n, F->auv))) return e;
+    if (ctxs[0]->pk_kind == BIDO_PK_CHEBYSHEV) {
+        const int m = ctxs[0]->cheb_steps;
+        std::vector<const Csr*> km;
+        std::vector<double> dinv(std::max<int64_t>(n, 1), 0.0);
+        std::vector<double> cf((size_t)S * (1 + 2 * (m - 1)));
+        for (int i = 0; i < S; ++i) {
+            const Csr& K = ctxs[i]->hs.km_int;
+            km.push_back(&K);
+            for (int64_t r = 0; r < K.n; ++r) {
+                double dg = 0.0;
+                for (int64_t q = K.ptr[r]; q < K.ptr[r + 1]; ++q)
+                    if (K.col[q] == r) dg += K.val[q];
+                if (!(dg > 0.0)) return fail(BIDO_ERR_NOT_SPD, "K_m has a non-positive diagonal entry");
+                dinv[ov[i] + r] = 1.0 / dg;
+            }
+            F->nv += K.n;
+            const ChebCoef& c = ctxs[i]->cheb;
+            cf[i] = c.inv_theta;
+            for (int k = 1; k < m; ++k) {
+                cf[(size_t)S * (1 + 2 * (k - 1)) + i] = c.c1[k - 1];
+                cf[(size_t)S * (2 + 2 * (k - 1)) + i] = c.c2[k - 1];
+            }
+        }
+        if ((e = union_csr(km, ov, ov, n, F->km))) return e;
+        HIP_OK(upload(&F->km_dinv, dinv.data(), dinv.size()));
+        HIP_OK(upload(&F->cheb, cf.data(), cf.size()));
+        for (double** v : {&F->ch_r, &F->ch_d[0], &F->ch_d[1]})
+            HIP_OK(hipMalloc((void**)v, std::max<int64_t>(n, 1) * sizeof(double)));
+        F->pk_kind = BIDO_PK_CHEBYSHEV;
+        F->cheb_steps = m;
+    }
     {
         // merged forests; each tree keeps the cut of its own plan (and its
         // hierarchical top), the tiles are those of the largest slice

@@ -120,6 +120,70 @@ __global__ __launch_bounds__(BB) void k_seg_csr(SegTable T, const int64_t* __res
     }
 }
 
+// P_K by Chebyshev-accelerated Jacobi on K_m, per slice (its coefficients at
+// index slice): d = z = inv_theta[s] D^-1 t on the rows of the table
+__global__ __launch_bounds__(BB) void k_seg_cheb_init(SegTable T, const double* __restrict__ t,
+                                                      const double* __restrict__ dinv,
+                                                      const double* __restrict__ inv_theta, double* __restrict__ d,
+                                                      double* __restrict__ z, const uint8_t* __restrict__ done) {
+    const SegBlock bk = T.blk[blockIdx.x];
+    if (done[bk.slice]) return;
+    const double it = inv_theta[bk.slice];
+    for (int64_t i = bk.r0 + threadIdx.x; i < bk.r1; i += BB) {
+        const double v = it * dinv[i] * t[i];
+        d[i] = v;
+        z[i] = v;
+    }
+}
+
+// r = r_in - K dp ; dn = c1[s] dp + c2[s] D^-1 r ; z += dn (r_in may be r;
+// the last step writes z only)
+template <int G>
+__global__ __launch_bounds__(BB) void k_seg_cheb_step(SegTable T, const int64_t* __restrict__ ptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ val,
+                                                      const double* __restrict__ dinv, const double* r_in, double* r,
+                                                      const double* __restrict__ dp, double* __restrict__ dn,
+                                                      double* __restrict__ z, const double* __restrict__ c1,
+                                                      const double* __restrict__ c2, int last,
+                                                      const uint8_t* __restrict__ done) {
+    const SegBlock bk = T.blk[blockIdx.x];
+    if (done[bk.slice]) return;
+    const double a1 = c1[bk.slice], a2 = c2[bk.slice];
+    constexpr int RU = SPMV_RU, NG = BB / G;
+    const int lane = threadIdx.x % G;
+    for (int64_t rb = bk.r0 + threadIdx.x / G; rb < bk.r1; rb += RU * NG) {
+        int64_t row[RU];
+        bool ok[RU];
+        double rv[RU], dv[RU], di[RU], zv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            row[u] = rb + u * NG;
+            ok[u] = row[u] < bk.r1;
+            const int64_t i = ok[u] ? row[u] : rb;
+            rv[u] = r_in[i];
+            dv[u] = dp[i];
+            di[u] = dinv[i];
+            zv[u] = z[i];
+        }
+        double sum[RU];
+        csr_rows<G, RU>(ptr, col, val, dp, row, ok, lane, sum);
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (!ok[u]) continue;
+                const double rn = rv[u] - sum[u];
+                const double d = a1 * dv[u] + a2 * di[u] * rn;
+                z[row[u]] = zv[u] + d;
+                if (!last) {
+                    r[row[u]] = rn;
+                    dn[row[u]] = d;
+                }
+            }
+        }
+    }
+}
+
 // alpha_s = rho_s / (p.q)_s (0 for a frozen slice); x += alpha p; r -= alpha q
 __global__ __launch_bounds__(BB) void k_seg_pcg_update(SegTable T, double* __restrict__ x, double* __restrict__ r,
                                                        double* __restrict__ r_old, const double* __restrict__ p,
@@ -226,6 +290,24 @@ void launch_seg_csr(hipStream_t s, const SegTable& T, const CsrDev& A, int group
     else if (group == 8) k_seg_csr<8><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, b, y, done);
     else if (group == 16) k_seg_csr<16><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, b, y, done);
     else k_seg_csr<32><<<T.nblocks, BB, 0, s>>>(T, A.ptr, A.col, A.val, x, b, y, done);
+}
+void launch_seg_cheb_init(hipStream_t s, const SegTable& T, const double* t, const double* dinv,
+                          const double* inv_theta, double* d, double* z, const uint8_t* done) {
+    if (T.nblocks <= 0) return;
+    k_seg_cheb_init<<<T.nblocks, BB, 0, s>>>(T, t, dinv, inv_theta, d, z, done);
+}
+void launch_seg_cheb_step(hipStream_t s, const SegTable& T, const CsrDev& K, int group, const double* dinv,
+                          const double* r_in, double* r, const double* dp, double* dn, double* z, const double* c1,
+                          const double* c2, bool last, const uint8_t* done) {
+    if (T.nblocks <= 0) return;
+#define BIDO_SEG_CHEB_CASE(G)                                                                             \
+    if (group == G) {                                                                                     \
+        k_seg_cheb_step<G><<<T.nblocks, BB, 0, s>>>(T, K.ptr, K.col, K.val, dinv, r_in, r, dp, dn, z, c1, \
+                                                    c2, last ? 1 : 0, done);                              \
+        return;                                                                                           \
+    }
+    BIDO_SEG_CHEB_CASE(4) BIDO_SEG_CHEB_CASE(8) BIDO_SEG_CHEB_CASE(16) BIDO_SEG_CHEB_CASE(32)
+#undef BIDO_SEG_CHEB_CASE
 }
 void launch_seg_pcg_update(hipStream_t s, const SegTable& T, double* x, double* r, double* r_old, const double* p,
                            const double* q, const double* part_pq, double* part_rr, const double* rho,

@@ -145,6 +145,12 @@ void launch_seg_spmv(hipStream_t s, const SegTable& T, const CsrDev& A, int grou
                      const double* y, double* out, double* part0, double* part1, const uint8_t* done);
 void launch_seg_csr(hipStream_t s, const SegTable& T, const CsrDev& A, int group, const double* x, const double* b,
                     double* y, const uint8_t* done);
+// Chebyshev P_K per slice (coefficients indexed by slice; see launch_cheb_*)
+void launch_seg_cheb_init(hipStream_t s, const SegTable& T, const double* t, const double* dinv,
+                          const double* inv_theta, double* d, double* z, const uint8_t* done);
+void launch_seg_cheb_step(hipStream_t s, const SegTable& T, const CsrDev& K, int group, const double* dinv,
+                          const double* r_in, double* r, const double* dp, double* dn, double* z, const double* c1,
+                          const double* c2, bool last, const uint8_t* done);
 void launch_seg_pcg_update(hipStream_t s, const SegTable& T, double* x, double* r, double* r_old, const double* p,
                            const double* q, const double* part_pq, double* part_rr, const double* rho,
                            const uint8_t* done, double* pq_out);

@@ -111,10 +111,12 @@ def test_graph_replays_match_eager_launches(torch, precision):
         assert np.array_equal(a, b)
 
 
-def _single_runs(B, cfgs, prec, n_steps, **kw):
+def _single_runs(B, cfgs, prec, n_steps, pk_steps=0, **kw):
     out = []
     for cfg in cfgs:
         s = B.Solver(cfg, tol=1e-12, precision=prec, **kw)
+        if pk_steps:
+            s.set_pk(B.PK_CHEBYSHEV, pk_steps)
         s.set_graphs(False)
         v, h, u = s.state()
         its = [s.step(v, h, u, n)["iterations"] for n in range(n_steps)]
@@ -243,6 +245,58 @@ def test_fused_batch_crank_nicolson(torch):
     batch.close()
     for s in solvers:
         s.close()
+
+
+def test_fused_batch_chebyshev_pk(torch):
+    """Slices with the polynomial P_K (Chebyshev-accelerated Jacobi on K_m,
+    each slice with its own interval) in one fused batch: segmented
+    Chebyshev launches over the union follow each slice run alone, graph
+    replays match eager launches bit for bit, the last step matches the
+    oracle, and slices with different step counts are refused."""
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd
+    cfgs = _slices()
+    n_steps = 8
+    ref = _single_runs(B, cfgs, B.PREC_FP64, n_steps, pk_steps=3)
+    out = []
+    for graphs in (False, True):
+        solvers = [B.Solver(cfg, tol=1e-12) for cfg in cfgs]
+        for sv in solvers:
+            sv.set_pk(B.PK_CHEBYSHEV, 3)
+        batch = B.Batch(solvers, fused=True)
+        batch.set_graphs(graphs)
+        states = [sv.state() for sv in solvers]
+        its = [[p["iterations"] for p in batch.run(states, n, 1)[1]] for n in range(n_steps - 1)]
+        before = [(st[0].cpu().numpy().copy(), st[1].cpu().numpy().copy()) for st in states]
+        its.append([p["iterations"] for p in batch.run(states, n_steps - 1, 1)[1]])
+        out.append(([[t.cpu().numpy() for t in st] for st in states], its, before))
+        batch.close()
+        for sv in solvers:
+            sv.close()
+    assert out[0][1] == out[1][1]
+    for a, b in zip(out[0][0], out[1][0]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    states, its, before = out[1]
+    for k, cfg in enumerate(cfgs):
+        fused_its = [row[k] for row in its]
+        print(f"  slice {k} ({cfg['name']}): iterations fused {fused_its} alone {ref[k][1]}")
+        assert all(abs(a - b) <= 1 for a, b in zip(fused_its, ref[k][1]))
+        for a, b in zip(states[k], ref[k][0]):
+            assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b), k
+        sy = bd.System(cfg)
+        Uo, Vo, _ = sy.step(before[k][0], before[k][1], n_steps - 1)
+        Uo = sy.to_global_u(Uo)
+        v, _, u = states[k]
+        assert np.linalg.norm(u - Uo) <= 1e-8 * np.linalg.norm(Uo)
+        assert np.linalg.norm(v - Vo) <= 1e-8 * np.linalg.norm(Vo)
+    solvers = [B.Solver(cfg, tol=1e-12) for cfg in cfgs[:2]]
+    solvers[0].set_pk(B.PK_CHEBYSHEV, 3)
+    solvers[1].set_pk(B.PK_CHEBYSHEV, 4)
+    with pytest.raises(B.BidoError, match="BIDO_ERR_STATE"):
+        B.Batch(solvers, fused=True)
+    for sv in solvers:
+        sv.close()
 
 
 def test_fused_batch64_sampled_slices_full_size(torch):

@@ -189,7 +189,7 @@ def test_set_pk_arguments_and_switching(torch):
     got = solver.pk()
     iv = B.HostSetup(cfg).pk_interval()
     assert got["steps"] == 4 and got["lo"] == iv["lo"] and got["hi"] == iv["hi"]
-    # a fused batch applies P_K by its factor only
+    # a fused batch needs one P_K choice for all its slices
     other = B.Solver(w.thorax2d(n_target=2000, seed=5), eps_h=0.0)
     with pytest.raises(RuntimeError, match="BIDO_ERR_STATE"):
         B.Batch([solver, other], fused=True)
