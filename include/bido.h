@@ -236,6 +236,32 @@ bido_status bido_set_pk(bido_ctx* ctx, int kind, int steps, double lo, double hi
 /* The current choice: kind, steps and interval (0 for the factor).        */
 bido_status bido_get_pk(const bido_ctx* ctx, int* kind, int* steps, double* lo, double* hi);
 
+/* --- recordings of a run (Sec. 6: activation maps and ECG) -------------- *
+ * The paper's test cases map the activation time of each point (the time at
+ * which the transmembrane potential crosses a fixed level during the
+ * depolarisation) and record the potential u at body-surface electrodes at
+ * every time step.  bido_record starts (or restarts) such a recording for
+ * the following steps of the context (bido_step, bido_run, batches):
+ *  - v_act: activation level in the units of v (mV above rest); NaN records
+ *    no activation times.  The activation time of heart vertex i is the
+ *    first t at which v_i reaches v_act, linearly interpolated between
+ *    t_n = n dt and t_n + dt over the step n that crosses it (t_n if v_i
+ *    was already at or above v_act before that step); fused into the
+ *    write-back of V^{n+1}.
+ *  - xyz: host, n_probes x dim probe points (copied); each must lie in the
+ *    mesh (BIDO_ERR_ARG otherwise).  After every step the P1 interpolant of
+ *    the normalised u at each probe is stored as one row, for the first
+ *    max_steps steps (later steps are not recorded).
+ * Device memory: 8 N_H + 8 n_probes max_steps bytes plus the weights.
+ * Errors: BIDO_ERR_ARG for bad sizes or an infinite v_act, BIDO_ERR_STATE
+ * for a context in a batch (start the recording before creating it).     */
+bido_status bido_record(bido_ctx* ctx, double v_act, int n_probes, const double* xyz, int64_t max_steps);
+/* Copy the recording to host memory: act (N_H, heart-local order; -1 for a
+ * vertex not reached; BIDO_ERR_STATE if none are recorded), probes (rows x
+ * n_probes, row-major) and the number of rows.  Any pointer may be null.
+ * Synchronises the context's stream.                                      */
+bido_status bido_record_read(bido_ctx* ctx, double* act, double* probes, int64_t* n_rows);
+
 /* --- learned correction of the monodomain preconditioner (flexible CG) -- *
  * One two-layer message-passing network on the heart vertices (the S_m
  * pattern as graph, hidden width 32, BF16 weights and activations, FP32

@@ -58,6 +58,12 @@ bido_status bido_host_vec(const bido_host* h, int which, int64_t* n, const doubl
  * `lanczos_steps` Lanczos steps on D^-1/2 K_m D^-1/2, and the rigorous
  * bounds (min gamma m_i / K_ii, Gershgorin).                              */
 bido_status bido_host_pk_interval(const bido_host* h, int lanczos_steps, double* out);
+
+/* Probe location of bido_record: for each of n points (host, n x dim) the
+ * dim + 1 vertex ids (caller's numbering) of an element holding it and the
+ * barycentric weights there (ids, wts: n x (dim + 1)).  BIDO_ERR_ARG if a
+ * point lies outside the mesh.                                           */
+bido_status bido_host_locate(const bido_host* h, int n, const double* pts, int64_t* ids, double* wts);
 bido_status bido_host_index(const bido_host* h, int which, int64_t* n, const int64_t** data);
 
 /* Sizes of a factor: entries uncompressed / as stored, low-rank blocks,

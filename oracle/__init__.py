@@ -15,4 +15,6 @@ Modules
   mpnn      FP64 message-passing network used as the learned correction
   chebyshev polynomial P_K (Chebyshev acceleration of the Jacobi iteration
             on K_m, one of the free choices of Sec. 5.3) from its closed form
+  record    activation times and probe (electrode) potentials of a run
+            (the recordings of the test cases of Sec. 6)
 """

@@ -134,6 +134,9 @@ ABI = {
     "bido_set_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_set_pk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_double]),
+    "bido_record": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, _c_double_p,
+                                   ctypes.c_int64]),
+    "bido_record_read": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p, _c_i64_p]),
     "bido_get_pk": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                    _c_double_p, _c_double_p]),
     "bido_set_graphs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -177,6 +180,7 @@ ABI = {
     "bido_host_vec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p,
                                      ctypes.POINTER(_c_double_p)]),
     "bido_host_pk_interval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p]),
+    "bido_host_locate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p, _c_i64_p, _c_double_p]),
     "bido_host_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p,
                                        ctypes.POINTER(_c_i64_p)]),
     "bido_host_factor_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p, _c_i64_p,
@@ -295,6 +299,8 @@ class Solver:
         self.N = int(self.info["n_nodes"])
         self.NH = int(self.info["n_heart"])
         self.dt = float(self.params.dt)
+        self.dim = int(cfg["dim"])
+        self._rec_np, self._rec_act = 0, False
 
     def _dev(self, t, n):
         torch = self.torch
@@ -348,6 +354,25 @@ class Solver:
         _check(lib.bido_get_pk(self.ctx, ctypes.byref(kind), ctypes.byref(steps), ctypes.byref(lo),
                                ctypes.byref(hi)))
         return dict(kind=kind.value, steps=steps.value, lo=lo.value, hi=hi.value)
+
+    def record(self, v_act=float("nan"), points=None, max_steps=0):
+        """Record activation times (level v_act; NaN: none) and the potential
+        u at probe points (n x dim) for the first max_steps later steps."""
+        pts = np.ascontiguousarray(np.zeros((0, self.dim)) if points is None else points, dtype=np.float64)
+        self._rec_np = len(pts)
+        self._rec_act = not np.isnan(v_act)
+        _check(lib.bido_record(self.ctx, float(v_act), len(pts),
+                               pts.ctypes.data_as(_c_double_p) if len(pts) else None, int(max_steps)))
+
+    def record_read(self):
+        """(activation times or None, probe rows) as numpy arrays."""
+        n = ctypes.c_int64()
+        _check(lib.bido_record_read(self.ctx, None, None, ctypes.byref(n)))
+        act = np.empty(self.NH) if self._rec_act else None
+        rows = np.empty((n.value, self._rec_np))
+        _check(lib.bido_record_read(self.ctx, act.ctypes.data_as(_c_double_p) if act is not None else None,
+                                    rows.ctypes.data_as(_c_double_p) if rows.size else None, ctypes.byref(n)))
+        return act, rows
 
     # ---- learned correction -------------------------------------------------
     def set_precond(self, precond):
@@ -548,6 +573,16 @@ class HostSetup:
         c = np.ctypeslib.as_array(col, shape=(nnz.value,)).copy() if nnz.value else np.zeros(0, np.int32)
         v = np.ctypeslib.as_array(val, shape=(nnz.value,)).copy() if nnz.value else np.zeros(0)
         return sp.csr_matrix((v, c, p), shape=(n.value, n.value))
+
+    def locate(self, points):
+        """(vertex ids, barycentric weights) of the element holding each point."""
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        n, d = pts.shape
+        ids = np.empty((n, d + 1), dtype=np.int64)
+        wts = np.empty((n, d + 1))
+        _check(lib.bido_host_locate(self.h, n, pts.ctypes.data_as(_c_double_p), ids.ctypes.data_as(_c_i64_p),
+                                    wts.ctypes.data_as(_c_double_p)), host=True)
+        return ids, wts
 
     def pk_interval(self, lanczos_steps=PK_LANCZOS_STEPS):
         out = (ctypes.c_double * 6)()

@@ -360,6 +360,26 @@ struct bido_ctx {
     ChebCoef cheb;
     CsrDev km;                        // K_m, internal v order (uploaded on first use)
     double *km_dinv = nullptr, *ch_r = nullptr, *ch_d[2] = {nullptr, nullptr};
+    // recording of the steps (bido_record): activation times, probe rows
+    int64_t step_n = 0;               // index of the step in progress
+    struct Recording {
+        bool on = false;
+        double v_act = 0.0;
+        bool act_on = false;
+        double* act = nullptr;        // N_H, heart-local order; < 0: not reached
+        int np = 0, nv = 0;
+        int64_t* ids = nullptr;       // np x nv vertex ids (caller's numbering)
+        double* wts = nullptr;        // np x nv barycentric weights
+        double* rows = nullptr;       // max_steps x np
+        int64_t max_steps = 0, n_rows = 0;
+        void release() {
+            hipFree(act);
+            hipFree(ids);
+            hipFree(wts);
+            hipFree(rows);
+            *this = Recording();
+        }
+    } rec;
 
     ~bido_ctx() {
         if (stream) hipStreamSynchronize(stream);
@@ -367,6 +387,7 @@ struct bido_ctx {
         pk.release();
         pk_learned.release();
         gnn.release();
+        rec.release();
         CsrHostView::release(lam);
         CsrHostView::release(avu);
         CsrHostView::release(auv);
@@ -776,6 +797,7 @@ IonicConst ionic_consts(const bido_ctx* c) {
 void step_prepare(bido_ctx* c, double* v, double* w, double* u, int64_t n) {
     hipStream_t s = c->stream;
     const int64_t N = c->N, NH = c->NH;
+    c->step_n = n;
     PROF(c, K_MISC, 24.0 * N, launch_scatter_in(s, N, c->u_pos, u, c->x));   // X0 = (U^n, V^n)
     const double on = (n >= c->hs.stim_n0 && n < c->hs.stim_n1) ? 1.0 : 0.0;
     const double* sub = nullptr;
@@ -810,7 +832,19 @@ void step_write(bido_ctx* c, double* v, double* u) {
     const int64_t N = c->N, NH = c->NH;
     PROF(c, K_MISC, 16.0 * N, launch_dot_reduce(s, N, c->m_int, c->x, c->rd, c->sc + S_MU));  // (M U, 1)
     PROF(c, K_MISC, 24.0 * N, launch_gather_out(s, N, c->u_pos, c->x, u, c->sc, S_MU, c->hs.msum));
-    PROF(c, K_MISC, 24.0 * NH, launch_gather_out(s, NH, c->v_pos, c->x + N, v, c->sc, -1, 1.0));
+    auto& rec = c->rec;
+    if (rec.on && rec.act_on) {
+        PROF(c, K_MISC, 48.0 * NH,
+             launch_gather_v_act(s, NH, c->v_pos, c->x + N, v, rec.act, rec.v_act, (double)c->step_n * c->params.dt,
+                                 c->params.dt));
+    } else {
+        PROF(c, K_MISC, 24.0 * NH, launch_gather_out(s, NH, c->v_pos, c->x + N, v, c->sc, -1, 1.0));
+    }
+    if (rec.on && rec.np > 0 && rec.n_rows < rec.max_steps) {
+        PROF(c, K_MISC, 24.0 * rec.np * rec.nv,
+             launch_probe(s, rec.np, rec.nv, rec.ids, rec.wts, u, rec.rows + rec.n_rows * rec.np));
+        ++rec.n_rows;
+    }
 }
 
 bido_status step_end(bido_ctx* c, double* v, double* u, const PcgRun& ps, bido_stats* st) {
@@ -1875,6 +1909,57 @@ bido_status bido_set_pk(bido_ctx* c, int kind, int steps, double lo, double hi) 
     c->cheb_lo = lo;
     c->cheb_hi = hi;
     c->cheb = chebyshev_coefficients(lo, hi, steps);
+    return BIDO_OK;
+}
+
+bido_status bido_record(bido_ctx* c, double v_act, int n_probes, const double* xyz, int64_t max_steps) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    if (n_probes < 0 || (n_probes > 0 && (!xyz || max_steps < 1)) || max_steps < 0)
+        return fail(BIDO_ERR_ARG, "bad probe arguments");
+    if (std::isinf(v_act)) return fail(BIDO_ERR_ARG, "v_act must be finite (or NaN for none)");
+    if (c->batched) return fail(BIDO_ERR_STATE, "context is in a batch");
+    if ((int64_t)n_probes * std::max<int64_t>(max_steps, 1) > (int64_t)1 << 31)
+        return fail(BIDO_ERR_ARG, "recording too large");
+    const int dim = c->hs.A.dim, nv = dim + 1;
+    std::vector<int64_t> ids;
+    std::vector<double> wts;
+    std::string err;
+    if (n_probes > 0 && !locate_points(dim, c->hs.xyz, c->hs.elems, xyz, n_probes, ids, wts, err))
+        return fail(BIDO_ERR_ARG, err);
+    HIP_OK(hipStreamSynchronize(c->stream));
+    auto& rec = c->rec;
+    rec.release();
+    rec.v_act = v_act;
+    rec.act_on = !std::isnan(v_act);
+    if (rec.act_on && c->NH > 0) {
+        HIP_OK(hipMalloc((void**)&rec.act, c->NH * sizeof(double)));
+        launch_fill(c->stream, c->NH, rec.act, -1.0);
+    }
+    rec.np = n_probes;
+    rec.nv = nv;
+    if (n_probes > 0) {
+        HIP_OK(upload(&rec.ids, ids.data(), ids.size()));
+        HIP_OK(upload(&rec.wts, wts.data(), wts.size()));
+        HIP_OK(hipMalloc((void**)&rec.rows, (size_t)n_probes * max_steps * sizeof(double)));
+        launch_fill(c->stream, (int64_t)n_probes * max_steps, rec.rows, std::nan(""));
+    }
+    rec.max_steps = n_probes > 0 ? max_steps : 0;
+    rec.on = rec.act_on || n_probes > 0;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return BIDO_OK;
+}
+
+bido_status bido_record_read(bido_ctx* c, double* act, double* probes, int64_t* n_rows) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    const auto& rec = c->rec;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (act) {
+        if (!rec.act_on) return fail(BIDO_ERR_STATE, "no activation times are being recorded");
+        HIP_OK(hipMemcpy(act, rec.act, c->NH * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    if (probes && rec.np > 0 && rec.n_rows > 0)
+        HIP_OK(hipMemcpy(probes, rec.rows, (size_t)rec.n_rows * rec.np * sizeof(double), hipMemcpyDeviceToHost));
+    if (n_rows) *n_rows = rec.n_rows;
     return BIDO_OK;
 }
 

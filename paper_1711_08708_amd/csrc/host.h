@@ -213,4 +213,11 @@ bool chebyshev_interval(const Csr& K, const std::vector<double>& gm, int lanczos
 struct ChebCoef { double inv_theta = 0; std::vector<double> c1, c2; };
 ChebCoef chebyshev_coefficients(double lo, double hi, int steps);
 
+// Element and barycentric weights of each of np points (np x dim, row-major)
+// in the mesh (xyz: vertices x dim, elems: elements x (dim+1)); a point on
+// shared faces goes to the element it is deepest in.  False if a point lies
+// outside every element.
+bool locate_points(int dim, const std::vector<double>& xyz, const std::vector<int32_t>& elems, const double* pts,
+                   int np, std::vector<int64_t>& ids, std::vector<double>& wts, std::string& err);
+
 }  // namespace bido

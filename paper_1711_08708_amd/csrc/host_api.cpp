@@ -72,6 +72,18 @@ bido_status bido_host_pk_interval(const bido_host* h, int lanczos_steps, double*
     return BIDO_OK;
 }
 
+bido_status bido_host_locate(const bido_host* h, int n, const double* pts, int64_t* ids, double* wts) {
+    if (!h || n < 0 || (n > 0 && (!pts || !ids || !wts))) return hfail(BIDO_ERR_ARG, "bad argument");
+    std::vector<int64_t> vi;
+    std::vector<double> vw;
+    std::string err;
+    if (!bido::locate_points(h->hs.A.dim, h->hs.xyz, h->hs.elems, pts, n, vi, vw, err))
+        return hfail(BIDO_ERR_ARG, err);
+    std::copy(vi.begin(), vi.end(), ids);
+    std::copy(vw.begin(), vw.end(), wts);
+    return BIDO_OK;
+}
+
 bido_status bido_host_vec(const bido_host* h, int which, int64_t* n, const double** data) {
     if (!h || !n || !data) return hfail(BIDO_ERR_ARG, "null argument");
     const std::vector<double>* v = nullptr;

@@ -111,6 +111,30 @@ __global__ void k_gather_out(int64_t n, const int64_t* __restrict__ pos,
         dst[i] = src[pos[i]] - s;
 }
 
+// dst[i] = src[pos[i]] for the new potential V^{n+1}, and the activation
+// time of vertex i: the first time its potential reaches v_act, linearly
+// interpolated between t_n (V^n = the old dst[i]) and t_n + dt; act < 0
+// marks a vertex not reached yet
+__global__ void k_gather_v_act(int64_t n, const int64_t* __restrict__ pos, const double* __restrict__ src,
+                               double* __restrict__ dst, double* __restrict__ act, double v_act, double t_n,
+                               double dt) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        const double vo = dst[i], vn = src[pos[i]], a = act[i];
+        dst[i] = vn;
+        if (a < 0.0 && vn >= v_act) act[i] = vo >= v_act ? t_n : t_n + dt * (v_act - vo) / (vn - vo);
+    }
+}
+
+// out[q] = sum_k w[q][k] u[id[q][k]]: the P1 interpolant of u at probe q
+__global__ void k_probe(int np, int nv, const int64_t* __restrict__ ids, const double* __restrict__ wts,
+                        const double* __restrict__ u, double* __restrict__ out) {
+    const int q = blockIdx.x * BLOCK + threadIdx.x;
+    if (q >= np) return;
+    double s = 0.0;
+    for (int k = 0; k < nv; ++k) s += wts[q * nv + k] * u[ids[q * nv + k]];
+    out[q] = s;
+}
+
 // (M U, 1) for the normalisation, and optionally sum of a second vector
 __global__ void k_dot_reduce(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
                              double* partials, unsigned* counter, double* out) {
@@ -1143,6 +1167,16 @@ void launch_gather_out(hipStream_t s, int64_t n, const int64_t* pos, const doubl
                        const double* sc, int shift_slot, double shift_den) {
     if (n <= 0) return;
     k_gather_out<<<grid_for(n), BLOCK, 0, s>>>(n, pos, src, dst, sc, shift_slot, shift_den);
+}
+void launch_gather_v_act(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst, double* act,
+                         double v_act, double t_n, double dt) {
+    if (n <= 0) return;
+    k_gather_v_act<<<grid_for(n), BLOCK, 0, s>>>(n, pos, src, dst, act, v_act, t_n, dt);
+}
+void launch_probe(hipStream_t s, int np, int nv, const int64_t* ids, const double* wts, const double* u,
+                  double* out) {
+    if (np <= 0) return;
+    k_probe<<<(np + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(np, nv, ids, wts, u, out);
 }
 void launch_dot_reduce(hipStream_t s, int64_t n, const double* a, const double* b, Reduce rd, double* out) {
     k_dot_reduce<<<grid_for(n, BLOCK * 4, rd.max_blocks), BLOCK, 0, s>>>(n, a, b, rd.partials, rd.counter, out);

@@ -92,6 +92,13 @@ void launch_scatter_in_f(hipStream_t s, int64_t n, const int64_t* pos, const flo
 void launch_gather_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst);
 void launch_gather_out(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst,
                        const double* sc, int shift_slot, double shift_den);
+// v write-back with activation times (first time v reaches v_act, linear
+// in time between t_n and t_n + dt; act < 0 = not reached)
+void launch_gather_v_act(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst, double* act,
+                         double v_act, double t_n, double dt);
+// out[q] = sum_k wts[q nv + k] u[ids[q nv + k]]
+void launch_probe(hipStream_t s, int np, int nv, const int64_t* ids, const double* wts, const double* u,
+                  double* out);
 void launch_dot_reduce(hipStream_t s, int64_t n, const double* a, const double* b, Reduce rd, double* out);
 void launch_shift(hipStream_t s, int64_t n, double* x, const double* sc, int slot, double den);
 // y2[pos] = scale M_H (gamma V - chi (I_ion - I_st)) - sub[pos] (sub may be

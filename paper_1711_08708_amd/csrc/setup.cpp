@@ -150,6 +150,8 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
     in.n_region_sigma = tissue->n_region_sigma;
     for (int i = 0; i < 3; ++i) { in.sigma_i[i] = tissue->sigma_i[i]; in.sigma_e[i] = tissue->sigma_e[i]; }
     if (!assemble(in, hs.A, err)) return false;
+    hs.xyz.assign(mesh->xyz, mesh->xyz + mesh->n_nodes * mesh->dim);
+    hs.elems.assign(mesh->elems, mesh->elems + mesh->n_elems * (mesh->dim + 1));
     const Assembled& A = hs.A;
     const int64_t N = A.N, NH = A.NH;
     const int d = A.dim;

@@ -31,6 +31,8 @@ struct HostSetup {
     std::vector<double> gnn_static;
     Csr gnn_agg;
     Csr km_int;                    // K_m = gamma M_H + S_m in internal v order
+    std::vector<double> xyz;       // the mesh (caller's numbering), for probe points
+    std::vector<int32_t> elems;
     double setup_seconds = 0.0;
 };
 

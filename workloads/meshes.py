@@ -263,6 +263,13 @@ def thorax2d(n_target=200_000, seed=1, sigma_scale=1.0, n_steps=500,
                 np.array(_SIG_E_2D) * sigma_scale, stim,
                 f"thorax2d_{len(xyz)}", n_steps, tol)
     out["mesh_h"] = h
+    # six body-surface electrodes (the ECG leads of the 2D test case): the
+    # mesh vertices nearest to the torso boundary at these angles, from the
+    # top of the slice round the side the heart lies on
+    used = xyz[np.unique(elems)]
+    ang = np.deg2rad([80.0, 100.0, 120.0, 140.0, 160.0, 180.0])
+    tgt = np.stack([a * np.cos(ang), b * np.sin(ang)], axis=1)
+    out["electrodes"] = np.array([used[np.argmin(np.linalg.norm(used - t, axis=1))] for t in tgt])
     return out
 
 
