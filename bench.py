@@ -295,6 +295,20 @@ def _variants(torch, B, solver, args):
         out[name]["speedup_vs_plain"] = round(out[name]["steps_per_s"] / base, 3)
     out["steps"] = [n1, n1 + args.variant_steps]
     out["chebyshev_pk_steps"] = args.pk_steps
+    # a change of time step: the factored P_K refactors K_m on the host, the
+    # Chebyshev P_K only updates device copies; then steps at dt / 2
+    solver.set_precision(B.PREC_FP64)
+    solver.set_precond(B.PRECOND_PLAIN)
+    dt0 = solver.dt
+    out["dt_change"] = {"dt_ms": [dt0, dt0 / 2]}
+    for name, pk in (("cholesky", chol), ("chebyshev", cheb)):
+        solver.set_pk(pk, args.pk_steps)
+        sec = solver.set_dt(dt0 / 2)
+        st = [t.clone() for t in saved]
+        _, ws, it = _timed_steps(torch, solver, st, n1, 10)
+        out["dt_change"][name] = {"set_dt_s": round(sec, 4), "steps_per_s": round(10 / ws, 2),
+                                  "cg_iterations_per_step": round(it / 10, 2)}
+        solver.set_dt(dt0)
     solver.set_precision(B.PREC_FP64)
     solver.set_precond(B.PRECOND_PLAIN)
     solver.set_pk(main_pk["kind"], max(1, main_pk["steps"]), main_pk["lo"], main_pk["hi"])

@@ -196,6 +196,22 @@ bido_status bido_solve(bido_ctx* ctx, const double* rhs, double* x,
  * solve as flexible CG in FP64.                                         */
 bido_status bido_set_precision(bido_ctx* ctx, int precision);
 
+/* Change the time step (steps then pass this dt).  gamma = chi cm / dt
+ * (2 gamma for Crank-Nicolson) enters only the v-v diagonal of Lambda and
+ * K_m = gamma M_H + S_m (Sec. 3.2, Sec. 5.2); S_1 and its factor P_1 do not
+ * depend on dt.  With the factored P_K (BIDO_PK_CHOLESKY) K_m is factored
+ * again on the host in its elimination tree and uploaded, with the plan
+ * options in use; with the Chebyshev P_K nothing is factored: the device
+ * copies of Lambda's values, K_m and its inverse diagonal are replaced and
+ * an estimated interval is estimated again (an explicit one is kept).  The
+ * stimulus window keeps its times (its step range follows dt).  A trained
+ * learned stencil is dropped (BIDO_PRECOND_LEARNED falls back to the plain
+ * preconditioner; train again at the new step).  Captured graphs are
+ * rebuilt.  seconds (may be null): wall time of the call.  Errors:
+ * BIDO_ERR_ARG for dt <= 0, BIDO_ERR_STATE inside a batch,
+ * BIDO_ERR_NOT_SPD if the new K_m cannot be factored.  Synchronises.    */
+bido_status bido_set_dt(bido_ctx* ctx, double dt, double* seconds);
+
 /* Override tolerance and iteration cap (tol <= 0 / max_iter <= 0 keep the
  * current values).                                                      */
 bido_status bido_set_solver(bido_ctx* ctx, double tol, int max_iter);

@@ -64,6 +64,10 @@ bido_status bido_host_pk_interval(const bido_host* h, int lanczos_steps, double*
  * barycentric weights there (ids, wts: n x (dim + 1)).  BIDO_ERR_ARG if a
  * point lies outside the mesh.                                           */
 bido_status bido_host_locate(const bido_host* h, int n, const double* pts, int64_t* ids, double* wts);
+
+/* The host part of bido_set_dt: gamma, the v-v diagonal of Lambda, K_m and
+ * (refactor != 0) the factor of K_m at the new dt.                        */
+bido_status bido_host_set_dt(bido_host* h, double dt, int refactor);
 bido_status bido_host_index(const bido_host* h, int which, int64_t* n, const int64_t** data);
 
 /* Sizes of a factor: entries uncompressed / as stored, low-rank blocks,

@@ -132,6 +132,7 @@ ABI = {
     "bido_inner_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p]),
     "bido_set_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "bido_set_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, _c_double_p]),
     "bido_set_pk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_double]),
     "bido_record": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, _c_double_p,
@@ -180,6 +181,7 @@ ABI = {
     "bido_host_vec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p,
                                      ctypes.POINTER(_c_double_p)]),
     "bido_host_pk_interval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p]),
+    "bido_host_set_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]),
     "bido_host_locate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p, _c_i64_p, _c_double_p]),
     "bido_host_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p,
                                        ctypes.POINTER(_c_i64_p)]),
@@ -342,6 +344,14 @@ class Solver:
     def inner_solve(self, which, b, x):
         n = self.N if which == FACTOR_P1 else self.NH
         _check(lib.bido_inner_solve(self.ctx, int(which), self._dev(b, n), self._dev(x, n)))
+
+    def set_dt(self, dt):
+        """Change the time step; returns the seconds the change took."""
+        sec = ctypes.c_double()
+        _check(lib.bido_set_dt(self.ctx, float(dt), ctypes.byref(sec)))
+        self.dt = float(dt)
+        self.params.dt = float(dt)
+        return sec.value
 
     def set_pk(self, kind, steps=3, lo=0.0, hi=0.0):
         """P_K by its factor (PK_CHOLESKY) or by `steps` Chebyshev-accelerated
@@ -573,6 +583,9 @@ class HostSetup:
         c = np.ctypeslib.as_array(col, shape=(nnz.value,)).copy() if nnz.value else np.zeros(0, np.int32)
         v = np.ctypeslib.as_array(val, shape=(nnz.value,)).copy() if nnz.value else np.zeros(0)
         return sp.csr_matrix((v, c, p), shape=(n.value, n.value))
+
+    def set_dt(self, dt, refactor=True):
+        _check(lib.bido_host_set_dt(self.h, float(dt), 1 if refactor else 0), host=True)
 
     def locate(self, points):
         """(vertex ids, barycentric weights) of the element holding each point."""

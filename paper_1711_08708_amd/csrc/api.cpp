@@ -357,6 +357,7 @@ struct bido_ctx {
     int pk_kind = BIDO_PK_CHOLESKY;
     int cheb_steps = 0;
     double cheb_lo = 0.0, cheb_hi = 0.0;
+    bool cheb_auto = false;           // interval estimated by the library
     ChebCoef cheb;
     CsrDev km;                        // K_m, internal v order (uploaded on first use)
     double *km_dinv = nullptr, *ch_r = nullptr, *ch_d[2] = {nullptr, nullptr};
@@ -1867,6 +1868,18 @@ bido_status bido_inner_solve(bido_ctx* c, int which, const double* b, double* x)
     return BIDO_OK;
 }
 
+// Interval of the Chebyshev P_K for the current K_m (host Lanczos).
+static bido_status estimate_pk_interval(bido_ctx* c, double* lo, double* hi) {
+    std::vector<double> gm(c->NH);
+    for (int64_t l = 0; l < c->NH; ++l) gm[c->hs.v_pos[l]] = c->hs.gamma * c->hs.mh_loc[l];
+    ChebInterval iv;
+    std::string err;
+    if (!chebyshev_interval(c->hs.km_int, gm, BIDO_PK_LANCZOS_STEPS, iv, err)) return fail(BIDO_ERR_ARG, err);
+    *lo = iv.lo;
+    *hi = iv.hi;
+    return BIDO_OK;
+}
+
 bido_status bido_set_pk(bido_ctx* c, int kind, int steps, double lo, double hi) {
     if (!c) return fail(BIDO_ERR_ARG, "null context");
     if (kind != BIDO_PK_CHOLESKY && kind != BIDO_PK_CHEBYSHEV) return fail(BIDO_ERR_ARG, "bad P_K kind");
@@ -1882,14 +1895,9 @@ bido_status bido_set_pk(bido_ctx* c, int kind, int steps, double lo, double hi) 
         return fail(BIDO_ERR_ARG, "bad Chebyshev interval (0 < lo < hi, or both 0 to estimate)");
     const Csr& K = c->hs.km_int;
     if (K.n != c->NH) return fail(BIDO_ERR_STATE, "K_m is not available");
-    if (lo == 0.0) {
-        std::vector<double> gm(c->NH);
-        for (int64_t l = 0; l < c->NH; ++l) gm[c->hs.v_pos[l]] = c->hs.gamma * c->hs.mh_loc[l];
-        ChebInterval iv;
-        std::string err;
-        if (!chebyshev_interval(K, gm, BIDO_PK_LANCZOS_STEPS, iv, err)) return fail(BIDO_ERR_ARG, err);
-        lo = iv.lo;
-        hi = iv.hi;
+    const bool estimate = lo == 0.0;
+    if (estimate) {
+        if (bido_status e = estimate_pk_interval(c, &lo, &hi)) return e;
     }
     if (!c->km.ptr && c->NH > 0) {
         if (bido_status e = CsrHostView::up(K, c->km)) return e;
@@ -1908,7 +1916,54 @@ bido_status bido_set_pk(bido_ctx* c, int kind, int steps, double lo, double hi) 
     c->cheb_steps = steps;
     c->cheb_lo = lo;
     c->cheb_hi = hi;
+    c->cheb_auto = estimate;
     c->cheb = chebyshev_coefficients(lo, hi, steps);
+    return BIDO_OK;
+}
+
+bido_status bido_set_dt(bido_ctx* c, double dt, double* seconds) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BIDO_ERR_ARG, "dt must be > 0");
+    if (c->batched) return fail(BIDO_ERR_STATE, "context is in a batch");
+    auto t0 = std::chrono::steady_clock::now();
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (seconds) *seconds = 0.0;
+    if (dt_matches(c, dt)) return BIDO_OK;
+    const bool refactor = c->pk_kind == BIDO_PK_CHOLESKY;
+    std::string err;
+    if (!host_set_dt(c->hs, dt, refactor, err)) return fail(BIDO_ERR_NOT_SPD, err);
+    c->params.dt = dt;
+    c->drop_graphs();
+    // Lambda: only its v-v diagonal changed, but the values go up whole
+    HIP_OK(hipMemcpy(c->lam.val, c->hs.lam.val.data(), c->hs.lam.val.size() * sizeof(double),
+                     hipMemcpyHostToDevice));
+    if (refactor) {
+        const PlanOptions opts = c->pk.opts;
+        c->pk.release();
+        if (bido_status e = build_factor_dev(c->hs.pk, true, c->pk, c->hs.params.n_threads, &opts)) return e;
+        c->hs.pk.trim_top_cache(c->pk.top_h);
+        HIP_OK(poison_workspace(c->pk));
+    }
+    if (c->km.ptr) {      // the Chebyshev P_K's copy of K_m and its inverse diagonal
+        const Csr& K = c->hs.km_int;
+        HIP_OK(hipMemcpy(c->km.val, K.val.data(), K.val.size() * sizeof(double), hipMemcpyHostToDevice));
+        std::vector<double> dinv(c->NH, 0.0);
+        for (int64_t i = 0; i < c->NH; ++i)
+            for (int64_t p = K.ptr[i]; p < K.ptr[i + 1]; ++p)
+                if (K.col[p] == i) dinv[i] += K.val[p];
+        for (auto& x : dinv) x = 1.0 / x;
+        HIP_OK(hipMemcpy(c->km_dinv, dinv.data(), dinv.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (c->pk_kind == BIDO_PK_CHEBYSHEV && c->cheb_auto) {
+        if (bido_status e = estimate_pk_interval(c, &c->cheb_lo, &c->cheb_hi)) return e;
+        c->cheb = chebyshev_coefficients(c->cheb_lo, c->cheb_hi, c->cheb_steps);
+    }
+    // the learned stencil was fitted to K_m at the old step: drop it
+    if (c->pk_learned.nodes) c->pk_learned.release();
+    c->gnn.stencil_ready = false;
+    if (c->precond == BIDO_PRECOND_LEARNED) c->precond = BIDO_PRECOND_PLAIN;
+    HIP_OK(hipDeviceSynchronize());
+    if (seconds) *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BIDO_OK;
 }
 

@@ -72,6 +72,13 @@ bido_status bido_host_pk_interval(const bido_host* h, int lanczos_steps, double*
     return BIDO_OK;
 }
 
+bido_status bido_host_set_dt(bido_host* h, double dt, int refactor) {
+    if (!h) return hfail(BIDO_ERR_ARG, "null argument");
+    std::string err;
+    if (!bido::host_set_dt(h->hs, dt, refactor != 0, err)) return hfail(BIDO_ERR_ARG, err);
+    return BIDO_OK;
+}
+
 bido_status bido_host_locate(const bido_host* h, int n, const double* pts, int64_t* ids, double* wts) {
     if (!h || n < 0 || (n > 0 && (!pts || !ids || !wts))) return hfail(BIDO_ERR_ARG, "bad argument");
     std::vector<int64_t> vi;

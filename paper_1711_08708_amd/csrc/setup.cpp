@@ -265,7 +265,56 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
     gnn_inputs(in, A, hs);
     hs.stim_n0 = std::llround(tissue->stim_t0 / P.dt);
     hs.stim_n1 = std::llround(tissue->stim_t1 / P.dt);
+    hs.stim_t0 = tissue->stim_t0;
+    hs.stim_t1 = tissue->stim_t1;
     hs.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return true;
+}
+
+}  // namespace bido
+
+namespace bido {
+
+bool host_set_dt(HostSetup& hs, double dt, bool refactor, std::string& err) {
+    bido_params& P = hs.params;
+    if (!(dt > 0.0) || !std::isfinite(dt)) { err = "dt must be > 0"; return false; }
+    const Assembled& A = hs.A;
+    const int64_t N = A.N, NH = A.NH;
+    const double gamma = P.chi * P.cm / dt * (P.scheme == BIDO_SCHEME_CN ? 2.0 : 1.0);
+    const NdTree& tk = hs.pk.tree;
+    // K_m = gamma M_H + S_m, as at set-up
+    Csr Km = add_diag(A.Sm, A.mH, gamma);
+    if (Km.n < 0) { err = "missing diagonal in S_m"; return false; }
+    Csr Kmp = permute(Km, tk.perm, tk.iperm);
+    // the v-v diagonal of Lambda: S_i(k, k) + gamma m_k
+    std::vector<double> sdiag(NH, 0.0);
+    bool found = true;
+    for (int64_t k = 0; k < NH; ++k) {
+        bool f = false;
+        for (int64_t q = A.Si.ptr[k]; q < A.Si.ptr[k + 1]; ++q)
+            if (A.Si.col[q] == k) { sdiag[k] = A.Si.val[q]; f = true; }
+        found = found && f;
+    }
+    if (!found) { err = "missing diagonal in S_i"; return false; }
+    if (refactor) {
+        Factor nf;
+        nf.tree = hs.pk.tree;
+        std::string e2;
+        if (!multifrontal(Kmp, nf, -1, P.n_threads, e2)) { err = "P_K: " + e2; return false; }
+        compress(nf, hs.pk.xyz.data(), hs.pk.dim, hs.pk.eps, hs.pk.eta, P.n_threads);
+        hs.pk = std::move(nf);
+    }
+    Csr& L = hs.lam;
+    for (int64_t l = 0; l < NH; ++l) {
+        const int64_t k = tk.perm[l], row = N + l;
+        for (int64_t q = L.ptr[row]; q < L.ptr[row + 1]; ++q)
+            if (L.col[q] == row) L.val[q] = sdiag[k] + gamma * A.mH[k];
+    }
+    hs.km_int = std::move(Kmp);
+    hs.gamma = gamma;
+    P.dt = dt;
+    hs.stim_n0 = std::llround(hs.stim_t0 / dt);
+    hs.stim_n1 = std::llround(hs.stim_t1 / dt);
     return true;
 }
 

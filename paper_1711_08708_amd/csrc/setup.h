@@ -23,6 +23,7 @@ struct HostSetup {
     std::vector<double> mh_loc;    // lumped M_H, heart-local order
     std::vector<double> stim_loc;  // stimulus amplitude per heart vertex (heart-local)
     int64_t stim_n0 = 0, stim_n1 = 0;
+    double stim_t0 = 0.0, stim_t1 = 0.0;   // stimulus window [ms]
     double gamma = 0.0;
     double msum = 0.0;
     // learned correction: static vertex features (N_H x 15, heart-local order:
@@ -38,5 +39,12 @@ struct HostSetup {
 
 bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_params* params,
                 HostSetup& hs, std::string& err);
+
+// New time step: gamma (the coefficient of M_H in Lambda and K_m, Sec. 3.2)
+// and the stimulus step range follow dt; the v-v diagonal of Lambda and
+// K_m are recomputed as at set-up (bit-identical to a set-up at dt).  With
+// refactor, K_m is factored again in its elimination tree (P_1 does not
+// depend on dt).
+bool host_set_dt(HostSetup& hs, double dt, bool refactor, std::string& err);
 
 }  // namespace bido
