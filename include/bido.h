@@ -204,9 +204,10 @@ bido_status bido_set_precision(bido_ctx* ctx, int precision);
  * options in use; with the Chebyshev P_K nothing is factored: the device
  * copies of Lambda's values, K_m and its inverse diagonal are replaced and
  * an estimated interval is estimated again (an explicit one is kept).  The
- * stimulus window keeps its times (its step range follows dt).  A trained
- * learned stencil is dropped (BIDO_PRECOND_LEARNED falls back to the plain
- * preconditioner; train again at the new step).  Captured graphs are
+ * stimulus window keeps its times (its step range follows dt).  The
+ * learned correction is set up again from scratch (its pairs, weights and
+ * stencil were fitted to K_m at the old step; collect and train again) and
+ * the preconditioner returns to BIDO_PRECOND_PLAIN.  Captured graphs are
  * rebuilt.  seconds (may be null): wall time of the call.  Errors:
  * BIDO_ERR_ARG for dt <= 0, BIDO_ERR_STATE inside a batch,
  * BIDO_ERR_NOT_SPD if the new K_m cannot be factored.  Synchronises.    */

@@ -1958,10 +1958,12 @@ bido_status bido_set_dt(bido_ctx* c, double dt, double* seconds) {
         if (bido_status e = estimate_pk_interval(c, &c->cheb_lo, &c->cheb_hi)) return e;
         c->cheb = chebyshev_coefficients(c->cheb_lo, c->cheb_hi, c->cheb_steps);
     }
-    // the learned stencil was fitted to K_m at the old step: drop it
+    // the learned correction (samples, loss weight, stencil and its factor)
+    // was fitted to K_m at the old step: set it up again from scratch
     if (c->pk_learned.nodes) c->pk_learned.release();
-    c->gnn.stencil_ready = false;
-    if (c->precond == BIDO_PRECOND_LEARNED) c->precond = BIDO_PRECOND_PLAIN;
+    c->gnn.release();
+    if (bido_status e = gnn_setup(c)) return e;
+    c->precond = BIDO_PRECOND_PLAIN;
     HIP_OK(hipDeviceSynchronize());
     if (seconds) *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BIDO_OK;

@@ -89,3 +89,31 @@ def test_set_dt_arguments_and_batch(torch):
     batch.close()
     for s in svs:
         s.close()
+
+
+def test_set_dt_resets_the_learned_correction(torch):
+    """Pairs and a trained stencil belong to K_m at the old step: after the
+    change the sample store is empty, the learned stencil cannot be selected
+    until trained again, and training at the new step works."""
+    import ctypes
+    import paper_1711_08708_amd as B
+    cfg = w.thorax2d(n_target=3000, seed=11)
+    sv = B.Solver(cfg, tol=1e-10)
+    v, h, u = sv.state()
+    col = sv.learn_collect(v, h, u, 0, 6, max_samples=64)
+    assert col["samples"] > 0
+    ts = sv.learn_train(kind=B.LEARN_STENCIL, epochs=2, batch=8, lr=2e-3, seed=0, n_val=1)
+    if ts["spd"]:
+        sv.set_precond(B.PRECOND_LEARNED)
+    sv.set_dt(0.05)
+    n = ctypes.c_int()
+    B._check(B.lib.bido_learn_samples(sv.ctx, ctypes.byref(n)))
+    assert n.value == 0
+    with pytest.raises(B.BidoError, match="BIDO_ERR_STATE"):
+        sv.set_precond(B.PRECOND_LEARNED)
+    assert sv.step(v, h, u, 6)["converged"] == 1
+    col = sv.learn_collect(v, h, u, 7, 6, max_samples=64)
+    assert col["samples"] > 0
+    ts = sv.learn_train(kind=B.LEARN_STENCIL, epochs=2, batch=8, lr=2e-3, seed=0, n_val=1)
+    assert np.isfinite(ts["loss_last"])
+    sv.close()
