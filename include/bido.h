@@ -210,7 +210,10 @@ bido_status bido_set_precision(bido_ctx* ctx, int precision);
  * the preconditioner returns to BIDO_PRECOND_PLAIN.  Captured graphs are
  * rebuilt.  seconds (may be null): wall time of the call.  Errors:
  * BIDO_ERR_ARG for dt <= 0, BIDO_ERR_STATE inside a batch,
- * BIDO_ERR_NOT_SPD if the new K_m cannot be factored.  Synchronises.    */
+ * BIDO_ERR_NOT_SPD if the new K_m cannot be factored (the context keeps
+ * its old step), BIDO_ERR_DEVICE for a failed upload (the context then
+ * refuses every step with BIDO_ERR_DT_MISMATCH until a later call
+ * succeeds).  Synchronises.                                              */
 bido_status bido_set_dt(bido_ctx* ctx, double dt, double* seconds);
 
 /* Override tolerance and iteration cap (tol <= 0 / max_iter <= 0 keep the

@@ -1921,19 +1921,10 @@ bido_status bido_set_pk(bido_ctx* c, int kind, int steps, double lo, double hi) 
     return BIDO_OK;
 }
 
-bido_status bido_set_dt(bido_ctx* c, double dt, double* seconds) {
-    if (!c) return fail(BIDO_ERR_ARG, "null context");
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BIDO_ERR_ARG, "dt must be > 0");
-    if (c->batched) return fail(BIDO_ERR_STATE, "context is in a batch");
-    auto t0 = std::chrono::steady_clock::now();
-    HIP_OK(hipStreamSynchronize(c->stream));
-    if (seconds) *seconds = 0.0;
-    if (dt_matches(c, dt)) return BIDO_OK;
-    const bool refactor = c->pk_kind == BIDO_PK_CHOLESKY;
-    std::string err;
-    if (!host_set_dt(c->hs, dt, refactor, err)) return fail(BIDO_ERR_NOT_SPD, err);
-    c->params.dt = dt;
-    c->drop_graphs();
+// Device side of a time-step change (the host state is already updated):
+// Lambda's values, the K_m factor or the Chebyshev P_K's copies, and the
+// learned correction set up again.
+static bido_status set_dt_device(bido_ctx* c, bool refactor) {
     // Lambda: only its v-v diagonal changed, but the values go up whole
     HIP_OK(hipMemcpy(c->lam.val, c->hs.lam.val.data(), c->hs.lam.val.size() * sizeof(double),
                      hipMemcpyHostToDevice));
@@ -1965,6 +1956,27 @@ bido_status bido_set_dt(bido_ctx* c, double dt, double* seconds) {
     if (bido_status e = gnn_setup(c)) return e;
     c->precond = BIDO_PRECOND_PLAIN;
     HIP_OK(hipDeviceSynchronize());
+    return BIDO_OK;
+}
+
+bido_status bido_set_dt(bido_ctx* c, double dt, double* seconds) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BIDO_ERR_ARG, "dt must be > 0");
+    if (c->batched) return fail(BIDO_ERR_STATE, "context is in a batch");
+    auto t0 = std::chrono::steady_clock::now();
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (seconds) *seconds = 0.0;
+    if (dt_matches(c, dt)) return BIDO_OK;
+    const bool refactor = c->pk_kind == BIDO_PK_CHOLESKY;
+    std::string err;
+    if (!host_set_dt(c->hs, dt, refactor, err)) return fail(BIDO_ERR_NOT_SPD, err);
+    // from here on the host state is at the new step: a failure below leaves
+    // the context refusing every step (dt NaN) until a later call succeeds
+    c->params.dt = std::nan("");
+    c->drop_graphs();
+    bido_status e = set_dt_device(c, refactor);
+    if (e) return e;
+    c->params.dt = dt;
     if (seconds) *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BIDO_OK;
 }
