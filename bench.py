@@ -47,7 +47,8 @@ def _parse():
                     help="do not record activation times and electrode potentials (thorax workloads)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the sampled parity check")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=8,
+                    help="oracle steps timed for the CPU baseline (about 10-30 s of host work)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mixed / learned / learned+mixed comparison")
     ap.add_argument("--collect-steps", type=int, default=40,
