@@ -1323,7 +1323,16 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     c->N = hs.A.N;
     c->NH = hs.A.NH;
     c->n2 = c->N + c->NH;
-    c->spmv_group = hs.A.dim == 2 ? 8 : 16;
+    // lanes per row of the sparse products: 2D rows hold ~7 (torso) or ~14
+    // (heart) entries, so 4 lanes cover them in the two unconditional passes
+    // without a pass of dropped loads (measured: the Lambda product 16.1 ->
+    // 13.2 us on thorax200k, 346 -> 281 us on the batch64 union); 3D rows
+    // (~15 and ~30 entries) keep 16
+    c->spmv_group = hs.A.dim == 2 ? 4 : 16;
+    if (const char* eg = std::getenv("BIDO_SPMV_GROUP")) {   // plan knob: lanes per row of the products
+        const int g = std::atoi(eg);
+        if (g == 4 || g == 8 || g == 16 || g == 32) c->spmv_group = g;
+    }
     c->heart_ids = hs.A.heart;
     bido_status e;
     if ((e = CsrHostView::up(hs.lam, c->lam))) return e;
