@@ -627,6 +627,9 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
         p.bwd_wide = o.bwd_wide >= 0 ? o.bwd_wide != 0 : (ew && *ew ? std::atoi(ew) != 0 : true);
         p.used.bwd_wide = p.bwd_wide ? 1 : 0;
     }
+    // wide backward items wanted per level of tall tiles (environment
+    // BIDO_BWD_LEVEL_ITEMS; 0 keeps every tile whole)
+    const int want_items = env_limit("BIDO_BWD_LEVEL_ITEMS", PLAN_BWD_LEVEL_ITEMS, 0, 1 << 20);
     std::vector<std::pair<size_t, size_t>> fspan, bspan, fcspan, bcspan;
     struct LdsSz { size_t f, b; };
     std::vector<LdsSz> lds;
@@ -678,14 +681,38 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     for (int h = lvl0; h <= Hl; ++h) {
         const size_t b0 = p.bwd_items.size(), bc0 = p.bwd_comb.size();
         size_t ldsb = 0;
+        // wide items take a whole column tile (up to the LDS staging bound).
+        // A level of few, tall tiles (3D separators: thousands of rows under
+        // each 64-column tile) would then leave most of the device idle, so
+        // without an explicit row limit its tiles are cut into row ranges
+        // until the level has about BWD_LEVEL_ITEMS items (never below 256
+        // rows; the thin tiles of 2D levels are left whole)
+        int level_rb = PLAN_LDS_DOUBLES;
+        if (p.bwd_wide && o.bwd_rows <= 0 && want_items > 0) {
+            int64_t tiles = 0, rows = 0;
+            for (int id : by_h[h]) {
+                if (is_top[id] || in_sub(id)) continue;
+                const Front& fr = f.fronts[id];
+                const int W = pow2_at_least(std::min(std::max(fr.nI, 1), 64), 64);
+                for (int c0 = 0; c0 < fr.nI; c0 += W) {
+                    ++tiles;
+                    rows += fr.nI + fr.nB - c0;
+                }
+            }
+            if (tiles > 0 && tiles < want_items && rows / tiles > 1024) {
+                int64_t rb = rows / want_items;
+                int pw = 256;
+                while (pw * 2 <= rb && pw * 2 <= PLAN_LDS_DOUBLES) pw *= 2;
+                level_rb = pw;
+            }
+        }
         for (int id : by_h[h]) {
             if (is_top[id] || in_sub(id)) continue;
             const Front& fr = f.fronts[id];
             const int nI = fr.nI, nF = fr.nI + fr.nB;
             if (nI == 0) continue;
             const int W = pow2_at_least(std::min(nI, 64), 64);
-            // wide items take a whole column tile (up to the LDS staging bound)
-            const int RB = p.bwd_wide ? (o.bwd_rows > 0 ? bwd_maxr : PLAN_LDS_DOUBLES)
+            const int RB = p.bwd_wide ? (o.bwd_rows > 0 ? bwd_maxr : level_rb)
                            : bwd_maxr == PLAN_BWD_MAXR ? std::min(PLAN_BWD_MAXR, std::max(64, 8192 / W))
                                                        : bwd_maxr;
             for (int c0 = 0; c0 < nI; c0 += W) {

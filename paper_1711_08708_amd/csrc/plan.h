@@ -82,6 +82,7 @@ constexpr int PLAN_FWD_ROWS = 64;      // forward row tile (one row per lane)
 constexpr int PLAN_FWD_COLS = 128;     // forward column chunk per work item (4 waves)
 constexpr int PLAN_BWD_MAXR = 512;     // backward rows per 256-thread work item (LDS staging)
 constexpr int PLAN_BWD_WIDE = 1024;    // threads of a wide backward work item
+constexpr int PLAN_BWD_LEVEL_ITEMS = 512; // wide backward items wanted per level (2 per CU)
 constexpr int PLAN_LDS_DOUBLES = 4096; // bound of the LDS staging per level item
 constexpr int PLAN_TOP_MAX = 6144;     // max n_top (w_top staged in LDS, FP64)
 constexpr int PLAN_HODLR_LEAF = 64;    // leaf size of the hierarchical top

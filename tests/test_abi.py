@@ -361,3 +361,22 @@ def test_forest_with_shared_subtree_budget(total, monkeypatch):
         print(which, total, plan, top)
         for lo, n, ref in refs:
             assert np.abs(emu[lo:lo + n] - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_tall_backward_tiles_are_split_and_still_exact(monkeypatch):
+    """3D separators give level tiles of thousands of rows; the default plan
+    cuts them into row ranges (with a combine step) when a level would
+    otherwise have too few work items, and the host emulation of that plan
+    still reproduces the factor."""
+    import paper_1711_08708_amd as B
+    cfg = w.slab3d(n=40)
+    items = {}
+    for want in ("512", "0"):
+        monkeypatch.setenv("BIDO_BWD_LEVEL_ITEMS", want)
+        h = B.HostSetup(cfg, eps_h=0.0)
+        items[want] = h.factor_plan(B.FACTOR_P1)["n_bwd_items"]
+        N = len(h.index(B.IDX_UPOS))
+        b = np.random.default_rng(0).normal(size=N)
+        x1, x2 = h.factor_apply(B.FACTOR_P1, b), h.factor_emulate(B.FACTOR_P1, b)
+        assert np.abs(x1 - x2).max() <= 1e-12 * np.abs(x1).max()
+    assert items["512"] > items["0"], items
