@@ -183,6 +183,10 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
     HIP_OK(upload(&fd.items, p.fwd_items.data(), p.fwd_items.size()));
     HIP_OK(upload(&fd.bitems, p.bwd_items.data(), p.bwd_items.size()));
     fd.plan.hc = p.hc;
+    // backward subtree heights of at most this many nodes use wave groups:
+    // the thin upper nodes of 2D subtrees gain nothing from them beyond 2,
+    // the fat 3D ones do up to 4 (slab64 tri_bwd_sub 133 -> 102 us)
+    fd.plan.bwd_group_max = f.dim == 3 ? 4 : 2;
     fd.lvl0 = p.lvl0;
     fd.plan.n_sub = p.n_sub;
     fd.plan.sub_maxw = p.sub_maxw;

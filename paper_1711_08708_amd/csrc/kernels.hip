@@ -1283,10 +1283,11 @@ template <typename T>
 void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
                         const int64_t* bidx, const double* y, double* x) {
     if (P.n_sub == 0) return;
-    static const int group_max = [] {
+    static const int env_max = [] {
         const char* e = std::getenv("BIDO_BWD_GROUP_MAXN");
-        return e && *e ? std::max(0, std::min(SUB_NW / 2, std::atoi(e))) : 2;
+        return e && *e ? std::max(0, std::min(SUB_NW / 2, std::atoi(e))) : -1;
     }();
+    const int group_max = env_max >= 0 ? env_max : std::max(0, std::min(SUB_NW / 2, P.bwd_group_max));
     k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel, bidx, y, x, group_max,
                                                    P.skip);
 }

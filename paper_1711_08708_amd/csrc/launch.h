@@ -51,6 +51,7 @@ struct TriPlan {
     TriNode* sub_tn = nullptr;    // device: the same nodes' records, in that order
     int32_t* sub_hoff = nullptr;  // device: n_sub x (hc+2) height offsets
     int sub_maxw = 0;             // max nI below the cut
+    int bwd_group_max = 2;        // backward subtree heights with <= this many nodes use wave groups
     double* scratch = nullptr;    // partial sums of split tiles
     const uint8_t* skip = nullptr; // device, per tree of a merged forest: 1 = leave its nodes alone
     // dense top (n_top = 0: none): x[top_pos] = S_top^-1 w_top
