@@ -202,3 +202,28 @@ def test_set_pk_arguments_and_switching(torch):
         v, h, u = sv.state()
         res.append(sv.step(v, h, u, 0)["iterations"])
     assert res[0] == res[1]
+
+
+def test_thorax200k_solve_parity_with_chebyshev_pk(torch):
+    """Full-size thorax slice (200,656 vertices, 25,768 heart vertices) with
+    the polynomial P_K at its default three steps: the normalised solution
+    of one step's system matches the oracle's sparse direct solve."""
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd
+    cfg = w.make_config("thorax200k")
+    s = bd.System(cfg)
+    rng = np.random.default_rng(7)
+    Y = s.rhs(rng.uniform(0, 100, s.NH), rng.uniform(0, 1, s.NH), 0)
+    Xo = s.solve(Y)
+    Uo, Vo = s.to_global_u(Xo[:s.N]), Xo[s.N:]
+    sv = B.Solver(cfg, tol=1e-12)
+    sv.set_pk(B.PK_CHEBYSHEV, 3)
+    rhs = torch.tensor(np.concatenate([s.to_global_u(Y[:s.N]), Y[s.N:]]), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(rhs)
+    st = sv.solve(rhs, x, tol=1e-12)
+    x = x.cpu().numpy()
+    eu = np.linalg.norm(x[:s.N] - Uo) / np.linalg.norm(Uo)
+    ev = np.linalg.norm(x[s.N:] - Vo) / np.linalg.norm(Vo)
+    print(f"thorax200k Chebyshev P_K: iterations {st['iterations']} e_u {eu:.2e} e_v {ev:.2e}", flush=True)
+    assert st["converged"] == 1
+    assert eu <= TOL_PARITY and ev <= TOL_PARITY
