@@ -245,18 +245,20 @@ def main():
         result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_steps, args.scheme)
 
     if not args.no_variants:
-        result["variants"] = _variants(torch, B, solver, args)
+        result["variants"] = _variants(torch, B, solver, args, cfg)
     print(json.dumps(result), flush=True)
 
 
-def _variants(torch, B, solver, args):
+def _variants(torch, B, solver, args, w_cfg):
     """Plain FP64 vs mixed vs learned vs learned+mixed on the same steps, and
     the factored P_K against the Chebyshev one (FP64 and mixed).
 
     The learned Schur-complement stencil is trained on pairs recorded during
     the first `collect_steps` plain steps from rest and K_m + C is factored;
     every variant then runs the following `variant_steps` steps from the
-    same saved state."""
+    same saved state, and one more step that is checked against the oracle's
+    step from the same state (e_u, e_v)."""
+    import numpy as np
     out = {}
     v, h, u = solver.state()
     solver.set_precond(B.PRECOND_PLAIN)
@@ -283,6 +285,10 @@ def _variants(torch, B, solver, args):
     if ts["spd"]:
         runs += [("learned_fp64", B.PREC_FP64, B.PRECOND_LEARNED, chol),
                  ("learned_mixed", B.PREC_MIXED, B.PRECOND_LEARNED, chol)]
+    sysm = None
+    if not args.no_parity:
+        from oracle import bidomain as bd
+        sysm = bd.System(w_cfg, scheme=args.scheme)
     for name, prec, pc, pk in runs:
         solver.set_precision(prec)
         solver.set_precond(pc)
@@ -291,6 +297,15 @@ def _variants(torch, B, solver, args):
         _, ws, it = _timed_steps(torch, solver, st, n1, args.variant_steps)
         out[name] = {"steps_per_s": round(args.variant_steps / ws, 3),
                      "cg_iterations_per_step": round(it / args.variant_steps, 3)}
+        if sysm is not None:    # one more step of the variant against the oracle's step from its state
+            n = n1 + args.variant_steps
+            V0, h0, U0 = [t.cpu().numpy().copy() for t in st]
+            solver.step(st[0], st[1], st[2], n)
+            Uo, Vo, _ = sysm.step(V0, h0, n, U0=sysm.from_global_u(U0))
+            Uo = sysm.to_global_u(Uo)
+            U, V = st[2].cpu().numpy(), st[0].cpu().numpy()
+            out[name]["e_u"] = float(np.linalg.norm(U - Uo) / np.linalg.norm(Uo))
+            out[name]["e_v"] = float(np.linalg.norm(V - Vo) / np.linalg.norm(Vo))
     base = out["plain_fp64"]["steps_per_s"]
     for name in [r[0] for r in runs[1:]]:
         out[name]["speedup_vs_plain"] = round(out[name]["steps_per_s"] / base, 3)
