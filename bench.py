@@ -44,7 +44,7 @@ def _parse():
                          "Chebyshev-accelerated Jacobi steps on K_m")
     ap.add_argument("--pk-steps", type=int, default=3, help="Chebyshev steps of --pk chebyshev")
     ap.add_argument("--no-record", action="store_true",
-                    help="do not record activation times and electrode potentials (thorax workloads)")
+                    help="do not record activation times (and the electrode potentials of the thorax workloads)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the sampled parity check")
     ap.add_argument("--cpu-steps", type=int, default=8,
@@ -148,9 +148,9 @@ def main():
     tune = None if args.no_tune else solver.autotune()
     if args.pk == "chebyshev":
         solver.set_pk(B.PK_CHEBYSHEV, args.pk_steps)
-    recording = "electrodes" in cfg and not args.no_record
-    if recording:       # activation times and the six electrode potentials, every step
-        solver.record(V_ACT, cfg["electrodes"], max_steps=args.warmup + args.steps)
+    recording = not args.no_record
+    if recording:       # activation times, and the electrode potentials where the workload has electrodes
+        solver.record(V_ACT, cfg.get("electrodes"), max_steps=args.warmup + args.steps if "electrodes" in cfg else 0)
     if args.graphs >= 0:
         solver.set_graphs(bool(args.graphs))
     info = solver.info
@@ -228,7 +228,7 @@ def main():
         result["parity"] = {"step": n0 + args.steps - 1,
                             "e_u": float(np.linalg.norm(U - Uo) / np.linalg.norm(Uo)),
                             "e_v": float(np.linalg.norm(V - Vo) / np.linalg.norm(Vo))}
-        if recording:
+        if recording and "electrodes" in cfg:
             from oracle import record as rc
             rows = solver.record_read()[1]
             ecg_o = rc.probe_values(cfg["xyz"], cfg["elems"], Uo, cfg["electrodes"])
@@ -236,10 +236,11 @@ def main():
 
     if recording:
         act, rows = solver.record_read()
-        result["recording"] = {"v_act_mV": V_ACT, "electrodes": len(cfg["electrodes"]), "rows": len(rows),
+        result["recording"] = {"v_act_mV": V_ACT, "electrodes": len(cfg.get("electrodes", [])), "rows": len(rows),
                                "activated": int((act >= 0).sum()), "heart_vertices": solver.NH,
-                               "latest_activation_ms": float(act.max()),
-                               "ecg_last_row": [round(float(x), 4) for x in rows[-1]]}
+                               "latest_activation_ms": float(act.max())}
+        if len(rows):
+            result["recording"]["ecg_last_row"] = [round(float(x), 4) for x in rows[-1]]
 
     if not args.no_cpu:
         result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_steps, args.scheme)

@@ -227,3 +227,32 @@ def test_thorax200k_solve_parity_with_chebyshev_pk(torch):
     print(f"thorax200k Chebyshev P_K: iterations {st['iterations']} e_u {eu:.2e} e_v {ev:.2e}", flush=True)
     assert st["converged"] == 1
     assert eu <= TOL_PARITY and ev <= TOL_PARITY
+
+
+def test_streams_batch_with_chebyshev_pk(torch):
+    """A batch on streams runs each slice's own steps, Chebyshev P_K included:
+    bit-identical to the slices run alone."""
+    import paper_1711_08708_amd as B
+    cfgs = [w.thorax2d(n_target=3000, seed=11), w.thorax2d(n_target=2000, seed=5), w.square2d(n=24, seed=3)]
+    alone = []
+    for cfg in cfgs:
+        sv = B.Solver(cfg, tol=1e-12)
+        sv.set_pk(B.PK_CHEBYSHEV, 3)
+        v, h, u = sv.state()
+        for n in range(6):
+            sv.step(v, h, u, n)
+        alone.append([t.cpu().numpy() for t in (v, h, u)])
+        sv.close()
+    solvers = [B.Solver(cfg, tol=1e-12) for cfg in cfgs]
+    for sv in solvers:
+        sv.set_pk(B.PK_CHEBYSHEV, 3)
+    batch = B.Batch(solvers, n_streams=2)
+    states = [sv.state() for sv in solvers]
+    tot, _ = batch.run(states, 0, 6)
+    assert tot["converged"] == 1
+    batch.close()
+    for st, ref in zip(states, alone):
+        for a, b in zip([t.cpu().numpy() for t in st], ref):
+            assert np.array_equal(a, b)
+    for sv in solvers:
+        sv.close()
