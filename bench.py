@@ -430,6 +430,25 @@ def _bench_batch(args):
         par[keep[k]["name"]] = {"e_u": float(np.linalg.norm(U - Uo) / np.linalg.norm(Uo)),
                                 "e_v": float(np.linalg.norm(V - Vo) / np.linalg.norm(Vo))}
     result["parity"] = {"step": n_last, "slices": par}
+    if mode == "fused":
+        # three more steps with per-launch events on the union's sweeps: the
+        # roofline of the dominant class (the segmented vector kernels are
+        # not bracketed; rocprofv3 covers them)
+        batch.profile(True)
+        batch.run(states, n_last + 1, 3)
+        prof = batch.profile_read()
+        batch.profile(False)
+        if prof:
+            dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
+            achieved = dom["bytes"] / (dom["ms"] / 1e3) / 1e9
+            result["roofline"] = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1),
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                  "traffic": None, "launches": dom["launches"],
+                                  "avg_launch_us": round(dom["ms"] * 1e3 / dom["launches"], 2),
+                                  "bytes_per_launch": round(dom["bytes"] / dom["launches"])}
+            result["kernels"] = {k: {"launches": p["launches"], "ms": round(p["ms"], 3),
+                                     "GBps": round(p["bytes"] / max(p["ms"], 1e-9) / 1e6, 1)}
+                                 for k, p in prof.items()}
     if not args.no_cpu:
         k = sample[0]
         cb = _cpu_baseline(keep[k], args.cpu_steps)

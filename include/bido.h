@@ -447,6 +447,13 @@ bido_status bido_profile(bido_ctx* ctx, int enable);
  * classes and clear the records.                                         */
 bido_status bido_profile_read(bido_ctx* ctx, bido_kprof* out, int cap, int* n);
 
+/* The same for a fused batch (BIDO_ERR_STATE for a batch on streams, whose
+ * contexts are profiled one by one): the union's triangular sweeps, tops
+ * and Chebyshev steps are bracketed, the segmented vector kernels are not;
+ * while profiling the batch launches eagerly instead of replaying graphs. */
+bido_status bido_batch_profile(bido_batch* b, int enable);
+bido_status bido_batch_profile_read(bido_batch* b, bido_kprof* out, int cap, int* n);
+
 #ifdef __cplusplus
 }
 #endif

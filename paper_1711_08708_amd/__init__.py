@@ -171,6 +171,9 @@ ABI = {
     "bido_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KProf), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int)]),
+    "bido_batch_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KProf), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int)]),
+    "bido_batch_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_host_last_error": (ctypes.c_char_p, []),
     "bido_host_setup": (ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.POINTER(Tissue),
                                        ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_void_p)]),
@@ -507,6 +510,17 @@ class Batch:
             _check(lib.bido_batch_create(arr, len(self.solvers), int(n_streams),
                                          ctypes.c_void_p(stream.cuda_stream), ctypes.byref(b)))
         self.b = b
+
+    def profile(self, on=True):
+        """Fused batches: per-launch events on the union's sweeps (see profile_read)."""
+        _check(lib.bido_batch_profile(self.b, 1 if on else 0))
+
+    def profile_read(self):
+        buf = (KProf * 16)()
+        n = ctypes.c_int()
+        _check(lib.bido_batch_profile_read(self.b, buf, 16, ctypes.byref(n)))
+        return {buf[i].name.decode(): dict(launches=buf[i].launches, ms=buf[i].ms,
+                                           bytes=buf[i].bytes) for i in range(min(n.value, 16))}
 
     def set_graphs(self, on):
         """Fused batches: replay captured iteration graphs (default) or not."""

@@ -430,6 +430,31 @@ namespace {
         }                                                                        \
     } while (0)
 
+// Aggregate a profiler's records by kernel class into out[0..cap) (after
+// the stream has drained) and clear them.
+bido_status profile_aggregate(Profiler& P, bido_kprof* out, int cap, int* n) {
+    bido_kprof agg[K_NCLASS];
+    std::memset(agg, 0, sizeof(agg));
+    for (int k = 0; k < K_NCLASS; ++k) std::strncpy(agg[k].name, kclass_name[k], sizeof(agg[k].name) - 1);
+    for (const auto& r : P.recs) {
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+        agg[r.cls].launches += 1;
+        agg[r.cls].ms += ms;
+        agg[r.cls].bytes += r.bytes;
+    }
+    int m = 0;
+    for (int k = 0; k < K_NCLASS; ++k)
+        if (agg[k].launches > 0) {
+            if (out && m < cap) out[m] = agg[k];
+            ++m;
+        }
+    *n = m;
+    P.recs.clear();
+    P.used = 0;
+    return BIDO_OK;
+}
+
 double csr_bytes(const CsrDev& a, int64_t ncols_read) {
     return 12.0 * a.nnz + 8.0 * (a.n + 1) + 8.0 * ncols_read + 8.0 * a.n;
 }
@@ -1649,6 +1674,24 @@ bido_status bido_batch_info(const bido_batch* b, int* fused, int64_t* n_union, d
     return BIDO_OK;
 }
 
+bido_status bido_batch_profile(bido_batch* b, int enable) {
+    if (!b) return fail(BIDO_ERR_ARG, "null batch");
+    if (!b->fused) return fail(BIDO_ERR_STATE, "only a fused batch has a profiler (profile its contexts instead)");
+    FusedBatch* F = b->fused.get();
+    HIP_OK(hipStreamSynchronize(F->stream));
+    F->prof.recs.clear();
+    F->prof.used = 0;
+    F->prof.on = enable != 0;
+    return BIDO_OK;
+}
+
+bido_status bido_batch_profile_read(bido_batch* b, bido_kprof* out, int cap, int* n) {
+    if (!b || !n) return fail(BIDO_ERR_ARG, "null argument");
+    if (!b->fused) return fail(BIDO_ERR_STATE, "only a fused batch has a profiler");
+    HIP_OK(hipStreamSynchronize(b->fused->stream));
+    return profile_aggregate(b->fused->prof, out, cap, n);
+}
+
 void bido_batch_destroy(bido_batch* b) {
     if (!b) return;
     for (hipStream_t s : b->own) hipStreamSynchronize(s);
@@ -1847,29 +1890,11 @@ bido_status bido_profile(bido_ctx* c, int enable) {
     return BIDO_OK;
 }
 
+
 bido_status bido_profile_read(bido_ctx* c, bido_kprof* out, int cap, int* n) {
     if (!c || !n) return fail(BIDO_ERR_ARG, "null argument");
     HIP_OK(hipStreamSynchronize(c->stream));
-    bido_kprof agg[K_NCLASS];
-    std::memset(agg, 0, sizeof(agg));
-    for (int k = 0; k < K_NCLASS; ++k) std::strncpy(agg[k].name, kclass_name[k], sizeof(agg[k].name) - 1);
-    for (const auto& r : c->prof.recs) {
-        float ms = 0.f;
-        HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
-        agg[r.cls].launches += 1;
-        agg[r.cls].ms += ms;
-        agg[r.cls].bytes += r.bytes;
-    }
-    int m = 0;
-    for (int k = 0; k < K_NCLASS; ++k)
-        if (agg[k].launches > 0) {
-            if (out && m < cap) out[m] = agg[k];
-            ++m;
-        }
-    *n = m;
-    c->prof.recs.clear();
-    c->prof.used = 0;
-    return BIDO_OK;
+    return profile_aggregate(c->prof, out, cap, n);
 }
 
 bido_status bido_inner_solve(bido_ctx* c, int which, const double* b, double* x) {

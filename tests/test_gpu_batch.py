@@ -330,3 +330,41 @@ def test_fused_batch64_sampled_slices_full_size(torch):
     batch.close()
     for s in solvers:
         s.close()
+
+
+def test_fused_batch_profiler(torch):
+    """bido_batch_profile brackets the union's sweeps with events: records
+    for the triangular classes with their algorithmic bytes, no change of
+    the trajectory (the profiled steps launch eagerly), and a batch on
+    streams is refused."""
+    import paper_1711_08708_amd as B
+    cfgs = _slices()[:3]
+    out = []
+    for prof in (False, True):
+        solvers = [B.Solver(cfg, tol=1e-12) for cfg in cfgs]
+        batch = B.Batch(solvers, fused=True)
+        states = [sv.state() for sv in solvers]
+        batch.run(states, 0, 2)
+        if prof:
+            batch.profile(True)
+        batch.run(states, 2, 2)
+        if prof:
+            rec = batch.profile_read()
+            batch.profile(False)
+            print("fused batch profile", {k: (v["launches"], round(v["ms"], 3)) for k, v in rec.items()})
+            for cls in ("tri_fwd_sub", "tri_bwd_sub", "tri_top"):
+                assert rec[cls]["launches"] > 0 and rec[cls]["bytes"] > 0 and rec[cls]["ms"] > 0
+        out.append([[t.cpu().numpy() for t in st] for st in states])
+        batch.close()
+        for sv in solvers:
+            sv.close()
+    for a, b in zip(out[0], out[1]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    solvers = [B.Solver(cfg) for cfg in cfgs[:2]]
+    batch = B.Batch(solvers, n_streams=2)
+    with pytest.raises(B.BidoError, match="BIDO_ERR_STATE"):
+        batch.profile(True)
+    batch.close()
+    for sv in solvers:
+        sv.close()
