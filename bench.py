@@ -445,7 +445,9 @@ def _bench_batch(args):
                                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                                   "traffic": None, "launches": dom["launches"],
                                   "avg_launch_us": round(dom["ms"] * 1e3 / dom["launches"], 2),
-                                  "bytes_per_launch": round(dom["bytes"] / dom["launches"])}
+                                  "bytes_per_launch": round(dom["bytes"] / dom["launches"]),
+                                  "bytes_basis": "nominal: every slice's trees; slices that have met their "
+                                                 "stopping test skip theirs, so the bytes moved are lower"}
             result["kernels"] = {k: {"launches": p["launches"], "ms": round(p["ms"], 3),
                                      "GBps": round(p["bytes"] / max(p["ms"], 1e-9) / 1e6, 1)}
                                  for k, p in prof.items()}
