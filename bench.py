@@ -37,8 +37,8 @@ def _parse():
     ap.add_argument("--eps", type=float, default=1e-8,
                     help="accuracy of the hierarchical top of the inner solves (0: exact)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--scheme", default="euler", choices=["euler", "cn"],
-                    help="time scheme: semi-implicit (Sec. 3.2) or Crank-Nicolson")
+    ap.add_argument("--scheme", default="euler", choices=["euler", "cn", "strang"],
+                    help="time scheme: semi-implicit (Sec. 3.2), Crank-Nicolson or Strang splitting")
     ap.add_argument("--pk", default="cholesky", choices=["cholesky", "chebyshev"],
                     help="P_K inside the block-LU preconditioner: the factor of K_m, or "
                          "Chebyshev-accelerated Jacobi steps on K_m")
@@ -142,7 +142,7 @@ def main():
     cfg = w.make_config(args.config)
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
     t_setup = time.perf_counter()
-    scheme = B.SCHEME_CN if args.scheme == "cn" else B.SCHEME_EULER
+    scheme = {"euler": B.SCHEME_EULER, "cn": B.SCHEME_CN, "strang": B.SCHEME_STRANG}[args.scheme]
     solver = B.Solver(cfg, tol=args.tol, eps_h=args.eps, precision=prec, scheme=scheme)
     t_setup = time.perf_counter() - t_setup
     tune = None if args.no_tune else solver.autotune()
@@ -202,7 +202,8 @@ def main():
         "config": {"workload": f"{cfg['name']}: " + (
                        f"2D thorax-like slice, {solver.N} vertices ({solver.NH} heart)" if cfg["dim"] == 2 else
                        f"3D orthotropic slab, {solver.N} vertices (isolated heart)") +
-                       (", Crank-Nicolson" if args.scheme == "cn" else ", semi-implicit") +
+                       {"cn": ", Crank-Nicolson", "strang": ", Strang splitting (Crank-Nicolson diffusion)",
+                        "euler": ", semi-implicit"}[args.scheme] +
                        f" bidomain step, block-LU/monodomain PCG, {args.precision} preconditioner" +
                        (f", Chebyshev P_K ({args.pk_steps} steps)" if args.pk == "chebyshev" else ""),
                    "scheme": args.scheme, "pk": solver.pk(),

@@ -113,9 +113,15 @@ typedef struct {
  * remark on the time discretisation after Prop. 3: only Step 1 and K
  * change): Lambda and K_m take 2 gamma instead of gamma, and Step 1 becomes
  * Y_2 = M_H (2 gamma V^n - 2 chi (I_ion - I_st)) - S_i (V^n + Pi U^n), so a
- * step reads U^n as well as V^n (both from the state arrays).            */
+ * step reads U^n as well as V^n (both from the state arrays).  STRANG:
+ * Strang operator splitting (named by the same remark): a reaction
+ * half-step of dt/2 (c dV/dt = I_st - I_ion, dw/dt = g, pointwise, Heun's
+ * method) from (V^n, w^n), the Crank-Nicolson diffusion step without the
+ * ionic term from (U^n, V*), and a second reaction half-step from the
+ * diffusion output; second order in dt.  Lambda and K_m as for CN.        */
 #define BIDO_SCHEME_EULER 0
 #define BIDO_SCHEME_CN 1
+#define BIDO_SCHEME_STRANG 2
 
 typedef struct {
     int iterations;        /* PCG iterations of the (last) solve            */

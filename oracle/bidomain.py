@@ -24,6 +24,15 @@ and in K) and
 
   Y = [0 ; M_H (2 gamma V^n - 2 chi (I_ion - I_st)) - S_i (V^n + Pi U^n)].
 
+Strang operator splitting (named by the same remark): the reaction
+c dV/dt = I_st - I_ion(V, W), dW/dt = g(V, W) and the diffusion are advanced
+in turn, reaction over dt/2 (Heun's method, pointwise), diffusion over dt
+(the Crank-Nicolson step above without the ionic term, from (U^n, V*)),
+reaction over dt/2 again; second order in dt.  The diffusion step starts
+from (U*, V*) with U* the potential the elliptic row gives V*
+(S_1 U* = -Pi^T S_i V*): starting from U^n, which belongs to V^n, would
+leave an O(dt) inconsistency and a first-order scheme.
+
 `reaction=False` drops I_ion and I_st (the linear problem, for the
 convergence-order pins).
 
@@ -51,8 +60,8 @@ class System:
     """Assembled bidomain system for one mesh and one time step."""
 
     def __init__(self, cfg, dt=None, scheme="euler", reaction=True):
-        if scheme not in ("euler", "cn"):
-            raise ValueError("scheme is 'euler' or 'cn'")
+        if scheme not in ("euler", "cn", "strang"):
+            raise ValueError("scheme is 'euler', 'cn' or 'strang'")
         self.cfg = cfg
         self.scheme = scheme
         self.reaction = reaction
@@ -69,7 +78,7 @@ class System:
         self.dt = cfg["dt"] if dt is None else dt
         self.gamma = self.chi * self.cm / self.dt
         # the coefficient of M_H in Lambda and K: gamma (Euler), 2 gamma (CN)
-        self.gamma_eff = self.gamma * (2.0 if scheme == "cn" else 1.0)
+        self.gamma_eff = self.gamma * (1.0 if scheme == "euler" else 2.0)
         P = self.perm
         self.S1 = a["S1"][P][:, P].tocsr()
         self.Se = a["Se"][P][:, P].tocsr()
@@ -102,10 +111,13 @@ class System:
         amp = self.cfg["stim_amp"] if self.n0 <= n < self.n1 else 0.0
         return np.where(self.stim_h, amp, 0.0)
 
-    def rhs(self, V, h, n, U=None):
+    def rhs(self, V, h, n, U=None, reaction=None):
         """Step 1: the right-hand side Y (heart-first order).  Crank-Nicolson
-        also needs U^n (heart-first order; constants do not matter, S_i 1 = 0)."""
-        src = ionic.i_ion(V, h, self.cm) - self.i_stim(n) if self.reaction else np.zeros(self.NH)
+        also needs U^n (heart-first order; constants do not matter, S_i 1 = 0).
+        reaction=False overrides the system's flag (the diffusion step of a
+        splitting)."""
+        react = self.reaction if reaction is None else reaction
+        src = ionic.i_ion(V, h, self.cm) - self.i_stim(n) if react else np.zeros(self.NH)
         if self.scheme == "euler":
             Y2 = self.mH * (self.gamma * V - self.chi * src)
         else:
@@ -191,10 +203,48 @@ class System:
             return self.solve_sparse(Y)
         return self.solve_cg(Y, x0=x0)
 
+    def elliptic_u(self, V):
+        """A U with S_1 U = -Pi^T S_i V (the elliptic row for V; defined up
+        to a constant, which S_i Pi ignores): the last u unknown fixed to 0,
+        sparse LU of the rest."""
+        N = self.N
+        b = -(self.PiT @ (self.Si @ V))
+        keep = np.arange(N - 1)
+        A = self.S1[keep][:, keep].tocsc()
+        U = np.zeros(N)
+        U[keep] = spla.spsolve(A, b[keep])
+        return U
+
+    def reaction_half(self, V, h, n):
+        """The reaction over dt/2 by Heun's method: with the rates
+        f(V, W) = (I_st - I_ion(V, W)) / c and g(V, W),
+        V1 = V + tau f, W1 = W + tau g at (V, W), then
+        V* = V + tau/2 (f(V, W) + f(V1, W1)), likewise W* (tau = dt/2)."""
+        tau = 0.5 * self.dt
+        ist = self.i_stim(n) if self.reaction else np.zeros(self.NH)
+
+        def rates(v, w):
+            if not self.reaction:
+                return np.zeros_like(v), np.zeros_like(w)
+            return (ist - ionic.i_ion(v, w, self.cm)) / self.cm, ionic.gate_rate(v, w)
+        f1, g1 = rates(V, h)
+        f2, g2 = rates(V + tau * f1, h + tau * g1)
+        return V + 0.5 * tau * (f1 + f2), h + 0.5 * tau * (g1 + g2)
+
     # ---- a full time step ------------------------------------------------
     def step(self, V, h, n, method="auto", U0=None):
         """Advance (V^n, h^n) -> (U^{n+1}, V^{n+1}, h^{n+1}).  U0: U^n in
-        heart-first order (initial guess; required by Crank-Nicolson)."""
+        heart-first order (initial guess; required by Crank-Nicolson and the
+        splitting)."""
+        if self.scheme == "strang":
+            if U0 is None:
+                raise ValueError("the splitting's diffusion step needs U^n")
+            Vs, hs = self.reaction_half(V, h, n)
+            Us = self.elliptic_u(Vs)
+            Y = self.rhs(Vs, hs, n, Us, reaction=False)
+            X = self.solve(Y, method=method, x0=np.concatenate([U0, Vs]))
+            V1, h1 = self.reaction_half(X[self.N:], hs, n)
+            return X[:self.N], V1, h1
         Y = self.rhs(V, h, n, U0)
         x0 = None
         if U0 is not None:

@@ -19,7 +19,7 @@ ERRORS = {-1: "BIDO_ERR_ARG", -2: "BIDO_ERR_DEVICE", -3: "BIDO_ERR_NOT_SPD",
           -6: "BIDO_ERR_RANGE", -7: "BIDO_ERR_STATE"}
 PREC_FP64, PREC_MIXED = 0, 1
 PRECOND_PLAIN, PRECOND_LEARNED, PRECOND_LEARNED_ADDITIVE = 0, 1, 2
-SCHEME_EULER, SCHEME_CN = 0, 1
+SCHEME_EULER, SCHEME_CN, SCHEME_STRANG = 0, 1, 2
 PK_CHOLESKY, PK_CHEBYSHEV = 0, 1
 PK_MAX_STEPS, PK_LANCZOS_STEPS = 64, 20
 LEARN_STENCIL, LEARN_ADDITIVE = 0, 1

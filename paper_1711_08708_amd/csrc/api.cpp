@@ -365,6 +365,7 @@ struct bido_ctx {
     ChebCoef cheb;
     CsrDev km;                        // K_m, internal v order (uploaded on first use)
     double *km_dinv = nullptr, *ch_r = nullptr, *ch_d[2] = {nullptr, nullptr};
+    double* vs = nullptr;             // Strang splitting: V* after the first reaction half-step
     // recording of the steps (bido_record): activation times, probe rows
     int64_t step_n = 0;               // index of the step in progress
     struct Recording {
@@ -398,7 +399,7 @@ struct bido_ctx {
         CsrHostView::release(auv);
         CsrHostView::release(km);
         for (double* b : {x, r, z, p, q, Y, tA, tB, tC, tD, r_old, sc, m_int, mh_loc, stim_loc, km_dinv, ch_r,
-                          ch_d[0], ch_d[1]})
+                          ch_d[0], ch_d[1], vs})
             hipFree(b);
         hipFree(rd.partials);
         hipFree(rd.counter);
@@ -819,7 +820,8 @@ IonicConst ionic_consts(const bido_ctx* c) {
     k.inv_tau_open = 1.0 / 120.0;
     k.inv_tau_close = 1.0 / 150.0;
     k.v_gate = 0.13;
-    k.scale = c->params.scheme == BIDO_SCHEME_CN ? 2.0 : 1.0;
+    k.scale = c->params.scheme == BIDO_SCHEME_EULER ? 1.0 : 2.0;
+    k.reaction = c->params.scheme == BIDO_SCHEME_STRANG ? 0.0 : 1.0;
     return k;
 }
 
@@ -828,24 +830,48 @@ void step_prepare(bido_ctx* c, double* v, double* w, double* u, int64_t n) {
     hipStream_t s = c->stream;
     const int64_t N = c->N, NH = c->NH;
     c->step_n = n;
-    PROF(c, K_MISC, 24.0 * N, launch_scatter_in(s, N, c->u_pos, u, c->x));   // X0 = (U^n, V^n)
     const double on = (n >= c->hs.stim_n0 && n < c->hs.stim_n1) ? 1.0 : 0.0;
     const double* sub = nullptr;
-    if (c->params.scheme == BIDO_SCHEME_CN) {
-        // Crank-Nicolson: S_i (V^n + Pi U^n) = (Lambda X^n)_v - 2 gamma M_H V^n,
-        // so Y_2 = 2 M_H (2 gamma V^n - chi (I_ion - I_st)) - (Lambda X^n)_v
-        // with 2 gamma the coefficient of M_H in Lambda
-        PROF(c, K_MISC, 24.0 * NH, launch_scatter_in(s, NH, c->v_pos, v, c->x + N));
-        CsrDev rows = c->lam;                    // the v rows of Lambda
-        rows.n = NH;
-        rows.ptr = c->lam.ptr + N;
-        rows.nnz = c->hs.lam.ptr[c->n2] - c->hs.lam.ptr[N];
+    const double* vin = v;
+    CsrDev rows = c->lam;                    // the v rows of Lambda
+    rows.n = NH;
+    rows.ptr = c->lam.ptr + N;
+    rows.nnz = c->hs.lam.ptr[c->n2] - c->hs.lam.ptr[N];
+    if (c->params.scheme == BIDO_SCHEME_STRANG) {
+        // Strang splitting: a reaction half-step first (V* into vs, h* into
+        // w), then the Crank-Nicolson diffusion step without the ionic term
+        // from (U*, V*), U* the elliptic potential of V*
+        // (S_1 U* = -Pi^T S_i V*; one P_1 apply): with tA = S_1^+ Pi^T S_i V*
+        // (up to a constant, which S_i Pi ignores) and X = (0, V*),
+        // S_i (V* + Pi U*) + 2 gamma M_H V* = (Lambda X)_v - S_i Pi tA
+        PROF(c, K_IONIC, 32.0 * NH,
+             launch_strang_in(s, NH, v, w, c->stim_loc, on, 0.5 * c->params.dt, ionic_consts(c), c->vs));
+        vin = c->vs;
+        PROF(c, K_MISC, 24.0 * NH, launch_scatter_in(s, NH, c->v_pos, vin, c->x + N));
+        PROF(c, K_SPMV_CSR, csr_bytes(c->auv, NH),
+             launch_spmv_csr(s, c->auv, c->spmv_group, c->x + N, nullptr, c->tC));   // Pi^T S_i V*
+        tri_solve<double>(c, c->p1, c->p1.panel64, c->p1.panel64_cm, c->tC, c->tA);   // FP64 in both precisions
+        PROF(c, K_MISC, 8.0 * N, launch_fill(s, N, c->x, 0.0));
         PROF(c, K_SPMV_CSR, csr_bytes(rows, c->n2),
-             launch_spmv_csr(s, rows, c->spmv_group, c->x, nullptr, c->tB));
-        sub = c->tB;
+             launch_spmv_csr(s, rows, c->spmv_group, c->x, nullptr, c->tB));          // (Lambda (0, V*))_v
+        PROF(c, K_SPMV_CSR, csr_bytes(c->avu, N) + 8.0 * NH,
+             launch_spmv_csr(s, c->avu, c->spmv_group, c->tA, c->tB, c->tD));
+        sub = c->tD;
+        PROF(c, K_MISC, 24.0 * N, launch_scatter_in(s, N, c->u_pos, u, c->x));      // initial guess U^n
+    } else {
+        PROF(c, K_MISC, 24.0 * N, launch_scatter_in(s, N, c->u_pos, u, c->x));      // X0 = (U^n, V^n)
+        if (c->params.scheme == BIDO_SCHEME_CN) {
+            // Crank-Nicolson: S_i (V^n + Pi U^n) = (Lambda X^n)_v - 2 gamma M_H V^n,
+            // so Y_2 = 2 M_H (2 gamma V^n - chi (I_ion - I_st)) - (Lambda X^n)_v
+            // with 2 gamma the coefficient of M_H in Lambda
+            PROF(c, K_MISC, 24.0 * NH, launch_scatter_in(s, NH, c->v_pos, v, c->x + N));
+            PROF(c, K_SPMV_CSR, csr_bytes(rows, c->n2),
+                 launch_spmv_csr(s, rows, c->spmv_group, c->x, nullptr, c->tB));
+            sub = c->tB;
+        }
     }
     PROF(c, K_IONIC, 64.0 * NH,
-         launch_ionic(s, NH, v, w, c->stim_loc, on, c->mh_loc, c->v_pos, c->Y + N, c->x + N, sub,
+         launch_ionic(s, NH, vin, w, c->stim_loc, on, c->mh_loc, c->v_pos, c->Y + N, c->x + N, sub,
                       ionic_consts(c)));                               // Steps 1 and 3
     PROF(c, K_MISC, 8.0 * N, launch_fill(s, N, c->Y, 0.0));           // Y1 = 0
 }
@@ -857,13 +883,21 @@ void step_begin(bido_ctx* c, double* v, double* w, double* u, int64_t n, PcgRun&
 }
 
 // After Step 2: normalisation (M U, 1) = 0 and the write-back of U, V.
-void step_write(bido_ctx* c, double* v, double* u) {
+void step_write(bido_ctx* c, double* v, double* w, double* u) {
     hipStream_t s = c->stream;
     const int64_t N = c->N, NH = c->NH;
     PROF(c, K_MISC, 16.0 * N, launch_dot_reduce(s, N, c->m_int, c->x, c->rd, c->sc + S_MU));  // (M U, 1)
     PROF(c, K_MISC, 24.0 * N, launch_gather_out(s, N, c->u_pos, c->x, u, c->sc, S_MU, c->hs.msum));
     auto& rec = c->rec;
-    if (rec.on && rec.act_on) {
+    if (c->params.scheme == BIDO_SCHEME_STRANG) {
+        // Strang splitting: the second reaction half-step from (V**, h*)
+        const int64_t n = c->step_n;
+        const double on = (n >= c->hs.stim_n0 && n < c->hs.stim_n1) ? 1.0 : 0.0;
+        const bool act = rec.on && rec.act_on;
+        PROF(c, K_IONIC, 48.0 * NH,
+             launch_strang_out(s, NH, c->v_pos, c->x + N, v, w, c->stim_loc, on, 0.5 * c->params.dt, ionic_consts(c),
+                               act ? rec.act : nullptr, rec.v_act, (double)n * c->params.dt, c->params.dt));
+    } else if (rec.on && rec.act_on) {
         PROF(c, K_MISC, 48.0 * NH,
              launch_gather_v_act(s, NH, c->v_pos, c->x + N, v, rec.act, rec.v_act, (double)c->step_n * c->params.dt,
                                  c->params.dt));
@@ -877,11 +911,11 @@ void step_write(bido_ctx* c, double* v, double* u) {
     }
 }
 
-bido_status step_end(bido_ctx* c, double* v, double* u, const PcgRun& ps, bido_stats* st) {
+bido_status step_end(bido_ctx* c, double* v, double* w, double* u, const PcgRun& ps, bido_stats* st) {
     bido_status e = pcg_result(c, ps, st);
     finish_collection(c, e == BIDO_OK);
     if (e && e != BIDO_ERR_NOT_CONVERGED) return e;
-    step_write(c, v, u);
+    step_write(c, v, w, u);
     return e;
 }
 
@@ -892,7 +926,7 @@ bido_status step_once(bido_ctx* c, double* v, double* w, double* u, int64_t n, b
         HIP_OK(hipStreamSynchronize(c->stream));
         pcg_advance(c, ps);
     }
-    return step_end(c, v, u, ps, st);
+    return step_end(c, v, w, u, ps, st);
 }
 
 bido_status gnn_setup(bido_ctx* c) {
@@ -1376,6 +1410,8 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
         HIP_OK(hipMalloc((void**)b, n2 * sizeof(double)));
     for (double** b : {&c->tA, &c->tC, &c->tD}) HIP_OK(hipMalloc((void**)b, c->N * sizeof(double)));
     HIP_OK(hipMalloc((void**)&c->tB, std::max<int64_t>(c->NH, 1) * sizeof(double)));
+    if (hs.params.scheme == BIDO_SCHEME_STRANG)
+        HIP_OK(hipMalloc((void**)&c->vs, std::max<int64_t>(c->NH, 1) * sizeof(double)));
     HIP_OK(hipMalloc((void**)&c->sc, pp_offset(PP_COUNT) * sizeof(double)));
     // Work vectors start as NaN (all-ones bit pattern): a kernel that reads
     // one before writing it shows up in every result instead of by chance.
@@ -1729,7 +1765,7 @@ static bido_status fused_run(bido_batch* b, double* const* v, double* const* w, 
                 err = sr[i].status;
                 err_msg = "slice " + std::to_string(i) + ": " + sr[i].err;
             }
-            if (!sr[i].status || sr[i].status == BIDO_ERR_NOT_CONVERGED) step_write(b->ctx[i], v[i], u[i]);
+            if (!sr[i].status || sr[i].status == BIDO_ERR_NOT_CONVERGED) step_write(b->ctx[i], v[i], w[i], u[i]);
         }
     }
     HIP_OK(hipEventRecord(b->done[0], F->stream));
@@ -1802,7 +1838,7 @@ bido_status bido_batch_run(bido_batch* b, double* const* v, double* const* w, do
             if (active == 0) break;
         }
         for (int i = 0; i < S; ++i) {
-            const bido_status e = step_end(b->ctx[i], v[i], u[i], ps[i], &last[i]);
+            const bido_status e = step_end(b->ctx[i], v[i], w[i], u[i], ps[i], &last[i]);
             tot[i] += last[i].iterations;
             fb[i] += last[i].fallbacks;
             max_it = std::max(max_it, last[i].iterations);

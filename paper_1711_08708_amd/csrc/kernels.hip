@@ -168,10 +168,57 @@ __global__ void k_ionic_rhs(int64_t nh, const double* __restrict__ v, double* __
         const double iion = c.cm * c.dv * (-hk * vt * vt * (1.0 - vt) * c.inv_tau_in + vt * c.inv_tau_out);
         const double ist = stim[k] * stim_on;
         const int64_t p = pos[k];
-        y2[p] = c.scale * mh[k] * (c.gamma * V - c.chi * (iion - ist)) - (sub ? sub[p] : 0.0);
+        y2[p] = c.scale * mh[k] * (c.gamma * V - c.reaction * c.chi * (iion - ist)) - (sub ? sub[p] : 0.0);
         x2[p] = V;
-        const double g = (vt < c.v_gate) ? (1.0 - hk) * c.inv_tau_open : -hk * c.inv_tau_close;
-        h[k] = hk + c.dt * g;
+        if (c.reaction != 0.0) {
+            const double g = (vt < c.v_gate) ? (1.0 - hk) * c.inv_tau_open : -hk * c.inv_tau_close;
+            h[k] = hk + c.dt * g;
+        }
+    }
+}
+
+// Strang splitting: the reaction c dV/dt = I_st - I_ion(V, h), dh/dt = g(V, h)
+// advanced pointwise by Heun's method over tau = dt/2 before and after the
+// diffusion step
+__device__ __forceinline__ void ms_rates(double V, double hk, double ist, const IonicConst& c, double& dv,
+                                         double& dh) {
+    const double vt = V * c.inv_dv;
+    const double iion = c.cm * c.dv * (-hk * vt * vt * (1.0 - vt) * c.inv_tau_in + vt * c.inv_tau_out);
+    dv = (ist - iion) / c.cm;
+    dh = (vt < c.v_gate) ? (1.0 - hk) * c.inv_tau_open : -hk * c.inv_tau_close;
+}
+__device__ __forceinline__ void ms_heun(double& V, double& hk, double ist, double tau, const IonicConst& c) {
+    double a1, b1, a2, b2;
+    ms_rates(V, hk, ist, c, a1, b1);
+    ms_rates(V + tau * a1, hk + tau * b1, ist, c, a2, b2);
+    V += 0.5 * tau * (a1 + a2);
+    hk += 0.5 * tau * (b1 + b2);
+}
+// first half-step from (V^n, h^n): vs = V*, h <- h*  (heart-local order)
+__global__ void k_strang_in(int64_t nh, const double* __restrict__ v, double* __restrict__ h,
+                            const double* __restrict__ stim, double stim_on, double tau, IonicConst c,
+                            double* __restrict__ vs) {
+    for (int64_t k = blockIdx.x * (int64_t)BLOCK + threadIdx.x; k < nh; k += (int64_t)gridDim.x * BLOCK) {
+        double V = v[k], hk = h[k];
+        ms_heun(V, hk, stim[k] * stim_on, tau, c);
+        vs[k] = V;
+        h[k] = hk;
+    }
+}
+// second half-step from (V**, h*), V** = x2[pos[k]] the diffusion step's
+// output: v <- V^{n+1}, h <- h^{n+1}; with act, the activation time of the
+// step (V^n = the old v, linear in time between t_n and t_n + dt)
+__global__ void k_strang_out(int64_t nh, const int64_t* __restrict__ pos, const double* __restrict__ x2,
+                             double* __restrict__ v, double* __restrict__ h, const double* __restrict__ stim,
+                             double stim_on, double tau, IonicConst c, double* __restrict__ act, double v_act,
+                             double t_n, double dt) {
+    for (int64_t k = blockIdx.x * (int64_t)BLOCK + threadIdx.x; k < nh; k += (int64_t)gridDim.x * BLOCK) {
+        const double vo = v[k];
+        double V = x2[pos[k]], hk = h[k];
+        ms_heun(V, hk, stim[k] * stim_on, tau, c);
+        v[k] = V;
+        h[k] = hk;
+        if (act && act[k] < 0.0 && V >= v_act) act[k] = vo >= v_act ? t_n : t_n + dt * (v_act - vo) / (V - vo);
     }
 }
 
@@ -1167,6 +1214,17 @@ void launch_gather_out(hipStream_t s, int64_t n, const int64_t* pos, const doubl
                        const double* sc, int shift_slot, double shift_den) {
     if (n <= 0) return;
     k_gather_out<<<grid_for(n), BLOCK, 0, s>>>(n, pos, src, dst, sc, shift_slot, shift_den);
+}
+void launch_strang_in(hipStream_t s, int64_t nh, const double* v, double* h, const double* stim, double stim_on,
+                      double tau, const IonicConst& c, double* vs) {
+    if (nh <= 0) return;
+    k_strang_in<<<grid_for(nh), BLOCK, 0, s>>>(nh, v, h, stim, stim_on, tau, c, vs);
+}
+void launch_strang_out(hipStream_t s, int64_t nh, const int64_t* pos, const double* x2, double* v, double* h,
+                       const double* stim, double stim_on, double tau, const IonicConst& c, double* act, double v_act,
+                       double t_n, double dt) {
+    if (nh <= 0) return;
+    k_strang_out<<<grid_for(nh), BLOCK, 0, s>>>(nh, pos, x2, v, h, stim, stim_on, tau, c, act, v_act, t_n, dt);
 }
 void launch_gather_v_act(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst, double* act,
                          double v_act, double t_n, double dt) {

@@ -26,6 +26,7 @@ struct IonicConst {
     double gamma, chi, cm, dt;
     double dv, inv_dv, inv_tau_in, inv_tau_out, inv_tau_open, inv_tau_close, v_gate;
     double scale;   // 1 (semi-implicit), 2 (Crank-Nicolson: the system times 2)
+    double reaction; // 1: Steps 1 + 3; 0: diffusion sub-step of a splitting (no ionic term, gates kept)
 };
 
 // Execution plan of one factor's sweeps: the subtrees below the cut height
@@ -93,6 +94,14 @@ void launch_scatter_in_f(hipStream_t s, int64_t n, const int64_t* pos, const flo
 void launch_gather_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst);
 void launch_gather_out(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst,
                        const double* sc, int shift_slot, double shift_den);
+// Strang splitting: Heun half-steps tau of the reaction before (vs = V*,
+// h <- h*) and after (v <- V^{n+1} from V** = x2[pos], h <- h^{n+1}; act:
+// activation times as in launch_gather_v_act) the diffusion step
+void launch_strang_in(hipStream_t s, int64_t nh, const double* v, double* h, const double* stim, double stim_on,
+                      double tau, const IonicConst& c, double* vs);
+void launch_strang_out(hipStream_t s, int64_t nh, const int64_t* pos, const double* x2, double* v, double* h,
+                       const double* stim, double stim_on, double tau, const IonicConst& c, double* act, double v_act,
+                       double t_n, double dt);
 // v write-back with activation times (first time v reaches v_act, linear
 // in time between t_n and t_n + dt; act < 0 = not reached)
 void launch_gather_v_act(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst, double* act,

@@ -133,7 +133,10 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
     if (P.ionic != 0) { err = "only the Mitchell-Schaeffer model (ionic = 0) is built in"; return false; }
     if (P.precision != BIDO_PREC_FP64 && P.precision != BIDO_PREC_MIXED) { err = "bad precision"; return false; }
     if (P.precond != BIDO_PRECOND_PLAIN && P.precond != BIDO_PRECOND_LEARNED) { err = "bad precond"; return false; }
-    if (P.scheme != BIDO_SCHEME_EULER && P.scheme != BIDO_SCHEME_CN) { err = "bad time scheme"; return false; }
+    if (P.scheme != BIDO_SCHEME_EULER && P.scheme != BIDO_SCHEME_CN && P.scheme != BIDO_SCHEME_STRANG) {
+        err = "bad time scheme";
+        return false;
+    }
 #ifdef _OPENMP
     if (P.n_threads > 0) omp_set_num_threads(P.n_threads);
 #endif
@@ -157,7 +160,7 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
     const int d = A.dim;
     // the coefficient of M_H in Lambda and K_m: gamma = chi cm / dt for the
     // semi-implicit scheme, 2 gamma for Crank-Nicolson (the system times 2)
-    hs.gamma = P.chi * P.cm / P.dt * (P.scheme == BIDO_SCHEME_CN ? 2.0 : 1.0);
+    hs.gamma = P.chi * P.cm / P.dt * (P.scheme == BIDO_SCHEME_EULER ? 1.0 : 2.0);
 
     // orderings: nested dissection of S_1 (u) and of K_m (v)
     nested_dissection(A.S1, mesh->xyz, d, P.leaf, hs.p1.tree);
@@ -280,7 +283,7 @@ bool host_set_dt(HostSetup& hs, double dt, bool refactor, std::string& err) {
     if (!(dt > 0.0) || !std::isfinite(dt)) { err = "dt must be > 0"; return false; }
     const Assembled& A = hs.A;
     const int64_t N = A.N, NH = A.NH;
-    const double gamma = P.chi * P.cm / dt * (P.scheme == BIDO_SCHEME_CN ? 2.0 : 1.0);
+    const double gamma = P.chi * P.cm / dt * (P.scheme == BIDO_SCHEME_EULER ? 1.0 : 2.0);
     const NdTree& tk = hs.pk.tree;
     // K_m = gamma M_H + S_m, as at set-up
     Csr Km = add_diag(A.Sm, A.mH, gamma);

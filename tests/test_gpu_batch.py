@@ -368,3 +368,22 @@ def test_fused_batch_profiler(torch):
     batch.close()
     for sv in solvers:
         sv.close()
+
+
+def test_fused_batch_strang(torch):
+    """A fused batch of Strang-splitting slices follows each slice run alone."""
+    import paper_1711_08708_amd as B
+    cfgs = _slices()[:3]
+    n_steps = 8
+    ref = _single_runs(B, cfgs, B.PREC_FP64, n_steps, scheme=B.SCHEME_STRANG)
+    solvers = [B.Solver(cfg, tol=1e-12, scheme=B.SCHEME_STRANG) for cfg in cfgs]
+    batch = B.Batch(solvers, fused=True)
+    states = [s.state() for s in solvers]
+    for n in range(n_steps):
+        batch.run(states, n, 1)
+    for k, st in enumerate(states):
+        for a, b in zip([t.cpu().numpy() for t in st], ref[k][0]):
+            assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b), k
+    batch.close()
+    for s in solvers:
+        s.close()

@@ -235,3 +235,32 @@ def test_zero_rhs_and_not_converged(torch):
     with pytest.raises(B.BidoError) as e:
         solver.solve(rhs, x)
     assert e.value.code == -4
+
+
+@pytest.mark.parametrize("mk,n_steps", [(lambda: w.make_config("square48"), 20),
+                                        (lambda: w.thorax2d(n_target=3000, seed=11), 12)],
+                         ids=["square48", "thorax3000"])
+def test_strang_splitting_trajectory(torch, mk, n_steps):
+    """Strang splitting (Heun reaction half-steps around the Crank-Nicolson
+    diffusion step started from the elliptic potential of V*): every step's
+    U^{n+1}, V^{n+1}, w^{n+1} match the oracle's splitting step from the
+    same state."""
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd
+    cfg = mk()
+    s = bd.System(cfg, scheme="strang")
+    solver = B.Solver(cfg, eps_h=0.0, tol=1e-12, scheme=B.SCHEME_STRANG)
+    v, h, u = solver.state()
+    worst = 0.0
+    for n in range(n_steps):
+        Vn = v.cpu().numpy().copy()
+        hn = h.cpu().numpy().copy()
+        Un = s.from_global_u(u.cpu().numpy())
+        st = solver.step(v, h, u, n)
+        assert st["converged"] == 1
+        Uo_p, Vo, ho = s.step(Vn, hn, n, U0=Un)
+        eu, ev = _errs(u.cpu().numpy(), v.cpu().numpy(), s.to_global_u(Uo_p), Vo)
+        worst = max(worst, eu, ev)
+        assert eu <= TOL_PARITY and ev <= TOL_PARITY, (n, eu, ev)
+        assert np.abs(h.cpu().numpy() - ho).max() <= 1e-12
+    print(cfg["name"], "Strang worst per-step error", worst, "iterations", st["iterations"])

@@ -163,3 +163,63 @@ def test_cn_rest_and_constants():
     np.testing.assert_allclose(V1, c, rtol=1e-12)
     assert np.abs(U).max() < 1e-10
     assert abs(lin.gamma_eff - 2.0 * lin.gamma) < 1e-12 * lin.gamma
+
+
+def test_strang_without_reaction_is_crank_nicolson():
+    """With the reaction switched off the reaction half-steps are the
+    identity, so the splitting is exactly the Crank-Nicolson step."""
+    cfg = w.square2d(n=8)
+    a = bd.System(cfg, scheme="strang", reaction=False)
+    b = bd.System(cfg, scheme="cn", reaction=False)
+    U, V = _bump_state(a)
+    h = np.ones(a.NH)
+    Ua, Va, ha = a.step(V, h, 0, method="dense", U0=U)
+    Ub, Vb, hb = b.step(V, h, 0, method="dense", U0=U)
+    assert np.abs(Va - Vb).max() <= 1e-12 * np.abs(Vb).max()
+    assert np.abs(Ua - Ub).max() <= 1e-12 * np.abs(Ub).max() and np.array_equal(ha, h)
+
+
+def test_reaction_half_step_is_heun():
+    """One half-step of a single uniform vertex state against Heun's method
+    written out for the scalar ODE system (no diffusion involved)."""
+    from oracle import ionic
+    cfg = w.square2d(n=4)
+    s = bd.System(cfg, scheme="strang")
+    V = np.full(s.NH, 7.0)
+    h = np.full(s.NH, 0.8)
+    Vs, hs = s.reaction_half(V, h, 10 ** 6)       # no stimulus
+    tau = s.dt / 2
+
+    def f(v, w):
+        return -ionic.i_ion(np.array([v]), np.array([w]), s.cm)[0] / s.cm, ionic.gate_rate(np.array([v]), np.array([w]))[0]
+    a1, b1 = f(7.0, 0.8)
+    a2, b2 = f(7.0 + tau * a1, 0.8 + tau * b1)
+    assert np.allclose(Vs, 7.0 + tau / 2 * (a1 + a2), rtol=1e-15, atol=0)
+    assert np.allclose(hs, 0.8 + tau / 2 * (b1 + b2), rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("scheme,order", [("euler", 1.0), ("strang", 2.0)])
+def test_orders_with_reaction(scheme, order):
+    """With the reaction on, in a smooth regime (potentials below the gate
+    threshold, no stimulus), the semi-implicit scheme converges at order 1
+    and the Strang splitting at order 2 (errors against a Strang run at
+    dt/16)."""
+    cfg = dict(w.square2d(n=8))
+    cfg["stim_amp"] = 0.0
+    T = 2.0
+
+    def run(dt, sch):
+        s = bd.System(cfg, dt=dt, scheme=sch)
+        U, V = _bump_state(s)
+        V = V * (8.0 / 60.0)                      # peak 8 mV: below the 13 mV gate threshold
+        U = U * (8.0 / 60.0)
+        h = np.full(s.NH, 0.9)
+        for n in range(int(round(T / dt))):
+            U, V, h = s.step(V, h, n, method="dense", U0=U)
+        return V
+
+    ref = run(0.2 / 16, "strang")
+    errs = [np.linalg.norm(run(dt, scheme) - ref) for dt in (0.2, 0.1, 0.05)]
+    rates = [np.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    print(scheme, "errors", errs, "rates", rates)
+    assert all(abs(r - order) < 0.3 for r in rates), rates
