@@ -9,7 +9,7 @@ import scipy.sparse as sp
 import workloads as w
 
 
-@pytest.mark.parametrize("scheme", [0, 1], ids=["euler", "cn"])
+@pytest.mark.parametrize("scheme", [0, 1, 2], ids=["euler", "cn", "strang"])
 @pytest.mark.parametrize("mk", [lambda: w.thorax2d(n_target=3000, seed=11), lambda: w.slab3d(n=6)],
                          ids=["thorax3000", "slab6"])
 def test_host_set_dt_equals_setup_at_new_step(mk, scheme):
