@@ -17,7 +17,7 @@ def torch():
     return torch
 
 
-@pytest.mark.parametrize("scheme", ["euler", "cn"])
+@pytest.mark.parametrize("scheme", ["euler", "cn", "strang"])
 @pytest.mark.parametrize("pk", ["cholesky", "chebyshev"])
 def test_steps_after_set_dt_match_oracle(torch, pk, scheme):
     """Three steps at dt, the step changed to 0.4 dt, three more steps: each
@@ -26,7 +26,7 @@ def test_steps_after_set_dt_match_oracle(torch, pk, scheme):
     import paper_1711_08708_amd as B
     from oracle import bidomain as bd
     cfg = w.thorax2d(n_target=3000, seed=11)
-    sch = B.SCHEME_CN if scheme == "cn" else B.SCHEME_EULER
+    sch = {"euler": B.SCHEME_EULER, "cn": B.SCHEME_CN, "strang": B.SCHEME_STRANG}[scheme]
     dt2 = 0.4 * cfg["dt"]
     sv = B.Solver(cfg, eps_h=0.0, tol=1e-12, scheme=sch)
     if pk == "chebyshev":
