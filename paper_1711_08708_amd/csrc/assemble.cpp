@@ -184,6 +184,8 @@ bool assemble(const MeshIn& in, Assembled& out, std::string& err) {
     }
     for (int64_t e = 0; e < E * k; ++e)
         if (in.elems[e] < 0 || in.elems[e] >= N) { err = "element vertex out of range"; return false; }
+    for (int64_t i = 0; i < N * d; ++i)
+        if (!std::isfinite(in.xyz[i])) { err = "non-finite vertex coordinate"; return false; }
     std::vector<char> is_heart_e(E, 0);
     for (int64_t e = 0; e < E; ++e) {
         int r = in.region[e];
@@ -192,17 +194,26 @@ bool assemble(const MeshIn& in, Assembled& out, std::string& err) {
             err = "torso region code without a conductivity";
             return false;
         }
-        if (!(in.region_sigma[r] > 0.0)) { err = "torso conductivity must be > 0"; return false; }
+        if (!(in.region_sigma[r] > 0.0) || !std::isfinite(in.region_sigma[r])) {
+            err = "torso conductivity must be finite and > 0";
+            return false;
+        }
     }
     bool any_heart = false;
     for (int64_t e = 0; e < E; ++e) any_heart |= is_heart_e[e] != 0;
     if (!any_heart) { err = "mesh has no heart element"; return false; }
     if (!in.fibre) { err = "missing fibre frames"; return false; }
     for (int i = 0; i < d; ++i)
-        if (!(in.sigma_i[i] > 0.0) || !(in.sigma_e[i] > 0.0)) {
-            err = "heart conductivities must be > 0";
+        if (!(in.sigma_i[i] > 0.0) || !(in.sigma_e[i] > 0.0) || !std::isfinite(in.sigma_i[i]) ||
+            !std::isfinite(in.sigma_e[i])) {
+            err = "heart conductivities must be finite and > 0";
             return false;
         }
+    for (int64_t e = 0; e < E; ++e) {
+        if (!is_heart_e[e]) continue;
+        for (int q = 0; q < d * d; ++q)
+            if (!std::isfinite(in.fibre[e * d * d + q])) { err = "non-finite fibre frame"; return false; }
+    }
 
     ElemGeo geo;
     if (!element_geometry(in, geo, err)) return false;

@@ -133,6 +133,11 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
     if (P.ionic != 0) { err = "only the Mitchell-Schaeffer model (ionic = 0) is built in"; return false; }
     if (P.precision != BIDO_PREC_FP64 && P.precision != BIDO_PREC_MIXED) { err = "bad precision"; return false; }
     if (P.precond != BIDO_PRECOND_PLAIN && P.precond != BIDO_PRECOND_LEARNED) { err = "bad precond"; return false; }
+    if (!std::isfinite(tissue->stim_amp) || !std::isfinite(tissue->stim_t0) || !std::isfinite(tissue->stim_t1) ||
+        tissue->stim_t1 < tissue->stim_t0) {
+        err = "stimulus amplitude and window must be finite, with t0 <= t1";
+        return false;
+    }
     if (P.scheme != BIDO_SCHEME_EULER && P.scheme != BIDO_SCHEME_CN && P.scheme != BIDO_SCHEME_STRANG) {
         err = "bad time scheme";
         return false;

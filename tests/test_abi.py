@@ -380,3 +380,38 @@ def test_tall_backward_tiles_are_split_and_still_exact(monkeypatch):
         x1, x2 = h.factor_apply(B.FACTOR_P1, b), h.factor_emulate(B.FACTOR_P1, b)
         assert np.abs(x1 - x2).max() <= 1e-12 * np.abs(x1).max()
     assert items["512"] > items["0"], items
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("index", "out of range"), ("negative", "out of range"), ("degenerate", "degenerate"),
+    ("nan_xyz", "non-finite vertex"), ("inf_sigma", "conductivities"), ("zero_sigma", "conductivities"),
+    ("nan_fibre", "fibre"), ("stim_window", "stimulus"), ("no_heart", "no heart")])
+def test_setup_refuses_malformed_input(case, msg):
+    """Malformed meshes, tissues and stimuli are refused at set-up with
+    BIDO_ERR_ARG and a message naming the problem, before any factorisation."""
+    import paper_1711_08708_amd as B
+    base = w.square2d(n=6)
+    cfg = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in base.items()}
+    heart_e = int(np.nonzero(cfg["region"] == 1)[0][0])
+    if case == "index":
+        cfg["elems"][0, 0] = len(cfg["xyz"]) + 5
+    elif case == "negative":
+        cfg["elems"][0, 1] = -3
+    elif case == "degenerate":
+        cfg["elems"][0] = [0, 0, 1]
+    elif case == "nan_xyz":
+        cfg["xyz"][3, 0] = np.nan
+    elif case == "inf_sigma":
+        cfg["sigma_i"] = np.array([np.inf, 1.0])
+    elif case == "zero_sigma":
+        cfg["sigma_e"] = np.array([1.0, 0.0])
+    elif case == "nan_fibre":
+        cfg["fibre"][heart_e, 0, 0] = np.nan
+    elif case == "stim_window":
+        cfg["stim_t0"], cfg["stim_t1"] = 2.0, 1.0
+    elif case == "no_heart":
+        cfg["region"] = np.zeros_like(cfg["region"])
+        cfg["stim_mask"] = np.zeros_like(cfg["stim_mask"])
+    with pytest.raises(B.BidoError, match=msg) as ei:
+        B.HostSetup(cfg)
+    assert ei.value.code == -1
