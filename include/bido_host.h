@@ -59,6 +59,11 @@ bido_status bido_host_vec(const bido_host* h, int which, int64_t* n, const doubl
  * bounds (min gamma m_i / K_ii, Gershgorin).                              */
 bido_status bido_host_pk_interval(const bido_host* h, int lanczos_steps, double* out);
 
+/* Host emulation of the Chebyshev P_K apply (the device recurrence and its
+ * coefficients, in FP64 on the CPU; a check hook): x = P_K^-1 b for `steps`
+ * steps on [lo, hi], b and x in the internal v order (N_H entries).       */
+bido_status bido_host_pk_emulate(const bido_host* h, int steps, double lo, double hi, const double* b, double* x);
+
 /* Probe location of bido_record: for each of n points (host, n x dim) the
  * dim + 1 vertex ids (caller's numbering) of an element holding it and the
  * barycentric weights there (ids, wts: n x (dim + 1)).  BIDO_ERR_ARG if a

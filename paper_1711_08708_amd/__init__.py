@@ -184,6 +184,8 @@ ABI = {
     "bido_host_vec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p,
                                      ctypes.POINTER(_c_double_p)]),
     "bido_host_pk_interval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p]),
+    "bido_host_pk_emulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                            _c_double_p, _c_double_p]),
     "bido_host_set_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]),
     "bido_host_locate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p, _c_i64_p, _c_double_p]),
     "bido_host_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p,
@@ -597,6 +599,13 @@ class HostSetup:
         c = np.ctypeslib.as_array(col, shape=(nnz.value,)).copy() if nnz.value else np.zeros(0, np.int32)
         v = np.ctypeslib.as_array(val, shape=(nnz.value,)).copy() if nnz.value else np.zeros(0)
         return sp.csr_matrix((v, c, p), shape=(n.value, n.value))
+
+    def pk_emulate(self, steps, lo, hi, b):
+        b = _arr(b, np.float64)
+        x = np.zeros_like(b)
+        _check(lib.bido_host_pk_emulate(self.h, int(steps), float(lo), float(hi), b.ctypes.data_as(_c_double_p),
+                                        x.ctypes.data_as(_c_double_p)), host=True)
+        return x
 
     def set_dt(self, dt, refactor=True):
         _check(lib.bido_host_set_dt(self.h, float(dt), 1 if refactor else 0), host=True)

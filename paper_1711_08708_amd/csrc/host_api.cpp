@@ -72,6 +72,30 @@ bido_status bido_host_pk_interval(const bido_host* h, int lanczos_steps, double*
     return BIDO_OK;
 }
 
+bido_status bido_host_pk_emulate(const bido_host* h, int steps, double lo, double hi, const double* b, double* x) {
+    if (!h || !b || !x || steps < 1 || !(lo > 0.0) || !(hi > lo)) return hfail(BIDO_ERR_ARG, "bad argument");
+    const bido::Csr& K = h->hs.km_int;
+    const int64_t n = K.n;
+    std::vector<double> dinv(n, 0.0), r(b, b + n), d(n), dn(n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = K.ptr[i]; p < K.ptr[i + 1]; ++p)
+            if (K.col[p] == i) dinv[i] += K.val[p];
+    for (auto& v : dinv) v = 1.0 / v;
+    const bido::ChebCoef c = bido::chebyshev_coefficients(lo, hi, steps);
+    for (int64_t i = 0; i < n; ++i) x[i] = d[i] = c.inv_theta * dinv[i] * b[i];
+    for (int k = 1; k < steps; ++k) {          // r -= K d; d = c1 d + c2 D^-1 r; x += d
+        for (int64_t i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int64_t p = K.ptr[i]; p < K.ptr[i + 1]; ++p) s += K.val[p] * d[K.col[p]];
+            r[i] -= s;
+            dn[i] = c.c1[k - 1] * d[i] + c.c2[k - 1] * dinv[i] * r[i];
+        }
+        for (int64_t i = 0; i < n; ++i) x[i] += dn[i];
+        d.swap(dn);
+    }
+    return BIDO_OK;
+}
+
 bido_status bido_host_set_dt(bido_host* h, double dt, int refactor) {
     if (!h) return hfail(BIDO_ERR_ARG, "null argument");
     std::string err;

@@ -162,3 +162,23 @@ def test_host_interval_brackets_the_spectrum(mk):
     vpos = hs.index(B.IDX_VPOS)
     P = sp.csr_matrix((np.ones(len(vpos)), (vpos, np.arange(len(vpos)))), shape=Kh.shape)
     assert abs(P @ K @ P.T - Kh).max() <= 1e-12 * abs(K).max()
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 6])
+def test_library_recurrence_matches_oracle_polynomial(m):
+    """The library's coefficients and three-term recurrence (host emulation
+    of the device apply) against the oracle's closed-form polynomial, on the
+    oracle's own K_m and interval."""
+    import paper_1711_08708_amd as B
+    cfg = w.thorax2d(n_target=3000, seed=11)
+    _, K = _km(cfg)
+    ev = _spectrum(K)
+    lo, hi = ev[0], 1.05 * ev[-1]
+    hs = B.HostSetup(cfg)
+    vpos = hs.index(B.IDX_VPOS)
+    t = np.random.default_rng(m).normal(size=K.shape[0])
+    ref = ch.chebyshev_jacobi(K, t, lo, hi, m)
+    t_int = np.empty_like(t)
+    t_int[vpos] = t
+    got = hs.pk_emulate(m, lo, hi, t_int)[vpos]
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
