@@ -1,4 +1,4 @@
-// Device context, PCG driver and the C ABI (include/bido.h).
+// Device context, the PCG loop and the C ABI (include/bido.h).
 //
 // Step 2 of the resolution algorithm (Sec. 3.2) is solved by conjugate
 // gradient on Lambda X = Y, preconditioned by the block-LU preconditioner

@@ -1,4 +1,4 @@
-// Device data layouts shared by the HIP kernels and the driver.
+// Device data layouts shared by the HIP kernels and the host code.
 #pragma once
 #include <cstdint>
 
