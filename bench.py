@@ -478,10 +478,24 @@ def _cpu_baseline(cfg, n_steps, scheme="euler"):
         for n in range(n_steps):
             U, V, h = s.step(V, h, n, U0=U)
         el = time.perf_counter() - t0
+    how = ("sparse LU of the grounded Lambda" if cfg["dim"] == 2 or s.N + s.NH <= 6000
+           else "Jacobi-CG with the condition-aware stop")
     return {"value": round(n_steps / el, 5), "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "threads": 1, "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(),
             "sample": f"{n_steps} steps of {cfg['name']} from rest (FP64 NumPy/SciPy oracle: "
-                      f"Step 1, sparse LU of the grounded Lambda, normalisation, Step 3; "
-                      f"assembly excluded), {el:.1f} s"}
+                      f"Step 1, {how}, normalisation, Step 3; assembly excluded; BLAS and "
+                      f"OpenMP pools limited to 1 thread), {el:.1f} s"}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":

@@ -96,7 +96,9 @@ typedef struct {
     double cm;         /* membrane capacitance [uF/cm^2]                      */
     double dt;         /* time step [ms]; gamma = chi*cm/dt                   */
     double eps_h;      /* H-matrix accuracy eps (Sec. 5.3); 0 = exact factor */
-    double eta;        /* admissibility parameter, min diam <= eta * dist    */
+    double eta;        /* reserved (kept for the layout; not read): the
+                          hierarchical top uses weak admissibility, every
+                          off-diagonal block of its bisection tree is low-rank */
     double tol;        /* default relative residual |Lambda X - Y| / |Y|     */
     int leaf;          /* nested-dissection leaf size (default 64)           */
     int max_iter;      /* PCG iteration cap (default 200)                    */
@@ -141,7 +143,8 @@ typedef struct {
                                     (the active precision)                    */
     int64_t dense_bytes_p1, dense_bytes_pk; /* same factors uncompressed      */
     int levels_p1, levels_pk;    /* nested-dissection tree heights           */
-    int64_t lowrank_blocks;      /* admissible (low-rank) blocks stored       */
+    int64_t lowrank_blocks;      /* low-rank blocks (rank > 0) stored in the
+                                    hierarchical tops of P_1 and P_K        */
     double setup_seconds;        /* host set-up time of bido_create           */
     int ground_index;            /* internal index of the grounded u node    */
     int launches_per_sweep_p1;   /* kernel launches of one triangular sweep   */
@@ -355,6 +358,45 @@ bido_status bido_gnn_loss_grad(bido_ctx* ctx, const float* that, const float* y,
  * the loss |r|^2 and its gradient (host; grad may be NULL).               */
 bido_status bido_stencil_check(bido_ctx* ctx, const float* zh, const float* bh, float* r, double* loss,
                                float* grad);
+
+/* Execution plan of an inner solve's triangular sweeps (the device layout
+ * of the Cholesky factors of Sec. 5.3; results do not depend on it beyond
+ * rounding).  The nodes of the elimination tree below a subtree cut height
+ * are swept by one workgroup per subtree, the levels above it by one launch
+ * per tree height (forward items of 64 rows x fwd_cols columns, backward
+ * items of up to 64 columns x a row range, split tiles summed by a combine
+ * launch), and the nodes from the top cut up by one product with the
+ * (dense or hierarchical) inverse of their Schur complement.  Fields <= 0
+ * (top_h, sub_h, bwd_wide, level_items < 0) take the defaults.           */
+typedef struct {
+    int top_h;          /* first tree height of the top; -1: cost model;
+                           tree height + 1: no top                        */
+    int fwd_cols;       /* columns per forward level item (0: 128)        */
+    int bwd_rows;       /* rows per backward level item (0: rule below)   */
+    int bwd_wide;       /* 1024-thread backward items over whole column
+                           tiles (1), 256-thread items over row ranges (0);
+                           -1: 1                                          */
+    int level_items;    /* without bwd_rows, a level of tall tiles is split
+                           into row ranges until it has about this many
+                           wide items (-1: 512; 0 keeps tiles whole)      */
+    int sub_h;          /* cap of the subtree cut heights (-1: none)      */
+    int sub_want;       /* subtrees wanted per tree (0: 256)              */
+    int sub_total;      /* subtrees shared over a fused batch's forest
+                           (0: 512 there, sub_want per tree elsewhere)    */
+    int bwd_group_max;  /* backward subtree heights with at most this many
+                           nodes use wave groups (0: 2 in 2D, 4 in 3D)    */
+    int spmv_group;     /* lanes per row of the sparse products of the
+                           context: 4, 8, 16 or 32 (0: 4 in 2D, 16 in 3D) */
+} bido_plan;
+void bido_default_plan(bido_plan* plan);
+/* Rebuild the device plan of factor `which` (BIDO_FACTOR_P1 = 0,
+ * BIDO_FACTOR_PK = 1) with these options, and set the context's spmv_group
+ * (when non-zero).  Synchronises; captured graphs are rebuilt.  Errors:
+ * BIDO_ERR_ARG (bad which or spmv_group; the old plan is kept),
+ * BIDO_ERR_STATE for a context in a batch.  bido_get_plan reads the options
+ * of the plan in use (defaults resolved as built).                        */
+bido_status bido_set_plan(bido_ctx* ctx, int which, const bido_plan* plan);
+bido_status bido_get_plan(const bido_ctx* ctx, int which, bido_plan* plan);
 
 /* Autotuning of the inner-solve plans: for P_1 and P_K, candidate plans
  * (the first height of the top one or two levels either side of the cost

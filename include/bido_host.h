@@ -75,14 +75,15 @@ bido_status bido_host_locate(const bido_host* h, int n, const double* pts, int64
 bido_status bido_host_set_dt(bido_host* h, double dt, int refactor);
 bido_status bido_host_index(const bido_host* h, int which, int64_t* n, const int64_t** data);
 
-/* Sizes of a factor: entries uncompressed / as stored, low-rank blocks,
- * tree height, largest separator.                                        */
-bido_status bido_host_factor_stats(const bido_host* h, int which, int64_t* dense_entries,
-                                   int64_t* stored_entries, int64_t* n_lowrank,
-                                   int* height, int* max_sep);
+/* Sizes of a factor: panel entries (the lower triangles of L_tt^-1 and the
+ * blocks L_Bt L_tt^-1 of every tree node, held exactly), tree height,
+ * largest separator.  The hierarchical compression at eps_h applies to the
+ * top of the execution plan (bido_host_factor_top).                       */
+bido_status bido_host_factor_stats(const bido_host* h, int which, int64_t* entries, int* height,
+                                   int* max_sep);
 
-/* Per tree node (post-order): nI, nB, height, depth, parent, low-rank block
- * count, as 6 int32 per node into out[0..6*cap).  *n_nodes gets the count. */
+/* Per tree node (post-order): nI, nB, height, depth, parent, as 5 int32
+ * per node into out[0..5*cap).  *n_nodes gets the count.                 */
 bido_status bido_host_factor_nodes(const bido_host* h, int which, int64_t* n_nodes, int32_t* out,
                                    int64_t cap);
 
@@ -96,9 +97,15 @@ bido_status bido_host_factor_apply(const bido_host* h, int which, const double* 
 bido_status bido_host_factor_emulate(const bido_host* h, int which, const double* b, double* x);
 
 /* Shape of that plan: subtree cut height, subtrees, level launches per
- * sweep above the cut, forward and backward work items.                   */
+ * sweep above the cut, forward and backward work items, and the backward
+ * column tiles split over several row-range items (summed by a combine
+ * launch).                                                               */
 bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n_sub, int* n_levels,
-                                  int64_t* n_fwd_items, int64_t* n_bwd_items);
+                                  int64_t* n_fwd_items, int64_t* n_bwd_items, int64_t* n_bwd_split);
+
+/* Plan options (bido_plan, bido.h) of the later bido_host_factor_emulate,
+ * _plan and _top queries of factor `which` (default: bido_default_plan).  */
+bido_status bido_host_set_plan(bido_host* h, int which, const bido_plan* plan);
 
 /* Test hook for batches of independent slices: a host object whose factors
  * are the forests of the slices' factors (the factors of the block-diagonal
@@ -116,14 +123,14 @@ bido_status bido_host_merge(const bido_host* const* hs, int n, bido_host** out);
  * Cholesky factor of Sec. 5.3 restricted to the top separators, inverted
  * once at set-up); n_top vertices, `seconds` of host time to invert.
  * top_h = tree height + 1 means no dense top.  The cut comes from a cost
- * model; environment BIDO_TOP_H forces it (raised as far as the bound of
- * the top size requires).  With eps_h > 0 the inverse is held in
+ * model; the plan option top_h (bido_host_set_plan) forces it (raised as
+ * far as the bound of the top size requires).  With eps_h > 0 the inverse is held in
  * hierarchical low-rank form (the top vertices in geometric bisection
  * order, off-diagonal blocks truncated by rank-revealing QR at relative
  * accuracy eps_h, Sec. 5.3): stored_entries counts its values, max_rank its
- * largest block rank (-1 when dense).                                    */
+ * largest block rank (-1 when dense), n_lowrank its blocks of rank > 0. */
 bido_status bido_host_factor_top(const bido_host* h, int which, int* top_h, int64_t* n_top, double* seconds,
-                                 int64_t* stored_entries, int* max_rank);
+                                 int64_t* stored_entries, int* max_rank, int64_t* n_lowrank);
 
 #ifdef __cplusplus
 }

@@ -162,8 +162,20 @@ class System:
 
     def solve_cg(self, Y, x0=None, rtol=1e-12, kappa_rtol=1e-10,
                  max_iter=200000):
-        A = self.Lam
-        dinv = 1.0 / A.diagonal()
+        """Jacobi-CG on the augmented matrix Lam + c w w^T of solve_dense
+        (w = [M 1; 0]): symmetric positive definite, and its solution is the
+        normalised one of Prop. 1.  On Lam itself the kernel (1, 0) made
+        rounding show up as a Ritz value near zero, so the condition
+        estimate of the stopping test never settled."""
+        L = self.Lam
+        w = np.concatenate([self.m, np.zeros(self.NH)])
+        c = abs(L).sum(axis=1).max() / np.dot(w, w)
+
+        class _Aug:
+            def __matmul__(self, v):
+                return L @ v + (c * np.dot(w, v)) * w
+        A = _Aug()
+        dinv = 1.0 / (L.diagonal() + c * w * w)
         x = np.zeros_like(Y) if x0 is None else x0.copy()
         r = Y - A @ x
         ny = np.linalg.norm(Y)

@@ -103,6 +103,27 @@ class TuneReport(ctypes.Structure):
                 for k, _ in self._fields_}
 
 
+class Plan(ctypes.Structure):
+    """bido_plan: execution-plan options of an inner solve (see bido.h)."""
+    _fields_ = [(k, ctypes.c_int) for k in ("top_h", "fwd_cols", "bwd_rows", "bwd_wide", "level_items",
+                                            "sub_h", "sub_want", "sub_total", "bwd_group_max",
+                                            "spmv_group")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def default_plan(**kw):
+    """bido_default_plan with the given fields overridden."""
+    q = Plan()
+    lib.bido_default_plan(ctypes.byref(q))
+    for k, v in kw.items():
+        if not hasattr(q, k):
+            raise KeyError(k)
+        setattr(q, k, int(v))
+    return q
+
+
 class KProf(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
                 ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -142,6 +163,9 @@ ABI = {
                                    _c_double_p, _c_double_p]),
     "bido_set_graphs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(TuneReport)]),
+    "bido_default_plan": (None, [ctypes.POINTER(Plan)]),
+    "bido_set_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Plan)]),
+    "bido_get_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Plan)]),
     "bido_learn_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
                                           ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Stats)]),
@@ -190,20 +214,21 @@ ABI = {
     "bido_host_locate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p, _c_i64_p, _c_double_p]),
     "bido_host_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p,
                                        ctypes.POINTER(_c_i64_p)]),
-    "bido_host_factor_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p, _c_i64_p,
-                                              _c_i64_p, ctypes.POINTER(ctypes.c_int),
-                                              ctypes.POINTER(ctypes.c_int)]),
+    "bido_host_factor_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p,
+                                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "bido_host_factor_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i64_p, _c_i32_p,
                                               ctypes.c_int64]),
     "bido_host_factor_emulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p,
                                                 _c_double_p]),
     "bido_host_factor_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                             _c_i64_p, _c_i64_p]),
+                                             _c_i64_p, _c_i64_p, _c_i64_p]),
+    "bido_host_set_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Plan)]),
     "bido_host_merge": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_void_p)]),
     "bido_host_factor_top": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _c_i64_p,
-                                            ctypes.POINTER(ctypes.c_double), _c_i64_p, ctypes.POINTER(ctypes.c_int)]),
+                                            ctypes.POINTER(ctypes.c_double), _c_i64_p, ctypes.POINTER(ctypes.c_int),
+                                            _c_i64_p]),
     "bido_host_factor_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p,
                                               _c_double_p]),
 }
@@ -455,6 +480,16 @@ class Solver:
         _check(lib.bido_autotune(self.ctx, int(reps), ctypes.byref(r)))
         return r.as_dict()
 
+    def set_plan(self, which, **kw):
+        """Rebuild factor `which`'s sweep plan with bido_plan fields kw (others default)."""
+        q = default_plan(**kw)
+        _check(lib.bido_set_plan(self.ctx, int(which), ctypes.byref(q)))
+
+    def get_plan(self, which):
+        q = Plan()
+        _check(lib.bido_get_plan(self.ctx, int(which), ctypes.byref(q)))
+        return q.as_dict()
+
     def set_graphs(self, on):
         """True: always replay captured graphs, False: never, None: only in a batch."""
         _check(lib.bido_set_graphs(self.ctx, -1 if on is None else (1 if on else 0)))
@@ -639,19 +674,17 @@ class HostSetup:
         return np.ctypeslib.as_array(d, shape=(n.value,)).copy()
 
     def factor_stats(self, which):
-        de, se, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        de = ctypes.c_int64()
         h, ms = ctypes.c_int(), ctypes.c_int()
-        _check(lib.bido_host_factor_stats(self.h, which, ctypes.byref(de), ctypes.byref(se),
-                                          ctypes.byref(nl), ctypes.byref(h), ctypes.byref(ms)),
+        _check(lib.bido_host_factor_stats(self.h, which, ctypes.byref(de), ctypes.byref(h), ctypes.byref(ms)),
                host=True)
-        return dict(dense_entries=de.value, stored_entries=se.value, n_lowrank=nl.value,
-                    height=h.value, max_sep=ms.value)
+        return dict(entries=de.value, height=h.value, max_sep=ms.value)
 
     def factor_nodes(self, which):
-        """(n_nodes, 6) int32: nI, nB, height, depth, parent, low-rank blocks."""
+        """(n_nodes, 5) int32: nI, nB, height, depth, parent."""
         n = ctypes.c_int64()
         _check(lib.bido_host_factor_nodes(self.h, which, ctypes.byref(n), None, 0), host=True)
-        out = np.zeros((n.value, 6), dtype=np.int32)
+        out = np.zeros((n.value, 5), dtype=np.int32)
         _check(lib.bido_host_factor_nodes(self.h, which, ctypes.byref(n),
                                           out.ctypes.data_as(_c_i32_p), n.value), host=True)
         return out
@@ -666,19 +699,25 @@ class HostSetup:
 
     def factor_plan(self, which):
         hc, ns, nl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        nf, nb = ctypes.c_int64(), ctypes.c_int64()
+        nf, nb, nsp = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib.bido_host_factor_plan(self.h, which, ctypes.byref(hc), ctypes.byref(ns),
-                                         ctypes.byref(nl), ctypes.byref(nf), ctypes.byref(nb)), host=True)
+                                         ctypes.byref(nl), ctypes.byref(nf), ctypes.byref(nb),
+                                         ctypes.byref(nsp)), host=True)
         return dict(hc=hc.value, n_sub=ns.value, n_levels=nl.value, n_fwd_items=nf.value,
-                    n_bwd_items=nb.value)
+                    n_bwd_items=nb.value, n_bwd_split=nsp.value)
+
+    def set_plan(self, which, **kw):
+        """Plan options of the later factor_emulate / factor_plan / factor_top queries."""
+        q = default_plan(**kw)
+        _check(lib.bido_host_set_plan(self.h, int(which), ctypes.byref(q)), host=True)
 
     def factor_top(self, which):
         th, nt, sec = ctypes.c_int(), ctypes.c_int64(), ctypes.c_double()
-        st, mr = ctypes.c_int64(), ctypes.c_int()
+        st, mr, nl = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int64()
         _check(lib.bido_host_factor_top(self.h, which, ctypes.byref(th), ctypes.byref(nt), ctypes.byref(sec),
-                                        ctypes.byref(st), ctypes.byref(mr)), host=True)
+                                        ctypes.byref(st), ctypes.byref(mr), ctypes.byref(nl)), host=True)
         return dict(top_h=th.value, n_top=nt.value, seconds=sec.value, stored_entries=st.value,
-                    max_rank=mr.value)
+                    max_rank=mr.value, n_lowrank=nl.value)
 
     def factor_apply(self, which, b):
         b = _arr(b, np.float64)

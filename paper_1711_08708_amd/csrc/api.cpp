@@ -120,6 +120,9 @@ struct FactorDev {
     int64_t dense_entries = 0;
     int64_t meta_bytes = 0;
     int64_t upd_size = 0;
+    int64_t scratch_size = 0;       // split-tile partial sums (doubles)
+    int64_t ht_size = 0;            // projections of the hierarchical top (doubles)
+    int64_t top_lowrank = 0;        // blocks of rank > 0 stored in the hierarchical top
     int max_nI = 0;
 
     void release() {
@@ -167,6 +170,7 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
     fd.height = p.height;
     fd.max_nI = p.max_nI;
     fd.upd_size = p.upd_size;
+    fd.scratch_size = p.scratch_size;
     fd.panel_entries = (int64_t)p.panel.size();
     fd.dense_entries = f.dense_entries();
     HIP_OK(upload(&fd.nodes, p.nodes.data(), p.nodes.size()));
@@ -186,7 +190,7 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
     // backward subtree heights of at most this many nodes use wave groups:
     // the thin upper nodes of 2D subtrees gain nothing from them beyond 2,
     // the fat 3D ones do up to 4 (slab64 tri_bwd_sub 133 -> 102 us)
-    fd.plan.bwd_group_max = f.dim == 3 ? 4 : 2;
+    fd.plan.bwd_group_max = p.used.bwd_group_max > 0 ? p.used.bwd_group_max : (f.dim == 3 ? 4 : 2);
     fd.lvl0 = p.lvl0;
     fd.plan.n_sub = p.n_sub;
     fd.plan.sub_maxw = p.sub_maxw;
@@ -230,6 +234,9 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
             fd.plan.n_hleaves = (int)hd.leaves.size();
             fd.plan.n_hcols = (int)p.hodlr_cols.size();
             HIP_OK(hipMalloc((void**)&fd.plan.ht, hd.t_size * sizeof(double)));
+            fd.ht_size = hd.t_size;
+            fd.top_lowrank = 0;
+            for (const auto& b : hd.blocks) fd.top_lowrank += b.k > 0;
             vec += 8.0 * 2.0 * (double)hd.t_size;
         }
         fd.top_bytes64 = 8.0 * (double)vals.size() + vec;
@@ -497,20 +504,25 @@ void inner_solve(C* c, const FactorDev& f, const double* in, double* out) {
 
 // Z2 = P_K^-1 t: the factor of K_m, or `cheb_steps` steps of the Chebyshev
 // acceleration of the Jacobi iteration on K_m (always FP64; z_0 = 0).
+void pk_solve(bido_ctx* c, const double* in, double* out, double* ch_r, double* ch_d0, double* ch_d1);
 void pk_solve(bido_ctx* c, const double* in, double* out) {
+    pk_solve(c, in, out, c->ch_r, c->ch_d[0], c->ch_d[1]);
+}
+void pk_solve(bido_ctx* c, const double* in, double* out, double* ch_r, double* ch_d0, double* ch_d1) {
     if (c->pk_kind != BIDO_PK_CHEBYSHEV) {
         inner_solve(c, c->pk, in, out);
         return;
     }
+    double* ch_d[2] = {ch_d0, ch_d1};
     hipStream_t s = c->stream;
     const int64_t n = c->NH;
     const double step_bytes = 12.0 * c->km.nnz + 8.0 * (n + 1) + 8.0 * 8 * n;
-    PROF(c, K_CHEB, 32.0 * n, launch_cheb_init(s, n, in, c->km_dinv, c->cheb.inv_theta, c->ch_d[0], out));
+    PROF(c, K_CHEB, 32.0 * n, launch_cheb_init(s, n, in, c->km_dinv, c->cheb.inv_theta, ch_d[0], out));
     for (int k = 1; k < c->cheb_steps; ++k) {
         const bool last = k + 1 == c->cheb_steps;
         PROF(c, K_CHEB, last ? step_bytes - 16.0 * n : step_bytes,
-             launch_cheb_step(s, c->km, c->spmv_group, c->km_dinv, k == 1 ? in : c->ch_r, c->ch_r,
-                              c->ch_d[(k - 1) & 1], c->ch_d[k & 1], out, c->cheb.c1[k - 1], c->cheb.c2[k - 1],
+             launch_cheb_step(s, c->km, c->spmv_group, c->km_dinv, k == 1 ? in : ch_r, ch_r,
+                              ch_d[(k - 1) & 1], ch_d[k & 1], out, c->cheb.c1[k - 1], c->cheb.c2[k - 1],
                               last));
     }
 }
@@ -825,6 +837,37 @@ IonicConst ionic_consts(const bido_ctx* c) {
     return k;
 }
 
+// The elliptic solve of a Strang step, S_1 tA = tC (tC = Pi^T S_i V*, zero
+// sum), to the context's tolerance: P_1 is exact only with exact factors
+// (a hierarchical top at eps_h > 0 leaves an O(eps_h) error), so the one
+// P_1 apply in tA is refined, tA += P_1^-1 (tC - S_1 tA), until
+// |tC - S_1 tA| <= tol/10 |tC| (S_1 tA is the u-row product of Lambda with
+// (tA, 0)).  FP64 throughout; one residual check (a host wait) per round.
+void elliptic_refine(bido_ctx* c) {
+    hipStream_t s = c->stream;
+    const int64_t N = c->N;
+    CsrDev urows = c->lam;                   // the u rows of Lambda: [S_1, Pi^T S_i]
+    urows.n = N;
+    urows.nnz = c->hs.lam.ptr[N];
+    const double want = 0.1 * c->params.tol;
+    PROF(c, K_MISC, 16.0 * N, launch_dot_reduce(s, N, c->tC, c->tC, c->rd, c->sc + S_EL_BB));
+    PROF(c, K_MISC, 8.0 * c->n2, launch_fill(s, c->n2, c->q, 0.0));
+    for (int round = 0; round < 20; ++round) {
+        if (hipMemcpyAsync(c->q, c->tA, N * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) return;
+        PROF(c, K_SPMV_CSR, csr_bytes(urows, c->n2),
+             launch_spmv_csr(s, urows, c->spmv_group, c->q, c->tC, c->tD));            // tC - S_1 tA
+        PROF(c, K_MISC, 16.0 * N, launch_dot_reduce(s, N, c->tD, c->tD, c->rd, c->sc + S_EL_RR));
+        if (hipMemcpyAsync(c->sc_host + S_EL_RR, c->sc + S_EL_RR, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return;                              // reported by the caller's error check
+        const double rr = c->sc_host[S_EL_RR], bb = c->sc_host[S_EL_BB];
+        if (!(rr > want * want * bb)) break;     // converged (or b = 0)
+        tri_solve<double>(c, c->p1, c->p1.panel64, c->p1.panel64_cm, c->tD, c->r);
+        PROF(c, K_MISC, 24.0 * N, launch_axpy(s, N, 1.0, c->r, c->tA));
+    }
+}
+
 // Steps 1 and 3 on the device: X0 = (U^n, V^n) and the right-hand side Y.
 void step_prepare(bido_ctx* c, double* v, double* w, double* u, int64_t n) {
     hipStream_t s = c->stream;
@@ -851,6 +894,7 @@ void step_prepare(bido_ctx* c, double* v, double* w, double* u, int64_t n) {
         PROF(c, K_SPMV_CSR, csr_bytes(c->auv, NH),
              launch_spmv_csr(s, c->auv, c->spmv_group, c->x + N, nullptr, c->tC));   // Pi^T S_i V*
         tri_solve<double>(c, c->p1, c->p1.panel64, c->p1.panel64_cm, c->tC, c->tA);   // FP64 in both precisions
+        elliptic_refine(c);
         PROF(c, K_MISC, 8.0 * N, launch_fill(s, N, c->x, 0.0));
         PROF(c, K_SPMV_CSR, csr_bytes(rows, c->n2),
              launch_spmv_csr(s, rows, c->spmv_group, c->x, nullptr, c->tB));          // (Lambda (0, V*))_v
@@ -1392,10 +1436,6 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     // 13.2 us on thorax200k, 346 -> 281 us on the batch64 union); 3D rows
     // (~15 and ~30 entries) keep 16
     c->spmv_group = hs.A.dim == 2 ? 4 : 16;
-    if (const char* eg = std::getenv("BIDO_SPMV_GROUP")) {   // plan knob: lanes per row of the products
-        const int g = std::atoi(eg);
-        if (g == 4 || g == 8 || g == 16 || g == 32) c->spmv_group = g;
-    }
     c->heart_ids = hs.A.heart;
     bido_status e;
     if ((e = CsrHostView::up(hs.lam, c->lam))) return e;
@@ -1625,9 +1665,9 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
         // sizes (each tree's cut kept below its top cut) instead of 256 per
         // tree: the union has subtrees enough to fill the device anyway, and
         // bigger ones keep the waves of a workgroup busy (batch64 FP64:
-        // 627 -> 802 slice-steps/s); environment BIDO_SUB_TOTAL overrides it
-        const char* est = std::getenv("BIDO_SUB_TOTAL");
-        const int sub_total = est && *est ? std::max(1, std::atoi(est)) : 512;
+        // 627 -> 802 slice-steps/s); a slice's plan option sub_total > 0
+        // (of the largest slice) replaces the 512
+        const int sub_total = ctxs[big]->p1.opts.sub_total > 0 ? ctxs[big]->p1.opts.sub_total : 512;
         PlanOptions op = ctxs[big]->p1.opts;
         op.top_h = -1;
         op.sub_h = -1;
@@ -1896,7 +1936,7 @@ bido_status bido_get_info(const bido_ctx* c, bido_info* info) {
     info->levels_pk = c->pk.height + 1;
     info->launches_per_sweep_p1 = (int)c->p1.top.size() + (c->p1.plan.n_sub > 0);
     info->launches_per_sweep_pk = (int)c->pk.top.size() + (c->pk.plan.n_sub > 0);
-    info->lowrank_blocks = c->hs.p1.n_lowrank() + c->hs.pk.n_lowrank();
+    info->lowrank_blocks = c->p1.top_lowrank + c->pk.top_lowrank;
     info->setup_seconds = c->hs.setup_seconds + c->p1.top_seconds + c->pk.top_seconds;
     info->ground_index = (int)c->p1.ground;
     return BIDO_OK;
@@ -2487,6 +2527,69 @@ bido_status bido_autotune(bido_ctx* c, int reps, bido_tune_report* rep) {
     HIP_OK(hipStreamSynchronize(c->stream));
     r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rep) *rep = r;
+    return BIDO_OK;
+}
+
+void bido_default_plan(bido_plan* q) {
+    if (!q) return;
+    *q = bido_plan{};
+    q->top_h = -1;
+    q->bwd_wide = -1;
+    q->level_items = -1;
+    q->sub_h = -1;
+}
+
+bido_status bido_set_plan(bido_ctx* c, int which, const bido_plan* q) {
+    if (!c || !q) return fail(BIDO_ERR_ARG, "null argument");
+    if (which != 0 && which != 1) return fail(BIDO_ERR_ARG, "unknown factor");
+    if (q->spmv_group != 0 && q->spmv_group != 4 && q->spmv_group != 8 && q->spmv_group != 16 &&
+        q->spmv_group != 32)
+        return fail(BIDO_ERR_ARG, "spmv_group must be 4, 8, 16 or 32");
+    if (c->batched) return fail(BIDO_ERR_STATE, "context belongs to a batch");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->drop_graphs();
+    PlanOptions o;
+    o.top_h = q->top_h;
+    o.fwd_cols = q->fwd_cols;
+    o.bwd_rows = q->bwd_rows;
+    o.bwd_wide = q->bwd_wide;
+    o.level_items = q->level_items;
+    o.sub_h = q->sub_h;
+    o.sub_want = q->sub_want;
+    o.sub_total = q->sub_total;
+    o.bwd_group_max = q->bwd_group_max;
+    FactorDev& cur = which == 0 ? c->p1 : c->pk;
+    const Factor& f = which == 0 ? c->hs.p1 : c->hs.pk;
+    FactorDev cand;
+    bido_status e = build_factor_dev(f, true, cand, c->hs.params.n_threads, &o);
+    if (e != BIDO_OK) {
+        cand.release();
+        return e;
+    }
+    std::swap(cur, cand);
+    cand.release();
+    f.trim_top_cache(cur.top_h);
+    HIP_OK(poison_workspace(cur));
+    if (q->spmv_group) c->spmv_group = q->spmv_group;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return BIDO_OK;
+}
+
+bido_status bido_get_plan(const bido_ctx* c, int which, bido_plan* q) {
+    if (!c || !q) return fail(BIDO_ERR_ARG, "null argument");
+    if (which != 0 && which != 1) return fail(BIDO_ERR_ARG, "unknown factor");
+    const PlanOptions& o = (which == 0 ? c->p1 : c->pk).opts;
+    bido_default_plan(q);
+    q->top_h = o.top_h;
+    q->fwd_cols = o.fwd_cols;
+    q->bwd_rows = o.bwd_rows;
+    q->bwd_wide = o.bwd_wide;
+    q->level_items = o.level_items;
+    q->sub_h = o.sub_h;
+    q->sub_want = o.sub_want;
+    q->sub_total = o.sub_total;
+    q->bwd_group_max = o.bwd_group_max;
+    q->spmv_group = c->spmv_group;
     return BIDO_OK;
 }
 

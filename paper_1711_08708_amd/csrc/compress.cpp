@@ -16,11 +16,9 @@
 
 namespace bido {
 
-void compress(Factor& f, const double* xyz, int dim, double eps, double eta, int n_threads) {
-    (void)n_threads;
+void set_top_compression(Factor& f, const double* xyz, int dim, double eps) {
     f.dim = dim;
     f.eps = eps;
-    f.eta = eta;
     f.xyz.assign(xyz, xyz + (size_t)f.n * dim);
 }
 

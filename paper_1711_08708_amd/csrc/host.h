@@ -88,26 +88,12 @@ Csr permute(const Csr& a, const std::vector<int64_t>& perm,
 // contribution subtracted from the boundary) and the backward solve of
 // L^T x = y is  x_t = P_t^T [y_t; -x_B].
 // ---------------------------------------------------------------------
-struct LowRank {               // admissible block U V^T of a panel
-    int r0, nr, c0, nc, rank;
-    std::vector<double> U;     // nr x rank, row-major
-    std::vector<double> V;     // nc x rank, row-major
-};
-struct DenseBlk {              // inadmissible (or small) block of a panel
-    int r0, nr, c0, nc;
-    bool lower_tri;            // diagonal block of L^-1: only c <= r stored
-    std::vector<double> D;     // nr x nc row-major (full storage)
-};
-
 struct Front {
     int node = -1;
     int64_t off = 0;                 // first own index
     int nI = 0, nB = 0;
     std::vector<int64_t> B;          // boundary indices (sorted, new order)
     std::vector<double> P;           // dense panel, (nI+nB) x nI row-major
-    bool compressed = false;
-    std::vector<DenseBlk> dense;     // hierarchical form (when compressed)
-    std::vector<LowRank> lowrank;
 };
 
 struct Hodlr {
@@ -142,8 +128,9 @@ struct Factor {
     std::vector<int64_t> grounds;    // every grounded index (several in a merged forest)
     NdTree tree;
     std::vector<Front> fronts;       // indexed like tree.nodes
-    // hierarchical compression (eps = 0: exact); vertex coordinates in tree order
-    double eps = 0.0, eta = 2.0;
+    // accuracy of the hierarchical top (eps = 0: exact); vertex coordinates in
+    // tree order (the top's bisection order is built from them)
+    double eps = 0.0;
     int dim = 0;
     std::vector<double> xyz;
     // tops of earlier plans, by cut height (plans built again while tuning
@@ -162,9 +149,7 @@ struct Factor {
     std::vector<const Factor*> parts;
     std::vector<int64_t> part_off;
     std::vector<int> part_node0, part_top_h;
-    int64_t dense_entries() const;
-    int64_t stored_entries() const;  // after compression
-    int64_t n_lowrank() const;
+    int64_t dense_entries() const;   // panel entries (lower triangles + boundary blocks)
 };
 
 // Factor the SPD matrix a (already in tree order).  If ground >= 0 the
@@ -172,11 +157,10 @@ struct Factor {
 bool multifrontal(const Csr& a, Factor& f, int64_t ground, int n_threads,
                   std::string& err);
 
-// Record the compression accuracy eps and the vertex coordinates (tree order)
-// of a factor; the execution plan then holds the inverse of the top
-// separators' Schur complement in hierarchical low-rank form at eps.
-void compress(Factor& f, const double* xyz, int dim, double eps, double eta,
-              int n_threads);
+// Record the accuracy eps and the vertex coordinates (tree order) of a
+// factor; the execution plan then holds the inverse of the top separators'
+// Schur complement in hierarchical low-rank form at eps (exact panels below).
+void set_top_compression(Factor& f, const double* xyz, int dim, double eps);
 
 // Rank-revealing QR truncation: B (m x n row-major, leading dimension ld)
 // ~ U V^T, U (m x k) and V (n x k) column-major, stopping at the first pivot
@@ -197,7 +181,7 @@ void merge_factors(const std::vector<const Factor*>& fs, const std::vector<int64
                    Factor& out);
 
 // Host application of the factor (test hook): x = (L L^T)^-1 b with the
-// grounded entry fixed to zero.  Uses the compressed form when present.
+// grounded entry fixed to zero.
 void host_solve(const Factor& f, const double* b, double* x);
 
 // Chebyshev-accelerated Jacobi iteration for P_K ~ K_m (chebyshev.cpp).

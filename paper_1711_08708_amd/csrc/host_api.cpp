@@ -10,6 +10,7 @@
 
 struct bido_host {
     bido::HostSetup hs;
+    bido::PlanOptions opt[2];   // plan options of the P_1 and P_K queries
 };
 
 namespace {
@@ -139,15 +140,12 @@ bido_status bido_host_index(const bido_host* h, int which, int64_t* n, const int
     return BIDO_OK;
 }
 
-bido_status bido_host_factor_stats(const bido_host* h, int which, int64_t* dense_entries,
-                                   int64_t* stored_entries, int64_t* n_lowrank, int* height,
+bido_status bido_host_factor_stats(const bido_host* h, int which, int64_t* entries, int* height,
                                    int* max_sep) {
     if (!h) return hfail(BIDO_ERR_ARG, "null argument");
     const bido::Factor* f = which == BIDO_FACTOR_P1 ? &h->hs.p1 : which == BIDO_FACTOR_PK ? &h->hs.pk : nullptr;
     if (!f) return hfail(BIDO_ERR_ARG, "unknown factor");
-    if (dense_entries) *dense_entries = f->dense_entries();
-    if (stored_entries) *stored_entries = f->stored_entries();
-    if (n_lowrank) *n_lowrank = f->n_lowrank();
+    if (entries) *entries = f->dense_entries();
     if (height) *height = f->tree.height;
     if (max_sep) {
         int m = 0;
@@ -167,12 +165,11 @@ bido_status bido_host_factor_nodes(const bido_host* h, int which, int64_t* n_nod
     if (out)
         for (int64_t i = 0; i < nn && i < cap; ++i) {
             const auto& nd = f->tree.nodes[i];
-            out[i * 6 + 0] = f->fronts[i].nI;
-            out[i * 6 + 1] = f->fronts[i].nB;
-            out[i * 6 + 2] = nd.height;
-            out[i * 6 + 3] = nd.depth;
-            out[i * 6 + 4] = nd.parent;
-            out[i * 6 + 5] = (int32_t)f->fronts[i].lowrank.size();
+            out[i * 5 + 0] = f->fronts[i].nI;
+            out[i * 5 + 1] = f->fronts[i].nB;
+            out[i * 5 + 2] = nd.height;
+            out[i * 5 + 3] = nd.depth;
+            out[i * 5 + 4] = nd.parent;
         }
     return BIDO_OK;
 }
@@ -183,7 +180,7 @@ bido_status bido_host_factor_emulate(const bido_host* h, int which, const double
     if (!f) return hfail(BIDO_ERR_ARG, "unknown factor");
     bido::FactorPlan p;
     std::string err;
-    if (!bido::build_plan(*f, p, err, h->hs.params.n_threads)) return hfail(BIDO_ERR_ARG, err);
+    if (!bido::build_plan(*f, p, err, h->hs.params.n_threads, &h->opt[which])) return hfail(BIDO_ERR_ARG, err);
     try {
         bido::emulate_plan(p, b, x);
     } catch (const std::exception& e) {
@@ -193,18 +190,36 @@ bido_status bido_host_factor_emulate(const bido_host* h, int which, const double
 }
 
 bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n_sub, int* n_levels,
-                                  int64_t* n_fwd_items, int64_t* n_bwd_items) {
+                                  int64_t* n_fwd_items, int64_t* n_bwd_items, int64_t* n_bwd_split) {
     if (!h) return hfail(BIDO_ERR_ARG, "null argument");
     const bido::Factor* f = which == BIDO_FACTOR_P1 ? &h->hs.p1 : which == BIDO_FACTOR_PK ? &h->hs.pk : nullptr;
     if (!f) return hfail(BIDO_ERR_ARG, "unknown factor");
     bido::FactorPlan p;
     std::string err;
-    if (!bido::build_plan(*f, p, err)) return hfail(BIDO_ERR_ARG, err);
+    if (!bido::build_plan(*f, p, err, 0, &h->opt[which])) return hfail(BIDO_ERR_ARG, err);
     if (hc) *hc = p.hc;
     if (n_sub) *n_sub = p.n_sub;
     if (n_levels) *n_levels = (int)p.spans.size();
     if (n_fwd_items) *n_fwd_items = (int64_t)p.fwd_items.size();
     if (n_bwd_items) *n_bwd_items = (int64_t)p.bwd_items.size();
+    if (n_bwd_split) *n_bwd_split = (int64_t)p.bwd_comb.size();
+    return BIDO_OK;
+}
+
+bido_status bido_host_set_plan(bido_host* h, int which, const bido_plan* q) {
+    if (!h || !q) return hfail(BIDO_ERR_ARG, "null argument");
+    if (which != BIDO_FACTOR_P1 && which != BIDO_FACTOR_PK) return hfail(BIDO_ERR_ARG, "unknown factor");
+    bido::PlanOptions o;
+    o.top_h = q->top_h;
+    o.fwd_cols = q->fwd_cols;
+    o.bwd_rows = q->bwd_rows;
+    o.bwd_wide = q->bwd_wide;
+    o.level_items = q->level_items;
+    o.sub_h = q->sub_h;
+    o.sub_want = q->sub_want;
+    o.sub_total = q->sub_total;
+    o.bwd_group_max = q->bwd_group_max;
+    h->opt[which] = o;
     return BIDO_OK;
 }
 
@@ -231,18 +246,24 @@ bido_status bido_host_merge(const bido_host* const* hs, int n, bido_host** out) 
 }
 
 bido_status bido_host_factor_top(const bido_host* h, int which, int* top_h, int64_t* n_top, double* seconds,
-                                 int64_t* stored_entries, int* max_rank) {
+                                 int64_t* stored_entries, int* max_rank, int64_t* n_lowrank) {
     if (!h) return hfail(BIDO_ERR_ARG, "null argument");
     const bido::Factor* f = which == BIDO_FACTOR_P1 ? &h->hs.p1 : which == BIDO_FACTOR_PK ? &h->hs.pk : nullptr;
     if (!f) return hfail(BIDO_ERR_ARG, "unknown factor");
     bido::FactorPlan p;
     std::string err;
-    if (!bido::build_plan(*f, p, err, h->hs.params.n_threads)) return hfail(BIDO_ERR_ARG, err);
+    if (!bido::build_plan(*f, p, err, h->hs.params.n_threads, &h->opt[which])) return hfail(BIDO_ERR_ARG, err);
     if (top_h) *top_h = p.top_h;
     if (n_top) *n_top = p.n_top;
     if (seconds) *seconds = p.top_seconds;
     if (stored_entries) *stored_entries = p.top_hodlr ? (int64_t)p.hodlr.val.size() : p.n_top * p.n_top;
     if (max_rank) *max_rank = p.top_hodlr ? p.hodlr.max_rank : -1;
+    if (n_lowrank) {
+        int64_t k = 0;
+        if (p.top_hodlr)
+            for (const auto& b : p.hodlr.blocks) k += b.k > 0;
+        *n_lowrank = k;
+    }
     return BIDO_OK;
 }
 

@@ -90,6 +90,8 @@ enum ScalarSlot {
     S_Y1SUM,        // sum of Y_1 (range check)
     S_TN2,          // |t|^2 of the learned correction's input
     S_ALPHA,        // step length of the latest PCG update
+    S_EL_RR,        // |b - S_1 x|^2 of the elliptic solve of a Strang step
+    S_EL_BB,        // |b|^2 of that solve
     S_COUNT = 32
 };
 

@@ -82,6 +82,11 @@ __global__ void k_fill(int64_t n, double* x, double v) {
         x[i] = v;
 }
 
+__global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        y[i] += a * x[i];
+}
+
 // dst[pos[i]] = src[i]
 __global__ void k_scatter_in(int64_t n, const int64_t* __restrict__ pos,
                              const double* __restrict__ src, double* __restrict__ dst) {
@@ -1194,6 +1199,10 @@ static inline unsigned grid_for(int64_t n, int64_t per_block = BLOCK, unsigned c
     return (unsigned)g;
 }
 
+void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
+    if (n <= 0) return;
+    k_axpy<<<grid_for(n), BLOCK, 0, s>>>(n, a, x, y);
+}
 void launch_fill(hipStream_t s, int64_t n, double* x, double v) {
     if (n <= 0) return;
     k_fill<<<grid_for(n), BLOCK, 0, s>>>(n, x, v);
@@ -1341,11 +1350,7 @@ template <typename T>
 void launch_tri_bwd_sub(hipStream_t s, const TriPlan& P, const TriNode* nodes, const T* panel,
                         const int64_t* bidx, const double* y, double* x) {
     if (P.n_sub == 0) return;
-    static const int env_max = [] {
-        const char* e = std::getenv("BIDO_BWD_GROUP_MAXN");
-        return e && *e ? std::max(0, std::min(SUB_NW / 2, std::atoi(e))) : -1;
-    }();
-    const int group_max = env_max >= 0 ? env_max : std::max(0, std::min(SUB_NW / 2, P.bwd_group_max));
+    const int group_max = std::max(0, std::min(SUB_NW / 2, P.bwd_group_max));
     k_tri_bwd_sub<T><<<P.n_sub, SUB_BLOCK, 0, s>>>(P.sub_tn, P.sub_hoff, P.hc, panel, bidx, y, x, group_max,
                                                    P.skip);
 }

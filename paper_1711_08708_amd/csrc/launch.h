@@ -89,6 +89,7 @@ struct SegTable {
 };
 
 void launch_fill(hipStream_t s, int64_t n, double* x, double v);
+void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y);   // y += a x
 void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst);
 void launch_scatter_in_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst);
 void launch_gather_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst);

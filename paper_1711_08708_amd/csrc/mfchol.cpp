@@ -29,26 +29,6 @@ int64_t Factor::dense_entries() const {
     return s;
 }
 
-int64_t Factor::stored_entries() const {
-    int64_t s = 0;
-    for (const auto& f : fronts) {
-        if (!f.compressed) {
-            s += (int64_t)f.nI * (f.nI + 1) / 2 + (int64_t)f.nB * f.nI;
-            continue;
-        }
-        for (const auto& d : f.dense)
-            s += d.lower_tri ? (int64_t)d.nr * (d.nr + 1) / 2 : (int64_t)d.nr * d.nc;
-        for (const auto& l : f.lowrank) s += (int64_t)(l.nr + l.nc) * l.rank;
-    }
-    return s;
-}
-
-int64_t Factor::n_lowrank() const {
-    int64_t s = 0;
-    for (const auto& f : fronts) s += (int64_t)f.lowrank.size();
-    return s;
-}
-
 namespace {
 
 // Pattern/values of the grounded matrix: row and column g reduced to the
@@ -242,34 +222,12 @@ namespace {
 void panel_apply(const Front& fr, const double* w, double* out) {
     // out = P_t w   (nI + nB rows)
     const int nI = fr.nI, nF = fr.nI + fr.nB;
-    if (!fr.compressed) {
-        for (int r = 0; r < nF; ++r) {
-            const double* p = &fr.P[(size_t)r * nI];
-            int len = r < nI ? r + 1 : nI;
-            double s = 0.0;
-            for (int c = 0; c < len; ++c) s += p[c] * w[c];
-            out[r] = s;
-        }
-        return;
-    }
-    std::fill(out, out + nF, 0.0);
-    for (const auto& d : fr.dense)
-        for (int r = 0; r < d.nr; ++r) {
-            double s = 0.0;
-            int len = d.lower_tri ? r + 1 : d.nc;
-            for (int c = 0; c < len; ++c) s += d.D[(size_t)r * d.nc + c] * w[d.c0 + c];
-            out[d.r0 + r] += s;
-        }
-    std::vector<double> tmp;
-    for (const auto& l : fr.lowrank) {
-        tmp.assign(l.rank, 0.0);
-        for (int c = 0; c < l.nc; ++c)
-            for (int k = 0; k < l.rank; ++k) tmp[k] += l.V[(size_t)c * l.rank + k] * w[l.c0 + c];
-        for (int r = 0; r < l.nr; ++r) {
-            double s = 0.0;
-            for (int k = 0; k < l.rank; ++k) s += l.U[(size_t)r * l.rank + k] * tmp[k];
-            out[l.r0 + r] += s;
-        }
+    for (int r = 0; r < nF; ++r) {
+        const double* p = &fr.P[(size_t)r * nI];
+        int len = r < nI ? r + 1 : nI;
+        double s = 0.0;
+        for (int c = 0; c < len; ++c) s += p[c] * w[c];
+        out[r] = s;
     }
 }
 
@@ -277,29 +235,10 @@ void panel_apply_t(const Front& fr, const double* z, double* out) {
     // out = P_t^T z   (nI entries), z has nI + nB entries
     const int nI = fr.nI, nF = fr.nI + fr.nB;
     std::fill(out, out + nI, 0.0);
-    if (!fr.compressed) {
-        for (int r = 0; r < nF; ++r) {
-            const double* p = &fr.P[(size_t)r * nI];
-            int len = r < nI ? r + 1 : nI;
-            for (int c = 0; c < len; ++c) out[c] += p[c] * z[r];
-        }
-        return;
-    }
-    for (const auto& d : fr.dense)
-        for (int r = 0; r < d.nr; ++r) {
-            int len = d.lower_tri ? r + 1 : d.nc;
-            for (int c = 0; c < len; ++c) out[d.c0 + c] += d.D[(size_t)r * d.nc + c] * z[d.r0 + r];
-        }
-    std::vector<double> tmp;
-    for (const auto& l : fr.lowrank) {
-        tmp.assign(l.rank, 0.0);
-        for (int r = 0; r < l.nr; ++r)
-            for (int k = 0; k < l.rank; ++k) tmp[k] += l.U[(size_t)r * l.rank + k] * z[l.r0 + r];
-        for (int c = 0; c < l.nc; ++c) {
-            double s = 0.0;
-            for (int k = 0; k < l.rank; ++k) s += l.V[(size_t)c * l.rank + k] * tmp[k];
-            out[l.c0 + c] += s;
-        }
+    for (int r = 0; r < nF; ++r) {
+        const double* p = &fr.P[(size_t)r * nI];
+        int len = r < nI ? r + 1 : nI;
+        for (int c = 0; c < len; ++c) out[c] += p[c] * z[r];
     }
 }
 
@@ -347,7 +286,6 @@ void merge_factors(const std::vector<const Factor*>& fs, const std::vector<int64
     out.n = n_total;
     out.ground = -1;
     out.eps = fs.empty() ? 0.0 : fs[0]->eps;
-    out.eta = fs.empty() ? 2.0 : fs[0]->eta;
     out.dim = fs.empty() ? 0 : fs[0]->dim;
     bool coords = out.dim > 0;
     for (const Factor* f : fs) coords = coords && f->dim == out.dim && (int64_t)f->xyz.size() >= f->n * f->dim;

@@ -22,31 +22,6 @@ int64_t panel_row_off(int64_t r, int64_t nI) {
     return r < nI ? r * (r + 1) / 2 : nI * (nI + 1) / 2 + (r - nI) * nI;
 }
 
-int env_limit(const char* name, int def, int lo, int hi) {
-    const char* e = std::getenv(name);
-    if (!e || !*e) return def;
-    return std::max(lo, std::min(hi, std::atoi(e)));
-}
-
-// Row-major dense (nI+nB) x nI view of a panel (rebuilt from its blocks when
-// the panel is held in compressed form).
-const double* dense_panel(const Front& fr, std::vector<double>& buf) {
-    if (!fr.compressed) return fr.P.data();
-    const int nI = fr.nI;
-    buf.assign((size_t)(nI + fr.nB) * nI, 0.0);
-    for (const auto& b : fr.dense)
-        for (int r = 0; r < b.nr; ++r)
-            for (int c = 0; c < (b.lower_tri ? r + 1 : b.nc); ++c)
-                buf[(size_t)(b.r0 + r) * nI + b.c0 + c] = b.D[(size_t)r * b.nc + c];
-    for (const auto& l : fr.lowrank)
-        for (int r = 0; r < l.nr; ++r)
-            for (int c = 0; c < l.nc; ++c) {
-                double s = 0.0;
-                for (int k = 0; k < l.rank; ++k) s += l.U[(size_t)r * l.rank + k] * l.V[(size_t)c * l.rank + k];
-                buf[(size_t)(l.r0 + r) * nI + l.c0 + c] = s;
-            }
-    return buf.data();
-}
 
 // S_top^-1 column by column: the sweeps of the top fronts applied to unit
 // vectors e_j (top numbering), in blocks of TB columns.  The forward sweep of
@@ -57,13 +32,12 @@ void top_inverse(const Factor& f, const std::vector<int>& top, const std::vector
                  int64_t ntop, std::vector<double>& inv, int n_threads) {
     constexpr int TB = 32;
     const int nt = (int)top.size();
-    std::vector<std::vector<double>> dbuf(nt);
     std::vector<const double*> P(nt);
     std::vector<int64_t> sb(nt), eb(nt);          // top-subtree range [sb, eb) per front
     std::vector<int> local(f.fronts.size(), -1);
     for (int q = 0; q < nt; ++q) {
         const Front& fr = f.fronts[top[q]];
-        P[q] = dense_panel(fr, dbuf[q]);
+        P[q] = fr.P.data();
         local[top[q]] = q;
         eb[q] = tmap[fr.off] + fr.nI;
         sb[q] = tmap[fr.off];
@@ -200,25 +174,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
         const Front& fr = f.fronts[id];
         const TriNode& d = p.nodes[id];
         const int nI = fr.nI;
-        std::vector<double> dense;
         const std::vector<double>* P = &fr.P;
-        if (fr.compressed) {
-            // dense view of a compressed panel, rebuilt from its blocks
-            dense.assign((size_t)(nI + fr.nB) * nI, 0.0);
-            for (const auto& b : fr.dense)
-                for (int r = 0; r < b.nr; ++r)
-                    for (int c = 0; c < (b.lower_tri ? r + 1 : b.nc); ++c)
-                        dense[(size_t)(b.r0 + r) * nI + b.c0 + c] = b.D[(size_t)r * b.nc + c];
-            for (const auto& l : fr.lowrank)
-                for (int r = 0; r < l.nr; ++r)
-                    for (int c = 0; c < l.nc; ++c) {
-                        double s = 0.0;
-                        for (int k = 0; k < l.rank; ++k)
-                            s += l.U[(size_t)r * l.rank + k] * l.V[(size_t)c * l.rank + k];
-                        dense[(size_t)(l.r0 + r) * nI + l.c0 + c] = s;
-                    }
-            P = &dense;
-        }
         int64_t o = d.panel;
         for (int r = 0; r < nI + fr.nB; ++r) {
             const int len = r < nI ? r + 1 : nI;
@@ -266,17 +222,15 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     };
     for (int id = 0; id < nn; ++id) p.nodes[id].tree = std::max(0, part_of(root_of[id]));
     std::vector<int> hc_of(nn, -1);
-    // cap of every tree's cut (environment BIDO_SUB_H when not given)
-    const char* esub = std::getenv("BIDO_SUB_H");
-    const int sub_cap = o.sub_h >= 0 ? o.sub_h : (esub && *esub ? std::atoi(esub) : -1);
+    // cap of every tree's cut
+    const int sub_cap = o.sub_h;
     {
         std::vector<std::vector<int>> members(nn);
         for (int id = 0; id < nn; ++id) members[root_of[id]].push_back(id);
         int64_t all_v = 0;
         for (int id = 0; id < nn; ++id) all_v += f.fronts[id].nI;
-        // a forest may share a subtree budget (environment BIDO_SUB_TOTAL)
-        const char* est = std::getenv("BIDO_SUB_TOTAL");
-        const int sub_total = o.sub_total > 0 ? o.sub_total : (forest && est && *est ? std::atoi(est) : 0);
+        // a forest may share a subtree budget
+        const int sub_total = o.sub_total > 0 ? o.sub_total : 0;
         for (int r : roots) {
             const int Hr = t.nodes[r].height;
             std::vector<int> mw(Hr + 1, 0), mf(Hr + 1, 0), nroots(Hr + 2, 0);
@@ -295,8 +249,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
                 nroots[h] += nroots[h - 1];
             }
             int cut = -1;
-            const char* ew = std::getenv("BIDO_SUB_WANT");
-            int want0 = ew && *ew ? std::max(1, std::atoi(ew)) : 256;
+            int want0 = o.sub_want > 0 ? o.sub_want : 256;
             if (sub_total > 0 && all_v > 0) {
                 int64_t tv = 0;
                 for (int id : members[r]) tv += f.fronts[id].nI;
@@ -383,9 +336,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
         int best = roots.empty() ? H + 1 : model_cut(roots[0], lowest);
         if (roots.empty()) lowest = H + 1;
         // a forced cut is raised as far as the top-size bound requires
-        const char* e = std::getenv("BIDO_TOP_H");
         if (o.top_h >= 0) best = std::max(lowest, std::min(H + 1, o.top_h));
-        else if (e && *e) best = std::max(lowest, std::min(H + 1, std::atoi(e)));
         for (int id = 0; id < nn; ++id) cut_of[id] = best;
         p.top_h = best;
     } else {
@@ -615,21 +566,18 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     // Work-item limits: columns per forward item and rows per backward item.
     // Splitting a tile over several items exposes more workgroups but needs a
     // combine launch after the level, so the limits are tunable
-    // (environment BIDO_FWD_COLS, BIDO_BWD_MAXR) within the LDS staging bound.
-    const int fwd_cols = o.fwd_cols > 0 ? std::max(32, std::min(PLAN_LDS_DOUBLES, o.fwd_cols))
-                                        : env_limit("BIDO_FWD_COLS", PLAN_FWD_COLS, 32, PLAN_LDS_DOUBLES);
-    const int bwd_maxr = o.bwd_rows > 0 ? std::max(64, std::min(PLAN_LDS_DOUBLES, o.bwd_rows))
-                                        : env_limit("BIDO_BWD_MAXR", PLAN_BWD_MAXR, 64, PLAN_LDS_DOUBLES);
+    // (PlanOptions fwd_cols, bwd_rows) within the LDS staging bound.
+    const int fwd_cols = o.fwd_cols > 0 ? std::max(32, std::min(PLAN_LDS_DOUBLES, o.fwd_cols)) : PLAN_FWD_COLS;
+    const int bwd_maxr = o.bwd_rows > 0 ? std::max(64, std::min(PLAN_LDS_DOUBLES, o.bwd_rows)) : PLAN_BWD_MAXR;
     p.used.fwd_cols = fwd_cols;
     p.used.bwd_rows = bwd_maxr == PLAN_BWD_MAXR ? 0 : bwd_maxr;
-    {
-        const char* ew = std::getenv("BIDO_BWD_WIDE");
-        p.bwd_wide = o.bwd_wide >= 0 ? o.bwd_wide != 0 : (ew && *ew ? std::atoi(ew) != 0 : true);
-        p.used.bwd_wide = p.bwd_wide ? 1 : 0;
-    }
-    // wide backward items wanted per level of tall tiles (environment
-    // BIDO_BWD_LEVEL_ITEMS; 0 keeps every tile whole)
-    const int want_items = env_limit("BIDO_BWD_LEVEL_ITEMS", PLAN_BWD_LEVEL_ITEMS, 0, 1 << 20);
+    p.bwd_wide = o.bwd_wide >= 0 ? o.bwd_wide != 0 : true;
+    p.used.bwd_wide = p.bwd_wide ? 1 : 0;
+    // wide backward items wanted per level of tall tiles (0 keeps every tile whole)
+    const int want_items = o.level_items >= 0 ? std::min(o.level_items, 1 << 20) : PLAN_BWD_LEVEL_ITEMS;
+    p.used.level_items = o.level_items;
+    p.used.sub_want = o.sub_want;
+    p.used.bwd_group_max = o.bwd_group_max;
     std::vector<std::pair<size_t, size_t>> fspan, bspan, fcspan, bcspan;
     struct LdsSz { size_t f, b; };
     std::vector<LdsSz> lds;

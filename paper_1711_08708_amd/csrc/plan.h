@@ -10,20 +10,24 @@
 
 namespace bido {
 
-// Work-item shapes and the top cut; values <= 0 (top_h < 0) take the
-// defaults (environment BIDO_FWD_COLS / BIDO_BWD_MAXR / BIDO_TOP_H, else the
-// built-in sizes and the cost model of the cut).
+// Work-item shapes, the subtree cuts and the top cut of a plan.  Zero or
+// negative values take the built-in defaults (the cost model for the top
+// cut).  These are the only plan knobs; the library reads no environment.
 struct PlanOptions {
-    int fwd_cols = 0;   // columns per forward level item
-    int bwd_rows = 0;   // rows per backward level item (0: 8192 / tile width, at most 512)
+    int fwd_cols = 0;   // columns per forward level item (0: PLAN_FWD_COLS)
+    int bwd_rows = 0;   // rows per backward level item (0: the level rule below)
     int top_h = -1;     // first height of the top (raised to fit the top-size bound)
     int sub_h = -1;     // highest subtree cut of any tree (< 0: the size rule alone)
+    int sub_want = 0;   // subtrees wanted per tree (0: 256)
     int sub_total = 0;  // > 0: subtrees wanted over the whole forest, shared by the trees
                         // in proportion to their vertices (each tree's cut then stays
-                        // below its recorded top cut); 0: 256 per tree
+                        // below its recorded top cut); 0: sub_want per tree
     int bwd_wide = -1;  // backward level items of 1024 threads over whole column tiles
-                        // (1), of 256 threads over row ranges (0); < 0: environment
-                        // BIDO_BWD_WIDE, else 1
+                        // (1), of 256 threads over row ranges (0); < 0: 1
+    int level_items = -1; // wide backward items wanted per level of tall tiles (< 0:
+                          // PLAN_BWD_LEVEL_ITEMS; 0 keeps every tile whole)
+    int bwd_group_max = 0; // backward subtree heights with at most this many nodes
+                           // use wave groups (0: 2 in 2D, 4 in 3D)
 };
 
 struct FactorPlan {

@@ -193,8 +193,8 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
             for (int a = 0; a < d; ++a) x1[p * d + a] = mesh->xyz[t1.perm[p] * d + a];
         for (int64_t p = 0; p < NH; ++p)
             for (int a = 0; a < d; ++a) xk[p * d + a] = xyz_h[tk.perm[p] * d + a];
-        compress(hs.p1, x1.data(), d, P.eps_h, P.eta, nth);
-        compress(hs.pk, xk.data(), d, P.eps_h, P.eta, nth);
+        set_top_compression(hs.p1, x1.data(), d, P.eps_h);
+        set_top_compression(hs.pk, xk.data(), d, P.eps_h);
     }
 
     // coupling blocks S_i Pi and Pi^T S_i in internal numbering
@@ -309,7 +309,7 @@ bool host_set_dt(HostSetup& hs, double dt, bool refactor, std::string& err) {
         nf.tree = hs.pk.tree;
         std::string e2;
         if (!multifrontal(Kmp, nf, -1, P.n_threads, e2)) { err = "P_K: " + e2; return false; }
-        compress(nf, hs.pk.xyz.data(), hs.pk.dim, hs.pk.eps, hs.pk.eta, P.n_threads);
+        set_top_compression(nf, hs.pk.xyz.data(), hs.pk.dim, hs.pk.eps);
         hs.pk = std::move(nf);
     }
     Csr& L = hs.lam;

@@ -115,7 +115,10 @@ def test_exact_factors_invert_the_inner_matrices(mk):
     yk = hs.factor_apply(B.FACTOR_PK, Km @ xk)
     assert np.linalg.norm(yk - xk) <= 1e-11 * np.linalg.norm(xk)
     st = hs.factor_stats(B.FACTOR_P1)
-    assert st["stored_entries"] == st["dense_entries"] and st["n_lowrank"] == 0
+    nodes = hs.factor_nodes(B.FACTOR_P1)
+    nI, nB = nodes[:, 0].astype(np.int64), nodes[:, 1].astype(np.int64)
+    assert st["entries"] == int((nI * (nI + 1) // 2 + nI * nB).sum())
+    assert nI.sum() == S1.shape[0] and st["max_sep"] == nI.max()
 
 
 def test_bad_inputs_are_rejected():
@@ -137,7 +140,7 @@ def test_bad_inputs_are_rejected():
 
 @pytest.mark.parametrize("mk", [lambda: w.thorax2d(n_target=3000, seed=2), lambda: w.slab3d(n=10),
                                 lambda: w.square2d(n=48)], ids=["thorax3000", "slab10", "square48"])
-def test_dense_top_at_every_cut(mk, monkeypatch):
+def test_dense_top_at_every_cut(mk):
     """Forcing the dense top at every possible cut height (down to the
     lowest level above the subtree phase) leaves the sweep result unchanged:
     S_top^-1 is the inverse of the Schur complement of the top vertices."""
@@ -152,7 +155,7 @@ def test_dense_top_at_every_cut(mk, monkeypatch):
         H = hs.factor_stats(which)["height"]
         cuts = []
         for th in range(hc + 1, H + 2):
-            monkeypatch.setenv("BIDO_TOP_H", str(th))
+            hs.set_plan(which, top_h=th)
             top = hs.factor_top(which)
             if top["top_h"] != th:               # raised to fit the top-size bound
                 continue
@@ -184,15 +187,15 @@ def test_device_plan_emulation_matches_host_factor(mk):
 
 @pytest.mark.parametrize("mk", [lambda: w.thorax2d(n_target=6000, seed=3), lambda: w.slab3d(n=12)],
                          ids=["thorax6000", "slab12"])
-def test_hierarchical_top_accuracy(mk, monkeypatch):
+def test_hierarchical_top_accuracy(mk):
     """With eps_h > 0 the inverse of the top separators' Schur complement is
     held in hierarchical low-rank form (Sec. 5.3).  The emulated inner solve
     then differs from the exact factor by an amount that shrinks with eps,
     and the storage shrinks as eps grows."""
     import paper_1711_08708_amd as B
     cfg = mk()
-    monkeypatch.setenv("BIDO_TOP_H", "0")             # lowest admissible cut: largest top
     exact = B.HostSetup(cfg, eps_h=0.0)
+    exact.set_plan(B.FACTOR_P1, top_h=0)              # lowest admissible cut: largest top
     n = len(exact.index(B.IDX_UPOS))
     b = np.random.default_rng(9).normal(size=n)
     ref = exact.factor_apply(B.FACTOR_P1, b)
@@ -200,6 +203,7 @@ def test_hierarchical_top_accuracy(mk, monkeypatch):
     rows = []
     for eps in (1e-12, 1e-8, 1e-5, 1e-3):
         hs = B.HostSetup(cfg, eps_h=eps)
+        hs.set_plan(B.FACTOR_P1, top_h=0)
         top = hs.factor_top(B.FACTOR_P1)
         emu = hs.factor_emulate(B.FACTOR_P1, b)
         err = np.linalg.norm(emu - ref) / np.linalg.norm(ref)
@@ -304,7 +308,7 @@ def test_hierarchical_top_with_a_decoupled_block():
 
 
 @pytest.mark.parametrize("sub_h", ["0", "1", "2"])
-def test_capped_subtree_cut_emulates_each_slice(sub_h, monkeypatch):
+def test_capped_subtree_cut_emulates_each_slice(sub_h):
     """Capping every tree's subtree cut (more of the sweep in level phases,
     tops chosen again where a tree had none) leaves the forest an exact
     solve of every slice (eps_h = 0: tops exact up to rounding)."""
@@ -322,18 +326,17 @@ def test_capped_subtree_cut_emulates_each_slice(sub_h, monkeypatch):
             lo, n = (off, N) if which == B.FACTOR_P1 else (off + N, NH)
             refs.append((lo, n, p.factor_apply(which, b[lo:lo + n])))
             off += N + NH
-        monkeypatch.setenv("BIDO_SUB_H", sub_h)
         merged = B.HostSetup.merged(parts)
+        merged.set_plan(which, sub_h=int(sub_h))
         plan = merged.factor_plan(which)
         emu = merged.factor_emulate(which, b)
-        monkeypatch.delenv("BIDO_SUB_H")
         assert plan["hc"] <= int(sub_h)
         for lo, n, ref in refs:
             assert np.abs(emu[lo:lo + n] - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("total", ["4", "64"])
-def test_forest_with_shared_subtree_budget(total, monkeypatch):
+def test_forest_with_shared_subtree_budget(total):
     """A forest that shares a subtree budget over its trees (bigger subtrees
     per tree, cuts kept below the trees' top cuts) is still an exact solve of
     every slice (eps_h = 0)."""
@@ -352,18 +355,17 @@ def test_forest_with_shared_subtree_budget(total, monkeypatch):
             p.factor_emulate(which, b[lo:lo + n])           # records the slice's top cut
             refs.append((lo, n, p.factor_apply(which, b[lo:lo + n])))
             off += N + NH
-        monkeypatch.setenv("BIDO_SUB_TOTAL", total)
         merged = B.HostSetup.merged(parts)
+        merged.set_plan(which, sub_total=int(total))
         plan = merged.factor_plan(which)
         top = merged.factor_top(which)
         emu = merged.factor_emulate(which, b)
-        monkeypatch.delenv("BIDO_SUB_TOTAL")
         print(which, total, plan, top)
         for lo, n, ref in refs:
             assert np.abs(emu[lo:lo + n] - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
-def test_tall_backward_tiles_are_split_and_still_exact(monkeypatch):
+def test_tall_backward_tiles_are_split_and_still_exact():
     """3D separators give level tiles of thousands of rows; the default plan
     cuts them into row ranges (with a combine step) when a level would
     otherwise have too few work items, and the host emulation of that plan
@@ -371,15 +373,15 @@ def test_tall_backward_tiles_are_split_and_still_exact(monkeypatch):
     import paper_1711_08708_amd as B
     cfg = w.slab3d(n=40)
     items = {}
-    for want in ("512", "0"):
-        monkeypatch.setenv("BIDO_BWD_LEVEL_ITEMS", want)
-        h = B.HostSetup(cfg, eps_h=0.0)
+    h = B.HostSetup(cfg, eps_h=0.0)
+    for want in (512, 0):
+        h.set_plan(B.FACTOR_P1, level_items=want)
         items[want] = h.factor_plan(B.FACTOR_P1)["n_bwd_items"]
         N = len(h.index(B.IDX_UPOS))
         b = np.random.default_rng(0).normal(size=N)
         x1, x2 = h.factor_apply(B.FACTOR_P1, b), h.factor_emulate(B.FACTOR_P1, b)
         assert np.abs(x1 - x2).max() <= 1e-12 * np.abs(x1).max()
-    assert items["512"] > items["0"], items
+    assert items[512] > items[0], items
 
 
 @pytest.mark.parametrize("case,msg", [

@@ -159,6 +159,31 @@ def test_learned_additive_and_flexible_cg(torch, setup, collected):
     assert wp <= 1e-8 and wl <= 1e-8
 
 
+@pytest.mark.xfail(reason="the trained corrections do not lower the iteration count: measured "
+                          "thorax200k 8.00 plain vs 8.14-8.22 stencil per step, thorax6000 5 vs 6 "
+                          "additive; the stencil on the S_m pattern cannot represent the non-local "
+                          "S_i S_1^+ S_i part of the Schur complement", strict=False)
+@pytest.mark.parametrize("kind", ["stencil", "additive"])
+def test_learned_gain(torch, setup, collected, kind):
+    """What the trained network gains over the plain block-LU preconditioner
+    on held-out steps (after the 12 collected ones), both at 1e-8 parity:
+    the total iteration count with the correction must not exceed the plain
+    one."""
+    B, mpnn, s, A, st, solver, theta = setup
+    solver.set_weights(mpnn.init_params(3) * np.concatenate([np.ones(mpnn.N_PARAMS - 33), np.zeros(33)]))
+    if kind == "stencil":
+        solver.learn_train(kind=B.LEARN_STENCIL, epochs=30, batch=4, lr=2e-3, seed=1, n_val=4)
+        mode = B.PRECOND_LEARNED
+    else:
+        solver.learn_train(kind=B.LEARN_ADDITIVE, epochs=40, batch=4, lr=2e-3, seed=1, n_val=4)
+        mode = B.PRECOND_LEARNED_ADDITIVE
+    it_p, wp, _, _ = _solve_steps(torch, solver, s, collected, 12, 6, learned=0)
+    it_l, wl, _, _ = _solve_steps(torch, solver, s, collected, 12, 6, learned=mode)
+    print(f"gain {kind}: plain {sum(it_p)} ({it_p}) learned {sum(it_l)} ({it_l})", flush=True)
+    assert wp <= 1e-8 and wl <= 1e-8
+    assert sum(it_l) <= sum(it_p)
+
+
 def test_fallback_keeps_parity(torch, setup):
     """A network with large random weights gives non-descent directions; the
     solve falls back to the plain apply there and still converges."""

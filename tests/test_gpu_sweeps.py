@@ -54,7 +54,7 @@ def test_inner_solve_matches_host(torch, name, which):
 
 @pytest.mark.parametrize("name", ["thorax40k", "slab10", "square48"])
 @pytest.mark.parametrize("which", [0, 1])
-def test_dense_top_at_lowest_cut(torch, name, which, monkeypatch):
+def test_dense_top_at_lowest_cut(torch, name, which):
     """The dense top forced down to the lowest cut it can take (every level
     phase replaced, or as many as fit the top-size bound) still reproduces
     the host factor on the device."""
@@ -63,13 +63,15 @@ def test_dense_top_at_lowest_cut(torch, name, which, monkeypatch):
     hs = B.HostSetup(cfg, eps_h=0.0)
     hc = hs.factor_plan(which)["hc"]
     H = hs.factor_stats(which)["height"]
-    monkeypatch.setenv("BIDO_TOP_H", str(hc + 1))   # raised to the lowest admissible cut
+    hs.set_plan(which, top_h=hc + 1)               # raised to the lowest admissible cut
     top = hs.factor_top(which)
     cut = top["top_h"]
     if cut > H:
         pytest.skip("no admissible dense top")
     print(f"{name} factor {which}: cut {cut} (hc {hc}, height {H}), n_top {top['n_top']}", flush=True)
-    solver = B.Solver(cfg, eps_h=0.0)        # plans are built with the forced cut
+    solver = B.Solver(cfg, eps_h=0.0)
+    solver.set_plan(which, top_h=hc + 1)     # the same forced cut on the device
+    assert solver.get_plan(which)["top_h"] == cut
     n = solver.N if which == 0 else solver.NH
     b = np.random.default_rng(2).normal(size=n)
     ref = hs.factor_apply(which, b)
@@ -83,15 +85,17 @@ def test_dense_top_at_lowest_cut(torch, name, which, monkeypatch):
 
 @pytest.mark.parametrize("name", ["thorax40k", "slab10"])
 @pytest.mark.parametrize("eps", [1e-10, 1e-4])
-def test_hierarchical_top_matches_emulation(torch, name, eps, monkeypatch):
+def test_hierarchical_top_matches_emulation(torch, name, eps):
     """With eps_h > 0 the top inverse is applied in hierarchical low-rank
     form; the device application equals the CPU emulation of the same plan
     to rounding, and stays within about eps of the exact factor."""
     import paper_1711_08708_amd as B
-    monkeypatch.setenv("BIDO_TOP_H", "0")     # lowest admissible cut: the largest top
     cfg = CASES[name]()
     hs = B.HostSetup(cfg, eps_h=eps)
     solver = B.Solver(cfg, eps_h=eps)
+    for which in (0, 1):                      # lowest admissible cut: the largest top
+        hs.set_plan(which, top_h=0)
+        solver.set_plan(which, top_h=0)
     for which in (0, 1):
         n = solver.N if which == 0 else solver.NH
         b = np.random.default_rng(4 + which).normal(size=n)

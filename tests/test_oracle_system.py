@@ -58,6 +58,28 @@ def test_three_solvers_agree(mk):
     assert bd.rel_err(Xc, Xd) < 1e-9
 
 
+@pytest.mark.parametrize("n", [12, 16])
+def test_cg_meets_sparse_lu_in_3d(n):
+    """At 3D sizes where the stopping test's condition estimate matters
+    (12^3 and 16^3 cubes, Jacobi condition numbers in the hundreds to
+    thousands), the Jacobi-CG solution agrees with the grounded sparse LU
+    solution to 1e-11, from rest and from a warm start, and its estimate
+    settles (the augmented matrix has no kernel)."""
+    s = bd.System(w.slab3d(n=n))
+    rng = np.random.default_rng(4)
+    V = rng.uniform(0, 100, s.NH)
+    h = rng.uniform(0, 1, s.NH)
+    Y = s.rhs(V, h, 0)
+    Xs = s.solve_sparse(Y)
+    Xc = s.solve_cg(Y)
+    kappa = s.last_cg["kappa"]
+    assert 10.0 < kappa < 1e6, s.last_cg
+    assert bd.rel_err(Xc[:s.N], Xs[:s.N]) < 1e-11 and bd.rel_err(Xc[s.N:], Xs[s.N:]) < 1e-11
+    x0 = Xs + rng.normal(0, 1.0, Xs.shape)
+    Xw = s.solve_cg(Y, x0=x0)
+    assert bd.rel_err(Xw[:s.N], Xs[:s.N]) < 1e-11 and bd.rel_err(Xw[s.N:], Xs[s.N:]) < 1e-11
+
+
 def test_constant_potential_is_stationary(small):
     """With Y = [0; gamma M_H c 1] the normalised solution is U = 0, V = c 1
     (S_i 1 = 0 and Pi^T S_i 1 = 0)."""
