@@ -236,6 +236,23 @@ bido_status bido_set_solver(bido_ctx* ctx, double tol, int max_iter);
  * point for the triangular sweeps; the solve path does not call it.      */
 bido_status bido_inner_solve(bido_ctx* ctx, int which, const double* b, double* x);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the apply of
+ * bido_inner_solve, same arguments, kernels and result (bit-identical),
+ * with the sweeps' work arrays (intermediate vector, update workspace,
+ * partial sums of split tiles, the top's vectors; the Chebyshev P_K's three
+ * vectors) taken from a fixed device workspace of 2^23 doubles (64 MiB)
+ * that every GPU the library runs on holds until the process ends, instead
+ * of the context's buffers.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine); the context must exist.  *need
+ * (may be null) gets the workspace doubles this apply uses.  Errors:
+ * BIDO_ERR_ARG as bido_inner_solve; BIDO_ERR_RANGE when the apply needs more
+ * than the fixed workspace (x untouched).  All calls on one GPU share its
+ * workspace and it keeps the last call's contents, so calls that overlap on
+ * one GPU (other streams, other threads) race; the call synchronises its
+ * stream before returning.                                               */
+bido_status bido_inner_solve_noalloc(bido_ctx* ctx, int which, const double* b, double* x, int64_t* need);
+
 /* --- alternative P_K (Sec. 5.3: P_1 and P_K are free choices) ----------- *
  * P_K ~ K_m = gamma M_H + S_m (Sec. 5.2) inside P_Lambda (Def. 2) is either
  * the hierarchical Cholesky factor of K_m (BIDO_PK_CHOLESKY, the default)

@@ -152,6 +152,8 @@ ABI = {
     "bido_set_solver": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]),
     "bido_inner_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p]),
+    "bido_inner_solve_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                                ctypes.c_void_p, _c_i64_p]),
     "bido_set_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "bido_set_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, _c_double_p]),
     "bido_set_pk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -374,6 +376,14 @@ class Solver:
     def inner_solve(self, which, b, x):
         n = self.N if which == FACTOR_P1 else self.NH
         _check(lib.bido_inner_solve(self.ctx, int(which), self._dev(b, n), self._dev(x, n)))
+
+    def inner_solve_noalloc(self, which, b, x):
+        """bido_inner_solve on the fixed workspace; returns the doubles it used."""
+        n = self.N if which == FACTOR_P1 else self.NH
+        need = ctypes.c_int64()
+        _check(lib.bido_inner_solve_noalloc(self.ctx, int(which), self._dev(b, n), self._dev(x, n),
+                                            ctypes.byref(need)))
+        return need.value
 
     def set_dt(self, dt):
         """Change the time step; returns the seconds the change took."""

@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libbido.so")
 
 HOST_SOURCES = ["assemble.cpp", "ndtree.cpp", "dense.cpp", "mfchol.cpp",
                 "compress.cpp", "plan.cpp", "setup.cpp", "host_api.cpp", "chebyshev.cpp", "record.cpp"]
-HIP_SOURCES = ["kernels.hip", "gnn.hip", "batch.hip", "api.cpp"]
+HIP_SOURCES = ["kernels.hip", "gnn.hip", "batch.hip", "noalloc.hip", "api.cpp"]
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")

@@ -1427,6 +1427,10 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     c->precision = params->precision;
     c->stream = (hipStream_t)stream;
     HIP_OK(hipGetDevice(&c->device));
+    {
+        double* ws = nullptr;                 // the fixed workspace's address on this device
+        HIP_OK(noalloc_scratch(c->device, &ws));
+    }
     c->N = hs.A.N;
     c->NH = hs.A.NH;
     c->n2 = c->N + c->NH;
@@ -1977,6 +1981,47 @@ bido_status bido_inner_solve(bido_ctx* c, int which, const double* b, double* x)
     if (!c || !b || !x || (which != 0 && which != 1)) return fail(BIDO_ERR_ARG, "bad argument");
     if (which == 0) inner_solve(c, c->p1, b, x);
     else pk_solve(c, b, x);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return BIDO_OK;
+}
+
+// The same apply with every work array of the sweeps (the intermediate y,
+// the update workspace, the partial sums of split tiles, the top's gathered
+// vector and projections; the Chebyshev P_K's three vectors) carved from the
+// fixed per-GPU workspace instead of the context's own buffers.  Allocates
+// nothing; clears the one entry that must start at zero (the update
+// workspace's constant 0.0) with a fill kernel.  Calls on one GPU share the
+// workspace: overlapping calls race.
+bido_status bido_inner_solve_noalloc(bido_ctx* c, int which, const double* b, double* x, int64_t* need) {
+    if (!c || !b || !x || (which != 0 && which != 1)) return fail(BIDO_ERR_ARG, "bad argument");
+    const bool cheb = which == 1 && c->pk_kind == BIDO_PK_CHEBYSHEV;
+    const FactorDev& src = which == 0 ? c->p1 : c->pk;
+    auto up = [](int64_t n) { return (std::max<int64_t>(n, 1) + 31) / 32 * 32; };   // 256-byte slots
+    int64_t total = 0;
+    if (cheb) total = 3 * up(c->NH);
+    else total = up(src.n) + up(src.upd_size) + up(src.scratch_size) + up(src.plan.n_top) + up(src.ht_size);
+    if (need) *need = total;
+    if (total > NOALLOC_SCRATCH_DOUBLES)
+        return fail(BIDO_ERR_RANGE, "inner solve needs " + std::to_string(total) +
+                                        " doubles of workspace; the fixed workspace holds " +
+                                        std::to_string(NOALLOC_SCRATCH_DOUBLES));
+    double* ws = nullptr;
+    HIP_OK(noalloc_scratch(c->device, &ws));
+    if (cheb) {
+        const int64_t m = up(c->NH);
+        pk_solve(c, b, x, ws, ws + m, ws + 2 * m);
+    } else {
+        FactorDev f = src;                         // shallow view: same factor, other workspace
+        double* q = ws;
+        f.ytmp = q;        q += up(src.n);
+        f.upd = q;         q += up(src.upd_size);
+        f.plan.scratch = q; q += up(src.scratch_size);
+        f.plan.top_w = src.plan.n_top > 0 ? q : nullptr; q += up(src.plan.n_top);
+        f.plan.ht = src.ht_size > 0 ? q : nullptr;
+        launch_fill(c->stream, 1, f.upd, 0.0);     // the constant 0.0 entry
+        inner_solve(c, f, b, x);
+    }
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(c->stream));
     return BIDO_OK;

@@ -88,6 +88,13 @@ struct SegTable {
     const SegSlice* sl = nullptr;    // device
 };
 
+// Fixed workspace of the allocation-free entry points (noalloc.hip): 64 MiB
+// per GPU, held until the process ends.  noalloc_scratch returns its device
+// address on `device` (looked up once per device; the caller's current
+// device is left unchanged).  Every call on a GPU shares that GPU's array.
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = int64_t(8) << 20;
+hipError_t noalloc_scratch(int device, double** ptr);
+
 void launch_fill(hipStream_t s, int64_t n, double* x, double v);
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y);   // y += a x
 void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst);
