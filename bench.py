@@ -39,9 +39,12 @@ def _parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--scheme", default="euler", choices=["euler", "cn", "strang"],
                     help="time scheme: semi-implicit (Sec. 3.2), Crank-Nicolson or Strang splitting")
-    ap.add_argument("--pk", default="cholesky", choices=["cholesky", "chebyshev"],
-                    help="P_K inside the block-LU preconditioner: the factor of K_m, or "
-                         "Chebyshev-accelerated Jacobi steps on K_m")
+    ap.add_argument("--pk", default="cholesky", choices=["cholesky", "chebyshev", "amg"],
+                    help="P_K inside the block-LU preconditioner: the factor of K_m, "
+                         "Chebyshev-accelerated Jacobi steps on K_m, or a multigrid V-cycle")
+    ap.add_argument("--p1", default="cholesky", choices=["cholesky", "amg"],
+                    help="P_1 inside the block-LU preconditioner: the factor of the grounded S_1, "
+                         "or a multigrid V-cycle (no factorisation)")
     ap.add_argument("--pk-steps", type=int, default=3, help="Chebyshev steps of --pk chebyshev")
     ap.add_argument("--no-record", action="store_true",
                     help="do not record activation times (and the electrode potentials of the thorax workloads)")
@@ -143,7 +146,10 @@ def main():
     prec = B.PREC_MIXED if args.precision == "mixed" else B.PREC_FP64
     t_setup = time.perf_counter()
     scheme = {"euler": B.SCHEME_EULER, "cn": B.SCHEME_CN, "strang": B.SCHEME_STRANG}[args.scheme]
-    solver = B.Solver(cfg, tol=args.tol, eps_h=args.eps, precision=prec, scheme=scheme)
+    inner_p1 = B.P1_AMG if args.p1 == "amg" else B.P1_CHOLESKY
+    inner_pk = {"cholesky": B.PK_CHOLESKY, "chebyshev": B.PK_CHEBYSHEV, "amg": B.PK_AMG}[args.pk]
+    solver = B.Solver(cfg, tol=args.tol, eps_h=args.eps, precision=prec, scheme=scheme,
+                      inner_p1=inner_p1, inner_pk=inner_pk)
     t_setup = time.perf_counter() - t_setup
     tune = None if args.no_tune else solver.autotune()
     if args.pk == "chebyshev":
@@ -205,7 +211,9 @@ def main():
                        {"cn": ", Crank-Nicolson", "strang": ", Strang splitting (Crank-Nicolson diffusion)",
                         "euler": ", semi-implicit"}[args.scheme] +
                        f" bidomain step, block-LU/monodomain PCG, {args.precision} preconditioner" +
-                       (f", Chebyshev P_K ({args.pk_steps} steps)" if args.pk == "chebyshev" else ""),
+                       (", multigrid P_1" if args.p1 == "amg" else "") +
+                       (f", Chebyshev P_K ({args.pk_steps} steps)" if args.pk == "chebyshev" else
+                        ", multigrid P_K" if args.pk == "amg" else ""),
                    "scheme": args.scheme, "pk": solver.pk(),
                    "n_nodes": solver.N, "n_heart": solver.NH, "dt_ms": cfg["dt"],
                    "tol": args.tol, "eps_h": args.eps, "precision": args.precision,

@@ -107,7 +107,23 @@ typedef struct {
     int ionic;         /* 0 = Mitchell-Schaeffer (one gate per vertex)       */
     int n_threads;     /* host threads for set-up; 0 = library default       */
     int scheme;        /* BIDO_SCHEME_*: time discretisation                 */
+    int inner_p1;      /* BIDO_P1_*: the inner solve P_1 ~ S_1 (Sec. 5.3)    */
+    int inner_pk;      /* BIDO_PK_*: the inner solve P_K ~ K_m (Sec. 5.3)    */
 } bido_params;
+
+/* Inner solves inside the block-LU preconditioner (Def. 2).  Sec. 5.3 lets
+ * P_1 and P_K be any preconditioners of the elliptic block S_1 and of the
+ * parabolic block K_m.  CHOLESKY: the multifrontal Cholesky factor in
+ * nested-dissection order with the hierarchical top (the default; the
+ * paper's choice).  AMG: a symmetric V-cycle of smoothed-aggregation
+ * algebraic multigrid (Chebyshev smoothing, dense coarsest solve), set up
+ * without any factorisation (linear in the non-zeros), FP64 in both
+ * precisions.  CHEBYSHEV (P_K only): Chebyshev-accelerated Jacobi steps on
+ * K_m (see bido_set_pk).  A block that is not CHOLESKY is never factored,
+ * so the factor-only calls (plans, autotuning, the allocation-free inner
+ * solve) refuse it with BIDO_ERR_STATE, and so does a fused batch.       */
+#define BIDO_P1_CHOLESKY 0
+#define BIDO_P1_AMG      1
 
 /* Time schemes.  EULER: the semi-implicit scheme of Sec. 3.2 (backward
  * Euler on the diffusion, reaction explicit).  CN: Crank-Nicolson on the
@@ -140,9 +156,12 @@ typedef struct {
     int64_t nnz_lambda;          /* stored entries of Lambda                  */
     int64_t bytes_lambda;        /* bytes read by one Lambda product          */
     int64_t bytes_p1, bytes_pk;  /* bytes of the P_1 / P_K factors as stored
-                                    (the active precision)                    */
+                                    (the active precision); for a multigrid
+                                    block, the bytes one V-cycle reads and
+                                    writes                                   */
     int64_t dense_bytes_p1, dense_bytes_pk; /* same factors uncompressed      */
-    int levels_p1, levels_pk;    /* nested-dissection tree heights           */
+    int levels_p1, levels_pk;    /* nested-dissection tree heights (multigrid
+                                    levels for a multigrid block)           */
     int64_t lowrank_blocks;      /* low-rank blocks (rank > 0) stored in the
                                     hierarchical tops of P_1 and P_K        */
     double setup_seconds;        /* host set-up time of bido_create           */
@@ -276,6 +295,7 @@ bido_status bido_inner_solve_noalloc(bido_ctx* ctx, int which, const double* b, 
  * over the union.                                                        */
 #define BIDO_PK_CHOLESKY  0
 #define BIDO_PK_CHEBYSHEV 1
+#define BIDO_PK_AMG       2
 #define BIDO_PK_MAX_STEPS 64
 #define BIDO_PK_LANCZOS_STEPS 20
 bido_status bido_set_pk(bido_ctx* ctx, int kind, int steps, double lo, double hi);

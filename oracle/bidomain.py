@@ -283,3 +283,58 @@ def _lanczos_kappa(alphas, betas):
 def rel_err(a, b):
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def sampled_residual(cfg, verts, Vn, hn, n, U1, V1):
+    """Rows of Lambda X - Y at sampled vertices, for a full-size check that
+    needs no global assembly: X = (U1, V1) is a computed solution of the
+    semi-implicit step from (V^n, h^n) (U1 in global order, Vn, hn, V1 in
+    heart-local order).  Each sampled row is assembled from the elements
+    that hold its vertex (Sec. 3.1), with Y from Step 1 (Sec. 3.2):
+
+      u row of g:  (S_1 U1)_g + (S_i V1)_g                  (0 in Y)
+      v row of g:  (S_i (U1 + V1))_g + gamma m_g V1_g - m_g (gamma V^n_g
+                   - chi (I_ion - I_st))_g
+
+    Returns (r_u, r_v, y_v): the residual rows at the sampled vertices and
+    the rows of Y_2 at the heart ones (r_v, y_v).  Only the semi-implicit
+    scheme.
+    """
+    xyz, el = cfg["xyz"], cfg["elems"].astype(np.int64)
+    N = len(xyz)
+    hn_ids = fem.heart_nodes(cfg)
+    loc = -np.ones(N, dtype=np.int64)
+    loc[hn_ids] = np.arange(len(hn_ids))
+    verts = np.asarray(verts, dtype=np.int64)
+    want = np.zeros(N, dtype=bool)
+    want[verts] = True
+    touch = np.nonzero(want[el].any(axis=1))[0]
+    sub = el[touch]
+    vol, G = fem.element_geometry(xyz, sub)
+    sig_i, _, sig_1, _, _ = fem.tensors(cfg, touch)
+    heart_e = cfg["region"][touch] == fem.REGION_HEART
+    K1 = vol[:, None, None] * np.einsum("eai,eij,ebj->eab", G, sig_1, G)
+    Ki = vol[:, None, None] * np.einsum("eai,eij,ebj->eab", G, sig_i, G)
+    k = sub.shape[1]
+    vh = np.where(loc[sub] >= 0, V1[np.maximum(loc[sub], 0)], 0.0)     # V1 at the element's vertices
+    u_e = U1[sub]
+    su = np.einsum("eab,eb->ea", K1, u_e) + np.where(heart_e[:, None], np.einsum("eab,eb->ea", Ki, vh), 0.0)
+    sv = np.where(heart_e[:, None], np.einsum("eab,eb->ea", Ki, u_e + vh), 0.0)
+    mass = np.where(heart_e[:, None], np.repeat(vol[:, None] / k, k, axis=1), 0.0)
+    ru = np.zeros(N)
+    rv = np.zeros(N)
+    mh = np.zeros(N)
+    np.add.at(ru, sub.ravel(), su.ravel())
+    np.add.at(rv, sub.ravel(), sv.ravel())
+    np.add.at(mh, sub.ravel(), mass.ravel())
+    gamma = cfg["chi"] * cfg["cm"] / cfg["dt"]
+    n0 = int(round(cfg["stim_t0"] / cfg["dt"]))
+    n1 = int(round(cfg["stim_t1"] / cfg["dt"]))
+    amp = cfg["stim_amp"] if n0 <= n < n1 else 0.0
+    ist = np.where(cfg["stim_mask"].astype(bool)[hn_ids], amp, 0.0)
+    src = ionic.i_ion(Vn, hn, cfg["cm"]) - ist                        # heart-local
+    hv = verts[loc[verts] >= 0]
+    lv = loc[hv]
+    r_v = rv[hv] + gamma * mh[hv] * V1[lv] - mh[hv] * (gamma * Vn[lv] - cfg["chi"] * src[lv])
+    y_v = mh[hv] * (gamma * Vn[lv] - cfg["chi"] * src[lv])
+    return ru[verts], r_v, y_v

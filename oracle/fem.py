@@ -33,19 +33,22 @@ def element_geometry(xyz, elems):
     return vol, G
 
 
-def tensors(cfg):
-    """Per-element tensors (sigma_i, sigma_e, sigma_1, sigma_e_bar, sigma_m).
+def tensors(cfg, elements=None):
+    """Per-element tensors (sigma_i, sigma_e, sigma_1, sigma_e_bar, sigma_m),
+    for every element or for the listed `elements` only.
 
     sigma_i, sigma_e and sigma_m are only meaningful on heart elements; on
     torso elements they are returned as zero.
     """
-    E = len(cfg["elems"])
+    sel = slice(None) if elements is None else elements
+    region = cfg["region"][sel]
+    E = len(region)
     d = cfg["dim"]
-    heart = cfg["region"] == REGION_HEART
-    Q = cfg["fibre"]
+    heart = region == REGION_HEART
+    Q = cfg["fibre"][sel]
     si = np.einsum("eij,j,ekj->eik", Q, cfg["sigma_i"], Q)
     se = np.einsum("eij,j,ekj->eik", Q, cfg["sigma_e"], Q)
-    kt = cfg["region_sigma"][cfg["region"].astype(np.int64)]
+    kt = cfg["region_sigma"][region.astype(np.int64)]
     iso = kt[:, None, None] * np.eye(d)[None]
     sm = np.linalg.inv(np.linalg.inv(si) + np.linalg.inv(se))
     zero = np.zeros((E, d, d))

@@ -20,7 +20,8 @@ ERRORS = {-1: "BIDO_ERR_ARG", -2: "BIDO_ERR_DEVICE", -3: "BIDO_ERR_NOT_SPD",
 PREC_FP64, PREC_MIXED = 0, 1
 PRECOND_PLAIN, PRECOND_LEARNED, PRECOND_LEARNED_ADDITIVE = 0, 1, 2
 SCHEME_EULER, SCHEME_CN, SCHEME_STRANG = 0, 1, 2
-PK_CHOLESKY, PK_CHEBYSHEV = 0, 1
+PK_CHOLESKY, PK_CHEBYSHEV, PK_AMG = 0, 1, 2
+P1_CHOLESKY, P1_AMG = 0, 1
 PK_MAX_STEPS, PK_LANCZOS_STEPS = 64, 20
 LEARN_STENCIL, LEARN_ADDITIVE = 0, 1
 MAT_S1, MAT_SI, MAT_SM, MAT_LAMBDA, MAT_GNN_AGG, MAT_KM = 0, 1, 2, 3, 4, 5
@@ -52,7 +53,7 @@ class Params(ctypes.Structure):
                 ("eps_h", ctypes.c_double), ("eta", ctypes.c_double), ("tol", ctypes.c_double),
                 ("leaf", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("precond", ctypes.c_int), ("ionic", ctypes.c_int), ("n_threads", ctypes.c_int),
-                ("scheme", ctypes.c_int)]
+                ("scheme", ctypes.c_int), ("inner_p1", ctypes.c_int), ("inner_pk", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -226,6 +227,14 @@ ABI = {
                                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                              _c_i64_p, _c_i64_p, _c_i64_p]),
     "bido_host_set_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Plan)]),
+    "bido_host_amg_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _c_i64_p,
+                                          _c_double_p, _c_double_p, ctypes.POINTER(ctypes.c_int)]),
+    "bido_host_amg_level": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_i64_p,
+                                           _c_i64_p, ctypes.POINTER(_c_i64_p), ctypes.POINTER(_c_i32_p),
+                                           ctypes.POINTER(_c_double_p)]),
+    "bido_host_amg_smoother": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                              ctypes.POINTER(_c_double_p), _c_double_p, _c_double_p]),
+    "bido_host_amg_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p, _c_double_p]),
     "bido_host_merge": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_void_p)]),
     "bido_host_factor_top": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _c_i64_p,
@@ -715,6 +724,53 @@ class HostSetup:
                                          ctypes.byref(nsp)), host=True)
         return dict(hc=hc.value, n_sub=ns.value, n_levels=nl.value, n_fwd_items=nf.value,
                     n_bwd_items=nb.value, n_bwd_split=nsp.value)
+
+    def amg_info(self, which):
+        lv, nc, oc, sec, st = ctypes.c_int(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        _check(lib.bido_host_amg_info(self.h, which, ctypes.byref(lv), ctypes.byref(nc), ctypes.byref(oc),
+                                      ctypes.byref(sec), ctypes.byref(st)), host=True)
+        return dict(levels=lv.value, n_coarse=nc.value, op_complexity=oc.value, seconds=sec.value,
+                    smooth_steps=st.value)
+
+    def amg_level(self, which, level):
+        """dict(A=scipy CSR, P=scipy CSR or None, dinv, lo, hi) of one level (copies)."""
+        import scipy.sparse as sp
+        info = self.amg_info(which)
+        out = {}
+        for what, key in ((0, "A"), (1, "P")):
+            if what == 1 and level + 1 == info["levels"]:
+                out[key] = None
+                continue
+            n, nnz = ctypes.c_int64(), ctypes.c_int64()
+            p, c, v = _c_i64_p(), _c_i32_p(), _c_double_p()
+            _check(lib.bido_host_amg_level(self.h, which, level, what, ctypes.byref(n), ctypes.byref(nnz),
+                                           ctypes.byref(p), ctypes.byref(c), ctypes.byref(v)), host=True)
+            ptr = np.ctypeslib.as_array(p, shape=(n.value + 1,)).copy()
+            col = np.ctypeslib.as_array(c, shape=(max(nnz.value, 1),))[:nnz.value].copy()
+            val = np.ctypeslib.as_array(v, shape=(max(nnz.value, 1),))[:nnz.value].copy()
+            ncols = n.value if what == 0 else self.amg_level_size(which, level + 1)
+            out[key] = sp.csr_matrix((val, col, ptr), shape=(n.value, ncols))
+        d = _c_double_p()
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        _check(lib.bido_host_amg_smoother(self.h, which, level, ctypes.byref(d), ctypes.byref(lo),
+                                          ctypes.byref(hi)), host=True)
+        out["dinv"] = np.ctypeslib.as_array(d, shape=(out["A"].shape[0],)).copy()
+        out["lo"], out["hi"] = lo.value, hi.value
+        return out
+
+    def amg_level_size(self, which, level):
+        n, nnz = ctypes.c_int64(), ctypes.c_int64()
+        p, c, v = _c_i64_p(), _c_i32_p(), _c_double_p()
+        _check(lib.bido_host_amg_level(self.h, which, level, 0, ctypes.byref(n), ctypes.byref(nnz),
+                                       ctypes.byref(p), ctypes.byref(c), ctypes.byref(v)), host=True)
+        return n.value
+
+    def amg_apply(self, which, b):
+        b = _arr(b, np.float64)
+        x = np.zeros_like(b)
+        _check(lib.bido_host_amg_apply(self.h, which, b.ctypes.data_as(_c_double_p),
+                                       x.ctypes.data_as(_c_double_p)), host=True)
+        return x
 
     def set_plan(self, which, **kw):
         """Plan options of the later factor_emulate / factor_plan / factor_top queries."""

@@ -11,8 +11,8 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libbido.so")
 
 HOST_SOURCES = ["assemble.cpp", "ndtree.cpp", "dense.cpp", "mfchol.cpp",
-                "compress.cpp", "plan.cpp", "setup.cpp", "host_api.cpp", "chebyshev.cpp", "record.cpp"]
-HIP_SOURCES = ["kernels.hip", "gnn.hip", "batch.hip", "noalloc.hip", "api.cpp"]
+                "compress.cpp", "plan.cpp", "setup.cpp", "host_api.cpp", "chebyshev.cpp", "record.cpp", "amg.cpp"]
+HIP_SOURCES = ["kernels.hip", "gnn.hip", "batch.hip", "noalloc.hip", "amg.hip", "api.cpp"]
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")

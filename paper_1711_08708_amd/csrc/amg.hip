@@ -1,0 +1,233 @@
+// HIP kernels of the multigrid V-cycle (the alternative inner solves P_1,
+// P_K of the block-LU preconditioner; host side in amg.cpp, driver in
+// api.cpp).  Every product is a CSR row product by a group of G lanes with
+// RU rows in flight (the row helper of the Lambda product), with the matrix
+// values in FP64 or, in mixed precision, FP32 (FP64 accumulation, FP64
+// vectors): the cycle is bound by the bytes of its level matrices.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "launch.h"
+
+namespace bido {
+
+namespace {
+
+constexpr int BLOCK = 256;
+constexpr int RU = 4;
+
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+// s[u] = sum_j A[row_u, j] * f(j) for RU rows, f(j) = x[j] (or x[j] * w[j]
+// when w is given: the scaled input of a fused smoother step); entries
+// past a row's end reread entry 0 and are dropped by a select.
+template <int G, typename T>
+__device__ __forceinline__ void rows_dot(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                         const T* __restrict__ val, const double* __restrict__ x,
+                                         const double* __restrict__ w, const int64_t (&row)[RU],
+                                         const bool (&ok)[RU], int lane, double (&s)[RU]) {
+    int64_t pb[RU], pe[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+        const int64_t rr = ok[u] ? row[u] : row[0];
+        pb[u] = ptr[rr];
+        pe[u] = ptr[rr + 1];
+        s[u] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t q = pb[u] + lane + k * G;
+            const bool in = q < pe[u];
+            const int64_t qc = in ? q : 0;
+            const int32_t c = col[qc];
+            double xv = x[c];
+            if (w) xv *= w[c];
+            const double v = (double)val[qc] * xv;
+            s[u] += in ? v : 0.0;
+        }
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+        for (int64_t q = pb[u] + lane + 2 * G; q < pe[u]; q += G) {
+            const int32_t c = col[q];
+            double xv = x[c];
+            if (w) xv *= w[c];
+            s[u] += (double)val[q] * xv;
+        }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) s[u] = group_sum<G>(s[u]);
+}
+
+// y = b + sign * A x  (b may be null)
+template <int G, typename T>
+__global__ __launch_bounds__(BLOCK) void k_amg_spmv(int64_t n, const int64_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                    const double* __restrict__ x, const double* __restrict__ b,
+                                                    double sign, double* __restrict__ y) {
+    const int lane = threadIdx.x % G;
+    const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
+    const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
+    for (int64_t rb = gid; rb < n; rb += RU * ngroups) {
+        int64_t row[RU];
+        bool ok[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            row[u] = rb + u * ngroups;
+            ok[u] = row[u] < n;
+        }
+        double s[RU];
+        rows_dot<G, T>(ptr, col, val, x, nullptr, row, ok, lane, s);
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+                if (ok[u]) y[row[u]] = (b ? b[row[u]] : 0.0) + sign * s[u];
+        }
+    }
+}
+
+// The first two Chebyshev smoothing steps from z = 0 in one pass:
+// d0 = a0 D^-1 b (formed on the fly from b and D^-1 at the gathered
+// columns), r1 = b - A d0, d1 = c1 d0 + c2 D^-1 r1, z = d0 + d1; r1 and d1
+// are kept when more steps follow (write_rd).
+template <int G, typename T>
+__global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const T* __restrict__ val, const double* __restrict__ dinv,
+                                                       const double* __restrict__ b, double a0, double c1, double c2,
+                                                       double* __restrict__ z, double* __restrict__ r1,
+                                                       double* __restrict__ d0o, double* __restrict__ d1o,
+                                                       int write_rd) {
+    const int lane = threadIdx.x % G;
+    const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
+    const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
+    for (int64_t rb = gid; rb < n; rb += RU * ngroups) {
+        int64_t row[RU];
+        bool ok[RU];
+        double bv[RU], di[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            row[u] = rb + u * ngroups;
+            ok[u] = row[u] < n;
+            const int64_t i = ok[u] ? row[u] : rb;
+            bv[u] = b[i];
+            di[u] = dinv[i];
+        }
+        double s[RU];
+        rows_dot<G, T>(ptr, col, val, b, dinv, row, ok, lane, s);   // (A D^-1 b)_i
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (!ok[u]) continue;
+                const double d0 = a0 * di[u] * bv[u];
+                const double r = bv[u] - a0 * s[u];
+                const double d1 = c1 * d0 + c2 * di[u] * r;
+                z[row[u]] = d0 + d1;
+                if (write_rd) {
+                    r1[row[u]] = r;
+                    d0o[row[u]] = d0;
+                    d1o[row[u]] = d1;
+                }
+            }
+        }
+    }
+}
+
+// One more Chebyshev step: r -= A dp, dn = c1 dp + c2 D^-1 r, z += dn.
+template <int G, typename T>
+__global__ __launch_bounds__(BLOCK) void k_amg_cheb(int64_t n, const int64_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                    const double* __restrict__ dinv, double* r,
+                                                    const double* __restrict__ dp, double* __restrict__ dn,
+                                                    double* __restrict__ z, double c1, double c2) {
+    const int lane = threadIdx.x % G;
+    const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
+    const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
+    for (int64_t rb = gid; rb < n; rb += RU * ngroups) {
+        int64_t row[RU];
+        bool ok[RU];
+        double rv[RU], dv[RU], di[RU], zv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            row[u] = rb + u * ngroups;
+            ok[u] = row[u] < n;
+            const int64_t i = ok[u] ? row[u] : rb;
+            rv[u] = r[i];
+            dv[u] = dp[i];
+            di[u] = dinv[i];
+            zv[u] = z[i];
+        }
+        double s[RU];
+        rows_dot<G, T>(ptr, col, val, dp, nullptr, row, ok, lane, s);
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (!ok[u]) continue;
+                const double rn = rv[u] - s[u];
+                const double d = c1 * dv[u] + c2 * di[u] * rn;
+                r[row[u]] = rn;
+                dn[row[u]] = d;
+                z[row[u]] = zv[u] + d;
+            }
+        }
+    }
+}
+
+unsigned grid_rows(int64_t n, int G) {
+    const int64_t groups = (n + RU - 1) / RU;
+    const int64_t blocks = (groups * G + BLOCK - 1) / BLOCK;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, 8192));
+}
+
+}  // namespace
+
+#define BIDO_G_SWITCH(G, ...)                                    \
+    switch (G) {                                                 \
+        case 4: { constexpr int GG = 4; __VA_ARGS__; } break;    \
+        case 8: { constexpr int GG = 8; __VA_ARGS__; } break;    \
+        case 16: { constexpr int GG = 16; __VA_ARGS__; } break;  \
+        default: { constexpr int GG = 32; __VA_ARGS__; } break;  \
+    }
+
+template <typename T>
+void launch_amg_spmv(hipStream_t s, const AmgMat<T>& A, const double* x, const double* b, double sign, double* y) {
+    if (A.n <= 0) return;
+    BIDO_G_SWITCH(A.group, k_amg_spmv<GG, T><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, b,
+                                                                                      sign, y))
+}
+
+template <typename T>
+void launch_amg_smooth2(hipStream_t s, const AmgMat<T>& A, const double* dinv, const double* b, double a0, double c1,
+                        double c2, double* z, double* r1, double* d0, double* d1, bool write_rd) {
+    if (A.n <= 0) return;
+    BIDO_G_SWITCH(A.group, k_amg_smooth2<GG, T><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
+                               A.n, A.ptr, A.col, A.val, dinv, b, a0, c1, c2, z, r1, d0, d1, write_rd ? 1 : 0))
+}
+
+template <typename T>
+void launch_amg_cheb(hipStream_t s, const AmgMat<T>& A, const double* dinv, double* r, const double* dp, double* dn,
+                     double* z, double c1, double c2) {
+    if (A.n <= 0) return;
+    BIDO_G_SWITCH(A.group, k_amg_cheb<GG, T><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, dinv, r,
+                                                                                      dp, dn, z, c1, c2))
+}
+
+#undef BIDO_G_SWITCH
+
+#define BIDO_INST(T)                                                                                              \
+    template void launch_amg_spmv<T>(hipStream_t, const AmgMat<T>&, const double*, const double*, double, double*); \
+    template void launch_amg_smooth2<T>(hipStream_t, const AmgMat<T>&, const double*, const double*, double,       \
+                                        double, double, double*, double*, double*, double*, bool);                 \
+    template void launch_amg_cheb<T>(hipStream_t, const AmgMat<T>&, const double*, double*, const double*,         \
+                                     double*, double*, double, double);
+BIDO_INST(double)
+BIDO_INST(float)
+#undef BIDO_INST
+
+}  // namespace bido

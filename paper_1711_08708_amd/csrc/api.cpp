@@ -63,11 +63,11 @@ int pow2_at_least(int n, int cap) {
 // Kernel classes of the optional per-launch profiler.
 enum KClass { K_SPMV_LAMBDA = 0, K_PCG_UPDATE, K_COMBINE_DOT, K_P_UPDATE, K_TRI_FWD_SUB,
               K_TRI_FWD_LVL, K_TRI_BWD_SUB, K_TRI_BWD_LVL, K_TRI_TOP, K_SPMV_CSR, K_IONIC, K_GNN, K_MISC,
-              K_CHEB, K_NCLASS };
+              K_CHEB, K_AMG_SMOOTH, K_AMG_SPMV, K_AMG_COARSE, K_NCLASS };
 const char* const kclass_name[K_NCLASS] = {"spmv_lambda", "pcg_update", "combine_dot", "p_update",
                                            "tri_fwd_sub", "tri_fwd_lvl", "tri_bwd_sub", "tri_bwd_lvl",
                                            "tri_top", "spmv_csr", "ionic_rhs", "gnn_infer", "misc",
-                                           "pk_chebyshev"};
+                                           "pk_chebyshev", "amg_smooth", "amg_spmv", "amg_coarse"};
 
 // Per-launch HIP-event timing with the algorithmic bytes of each launch.
 struct Profiler {
@@ -273,6 +273,123 @@ bido_status build_factor_dev(const Factor& f, bool want32, FactorDev& fd, int n_
 // Work vectors of a factor's sweeps start as NaN (all-ones bits), so that a
 // read before a write shows up in every result; entry 0 of the update
 // workspace is the 0.0 the sweeps read for a missing child update.
+// Device copy of a multigrid hierarchy (Amg): per level the matrix A, the
+// prolongation P and R = P^T (FP64 values, and FP32 copies of the values for
+// mixed precision), D^-1, the Chebyshev coefficients of the smoother and the
+// work vectors of one V-cycle.
+struct AmgDev {
+    struct Lev {
+        int64_t n = 0;
+        CsrDev A, P, R;
+        float *A32 = nullptr, *P32 = nullptr, *R32 = nullptr;
+        int gA = 4, gP = 4, gR = 4;        // lanes per row of the three products
+        double* dinv = nullptr;
+        ChebCoef cf;
+        double *b = nullptr, *out = nullptr;   // input and output of this level (levels >= 1)
+        double *x = nullptr, *r = nullptr, *d0 = nullptr, *d1 = nullptr, *xp = nullptr, *t = nullptr;
+        int64_t nnz_A = 0, nnz_P = 0, nnz_R = 0;
+        template <typename T>
+        AmgMat<T> mat(const CsrDev& m, const float* v32, int g) const {
+            AmgMat<T> o;
+            o.n = m.n;
+            o.nnz = m.nnz;
+            o.ptr = m.ptr;
+            o.col = m.col;
+            if constexpr (sizeof(T) == 4) o.val = v32;
+            else o.val = m.val;
+            o.group = g;
+            return o;
+        }
+    };
+    std::vector<Lev> lv;
+    double* cinv = nullptr;
+    int64_t nc = 0;
+    int steps = 2;
+    double op_complexity = 1.0, setup_seconds = 0.0;
+    bool on() const { return !lv.empty(); }
+    // algorithmic bytes of one V-cycle with value bytes w (8 or 4)
+    double bytes(int w) const {
+        double b = 8.0 * (double)nc * nc + 16.0 * nc;
+        for (size_t l = 0; l + 1 < lv.size(); ++l) {
+            const Lev& L = lv[l];
+            auto mb = [&](int64_t nnz, int64_t rows) { return (4.0 + w) * nnz + 8.0 * (rows + 1); };
+            const double A = mb(L.nnz_A, L.n), vec = 8.0 * L.n;
+            const double nc_l = 8.0 * lv[l + 1].n;
+            // two smoothings (fused first two steps: A, b and D^-1 gathered, z, r1, d0, d1
+            // written; each further step A + 7 vectors), two residuals, restriction,
+            // prolongation, the final sum
+            const double sm = A + 6.0 * vec + (steps - 2) * (A + 7.0 * vec);
+            b += 2.0 * sm + 2.0 * (A + 3.0 * vec) + mb(L.nnz_R, lv[l + 1].n) + vec + nc_l +
+                 mb(L.nnz_P, L.n) + nc_l + 2.0 * vec + 3.0 * vec;
+        }
+        return b;
+    }
+    void release() {
+        for (auto& L : lv) {
+            for (CsrDev* m : {&L.A, &L.P, &L.R}) {
+                hipFree(m->ptr); hipFree(m->col); hipFree(m->val);
+            }
+            for (float* v : {L.A32, L.P32, L.R32}) hipFree(v);
+            for (double* v : {L.dinv, L.b, L.out, L.x, L.r, L.d0, L.d1, L.xp, L.t}) hipFree(v);
+        }
+        lv.clear();
+        hipFree(cinv);
+        cinv = nullptr;
+        nc = 0;
+    }
+};
+
+// lanes per row for a CSR product: enough lanes for the average row
+int group_for(const Csr& a) {
+    const double avg = a.n > 0 ? (double)a.nnz() / (double)a.n : 0.0;
+    return avg <= 8 ? 4 : avg <= 20 ? 8 : avg <= 48 ? 16 : 32;
+}
+
+bido_status upload_amg(const Amg& M, AmgDev& d) {
+    d.release();
+    d.steps = M.smooth_steps;
+    d.op_complexity = M.op_complexity;
+    d.setup_seconds = M.setup_seconds;
+    const size_t L = M.levels.size();
+    d.lv.resize(L);
+    for (size_t l = 0; l < L; ++l) {
+        const AmgLevel& h = M.levels[l];
+        AmgDev::Lev& v = d.lv[l];
+        v.n = h.A.n;
+        const bool last = l + 1 == L;
+        const int64_t n = std::max<int64_t>(v.n, 1);
+        if (l > 0) {
+            HIP_OK(hipMalloc((void**)&v.b, n * sizeof(double)));
+            HIP_OK(hipMalloc((void**)&v.out, n * sizeof(double)));
+        }
+        if (last) break;
+        bido_status e;
+        if ((e = CsrHostView::up(h.A, v.A))) return e;
+        if ((e = CsrHostView::up(h.P, v.P))) return e;
+        if ((e = CsrHostView::up(h.R, v.R))) return e;
+        auto up32 = [&](const Csr& m, float** dst) -> hipError_t {
+            std::vector<float> f(m.val.begin(), m.val.end());
+            if (f.empty()) f.push_back(0.0f);
+            return upload(dst, f.data(), f.size());
+        };
+        HIP_OK(up32(h.A, &v.A32));
+        HIP_OK(up32(h.P, &v.P32));
+        HIP_OK(up32(h.R, &v.R32));
+        v.gA = group_for(h.A);
+        v.gP = group_for(h.P);
+        v.gR = group_for(h.R);
+        v.nnz_A = h.A.nnz();
+        v.nnz_P = h.P.nnz();
+        v.nnz_R = h.R.nnz();
+        HIP_OK(upload(&v.dinv, h.dinv.data(), h.dinv.size()));
+        v.cf = chebyshev_coefficients(h.lo, h.hi, std::max(2, M.smooth_steps));
+        for (double** b : {&v.x, &v.r, &v.d0, &v.d1, &v.xp, &v.t}) HIP_OK(hipMalloc((void**)b, n * sizeof(double)));
+    }
+    d.nc = M.levels.back().A.n;
+    HIP_OK(upload(&d.cinv, M.coarse_inv.data(), M.coarse_inv.size()));
+    return BIDO_OK;
+}
+
 hipError_t poison_workspace(const FactorDev& f) {
     hipError_t e = hipMemset(f.ytmp, 0xFF, std::max<int64_t>(f.n, 1) * sizeof(double));
     if (e == hipSuccess) e = hipMemset(f.upd, 0xFF, std::max<int64_t>(f.upd_size, 1) * sizeof(double));
@@ -362,6 +479,8 @@ struct bido_ctx {
     Profiler prof;
     GnnState gnn;
     FactorDev pk_learned;             // factor of K_m + C (learned stencil)
+    AmgDev amg1, amgk;                // multigrid P_1 / P_K (inner_p1 / inner_pk = AMG)
+    AmgDev amgk_learned;              // multigrid of K_m + C (learned stencil with a multigrid P_K)
     int precond = BIDO_PRECOND_PLAIN;
     int fallbacks = 0;
     // P_K ~ K_m: the factor `pk`, or Chebyshev-accelerated Jacobi on K_m
@@ -399,6 +518,9 @@ struct bido_ctx {
         p1.release();
         pk.release();
         pk_learned.release();
+        amg1.release();
+        amgk.release();
+        amgk_learned.release();
         gnn.release();
         rec.release();
         CsrHostView::release(lam);
@@ -504,11 +626,78 @@ void inner_solve(C* c, const FactorDev& f, const double* in, double* out) {
 
 // Z2 = P_K^-1 t: the factor of K_m, or `cheb_steps` steps of the Chebyshev
 // acceleration of the Jacobi iteration on K_m (always FP64; z_0 = 0).
+// z = S b for level L of a multigrid hierarchy: the Chebyshev steps of the
+// smoother from z = 0 (the recurrence of the Chebyshev P_K on the level's
+// interval of D^-1 A; the first two steps in one fused pass).
+template <typename T, typename C>
+void amg_smooth(C* c, const AmgDev& M, const AmgDev::Lev& L, const double* b, double* z) {
+    hipStream_t s = c->stream;
+    const int64_t n = L.n;
+    const AmgMat<T> A = L.mat<T>(L.A, L.A32, L.gA);
+    const double Ab = (4.0 + sizeof(T)) * L.nnz_A + 8.0 * (n + 1);
+    if (M.steps < 2) {
+        PROF(c, K_AMG_SMOOTH, 32.0 * n, launch_cheb_init(s, n, b, L.dinv, L.cf.inv_theta, L.d0, z));
+        return;
+    }
+    PROF(c, K_AMG_SMOOTH, Ab + 8.0 * n * (M.steps > 2 ? 6 : 3),
+         launch_amg_smooth2<T>(s, A, L.dinv, b, L.cf.inv_theta, L.cf.c1[0], L.cf.c2[0], z, L.r, L.d0, L.d1,
+                               M.steps > 2));
+    double* d[2] = {L.d0, L.d1};
+    for (int k = 2; k < M.steps; ++k)
+        PROF(c, K_AMG_SMOOTH, Ab + 56.0 * n,
+             launch_amg_cheb<T>(s, A, L.dinv, L.r, d[(k - 1) & 1], d[k & 1], z, L.cf.c1[k - 1], L.cf.c2[k - 1]));
+}
+
+// out = B b: the symmetric V-cycle from level l (pre-smoothing, residual,
+// restriction, the coarser cycle, prolongation, residual, post-smoothing;
+// the coarsest level by its dense inverse).
+template <typename T, typename C>
+void amg_vcycle_t(C* c, const AmgDev& M, size_t l, const double* b, double* out) {
+    hipStream_t s = c->stream;
+    const AmgDev::Lev& L = M.lv[l];
+    if (l + 1 == M.lv.size()) {
+        PROF(c, K_AMG_COARSE, 8.0 * (double)M.nc * M.nc + 16.0 * M.nc, launch_dense_gemv(s, M.nc, M.cinv, b, out));
+        return;
+    }
+    const AmgDev::Lev& Lc = M.lv[l + 1];
+    const double vec = 8.0 * L.n, w = 4.0 + sizeof(T);
+    const AmgMat<T> A = L.mat<T>(L.A, L.A32, L.gA);
+    const AmgMat<T> P = L.mat<T>(L.P, L.P32, L.gP);
+    const AmgMat<T> R = L.mat<T>(L.R, L.R32, L.gR);
+    const double Ab = w * L.nnz_A + vec, Pb = w * L.nnz_P + vec, Rb = w * L.nnz_R + 8.0 * Lc.n;
+    amg_smooth<T>(c, M, L, b, L.x);
+    PROF(c, K_AMG_SPMV, Ab + 3 * vec, launch_amg_spmv<T>(s, A, L.x, b, -1.0, L.r));          // r = b - A x
+    PROF(c, K_AMG_SPMV, Rb + vec + 8.0 * Lc.n, launch_amg_spmv<T>(s, R, L.r, nullptr, 1.0, Lc.b));
+    amg_vcycle_t<T>(c, M, l + 1, Lc.b, Lc.out);
+    PROF(c, K_AMG_SPMV, Pb + 8.0 * Lc.n + 2 * vec, launch_amg_spmv<T>(s, P, Lc.out, L.x, 1.0, L.xp));  // xp = x + P e
+    PROF(c, K_AMG_SPMV, Ab + 3 * vec, launch_amg_spmv<T>(s, A, L.xp, b, -1.0, L.r));         // r = b - A xp
+    amg_smooth<T>(c, M, L, L.r, L.t);
+    PROF(c, K_AMG_SMOOTH, 3 * vec, launch_add2(s, L.n, L.xp, L.t, out));
+}
+
+// The cycle with FP32 level values in mixed precision, FP64 otherwise.
+template <typename C>
+void amg_vcycle(C* c, const AmgDev& M, size_t l, const double* b, double* out, bool fp64 = false) {
+    if (c->precision == BIDO_PREC_MIXED && !fp64) amg_vcycle_t<float>(c, M, l, b, out);
+    else amg_vcycle_t<double>(c, M, l, b, out);
+}
+
+// Z1 = P_1^-1 r1: the factor's sweeps, or the multigrid V-cycle.
+template <typename C>
+void p1_solve(C* c, const double* in, double* out) {
+    if (c->amg1.on()) amg_vcycle(c, c->amg1, 0, in, out);
+    else inner_solve(c, c->p1, in, out);
+}
+
 void pk_solve(bido_ctx* c, const double* in, double* out, double* ch_r, double* ch_d0, double* ch_d1);
 void pk_solve(bido_ctx* c, const double* in, double* out) {
     pk_solve(c, in, out, c->ch_r, c->ch_d[0], c->ch_d[1]);
 }
 void pk_solve(bido_ctx* c, const double* in, double* out, double* ch_r, double* ch_d0, double* ch_d1) {
+    if (c->pk_kind == BIDO_PK_AMG) {
+        amg_vcycle(c, c->amgk, 0, in, out);
+        return;
+    }
     if (c->pk_kind != BIDO_PK_CHEBYSHEV) {
         inner_solve(c, c->pk, in, out);
         return;
@@ -561,12 +750,13 @@ void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old,
     const int64_t N = c->N, NH = c->NH;
     GnnState& g = c->gnn;
     debug_check(c, "r", r, c->n2);
-    inner_solve(c, c->p1, r, c->tA);                                 // Z1 = P1^-1 R1
+    p1_solve(c, r, c->tA);                                           // Z1 = P1^-1 R1
     debug_check(c, "Z1", c->tA, N);
     PROF(c, K_SPMV_CSR, csr_bytes(c->avu, c->NH) + 8.0 * c->NH,
          launch_spmv_csr(s, c->avu, c->spmv_group, c->tA, r + N, c->tB));  // R2 - S_i Pi Z1
     debug_check(c, "t", c->tB, c->NH);
-    if (stencil) inner_solve(c, c->pk_learned, c->tB, z + N);        // Z2 = PK^-1 (...)
+    if (stencil && c->amgk_learned.on()) amg_vcycle(c, c->amgk_learned, 0, c->tB, z + N);
+    else if (stencil) inner_solve(c, c->pk_learned, c->tB, z + N);   // Z2 = PK^-1 (...)
     else pk_solve(c, c->tB, z + N);
     debug_check(c, "Z2", z + N, c->NH);
     if (g.collecting && g.n_samples + g.n_pending < g.max_samples && g.n_pending < g.max_pending) {
@@ -589,7 +779,7 @@ void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old,
     PROF(c, K_SPMV_CSR, csr_bytes(c->auv, c->NH),
          launch_spmv_csr(s, c->auv, c->spmv_group, z + N, nullptr, c->tC));   // Pi^T S_i Z2
     debug_check(c, "PiSZ2", c->tC, N);
-    inner_solve(c, c->p1, c->tC, c->tD);                             // P1^-1 Pi^T S_i Z2
+    p1_solve(c, c->tC, c->tD);                                       // P1^-1 Pi^T S_i Z2
     debug_check(c, "W", c->tD, N);
     PROF(c, K_COMBINE_DOT, 8.0 * (3 * N + c->NH + c->n2 * (r_old ? 2 : 1)),
          c->nb_rz = launch_combine_dot(s, N, c->n2, z, c->tA, c->tD, r, r_old, c->sc));
@@ -702,7 +892,8 @@ bool seq_graph(bido_ctx* c, PcgRun& ps, int variant) {
     const bool on = c->graph_mode > 0 || (c->graph_mode < 0 && c->batched);
     if (!on || c->prof.on || c->gnn.collecting || ps.learned || !c->stream || debug_on()) return false;
     const void* key[4] = {(const void*)(intptr_t)(c->precision + 1), (const void*)(intptr_t)(ps.stencil ? 2 : 1),
-                          c->pk_learned.nodes, ps.r_old};
+                          c->amgk_learned.on() ? (const void*)c->amgk_learned.cinv : (const void*)c->pk_learned.nodes,
+                          ps.r_old};
     if (!std::equal(key, key + 4, c->gx_key)) {
         c->drop_graphs();
         std::copy(key, key + 4, c->gx_key);
@@ -852,7 +1043,7 @@ void elliptic_refine(bido_ctx* c) {
     const double want = 0.1 * c->params.tol;
     PROF(c, K_MISC, 16.0 * N, launch_dot_reduce(s, N, c->tC, c->tC, c->rd, c->sc + S_EL_BB));
     PROF(c, K_MISC, 8.0 * c->n2, launch_fill(s, c->n2, c->q, 0.0));
-    for (int round = 0; round < 20; ++round) {
+    for (int round = 0; round < 60; ++round) {
         if (hipMemcpyAsync(c->q, c->tA, N * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) return;
         PROF(c, K_SPMV_CSR, csr_bytes(urows, c->n2),
              launch_spmv_csr(s, urows, c->spmv_group, c->q, c->tC, c->tD));            // tC - S_1 tA
@@ -863,7 +1054,8 @@ void elliptic_refine(bido_ctx* c) {
             return;                              // reported by the caller's error check
         const double rr = c->sc_host[S_EL_RR], bb = c->sc_host[S_EL_BB];
         if (!(rr > want * want * bb)) break;     // converged (or b = 0)
-        tri_solve<double>(c, c->p1, c->p1.panel64, c->p1.panel64_cm, c->tD, c->r);
+        if (c->amg1.on()) amg_vcycle(c, c->amg1, 0, c->tD, c->r, true);
+        else tri_solve<double>(c, c->p1, c->p1.panel64, c->p1.panel64_cm, c->tD, c->r);
         PROF(c, K_MISC, 24.0 * N, launch_axpy(s, N, 1.0, c->r, c->tA));
     }
 }
@@ -893,7 +1085,8 @@ void step_prepare(bido_ctx* c, double* v, double* w, double* u, int64_t n) {
         PROF(c, K_MISC, 24.0 * NH, launch_scatter_in(s, NH, c->v_pos, vin, c->x + N));
         PROF(c, K_SPMV_CSR, csr_bytes(c->auv, NH),
              launch_spmv_csr(s, c->auv, c->spmv_group, c->x + N, nullptr, c->tC));   // Pi^T S_i V*
-        tri_solve<double>(c, c->p1, c->p1.panel64, c->p1.panel64_cm, c->tC, c->tA);   // FP64 in both precisions
+        if (c->amg1.on()) amg_vcycle(c, c->amg1, 0, c->tC, c->tA, true);             // FP64 in both precisions
+        else tri_solve<double>(c, c->p1, c->p1.panel64, c->p1.panel64_cm, c->tC, c->tA);
         elliptic_refine(c);
         PROF(c, K_MISC, 8.0 * N, launch_fill(s, N, c->x, 0.0));
         PROF(c, K_SPMV_CSR, csr_bytes(rows, c->n2),
@@ -1445,10 +1638,19 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     if ((e = CsrHostView::up(hs.lam, c->lam))) return e;
     if ((e = CsrHostView::up(hs.avu, c->avu))) return e;
     if ((e = CsrHostView::up(hs.auv, c->auv))) return e;
-    if ((e = build_factor_dev(hs.p1, true, c->p1, hs.params.n_threads))) return e;
-    if ((e = build_factor_dev(hs.pk, true, c->pk, hs.params.n_threads))) return e;
-    hs.p1.trim_top_cache(c->p1.top_h);      // a fused batch reuses hierarchical tops
-    hs.pk.trim_top_cache(c->pk.top_h);
+    if (hs.p1_factored) {
+        if ((e = build_factor_dev(hs.p1, true, c->p1, hs.params.n_threads))) return e;
+        hs.p1.trim_top_cache(c->p1.top_h);  // a fused batch reuses hierarchical tops
+    } else if ((e = upload_amg(hs.amg1, c->amg1))) {
+        return e;
+    }
+    if (hs.pk_factored) {
+        if ((e = build_factor_dev(hs.pk, true, c->pk, hs.params.n_threads))) return e;
+        hs.pk.trim_top_cache(c->pk.top_h);
+    } else if (params->inner_pk == BIDO_PK_AMG) {
+        if ((e = upload_amg(hs.amgk, c->amgk))) return e;
+        c->pk_kind = BIDO_PK_AMG;
+    }
     const int64_t n2 = c->n2;
     for (double** b : {&c->x, &c->r, &c->z, &c->p, &c->q, &c->Y, &c->r_old})
         HIP_OK(hipMalloc((void**)b, n2 * sizeof(double)));
@@ -1464,9 +1666,8 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     for (double* b : {c->tA, c->tC, c->tD}) HIP_OK(hipMemset(b, 0xFF, c->N * sizeof(double)));
     HIP_OK(hipMemset(c->tB, 0xFF, std::max<int64_t>(c->NH, 1) * sizeof(double)));
     HIP_OK(hipMemset(c->sc, 0xFF, pp_offset(PP_COUNT) * sizeof(double)));
-    for (FactorDev* f : {&c->p1, &c->pk}) {
-        HIP_OK(poison_workspace(*f));
-    }
+    if (hs.p1_factored) HIP_OK(poison_workspace(c->p1));
+    if (hs.pk_factored) HIP_OK(poison_workspace(c->pk));
     HIP_OK(hipHostMalloc((void**)&c->sc_host, pp_offset(PP_COUNT) * sizeof(double), hipHostMallocDefault));
     HIP_OK(hipMalloc((void**)&c->rd.partials, 2 * c->rd.max_blocks * sizeof(double)));
     HIP_OK(hipMalloc((void**)&c->rd.counter, sizeof(unsigned)));
@@ -1483,6 +1684,9 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     HIP_OK(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
     if ((e = gnn_setup(c.get()))) return e;
     c->precond = params->precond == BIDO_PRECOND_LEARNED_ADDITIVE ? params->precond : BIDO_PRECOND_PLAIN;
+    if (params->inner_pk == BIDO_PK_CHEBYSHEV &&
+        (e = bido_set_pk(c.get(), BIDO_PK_CHEBYSHEV, 3, 0.0, 0.0)))   // K_m and an estimated interval
+        return e;
     HIP_OK(hipDeviceSynchronize());
     *out = c.release();
     return BIDO_OK;
@@ -1584,6 +1788,9 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
             return fail(BIDO_ERR_STATE, "a fused batch needs one P_K choice (kind, Chebyshev steps) for all slices");
         if (ctxs[i]->precision != ctxs[0]->precision)
             return fail(BIDO_ERR_STATE, "a fused batch needs one precision for all slices");
+        if (!ctxs[i]->hs.p1_factored || !ctxs[i]->hs.pk_factored || ctxs[i]->pk_kind == BIDO_PK_AMG)
+            return fail(BIDO_ERR_STATE, "a fused batch sweeps the forest of the slices' factors: every slice "
+                                        "needs factored P_1 and K_m");
     }
     auto t0 = std::chrono::steady_clock::now();
     auto b = std::make_unique<bido_batch>();
@@ -1942,7 +2149,17 @@ bido_status bido_get_info(const bido_ctx* c, bido_info* info) {
     info->launches_per_sweep_pk = (int)c->pk.top.size() + (c->pk.plan.n_sub > 0);
     info->lowrank_blocks = c->p1.top_lowrank + c->pk.top_lowrank;
     info->setup_seconds = c->hs.setup_seconds + c->p1.top_seconds + c->pk.top_seconds;
-    info->ground_index = (int)c->p1.ground;
+    info->ground_index = (int)c->hs.p1.ground;
+    if (c->amg1.on()) {
+        info->bytes_p1 = (int64_t)c->amg1.bytes(c->precision == BIDO_PREC_MIXED ? 4 : 8);
+        info->levels_p1 = (int)c->amg1.lv.size();
+        info->launches_per_sweep_p1 = 0;
+    }
+    if (c->amgk.on()) {
+        info->bytes_pk = (int64_t)c->amgk.bytes(c->precision == BIDO_PREC_MIXED ? 4 : 8);
+        info->levels_pk = (int)c->amgk.lv.size();
+        info->launches_per_sweep_pk = 0;
+    }
     return BIDO_OK;
 }
 
@@ -1979,7 +2196,7 @@ bido_status bido_profile_read(bido_ctx* c, bido_kprof* out, int cap, int* n) {
 
 bido_status bido_inner_solve(bido_ctx* c, int which, const double* b, double* x) {
     if (!c || !b || !x || (which != 0 && which != 1)) return fail(BIDO_ERR_ARG, "bad argument");
-    if (which == 0) inner_solve(c, c->p1, b, x);
+    if (which == 0) p1_solve(c, b, x);
     else pk_solve(c, b, x);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(c->stream));
@@ -1995,6 +2212,8 @@ bido_status bido_inner_solve(bido_ctx* c, int which, const double* b, double* x)
 // workspace: overlapping calls race.
 bido_status bido_inner_solve_noalloc(bido_ctx* c, int which, const double* b, double* x, int64_t* need) {
     if (!c || !b || !x || (which != 0 && which != 1)) return fail(BIDO_ERR_ARG, "bad argument");
+    if ((which == 0 && !c->hs.p1_factored) || (which == 1 && c->pk_kind == BIDO_PK_AMG))
+        return fail(BIDO_ERR_STATE, "the allocation-free apply covers the factor sweeps and the Chebyshev P_K");
     const bool cheb = which == 1 && c->pk_kind == BIDO_PK_CHEBYSHEV;
     const FactorDev& src = which == 0 ? c->p1 : c->pk;
     auto up = [](int64_t n) { return (std::max<int64_t>(n, 1) + 31) / 32 * 32; };   // 256-byte slots
@@ -2041,11 +2260,16 @@ static bido_status estimate_pk_interval(bido_ctx* c, double* lo, double* hi) {
 
 bido_status bido_set_pk(bido_ctx* c, int kind, int steps, double lo, double hi) {
     if (!c) return fail(BIDO_ERR_ARG, "null context");
-    if (kind != BIDO_PK_CHOLESKY && kind != BIDO_PK_CHEBYSHEV) return fail(BIDO_ERR_ARG, "bad P_K kind");
+    if (kind != BIDO_PK_CHOLESKY && kind != BIDO_PK_CHEBYSHEV && kind != BIDO_PK_AMG)
+        return fail(BIDO_ERR_ARG, "bad P_K kind");
     if (c->batched) return fail(BIDO_ERR_STATE, "context is in a batch");
+    if (kind == BIDO_PK_CHOLESKY && !c->hs.pk_factored)
+        return fail(BIDO_ERR_STATE, "K_m was not factored (inner_pk at create)");
+    if (kind == BIDO_PK_AMG && !c->amgk.on())
+        return fail(BIDO_ERR_STATE, "no multigrid hierarchy of K_m (inner_pk = BIDO_PK_AMG at create)");
     HIP_OK(hipStreamSynchronize(c->stream));
     c->drop_graphs();
-    if (kind == BIDO_PK_CHOLESKY) {
+    if (kind == BIDO_PK_CHOLESKY || kind == BIDO_PK_AMG) {
         c->pk_kind = kind;
         return BIDO_OK;
     }
@@ -2087,7 +2311,9 @@ static bido_status set_dt_device(bido_ctx* c, bool refactor) {
     // Lambda: only its v-v diagonal changed, but the values go up whole
     HIP_OK(hipMemcpy(c->lam.val, c->hs.lam.val.data(), c->hs.lam.val.size() * sizeof(double),
                      hipMemcpyHostToDevice));
-    if (refactor) {
+    if (refactor && c->pk_kind == BIDO_PK_AMG) {
+        if (bido_status e = upload_amg(c->hs.amgk, c->amgk)) return e;
+    } else if (refactor) {
         const PlanOptions opts = c->pk.opts;
         c->pk.release();
         if (bido_status e = build_factor_dev(c->hs.pk, true, c->pk, c->hs.params.n_threads, &opts)) return e;
@@ -2111,6 +2337,7 @@ static bido_status set_dt_device(bido_ctx* c, bool refactor) {
     // the learned correction (samples, loss weight, stencil and its factor)
     // was fitted to K_m at the old step: set it up again from scratch
     if (c->pk_learned.nodes) c->pk_learned.release();
+    c->amgk_learned.release();
     c->gnn.release();
     if (bido_status e = gnn_setup(c)) return e;
     c->precond = BIDO_PRECOND_PLAIN;
@@ -2126,7 +2353,7 @@ bido_status bido_set_dt(bido_ctx* c, double dt, double* seconds) {
     HIP_OK(hipStreamSynchronize(c->stream));
     if (seconds) *seconds = 0.0;
     if (dt_matches(c, dt)) return BIDO_OK;
-    const bool refactor = c->pk_kind == BIDO_PK_CHOLESKY;
+    const bool refactor = c->pk_kind == BIDO_PK_CHOLESKY || c->pk_kind == BIDO_PK_AMG;
     std::string err;
     if (!host_set_dt(c->hs, dt, refactor, err)) return fail(BIDO_ERR_NOT_SPD, err);
     // from here on the host state is at the new step: a failure below leaves
@@ -2396,15 +2623,22 @@ static bido_status train_stencil(bido_ctx* c, int epochs, int batch, float lr, u
         ts->loss_last = hl[2] / n_tr;
         ts->loss_val = n_val ? hl[3] / n_val : 0.0;
     }
-    // factor K_m + C on the host and upload it as the learned P_K
+    // factor K_m + C on the host and upload it as the learned P_K (without a
+    // factored K_m: a multigrid hierarchy of K_m + C instead)
     auto t1 = std::chrono::steady_clock::now();
     Csr Kt = c->hs.km_int;
     for (int64_t p = 0; p < Kt.nnz(); ++p) Kt.val[p] += g.dbar * (double)cv[p];
     Factor f;
     f.tree = c->hs.pk.tree;
     std::string err;
-    const bool spd = multifrontal(Kt, f, -1, c->params.n_threads, err);
-    if (spd) {
+    bool spd = false;
+    if (!c->hs.pk_factored) {
+        Amg am;
+        spd = amg_build(Kt, -1, AmgOptions(), am, err);
+        if (spd) {
+            if (bido_status e = upload_amg(am, c->amgk_learned)) return e;
+        }
+    } else if ((spd = multifrontal(Kt, f, -1, c->params.n_threads, err))) {
         c->pk_learned.release();
         bido_status e = build_factor_dev(f, true, c->pk_learned, c->params.n_threads);
         if (e) return e;
@@ -2526,6 +2760,7 @@ bido_status bido_autotune(bido_ctx* c, int reps, bido_tune_report* rep) {
     bido_tune_report r{};
     const int nth = c->hs.params.n_threads;
     for (int which = 0; which < 2; ++which) {
+        if (!(which == 0 ? c->hs.p1_factored : c->hs.pk_factored)) continue;   // nothing to tune
         FactorDev& cur = which == 0 ? c->p1 : c->pk;
         const Factor& f = which == 0 ? c->hs.p1 : c->hs.pk;
         launch_fill(c->stream, cur.n, c->r, 1.0);
@@ -2591,6 +2826,8 @@ bido_status bido_set_plan(bido_ctx* c, int which, const bido_plan* q) {
         q->spmv_group != 32)
         return fail(BIDO_ERR_ARG, "spmv_group must be 4, 8, 16 or 32");
     if (c->batched) return fail(BIDO_ERR_STATE, "context belongs to a batch");
+    if (!(which == 0 ? c->hs.p1_factored : c->hs.pk_factored))
+        return fail(BIDO_ERR_STATE, "that block is not factored (inner_p1 / inner_pk at create)");
     HIP_OK(hipStreamSynchronize(c->stream));
     c->drop_graphs();
     PlanOptions o;

@@ -184,6 +184,36 @@ void merge_factors(const std::vector<const Factor*>& fs, const std::vector<int64
 // grounded entry fixed to zero.
 void host_solve(const Factor& f, const double* b, double* x);
 
+// Smoothed-aggregation multigrid (amg.cpp): level l holds its matrix A,
+// the smoother's D^-1 (0 at an excluded vertex) and interval [lo, hi] of
+// D^-1 A, and (all but the coarsest) the prolongation P (n_l x n_{l+1}) and
+// R = P^T; the coarsest matrix is held as its dense inverse.
+struct AmgLevel {
+    Csr A, P, R;
+    std::vector<double> dinv;
+    double lo = 0.0, hi = 0.0;
+};
+struct Amg {
+    std::vector<AmgLevel> levels;
+    std::vector<double> coarse_inv;   // n_c x n_c row-major
+    int64_t excluded = -1;            // fine vertex held at zero (grounded), or -1
+    int smooth_steps = 2;             // Chebyshev steps per smoothing
+    double op_complexity = 1.0;       // sum of nnz over levels / nnz of A_0
+    double setup_seconds = 0.0;
+};
+struct AmgOptions {
+    double theta = 0.08;        // strength threshold
+    int max_coarse = 1024;      // coarsest size
+    int max_levels = 16;
+    int smooth_steps = 2;       // Chebyshev steps (degree of the smoother polynomial)
+    double smooth_ratio = 10.0; // smoother interval [hi / ratio, hi]
+    int lanczos_steps = 20;     // estimate of lambda_max(D^-1 A) per level
+};
+bool amg_build(const Csr& A, int64_t excluded, const AmgOptions& opt, Amg& out, std::string& err);
+// Host V-cycle x = B b (the device apply in FP64 order-independent form; a
+// check hook).
+void amg_apply(const Amg& M, const double* b, double* x);
+
 // Chebyshev-accelerated Jacobi iteration for P_K ~ K_m (chebyshev.cpp).
 // Interval for the spectrum of D^-1 K (D = diag K): rigorous bounds
 // [min gamma m_i / K_ii, Gershgorin] (gm = gamma M_H in the order of K),

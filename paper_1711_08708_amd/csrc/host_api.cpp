@@ -206,6 +206,63 @@ bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n
     return BIDO_OK;
 }
 
+static const bido::Amg* host_amg(const bido_host* h, int which) {
+    const bido::Amg* m = which == BIDO_FACTOR_P1 ? &h->hs.amg1 : which == BIDO_FACTOR_PK ? &h->hs.amgk : nullptr;
+    return m && !m->levels.empty() ? m : nullptr;
+}
+
+bido_status bido_host_amg_info(const bido_host* h, int which, int* levels, int64_t* n_coarse, double* op_complexity,
+                               double* seconds, int* smooth_steps) {
+    if (!h) return hfail(BIDO_ERR_ARG, "null argument");
+    const bido::Amg* m = host_amg(h, which);
+    if (!m) return hfail(BIDO_ERR_STATE, "no multigrid hierarchy for that block");
+    if (levels) *levels = (int)m->levels.size();
+    if (n_coarse) *n_coarse = m->levels.back().A.n;
+    if (op_complexity) *op_complexity = m->op_complexity;
+    if (seconds) *seconds = m->setup_seconds;
+    if (smooth_steps) *smooth_steps = m->smooth_steps;
+    return BIDO_OK;
+}
+
+bido_status bido_host_amg_level(const bido_host* h, int which, int level, int what, int64_t* n, int64_t* nnz,
+                                const int64_t** ptr, const int32_t** col, const double** val) {
+    if (!h || !n || !nnz || !ptr || !col || !val) return hfail(BIDO_ERR_ARG, "null argument");
+    const bido::Amg* m = host_amg(h, which);
+    if (!m) return hfail(BIDO_ERR_STATE, "no multigrid hierarchy for that block");
+    if (level < 0 || level >= (int)m->levels.size()) return hfail(BIDO_ERR_ARG, "level out of range");
+    const bido::AmgLevel& L = m->levels[level];
+    if (what != 0 && level + 1 == (int)m->levels.size()) return hfail(BIDO_ERR_ARG, "the coarsest level has no P");
+    const bido::Csr& a = what == 0 ? L.A : L.P;
+    if (what != 0 && what != 1) return hfail(BIDO_ERR_ARG, "what: 0 = A, 1 = P");
+    *n = a.n;
+    *nnz = a.nnz();
+    *ptr = a.ptr.data();
+    *col = a.col.data();
+    *val = a.val.data();
+    return BIDO_OK;
+}
+
+bido_status bido_host_amg_smoother(const bido_host* h, int which, int level, const double** dinv, double* lo,
+                                   double* hi) {
+    if (!h || !dinv || !lo || !hi) return hfail(BIDO_ERR_ARG, "null argument");
+    const bido::Amg* m = host_amg(h, which);
+    if (!m) return hfail(BIDO_ERR_STATE, "no multigrid hierarchy for that block");
+    if (level < 0 || level >= (int)m->levels.size()) return hfail(BIDO_ERR_ARG, "level out of range");
+    const bido::AmgLevel& L = m->levels[level];
+    *dinv = L.dinv.data();
+    *lo = L.lo;
+    *hi = L.hi;
+    return BIDO_OK;
+}
+
+bido_status bido_host_amg_apply(const bido_host* h, int which, const double* b, double* x) {
+    if (!h || !b || !x) return hfail(BIDO_ERR_ARG, "null argument");
+    const bido::Amg* m = host_amg(h, which);
+    if (!m) return hfail(BIDO_ERR_STATE, "no multigrid hierarchy for that block");
+    bido::amg_apply(*m, b, x);
+    return BIDO_OK;
+}
+
 bido_status bido_host_set_plan(bido_host* h, int which, const bido_plan* q) {
     if (!h || !q) return hfail(BIDO_ERR_ARG, "null argument");
     if (which != BIDO_FACTOR_P1 && which != BIDO_FACTOR_PK) return hfail(BIDO_ERR_ARG, "unknown factor");

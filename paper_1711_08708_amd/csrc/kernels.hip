@@ -82,6 +82,27 @@ __global__ void k_fill(int64_t n, double* x, double v) {
         x[i] = v;
 }
 
+__global__ void k_add2(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                       double* __restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        out[i] = a[i] + b[i];
+}
+
+// y = A x for a dense n x n row-major A: one wave per row, the lanes stride
+// the row (coalesced), a wave reduction.
+__global__ __launch_bounds__(BLOCK) void k_dense_gemv(int64_t n, const double* __restrict__ A,
+                                                      const double* __restrict__ x, double* __restrict__ y) {
+    const int lane = threadIdx.x % WAVE;
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    for (int64_t r = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / WAVE; r < n; r += nw) {
+        const double* a = A + r * n;
+        double s = 0.0;
+        for (int64_t j = lane; j < n; j += WAVE) s += a[j] * x[j];
+        s = wave_sum(s);
+        if (lane == 0) y[r] = s;
+    }
+}
+
 __global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
     for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
         y[i] += a * x[i];
@@ -1199,6 +1220,15 @@ static inline unsigned grid_for(int64_t n, int64_t per_block = BLOCK, unsigned c
     return (unsigned)g;
 }
 
+void launch_add2(hipStream_t s, int64_t n, const double* a, const double* b, double* out) {
+    if (n <= 0) return;
+    k_add2<<<grid_for(n), BLOCK, 0, s>>>(n, a, b, out);
+}
+void launch_dense_gemv(hipStream_t s, int64_t n, const double* A, const double* x, double* y) {
+    if (n <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>((n + BLOCK / WAVE - 1) / (BLOCK / WAVE), 65535);
+    k_dense_gemv<<<g, BLOCK, 0, s>>>(n, A, x, y);
+}
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
     if (n <= 0) return;
     k_axpy<<<grid_for(n), BLOCK, 0, s>>>(n, a, x, y);

@@ -97,6 +97,30 @@ hipError_t noalloc_scratch(int device, double** ptr);
 
 void launch_fill(hipStream_t s, int64_t n, double* x, double v);
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y);   // y += a x
+void launch_add2(hipStream_t s, int64_t n, const double* a, const double* b, double* out);   // out = a + b
+// A CSR matrix of a multigrid level with FP64 or FP32 values, and the lanes
+// per row its products use (amg.hip).
+template <typename T>
+struct AmgMat {
+    int64_t n = 0, nnz = 0;
+    const int64_t* ptr = nullptr;
+    const int32_t* col = nullptr;
+    const T* val = nullptr;
+    int group = 4;
+};
+// y = b + sign A x (b may be null)
+template <typename T>
+void launch_amg_spmv(hipStream_t s, const AmgMat<T>& A, const double* x, const double* b, double sign, double* y);
+// the first two Chebyshev smoothing steps from z = 0 in one pass (see amg.hip)
+template <typename T>
+void launch_amg_smooth2(hipStream_t s, const AmgMat<T>& A, const double* dinv, const double* b, double a0, double c1,
+                        double c2, double* z, double* r1, double* d0, double* d1, bool write_rd);
+// one further Chebyshev step: r -= A dp, dn = c1 dp + c2 D^-1 r, z += dn
+template <typename T>
+void launch_amg_cheb(hipStream_t s, const AmgMat<T>& A, const double* dinv, double* r, const double* dp, double* dn,
+                     double* z, double c1, double c2);
+// y = A x, A dense n x n row-major (the coarsest level of a multigrid V-cycle)
+void launch_dense_gemv(hipStream_t s, int64_t n, const double* A, const double* x, double* y);
 void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst);
 void launch_scatter_in_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst);
 void launch_gather_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst);

@@ -142,6 +142,11 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
         err = "bad time scheme";
         return false;
     }
+    if (P.inner_p1 != BIDO_P1_CHOLESKY && P.inner_p1 != BIDO_P1_AMG) { err = "bad inner_p1"; return false; }
+    if (P.inner_pk != BIDO_PK_CHOLESKY && P.inner_pk != BIDO_PK_CHEBYSHEV && P.inner_pk != BIDO_PK_AMG) {
+        err = "bad inner_pk";
+        return false;
+    }
 #ifdef _OPENMP
     if (P.n_threads > 0) omp_set_num_threads(P.n_threads);
 #endif
@@ -185,8 +190,26 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
     Csr Kmp = permute(Km, tk.perm, tk.iperm);
     hs.km_int = Kmp;
     const int nth = P.n_threads;
-    if (!multifrontal(S1p, hs.p1, N - 1, nth, err)) { err = "P_1: " + err; return false; }
-    if (!multifrontal(Kmp, hs.pk, -1, nth, err)) { err = "P_K: " + err; return false; }
+    hs.p1_factored = P.inner_p1 == BIDO_P1_CHOLESKY;
+    hs.pk_factored = P.inner_pk == BIDO_PK_CHOLESKY;
+    if (hs.p1_factored) {
+        if (!multifrontal(S1p, hs.p1, N - 1, nth, err)) { err = "P_1: " + err; return false; }
+    } else {
+        hs.p1.n = N;
+        hs.p1.ground = N - 1;
+        hs.p1.grounds.assign(1, N - 1);
+        // the grounded vertex N - 1 is held at zero (excluded), as in the factor
+        if (!amg_build(S1p, N - 1, AmgOptions(), hs.amg1, err)) { err = "P_1: " + err; return false; }
+    }
+    if (hs.pk_factored) {
+        if (!multifrontal(Kmp, hs.pk, -1, nth, err)) { err = "P_K: " + err; return false; }
+    } else {
+        hs.pk.n = NH;
+        if (P.inner_pk == BIDO_PK_AMG && !amg_build(Kmp, -1, AmgOptions(), hs.amgk, err)) {
+            err = "P_K: " + err;
+            return false;
+        }
+    }
     {   // coordinates (tree order) and the accuracy of the hierarchical top
         std::vector<double> x1((size_t)N * d), xk((size_t)NH * d);
         for (int64_t p = 0; p < N; ++p)
@@ -304,7 +327,14 @@ bool host_set_dt(HostSetup& hs, double dt, bool refactor, std::string& err) {
         found = found && f;
     }
     if (!found) { err = "missing diagonal in S_i"; return false; }
-    if (refactor) {
+    if (refactor && !hs.pk_factored) {
+        if (P.inner_pk == BIDO_PK_AMG) {
+            Amg na;
+            std::string e2;
+            if (!amg_build(Kmp, -1, AmgOptions(), na, e2)) { err = "P_K: " + e2; return false; }
+            hs.amgk = std::move(na);
+        }
+    } else if (refactor) {
         Factor nf;
         nf.tree = hs.pk.tree;
         std::string e2;

@@ -13,7 +13,10 @@ namespace bido {
 struct HostSetup {
     bido_params params{};
     Assembled A;
-    Factor p1, pk;                 // factors of the grounded S_1 and of K_m
+    Factor p1, pk;                 // factors of the grounded S_1 and of K_m (trees always;
+                                   // fronts only when that block is factored)
+    bool p1_factored = true, pk_factored = true;
+    Amg amg1, amgk;                // multigrid hierarchies (inner_p1 / inner_pk = AMG)
     Csr lam;                       // Lambda, internal order [u (ND of S_1); v (ND of K_m)]
     Csr avu;                       // S_i Pi: N_H rows (v order), u columns
     Csr auv;                       // Pi^T S_i: N rows (u order), v columns

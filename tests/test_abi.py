@@ -34,9 +34,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header():
     import paper_1711_08708_amd as B
-    # bido_params: 6 doubles + 7 ints (+ 4 bytes of tail padding); bido_stats:
+    # bido_params: 6 doubles + 9 ints (+ 4 bytes of tail padding); bido_stats:
     # 2 ints, 2 doubles, int, double, int64
-    assert ctypes.sizeof(B.Params) == 6 * 8 + 7 * 4 + 4
+    assert ctypes.sizeof(B.Params) == 6 * 8 + 9 * 4 + 4
     assert B.default_params().scheme == B.SCHEME_EULER
     assert ctypes.sizeof(B.Stats) == 48
     p = B.default_params()

@@ -182,37 +182,38 @@ def _check_solve_cg(torch, cfg, solver, label):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("wide,rows", [(1, 256), (0, 128)], ids=["wide256", "narrow128"])
+@pytest.mark.parametrize("wide,rows", [(1, 128), (0, 64)], ids=["wide128", "narrow64"])
 def test_split_backward_items_parity(torch, precision, wide, rows):
     """Backward level items forced onto row ranges (the split tiles of tall
-    3D separators, summed by the combine launch), on a slab small enough
-    for the oracle: the plan really splits tiles, and the solve matches
-    the oracle."""
+    3D separators, summed by the combine launch) on every level up to the
+    root (no top), on a slab small enough for the oracle: the plan really
+    splits tiles, and the solve matches the oracle."""
     import paper_1711_08708_amd as B
     cfg = w.slab3d(n=20)
     hs = B.HostSetup(cfg, eps_h=0.0)
     solver = B.Solver(cfg, eps_h=0.0, precision=precision)
     for which in (0, 1):
-        hs.set_plan(which, bwd_wide=wide, bwd_rows=rows)
+        H = hs.factor_stats(which)["height"]
+        hs.set_plan(which, bwd_wide=wide, bwd_rows=rows, top_h=H + 1)
         plan = hs.factor_plan(which)
         print(f"slab20 factor {which} plan {plan}", flush=True)
         assert plan["n_bwd_split"] > 0
-        solver.set_plan(which, bwd_wide=wide, bwd_rows=rows)
+        solver.set_plan(which, bwd_wide=wide, bwd_rows=rows, top_h=H + 1)
     _check_solve_cg(torch, cfg, solver, f"slab20 split {wide}/{rows} precision {precision}")
 
 
-def test_slab32_default_plan_splits_and_matches_oracle(torch):
-    """A 33^3-vertex slab: its default plan cuts the tall backward tiles of
+def test_slab40_default_plan_splits_and_matches_oracle(torch):
+    """A 41^3-vertex slab: its default plan cuts the tall backward tiles of
     its separators into row ranges (asserted), and the mixed-precision
     solve matches the oracle."""
     import paper_1711_08708_amd as B
-    cfg = w.slab3d(n=32)
+    cfg = w.slab3d(n=40)
     hs = B.HostSetup(cfg, eps_h=0.0)
     plan = hs.factor_plan(0)
-    print("slab32 P1 plan", plan, flush=True)
+    print("slab40 P1 plan", plan, flush=True)
     assert plan["n_bwd_split"] > 0
     solver = B.Solver(cfg, eps_h=0.0, precision=B.PREC_MIXED)
-    _check_solve_cg(torch, cfg, solver, "slab32 mixed")
+    _check_solve_cg(torch, cfg, solver, "slab40 mixed")
 
 
 @pytest.mark.timeout(900)

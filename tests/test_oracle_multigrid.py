@@ -1,0 +1,137 @@
+"""CPU pins of the multigrid inner preconditioner (an alternative P_1 ~ S_1
+and P_K ~ K_m; Sec. 5.3 leaves both free).
+
+The oracle V-cycle (oracle/multigrid.py) is pinned by properties that hold
+for any hierarchy: with the identity as prolongation the cycle is the exact
+solve; the cycle is a symmetric operator; for a symmetric positive definite
+matrix and a convergent smoother the spectrum of B A lies in (0, 1]; the
+excluded (grounded) vertex stays at zero.  The library's hierarchy is
+checked for the Galerkin relation A_{l+1} = P_l^T A_l P_l, and its host
+V-cycle against the oracle cycle on the same hierarchy."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as w
+from oracle import multigrid as mg
+
+
+def _laplacian_2d(n, shift=0.0):
+    """5-point Laplacian on an n x n grid with Dirichlet boundary, plus shift I."""
+    e = np.ones(n)
+    T = sp.diags([-e[:-1], 2 * e, -e[:-1]], [-1, 0, 1])
+    I = sp.identity(n)
+    return (sp.kron(I, T) + sp.kron(T, I) + shift * sp.identity(n * n)).tocsr()
+
+
+def _pair_aggregation(n_fine):
+    """Tentative prolongation of aggregates {2k, 2k+1} (plain, not smoothed)."""
+    nc = (n_fine + 1) // 2
+    rows = np.arange(n_fine)
+    return sp.csr_matrix((np.full(n_fine, 1.0), (rows, rows // 2)), shape=(n_fine, nc))
+
+
+def _level(A, P, hi_factor=1.1, ratio=10.0):
+    d = A.diagonal()
+    dinv = 1.0 / d
+    lam = np.linalg.eigvalsh((sp.diags(np.sqrt(dinv)) @ A @ sp.diags(np.sqrt(dinv))).toarray()).max()
+    return dict(A=A, P=P, dinv=dinv, lo=hi_factor * lam / ratio, hi=hi_factor * lam)
+
+
+def test_identity_prolongation_gives_the_exact_solve():
+    A = _laplacian_2d(6, 0.3)
+    n = A.shape[0]
+    levels = [_level(A, sp.identity(n, format="csr")), dict(A=A, P=None, dinv=A.diagonal() ** -1)]
+    b = np.random.default_rng(0).normal(size=n)
+    x = mg.vcycle(levels, 2, b)
+    np.testing.assert_allclose(A @ x, b, rtol=0, atol=1e-12 * np.abs(b).max())
+
+
+def test_single_level_is_the_exact_solve_with_excluded_vertex_at_zero():
+    A = _laplacian_2d(5).tolil()
+    n = A.shape[0]
+    dinv = 1.0 / A.diagonal()
+    dinv[-1] = 0.0
+    b = np.random.default_rng(1).normal(size=n)
+    x = mg.vcycle([dict(A=A.tocsr(), P=None, dinv=dinv)], 2, b)
+    assert x[-1] == 0.0
+    keep = np.arange(n - 1)
+    Ad = A.toarray()[np.ix_(keep, keep)]
+    np.testing.assert_allclose(Ad @ x[keep], b[keep], atol=1e-12 * np.abs(b).max())
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_vcycle_is_symmetric_and_contracting(m):
+    """Three levels built by pair aggregation: B symmetric, spectrum of B A
+    in (0, 1] (a symmetric V-cycle with Galerkin coarse matrices and a
+    smoother with |1 - lambda q(lambda)| <= 1 on the spectrum)."""
+    A0 = _laplacian_2d(8, 0.05)
+    P0 = _pair_aggregation(A0.shape[0])
+    A1 = (P0.T @ A0 @ P0).tocsr()
+    P1 = _pair_aggregation(A1.shape[0])
+    A2 = (P1.T @ A1 @ P1).tocsr()
+    levels = [_level(A0, P0), _level(A1, P1), dict(A=A2, P=None, dinv=1.0 / A2.diagonal())]
+    n = A0.shape[0]
+    Bm = np.column_stack([mg.vcycle(levels, m, e) for e in np.eye(n)])
+    assert np.abs(Bm - Bm.T).max() <= 1e-12 * np.abs(Bm).max()
+    ev = np.linalg.eigvals(Bm @ A0.toarray()).real
+    assert ev.min() > 0.0 and ev.max() <= 1.0 + 1e-10, (ev.min(), ev.max())
+    # a missing post-smoothing or a wrong sign of the coarse correction breaks one of these
+    assert ev.min() > 0.05
+
+
+@pytest.mark.parametrize("mk", [lambda: w.slab3d(n=12), lambda: w.thorax2d(n_target=6000, seed=3),
+                                lambda: w.square2d(n=20)], ids=["slab12", "thorax6000", "square20"])
+def test_library_hierarchy_is_galerkin_and_its_cycle_is_the_oracle_cycle(mk):
+    import paper_1711_08708_amd as B
+    hs = B.HostSetup(mk(), eps_h=0.0, inner_p1=B.P1_AMG, inner_pk=B.PK_AMG)
+    for which in (B.FACTOR_P1, B.FACTOR_PK):
+        info = hs.amg_info(which)
+        levels = [hs.amg_level(which, l) for l in range(info["levels"])]
+        for a, b in zip(levels, levels[1:]):
+            if a["P"] is None:
+                continue
+            G = (a["P"].T @ a["A"] @ a["P"]).toarray()
+            np.testing.assert_allclose(b["A"].toarray(), G, atol=1e-12 * np.abs(G).max())
+        n = levels[0]["A"].shape[0]
+        b = np.random.default_rng(5 + which).normal(size=n)
+        xo = mg.vcycle(levels, info["smooth_steps"], b)
+        xl = hs.amg_apply(which, b)
+        err = np.linalg.norm(xl - xo) / np.linalg.norm(xo)
+        print(which, info, "host vs oracle cycle", err)
+        assert err <= 1e-11
+        if which == B.FACTOR_P1:
+            assert xl[-1] == 0.0 and levels[0]["dinv"][-1] == 0.0   # the grounded vertex
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_multigrid_p1_converges_in_few_iterations(n):
+    """CG on the grounded S_1 of a slab with the library's host V-cycle:
+    the iteration count to 1e-10 stays small and nearly flat in the mesh
+    size (a quality check of the hierarchy, not of the arithmetic)."""
+    import paper_1711_08708_amd as B
+    hs = B.HostSetup(w.slab3d(n=n), eps_h=0.0, inner_p1=B.P1_AMG)
+    A = hs.amg_level(B.FACTOR_P1, 0)["A"]
+    N = A.shape[0]
+    rng = np.random.default_rng(0)
+    b = rng.normal(size=N)
+    b[-1] = 0.0
+    b[:-1] -= b[:-1].mean()
+    x = np.zeros(N)
+    r = b.copy()
+    z = hs.amg_apply(B.FACTOR_P1, r)
+    p = z.copy()
+    rz = r @ z
+    for it in range(100):
+        q = A @ p
+        q[-1] = 0.0
+        a = rz / (p @ q)
+        x += a * p
+        r -= a * q
+        if np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b):
+            break
+        z = hs.amg_apply(B.FACTOR_P1, r)
+        rz, rz_old = r @ z, rz
+        p = z + (rz / rz_old) * p
+    print("slab", n, "CG iterations with the multigrid P_1", it + 1, hs.amg_info(B.FACTOR_P1))
+    assert it + 1 <= 25

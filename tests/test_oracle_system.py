@@ -245,3 +245,32 @@ def test_orders_with_reaction(scheme, order):
     rates = [np.log2(errs[k] / errs[k + 1]) for k in range(2)]
     print(scheme, "errors", errs, "rates", rates)
     assert all(abs(r - order) < 0.3 for r in rates), rates
+
+
+@pytest.mark.parametrize("mk", [lambda: w.thorax2d(n_target=3000, seed=5), lambda: w.slab3d(n=6)],
+                         ids=["thorax3000", "slab6"])
+def test_sampled_residual_rows_equal_the_assembled_system(mk):
+    """The row-by-row residual used for full-size checks (each row assembled
+    from the elements of its vertex) equals the rows of Lambda X - Y of the
+    fully assembled system, for an arbitrary X (torso and heart rows)."""
+    cfg = mk()
+    s = bd.System(cfg)
+    rng = np.random.default_rng(8)
+    Vn = rng.uniform(0, 100, s.NH)
+    hn = rng.uniform(0, 1, s.NH)
+    U1 = rng.normal(size=s.N)
+    V1 = rng.normal(size=s.NH)
+    n = 0
+    Y = s.rhs(Vn, hn, n)
+    X = np.concatenate([s.from_global_u(U1), V1])
+    R = s.Lam @ X - Y
+    Ru = s.to_global_u(R[:s.N])
+    verts = rng.choice(s.N, size=min(200, s.N), replace=False)
+    ru, rv, yv = bd.sampled_residual(cfg, verts, Vn, hn, n, U1, V1)
+    np.testing.assert_allclose(ru, Ru[verts], rtol=1e-12, atol=1e-12 * np.abs(Ru).max())
+    loc = -np.ones(s.N, dtype=np.int64)
+    loc[s.hn] = np.arange(s.NH)
+    hv = verts[loc[verts] >= 0]
+    assert len(hv) > 0
+    np.testing.assert_allclose(rv, R[s.N + loc[hv]], rtol=1e-12, atol=1e-12 * np.abs(R[s.N:]).max())
+    np.testing.assert_allclose(yv, Y[s.N + loc[hv]], rtol=1e-13, atol=0)
