@@ -30,9 +30,12 @@ V_ACT = 64.0    # activation level, mV above rest (the -20 mV level of the paper
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 100; 10 per variant on slab128)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="thorax200k")
+    ap.add_argument("--config", default="slab128",
+                    help="slab128 (the 3D slab of 2,146,689 vertices: plain vs learned+mixed, the headline), "
+                         "thorax200k, slab64, square48 or batch64")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--eps", type=float, default=1e-8,
                     help="accuracy of the hierarchical top of the inner solves (0: exact)")
@@ -125,6 +128,8 @@ def _timed_steps(torch, solver, state, n0, k):
 
 def main():
     args = _parse()
+    if args.steps is None:
+        args.steps = 10 if args.config == "slab128" else 100
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -134,6 +139,9 @@ def main():
         return
     if args.config == "batch64":
         _bench_batch(args)
+        return
+    if args.config == "slab128":
+        _bench_slab128(args)
         return
     import numpy as np
     import torch
@@ -339,6 +347,174 @@ def _variants(torch, B, solver, args, w_cfg):
     solver.set_precond(B.PRECOND_PLAIN)
     solver.set_pk(main_pk["kind"], max(1, main_pk["steps"]), main_pk["lo"], main_pk["hi"])
     return out
+
+
+def _bench_slab128(args):
+    """The 3D orthotropic slab at 128^3 hexes (2,146,689 vertices, isolated
+    heart): plain FP64 block-LU PCG against the learned correction with
+    mixed precision, at tol 1e-10.
+
+    Both inner solves are multigrid V-cycles (no factorisation: exact or
+    hierarchical factors of this mesh do not fit a set-up budget).  The
+    learned Schur-complement stencil is trained on the residual/error pairs
+    of the first `collect_steps` (default 100) plain steps from rest; the
+    preconditioner then uses a multigrid hierarchy of K_m + C.  Every variant
+    runs the same `steps` steps from the state after the collection, then
+    one more step whose solution is checked against the oracle on sampled
+    rows (Lambda X - Y assembled row by row from the elements of 4,096
+    sampled vertices) and for the normalisation (M U, 1) = 0."""
+    import numpy as np
+    import torch
+
+    import paper_1711_08708_amd as B
+    import workloads as w
+    from oracle import bidomain as bd
+
+    torch.cuda.set_device(0)
+    if args.collect_steps == 40:        # the parser's default is sized for the 2D slice
+        args.collect_steps = 100
+    cfg = w.make_config("slab128")
+    t0 = time.perf_counter()
+    solver = B.Solver(cfg, tol=args.tol, eps_h=0.0, precision=B.PREC_FP64, inner_p1=B.P1_AMG,
+                      inner_pk=B.PK_AMG)
+    t_setup = time.perf_counter() - t0
+    info = solver.info
+    print(f"[bench] slab128: N={solver.N} setup {t_setup:.1f} s; one V-cycle reads P1 "
+          f"{info['bytes_p1'] / 1e6:.0f} MB, PK {info['bytes_pk'] / 1e6:.0f} MB", file=sys.stderr, flush=True)
+    v, h, u = solver.state()
+    t0 = time.perf_counter()
+    col = solver.learn_collect(v, h, u, 0, args.collect_steps, max_samples=200)
+    t_col = time.perf_counter() - t0
+    print(f"[bench] collected {col['samples']} pairs over {args.collect_steps} plain steps in {t_col:.1f} s",
+          file=sys.stderr, flush=True)
+    n_val = max(1, col["samples"] // 10)
+    ts = solver.learn_train(kind=B.LEARN_STENCIL, epochs=args.epochs, batch=8, lr=2e-3, seed=0, n_val=n_val)
+    print(f"[bench] trained the stencil in {ts['seconds']:.1f} s (hierarchy of K_m + C "
+          f"{ts['refactor_seconds']:.1f} s), loss {ts['loss_zero']:.3g} -> {ts['loss_last']:.3g}",
+          file=sys.stderr, flush=True)
+    saved = [t.clone() for t in (v, h, u)]
+    n1 = args.collect_steps
+    rng = np.random.default_rng(11)
+    sample = np.sort(rng.choice(solver.N, size=4096, replace=False))
+    runs = [("plain_fp64", B.PREC_FP64, B.PRECOND_PLAIN), ("mixed", B.PREC_MIXED, B.PRECOND_PLAIN)]
+    if ts["spd"]:
+        runs += [("learned_fp64", B.PREC_FP64, B.PRECOND_LEARNED), ("learned_mixed", B.PREC_MIXED, B.PRECOND_LEARNED)]
+    variants = {}
+    m = cfg_mass(cfg)
+    for name, prec, pc in runs:
+        solver.set_precision(prec)
+        solver.set_precond(pc)
+        st = [t.clone() for t in saved]
+        for n in range(n1, n1 + args.warmup):                 # warm-up steps of this variant
+            solver.step(st[0], st[1], st[2], n)
+        gpu_s, wall_s, it = _timed_steps(torch, solver, st, n1 + args.warmup, args.steps)
+        variants[name] = {"steps_per_s": round(args.steps / wall_s, 3), "ms_per_step": round(wall_s * 1e3 / args.steps, 3),
+                          "cg_iterations_per_step": round(it / args.steps, 3)}
+        # one more step, checked on sampled rows against the oracle
+        n = n1 + args.warmup + args.steps
+        Vn, hn = st[0].cpu().numpy().copy(), st[1].cpu().numpy().copy()
+        solver.step(st[0], st[1], st[2], n)
+        U1, V1 = st[2].cpu().numpy(), st[0].cpu().numpy()
+        ru, rv, yv = bd.sampled_residual(cfg, sample, Vn, hn, n, U1, V1)
+        variants[name]["parity"] = {"sampled_rows": int(len(sample)),
+                                    "max_abs_residual_over_max_abs_y": float(max(np.abs(ru).max(), np.abs(rv).max())
+                                                                            / np.abs(yv).max()),
+                                    "mean_u_over_max_u": float(abs(m @ U1) / m.sum() / np.abs(U1).max())}
+        print(f"[bench] {name}: {variants[name]}", file=sys.stderr, flush=True)
+    plain = variants["plain_fp64"]["steps_per_s"]
+    for name in variants:
+        variants[name]["speedup_vs_plain"] = round(variants[name]["steps_per_s"] / plain, 3)
+    head = "learned_mixed" if "learned_mixed" in variants else "mixed"
+
+    # replay the headline variant's timed steps with per-launch events
+    solver.set_precision(B.PREC_MIXED)
+    solver.set_precond(B.PRECOND_LEARNED if head == "learned_mixed" else B.PRECOND_PLAIN)
+    st = [t.clone() for t in saved]
+    for n in range(n1, n1 + args.warmup):
+        solver.step(st[0], st[1], st[2], n)
+    solver.profile(True)
+    for n in range(n1 + args.warmup, n1 + args.warmup + args.steps):
+        solver.step(st[0], st[1], st[2], n)
+    prof = solver.profile_read()
+    solver.profile(False)
+    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    achieved = dom["bytes"] / (dom["ms"] / 1e3) / 1e9
+    total_ms = sum(p["ms"] for p in prof.values())
+    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": _traffic(dom_name, cfg["name"], "mixed"),
+                "launches": dom["launches"], "avg_launch_us": round(dom["ms"] * 1e3 / dom["launches"], 2),
+                "bytes_per_launch": round(dom["bytes"] / dom["launches"]),
+                "step_bytes": round(sum(p["bytes"] for p in prof.values()) / args.steps),
+                "step_kernel_ms": round(total_ms / args.steps, 4)}
+    kernels = {k: {"launches": p["launches"], "ms": round(p["ms"], 3),
+                   "GBps": round(p["bytes"] / max(p["ms"], 1e-9) / 1e6, 1)} for k, p in prof.items()}
+    hv = variants[head]
+    result = {
+        "metric": METRIC, "value": hv["steps_per_s"], "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": hv["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"slab3d_n128: 3D orthotropic slab [0,1]^3 cm, 128^3 hexes x 6 tets, "
+                               f"{solver.N} vertices (isolated heart), semi-implicit bidomain step, "
+                               f"block-LU/monodomain flexible PCG to tol {args.tol:g}, multigrid P_1 and P_K, "
+                               f"{head.replace('_', ' + ')} (value) against plain FP64 (plain_fp64)",
+                   "n_nodes": solver.N, "n_heart": solver.NH, "dt_ms": cfg["dt"], "tol": args.tol,
+                   "first_timed_step": n1 + args.warmup, "setup_s": round(t_setup, 2),
+                   "p1": "multigrid", "pk": "multigrid",
+                   "multigrid_bytes_per_vcycle_fp64": {"p1": info["bytes_p1"], "pk": info["bytes_pk"]},
+                   "cg_iterations_per_step": hv["cg_iterations_per_step"]},
+        "plain_fp64": variants["plain_fp64"],
+        "speedup_vs_plain": hv["speedup_vs_plain"],
+        "variants": variants,
+        "training": {"kind": "stencil", "collect_steps": args.collect_steps, "pairs": col["samples"],
+                     "collect_s": round(t_col, 2), "train_s": round(ts["seconds"], 2),
+                     "hierarchy_s": round(ts["refactor_seconds"], 2), "spd": ts["spd"], "epochs": args.epochs,
+                     "loss_zero": ts["loss_zero"], "loss_trained": ts["loss_last"],
+                     "loss_zero_val": ts["loss_zero_val"], "loss_val": ts["loss_val"]},
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+    if not args.no_cpu:
+        result["cpu_baseline"] = _cpu_baseline_slab(solver.N)
+    print(json.dumps(result), flush=True)
+
+
+def cfg_mass(cfg):
+    """Lumped mass of every vertex (the weight of the normalisation (M U, 1))."""
+    import numpy as np
+    from oracle import fem
+    return fem.lumped_mass(cfg["xyz"], cfg["elems"].astype(np.int64), len(cfg["xyz"]))
+
+
+def _cpu_baseline_slab(n_target):
+    """The oracle on the host: one step from rest of a 32^3 and a 40^3 slab
+    (FP64 Jacobi-CG with the condition-aware stop; assembly excluded),
+    extrapolated to n_target vertices with the exponent the two sizes give."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import workloads as w
+    from oracle import bidomain as bd
+    pts = []
+    with threadpool_limits(limits=1):
+        for n in (32, 40):
+            s = bd.System(w.slab3d(n=n))
+            V = np.zeros(s.NH)
+            hh = np.ones(s.NH)
+            t0 = time.perf_counter()
+            s.step(V, hh, 0, U0=np.zeros(s.N))
+            pts.append((s.N, time.perf_counter() - t0))
+    (n0, t0_), (n1, t1_) = pts
+    alpha = float(np.log(t1_ / t0_) / np.log(n1 / n0))
+    t_full = t1_ * (n_target / n1) ** alpha
+    return {"value": round(1.0 / t_full, 6), "unit": "steps/s", "cores": 1, "kind": "oracle", "threads": 1,
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(),
+            "sample": f"one oracle step (FP64 NumPy/SciPy: Step 1, Jacobi-CG with the condition-aware stop, "
+                      f"normalisation, Step 3; assembly excluded) of the 32^3 slab ({n0} vertices, {t0_:.2f} s) "
+                      f"and the 40^3 slab ({n1} vertices, {t1_:.2f} s); value extrapolated to {n_target} "
+                      f"vertices as t ~ N^{alpha:.2f}",
+            "measured_steps_per_s": {str(n0): round(1.0 / t0_, 4), str(n1): round(1.0 / t1_, 4)}}
 
 
 def _gen_slice(kw):

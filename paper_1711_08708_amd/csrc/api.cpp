@@ -427,6 +427,10 @@ struct GnnState {
     double *s_zz = nullptr;
     double *pend_t = nullptr, *pend_v = nullptr;
     bool stencil_ready = false;
+    // pairs from consecutive steps instead of PCG iterates (an inexact P_1):
+    // K (V^{n+1} - V^n) = Y_2^n - Y_2^{n-1}, exact whatever the inner solves
+    bool increments = false, inc_ok = false;
+    double *inc_v = nullptr, *inc_y = nullptr;
     void release() {
         for (void* b : {(void*)stat, (void*)A.ptr, (void*)A.col, (void*)A.val, (void*)At.ptr, (void*)At.col,
                         (void*)At.val, (void*)Wk.ptr, (void*)Wk.col, (void*)Wk.val, (void*)act.res,
@@ -434,7 +438,7 @@ struct GnnState {
                         (void*)act.f, (void*)act.m0, (void*)act.h1, (void*)act.m1, (void*)act.h2,
                         (void*)act.o, (void*)act.dout, (void*)act.dz2, (void*)act.g2, (void*)act.dz1,
                         (void*)partials, (void*)dloss, (void*)ft, (void*)fy, (void*)tz, (void*)s_t,
-                        (void*)s_y, (void*)s_tn2, (void*)pend})
+                        (void*)s_y, (void*)s_tn2, (void*)pend, (void*)inc_v, (void*)inc_y})
             hipFree(b);
         *this = GnnState();
     }
@@ -759,7 +763,8 @@ void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old,
     else if (stencil) inner_solve(c, c->pk_learned, c->tB, z + N);   // Z2 = PK^-1 (...)
     else pk_solve(c, c->tB, z + N);
     debug_check(c, "Z2", z + N, c->NH);
-    if (g.collecting && g.n_samples + g.n_pending < g.max_samples && g.n_pending < g.max_pending) {
+    if (g.collecting && !g.increments && g.n_samples + g.n_pending < g.max_samples &&
+        g.n_pending < g.max_pending) {
         const int k = g.n_samples + g.n_pending;
         launch_dot_reduce(s, NH, c->tB, c->tB, c->rd, g.s_tn2 + k);
         launch_gnn_store_sample(s, NH, c->tB, g.s_tn2 + k, g.s_t + (int64_t)k * NH);
@@ -994,6 +999,28 @@ bido_status pcg(bido_ctx* c, double tol, bido_stats* st) {
 void finish_collection(bido_ctx* c, bool converged) {
     GnnState& g = c->gnn;
     if (!g.collecting) return;
+    if (g.increments) {
+        // one stencil pair per step from the converged solutions of this step
+        // and the previous one: z = V^{n+1} - V^n, t = Y_2^n - Y_2^{n-1}
+        const int64_t NH = c->NH;
+        if (!converged) {
+            g.inc_ok = false;
+            return;
+        }
+        if (g.inc_ok && g.n_samples < g.max_samples) {
+            const int slot = g.n_samples;
+            launch_gnn_sub(c->stream, NH, c->x + c->N, g.inc_v, g.tz);
+            launch_gnn_sub(c->stream, NH, c->Y + c->N, g.inc_y, g.pend_t);
+            launch_dot_reduce(c->stream, NH, g.tz, g.tz, c->rd, g.s_zz + slot);
+            launch_stencil_sample(c->stream, NH, g.K, g.tz, g.s_zz + slot, g.pend_t, g.dbar,
+                                  g.s_z + (int64_t)slot * NH, g.s_b + (int64_t)slot * NH);
+            ++g.n_samples;
+        }
+        hipMemcpyAsync(g.inc_v, c->x + c->N, NH * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+        hipMemcpyAsync(g.inc_y, c->Y + c->N, NH * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+        g.inc_ok = true;
+        return;
+    }
     if (converged)
         for (int k = 0; k < g.n_pending; ++k) {
             const int slot = g.n_samples + k;
@@ -2471,6 +2498,14 @@ bido_status bido_learn_collect(bido_ctx* c, double* v, double* w, double* u, dou
     }
     for (double** b : {&g.pend, &g.pend_t, &g.pend_v})
         if (!*b) HIP_OK(hipMalloc((void**)b, (size_t)g.max_pending * std::max<int64_t>(c->NH, 1) * sizeof(double)));
+    // with a multigrid P_1 the Schur right-hand side of a PCG iterate is not
+    // exact, so the stencil pairs come from consecutive converged steps
+    g.increments = !c->hs.p1_factored;
+    if (g.increments) {
+        for (double** b : {&g.inc_v, &g.inc_y})
+            if (!*b) HIP_OK(hipMalloc((void**)b, std::max<int64_t>(c->NH, 1) * sizeof(double)));
+        g.inc_ok = false;
+    }
     g.collecting = true;
     g.n_pending = 0;
     bido_status e = bido_run(c, v, w, u, dt, n0, n_steps, st);
@@ -2661,6 +2696,8 @@ bido_status bido_learn_train(bido_ctx* c, int kind, int epochs, int batch, float
     const int n_tr = c->gnn.n_samples - n_val;
     if (n_val < 0 || n_tr < 1) return fail(BIDO_ERR_STATE, "not enough collected samples");
     if (kind == BIDO_LEARN_STENCIL) return train_stencil(c, epochs, batch, lr, seed, n_val, ts);
+    if (kind == BIDO_LEARN_ADDITIVE && c->gnn.increments)
+        return fail(BIDO_ERR_STATE, "the pairs were collected as step increments (multigrid P_1): stencil only");
     if (kind == BIDO_LEARN_ADDITIVE) return train_additive(c, epochs, batch, lr, seed, n_val, ts);
     return fail(BIDO_ERR_ARG, "unknown learning target");
 }

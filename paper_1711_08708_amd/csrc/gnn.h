@@ -20,7 +20,7 @@ constexpr int GNN_OFF_B2 = GNN_OFF_W2N + GNN_H * GNN_H;
 constexpr int GNN_OFF_W3 = GNN_OFF_B2 + GNN_H;
 constexpr int GNN_OFF_B3 = GNN_OFF_W3 + GNN_H;
 constexpr int GNN_P = GNN_OFF_B3 + 1;          // 3169 parameters
-constexpr int GNN_WG_BLOCKS = 256;             // partial-sum blocks of the weight gradients
+constexpr int GNN_WG_BLOCKS = 1024;            // partial-sum blocks of the weight gradients
 
 struct GnnGraph {                 // row-normalised neighbour weights (internal v order)
     int64_t n = 0;

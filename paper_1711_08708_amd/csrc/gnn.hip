@@ -212,6 +212,60 @@ __global__ void k_wgrad(int64_t n, const float* __restrict__ G, const uint16_t* 
         }
 }
 
+// The same weight-gradient partials on the matrix cores: the product
+// G^T X (32 x IN) is a sum over vertices, so each wave runs FP32 MFMA
+// 32x32x2 steps (two vertices per step: lane l feeds G[v][l % 32] and
+// X[v][l % 32] of vertex v = v0 + l / 32), the four waves of the block add
+// their 32 x 32 tiles in LDS, and the bias (sum over vertices of G[v][a])
+// rides in column IN when IN < 32, else in a per-lane sum.  X is BF16 and
+// widened exactly to FP32; accumulation is FP32 as in k_wgrad.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <int IN>
+__global__ __launch_bounds__(256) void k_wgrad_mfma(int64_t n, const float* __restrict__ G,
+                                                    const uint16_t* __restrict__ X, float* __restrict__ part,
+                                                    int off_w, int off_b) {
+    __shared__ float tile[4][32 * 33];
+    __shared__ float bsum[4][32];
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = blockIdx.x * per, b1 = min(n, b0 + per);
+    const int64_t wper = (b1 - b0 + 3) / 4;
+    const int64_t w0 = b0 + wave * wper, w1 = min(b1, w0 + wper);
+    const int a = lane % 32, half = lane / 32;
+    floatx16 acc = {};
+    float bs = 0.0f;
+    for (int64_t v0 = w0; v0 < w1; v0 += 2) {
+        const int64_t v = v0 + half;
+        const bool in = v < w1;
+        const int64_t vc = in ? v : w0;
+        const float g = in ? G[vc * 32 + a] : 0.0f;
+        float x;
+        if (a < IN) x = in ? bf2f(X[vc * IN + a]) : 0.0f;
+        else x = (a == IN && in) ? 1.0f : 0.0f;
+        bs += g;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(g, x, acc, 0, 0, 0);
+    }
+    // D[row][col], row = 8 (r / 4) + 4 (lane / 32) + r % 4, col = lane % 32
+#pragma unroll
+    for (int r = 0; r < 16; ++r) tile[wave][(8 * (r / 4) + 4 * half + (r % 4)) * 33 + a] = acc[r];
+    const float bo = __shfl_down(bs, 32, WAVE);
+    if (lane < 32) bsum[wave][lane] = bs + bo;
+    __syncthreads();
+    float* P = part + (int64_t)blockIdx.x * GNN_P;
+    for (int e = threadIdx.x; e < 32 * IN; e += blockDim.x) {
+        const int row = e / IN, col = e % IN;
+        P[off_w + e] = tile[0][row * 33 + col] + tile[1][row * 33 + col] + tile[2][row * 33 + col] +
+                       tile[3][row * 33 + col];
+    }
+    if (off_b >= 0 && threadIdx.x < 32) {
+        const int row = threadIdx.x;
+        P[off_b + row] = IN < 32 ? tile[0][row * 33 + IN] + tile[1][row * 33 + IN] + tile[2][row * 33 + IN] +
+                                       tile[3][row * 33 + IN]
+                                 : bsum[0][row] + bsum[1][row] + bsum[2][row] + bsum[3][row];
+    }
+}
+
 // sum of squares of a float vector into per-block partials
 __global__ void k_sumsq_f(int64_t n, const float* __restrict__ a, float* __restrict__ part) {
     __shared__ float red[BLOCK];
@@ -328,10 +382,10 @@ void launch_gnn_backward(hipStream_t s, int64_t n, const float* y, const GnnGrap
     k_bwd_hidden<<<gb, BLOCK, 0, s>>>(n, a.dz2, a.g2, At.ptr, At.col, At.val, a.h1, wbf, a.dz1);
     const int wb = GNN_WG_BLOCKS;
     k_wgrad<1, GNN_H><<<wb, BLOCK, 0, s>>>(n, a.dout, a.h2, partials, GNN_OFF_W3, GNN_OFF_B3);
-    k_wgrad<GNN_H, GNN_H><<<wb, 1024, 0, s>>>(n, a.dz2, a.h1, partials, GNN_OFF_W2S, GNN_OFF_B2);
-    k_wgrad<GNN_H, GNN_H><<<wb, 1024, 0, s>>>(n, a.dz2, a.m1, partials, GNN_OFF_W2N, -1);
-    k_wgrad<GNN_H, GNN_F><<<wb, 512, 0, s>>>(n, a.dz1, a.f, partials, GNN_OFF_W1S, GNN_OFF_B1);
-    k_wgrad<GNN_H, GNN_F><<<wb, 512, 0, s>>>(n, a.dz1, a.m0, partials, GNN_OFF_W1N, -1);
+    k_wgrad_mfma<GNN_H><<<wb, 256, 0, s>>>(n, a.dz2, a.h1, partials, GNN_OFF_W2S, GNN_OFF_B2);
+    k_wgrad_mfma<GNN_H><<<wb, 256, 0, s>>>(n, a.dz2, a.m1, partials, GNN_OFF_W2N, -1);
+    k_wgrad_mfma<GNN_F><<<wb, 256, 0, s>>>(n, a.dz1, a.f, partials, GNN_OFF_W1S, GNN_OFF_B1);
+    k_wgrad_mfma<GNN_F><<<wb, 256, 0, s>>>(n, a.dz1, a.m0, partials, GNN_OFF_W1N, -1);
     k_reduce_grad<<<(GNN_P + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(GNN_WG_BLOCKS, partials, grad, loss_part,
                                                                  (int)nb, loss);
 }
@@ -429,20 +483,35 @@ __global__ __launch_bounds__(BLOCK) void k_dh2(int64_t n, const int64_t* __restr
     dz2[id] = bf2f(h2[id]) > 0.0f ? s * bf2f(wbf[GNN_OFF_W3 + a]) : 0.0f;
 }
 
-// partials of d/dw3_a = sum_p G_p h2_ia h2_ja and d/db3 = sum_{diag} G_p
-__global__ void k_w3grad(int64_t nnz, const int32_t* __restrict__ row, const int32_t* __restrict__ col,
-                         const float* __restrict__ G, const uint16_t* __restrict__ h2, float* __restrict__ part) {
-    const int64_t per = (nnz + gridDim.x - 1) / gridDim.x;
-    const int64_t p0 = blockIdx.x * per, p1 = min(nnz, p0 + per);
-    float* P = part + (int64_t)blockIdx.x * GNN_P;
-    for (int a = threadIdx.x; a <= GNN_H; a += blockDim.x) {
-        float s = 0.0f;
-        for (int64_t p = p0; p < p1; ++p) {
-            const int64_t i = row[p], j = col[p];
-            if (a < GNN_H) s += G[p] * bf2f(h2[i * GNN_H + a]) * bf2f(h2[j * GNN_H + a]);
-            else if (i == j) s += G[p];
+// partials of d/dw3_a = sum_p G_p h2_ia h2_ja and d/db3 = sum_{diag} G_p, by
+// rows: block b takes a range of rows, 8 rows at a time (32 lanes per row,
+// lane a), then the 8 row slots are summed in LDS in a fixed order.
+__global__ __launch_bounds__(256) void k_w3grad(int64_t n, const int64_t* __restrict__ ptr,
+                                                const int32_t* __restrict__ col, const float* __restrict__ G,
+                                                const uint16_t* __restrict__ h2, float* __restrict__ part) {
+    __shared__ float red[8][GNN_H + 1];
+    const int a = threadIdx.x % GNN_H, slot = threadIdx.x / GNN_H;
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = blockIdx.x * per, i1 = min(n, i0 + per);
+    float s = 0.0f, sd = 0.0f;
+    for (int64_t i = i0 + slot; i < i1; i += 8) {
+        const float hi = bf2f(h2[i * GNN_H + a]);
+        float q = 0.0f;
+        for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p) {
+            const int32_t j = col[p];
+            q += G[p] * bf2f(h2[(int64_t)j * GNN_H + a]);
+            if (j == i) sd += G[p];
         }
-        P[a < GNN_H ? GNN_OFF_W3 + a : GNN_OFF_B3] = s;
+        s += hi * q;
+    }
+    red[slot][a] = s;
+    if (a == 0) red[slot][GNN_H] = sd;
+    __syncthreads();
+    float* P = part + (int64_t)blockIdx.x * GNN_P;
+    if (threadIdx.x <= GNN_H) {
+        float t = 0.0f;
+        for (int k = 0; k < 8; ++k) t += red[k][threadIdx.x];
+        P[threadIdx.x < GNN_H ? GNN_OFF_W3 + threadIdx.x : GNN_OFF_B3] = t;
     }
 }
 
@@ -503,13 +572,13 @@ void launch_stencil_backward(hipStream_t s, const StencilPattern& P, const GnnGr
     const unsigned gb = blocks_for(n * GNN_H);
     const int wb = GNN_WG_BLOCKS;
     k_dh2<<<gb, BLOCK, 0, s>>>(n, P.ptr, P.col, P.tpos, G, a.h2, wbf, a.dz2);
-    k_w3grad<<<wb, 64, 0, s>>>(P.nnz, P.row, P.col, G, a.h2, partials);
+    k_w3grad<<<wb, 256, 0, s>>>(n, P.ptr, P.col, G, a.h2, partials);
     k_bwd_g<<<gb, BLOCK, 0, s>>>(n, a.dz2, wbf, a.g2);
     k_bwd_hidden<<<gb, BLOCK, 0, s>>>(n, a.dz2, a.g2, At.ptr, At.col, At.val, a.h1, wbf, a.dz1);
-    k_wgrad<GNN_H, GNN_H><<<wb, 1024, 0, s>>>(n, a.dz2, a.h1, partials, GNN_OFF_W2S, GNN_OFF_B2);
-    k_wgrad<GNN_H, GNN_H><<<wb, 1024, 0, s>>>(n, a.dz2, a.m1, partials, GNN_OFF_W2N, -1);
-    k_wgrad<GNN_H, GNN_F><<<wb, 512, 0, s>>>(n, a.dz1, a.f, partials, GNN_OFF_W1S, GNN_OFF_B1);
-    k_wgrad<GNN_H, GNN_F><<<wb, 512, 0, s>>>(n, a.dz1, a.m0, partials, GNN_OFF_W1N, -1);
+    k_wgrad_mfma<GNN_H><<<wb, 256, 0, s>>>(n, a.dz2, a.h1, partials, GNN_OFF_W2S, GNN_OFF_B2);
+    k_wgrad_mfma<GNN_H><<<wb, 256, 0, s>>>(n, a.dz2, a.m1, partials, GNN_OFF_W2N, -1);
+    k_wgrad_mfma<GNN_F><<<wb, 256, 0, s>>>(n, a.dz1, a.f, partials, GNN_OFF_W1S, GNN_OFF_B1);
+    k_wgrad_mfma<GNN_F><<<wb, 256, 0, s>>>(n, a.dz1, a.m0, partials, GNN_OFF_W1N, -1);
     k_reduce_grad<<<(GNN_P + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(wb, partials, grad, nullptr, 0, nullptr);
 }
 
