@@ -93,9 +93,10 @@ __global__ __launch_bounds__(BLOCK) void k_amg_spmv(int64_t n, const int64_t* __
 }
 
 // The first two Chebyshev smoothing steps from z = 0 in one pass:
-// d0 = a0 D^-1 b (formed on the fly from b and D^-1 at the gathered
-// columns), r1 = b - A d0, d1 = c1 d0 + c2 D^-1 r1, z = d0 + d1; r1 and d1
-// are kept when more steps follow (write_rd).
+// d0 = a0 D^-1 b, r1 = b - A d0 = b - a0 (A D^-1) b (the column-scaled copy
+// As = A D^-1 of the level matrix, so one gather per entry),
+// d1 = c1 d0 + c2 D^-1 r1, z = d0 + d1; r1, d0 and d1 are kept when more
+// steps follow (write_rd).
 template <int G, typename T>
 __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t* __restrict__ ptr,
                                                        const int32_t* __restrict__ col,
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t*
             di[u] = dinv[i];
         }
         double s[RU];
-        rows_dot<G, T>(ptr, col, val, b, dinv, row, ok, lane, s);   // (A D^-1 b)_i
+        rows_dot<G, T>(ptr, col, val, b, nullptr, row, ok, lane, s);   // (A D^-1 b)_i with val = As
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < RU; ++u) {

@@ -63,11 +63,12 @@ int pow2_at_least(int n, int cap) {
 // Kernel classes of the optional per-launch profiler.
 enum KClass { K_SPMV_LAMBDA = 0, K_PCG_UPDATE, K_COMBINE_DOT, K_P_UPDATE, K_TRI_FWD_SUB,
               K_TRI_FWD_LVL, K_TRI_BWD_SUB, K_TRI_BWD_LVL, K_TRI_TOP, K_SPMV_CSR, K_IONIC, K_GNN, K_MISC,
-              K_CHEB, K_AMG_SMOOTH, K_AMG_SPMV, K_AMG_COARSE, K_NCLASS };
+              K_CHEB, K_AMG_SMOOTH, K_AMG_SPMV, K_AMG_TRANSFER, K_AMG_COARSE, K_NCLASS };
 const char* const kclass_name[K_NCLASS] = {"spmv_lambda", "pcg_update", "combine_dot", "p_update",
                                            "tri_fwd_sub", "tri_fwd_lvl", "tri_bwd_sub", "tri_bwd_lvl",
                                            "tri_top", "spmv_csr", "ionic_rhs", "gnn_infer", "misc",
-                                           "pk_chebyshev", "amg_smooth", "amg_spmv", "amg_coarse"};
+                                           "pk_chebyshev", "amg_smooth_l0", "amg_resid_l0", "amg_transfer_l0",
+                                           "amg_coarser"};
 
 // Per-launch HIP-event timing with the algorithmic bytes of each launch.
 struct Profiler {
@@ -282,6 +283,8 @@ struct AmgDev {
         int64_t n = 0;
         CsrDev A, P, R;
         float *A32 = nullptr, *P32 = nullptr, *R32 = nullptr;
+        double* As64 = nullptr;            // A D^-1 (columns scaled), for the fused smoother
+        float* As32 = nullptr;
         int gA = 4, gP = 4, gR = 4;        // lanes per row of the three products
         double* dinv = nullptr;
         ChebCoef cf;
@@ -329,8 +332,8 @@ struct AmgDev {
             for (CsrDev* m : {&L.A, &L.P, &L.R}) {
                 hipFree(m->ptr); hipFree(m->col); hipFree(m->val);
             }
-            for (float* v : {L.A32, L.P32, L.R32}) hipFree(v);
-            for (double* v : {L.dinv, L.b, L.out, L.x, L.r, L.d0, L.d1, L.xp, L.t}) hipFree(v);
+            for (float* v : {L.A32, L.P32, L.R32, L.As32}) hipFree(v);
+            for (double* v : {L.dinv, L.b, L.out, L.x, L.r, L.d0, L.d1, L.xp, L.t, L.As64}) hipFree(v);
         }
         lv.clear();
         hipFree(cinv);
@@ -375,6 +378,13 @@ bido_status upload_amg(const Amg& M, AmgDev& d) {
         HIP_OK(up32(h.A, &v.A32));
         HIP_OK(up32(h.P, &v.P32));
         HIP_OK(up32(h.R, &v.R32));
+        {
+            Csr as = h.A;
+            for (int64_t i = 0; i < as.n; ++i)
+                for (int64_t p = as.ptr[i]; p < as.ptr[i + 1]; ++p) as.val[p] *= h.dinv[as.col[p]];
+            HIP_OK(upload(&v.As64, as.val.data(), std::max<size_t>(as.val.size(), 1)));
+            HIP_OK(up32(as, &v.As32));
+        }
         v.gA = group_for(h.A);
         v.gP = group_for(h.P);
         v.gR = group_for(h.R);
@@ -634,21 +644,24 @@ void inner_solve(C* c, const FactorDev& f, const double* in, double* out) {
 // smoother from z = 0 (the recurrence of the Chebyshev P_K on the level's
 // interval of D^-1 A; the first two steps in one fused pass).
 template <typename T, typename C>
-void amg_smooth(C* c, const AmgDev& M, const AmgDev::Lev& L, const double* b, double* z) {
+void amg_smooth(C* c, const AmgDev& M, const AmgDev::Lev& L, const double* b, double* z, int cls) {
     hipStream_t s = c->stream;
     const int64_t n = L.n;
     const AmgMat<T> A = L.mat<T>(L.A, L.A32, L.gA);
+    AmgMat<T> As = A;                      // the column-scaled copy A D^-1
+    if constexpr (sizeof(T) == 4) As.val = L.As32;
+    else As.val = L.As64;
     const double Ab = (4.0 + sizeof(T)) * L.nnz_A + 8.0 * (n + 1);
     if (M.steps < 2) {
-        PROF(c, K_AMG_SMOOTH, 32.0 * n, launch_cheb_init(s, n, b, L.dinv, L.cf.inv_theta, L.d0, z));
+        PROF(c, cls, 32.0 * n, launch_cheb_init(s, n, b, L.dinv, L.cf.inv_theta, L.d0, z));
         return;
     }
-    PROF(c, K_AMG_SMOOTH, Ab + 8.0 * n * (M.steps > 2 ? 6 : 3),
-         launch_amg_smooth2<T>(s, A, L.dinv, b, L.cf.inv_theta, L.cf.c1[0], L.cf.c2[0], z, L.r, L.d0, L.d1,
+    PROF(c, cls, Ab + 8.0 * n * (M.steps > 2 ? 6 : 3),
+         launch_amg_smooth2<T>(s, As, L.dinv, b, L.cf.inv_theta, L.cf.c1[0], L.cf.c2[0], z, L.r, L.d0, L.d1,
                                M.steps > 2));
     double* d[2] = {L.d0, L.d1};
     for (int k = 2; k < M.steps; ++k)
-        PROF(c, K_AMG_SMOOTH, Ab + 56.0 * n,
+        PROF(c, cls, Ab + 56.0 * n,
              launch_amg_cheb<T>(s, A, L.dinv, L.r, d[(k - 1) & 1], d[k & 1], z, L.cf.c1[k - 1], L.cf.c2[k - 1]));
 }
 
@@ -669,14 +682,17 @@ void amg_vcycle_t(C* c, const AmgDev& M, size_t l, const double* b, double* out)
     const AmgMat<T> P = L.mat<T>(L.P, L.P32, L.gP);
     const AmgMat<T> R = L.mat<T>(L.R, L.R32, L.gR);
     const double Ab = w * L.nnz_A + vec, Pb = w * L.nnz_P + vec, Rb = w * L.nnz_R + 8.0 * Lc.n;
-    amg_smooth<T>(c, M, L, b, L.x);
-    PROF(c, K_AMG_SPMV, Ab + 3 * vec, launch_amg_spmv<T>(s, A, L.x, b, -1.0, L.r));          // r = b - A x
-    PROF(c, K_AMG_SPMV, Rb + vec + 8.0 * Lc.n, launch_amg_spmv<T>(s, R, L.r, nullptr, 1.0, Lc.b));
+    const bool fine = l == 0;      // profiler classes: the finest level apart, the coarser ones together
+    const int c_sm = fine ? K_AMG_SMOOTH : K_AMG_COARSE, c_re = fine ? K_AMG_SPMV : K_AMG_COARSE,
+              c_tr = fine ? K_AMG_TRANSFER : K_AMG_COARSE;
+    amg_smooth<T>(c, M, L, b, L.x, c_sm);
+    PROF(c, c_re, Ab + 3 * vec, launch_amg_spmv<T>(s, A, L.x, b, -1.0, L.r));                // r = b - A x
+    PROF(c, c_tr, Rb + vec + 8.0 * Lc.n, launch_amg_spmv<T>(s, R, L.r, nullptr, 1.0, Lc.b));
     amg_vcycle_t<T>(c, M, l + 1, Lc.b, Lc.out);
-    PROF(c, K_AMG_SPMV, Pb + 8.0 * Lc.n + 2 * vec, launch_amg_spmv<T>(s, P, Lc.out, L.x, 1.0, L.xp));  // xp = x + P e
-    PROF(c, K_AMG_SPMV, Ab + 3 * vec, launch_amg_spmv<T>(s, A, L.xp, b, -1.0, L.r));         // r = b - A xp
-    amg_smooth<T>(c, M, L, L.r, L.t);
-    PROF(c, K_AMG_SMOOTH, 3 * vec, launch_add2(s, L.n, L.xp, L.t, out));
+    PROF(c, c_tr, Pb + 8.0 * Lc.n + 2 * vec, launch_amg_spmv<T>(s, P, Lc.out, L.x, 1.0, L.xp));  // xp = x + P e
+    PROF(c, c_re, Ab + 3 * vec, launch_amg_spmv<T>(s, A, L.xp, b, -1.0, L.r));               // r = b - A xp
+    amg_smooth<T>(c, M, L, L.r, L.t, c_sm);
+    PROF(c, fine ? K_MISC : K_AMG_COARSE, 3 * vec, launch_add2(s, L.n, L.xp, L.t, out));
 }
 
 // The cycle with FP32 level values in mixed precision, FP64 otherwise.
