@@ -187,6 +187,9 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue,
                         const bido_params* params, void* stream,
                         bido_ctx** out);
 
+/* Frees the context.  A context still in a batch first leaves it (its own
+ * stream and vectors back); that batch then returns BIDO_ERR_STATE from
+ * bido_batch_run and must still be destroyed.                            */
 void bido_destroy(bido_ctx* ctx);
 
 bido_status bido_get_info(const bido_ctx* ctx, bido_info* info);
@@ -493,16 +496,27 @@ void bido_batch_destroy(bido_batch* b);
  * union (slice s at the sum of the earlier slices' N + N_H, u rows first),
  * so that each phase of the PCG iteration of Sec. 3.2 is one launch for all
  * slices: segmented vector kernels keep alpha, beta and r.z per slice, the
- * stopping test is per slice and a slice that has met it is frozen (alpha =
- * beta = 0) while the others iterate; the inner solves sweep the forest of
+ * stopping test is per slice and runs on the device at the end of every
+ * iteration (the next iteration's kernels read its flags), so the host
+ * waits once per chunk of iterations (one less than the previous step's
+ * count, then one at a time), not once per iteration; a slice that has met
+ * the test is frozen (alpha = beta = 0) while the others iterate; the inner
+ * solves sweep the forest of
  * all slices' elimination trees level by level, each tree with the top cut
  * of its own plan.  Steps 1 and 3 and the normalisation stay per slice.
- * Needs the plain preconditioner, one precision and one P_K choice
- * (bido_set_pk) for all slices, and refuses contexts already in a batch
- * (BIDO_ERR_STATE).  Set-up merges the
- * host factors and uploads a second copy of them (the contexts keep
- * theirs); results agree with the slices run alone up to rounding order.
- * The contexts' U/V work vectors alias the union while in the batch.     */
+ * Each slice runs the plain preconditioner or the learned stencil
+ * (BIDO_PRECOND_LEARNED with a trained stencil and the factored P_K: its
+ * factor of K_m + C takes K_m's place in the slice's tree; the union then
+ * takes the flexible direction update, as the slice alone does); the
+ * additive network form is refused.  Needs one precision, one P_K choice
+ * (bido_set_pk) and factored P_1 and K_m for all slices, and refuses
+ * contexts already in a batch (BIDO_ERR_STATE).  While in the batch a
+ * slice's preconditioner, precision and learned state are fixed
+ * (bido_set_precond, bido_learn_collect and bido_learn_train return
+ * BIDO_ERR_STATE).  Set-up merges the host factors and uploads a second
+ * copy of them (the contexts keep theirs); results agree with the slices
+ * run alone up to rounding order.  The contexts' U/V work vectors alias
+ * the union while in the batch.                                          */
 bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stream, bido_batch** out);
 /* Fused batch only: replay captured graphs of the PCG iterations (on != 0,
  * the default) or launch every kernel eagerly (BIDO_ERR_STATE for a batch
@@ -512,6 +526,13 @@ bido_status bido_batch_set_graphs(bido_batch* b, int on);
  * setup_seconds: host and upload time of bido_batch_create_fused.  Any
  * output may be NULL.                                                    */
 bido_status bido_batch_info(const bido_batch* b, int* fused, int64_t* n_union, double* setup_seconds);
+/* Fused batch counters since its creation: steps, PCG iterations launched
+ * (over all steps; the union iterates until its last slice stops), host
+ * waits inside the iterations, kernel launches of the captured iteration
+ * graphs (0 when graphs are off).  Any output may be NULL; BIDO_ERR_STATE
+ * for a batch of streams.                                                */
+bido_status bido_batch_counters(const bido_batch* b, int64_t* steps, int64_t* iterations, int64_t* host_waits,
+                                int64_t* kernels);
 
 /* Per-kernel profile: launches, summed event-timed duration [ms] and the
  * algorithmic bytes those launches must move (inputs read once, outputs

@@ -193,6 +193,7 @@ ABI = {
     "bido_batch_create_fused": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p,
                                                ctypes.POINTER(ctypes.c_void_p)]),
     "bido_batch_set_graphs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "bido_batch_counters": (ctypes.c_int, [ctypes.c_void_p, _c_i64_p, _c_i64_p, _c_i64_p, _c_i64_p]),
     "bido_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "bido_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -586,6 +587,13 @@ class Batch:
         f, n, t = ctypes.c_int(), ctypes.c_int64(), ctypes.c_double()
         _check(lib.bido_batch_info(self.b, ctypes.byref(f), ctypes.byref(n), ctypes.byref(t)))
         return {"fused": bool(f.value), "n_union": n.value, "setup_seconds": t.value}
+
+    def counters(self):
+        """Fused batches: steps, PCG iterations launched, host waits inside the
+        iterations, kernel launches of the captured iteration graphs."""
+        v = [ctypes.c_int64() for _ in range(4)]
+        _check(lib.bido_batch_counters(self.b, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("steps", "iterations", "host_waits", "kernels"), [x.value for x in v]))
 
     def run(self, states, n0, n_steps, check=True):
         """states: one (v, w, u) tuple of device tensors per solver.  Returns

@@ -9,6 +9,7 @@
 #include <algorithm>
 
 #include "launch.h"
+#include "rows.h"
 
 namespace bido {
 
@@ -16,6 +17,7 @@ namespace {
 
 constexpr int BLOCK = 256;
 constexpr int RU = 4;
+constexpr int ITER = 2;       // row rounds of RU rows per lane group and workgroup
 
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
@@ -72,15 +74,15 @@ __global__ __launch_bounds__(BLOCK) void k_amg_spmv(int64_t n, const int64_t* __
                                                     const double* __restrict__ x, const double* __restrict__ b,
                                                     double sign, double* __restrict__ y) {
     const int lane = threadIdx.x % G;
-    const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
-    const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
-    for (int64_t rb = gid; rb < n; rb += RU * ngroups) {
+    constexpr int GPB = BLOCK / G;     // lane groups per workgroup
+    const RowRange rr = block_rows(n);
+    for (int64_t rb = rr.r0 + threadIdx.x / G; rb < rr.r1; rb += RU * GPB) {
         int64_t row[RU];
         bool ok[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            row[u] = rb + u * ngroups;
-            ok[u] = row[u] < n;
+            row[u] = rb + u * GPB;
+            ok[u] = row[u] < rr.r1;
         }
         double s[RU];
         rows_dot<G, T>(ptr, col, val, x, nullptr, row, ok, lane, s);
@@ -106,16 +108,16 @@ __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t*
                                                        double* __restrict__ d0o, double* __restrict__ d1o,
                                                        int write_rd) {
     const int lane = threadIdx.x % G;
-    const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
-    const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
-    for (int64_t rb = gid; rb < n; rb += RU * ngroups) {
+    constexpr int GPB = BLOCK / G;     // lane groups per workgroup
+    const RowRange rr = block_rows(n);
+    for (int64_t rb = rr.r0 + threadIdx.x / G; rb < rr.r1; rb += RU * GPB) {
         int64_t row[RU];
         bool ok[RU];
         double bv[RU], di[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            row[u] = rb + u * ngroups;
-            ok[u] = row[u] < n;
+            row[u] = rb + u * GPB;
+            ok[u] = row[u] < rr.r1;
             const int64_t i = ok[u] ? row[u] : rb;
             bv[u] = b[i];
             di[u] = dinv[i];
@@ -148,16 +150,16 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cheb(int64_t n, const int64_t* __
                                                     const double* __restrict__ dp, double* __restrict__ dn,
                                                     double* __restrict__ z, double c1, double c2) {
     const int lane = threadIdx.x % G;
-    const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
-    const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
-    for (int64_t rb = gid; rb < n; rb += RU * ngroups) {
+    constexpr int GPB = BLOCK / G;     // lane groups per workgroup
+    const RowRange rr = block_rows(n);
+    for (int64_t rb = rr.r0 + threadIdx.x / G; rb < rr.r1; rb += RU * GPB) {
         int64_t row[RU];
         bool ok[RU];
         double rv[RU], dv[RU], di[RU], zv[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            row[u] = rb + u * ngroups;
-            ok[u] = row[u] < n;
+            row[u] = rb + u * GPB;
+            ok[u] = row[u] < rr.r1;
             const int64_t i = ok[u] ? row[u] : rb;
             rv[u] = r[i];
             dv[u] = dp[i];
@@ -180,10 +182,10 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cheb(int64_t n, const int64_t* __
     }
 }
 
+// workgroups of ITER rounds of RU rows per lane group
 unsigned grid_rows(int64_t n, int G) {
-    const int64_t groups = (n + RU - 1) / RU;
-    const int64_t blocks = (groups * G + BLOCK - 1) / BLOCK;
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, 8192));
+    const int64_t rows = (int64_t)ITER * RU * (BLOCK / G);
+    return (unsigned)std::max<int64_t>(1, (n + rows - 1) / rows);
 }
 
 }  // namespace
@@ -193,7 +195,8 @@ unsigned grid_rows(int64_t n, int G) {
         case 4: { constexpr int GG = 4; __VA_ARGS__; } break;    \
         case 8: { constexpr int GG = 8; __VA_ARGS__; } break;    \
         case 16: { constexpr int GG = 16; __VA_ARGS__; } break;  \
-        default: { constexpr int GG = 32; __VA_ARGS__; } break;  \
+        case 32: { constexpr int GG = 32; __VA_ARGS__; } break;  \
+        default: { constexpr int GG = 64; __VA_ARGS__; } break;  \
     }
 
 template <typename T>

@@ -318,10 +318,12 @@ struct AmgDev {
             auto mb = [&](int64_t nnz, int64_t rows) { return (4.0 + w) * nnz + 8.0 * (rows + 1); };
             const double A = mb(L.nnz_A, L.n), vec = 8.0 * L.n;
             const double nc_l = 8.0 * lv[l + 1].n;
-            // two smoothings (fused first two steps: A, b and D^-1 gathered, z, r1, d0, d1
-            // written; each further step A + 7 vectors), two residuals, restriction,
-            // prolongation, the final sum
-            const double sm = A + 6.0 * vec + (steps - 2) * (A + 7.0 * vec);
+            // two smoothings (the fused first two steps read A D^-1, b and D^-1 and write
+            // z, plus r1, d0 and d1 when more steps follow; each further step A + 7
+            // vectors), two residuals, restriction, prolongation, the final sum
+            const double sm = steps < 2    ? 4.0 * vec
+                              : steps == 2 ? A + 3.0 * vec
+                                           : A + 6.0 * vec + (steps - 2) * (A + 7.0 * vec);
             b += 2.0 * sm + 2.0 * (A + 3.0 * vec) + mb(L.nnz_R, lv[l + 1].n) + vec + nc_l +
                  mb(L.nnz_P, L.n) + nc_l + 2.0 * vec + 3.0 * vec;
         }
@@ -345,7 +347,7 @@ struct AmgDev {
 // lanes per row for a CSR product: enough lanes for the average row
 int group_for(const Csr& a) {
     const double avg = a.n > 0 ? (double)a.nnz() / (double)a.n : 0.0;
-    return avg <= 8 ? 4 : avg <= 20 ? 8 : avg <= 48 ? 16 : 32;
+    return avg <= 8 ? 4 : avg <= 20 ? 8 : avg <= 48 ? 16 : avg <= 96 ? 32 : 64;
 }
 
 bido_status upload_amg(const Amg& M, AmgDev& d) {
@@ -472,6 +474,7 @@ struct bido_ctx {
     double* sc_host = nullptr;   // pinned
     unsigned nb_rz = 0;          // partials of r.z written by the latest apply
     bool batched = false;        // owned by a bido_batch (runs on its stream)
+    bido_batch* batch = nullptr; // that batch
     // HIP graphs of one PCG iteration's launch sequence (preconditioner apply,
     // direction update, SpMV, PCG update, scalar copy): [0] the first
     // iteration, [1] and [2] the later ones by the slot of r.z they read
@@ -493,6 +496,7 @@ struct bido_ctx {
     Profiler prof;
     GnnState gnn;
     FactorDev pk_learned;             // factor of K_m + C (learned stencil)
+    std::unique_ptr<Factor> pk_learned_host;   // its host factor (a fused batch merges it)
     AmgDev amg1, amgk;                // multigrid P_1 / P_K (inner_p1 / inner_pk = AMG)
     AmgDev amgk_learned;              // multigrid of K_m + C (learned stencil with a multigrid P_K)
     int precond = BIDO_PRECOND_PLAIN;
@@ -682,7 +686,9 @@ void amg_vcycle_t(C* c, const AmgDev& M, size_t l, const double* b, double* out)
     const AmgMat<T> P = L.mat<T>(L.P, L.P32, L.gP);
     const AmgMat<T> R = L.mat<T>(L.R, L.R32, L.gR);
     const double Ab = w * L.nnz_A + vec, Pb = w * L.nnz_P + vec, Rb = w * L.nnz_R + 8.0 * Lc.n;
-    const bool fine = l == 0;      // profiler classes: the finest level apart, the coarser ones together
+    // profiler classes: the finest level by kernel (its smoother is one
+    // kernel on one matrix), the coarser levels together
+    const bool fine = l == 0;
     const int c_sm = fine ? K_AMG_SMOOTH : K_AMG_COARSE, c_re = fine ? K_AMG_SPMV : K_AMG_COARSE,
               c_tr = fine ? K_AMG_TRANSFER : K_AMG_COARSE;
     amg_smooth<T>(c, M, L, b, L.x, c_sm);
@@ -1362,6 +1368,14 @@ struct FusedBatch {
     double* sc = nullptr;               // r.z (2 slots of S), p.q (S), then FR_COUNT partial regions
     double* sc_host = nullptr;          // pinned
     uint8_t *done = nullptr, *done_host = nullptr;
+    // the stopping test on the device: per slice |Y|^2, tol, iteration cap,
+    // and the test's outputs (iterations, status, |r| / |Y|), copied back
+    // in one block (it_host points at the pinned copy)
+    double *yy = nullptr, *tol = nullptr, *rel = nullptr;
+    int *max_it = nullptr, *iters = nullptr, *status = nullptr;
+    void* back_host = nullptr;            // pinned: done, iters, status, rel
+    int last_iters = 0;                   // iterations of the latest step (first chunk of the next)
+    int64_t n_steps = 0, host_waits = 0, iterations = 0, graph_kernels[3] = {0, 0, 0}, kernels = 0;
     hipGraphExec_t gx[3] = {nullptr, nullptr, nullptr};
     double setup_seconds = 0.0;
     // P_K by Chebyshev-accelerated Jacobi on the union K_m (one step count
@@ -1380,7 +1394,12 @@ struct FusedBatch {
         for (int b = slices[s].b0; b < slices[s].b1; ++b) a += sc_host[region(k) + b];
         return a;
     }
-    bool flexible() const { return precision == BIDO_PREC_MIXED; }
+    // each slice's preconditioner at creation (plain or the learned
+    // stencil); the direction update is the flexible one in mixed precision
+    // or with a learned slice, as for the slice run alone
+    std::vector<int> precond;
+    bool learned = false;
+    bool flexible() const { return precision == BIDO_PREC_MIXED || learned; }
     void drop_graphs() {
         for (auto& g : gx)
             if (g) { hipGraphExecDestroy(g); g = nullptr; }
@@ -1398,6 +1417,8 @@ struct FusedBatch {
         for (double* b : {x, r, z, p, q, Y, tA, tB, tC, tD, r_old, sc, km_dinv, cheb, ch_r, ch_d[0], ch_d[1]})
             hipFree(b);
         hipFree(done);
+        for (void* b : {(void*)yy, (void*)tol, (void*)rel, (void*)max_it, (void*)iters, (void*)status}) hipFree(b);
+        if (back_host) hipHostFree(back_host);
         if (sc_host) hipHostFree(sc_host);
         if (done_host) hipHostFree(done_host);
         if (stream) hipStreamDestroy(stream);
@@ -1508,7 +1529,8 @@ void fused_tail(FusedBatch* F, int rho) {
     launch_seg_spmv(s, F->T, F->lam, F->spmv_group, 0, F->p, nullptr, F->q, F->part(FR_PQ), nullptr, F->done);
     launch_seg_pcg_update(s, F->T, F->x, F->r, F->flexible() ? F->r_old : nullptr, F->p, F->q, F->part(FR_PQ),
                           F->part(FR_RR), F->sc + (int64_t)rho * S, F->done, F->sc + 2 * (int64_t)S);
-    hipMemcpyAsync(F->sc_host, F->sc, F->region(FR_RR + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+    launch_seg_stop(s, S, F->T, F->part(FR_RR), F->sc, rho, F->yy, F->tol, F->max_it, F->done, F->iters, F->status,
+                    F->rel);
 }
 
 // variant 0: the first iteration (p = z, r.z into slot 0); 1 and 2: a later
@@ -1539,6 +1561,8 @@ bido_status fused_launch(FusedBatch* F, int variant) {
         fused_seq(F, variant);
         hipGraph_t g = nullptr;
         HIP_OK(hipStreamEndCapture(F->stream, &g));
+        size_t nodes = 0;
+        if (hipGraphGetNodes(g, nullptr, &nodes) == hipSuccess) F->graph_kernels[variant] = (int64_t)nodes;
         hipGraphExec_t x = nullptr;
         const hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
@@ -1580,42 +1604,75 @@ bido_status fused_pcg(FusedBatch* F, const std::vector<bido_ctx*>& ctx, std::vec
         F->done_host[i] = q.done ? 1 : 0;
         active += !q.done;
     }
-    int rho = 0;
-    bool first = true;
-    while (active > 0) {
-        HIP_OK(hipMemcpyAsync(F->done, F->done_host, S, hipMemcpyHostToDevice, s));
-        bido_status e;
-        if (first) {
-            e = fused_launch(F, 0);
-        } else {
-            e = fused_launch(F, rho == 0 ? 1 : 2);
-            rho = 1 - rho;
+    // the iterations run without the host: each captured iteration ends with
+    // the device stopping test; the host looks once per chunk (first chunk:
+    // one less than the previous step's count, then one at a time)
+    {
+        std::vector<double> yy(S), tl(S);
+        std::vector<int> mi(S);
+        for (int i = 0; i < S; ++i) {
+            yy[i] = sr[i].yy > 0.0 ? sr[i].yy : 1.0;
+            tl[i] = ctx[i]->params.tol;
+            mi[i] = ctx[i]->params.max_iter;
         }
-        if (e) return e;
-        first = false;
-        for (int i = 0; i < S; ++i) sr[i].it += !sr[i].done;
+        HIP_OK(hipMemcpyAsync(F->yy, yy.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(F->tol, tl.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(F->max_it, mi.data(), S * sizeof(int), hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(F->done, F->done_host, S, hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemsetAsync(F->iters, 0, S * sizeof(int), s));
+        HIP_OK(hipMemsetAsync(F->status, 0, S * sizeof(int), s));
+    }
+    uint8_t* bdone = (uint8_t*)F->back_host;
+    int* biters = (int*)((char*)F->back_host + 64 * (((int64_t)S + 63) / 64));
+    int* bstat = biters + S;
+    double* brel = (double*)((char*)F->back_host + 64 * (((int64_t)S + 63) / 64) + 8 * (((int64_t)2 * S * 4 + 7) / 8));
+    int rho = 0, launched = 0;
+    int chunk = std::max(1, F->last_iters - 1);
+    while (active > 0) {
+        for (int k = 0; k < chunk; ++k) {
+            bido_status e;
+            int variant = 0;
+            if (launched > 0) {
+                variant = rho == 0 ? 1 : 2;
+                rho = 1 - rho;
+            }
+            if ((e = fused_launch(F, variant))) return e;
+            F->kernels += F->graph_kernels[variant];
+            ++launched;
+        }
+        HIP_OK(hipMemcpyAsync(bdone, F->done, S, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(biters, F->iters, S * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(bstat, F->status, S * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(brel, F->rel, S * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
+        ++F->host_waits;
         active = 0;
         for (int i = 0; i < S; ++i) {
             SliceRun& q = sr[i];
             if (q.done) continue;
-            const double pq = F->sc_host[2 * (int64_t)S + i], rz = F->sc_host[(int64_t)rho * S + i];
-            q.rel = std::sqrt(F->host_sum(FR_RR, i) / q.yy);
-            if (!(pq > 0.0) || !(rz > 0.0) || !std::isfinite(q.rel)) {
+            q.it = biters[i];
+            q.rel = brel[i];
+            if (bdone[i]) {
                 q.done = true;
-                q.status = BIDO_ERR_NOT_SPD;
-                q.err = "CG breakdown (p.Ap = " + std::to_string(pq) + ", r.z = " + std::to_string(rz) + ")";
-            } else if (q.rel <= ctx[i]->params.tol) {
-                q.done = q.conv = true;
-            } else if (q.it >= ctx[i]->params.max_iter) {
-                q.done = true;
-                q.status = BIDO_ERR_NOT_CONVERGED;
-                q.err = "tolerance not reached within max_iter";
+                if (bstat[i] == 0) {
+                    q.conv = true;
+                } else if (bstat[i] == 1) {
+                    q.status = BIDO_ERR_NOT_SPD;
+                    q.err = "CG breakdown (p.Ap or r.z not positive)";
+                } else {
+                    q.status = BIDO_ERR_NOT_CONVERGED;
+                    q.err = "tolerance not reached within max_iter";
+                }
             }
-            F->done_host[i] = q.done ? 1 : 0;
             active += !q.done;
         }
+        chunk = 1;
     }
+    int need = 0;
+    for (int i = 0; i < S; ++i) need = std::max(need, sr[i].it);
+    F->last_iters = need;
+    F->iterations += launched;
+    ++F->n_steps;
     return BIDO_OK;
 }
 
@@ -1735,7 +1792,12 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     return BIDO_OK;
 }
 
-void bido_destroy(bido_ctx* ctx) { delete ctx; }
+void batch_detach(bido_ctx* c);
+// A context still in a batch leaves it first (the batch then refuses to run).
+void bido_destroy(bido_ctx* ctx) {
+    if (ctx && ctx->batch) batch_detach(ctx);
+    delete ctx;
+}
 
 // ---------------------------------------------------------------------------
 // Batched execution of independent slices: every context advances Steps 1-3
@@ -1753,24 +1815,37 @@ struct bido_batch {
     hipStream_t stream = nullptr;      // caller's stream
     std::unique_ptr<FusedBatch> fused; // fused batch (then no own streams)
     std::vector<double*> saved_x, saved_Y;
+    // give slot i's context back its own stream and vectors
+    void release_slot(size_t i) {
+        bido_ctx* c = ctx[i];
+        if (!c) return;
+        hipStreamSynchronize(c->stream);
+        c->stream = saved[i];
+        c->batched = false;
+        c->batch = nullptr;
+        c->drop_graphs();
+        if (i < saved_x.size()) {
+            c->x = saved_x[i];
+            c->Y = saved_Y[i];
+        }
+        ctx[i] = nullptr;
+    }
     ~bido_batch() {
         if (fused) fused->drop_graphs();
-        for (size_t i = 0; i < ctx.size(); ++i) {
-            if (fused) hipStreamSynchronize(ctx[i]->stream);
-            ctx[i]->stream = saved[i];
-            ctx[i]->batched = false;
-            ctx[i]->drop_graphs();
-            if (i < saved_x.size()) {
-                ctx[i]->x = saved_x[i];
-                ctx[i]->Y = saved_Y[i];
-            }
-        }
+        for (size_t i = 0; i < ctx.size(); ++i) release_slot(i);
         fused.reset();
         for (hipStream_t s : own) hipStreamDestroy(s);
         for (hipEvent_t e : done) hipEventDestroy(e);
         if (start) hipEventDestroy(start);
     }
 };
+
+void batch_detach(bido_ctx* c) {
+    bido_batch* b = c->batch;
+    if (b->fused) b->fused->drop_graphs();
+    for (size_t i = 0; i < b->ctx.size(); ++i)
+        if (b->ctx[i] == c) b->release_slot(i);
+}
 
 bido_status bido_batch_create(bido_ctx* const* ctxs, int n_ctx, int n_streams, void* stream,
                               bido_batch** out) {
@@ -1810,6 +1885,7 @@ bido_status bido_batch_create(bido_ctx* const* ctxs, int n_ctx, int n_streams, v
         b->saved.push_back(ctxs[i]->stream);
         ctxs[i]->stream = b->own[which[i]];
         ctxs[i]->batched = true;
+        ctxs[i]->batch = b.get();
         ctxs[i]->drop_graphs();
     }
     *out = b.release();
@@ -1824,8 +1900,14 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
         if (ctxs[i]->batched) return fail(BIDO_ERR_STATE, "context already in a batch");
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(BIDO_ERR_ARG, "context listed twice");
-        if (ctxs[i]->precond != BIDO_PRECOND_PLAIN || ctxs[i]->gnn.collecting)
-            return fail(BIDO_ERR_STATE, "a fused batch runs the plain preconditioner only");
+        // the learned stencil replaces K_m by K_m + C in the slice's P_K
+        // tree of the forest; the additive network form stays per context
+        const bool stencil = ctxs[i]->precond == BIDO_PRECOND_LEARNED && ctxs[i]->gnn.stencil_ready &&
+                             ctxs[i]->pk_learned_host &&
+                             ctxs[i]->pk_kind == BIDO_PK_CHOLESKY;
+        if ((ctxs[i]->precond != BIDO_PRECOND_PLAIN && !stencil) || ctxs[i]->gnn.collecting)
+            return fail(BIDO_ERR_STATE, "a fused batch runs the plain preconditioner or the learned stencil "
+                                        "(with the factored P_K)");
         if (ctxs[i]->pk_kind != ctxs[0]->pk_kind ||
             (ctxs[i]->pk_kind == BIDO_PK_CHEBYSHEV && ctxs[i]->cheb_steps != ctxs[0]->cheb_steps))
             return fail(BIDO_ERR_STATE, "a fused batch needs one P_K choice (kind, Chebyshev steps) for all slices");
@@ -1847,6 +1929,10 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
     F->S = S;
     F->precision = ctxs[0]->precision;
     F->spmv_group = ctxs[0]->spmv_group;
+    for (int i = 0; i < n_ctx; ++i) {
+        F->precond.push_back(ctxs[i]->precond);
+        F->learned = F->learned || ctxs[i]->precond == BIDO_PRECOND_LEARNED;
+    }
     int64_t n = 0;
     int big = 0;
     for (int i = 0; i < S; ++i) {
@@ -1928,8 +2014,11 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
         op.sub_total = sub_total;
         if ((e = build_factor_dev(m, want32, F->p1, nth, &op))) return e;
         m = Factor();
+        for (int i = 0; i < S; ++i)           // a learned slice brings its factor of K_m + C
+            if (ctxs[i]->precond == BIDO_PRECOND_LEARNED) fk[i] = ctxs[i]->pk_learned_host.get();
         merge_factors(fk, ov, n, m);
-        for (int i = 0; i < S; ++i) m.part_top_h[i] = ctxs[i]->pk.top_h;
+        for (int i = 0; i < S; ++i)
+            m.part_top_h[i] = ctxs[i]->precond == BIDO_PRECOND_LEARNED ? ctxs[i]->pk_learned.top_h : ctxs[i]->pk.top_h;
         op = ctxs[big]->pk.opts;
         op.top_h = -1;
         op.sub_h = -1;
@@ -1962,6 +2051,10 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
     HIP_OK(hipHostMalloc((void**)&F->sc_host, nsc * sizeof(double), hipHostMallocDefault));
     HIP_OK(hipMalloc((void**)&F->done, S));
     HIP_OK(hipHostMalloc((void**)&F->done_host, S, hipHostMallocDefault));
+    for (double** b : {&F->yy, &F->tol, &F->rel}) HIP_OK(hipMalloc((void**)b, S * sizeof(double)));
+    for (int** b : {&F->max_it, &F->iters, &F->status}) HIP_OK(hipMalloc((void**)b, S * sizeof(int)));
+    HIP_OK(hipHostMalloc(&F->back_host, 64 * (((int64_t)S + 63) / 64) + 8 * (((int64_t)2 * S * 4 + 7) / 8) + 8 * S,
+                         hipHostMallocDefault));
     for (FactorDev* f : {&F->p1, &F->pk}) {
         HIP_OK(poison_workspace(*f));
     }
@@ -1980,6 +2073,7 @@ bido_status bido_batch_create_fused(bido_ctx* const* ctxs, int n_ctx, void* stre
         c->x = F->x + F->off[i];
         c->Y = F->Y + F->off[i];
         c->batched = true;
+        c->batch = b.get();
         c->drop_graphs();
     }
     F->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -2001,6 +2095,18 @@ bido_status bido_batch_info(const bido_batch* b, int* fused, int64_t* n_union, d
     if (fused) *fused = b->fused ? 1 : 0;
     if (n_union) *n_union = b->fused ? b->fused->n : 0;
     if (setup_seconds) *setup_seconds = b->fused ? b->fused->setup_seconds : 0.0;
+    return BIDO_OK;
+}
+
+bido_status bido_batch_counters(const bido_batch* b, int64_t* steps, int64_t* iterations, int64_t* host_waits,
+                                int64_t* kernels) {
+    if (!b) return fail(BIDO_ERR_ARG, "null batch");
+    if (!b->fused) return fail(BIDO_ERR_STATE, "not a fused batch");
+    const FusedBatch* F = b->fused.get();
+    if (steps) *steps = F->n_steps;
+    if (iterations) *iterations = F->iterations;
+    if (host_waits) *host_waits = F->host_waits;
+    if (kernels) *kernels = F->kernels;
     return BIDO_OK;
 }
 
@@ -2034,7 +2140,7 @@ static bido_status fused_run(bido_batch* b, double* const* v, double* const* w, 
     const int S = (int)b->ctx.size();
     for (int i = 0; i < S; ++i) {
         const bido_ctx* c = b->ctx[i];
-        if (c->precond != BIDO_PRECOND_PLAIN || c->precision != F->precision || c->gnn.collecting)
+        if (c->precond != F->precond[i] || c->precision != F->precision || c->gnn.collecting)
             return fail(BIDO_ERR_STATE, "a slice of the fused batch changed its preconditioner or precision");
     }
     auto t0 = std::chrono::steady_clock::now();
@@ -2098,6 +2204,8 @@ bido_status bido_batch_run(bido_batch* b, double* const* v, double* const* w, do
                            int64_t n0, int64_t n_steps, bido_stats* per_ctx, bido_stats* total) {
     if (!b || !v || !w || !u || n_steps < 0) return fail(BIDO_ERR_ARG, "null argument");
     const int S = (int)b->ctx.size();
+    for (int i = 0; i < S; ++i)
+        if (!b->ctx[i]) return fail(BIDO_ERR_STATE, "a context of the batch was destroyed");
     for (int i = 0; i < S; ++i) {
         bido_ctx* c = b->ctx[i];
         if (!v[i] || !w[i] || !u[i]) return fail(BIDO_ERR_ARG, "null state pointer");
@@ -2380,6 +2488,7 @@ static bido_status set_dt_device(bido_ctx* c, bool refactor) {
     // the learned correction (samples, loss weight, stencil and its factor)
     // was fitted to K_m at the old step: set it up again from scratch
     if (c->pk_learned.nodes) c->pk_learned.release();
+    c->pk_learned_host.reset();
     c->amgk_learned.release();
     c->gnn.release();
     if (bido_status e = gnn_setup(c)) return e;
@@ -2477,6 +2586,8 @@ bido_status bido_set_precond(bido_ctx* c, int precond) {
         return fail(BIDO_ERR_ARG, "bad precond");
     if (precond == BIDO_PRECOND_LEARNED && !c->gnn.stencil_ready)
         return fail(BIDO_ERR_STATE, "the learned stencil has not been trained (or K_m + C was not SPD)");
+    if (c->batch && c->batch->fused && precond != c->precond)
+        return fail(BIDO_ERR_STATE, "context belongs to a fused batch (its preconditioner is fixed there)");
     c->precond = precond;
     return BIDO_OK;
 }
@@ -2484,6 +2595,7 @@ bido_status bido_set_precond(bido_ctx* c, int precond) {
 bido_status bido_learn_collect(bido_ctx* c, double* v, double* w, double* u, double dt, int64_t n0,
                                int64_t n_steps, int max_samples, bido_stats* st) {
     if (!c || max_samples < 1) return fail(BIDO_ERR_ARG, "bad argument");
+    if (c->batched) return fail(BIDO_ERR_STATE, "context is in a batch");
     GnnState& g = c->gnn;
     if (max_samples > g.max_samples) {
         hipStreamSynchronize(c->stream);
@@ -2690,12 +2802,15 @@ static bido_status train_stencil(bido_ctx* c, int epochs, int batch, float lr, u
             if (bido_status e = upload_amg(am, c->amgk_learned)) return e;
         }
     } else if ((spd = multifrontal(Kt, f, -1, c->params.n_threads, err))) {
+        set_top_compression(f, c->hs.pk.xyz.data(), c->hs.pk.dim, c->hs.pk.eps);
         c->pk_learned.release();
         bido_status e = build_factor_dev(f, true, c->pk_learned, c->params.n_threads);
         if (e) return e;
         for (FactorDev* fd : {&c->pk_learned}) {
             HIP_OK(poison_workspace(*fd));
         }
+        f.trim_top_cache(c->pk_learned.top_h);
+        c->pk_learned_host = std::make_unique<Factor>(std::move(f));
     }
     g.stencil_ready = spd;
     if (ts) {
@@ -2709,6 +2824,7 @@ static bido_status train_stencil(bido_ctx* c, int epochs, int batch, float lr, u
 bido_status bido_learn_train(bido_ctx* c, int kind, int epochs, int batch, float lr, uint64_t seed, int n_val,
                              bido_train_stats* ts) {
     if (!c || epochs < 0 || batch < 1 || !(lr > 0)) return fail(BIDO_ERR_ARG, "bad argument");
+    if (c->batched) return fail(BIDO_ERR_STATE, "context is in a batch");
     const int n_tr = c->gnn.n_samples - n_val;
     if (n_val < 0 || n_tr < 1) return fail(BIDO_ERR_STATE, "not enough collected samples");
     if (kind == BIDO_LEARN_STENCIL) return train_stencil(c, epochs, batch, lr, seed, n_val, ts);

@@ -265,6 +265,37 @@ __global__ __launch_bounds__(BB) void k_seg_p_update(SegTable T, const double* _
     for (int64_t i = bk.r0 + threadIdx.x; i < bk.r1; i += BB) p[i] = first ? z[i] : z[i] + beta * p[i];
 }
 
+// The stopping test of every slice after a PCG iteration, on the device (one
+// thread per slice): a slice still active counts the iteration, forms
+// |r| / |Y| from its |r|^2 partials (summed in block order, as the host did)
+// and stops at the tolerance, at a breakdown (p.Ap or r.z not positive, or a
+// non-finite residual) or at its iteration cap.  The next iteration's
+// kernels read the flags, so the host need not look between iterations.
+__global__ void k_seg_stop(int S, SegTable T, const double* __restrict__ part_rr, const double* __restrict__ sc,
+                           int rho_slot, const double* __restrict__ yy, const double* __restrict__ tol,
+                           const int* __restrict__ max_it, uint8_t* __restrict__ done, int* __restrict__ iters,
+                           int* __restrict__ status, double* __restrict__ rel) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S || done[s]) return;
+    double rr = 0.0;
+    for (int b = T.sl[s].b0; b < T.sl[s].b1; ++b) rr += part_rr[b];
+    const int it = iters[s] + 1;
+    iters[s] = it;
+    const double q = sqrt(rr / yy[s]);
+    const double pq = sc[2 * (int64_t)S + s], rz = sc[(int64_t)rho_slot * S + s];
+    rel[s] = q;
+    if (!(pq > 0.0) || !(rz > 0.0) || !isfinite(q)) {
+        done[s] = 1;
+        status[s] = 1;            // breakdown
+    } else if (q <= tol[s]) {
+        done[s] = 1;
+        status[s] = 0;            // converged
+    } else if (it >= max_it[s]) {
+        done[s] = 1;
+        status[s] = 2;            // iteration cap
+    }
+}
+
 }  // namespace
 
 void launch_seg_spmv(hipStream_t s, const SegTable& T, const CsrDev& A, int group, int mode, const double* x,
@@ -326,6 +357,14 @@ void launch_seg_p_update(hipStream_t s, const SegTable& T, const double* z, doub
                          const uint8_t* done) {
     if (T.nblocks <= 0) return;
     k_seg_p_update<<<T.nblocks, BB, 0, s>>>(T, z, p, part_rz, part_zro, first, flexible, rho_old, rho_new, done);
+}
+
+void launch_seg_stop(hipStream_t s, int S, const SegTable& T, const double* part_rr, const double* sc, int rho_slot,
+                     const double* yy, const double* tol, const int* max_it, uint8_t* done, int* iters, int* status,
+                     double* rel) {
+    if (S <= 0) return;
+    k_seg_stop<<<(S + BB - 1) / BB, BB, 0, s>>>(S, T, part_rr, sc, rho_slot, yy, tol, max_it, done, iters, status,
+                                                rel);
 }
 
 }  // namespace bido

@@ -263,18 +263,18 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lambda(int64_t n, const int64_t*
                                                        double* __restrict__ out, double* __restrict__ pp) {
     __shared__ double sh[BLOCK / WAVE];
     constexpr int RU = SPMV_RU;
+    constexpr int GPB = BLOCK / G;    // lane groups per workgroup
     const int lane = threadIdx.x % G;
-    const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
-    const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
+    const RowRange rr = block_rows(n);
     double acc0 = 0.0, acc1 = 0.0;
-    for (int64_t rb = gid; rb < n; rb += RU * ngroups) {
+    for (int64_t rb = rr.r0 + threadIdx.x / G; rb < rr.r1; rb += RU * GPB) {
         int64_t row[RU];
         bool ok[RU];
         double own[RU];   // x[row] (p.q) or y[row] (residual), loaded with the rows
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            row[u] = rb + u * ngroups;
-            ok[u] = row[u] < n;
+            row[u] = rb + u * GPB;
+            ok[u] = row[u] < rr.r1;
             own[u] = (MODE == 0 ? x : y)[ok[u] ? row[u] : rb];
         }
         double s[RU];
@@ -317,9 +317,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_csr(int64_t n, const int64_t* __
                                                     const double* __restrict__ b,
                                                     double* __restrict__ y) {
     const int lane = threadIdx.x % G;
-    const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
-    const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
-    for (int64_t r = gid; r < n; r += ngroups) {
+    const RowRange rr = block_rows(n);
+    for (int64_t r = rr.r0 + threadIdx.x / G; r < rr.r1; r += BLOCK / G) {
         double s = 0.0;
         for (int64_t p = ptr[r] + lane; p < ptr[r + 1]; p += G) s += val[p] * x[col[p]];
         s = lane_group_sum<G>(s);
@@ -354,17 +353,17 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_step(int64_t n, const int64_t* _
                                                      double* __restrict__ dn, double* __restrict__ z,
                                                      double c1, double c2, int last) {
     constexpr int RU = SPMV_RU;
+    constexpr int GPB = BLOCK / G;
     const int lane = threadIdx.x % G;
-    const int64_t gid = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / G;
-    const int64_t ngroups = (int64_t)gridDim.x * BLOCK / G;
-    for (int64_t rb = gid; rb < n; rb += RU * ngroups) {
+    const RowRange rr = block_rows(n);
+    for (int64_t rb = rr.r0 + threadIdx.x / G; rb < rr.r1; rb += RU * GPB) {
         int64_t row[RU];
         bool ok[RU];
         double rv[RU], dv[RU], di[RU], zv[RU];   // the rows' own entries, loaded with the rows
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            row[u] = rb + u * ngroups;
-            ok[u] = row[u] < n;
+            row[u] = rb + u * GPB;
+            ok[u] = row[u] < rr.r1;
             const int64_t i = ok[u] ? row[u] : rb;
             rv[u] = r_in[i];
             dv[u] = dp[i];

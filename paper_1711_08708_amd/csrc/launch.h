@@ -119,6 +119,11 @@ void launch_amg_smooth2(hipStream_t s, const AmgMat<T>& A, const double* dinv, c
 template <typename T>
 void launch_amg_cheb(hipStream_t s, const AmgMat<T>& A, const double* dinv, double* r, const double* dp, double* dn,
                      double* z, double c1, double c2);
+// per-slice stopping test of a fused batch after a PCG iteration (batch.hip):
+// status 0 converged, 1 breakdown, 2 iteration cap (set together with done)
+void launch_seg_stop(hipStream_t s, int S, const SegTable& T, const double* part_rr, const double* sc, int rho_slot,
+                     const double* yy, const double* tol, const int* max_it, uint8_t* done, int* iters, int* status,
+                     double* rel);
 // y = A x, A dense n x n row-major (the coarsest level of a multigrid V-cycle)
 void launch_dense_gemv(hipStream_t s, int64_t n, const double* A, const double* x, double* y);
 void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst);

@@ -12,6 +12,24 @@
 namespace bido {
 
 constexpr int SPMV_RU = 4;   // rows per group in flight
+constexpr unsigned XCDS = 8; // the dispatcher deals workgroups round robin over 8 XCDs
+
+// The rows [r0, r1) of this workgroup.  Each workgroup takes a contiguous
+// range, and the workgroups of one XCD take consecutive ranges (logical index
+// = the XCD's first index + its count of earlier workgroups), so an XCD sweeps
+// one contiguous part of the rows: the vector entries its rows gather stay in
+// its own L2 instead of being fetched by every XCD.
+struct RowRange {
+    int64_t r0, r1;
+};
+__device__ __forceinline__ RowRange block_rows(int64_t n) {
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned x = b % XCDS, q = nb / XCDS, rem = nb % XCDS;
+    const unsigned lb = x * q + (x < rem ? x : rem) + b / XCDS;
+    const int64_t rpb = (n + nb - 1) / nb;
+    const int64_t r0 = (int64_t)lb * rpb < n ? (int64_t)lb * rpb : n;
+    return {r0, r0 + rpb < n ? r0 + rpb : n};
+}
 
 template <int G>
 __device__ __forceinline__ double lane_group_sum(double v) {

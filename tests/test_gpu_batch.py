@@ -85,7 +85,15 @@ def test_batch_refusals(torch):
     a.set_precond(B.PRECOND_PLAIN)
     v, h, u = a.state()
     a.run(v, h, u, 0, 2)                     # usable on its own again
+    # a context destroyed while in a batch leaves it: the batch refuses to
+    # run, closes cleanly, and the other context works on its own
+    bt = B.Batch([a, b])
     a.close()
+    with pytest.raises(B.BidoError):
+        bt.run([states[0], states[1]], 0, 1)
+    bt.close()
+    v, h, u = b.state()
+    assert b.step(v, h, u, 0)["converged"] == 1
     b.close()
 
 
@@ -152,6 +160,14 @@ def test_fused_batch_matches_single_slices_and_oracle(torch, precision):
     before = [(st[0].cpu().numpy().copy(), st[1].cpu().numpy().copy()) for st in states]
     tot, per = batch.run(states, n_steps - 1, 1)
     its.append([p["iterations"] for p in per])
+    # the stopping test runs on the device: the host waits about twice per
+    # step (one less than the previous step's count, then one at a time),
+    # not once per iteration
+    cnt = batch.counters()
+    per_step = max(max(row) for row in its[1:])
+    print(precision, "counters", cnt, "iterations per step up to", per_step)
+    assert cnt["steps"] == n_steps
+    assert cnt["host_waits"] <= 3 * cnt["steps"] < cnt["iterations"]
     for k, (cfg, st) in enumerate(zip(cfgs, states)):
         v, h, u = [t.cpu().numpy() for t in st]
         fused_its = [row[k] for row in its]
@@ -170,6 +186,63 @@ def test_fused_batch_matches_single_slices_and_oracle(torch, precision):
     # the contexts work on their own again, on their own vectors
     v, h, u = solvers[0].state()
     assert solvers[0].step(v, h, u, 0)["converged"] == 1
+    for s in solvers:
+        s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_batch_learned_stencil(torch, precision):
+    """Slices with a trained stencil (P_K = (K_m + C)^-1, C on the pattern of
+    S_m) next to a plain slice in one fused batch: the learned slices bring
+    their factor of K_m + C into the merged forest and the union PCG takes the
+    flexible direction update, as each slice run alone does.  Iteration counts
+    within one of the slices run alone, states within 1e-9, the last step
+    against the FP64 oracle at 1e-8."""
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd, mpnn
+    prec = B.PREC_MIXED if precision == "mixed" else B.PREC_FP64
+    cfgs = _slices()[:3]
+    learned = [True, False, True]
+    # the network starts with a zero last layer (C = 0)
+    theta = mpnn.init_params(3) * np.concatenate([np.ones(mpnn.N_PARAMS - 33), np.zeros(33)])
+    solvers = [B.Solver(cfg, tol=1e-12, precision=prec) for cfg in cfgs]
+    for s, ln in zip(solvers, learned):
+        if not ln:
+            continue
+        s.set_weights(theta)
+        v, h, u = s.state()
+        info = s.learn_collect(v, h, u, 0, 8, max_samples=64)
+        ts = s.learn_train(kind=B.LEARN_STENCIL, epochs=10, batch=4, lr=2e-3, seed=1, n_val=2)
+        print("collected", info["samples"], "train", ts)
+        assert ts["spd"] == 1
+        s.set_precond(B.PRECOND_LEARNED)
+    n_steps = 8
+    ref = []
+    for s in solvers:
+        v, h, u = s.state()
+        its = [s.step(v, h, u, n)["iterations"] for n in range(n_steps)]
+        ref.append(((v.cpu().numpy(), h.cpu().numpy(), u.cpu().numpy()), its))
+    batch = B.Batch(solvers, fused=True)
+    states = [s.state() for s in solvers]
+    its = [[p["iterations"] for p in batch.run(states, n, 1)[1]] for n in range(n_steps - 1)]
+    before = [(st[0].cpu().numpy().copy(), st[1].cpu().numpy().copy()) for st in states]
+    its.append([p["iterations"] for p in batch.run(states, n_steps - 1, 1)[1]])
+    with pytest.raises(B.BidoError):
+        solvers[0].set_precond(B.PRECOND_PLAIN)     # fixed while batched
+    for k, (cfg, st) in enumerate(zip(cfgs, states)):
+        v, h, u = [t.cpu().numpy() for t in st]
+        fused_its = [row[k] for row in its]
+        print(f"  slice {k} learned={learned[k]}: iterations fused {fused_its} alone {ref[k][1]}")
+        assert all(abs(a - b) <= 1 for a, b in zip(fused_its, ref[k][1]))
+        for a, b in zip((v, h, u), ref[k][0]):
+            assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b), k
+        sy = bd.System(cfg)
+        Uo, Vo, _ = sy.step(before[k][0], before[k][1], n_steps - 1)
+        Uo = sy.to_global_u(Uo)
+        eu = np.linalg.norm(u - Uo) / np.linalg.norm(Uo)
+        ev = np.linalg.norm(v - Vo) / np.linalg.norm(Vo)
+        assert eu <= 1e-8 and ev <= 1e-8
+    batch.close()
     for s in solvers:
         s.close()
 
@@ -212,7 +285,7 @@ def test_fused_batch_refusals(torch):
         B.Batch([a, a], fused=True)          # listed twice
     a.set_precond(B.PRECOND_LEARNED_ADDITIVE)
     with pytest.raises(B.BidoError):
-        B.Batch([a, b], fused=True)          # plain preconditioner only
+        B.Batch([a, b], fused=True)          # no additive network correction
     a.set_precond(B.PRECOND_PLAIN)
     bt = B.Batch([a, b], fused=True)
     with pytest.raises(B.BidoError):
@@ -224,8 +297,16 @@ def test_fused_batch_refusals(torch):
     a.set_precision(B.PREC_FP64)
     v, h, u = a.state()
     a.run(v, h, u, 0, 2)
-    a.close()
+    # destroying a context of a fused batch gives it back its own vectors first
+    bt = B.Batch([a, b], fused=True)
+    st2 = [a.state(), b.state()]
     b.close()
+    with pytest.raises(B.BidoError):
+        bt.run(st2, 0, 1)
+    bt.close()
+    v, h, u = a.state()
+    assert a.step(v, h, u, 0)["converged"] == 1
+    a.close()
 
 
 def test_fused_batch_crank_nicolson(torch):
