@@ -29,7 +29,7 @@ __device__ __forceinline__ double group_sum(double v) {
 // s[u] = sum_j A[row_u, j] * f(j) for RU rows, f(j) = x[j] (or x[j] * w[j]
 // when w is given: the scaled input of a fused smoother step); entries
 // past a row's end reread entry 0 and are dropped by a select.
-template <int G, typename T>
+template <int G, int K, typename T>
 __device__ __forceinline__ void rows_dot(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                          const T* __restrict__ val, const double* __restrict__ x,
                                          const double* __restrict__ w, const int64_t (&row)[RU],
@@ -43,7 +43,7 @@ __device__ __forceinline__ void rows_dot(const int64_t* __restrict__ ptr, const 
         s[u] = 0.0;
     }
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int64_t q = pb[u] + lane + k * G;
@@ -57,7 +57,7 @@ __device__ __forceinline__ void rows_dot(const int64_t* __restrict__ ptr, const 
         }
 #pragma unroll
     for (int u = 0; u < RU; ++u)
-        for (int64_t q = pb[u] + lane + 2 * G; q < pe[u]; q += G) {
+        for (int64_t q = pb[u] + lane + K * G; q < pe[u]; q += G) {
             const int32_t c = col[q];
             double xv = x[c];
             if (w) xv *= w[c];
@@ -68,7 +68,7 @@ __device__ __forceinline__ void rows_dot(const int64_t* __restrict__ ptr, const 
 }
 
 // y = b + sign * A x  (b may be null)
-template <int G, typename T>
+template <int G, int K, typename T>
 __global__ __launch_bounds__(BLOCK) void k_amg_spmv(int64_t n, const int64_t* __restrict__ ptr,
                                                     const int32_t* __restrict__ col, const T* __restrict__ val,
                                                     const double* __restrict__ x, const double* __restrict__ b,
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_spmv(int64_t n, const int64_t* __
             ok[u] = row[u] < rr.r1;
         }
         double s[RU];
-        rows_dot<G, T>(ptr, col, val, x, nullptr, row, ok, lane, s);
+        rows_dot<G, K, T>(ptr, col, val, x, nullptr, row, ok, lane, s);
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < RU; ++u)
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_spmv(int64_t n, const int64_t* __
 // As = A D^-1 of the level matrix, so one gather per entry),
 // d1 = c1 d0 + c2 D^-1 r1, z = d0 + d1; r1, d0 and d1 are kept when more
 // steps follow (write_rd).
-template <int G, typename T>
+template <int G, int K, typename T>
 __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t* __restrict__ ptr,
                                                        const int32_t* __restrict__ col,
                                                        const T* __restrict__ val, const double* __restrict__ dinv,
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t*
             di[u] = dinv[i];
         }
         double s[RU];
-        rows_dot<G, T>(ptr, col, val, b, nullptr, row, ok, lane, s);   // (A D^-1 b)_i with val = As
+        rows_dot<G, K, T>(ptr, col, val, b, nullptr, row, ok, lane, s);   // (A D^-1 b)_i with val = As
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t*
 }
 
 // One more Chebyshev step: r -= A dp, dn = c1 dp + c2 D^-1 r, z += dn.
-template <int G, typename T>
+template <int G, int K, typename T>
 __global__ __launch_bounds__(BLOCK) void k_amg_cheb(int64_t n, const int64_t* __restrict__ ptr,
                                                     const int32_t* __restrict__ col, const T* __restrict__ val,
                                                     const double* __restrict__ dinv, double* r,
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cheb(int64_t n, const int64_t* __
             zv[u] = z[i];
         }
         double s[RU];
-        rows_dot<G, T>(ptr, col, val, dp, nullptr, row, ok, lane, s);
+        rows_dot<G, K, T>(ptr, col, val, dp, nullptr, row, ok, lane, s);
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
@@ -190,39 +190,58 @@ unsigned grid_rows(int64_t n, int G) {
 
 }  // namespace
 
-#define BIDO_G_SWITCH(G, ...)                                    \
-    switch (G) {                                                 \
-        case 4: { constexpr int GG = 4; __VA_ARGS__; } break;    \
-        case 8: { constexpr int GG = 8; __VA_ARGS__; } break;    \
-        case 16: { constexpr int GG = 16; __VA_ARGS__; } break;  \
-        case 32: { constexpr int GG = 32; __VA_ARGS__; } break;  \
-        default: { constexpr int GG = 64; __VA_ARGS__; } break;  \
+// lane groups of G lanes, K unrolled passes of G entries per row (the
+// average row length over G, 2 to 4; longer rows finish in a loop)
+#define BIDO_K_SWITCH(K, ...)                                   \
+    switch (K) {                                                \
+        case 2: { constexpr int KK = 2; __VA_ARGS__; } break;   \
+        case 3: { constexpr int KK = 3; __VA_ARGS__; } break;   \
+        default: { constexpr int KK = 4; __VA_ARGS__; } break;  \
     }
+#define BIDO_G_SWITCH(A, ...)                                                       \
+    {                                                                               \
+        const int kk = unroll_for(A);                                               \
+        switch (A.group) {                                                          \
+            case 4: { constexpr int GG = 4; BIDO_K_SWITCH(kk, __VA_ARGS__) } break;   \
+            case 8: { constexpr int GG = 8; BIDO_K_SWITCH(kk, __VA_ARGS__) } break;   \
+            case 16: { constexpr int GG = 16; BIDO_K_SWITCH(kk, __VA_ARGS__) } break; \
+            case 32: { constexpr int GG = 32; BIDO_K_SWITCH(kk, __VA_ARGS__) } break; \
+            default: { constexpr int GG = 64; BIDO_K_SWITCH(kk, __VA_ARGS__) } break; \
+        }                                                                           \
+    }
+
+template <typename T>
+int unroll_for(const AmgMat<T>& A) {
+    const int64_t per = A.group * (int64_t)std::max<int64_t>(A.n, 1);
+    const int64_t k = (A.nnz + per - 1) / per;
+    return (int)std::min<int64_t>(4, std::max<int64_t>(2, k));
+}
 
 template <typename T>
 void launch_amg_spmv(hipStream_t s, const AmgMat<T>& A, const double* x, const double* b, double sign, double* y) {
     if (A.n <= 0) return;
-    BIDO_G_SWITCH(A.group, k_amg_spmv<GG, T><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, b,
-                                                                                      sign, y))
+    BIDO_G_SWITCH(A, k_amg_spmv<GG, KK, T><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, b,
+                                                                                    sign, y))
 }
 
 template <typename T>
 void launch_amg_smooth2(hipStream_t s, const AmgMat<T>& A, const double* dinv, const double* b, double a0, double c1,
                         double c2, double* z, double* r1, double* d0, double* d1, bool write_rd) {
     if (A.n <= 0) return;
-    BIDO_G_SWITCH(A.group, k_amg_smooth2<GG, T><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
-                               A.n, A.ptr, A.col, A.val, dinv, b, a0, c1, c2, z, r1, d0, d1, write_rd ? 1 : 0))
+    BIDO_G_SWITCH(A, k_amg_smooth2<GG, KK, T><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
+                         A.n, A.ptr, A.col, A.val, dinv, b, a0, c1, c2, z, r1, d0, d1, write_rd ? 1 : 0))
 }
 
 template <typename T>
 void launch_amg_cheb(hipStream_t s, const AmgMat<T>& A, const double* dinv, double* r, const double* dp, double* dn,
                      double* z, double c1, double c2) {
     if (A.n <= 0) return;
-    BIDO_G_SWITCH(A.group, k_amg_cheb<GG, T><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, dinv, r,
-                                                                                      dp, dn, z, c1, c2))
+    BIDO_G_SWITCH(A, k_amg_cheb<GG, KK, T><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, dinv, r,
+                                                                                    dp, dn, z, c1, c2))
 }
 
 #undef BIDO_G_SWITCH
+#undef BIDO_K_SWITCH
 
 #define BIDO_INST(T)                                                                                              \
     template void launch_amg_spmv<T>(hipStream_t, const AmgMat<T>&, const double*, const double*, double, double*); \
