@@ -154,7 +154,11 @@ typedef struct {
 typedef struct {
     int64_t n_nodes, n_heart, n_elems;
     int64_t nnz_lambda;          /* stored entries of Lambda                  */
-    int64_t bytes_lambda;        /* bytes read by one Lambda product          */
+    int64_t bytes_lambda;        /* bytes one Lambda product moves: the blocked
+                                    form (one column and the S_1, S_i values
+                                    per position, 20 bytes) when the heart is
+                                    the whole mesh, else the CSR (12 bytes per
+                                    stored entry)                             */
     int64_t bytes_p1, bytes_pk;  /* bytes of the P_1 / P_K factors as stored
                                     (the active precision); for a multigrid
                                     block, the bytes one V-cycle reads and

@@ -103,6 +103,19 @@ bido_status bido_host_factor_emulate(const bido_host* h, int which, const double
 bido_status bido_host_factor_plan(const bido_host* h, int which, int* hc, int* n_sub, int* n_levels,
                                   int64_t* n_fwd_items, int64_t* n_bwd_items, int64_t* n_bwd_split);
 
+/* Lambda in blocked form (Sec. 3.2 system with Pi = I: the heart is the
+ * whole mesh and u and v share one internal order).  Row k of the u rows
+ * and row k of the v rows share one position list: columns col[ptr[k] ..
+ * ptr[k+1]) with the value pairs val[2q] = S_1[k, c], val[2q+1] =
+ * S_i[k, c], and gm[k] = gamma m_k, so that
+ *   (Lambda x)_u[k] = sum S_1 x_u[c] + S_i x_v[c],
+ *   (Lambda x)_v[k] = sum S_i (x_u[c] + x_v[c]) + gm[k] x_v[k].
+ * The device's Lambda product reads this form when it exists.  Arrays are
+ * owned by the set-up.  BIDO_ERR_STATE when there is none (torso rows, or
+ * the two orders differ).                                                */
+bido_status bido_host_lambda_blocked(const bido_host* h, int64_t* n, int64_t* npos, const int64_t** ptr,
+                                     const int32_t** col, const double** val, const double** gm);
+
 /* Multigrid hierarchy of a block set up with inner_p1 / inner_pk = AMG
  * (which = BIDO_FACTOR_P1 / BIDO_FACTOR_PK; BIDO_ERR_STATE if it has none).
  * info: levels, size of the coarsest level, operator complexity (sum of the

@@ -230,6 +230,9 @@ ABI = {
     "bido_host_set_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Plan)]),
     "bido_host_amg_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _c_i64_p,
                                           _c_double_p, _c_double_p, ctypes.POINTER(ctypes.c_int)]),
+    "bido_host_lambda_blocked": (ctypes.c_int, [ctypes.c_void_p, _c_i64_p, _c_i64_p, ctypes.POINTER(_c_i64_p),
+                                                ctypes.POINTER(_c_i32_p), ctypes.POINTER(_c_double_p),
+                                                ctypes.POINTER(_c_double_p)]),
     "bido_host_amg_level": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_i64_p,
                                            _c_i64_p, ctypes.POINTER(_c_i64_p), ctypes.POINTER(_c_i32_p),
                                            ctypes.POINTER(_c_double_p)]),
@@ -739,6 +742,21 @@ class HostSetup:
                                       ctypes.byref(sec), ctypes.byref(st)), host=True)
         return dict(levels=lv.value, n_coarse=nc.value, op_complexity=oc.value, seconds=sec.value,
                     smooth_steps=st.value)
+
+    def lambda_blocked(self):
+        """dict(ptr, col, val (n_pos x 2: S_1, S_i), gm) of Lambda's blocked
+        form (copies), or None when it has none."""
+        n, npos = ctypes.c_int64(), ctypes.c_int64()
+        p, c, v, g = _c_i64_p(), _c_i32_p(), _c_double_p(), _c_double_p()
+        code = lib.bido_host_lambda_blocked(self.h, ctypes.byref(n), ctypes.byref(npos), ctypes.byref(p),
+                                            ctypes.byref(c), ctypes.byref(v), ctypes.byref(g))
+        if code == -7:                      # BIDO_ERR_STATE: no blocked form
+            return None
+        _check(code, host=True)
+        nn, m = n.value, npos.value
+        return dict(ptr=np.ctypeslib.as_array(p, (nn + 1,)).copy(), col=np.ctypeslib.as_array(c, (m,)).copy(),
+                    val=np.ctypeslib.as_array(v, (2 * m,)).copy().reshape(m, 2),
+                    gm=np.ctypeslib.as_array(g, (nn,)).copy())
 
     def amg_level(self, which, level):
         """dict(A=scipy CSR, P=scipy CSR or None, dinv, lo, hi) of one level (copies)."""

@@ -462,6 +462,24 @@ struct GnnState {
 
 }  // namespace
 
+void release_lam_blk(LamBlk& b) {
+    hipFree(b.ptr); hipFree(b.col); hipFree(b.val); hipFree(b.gm);
+    b = LamBlk();
+}
+
+bido_status upload_lam_blk(const HostSetup& hs, LamBlk& b) {
+    release_lam_blk(b);
+    const LamBlocked& h = hs.lamb;
+    if (h.n == 0) return BIDO_OK;
+    HIP_OK(upload(&b.ptr, h.ptr.data(), h.ptr.size()));
+    HIP_OK(upload(&b.col, h.col.data(), h.col.size()));
+    HIP_OK(upload(&b.val, h.val.data(), h.val.size()));
+    HIP_OK(upload(&b.gm, h.gm.data(), h.gm.size()));
+    b.npos = (int64_t)h.col.size();
+    b.n = h.n;
+    return BIDO_OK;
+}
+
 struct bido_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -502,6 +520,7 @@ struct bido_ctx {
     FactorDev pk_learned;             // factor of K_m + C (learned stencil)
     std::unique_ptr<Factor> pk_learned_host;   // its host factor (a fused batch merges it)
     AmgDev amg1, amgk;                // multigrid P_1 / P_K (inner_p1 / inner_pk = AMG)
+    LamBlk lamb;                      // blocked Lambda (heart = whole mesh, one order)
     AmgDev amgk_learned;              // multigrid of K_m + C (learned stencil with a multigrid P_K)
     int precond = BIDO_PRECOND_PLAIN;
     int fallbacks = 0;
@@ -546,6 +565,7 @@ struct bido_ctx {
         gnn.release();
         rec.release();
         CsrHostView::release(lam);
+        release_lam_blk(lamb);
         CsrHostView::release(avu);
         CsrHostView::release(auv);
         CsrHostView::release(km);
@@ -609,6 +629,11 @@ bido_status profile_aggregate(Profiler& P, bido_kprof* out, int cap, int* n) {
 
 double csr_bytes(const CsrDev& a, int64_t ncols_read) {
     return 12.0 * a.nnz + 8.0 * (a.n + 1) + 8.0 * ncols_read + 8.0 * a.n;
+}
+// blocked Lambda product: positions (4 + 16 bytes), row pointers, gm, x (u
+// and v), the output (u and v), and y in mode 1
+double blk_bytes(const LamBlk& b, int mode) {
+    return 20.0 * b.npos + 8.0 * (b.n + 1) + 8.0 * b.n + 32.0 * b.n + (mode == 1 ? 16.0 * b.n : 0.0);
 }
 
 template <typename T> const T* top_inv(const FactorDev& f);
@@ -872,8 +897,12 @@ void pcg_tail(bido_ctx* c, PcgRun& ps) {
     hipStream_t s = c->stream;
     const int64_t n = c->n2;
     unsigned nb = 0;
-    PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n),
-         nb = launch_spmv_lambda(s, c->lam, c->spmv_group, 0, c->p, nullptr, c->q, c->sc));
+    if (c->lamb.on())
+        PROF(c, K_SPMV_LAMBDA, blk_bytes(c->lamb, 0),
+             nb = launch_spmv_lam_blk(s, c->lamb, c->spmv_group, 0, c->p, nullptr, c->q, c->sc));
+    else
+        PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n),
+             nb = launch_spmv_lambda(s, c->lam, c->spmv_group, 0, c->p, nullptr, c->q, c->sc));
     PROF(c, K_PCG_UPDATE, (ps.r_old ? 56.0 : 48.0) * n,
          ps.nb = launch_pcg_update(s, n, c->x, c->r, ps.r_old, c->p, c->q, c->sc, nb, ps.rho));
     copy_scalars_async(c, PP_RR + 1);
@@ -888,8 +917,12 @@ void pcg_start(bido_ctx* c, PcgRun& ps, double tol) {
     ps.flexible = c->precision == BIDO_PREC_MIXED || ps.learned || ps.stencil;
     ps.r_old = ps.flexible ? c->r_old : nullptr;
     const int64_t n = c->n2;
-    PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n) + 8.0 * n,
-         ps.nb = launch_spmv_lambda(c->stream, c->lam, c->spmv_group, 1, c->x, c->Y, c->r, c->sc));
+    if (c->lamb.on())
+        PROF(c, K_SPMV_LAMBDA, blk_bytes(c->lamb, 1),
+             ps.nb = launch_spmv_lam_blk(c->stream, c->lamb, c->spmv_group, 1, c->x, c->Y, c->r, c->sc));
+    else
+        PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n) + 8.0 * n,
+             ps.nb = launch_spmv_lambda(c->stream, c->lam, c->spmv_group, 1, c->x, c->Y, c->r, c->sc));
     copy_scalars_async(c, PP_YY + 1);
 }
 
@@ -1740,6 +1773,7 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     c->heart_ids = hs.A.heart;
     bido_status e;
     if ((e = CsrHostView::up(hs.lam, c->lam))) return e;
+    if ((e = upload_lam_blk(hs, c->lamb))) return e;
     if ((e = CsrHostView::up(hs.avu, c->avu))) return e;
     if ((e = CsrHostView::up(hs.auv, c->auv))) return e;
     if (hs.p1_factored) {
@@ -2292,7 +2326,9 @@ bido_status bido_get_info(const bido_ctx* c, bido_info* info) {
     info->n_elems = 0;
     info->nnz_lambda = c->lam.nnz;
     // one Lambda product: values + columns + row pointers + x read + y write
-    info->bytes_lambda = c->lam.nnz * 12 + (c->n2 + 1) * 8 + c->n2 * 16;
+    // (the blocked form when there is one)
+    info->bytes_lambda = c->lamb.on() ? (int64_t)blk_bytes(c->lamb, 0)
+                                      : c->lam.nnz * 12 + (c->n2 + 1) * 8 + c->n2 * 16;
     const int64_t w = c->precision == BIDO_PREC_MIXED ? 4 : 8;
     info->bytes_p1 = c->p1.panel_entries * w + c->p1.meta_bytes;
     info->bytes_pk = c->pk.panel_entries * w + c->pk.meta_bytes;
@@ -2466,6 +2502,8 @@ static bido_status set_dt_device(bido_ctx* c, bool refactor) {
     // Lambda: only its v-v diagonal changed, but the values go up whole
     HIP_OK(hipMemcpy(c->lam.val, c->hs.lam.val.data(), c->hs.lam.val.size() * sizeof(double),
                      hipMemcpyHostToDevice));
+    if (c->lamb.on())
+        if (bido_status e = upload_lam_blk(c->hs, c->lamb)) return e;
     if (refactor && c->pk_kind == BIDO_PK_AMG) {
         if (bido_status e = upload_amg(c->hs.amgk, c->amgk)) return e;
     } else if (refactor) {

@@ -224,6 +224,20 @@ bido_status bido_host_amg_info(const bido_host* h, int which, int* levels, int64
     return BIDO_OK;
 }
 
+bido_status bido_host_lambda_blocked(const bido_host* h, int64_t* n, int64_t* npos, const int64_t** ptr,
+                                     const int32_t** col, const double** val, const double** gm) {
+    if (!h || !n || !npos || !ptr || !col || !val || !gm) return hfail(BIDO_ERR_ARG, "null argument");
+    const bido::LamBlocked& b = h->hs.lamb;
+    if (b.n == 0) return hfail(BIDO_ERR_STATE, "no blocked form of Lambda (torso rows or two orders)");
+    *n = b.n;
+    *npos = (int64_t)b.col.size();
+    *ptr = b.ptr.data();
+    *col = b.col.data();
+    *val = b.val.data();
+    *gm = b.gm.data();
+    return BIDO_OK;
+}
+
 bido_status bido_host_amg_level(const bido_host* h, int which, int level, int what, int64_t* n, int64_t* nnz,
                                 const int64_t** ptr, const int32_t** col, const double** val) {
     if (!h || !n || !nnz || !ptr || !col || !val) return hfail(BIDO_ERR_ARG, "null argument");

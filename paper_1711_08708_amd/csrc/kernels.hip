@@ -307,6 +307,101 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lambda(int64_t n, const int64_t*
     }
 }
 
+// The same products on the blocked form of Lambda (Pi = I, one order for u
+// and v): row k gives the u output k and the v output N + k from one pass
+// over its positions (column, {S_1, S_i}), gathering x_u and x_v at each
+// column; partials as in k_spmv_lambda.
+template <int G, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_spmv_lam_blk(int64_t n, const int64_t* __restrict__ ptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const double2* __restrict__ val,
+                                                        const double* __restrict__ gm,
+                                                        const double* __restrict__ x,
+                                                        const double* __restrict__ y,
+                                                        double* __restrict__ out, double* __restrict__ pp) {
+    __shared__ double sh[BLOCK / WAVE];
+    constexpr int RU = SPMV_RU;
+    constexpr int GPB = BLOCK / G;
+    const int lane = threadIdx.x % G;
+    const double* __restrict__ xv = x + n;
+    const RowRange rr = block_rows(n);
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int64_t rb = rr.r0 + threadIdx.x / G; rb < rr.r1; rb += RU * GPB) {
+        int64_t row[RU], pb[RU], pe[RU];
+        bool ok[RU];
+        double su[RU], sv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            row[u] = rb + u * GPB;
+            ok[u] = row[u] < rr.r1;
+            const int64_t r = ok[u] ? row[u] : rb;
+            pb[u] = ptr[r];
+            pe[u] = ptr[r + 1];
+            su[u] = 0.0;
+            sv[u] = 0.0;
+        }
+        // two unconditional passes (an entry past the row's end rereads
+        // position 0 and is dropped by a select), then the rest of the row
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int64_t q = pb[u] + lane + k * G;
+                const bool in = q < pe[u];
+                const int64_t qc = in ? q : 0;
+                const int32_t c = col[qc];
+                const double2 w = val[qc];
+                const double a = x[c], b = xv[c];
+                su[u] += in ? w.x * a + w.y * b : 0.0;
+                sv[u] += in ? w.y * (a + b) : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            for (int64_t q = pb[u] + lane + 2 * G; q < pe[u]; q += G) {
+                const int32_t c = col[q];
+                const double2 w = val[q];
+                const double a = x[c], b = xv[c];
+                su[u] += w.x * a + w.y * b;
+                sv[u] += w.y * (a + b);
+            }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            su[u] = lane_group_sum<G>(su[u]);
+            sv[u] = lane_group_sum<G>(sv[u]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (!ok[u]) continue;
+                const int64_t k = row[u];
+                const double yu = su[u], yv = sv[u] + gm[k] * xv[k];
+                if (MODE == 0) {
+                    out[k] = yu;
+                    out[n + k] = yv;
+                    acc0 += yu * x[k] + yv * xv[k];
+                } else {
+                    const double bu = y[k], bv = y[n + k];
+                    const double ru = bu - yu, rv = bv - yv;
+                    out[k] = ru;
+                    out[n + k] = rv;
+                    acc0 += ru * ru + rv * rv;
+                    acc1 += bu * bu + bv * bv;
+                }
+            }
+        }
+    }
+    acc0 = block_sum(acc0, sh);
+    if (MODE == 0) {
+        if (threadIdx.x == 0) pp[pp_offset(PP_PQ) + blockIdx.x] = acc0;
+    } else {
+        acc1 = block_sum(acc1, sh);
+        if (threadIdx.x == 0) {
+            pp[pp_offset(PP_RR) + blockIdx.x] = acc0;
+            pp[pp_offset(PP_YY) + blockIdx.x] = acc1;
+        }
+    }
+}
+
 // y = b - A x  (b may be null: y = A x), rows of a CSR block (one row per
 // group at a time: Pi^T S_i has mostly empty rows, the torso vertices)
 template <int G>
@@ -1301,6 +1396,23 @@ unsigned launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode,
     }
     BIDO_SPMV_CASE(4) BIDO_SPMV_CASE(8) BIDO_SPMV_CASE(16) BIDO_SPMV_CASE(32)
 #undef BIDO_SPMV_CASE
+    return 0;
+}
+
+unsigned launch_spmv_lam_blk(hipStream_t s, const LamBlk& A, int group, int mode, const double* x, const double* y,
+                             double* out, double* pp) {
+    const unsigned g = grid_for(A.n * group, BLOCK * 2, PP_MAX);
+    const double2* v = reinterpret_cast<const double2*>(A.val);
+#define BIDO_BLK_CASE(G)                                                                              \
+    if (group == G) {                                                                                 \
+        if (mode == 0)                                                                                \
+            k_spmv_lam_blk<G, 0><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, v, A.gm, x, y, out, pp);      \
+        else                                                                                          \
+            k_spmv_lam_blk<G, 1><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, v, A.gm, x, y, out, pp);      \
+        return g;                                                                                     \
+    }
+    BIDO_BLK_CASE(4) BIDO_BLK_CASE(8) BIDO_BLK_CASE(16) BIDO_BLK_CASE(32)
+#undef BIDO_BLK_CASE
     return 0;
 }
 

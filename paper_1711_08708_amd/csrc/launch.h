@@ -154,6 +154,24 @@ void launch_ionic(hipStream_t s, int64_t nh, const double* v, double* h, const d
                   double stim_on, const double* mh, const int64_t* pos, double* y2, double* x2,
                   const double* sub, const IonicConst& c);
 // Each returns its grid size: the number of block partials it wrote.
+// Lambda in blocked form when the heart is the whole mesh and u and v share
+// one internal order (Pi = I): per row k one position list (column c,
+// values {S_1[k,c], S_i[k,c]} interleaved) and gm[k] = gamma m_k, so that
+//   (Lambda x)_u[k] = sum S_1 x_u[c] + S_i x_v[c]
+//   (Lambda x)_v[k] = sum S_i (x_u[c] + x_v[c]) + gm[k] x_v[k]
+// read 20 bytes per position instead of 48 for the four CSR blocks.
+struct LamBlk {
+    int64_t n = 0, npos = 0;           // rows (N = N_H) and positions
+    int64_t* ptr = nullptr;             // n + 1
+    int32_t* col = nullptr;             // npos
+    double* val = nullptr;              // 2 npos: S_1, S_i per position
+    double* gm = nullptr;               // n
+    bool on() const { return n > 0; }
+};
+// the Lambda product on the blocked form (modes and partials of
+// launch_spmv_lambda); returns the number of partials
+unsigned launch_spmv_lam_blk(hipStream_t s, const LamBlk& A, int group, int mode, const double* x, const double* y,
+                             double* out, double* pp);
 unsigned launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode, const double* x,
                             const double* y, double* out, double* pp);
 void launch_spmv_csr(hipStream_t s, const CsrDev& A, int group, const double* x, const double* b,

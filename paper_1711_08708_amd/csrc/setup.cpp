@@ -298,6 +298,7 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
     hs.stim_n1 = std::llround(tissue->stim_t1 / P.dt);
     hs.stim_t0 = tissue->stim_t0;
     hs.stim_t1 = tissue->stim_t1;
+    build_lam_blocked(hs, hs.lamb);   // (none when the heart is not the whole mesh)
     hs.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return true;
 }
@@ -305,6 +306,69 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
 }  // namespace bido
 
 namespace bido {
+
+// The blocked form of Lambda (see LamBlocked), built from its CSR when the heart
+// is the whole mesh and the u and v orders agree: row k pairs u row k with v
+// row N + k; positions are the union of the columns of S_1 and S_i in that
+// row, S_i read from Pi^T S_i and checked against S_i Pi and the off-
+// diagonal v-v entries; gm[k] = the v-v diagonal minus S_i's.  Returns false
+// (CSR products only) when the structure does not match.
+bool build_lam_blocked(const HostSetup& hs, LamBlocked& out) {
+    out = LamBlocked();
+    std::vector<int64_t>& ptr = out.ptr;
+    std::vector<int32_t>& col = out.col;
+    std::vector<double>& val = out.val;
+    std::vector<double>& gm = out.gm;
+    const int64_t N = hs.A.N;
+    if (N != hs.A.NH || N == 0) return false;
+    for (int64_t j = 0; j < N; ++j)
+        if (hs.u_pos[hs.A.heart[j]] != hs.v_pos[j]) return false;
+    const Csr& L = hs.lam;
+    double big = 0.0;
+    for (double v : L.val) big = std::max(big, std::fabs(v));
+    const double tol = 1e-13 * big;
+    ptr.assign(N + 1, 0);
+    col.clear();
+    val.clear();
+    gm.assign(N, 0.0);
+    struct E { int32_t c; double s1, si, vu, vv; bool has_si, has_vu, has_vv; };
+    std::vector<E> row;
+    std::vector<int64_t> tag(N, -1);     // row that last saw a column, and its slot
+    std::vector<int32_t> slot(N, 0);
+    for (int64_t k = 0; k < N; ++k) {
+        row.clear();
+        auto at = [&](int32_t c) -> E& {
+            if (tag[c] != k) {
+                tag[c] = k;
+                slot[c] = (int32_t)row.size();
+                row.push_back({c, 0.0, 0.0, 0.0, 0.0, false, false, false});
+            }
+            return row[slot[c]];
+        };
+        for (int64_t q = L.ptr[k]; q < L.ptr[k + 1]; ++q) {
+            const int64_t c = L.col[q];
+            if (c < N) at((int32_t)c).s1 += L.val[q];
+            else { E& e = at((int32_t)(c - N)); e.si += L.val[q]; e.has_si = true; }
+        }
+        for (int64_t q = L.ptr[N + k]; q < L.ptr[N + k + 1]; ++q) {
+            const int64_t c = L.col[q];
+            if (c < N) { E& e = at((int32_t)c); e.vu += L.val[q]; e.has_vu = true; }
+            else { E& e = at((int32_t)(c - N)); e.vv += L.val[q]; e.has_vv = true; }
+        }
+        std::sort(row.begin(), row.end(), [](const E& a, const E& b) { return a.c < b.c; });
+        for (const E& e : row) {
+            if (std::fabs(e.si - e.vu) > tol) return false;
+            if (e.c == k) gm[k] = e.vv - e.si;
+            else if (std::fabs(e.vv - e.si) > tol) return false;
+            col.push_back(e.c);
+            val.push_back(e.s1);
+            val.push_back(e.si);
+        }
+        ptr[k + 1] = (int64_t)col.size();
+    }
+    out.n = N;
+    return true;
+}
 
 bool host_set_dt(HostSetup& hs, double dt, bool refactor, std::string& err) {
     bido_params& P = hs.params;
@@ -351,6 +415,7 @@ bool host_set_dt(HostSetup& hs, double dt, bool refactor, std::string& err) {
     hs.km_int = std::move(Kmp);
     hs.gamma = gamma;
     P.dt = dt;
+    if (hs.lamb.n > 0 && !build_lam_blocked(hs, hs.lamb)) { err = "blocked Lambda"; return false; }
     hs.stim_n0 = std::llround(hs.stim_t0 / dt);
     hs.stim_n1 = std::llround(hs.stim_t1 / dt);
     return true;

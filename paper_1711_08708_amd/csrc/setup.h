@@ -10,6 +10,20 @@
 
 namespace bido {
 
+// Lambda in blocked form when the heart is the whole mesh and u and v share
+// one internal order (Pi = I): row k holds the columns c of S_1's row k and
+// per column the pair {S_1[k,c], S_i[k,c]} (val, interleaved), and gm[k] =
+// gamma m_k, so that
+//   (Lambda x)_u[k] = sum_c S_1 x_u[c] + S_i x_v[c]
+//   (Lambda x)_v[k] = sum_c S_i (x_u[c] + x_v[c]) + gm[k] x_v[k].
+// n = 0: no blocked form.
+struct LamBlocked {
+    int64_t n = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> col;
+    std::vector<double> val, gm;
+};
+
 struct HostSetup {
     bido_params params{};
     Assembled A;
@@ -18,6 +32,7 @@ struct HostSetup {
     bool p1_factored = true, pk_factored = true;
     Amg amg1, amgk;                // multigrid hierarchies (inner_p1 / inner_pk = AMG)
     Csr lam;                       // Lambda, internal order [u (ND of S_1); v (ND of K_m)]
+    LamBlocked lamb;               // its blocked form (heart = whole mesh), or n = 0
     Csr avu;                       // S_i Pi: N_H rows (v order), u columns
     Csr auv;                       // Pi^T S_i: N rows (u order), v columns
     std::vector<int64_t> u_pos;    // global id   -> internal u index
@@ -49,5 +64,9 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
 // refactor, K_m is factored again in its elimination tree (P_1 does not
 // depend on dt).
 bool host_set_dt(HostSetup& hs, double dt, bool refactor, std::string& err);
+
+// The blocked form of hs.lam (LamBlocked); false when the heart is not the
+// whole mesh, the u and v orders differ or the blocks do not match.
+bool build_lam_blocked(const HostSetup& hs, LamBlocked& out);
 
 }  // namespace bido

@@ -90,6 +90,48 @@ def test_host_lambda_is_the_oracle_lambda_reordered():
     assert abs(L - Lo).max() <= 1e-13 * abs(Lo).max()
 
 
+def _blocked_product(b, x):
+    """(Lambda x) from the blocked form: u rows then v rows."""
+    n = len(b["gm"])
+    xu, xv = x[:n], x[n:]
+    rows = np.repeat(np.arange(n), np.diff(b["ptr"]))
+    c = b["col"]
+    yu = np.bincount(rows, b["val"][:, 0] * xu[c] + b["val"][:, 1] * xv[c], minlength=n)
+    yv = np.bincount(rows, b["val"][:, 1] * (xu[c] + xv[c]), minlength=n) + b["gm"] * xv
+    return np.concatenate([yu, yv])
+
+
+def test_blocked_lambda_is_the_oracle_lambda():
+    """A slab (heart = whole mesh, one order for u and v) has Lambda's blocked
+    form; its product equals the oracle's Lambda (reordered) times x, also
+    after a change of time step; a mesh with torso rows has none."""
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd
+    cfg = w.slab3d(n=7)
+    hs = B.HostSetup(cfg, eps_h=0.0)
+    b = hs.lambda_blocked()
+    assert b is not None
+    s = bd.System(cfg)
+    upos, vpos = hs.index(B.IDX_UPOS), hs.index(B.IDX_VPOS)
+    N, NH = s.N, s.NH
+    assert np.array_equal(upos[s.perm], vpos)      # one order for u and v
+    o2i = np.concatenate([upos[s.perm], N + vpos])
+    P = np.empty(N + NH, dtype=np.int64)
+    P[o2i] = np.arange(N + NH)
+    Lo = s.Lam[P][:, P]
+    x = np.random.default_rng(3).normal(size=N + NH)
+    y = Lo @ x
+    assert np.abs(_blocked_product(b, x) - y).max() <= 1e-13 * np.abs(y).max()
+    # 20 bytes per position against 12 per entry of the four CSR blocks
+    assert 20 * len(b["col"]) < 12 * hs.csr(B.MAT_LAMBDA).nnz
+    hs.set_dt(0.05)
+    b2 = hs.lambda_blocked()
+    L2 = hs.csr(B.MAT_LAMBDA)
+    assert np.abs(_blocked_product(b2, x) - L2 @ x).max() <= 1e-13 * np.abs(L2 @ x).max()
+    assert np.allclose(b2["gm"], 2.0 * b["gm"], rtol=1e-12)   # gamma ~ 1/dt
+    assert B.HostSetup(w.square2d(n=12), eps_h=0.0).lambda_blocked() is None
+
+
 @pytest.mark.parametrize("mk", [lambda: w.square2d(n=30), lambda: w.slab3d(n=7),
                                 lambda: w.thorax2d(n_target=6000, seed=4)])
 def test_exact_factors_invert_the_inner_matrices(mk):
