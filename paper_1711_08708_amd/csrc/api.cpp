@@ -521,6 +521,7 @@ struct bido_ctx {
     std::unique_ptr<Factor> pk_learned_host;   // its host factor (a fused batch merges it)
     AmgDev amg1, amgk;                // multigrid P_1 / P_K (inner_p1 / inner_pk = AMG)
     LamBlk lamb;                      // blocked Lambda (heart = whole mesh, one order)
+    float *avu32 = nullptr, *auv32 = nullptr;   // FP32 values of S_i Pi, Pi^T S_i (mixed precision)
     AmgDev amgk_learned;              // multigrid of K_m + C (learned stencil with a multigrid P_K)
     int precond = BIDO_PRECOND_PLAIN;
     int fallbacks = 0;
@@ -566,6 +567,8 @@ struct bido_ctx {
         rec.release();
         CsrHostView::release(lam);
         release_lam_blk(lamb);
+        hipFree(avu32);
+        hipFree(auv32);
         CsrHostView::release(avu);
         CsrHostView::release(auv);
         CsrHostView::release(km);
@@ -796,6 +799,25 @@ void debug_check(bido_ctx* c, const char* name, const double* v, int64_t n) {
                  (long long)n, (long long)bad, (long long)first, mx);
 }
 
+// y = b + sign * B x for a coupling block B (S_i Pi or Pi^T S_i) on the
+// multigrid products' kernels (row groups sized to the average row): FP32
+// values in mixed precision, where the block only feeds the preconditioner
+void coupling_product(bido_ctx* c, const CsrDev& B, const float* v32, const double* x, const double* b,
+                      double sign, double* y) {
+    const int64_t avg = B.n > 0 ? (B.nnz + B.n - 1) / B.n : 1;
+    const int g = avg <= 16 ? 4 : avg <= 32 ? 8 : avg <= 64 ? 16 : 32;
+    const bool f32 = c->precision == BIDO_PREC_MIXED;
+    const double bytes = (f32 ? 8.0 : 12.0) * B.nnz + 8.0 * (B.n + 1) + 8.0 * B.n * (b ? 2 : 1) +
+                         8.0 * (B.nnz > 0 ? B.n : 0);
+    if (f32) {
+        AmgMat<float> m{B.n, B.nnz, B.ptr, B.col, v32, g};
+        PROF(c, K_SPMV_CSR, bytes, launch_amg_spmv<float>(c->stream, m, x, b, sign, y));
+    } else {
+        AmgMat<double> m{B.n, B.nnz, B.ptr, B.col, B.val, g};
+        PROF(c, K_SPMV_CSR, bytes, launch_amg_spmv<double>(c->stream, m, x, b, sign, y));
+    }
+}
+
 // z = P_Lambda^-1 r  and  rho_new = r.z  (plus z.r_old for flexible CG).
 // learned: add the network's correction to Z2 (Schur-complement block);
 // collecting: record (t, V_k + Z2_k) for training targets.
@@ -807,8 +829,7 @@ void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old,
     debug_check(c, "r", r, c->n2);
     p1_solve(c, r, c->tA);                                           // Z1 = P1^-1 R1
     debug_check(c, "Z1", c->tA, N);
-    PROF(c, K_SPMV_CSR, csr_bytes(c->avu, c->NH) + 8.0 * c->NH,
-         launch_spmv_csr(s, c->avu, c->spmv_group, c->tA, r + N, c->tB));  // R2 - S_i Pi Z1
+    coupling_product(c, c->avu, c->avu32, c->tA, r + N, -1.0, c->tB);     // R2 - S_i Pi Z1
     debug_check(c, "t", c->tB, c->NH);
     if (stencil && c->amgk_learned.on()) amg_vcycle(c, c->amgk_learned, 0, c->tB, z + N);
     else if (stencil) inner_solve(c, c->pk_learned, c->tB, z + N);   // Z2 = PK^-1 (...)
@@ -832,8 +853,7 @@ void precond_apply(bido_ctx* c, const double* r, double* z, const double* r_old,
              launch_gnn_forward(s, NH, c->tB, c->sc + S_TN2, g.stat, g.A, g.wbf, g.act, 0, z + N,
                                 g.out_scale));
     }
-    PROF(c, K_SPMV_CSR, csr_bytes(c->auv, c->NH),
-         launch_spmv_csr(s, c->auv, c->spmv_group, z + N, nullptr, c->tC));   // Pi^T S_i Z2
+    coupling_product(c, c->auv, c->auv32, z + N, nullptr, 1.0, c->tC);     // Pi^T S_i Z2
     debug_check(c, "PiSZ2", c->tC, N);
     p1_solve(c, c->tC, c->tD);                                       // P1^-1 Pi^T S_i Z2
     debug_check(c, "W", c->tD, N);
@@ -1776,6 +1796,11 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     if ((e = upload_lam_blk(hs, c->lamb))) return e;
     if ((e = CsrHostView::up(hs.avu, c->avu))) return e;
     if ((e = CsrHostView::up(hs.auv, c->auv))) return e;
+    for (auto [src, dst] : {std::pair<const Csr*, float**>{&hs.avu, &c->avu32}, {&hs.auv, &c->auv32}}) {
+        std::vector<float> v32(src->val.begin(), src->val.end());
+        if (v32.empty()) v32.push_back(0.0f);
+        HIP_OK(upload(dst, v32.data(), v32.size()));
+    }
     if (hs.p1_factored) {
         if ((e = build_factor_dev(hs.p1, true, c->p1, hs.params.n_threads))) return e;
         hs.p1.trim_top_cache(c->p1.top_h);  // a fused batch reuses hierarchical tops

@@ -311,7 +311,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lambda(int64_t n, const int64_t*
 // and v): row k gives the u output k and the v output N + k from one pass
 // over its positions (column, {S_1, S_i}), gathering x_u and x_v at each
 // column; partials as in k_spmv_lambda.
-template <int G, int MODE>
+template <int G, int K, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_spmv_lam_blk(int64_t n, const int64_t* __restrict__ ptr,
                                                         const int32_t* __restrict__ col,
                                                         const double2* __restrict__ val,
@@ -340,10 +340,10 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lam_blk(int64_t n, const int64_t
             su[u] = 0.0;
             sv[u] = 0.0;
         }
-        // two unconditional passes (an entry past the row's end rereads
+        // K unconditional passes (an entry past the row's end rereads
         // position 0 and is dropped by a select), then the rest of the row
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
+        for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
                 const int64_t q = pb[u] + lane + k * G;
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lam_blk(int64_t n, const int64_t
             }
 #pragma unroll
         for (int u = 0; u < RU; ++u)
-            for (int64_t q = pb[u] + lane + 2 * G; q < pe[u]; q += G) {
+            for (int64_t q = pb[u] + lane + K * G; q < pe[u]; q += G) {
                 const int32_t c = col[q];
                 const double2 w = val[q];
                 const double a = x[c], b = xv[c];
@@ -1401,14 +1401,20 @@ unsigned launch_spmv_lambda(hipStream_t s, const CsrDev& A, int group, int mode,
 
 unsigned launch_spmv_lam_blk(hipStream_t s, const LamBlk& A, int group, int mode, const double* x, const double* y,
                              double* out, double* pp) {
-    const unsigned g = grid_for(A.n * group, BLOCK * 2, PP_MAX);
+    (void)group;
+    // one lane per two positions of the average row, two passes (measured
+    // on the 128^3 slab, 15 positions per row: 8 lanes 5.6 ms per step, 16
+    // lanes 6.0, 4 lanes with four passes 7.8)
+    const int64_t avg = A.n > 0 ? (A.npos + A.n - 1) / A.n : 1;
+    const int g4 = avg <= 8 ? 4 : avg <= 16 ? 8 : avg <= 32 ? 16 : 32;
+    const unsigned g = grid_for(A.n * g4, BLOCK * 2, PP_MAX);
     const double2* v = reinterpret_cast<const double2*>(A.val);
 #define BIDO_BLK_CASE(G)                                                                              \
-    if (group == G) {                                                                                 \
+    if (g4 == G) {                                                                                    \
         if (mode == 0)                                                                                \
-            k_spmv_lam_blk<G, 0><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, v, A.gm, x, y, out, pp);      \
+            k_spmv_lam_blk<G, 2, 0><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, v, A.gm, x, y, out, pp);   \
         else                                                                                          \
-            k_spmv_lam_blk<G, 1><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, v, A.gm, x, y, out, pp);      \
+            k_spmv_lam_blk<G, 2, 1><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, v, A.gm, x, y, out, pp);   \
         return g;                                                                                     \
     }
     BIDO_BLK_CASE(4) BIDO_BLK_CASE(8) BIDO_BLK_CASE(16) BIDO_BLK_CASE(32)
