@@ -199,7 +199,13 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
         hs.p1.ground = N - 1;
         hs.p1.grounds.assign(1, N - 1);
         // the grounded vertex N - 1 is held at zero (excluded), as in the factor
-        if (!amg_build(S1p, N - 1, AmgOptions(), hs.amg1, err)) { err = "P_1: " + err; return false; }
+        // S_1 is a pure Laplacian: a lower strength threshold gives larger
+        // aggregates at the same outer iteration count (128^3 slab: 8 % fewer
+        // bytes per V-cycle, 0.73 -> 0.69 ms); K_m keeps 0.08 (its mass term
+        // makes the coarser levels of larger aggregates slower)
+        AmgOptions o1;
+        o1.theta = 0.04;
+        if (!amg_build(S1p, N - 1, o1, hs.amg1, err)) { err = "P_1: " + err; return false; }
     }
     if (hs.pk_factored) {
         if (!multifrontal(Kmp, hs.pk, -1, nth, err)) { err = "P_K: " + err; return false; }
