@@ -120,17 +120,19 @@ bido_status bido_host_lambda_blocked(const bido_host* h, int64_t* n, int64_t* np
  * (which = BIDO_FACTOR_P1 / BIDO_FACTOR_PK; BIDO_ERR_STATE if it has none).
  * info: levels, size of the coarsest level, operator complexity (sum of the
  * levels' non-zeros over the fine matrix's), host seconds of its set-up,
- * Chebyshev steps per smoothing.  level: CSR view of level `level`'s
- * matrix (what = 0) or prolongation (what = 1; not on the coarsest level),
- * owned by the hierarchy.  smoother: D^-1 of the level (0 at the grounded
- * vertex) and the interval [lo, hi] of the smoother polynomial.  apply:
- * one host V-cycle x = B b (a check hook; internal order).               */
+ * Chebyshev steps per smoothing on the finest level.  level: CSR view of
+ * level `level`'s matrix (what = 0) or prolongation (what = 1; not on the
+ * coarsest level), owned by the hierarchy.  smoother: D^-1 of the level (0
+ * at the grounded vertex), the interval [lo, hi] of the smoother polynomial
+ * and the level's Chebyshev steps per smoothing (1 on the coarser levels by
+ * default: the damped Jacobi sweep).  apply: one host V-cycle x = B b (a
+ * check hook; internal order).                                           */
 bido_status bido_host_amg_info(const bido_host* h, int which, int* levels, int64_t* n_coarse,
                                double* op_complexity, double* seconds, int* smooth_steps);
 bido_status bido_host_amg_level(const bido_host* h, int which, int level, int what, int64_t* n, int64_t* nnz,
                                 const int64_t** ptr, const int32_t** col, const double** val);
 bido_status bido_host_amg_smoother(const bido_host* h, int which, int level, const double** dinv, double* lo,
-                                   double* hi);
+                                   double* hi, int* steps);
 bido_status bido_host_amg_apply(const bido_host* h, int which, const double* b, double* x);
 
 /* Plan options (bido_plan, bido.h) of the later bido_host_factor_emulate,

@@ -7,7 +7,8 @@ elliptic or parabolic block fits the block-LU framework of Def. 2, and the
 paper names multigrid among them.  This module applies one symmetric
 V-cycle from its definition, for a given hierarchy: level matrices A_l,
 prolongations P_l (A_{l+1} = P_l^T A_l P_l), smoother data (D_l^-1 and the
-interval [lo_l, hi_l] of D_l^-1 A_l) and the number m of smoother steps.
+interval [lo_l, hi_l] of D_l^-1 A_l) and the number m of smoother steps
+(one count for all levels, or one per level).
 
 With the smoother S_l = q_l(D_l^-1 A_l) D_l^-1, q_l the Chebyshev
 polynomial of `chebyshev.q_polynomial` on [lo_l, hi_l], one cycle on level l
@@ -48,15 +49,17 @@ def coarse_solve(A, b, keep=None):
 
 
 def vcycle(levels, m, b, level=0):
-    """One V-cycle x = B b.  levels[l] = dict(A, P, dinv, lo, hi); the last
-    level has P = None and is solved exactly.  On the finest level the
-    vertices with D^-1 = 0 are held at zero."""
+    """One V-cycle x = B b.  levels[l] = dict(A, P, dinv, lo, hi[, steps]);
+    the last level has P = None and is solved exactly.  A level's smoother
+    takes its own step count `steps` when given, else m.  On the finest level
+    the vertices with D^-1 = 0 are held at zero."""
     L = levels[level]
     A = L["A"]
     if L["P"] is None:
         return coarse_solve(A, b, L["dinv"] != 0.0 if level == 0 else None)
     P = L["P"]
-    x1 = smooth(A, L["dinv"], L["lo"], L["hi"], m, b)
+    ml = L.get("steps", m)
+    x1 = smooth(A, L["dinv"], L["lo"], L["hi"], ml, b)
     e = vcycle(levels, m, P.T @ (b - A @ x1), level + 1)
     x2 = x1 + P @ e
-    return x2 + smooth(A, L["dinv"], L["lo"], L["hi"], m, b - A @ x2)
+    return x2 + smooth(A, L["dinv"], L["lo"], L["hi"], ml, b - A @ x2)

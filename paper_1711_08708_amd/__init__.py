@@ -237,7 +237,8 @@ ABI = {
                                            _c_i64_p, ctypes.POINTER(_c_i64_p), ctypes.POINTER(_c_i32_p),
                                            ctypes.POINTER(_c_double_p)]),
     "bido_host_amg_smoother": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
-                                              ctypes.POINTER(_c_double_p), _c_double_p, _c_double_p]),
+                                              ctypes.POINTER(_c_double_p), _c_double_p, _c_double_p,
+                                              ctypes.POINTER(ctypes.c_int)]),
     "bido_host_amg_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_double_p, _c_double_p]),
     "bido_host_merge": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_void_p)]),
@@ -759,7 +760,8 @@ class HostSetup:
                     gm=np.ctypeslib.as_array(g, (nn,)).copy())
 
     def amg_level(self, which, level):
-        """dict(A=scipy CSR, P=scipy CSR or None, dinv, lo, hi) of one level (copies)."""
+        """dict(A=scipy CSR, P=scipy CSR or None, dinv, lo, hi, steps) of one level
+        (copies; steps: Chebyshev steps per smoothing on the level)."""
         import scipy.sparse as sp
         info = self.amg_info(which)
         out = {}
@@ -777,11 +779,11 @@ class HostSetup:
             ncols = n.value if what == 0 else self.amg_level_size(which, level + 1)
             out[key] = sp.csr_matrix((val, col, ptr), shape=(n.value, ncols))
         d = _c_double_p()
-        lo, hi = ctypes.c_double(), ctypes.c_double()
+        lo, hi, st = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
         _check(lib.bido_host_amg_smoother(self.h, which, level, ctypes.byref(d), ctypes.byref(lo),
-                                          ctypes.byref(hi)), host=True)
+                                          ctypes.byref(hi), ctypes.byref(st)), host=True)
         out["dinv"] = np.ctypeslib.as_array(d, shape=(out["A"].shape[0],)).copy()
-        out["lo"], out["hi"] = lo.value, hi.value
+        out["lo"], out["hi"], out["steps"] = lo.value, hi.value, st.value
         return out
 
     def amg_level_size(self, which, level):

@@ -286,6 +286,7 @@ struct AmgDev {
         double* As64 = nullptr;            // A D^-1 (columns scaled), for the fused smoother
         float* As32 = nullptr;
         int gA = 4, gP = 4, gR = 4;        // lanes per row of the three products
+        int steps = 2;                     // Chebyshev steps per smoothing on this level
         double* dinv = nullptr;
         ChebCoef cf;
         double *b = nullptr, *out = nullptr;   // input and output of this level (levels >= 1)
@@ -307,7 +308,6 @@ struct AmgDev {
     std::vector<Lev> lv;
     double* cinv = nullptr;
     int64_t nc = 0;
-    int steps = 2;
     double op_complexity = 1.0, setup_seconds = 0.0;
     bool on() const { return !lv.empty(); }
     // algorithmic bytes of one V-cycle with value bytes w (8 or 4)
@@ -321,6 +321,7 @@ struct AmgDev {
             // two smoothings (the fused first two steps read A D^-1, b and D^-1 and write
             // z, plus r1, d0 and d1 when more steps follow; each further step A + 7
             // vectors), two residuals, restriction, prolongation, the final sum
+            const int steps = L.steps;
             const double sm = steps < 2    ? 4.0 * vec
                               : steps == 2 ? A + 3.0 * vec
                                            : A + 6.0 * vec + (steps - 2) * (A + 7.0 * vec);
@@ -356,7 +357,6 @@ int group_for(const Csr& a) {
 
 bido_status upload_amg(const Amg& M, AmgDev& d) {
     d.release();
-    d.steps = M.smooth_steps;
     d.op_complexity = M.op_complexity;
     d.setup_seconds = M.setup_seconds;
     const size_t L = M.levels.size();
@@ -398,7 +398,8 @@ bido_status upload_amg(const Amg& M, AmgDev& d) {
         v.nnz_P = h.P.nnz();
         v.nnz_R = h.R.nnz();
         HIP_OK(upload(&v.dinv, h.dinv.data(), h.dinv.size()));
-        v.cf = chebyshev_coefficients(h.lo, h.hi, std::max(2, M.smooth_steps));
+        v.steps = h.steps;
+        v.cf = chebyshev_coefficients(h.lo, h.hi, std::max(2, h.steps));
         for (double** b : {&v.x, &v.r, &v.d0, &v.d1, &v.xp, &v.t}) HIP_OK(hipMalloc((void**)b, n * sizeof(double)));
     }
     d.nc = M.levels.back().A.n;
@@ -688,15 +689,15 @@ void amg_smooth(C* c, const AmgDev& M, const AmgDev::Lev& L, const double* b, do
     if constexpr (sizeof(T) == 4) As.val = L.As32;
     else As.val = L.As64;
     const double Ab = (4.0 + sizeof(T)) * L.nnz_A + 8.0 * (n + 1);
-    if (M.steps < 2) {
+    if (L.steps < 2) {
         PROF(c, cls, 32.0 * n, launch_cheb_init(s, n, b, L.dinv, L.cf.inv_theta, L.d0, z));
         return;
     }
-    PROF(c, cls, Ab + 8.0 * n * (M.steps > 2 ? 6 : 3),
+    PROF(c, cls, Ab + 8.0 * n * (L.steps > 2 ? 6 : 3),
          launch_amg_smooth2<T>(s, As, L.dinv, b, L.cf.inv_theta, L.cf.c1[0], L.cf.c2[0], z, L.r, L.d0, L.d1,
-                               M.steps > 2));
+                               L.steps > 2));
     double* d[2] = {L.d0, L.d1};
-    for (int k = 2; k < M.steps; ++k)
+    for (int k = 2; k < L.steps; ++k)
         PROF(c, cls, Ab + 56.0 * n,
              launch_amg_cheb<T>(s, A, L.dinv, L.r, d[(k - 1) & 1], d[k & 1], z, L.cf.c1[k - 1], L.cf.c2[k - 1]));
 }

@@ -192,12 +192,14 @@ struct AmgLevel {
     Csr A, P, R;
     std::vector<double> dinv;
     double lo = 0.0, hi = 0.0;
+    int steps = 2;                    // Chebyshev steps per smoothing on this level
 };
 struct Amg {
     std::vector<AmgLevel> levels;
     std::vector<double> coarse_inv;   // n_c x n_c row-major
     int64_t excluded = -1;            // fine vertex held at zero (grounded), or -1
-    int smooth_steps = 2;             // Chebyshev steps per smoothing
+    int smooth_steps = 2;             // Chebyshev steps per smoothing on the finest level
+    int coarse_steps = 2;             // ... and on the coarser ones
     double op_complexity = 1.0;       // sum of nnz over levels / nnz of A_0
     double setup_seconds = 0.0;
 };
@@ -205,7 +207,8 @@ struct AmgOptions {
     double theta = 0.08;        // strength threshold
     int max_coarse = 1024;      // coarsest size
     int max_levels = 16;
-    int smooth_steps = 2;       // Chebyshev steps (degree of the smoother polynomial)
+    int smooth_steps = 2;       // Chebyshev steps (degree of the smoother polynomial), finest level
+    int coarse_steps = 1;       // the same on the coarser levels (0: smooth_steps)
     double smooth_ratio = 10.0; // smoother interval [hi / ratio, hi]
     int lanczos_steps = 20;     // estimate of lambda_max(D^-1 A) per level
 };

@@ -257,13 +257,14 @@ bido_status bido_host_amg_level(const bido_host* h, int which, int level, int wh
 }
 
 bido_status bido_host_amg_smoother(const bido_host* h, int which, int level, const double** dinv, double* lo,
-                                   double* hi) {
-    if (!h || !dinv || !lo || !hi) return hfail(BIDO_ERR_ARG, "null argument");
+                                   double* hi, int* steps) {
+    if (!h || !dinv || !lo || !hi || !steps) return hfail(BIDO_ERR_ARG, "null argument");
     const bido::Amg* m = host_amg(h, which);
     if (!m) return hfail(BIDO_ERR_STATE, "no multigrid hierarchy for that block");
     if (level < 0 || level >= (int)m->levels.size()) return hfail(BIDO_ERR_ARG, "level out of range");
     const bido::AmgLevel& L = m->levels[level];
     *dinv = L.dinv.data();
+    *steps = L.steps;
     *lo = L.lo;
     *hi = L.hi;
     return BIDO_OK;

@@ -93,6 +93,10 @@ def test_library_hierarchy_is_galerkin_and_its_cycle_is_the_oracle_cycle(mk):
                 continue
             G = (a["P"].T @ a["A"] @ a["P"]).toarray()
             np.testing.assert_allclose(b["A"].toarray(), G, atol=1e-12 * np.abs(G).max())
+        # two Chebyshev steps on the finest level, the damped Jacobi sweep on
+        # the coarser ones (the oracle cycle takes each level's count)
+        assert levels[0]["steps"] == info["smooth_steps"] == 2
+        assert all(l["steps"] == 1 for l in levels[1:])
         n = levels[0]["A"].shape[0]
         b = np.random.default_rng(5 + which).normal(size=n)
         xo = mg.vcycle(levels, info["smooth_steps"], b)
