@@ -94,16 +94,26 @@ __global__ __launch_bounds__(BLOCK) void k_amg_spmv(int64_t n, const int64_t* __
     }
 }
 
+// One Chebyshev step from zero, the damped Jacobi sweep, plus an optional
+// base: z = base + a0 D^-1 b.
+__global__ __launch_bounds__(BLOCK) void k_amg_jacobi(int64_t n, const double* __restrict__ b,
+                                                      const double* __restrict__ dinv, double a0,
+                                                      const double* __restrict__ base, double* __restrict__ z) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        z[i] = (base ? base[i] : 0.0) + a0 * dinv[i] * b[i];
+}
+
 // The first two Chebyshev smoothing steps from z = 0 in one pass:
 // d0 = a0 D^-1 b, r1 = b - A d0 = b - a0 (A D^-1) b (the column-scaled copy
 // As = A D^-1 of the level matrix, so one gather per entry),
-// d1 = c1 d0 + c2 D^-1 r1, z = d0 + d1; r1, d0 and d1 are kept when more
-// steps follow (write_rd).
+// d1 = c1 d0 + c2 D^-1 r1, z = base + d0 + d1 (base may be null); r1, d0
+// and d1 are kept when more steps follow (write_rd).
 template <int G, int K, typename T>
 __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t* __restrict__ ptr,
                                                        const int32_t* __restrict__ col,
                                                        const T* __restrict__ val, const double* __restrict__ dinv,
                                                        const double* __restrict__ b, double a0, double c1, double c2,
+                                                       const double* __restrict__ base,
                                                        double* __restrict__ z, double* __restrict__ r1,
                                                        double* __restrict__ d0o, double* __restrict__ d1o,
                                                        int write_rd) {
@@ -131,7 +141,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t*
                 const double d0 = a0 * di[u] * bv[u];
                 const double r = bv[u] - a0 * s[u];
                 const double d1 = c1 * d0 + c2 * di[u] * r;
-                z[row[u]] = d0 + d1;
+                z[row[u]] = (base ? base[row[u]] : 0.0) + d0 + d1;
                 if (write_rd) {
                     r1[row[u]] = r;
                     d0o[row[u]] = d0;
@@ -226,10 +236,18 @@ void launch_amg_spmv(hipStream_t s, const AmgMat<T>& A, const double* x, const d
 
 template <typename T>
 void launch_amg_smooth2(hipStream_t s, const AmgMat<T>& A, const double* dinv, const double* b, double a0, double c1,
-                        double c2, double* z, double* r1, double* d0, double* d1, bool write_rd) {
+                        double c2, const double* base, double* z, double* r1, double* d0, double* d1,
+                        bool write_rd) {
     if (A.n <= 0) return;
     BIDO_G_SWITCH(A, k_amg_smooth2<GG, KK, T><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
-                         A.n, A.ptr, A.col, A.val, dinv, b, a0, c1, c2, z, r1, d0, d1, write_rd ? 1 : 0))
+                         A.n, A.ptr, A.col, A.val, dinv, b, a0, c1, c2, base, z, r1, d0, d1, write_rd ? 1 : 0))
+}
+
+void launch_amg_jacobi(hipStream_t s, int64_t n, const double* b, const double* dinv, double a0, const double* base,
+                       double* z) {
+    if (n <= 0) return;
+    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + BLOCK - 1) / BLOCK, 4096));
+    k_amg_jacobi<<<g, BLOCK, 0, s>>>(n, b, dinv, a0, base, z);
 }
 
 template <typename T>
@@ -246,7 +264,7 @@ void launch_amg_cheb(hipStream_t s, const AmgMat<T>& A, const double* dinv, doub
 #define BIDO_INST(T)                                                                                              \
     template void launch_amg_spmv<T>(hipStream_t, const AmgMat<T>&, const double*, const double*, double, double*); \
     template void launch_amg_smooth2<T>(hipStream_t, const AmgMat<T>&, const double*, const double*, double,       \
-                                        double, double, double*, double*, double*, double*, bool);                 \
+                                        double, double, const double*, double*, double*, double*, double*, bool);  \
     template void launch_amg_cheb<T>(hipStream_t, const AmgMat<T>&, const double*, double*, const double*,         \
                                      double*, double*, double, double);
 BIDO_INST(double)

@@ -290,7 +290,7 @@ struct AmgDev {
         double* dinv = nullptr;
         ChebCoef cf;
         double *b = nullptr, *out = nullptr;   // input and output of this level (levels >= 1)
-        double *x = nullptr, *r = nullptr, *d0 = nullptr, *d1 = nullptr, *xp = nullptr, *t = nullptr;
+        double *x = nullptr, *r = nullptr, *d0 = nullptr, *d1 = nullptr, *xp = nullptr;
         int64_t nnz_A = 0, nnz_P = 0, nnz_R = 0;
         template <typename T>
         AmgMat<T> mat(const CsrDev& m, const float* v32, int g) const {
@@ -318,15 +318,16 @@ struct AmgDev {
             auto mb = [&](int64_t nnz, int64_t rows) { return (4.0 + w) * nnz + 8.0 * (rows + 1); };
             const double A = mb(L.nnz_A, L.n), vec = 8.0 * L.n;
             const double nc_l = 8.0 * lv[l + 1].n;
-            // two smoothings (the fused first two steps read A D^-1, b and D^-1 and write
-            // z, plus r1, d0 and d1 when more steps follow; each further step A + 7
-            // vectors), two residuals, restriction, prolongation, the final sum
+            // two smoothings (one step: b and D^-1 read, z written; the fused first two
+            // steps read A D^-1, b and D^-1 and write z, plus r1, d0 and d1 when more
+            // steps follow; each further step A + 7 vectors; the post-smoothing also
+            // reads the base it adds), two residuals, restriction, prolongation
             const int steps = L.steps;
-            const double sm = steps < 2    ? 4.0 * vec
+            const double sm = steps < 2    ? 3.0 * vec
                               : steps == 2 ? A + 3.0 * vec
                                            : A + 6.0 * vec + (steps - 2) * (A + 7.0 * vec);
-            b += 2.0 * sm + 2.0 * (A + 3.0 * vec) + mb(L.nnz_R, lv[l + 1].n) + vec + nc_l +
-                 mb(L.nnz_P, L.n) + nc_l + 2.0 * vec + 3.0 * vec;
+            b += 2.0 * sm + vec + 2.0 * (A + 3.0 * vec) + mb(L.nnz_R, lv[l + 1].n) + vec + nc_l +
+                 mb(L.nnz_P, L.n) + nc_l + 2.0 * vec;
         }
         return b;
     }
@@ -336,7 +337,7 @@ struct AmgDev {
                 hipFree(m->ptr); hipFree(m->col); hipFree(m->val);
             }
             for (float* v : {L.A32, L.P32, L.R32, L.As32}) hipFree(v);
-            for (double* v : {L.dinv, L.b, L.out, L.x, L.r, L.d0, L.d1, L.xp, L.t, L.As64}) hipFree(v);
+            for (double* v : {L.dinv, L.b, L.out, L.x, L.r, L.d0, L.d1, L.xp, L.As64}) hipFree(v);
         }
         lv.clear();
         hipFree(cinv);
@@ -400,7 +401,7 @@ bido_status upload_amg(const Amg& M, AmgDev& d) {
         HIP_OK(upload(&v.dinv, h.dinv.data(), h.dinv.size()));
         v.steps = h.steps;
         v.cf = chebyshev_coefficients(h.lo, h.hi, std::max(2, h.steps));
-        for (double** b : {&v.x, &v.r, &v.d0, &v.d1, &v.xp, &v.t}) HIP_OK(hipMalloc((void**)b, n * sizeof(double)));
+        for (double** b : {&v.x, &v.r, &v.d0, &v.d1, &v.xp}) HIP_OK(hipMalloc((void**)b, n * sizeof(double)));
     }
     d.nc = M.levels.back().A.n;
     HIP_OK(upload(&d.cinv, M.coarse_inv.data(), M.coarse_inv.size()));
@@ -681,7 +682,8 @@ void inner_solve(C* c, const FactorDev& f, const double* in, double* out) {
 // smoother from z = 0 (the recurrence of the Chebyshev P_K on the level's
 // interval of D^-1 A; the first two steps in one fused pass).
 template <typename T, typename C>
-void amg_smooth(C* c, const AmgDev& M, const AmgDev::Lev& L, const double* b, double* z, int cls) {
+void amg_smooth(C* c, const AmgDev& M, const AmgDev::Lev& L, const double* b, double* z, int cls,
+                const double* base = nullptr) {
     hipStream_t s = c->stream;
     const int64_t n = L.n;
     const AmgMat<T> A = L.mat<T>(L.A, L.A32, L.gA);
@@ -689,13 +691,14 @@ void amg_smooth(C* c, const AmgDev& M, const AmgDev::Lev& L, const double* b, do
     if constexpr (sizeof(T) == 4) As.val = L.As32;
     else As.val = L.As64;
     const double Ab = (4.0 + sizeof(T)) * L.nnz_A + 8.0 * (n + 1);
+    const double bb = base ? 8.0 * n : 0.0;
     if (L.steps < 2) {
-        PROF(c, cls, 32.0 * n, launch_cheb_init(s, n, b, L.dinv, L.cf.inv_theta, L.d0, z));
+        PROF(c, cls, 24.0 * n + bb, launch_amg_jacobi(s, n, b, L.dinv, L.cf.inv_theta, base, z));
         return;
     }
-    PROF(c, cls, Ab + 8.0 * n * (L.steps > 2 ? 6 : 3),
-         launch_amg_smooth2<T>(s, As, L.dinv, b, L.cf.inv_theta, L.cf.c1[0], L.cf.c2[0], z, L.r, L.d0, L.d1,
-                               L.steps > 2));
+    PROF(c, cls, Ab + 8.0 * n * (L.steps > 2 ? 6 : 3) + bb,
+         launch_amg_smooth2<T>(s, As, L.dinv, b, L.cf.inv_theta, L.cf.c1[0], L.cf.c2[0], base, z, L.r, L.d0,
+                               L.d1, L.steps > 2));
     double* d[2] = {L.d0, L.d1};
     for (int k = 2; k < L.steps; ++k)
         PROF(c, cls, Ab + 56.0 * n,
@@ -730,8 +733,7 @@ void amg_vcycle_t(C* c, const AmgDev& M, size_t l, const double* b, double* out)
     amg_vcycle_t<T>(c, M, l + 1, Lc.b, Lc.out);
     PROF(c, c_tr, Pb + 8.0 * Lc.n + 2 * vec, launch_amg_spmv<T>(s, P, Lc.out, L.x, 1.0, L.xp));  // xp = x + P e
     PROF(c, c_re, Ab + 3 * vec, launch_amg_spmv<T>(s, A, L.xp, b, -1.0, L.r));               // r = b - A xp
-    amg_smooth<T>(c, M, L, L.r, L.t, c_sm);
-    PROF(c, fine ? K_MISC : K_AMG_COARSE, 3 * vec, launch_add2(s, L.n, L.xp, L.t, out));
+    amg_smooth<T>(c, M, L, L.r, out, c_sm, L.xp);                                            // out = xp + S r
 }
 
 // The cycle with FP32 level values in mixed precision, FP64 otherwise.

@@ -114,7 +114,11 @@ void launch_amg_spmv(hipStream_t s, const AmgMat<T>& A, const double* x, const d
 // the first two Chebyshev smoothing steps from z = 0 in one pass (see amg.hip)
 template <typename T>
 void launch_amg_smooth2(hipStream_t s, const AmgMat<T>& A, const double* dinv, const double* b, double a0, double c1,
-                        double c2, double* z, double* r1, double* d0, double* d1, bool write_rd);
+                        double c2, const double* base, double* z, double* r1, double* d0, double* d1,
+                        bool write_rd);
+// z = base + a0 D^-1 b (base may be null): one Chebyshev step from zero
+void launch_amg_jacobi(hipStream_t s, int64_t n, const double* b, const double* dinv, double a0, const double* base,
+                       double* z);
 // one further Chebyshev step: r -= A dp, dn = c1 dp + c2 D^-1 r, z += dn
 template <typename T>
 void launch_amg_cheb(hipStream_t s, const AmgMat<T>& A, const double* dinv, double* r, const double* dp, double* dn,
