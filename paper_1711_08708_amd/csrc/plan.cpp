@@ -304,7 +304,7 @@ bool build_plan(const Factor& f, FactorPlan& p, std::string& err, int n_threads,
     // bandwidth when larger); the top costs two launches plus n_top^2 FP64
     // entries at streaming bandwidth.  A forest (the factor of several
     // independent blocks) gets one cut per tree and one hierarchical top per
-    // tree, concatenated.  Environment BIDO_TOP_H forces a single tree's cut
+    // tree, concatenated.  The plan option top_h forces a single tree's cut
     // (a value above the tree height switches the top off).
     // cost-model cut of the tree rooted at r (heights of its own nodes)
     auto model_cut = [&](int r, int& lowest) {

@@ -80,6 +80,26 @@ def test_vcycle_is_symmetric_and_contracting(m):
     assert ev.min() > 0.05
 
 
+def test_two_grid_cycle_with_one_jacobi_step_is_the_written_out_propagator():
+    """One smoothing step is the damped Jacobi sweep S = 2/(lo + hi) D^-1 (the
+    degree-0 Chebyshev polynomial on [lo, hi]); a two-grid cycle with it has
+    the error propagator I - B A = (I - S A)(I - P A_c^-1 P^T A)(I - S A).  The
+    level's own step count (steps = 1) overrides the cycle's m = 3."""
+    A = _laplacian_2d(6, 0.2)
+    P = _pair_aggregation(A.shape[0])
+    Ac = (P.T @ A @ P).tocsr()
+    L0 = _level(A, P)
+    L0["steps"] = 1
+    levels = [L0, dict(A=Ac, P=None, dinv=1.0 / Ac.diagonal())]
+    n = A.shape[0]
+    Bm = np.column_stack([mg.vcycle(levels, 3, e) for e in np.eye(n)])
+    Ad, Pd = A.toarray(), P.toarray()
+    S = 2.0 / (L0["lo"] + L0["hi"]) * np.diag(L0["dinv"])
+    I = np.eye(n)
+    E = (I - S @ Ad) @ (I - Pd @ np.linalg.solve(Ac.toarray(), Pd.T @ Ad)) @ (I - S @ Ad)
+    np.testing.assert_allclose(I - Bm @ Ad, E, atol=1e-12)
+
+
 @pytest.mark.parametrize("mk", [lambda: w.slab3d(n=12), lambda: w.thorax2d(n_target=6000, seed=3),
                                 lambda: w.square2d(n=20)], ids=["slab12", "thorax6000", "square20"])
 def test_library_hierarchy_is_galerkin_and_its_cycle_is_the_oracle_cycle(mk):
