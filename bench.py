@@ -467,6 +467,27 @@ def _bench_slab128(args):
                                       "GBps": round(c["bytes"] / max(c["ms"], 1e-9) / 1e6, 1)}
     kernels = {k: {"launches": p["launches"], "ms": round(p["ms"], 3),
                    "GBps": round(p["bytes"] / max(p["ms"], 1e-9) / 1e6, 1)} for k, p in prof.items()}
+    # a change of time step: the multigrid K_m moves to the new gamma on the
+    # device (no new aggregation); then plain FP64 steps at dt / 2, the last
+    # one checked on the sampled rows at the new step
+    solver.set_precision(B.PREC_FP64)
+    solver.set_precond(B.PRECOND_PLAIN)
+    dt0 = cfg["dt"]
+    sec = solver.set_dt(dt0 / 2)
+    st = [t.clone() for t in saved]
+    _, ws, it = _timed_steps(torch, solver, st, n1, 5)
+    n = n1 + 5
+    Vn, hn = st[0].cpu().numpy().copy(), st[1].cpu().numpy().copy()
+    solver.step(st[0], st[1], st[2], n)
+    U1, V1 = st[2].cpu().numpy(), st[0].cpu().numpy()
+    ru, rv, yv = bd.sampled_residual(dict(cfg, dt=dt0 / 2), sample, Vn, hn, n, U1, V1)
+    dt_change = {"dt_ms": [dt0, dt0 / 2], "set_dt_s": round(sec, 4), "steps_per_s": round(5 / ws, 3),
+                 "cg_iterations_per_step": round(it / 5, 2),
+                 "parity": {"sampled_rows": int(len(sample)),
+                            "max_abs_residual_over_max_abs_y": float(max(np.abs(ru).max(), np.abs(rv).max())
+                                                                    / np.abs(yv).max())}}
+    print(f"[bench] dt change: {dt_change}", file=sys.stderr, flush=True)
+    solver.set_dt(dt0)
     hv = variants[head]
     result = {
         "metric": METRIC, "value": hv["steps_per_s"], "unit": "steps/s", "n_gpus": 1,
@@ -492,6 +513,7 @@ def _bench_slab128(args):
                      "loss_zero_val": ts["loss_zero_val"], "loss_val": ts["loss_val"]},
         "roofline": roofline,
         "kernels": kernels,
+        "dt_change": dt_change,
     }
     if not args.no_cpu:
         result["cpu_baseline"] = _cpu_baseline_slab(solver.N)

@@ -238,7 +238,13 @@ bido_status bido_set_precision(bido_ctx* ctx, int precision);
  * again on the host in its elimination tree and uploaded, with the plan
  * options in use; with the Chebyshev P_K nothing is factored: the device
  * copies of Lambda's values, K_m and its inverse diagonal are replaced and
- * an estimated interval is estimated again (an explicit one is kept).  The
+ * an estimated interval is estimated again (an explicit one is kept).  A
+ * multigrid K_m (inner_pk = BIDO_PK_AMG, also while another P_K is active)
+ * moves to the new gamma on the device, on the same aggregation and
+ * transfer operators: every level's matrix plus (gamma' - gamma) times its
+ * Galerkin mass part, new inverse diagonals, smoother copies and smoother
+ * intervals (the set-up's Lanczos estimate), and the coarsest inverse by
+ * Gauss-Jordan; no host work but the Lanczos scalars.  The
  * stimulus window keeps its times (its step range follows dt).  The
  * learned correction is set up again from scratch (its pairs, weights and
  * stencil were fitted to K_m at the old step; collect and train again) and

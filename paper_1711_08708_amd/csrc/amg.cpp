@@ -171,22 +171,102 @@ uint64_t mix64(uint64_t& s) {
     return z ^ (z >> 31);
 }
 
-// Largest eigenvalue of D^-1 A (dinv = 0 on excluded rows) by Lanczos on
-// D^-1/2 A D^-1/2 from a fixed pseudo-random start; Ritz values lie inside
-// the spectrum, so the caller adds a margin.
-double lambda_max_dinv(const Csr& A, const std::vector<double>& dinv, int steps) {
-    const int64_t n = A.n;
-    std::vector<double> s(n), v(n), vp(n, 0.0), w(n), t(n), al, be;
-    for (int64_t i = 0; i < n; ++i) s[i] = std::sqrt(dinv[i]);
+}  // namespace
+
+// The fixed pseudo-random start of the Lanczos estimates (zero on excluded
+// rows), normalised; false when it is zero.
+bool lanczos_start(const std::vector<double>& dinv, std::vector<double>& v) {
+    const int64_t n = (int64_t)dinv.size();
+    v.assign(n, 0.0);
     uint64_t seed = 0xa36ull;
     double nv = 0.0;
     for (int64_t i = 0; i < n; ++i) {
-        v[i] = s[i] > 0.0 ? (double)(mix64(seed) >> 11) * 0x1.0p-53 - 0.5 : 0.0;
+        v[i] = dinv[i] > 0.0 ? (double)(mix64(seed) >> 11) * 0x1.0p-53 - 0.5 : 0.0;
         nv += v[i] * v[i];
     }
-    if (!(nv > 0.0)) return 1.0;
+    if (!(nv > 0.0)) return false;
     nv = std::sqrt(nv);
     for (auto& x : v) x /= nv;
+    return true;
+}
+
+// Largest eigenvalue of the symmetric tridiagonal matrix (diagonal al,
+// off-diagonal be): bisection on the Sturm count.
+double tridiag_largest(const std::vector<double>& al, const std::vector<double>& be) {
+    double lo = al[0], hi = al[0];
+    for (size_t i = 0; i < al.size(); ++i) {
+        const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i + 1 < al.size() ? std::fabs(be[i]) : 0.0);
+        lo = std::min(lo, al[i] - r);
+        hi = std::max(hi, al[i] + r);
+    }
+    const int k = (int)al.size() - 1;
+    for (int it = 0; it < 200 && hi - lo > 1e-14 * std::max(1.0, std::fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        int count = 0;
+        double q = 1.0;
+        for (size_t i = 0; i < al.size(); ++i) {
+            const double b2 = i > 0 ? be[i - 1] * be[i - 1] : 0.0;
+            q = al[i] - mid - (i > 0 ? b2 / q : 0.0);
+            if (q == 0.0) q = -1e-300;
+            if (q < 0.0) ++count;
+        }
+        if (count > k) hi = mid; else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+namespace {
+
+// Dense inverse of a coarsest level (n <= 8192; an excluded vertex's row and
+// column become the unit vector, and its row and column of the inverse 0):
+// Cholesky, inverse of the factor, L^-T L^-1.
+bool coarse_inverse(const Csr& A, int64_t excluded, std::vector<double>& inv, std::string& err) {
+    const int64_t n = A.n;
+    if (n > 8192) {
+        err = "multigrid: coarsest level too large (" + std::to_string(n) + " > 8192)";
+        return false;
+    }
+    std::vector<double> M((size_t)n * n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) M[(size_t)i * n + A.col[p]] = A.val[p];
+    if (excluded >= 0) {         // ground the excluded vertex: unit row and column
+        for (int64_t j = 0; j < n; ++j) {
+            M[(size_t)excluded * n + j] = 0.0;
+            M[(size_t)j * n + excluded] = 0.0;
+        }
+        M[(size_t)excluded * n + excluded] = 1.0;
+    }
+    if (dense::potrf_lower(n, M.data(), n, true) >= 0) {
+        err = "multigrid: coarsest matrix is not positive definite";
+        return false;
+    }
+    std::vector<double> Li((size_t)n * n);
+    dense::trtri_lower(n, M.data(), n, Li.data(), true);
+    inv.assign((size_t)n * n, 0.0);   // L^-T L^-1
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j <= i; ++j) {
+            double s = 0.0;
+            for (int64_t k = i; k < n; ++k) s += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
+            inv[(size_t)i * n + j] = s;
+            inv[(size_t)j * n + i] = s;
+        }
+    if (excluded >= 0)
+        for (int64_t j = 0; j < n; ++j) {
+            inv[(size_t)excluded * n + j] = 0.0;
+            inv[(size_t)j * n + excluded] = 0.0;
+        }
+    return true;
+}
+
+// Largest eigenvalue of D^-1 A (dinv = 0 on excluded rows) by Lanczos on
+// D^-1/2 A D^-1/2 from the fixed start; Ritz values lie inside the
+// spectrum, so the caller adds a margin.
+double lambda_max_dinv(const Csr& A, const std::vector<double>& dinv, int steps) {
+    const int64_t n = A.n;
+    std::vector<double> s(n), v, vp(n, 0.0), w(n), t(n), al, be;
+    for (int64_t i = 0; i < n; ++i) s[i] = std::sqrt(dinv[i]);
+    if (!lanczos_start(dinv, v)) return 1.0;
     double beta = 0.0;
     steps = (int)std::min<int64_t>(steps, n);
     for (int j = 0; j < steps; ++j) {
@@ -212,27 +292,7 @@ double lambda_max_dinv(const Csr& A, const std::vector<double>& dinv, int steps)
             v[i] = w[i] / b;
         }
     }
-    // largest eigenvalue of the tridiagonal matrix: bisection on the Sturm count
-    double lo = al[0], hi = al[0];
-    for (size_t i = 0; i < al.size(); ++i) {
-        const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i + 1 < al.size() ? std::fabs(be[i]) : 0.0);
-        lo = std::min(lo, al[i] - r);
-        hi = std::max(hi, al[i] + r);
-    }
-    const int k = (int)al.size() - 1;
-    for (int it = 0; it < 200 && hi - lo > 1e-14 * std::max(1.0, std::fabs(hi)); ++it) {
-        const double mid = 0.5 * (lo + hi);
-        int count = 0;
-        double q = 1.0;
-        for (size_t i = 0; i < al.size(); ++i) {
-            const double b2 = i > 0 ? be[i - 1] * be[i - 1] : 0.0;
-            q = al[i] - mid - (i > 0 ? b2 / q : 0.0);
-            if (q == 0.0) q = -1e-300;
-            if (q < 0.0) ++count;
-        }
-        if (count > k) hi = mid; else lo = mid;
-    }
-    return 0.5 * (lo + hi);
+    return tridiag_largest(al, be);
 }
 
 }  // namespace
@@ -242,6 +302,8 @@ bool amg_build(const Csr& A0, int64_t excluded, const AmgOptions& opt, Amg& out,
     out = Amg();
     out.excluded = excluded;
     out.smooth_steps = std::max(1, opt.smooth_steps);
+    out.lanczos_steps = opt.lanczos_steps;
+    out.smooth_ratio = opt.smooth_ratio;
     out.coarse_steps = opt.coarse_steps > 0 ? opt.coarse_steps : out.smooth_steps;
     Csr A = A0;
     for (int lev = 0;; ++lev) {
@@ -264,42 +326,7 @@ bool amg_build(const Csr& A0, int64_t excluded, const AmgOptions& opt, Amg& out,
         L.steps = lev == 0 ? out.smooth_steps : out.coarse_steps;
         const bool last = n <= opt.max_coarse || lev + 1 >= opt.max_levels;
         if (last) {
-            // dense inverse of the coarsest matrix (excluded rows: the unit vector)
-            if (n > 8192) {
-                err = "multigrid: coarsest level too large (" + std::to_string(n) + " > 8192)";
-                return false;
-            }
-            std::vector<double> M((size_t)n * n, 0.0);
-            for (int64_t i = 0; i < n; ++i)
-                for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) M[(size_t)i * n + A.col[p]] = A.val[p];
-            if (lev == 0 && excluded >= 0) {         // ground the excluded vertex: unit row and column
-                for (int64_t j = 0; j < n; ++j) {
-                    M[(size_t)excluded * n + j] = 0.0;
-                    M[(size_t)j * n + excluded] = 0.0;
-                }
-                M[(size_t)excluded * n + excluded] = 1.0;
-            }
-
-            if (dense::potrf_lower(n, M.data(), n, true) >= 0) {
-                err = "multigrid: coarsest matrix is not positive definite";
-                return false;
-            }
-            std::vector<double> Li((size_t)n * n);
-            dense::trtri_lower(n, M.data(), n, Li.data(), true);
-            out.coarse_inv.assign((size_t)n * n, 0.0);   // L^-T L^-1
-#pragma omp parallel for schedule(dynamic, 8)
-            for (int64_t i = 0; i < n; ++i)
-                for (int64_t j = 0; j <= i; ++j) {
-                    double s = 0.0;
-                    for (int64_t k = i; k < n; ++k) s += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
-                    out.coarse_inv[(size_t)i * n + j] = s;
-                    out.coarse_inv[(size_t)j * n + i] = s;
-                }
-            if (lev == 0 && excluded >= 0)
-                for (int64_t j = 0; j < n; ++j) {
-                    out.coarse_inv[(size_t)excluded * n + j] = 0.0;
-                    out.coarse_inv[(size_t)j * n + excluded] = 0.0;
-                }
+            if (!coarse_inverse(A, lev == 0 ? excluded : -1, out.coarse_inv, err)) return false;
             L.A = std::move(A);
             out.levels.push_back(std::move(L));
             break;
@@ -493,6 +520,64 @@ void vcycle(const Amg& M, size_t l, const double* b, double* x) {
 }
 
 }  // namespace
+
+bool amg_split_mass(Amg& M, const std::vector<double>& m0, double gamma, std::string& err) {
+    M.mass.clear();
+    if (M.levels.empty()) return true;
+    Csr Ml = M.levels[0].A;
+    if ((int64_t)m0.size() != Ml.n) { err = "mass vector size"; return false; }
+    for (int64_t i = 0; i < Ml.n; ++i)
+        for (int64_t p = Ml.ptr[i]; p < Ml.ptr[i + 1]; ++p) Ml.val[p] = Ml.col[p] == i ? m0[i] : 0.0;
+    M.mass.push_back(Ml.val);
+    for (size_t l = 0; l + 1 < M.levels.size(); ++l) {
+        const AmgLevel& L = M.levels[l];
+        const Csr& Ac = M.levels[l + 1].A;
+        const int64_t nc = Ac.n;
+        Csr Mc = spgemm(L.R, spgemm(Ml, L.P, nc), nc);
+        Csr Mt = transpose(Mc, nc);
+        for (int64_t p = 0; p < Mc.nnz(); ++p) Mc.val[p] = 0.5 * (Mc.val[p] + Mt.val[p]);
+        if (Mc.ptr != Ac.ptr || Mc.col != Ac.col) {
+            err = "multigrid: the mass part's pattern differs at level " + std::to_string(l + 1);
+            return false;
+        }
+        M.mass.push_back(Mc.val);
+        Ml = std::move(Mc);
+    }
+    M.gamma = gamma;
+    return true;
+}
+
+bool amg_refresh_gamma(Amg& M, double gamma, std::string& err) {
+    if (M.mass.size() != M.levels.size()) {
+        err = "multigrid: no mass parts to refresh with";
+        return false;
+    }
+    const double dg = gamma - M.gamma;
+    for (size_t l = 0; l < M.levels.size(); ++l) {
+        AmgLevel& L = M.levels[l];
+        Csr& A = L.A;
+        const int64_t n = A.n;
+        for (int64_t p = 0; p < A.nnz(); ++p) A.val[p] += dg * M.mass[l][p];
+        const bool last = l + 1 == M.levels.size();
+        if (last) {
+            if (!coarse_inverse(A, l == 0 ? M.excluded : -1, M.coarse_inv, err)) return false;
+            break;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            if (l == 0 && i == M.excluded) continue;
+            const double d = diag_of(A, i);
+            if (!(d > 0.0)) {
+                err = "multigrid: non-positive diagonal at level " + std::to_string(l);
+                return false;
+            }
+            L.dinv[i] = 1.0 / d;
+        }
+        L.hi = 1.1 * lambda_max_dinv(A, L.dinv, M.lanczos_steps);
+        L.lo = L.hi / M.smooth_ratio;
+    }
+    M.gamma = gamma;
+    return true;
+}
 
 void amg_apply(const Amg& M, const double* b, double* x) {
     if (M.levels.empty()) return;

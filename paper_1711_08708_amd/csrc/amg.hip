@@ -198,7 +198,154 @@ unsigned grid_rows(int64_t n, int G) {
     return (unsigned)std::max<int64_t>(1, (n + rows - 1) / rows);
 }
 
+// ---------------------------------------------------------------------------
+// A new gamma on the device (a change of time step with a multigrid P_K):
+// A_l += dg M_l, D^-1, the column-scaled copy, the Lanczos estimate of the
+// smoother bound and the coarsest inverse.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_amg_shift(int64_t nnz, double dg, const double* __restrict__ mass,
+                                                     double* __restrict__ a64, float* __restrict__ a32) {
+    for (int64_t p = blockIdx.x * (int64_t)BLOCK + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * BLOCK) {
+        const double v = a64[p] + dg * mass[p];
+        a64[p] = v;
+        if (a32) a32[p] = (float)v;
+    }
+}
+
+// D^-1 of every row (the excluded row keeps 0)
+__global__ __launch_bounds__(BLOCK) void k_amg_dinv(int64_t n, const int64_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                    int64_t excluded, double* __restrict__ dinv) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        double d = 0.0;
+        for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q)
+            if (col[q] == i) d += val[q];
+        dinv[i] = i == excluded ? 0.0 : 1.0 / d;
+    }
+}
+
+// A D^-1 (columns scaled), FP64 and FP32
+__global__ __launch_bounds__(BLOCK) void k_amg_colscale(int64_t nnz, const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val,
+                                                        const double* __restrict__ dinv, double* __restrict__ s64,
+                                                        float* __restrict__ s32) {
+    for (int64_t p = blockIdx.x * (int64_t)BLOCK + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * BLOCK) {
+        const double v = val[p] * dinv[col[p]];
+        s64[p] = v;
+        s32[p] = (float)v;
+    }
+}
+
+// Lanczos on D^-1/2 A D^-1/2: t = D^-1/2 v; w = D^-1/2 y - beta vp; vp = v, v = w / b
+__global__ __launch_bounds__(BLOCK) void k_lz_in(int64_t n, const double* __restrict__ dinv,
+                                                 const double* __restrict__ v, double* __restrict__ t) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        t[i] = sqrt(dinv[i]) * v[i];
+}
+__global__ __launch_bounds__(BLOCK) void k_lz_w(int64_t n, const double* __restrict__ dinv,
+                                                const double* __restrict__ y, double beta,
+                                                const double* __restrict__ vp, double* __restrict__ w) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        w[i] = sqrt(dinv[i]) * y[i] - beta * vp[i];
+}
+__global__ __launch_bounds__(BLOCK) void k_lz_next(int64_t n, const double* __restrict__ w, double inv_b,
+                                                   double* __restrict__ v, double* __restrict__ vp) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        vp[i] = v[i];
+        v[i] = w[i] * inv_b;
+    }
+}
+
+// dense n x n copy of a CSR matrix (the output zeroed before); with an
+// excluded row, its row and column become the unit vector
+__global__ __launch_bounds__(BLOCK) void k_amg_densify(int64_t n, const int64_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val, int64_t excluded,
+                                                       double* __restrict__ m) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        if (i == excluded) {
+            m[i * n + i] = 1.0;
+            continue;
+        }
+        for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q)
+            if (col[q] != excluded) m[i * n + col[q]] = val[q];
+    }
+}
+// Gauss-Jordan inversion in place, pivot k (SPD: no pivoting).  prep: f =
+// column k (f[k] the pivot); row: row k / pivot with the identity's 1 at
+// (k, k); update: every other row i minus f[i] times row k, its entry k
+// starting from the identity's 0.
+__global__ __launch_bounds__(BLOCK) void k_gj_prep(int64_t n, int64_t k, const double* __restrict__ m,
+                                                   double* __restrict__ f) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        f[i] = m[i * n + k];
+}
+__global__ __launch_bounds__(BLOCK) void k_gj_row(int64_t n, int64_t k, double* __restrict__ m,
+                                                  const double* __restrict__ f) {
+    const double inv = 1.0 / f[k];
+    for (int64_t j = blockIdx.x * (int64_t)BLOCK + threadIdx.x; j < n; j += (int64_t)gridDim.x * BLOCK)
+        m[k * n + j] = (j == k ? 1.0 : m[k * n + j]) * inv;
+}
+__global__ __launch_bounds__(BLOCK) void k_gj_update(int64_t n, int64_t k, double* __restrict__ m,
+                                                     const double* __restrict__ f) {
+    const int64_t nn = n * n;
+    for (int64_t e = blockIdx.x * (int64_t)BLOCK + threadIdx.x; e < nn; e += (int64_t)gridDim.x * BLOCK) {
+        const int64_t i = e / n, j = e - i * n;
+        if (i == k) continue;
+        m[e] = (j == k ? 0.0 : m[e]) - f[i] * m[k * n + j];
+    }
+}
+// the excluded row and column of the inverse are 0
+__global__ __launch_bounds__(BLOCK) void k_amg_zero_rc(int64_t n, int64_t r, double* __restrict__ m) {
+    for (int64_t j = blockIdx.x * (int64_t)BLOCK + threadIdx.x; j < n; j += (int64_t)gridDim.x * BLOCK) {
+        m[r * n + j] = 0.0;
+        m[j * n + r] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_amg_fill(int64_t n, double* __restrict__ m) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) m[i] = 0.0;
+}
+
+unsigned grid_elems(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + BLOCK - 1) / BLOCK, 8192));
+}
+
 }  // namespace
+
+void launch_amg_shift(hipStream_t s, int64_t nnz, double dg, const double* mass, double* a64, float* a32) {
+    if (nnz > 0) k_amg_shift<<<grid_elems(nnz), BLOCK, 0, s>>>(nnz, dg, mass, a64, a32);
+}
+void launch_amg_dinv(hipStream_t s, int64_t n, const int64_t* ptr, const int32_t* col, const double* val,
+                     int64_t excluded, double* dinv) {
+    if (n > 0) k_amg_dinv<<<grid_elems(n), BLOCK, 0, s>>>(n, ptr, col, val, excluded, dinv);
+}
+void launch_amg_colscale(hipStream_t s, int64_t nnz, const int32_t* col, const double* val, const double* dinv,
+                         double* s64, float* s32) {
+    if (nnz > 0) k_amg_colscale<<<grid_elems(nnz), BLOCK, 0, s>>>(nnz, col, val, dinv, s64, s32);
+}
+void launch_lz_in(hipStream_t s, int64_t n, const double* dinv, const double* v, double* t) {
+    if (n > 0) k_lz_in<<<grid_elems(n), BLOCK, 0, s>>>(n, dinv, v, t);
+}
+void launch_lz_w(hipStream_t s, int64_t n, const double* dinv, const double* y, double beta, const double* vp,
+                 double* w) {
+    if (n > 0) k_lz_w<<<grid_elems(n), BLOCK, 0, s>>>(n, dinv, y, beta, vp, w);
+}
+void launch_lz_next(hipStream_t s, int64_t n, const double* w, double inv_b, double* v, double* vp) {
+    if (n > 0) k_lz_next<<<grid_elems(n), BLOCK, 0, s>>>(n, w, inv_b, v, vp);
+}
+void launch_amg_dense_inverse(hipStream_t s, int64_t n, const int64_t* ptr, const int32_t* col, const double* val,
+                              int64_t excluded, double* m, double* f) {
+    if (n <= 0) return;
+    k_amg_fill<<<grid_elems(n * n), BLOCK, 0, s>>>(n * n, m);
+    k_amg_densify<<<grid_elems(n), BLOCK, 0, s>>>(n, ptr, col, val, excluded, m);
+    for (int64_t k = 0; k < n; ++k) {
+        k_gj_prep<<<grid_elems(n), BLOCK, 0, s>>>(n, k, m, f);
+        k_gj_row<<<grid_elems(n), BLOCK, 0, s>>>(n, k, m, f);
+        k_gj_update<<<grid_elems(n * n), BLOCK, 0, s>>>(n, k, m, f);
+    }
+    if (excluded >= 0) k_amg_zero_rc<<<grid_elems(n), BLOCK, 0, s>>>(n, excluded, m);
+}
 
 // lane groups of G lanes, K unrolled passes of G entries per row (the
 // average row length over G, 2 to 4; longer rows finish in a loop)

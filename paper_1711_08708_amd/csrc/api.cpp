@@ -287,6 +287,8 @@ struct AmgDev {
         float* As32 = nullptr;
         int gA = 4, gP = 4, gR = 4;        // lanes per row of the three products
         int steps = 2;                     // Chebyshev steps per smoothing on this level
+        double lo = 0.0, hi = 0.0;         // the smoother's interval of D^-1 A
+        double* mass = nullptr;            // Galerkin mass part on A's pattern (K_m), or null
         double* dinv = nullptr;
         ChebCoef cf;
         double *b = nullptr, *out = nullptr;   // input and output of this level (levels >= 1)
@@ -308,6 +310,12 @@ struct AmgDev {
     std::vector<Lev> lv;
     double* cinv = nullptr;
     int64_t nc = 0;
+    // the gamma the level matrices hold, and what a refresh needs
+    double gamma = 0.0;
+    int64_t excluded = -1;
+    int lanczos_steps = 20;
+    double smooth_ratio = 10.0;
+    bool refreshable() const { return !lv.empty() && lv[0].mass; }
     double op_complexity = 1.0, setup_seconds = 0.0;
     bool on() const { return !lv.empty(); }
     // algorithmic bytes of one V-cycle with value bytes w (8 or 4)
@@ -337,7 +345,7 @@ struct AmgDev {
                 hipFree(m->ptr); hipFree(m->col); hipFree(m->val);
             }
             for (float* v : {L.A32, L.P32, L.R32, L.As32}) hipFree(v);
-            for (double* v : {L.dinv, L.b, L.out, L.x, L.r, L.d0, L.d1, L.xp, L.As64}) hipFree(v);
+            for (double* v : {L.dinv, L.b, L.out, L.x, L.r, L.d0, L.d1, L.xp, L.As64, L.mass}) hipFree(v);
         }
         lv.clear();
         hipFree(cinv);
@@ -360,7 +368,12 @@ bido_status upload_amg(const Amg& M, AmgDev& d) {
     d.release();
     d.op_complexity = M.op_complexity;
     d.setup_seconds = M.setup_seconds;
+    d.gamma = M.gamma;
+    d.excluded = M.excluded;
+    d.lanczos_steps = M.lanczos_steps;
+    d.smooth_ratio = M.smooth_ratio;
     const size_t L = M.levels.size();
+    const bool refresh = M.mass.size() == L;   // K_m: a new gamma moves the levels on the device
     d.lv.resize(L);
     for (size_t l = 0; l < L; ++l) {
         const AmgLevel& h = M.levels[l];
@@ -372,8 +385,16 @@ bido_status upload_amg(const Amg& M, AmgDev& d) {
             HIP_OK(hipMalloc((void**)&v.b, n * sizeof(double)));
             HIP_OK(hipMalloc((void**)&v.out, n * sizeof(double)));
         }
-        if (last) break;
         bido_status e;
+        if (last) {
+            if (refresh) {           // the coarsest matrix, its mass part and the inverse's scratch
+                if ((e = CsrHostView::up(h.A, v.A))) return e;
+                v.nnz_A = h.A.nnz();
+                HIP_OK(upload(&v.mass, M.mass[l].data(), std::max<size_t>(M.mass[l].size(), 1)));
+                HIP_OK(hipMalloc((void**)&v.x, n * sizeof(double)));
+            }
+            break;
+        }
         if ((e = CsrHostView::up(h.A, v.A))) return e;
         if ((e = CsrHostView::up(h.P, v.P))) return e;
         if ((e = CsrHostView::up(h.R, v.R))) return e;
@@ -400,7 +421,10 @@ bido_status upload_amg(const Amg& M, AmgDev& d) {
         v.nnz_R = h.R.nnz();
         HIP_OK(upload(&v.dinv, h.dinv.data(), h.dinv.size()));
         v.steps = h.steps;
+        v.lo = h.lo;
+        v.hi = h.hi;
         v.cf = chebyshev_coefficients(h.lo, h.hi, std::max(2, h.steps));
+        if (refresh) HIP_OK(upload(&v.mass, M.mass[l].data(), std::max<size_t>(M.mass[l].size(), 1)));
         for (double** b : {&v.x, &v.r, &v.d0, &v.d1, &v.xp}) HIP_OK(hipMalloc((void**)b, n * sizeof(double)));
     }
     d.nc = M.levels.back().A.n;
@@ -1807,14 +1831,16 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     if (hs.p1_factored) {
         if ((e = build_factor_dev(hs.p1, true, c->p1, hs.params.n_threads))) return e;
         hs.p1.trim_top_cache(c->p1.top_h);  // a fused batch reuses hierarchical tops
-    } else if ((e = upload_amg(hs.amg1, c->amg1))) {
-        return e;
+    } else {
+        if ((e = upload_amg(hs.amg1, c->amg1))) return e;
+        hs.amg1 = Amg();                    // the device copy is the only one kept
     }
     if (hs.pk_factored) {
         if ((e = build_factor_dev(hs.pk, true, c->pk, hs.params.n_threads))) return e;
         hs.pk.trim_top_cache(c->pk.top_h);
     } else if (params->inner_pk == BIDO_PK_AMG) {
         if ((e = upload_amg(hs.amgk, c->amgk))) return e;
+        hs.amgk = Amg();                    // (a time-step change moves it on the device)
         c->pk_kind = BIDO_PK_AMG;
     }
     const int64_t n2 = c->n2;
@@ -2526,15 +2552,93 @@ bido_status bido_set_pk(bido_ctx* c, int kind, int steps, double lo, double hi) 
 // Device side of a time-step change (the host state is already updated):
 // Lambda's values, the K_m factor or the Chebyshev P_K's copies, and the
 // learned correction set up again.
+// One dot product on the device, read back (set-up paths only: it waits).
+static bido_status device_dot(bido_ctx* c, int64_t n, const double* a, const double* b, double* out) {
+    launch_dot_reduce(c->stream, n, a, b, c->rd, c->sc + S_LZ);
+    HIP_OK(hipMemcpyAsync(out, c->sc + S_LZ, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return BIDO_OK;
+}
+
+// The largest eigenvalue of D^-1 A of a level by the host's Lanczos estimate
+// (same start vector, same steps, same recurrence), run on the device with
+// the level's work vectors.
+static bido_status device_lambda_max(bido_ctx* c, const AmgDev& M, AmgDev::Lev& L, double* lmax) {
+    hipStream_t s = c->stream;
+    const int64_t n = L.n;
+    std::vector<double> dinv(n), v0;
+    HIP_OK(hipMemcpy(dinv.data(), L.dinv, n * sizeof(double), hipMemcpyDeviceToHost));
+    if (!lanczos_start(dinv, v0)) {
+        *lmax = 1.0;
+        return BIDO_OK;
+    }
+    double *v = L.x, *vp = L.r, *w = L.xp, *t = L.d0, *y = L.d1;
+    HIP_OK(hipMemcpy(v, v0.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    launch_fill(s, n, vp, 0.0);
+    const AmgMat<double> A = L.mat<double>(L.A, L.A32, L.gA);
+    std::vector<double> al, be;
+    double beta = 0.0;
+    const int steps = (int)std::min<int64_t>(M.lanczos_steps, n);
+    for (int j = 0; j < steps; ++j) {
+        launch_lz_in(s, n, L.dinv, v, t);
+        launch_amg_spmv<double>(s, A, t, nullptr, 1.0, y);
+        launch_lz_w(s, n, L.dinv, y, beta, vp, w);
+        double a = 0.0, b = 0.0;
+        if (bido_status e = device_dot(c, n, w, v, &a)) return e;
+        launch_axpy(s, n, -a, v, w);
+        if (bido_status e = device_dot(c, n, w, w, &b)) return e;
+        al.push_back(a);
+        b = std::sqrt(b);
+        if (j + 1 == steps || b <= 1e-14 * std::fabs(a)) break;
+        be.push_back(b);
+        beta = b;
+        launch_lz_next(s, n, w, 1.0 / b, v, vp);
+    }
+    *lmax = tridiag_largest(al, be);
+    return BIDO_OK;
+}
+
+// A new gamma for a multigrid hierarchy of K_m, on the device: every level's
+// matrix moves by (gamma' - gamma) times its Galerkin mass part (FP64 and
+// FP32 copies), then D^-1, the smoother's column-scaled copy, the smoother
+// interval (the host's Lanczos estimate) and the coarsest inverse (Gauss-
+// Jordan, one pivot per launch).  The aggregation and the transfer
+// operators stay.
+static bido_status amg_refresh_device(bido_ctx* c, AmgDev& M, double gamma) {
+    if (!M.refreshable()) return fail(BIDO_ERR_STATE, "multigrid hierarchy without mass parts");
+    hipStream_t s = c->stream;
+    const double dg = gamma - M.gamma;
+    for (size_t l = 0; l < M.lv.size(); ++l) {
+        AmgDev::Lev& L = M.lv[l];
+        const bool last = l + 1 == M.lv.size();
+        const int64_t excl = l == 0 ? M.excluded : -1;
+        launch_amg_shift(s, L.nnz_A, dg, L.mass, L.A.val, last ? nullptr : L.A32);
+        if (last) {
+            launch_amg_dense_inverse(s, L.n, L.A.ptr, L.A.col, L.A.val, excl, M.cinv, L.x);
+            break;
+        }
+        launch_amg_dinv(s, L.n, L.A.ptr, L.A.col, L.A.val, excl, L.dinv);
+        launch_amg_colscale(s, L.nnz_A, L.A.col, L.A.val, L.dinv, L.As64, L.As32);
+        double lmax = 1.0;
+        if (bido_status e = device_lambda_max(c, M, L, &lmax)) return e;
+        L.hi = 1.1 * lmax;
+        L.lo = L.hi / M.smooth_ratio;
+        L.cf = chebyshev_coefficients(L.lo, L.hi, std::max(2, L.steps));
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    M.gamma = gamma;
+    return BIDO_OK;
+}
+
 static bido_status set_dt_device(bido_ctx* c, bool refactor) {
     // Lambda: only its v-v diagonal changed, but the values go up whole
     HIP_OK(hipMemcpy(c->lam.val, c->hs.lam.val.data(), c->hs.lam.val.size() * sizeof(double),
                      hipMemcpyHostToDevice));
     if (c->lamb.on())
         if (bido_status e = upload_lam_blk(c->hs, c->lamb)) return e;
-    if (refactor && c->pk_kind == BIDO_PK_AMG) {
-        if (bido_status e = upload_amg(c->hs.amgk, c->amgk)) return e;
-    } else if (refactor) {
+    if (c->amgk.on())      // (also when another P_K is active: kept at the current gamma)
+        if (bido_status e = amg_refresh_device(c, c->amgk, c->hs.gamma)) return e;
+    if (refactor && c->pk_kind == BIDO_PK_CHOLESKY) {
         const PlanOptions opts = c->pk.opts;
         c->pk.release();
         if (bido_status e = build_factor_dev(c->hs.pk, true, c->pk, c->hs.params.n_threads, &opts)) return e;
@@ -2575,7 +2679,10 @@ bido_status bido_set_dt(bido_ctx* c, double dt, double* seconds) {
     HIP_OK(hipStreamSynchronize(c->stream));
     if (seconds) *seconds = 0.0;
     if (dt_matches(c, dt)) return BIDO_OK;
-    const bool refactor = c->pk_kind == BIDO_PK_CHOLESKY || c->pk_kind == BIDO_PK_AMG;
+    // the factored K_m is factored again on the host; a multigrid K_m moves
+    // to the new gamma on the device (amg_refresh_device), the host copy of
+    // its hierarchy is not kept
+    const bool refactor = c->pk_kind == BIDO_PK_CHOLESKY;
     std::string err;
     if (!host_set_dt(c->hs, dt, refactor, err)) return fail(BIDO_ERR_NOT_SPD, err);
     // from here on the host state is at the new step: a failure below leaves

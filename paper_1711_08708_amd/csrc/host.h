@@ -200,6 +200,13 @@ struct Amg {
     int64_t excluded = -1;            // fine vertex held at zero (grounded), or -1
     int smooth_steps = 2;             // Chebyshev steps per smoothing on the finest level
     int coarse_steps = 2;             // ... and on the coarser ones
+    // K_m = gamma M_H + S_m: the Galerkin mass part of every level's matrix on
+    // its pattern (amg_split_mass), so that a new gamma needs no new
+    // aggregation: A_l(gamma') = A_l + (gamma' - gamma) M_l
+    std::vector<std::vector<double>> mass;
+    double gamma = 0.0;
+    int lanczos_steps = 20;           // of the smoother bounds (as built)
+    double smooth_ratio = 10.0;
     double op_complexity = 1.0;       // sum of nnz over levels / nnz of A_0
     double setup_seconds = 0.0;
 };
@@ -213,6 +220,19 @@ struct AmgOptions {
     int lanczos_steps = 20;     // estimate of lambda_max(D^-1 A) per level
 };
 bool amg_build(const Csr& A, int64_t excluded, const AmgOptions& opt, Amg& out, std::string& err);
+// The mass part of every level (m0: the diagonal mass of the finest level,
+// A_0 = gamma diag(m0) + S): M_0 = diag(m0) on A_0's pattern, M_{l+1} =
+// P_l^T M_l P_l symmetrised as the levels are, checked to share A_{l+1}'s
+// pattern.
+bool amg_split_mass(Amg& M, const std::vector<double>& m0, double gamma, std::string& err);
+// A new gamma on the same aggregation and transfer operators: A_l += (gamma
+// - M.gamma) M_l on every level, new D_l^-1 and smoother bounds (the same
+// Lanczos estimate as at build), the coarsest inverse again.
+bool amg_refresh_gamma(Amg& M, double gamma, std::string& err);
+// The fixed start vector of the Lanczos estimates (zero where dinv = 0),
+// normalised, and the largest eigenvalue of a symmetric tridiagonal matrix.
+bool lanczos_start(const std::vector<double>& dinv, std::vector<double>& v);
+double tridiag_largest(const std::vector<double>& al, const std::vector<double>& be);
 // Host V-cycle x = B b (the device apply in FP64 order-independent form; a
 // check hook).
 void amg_apply(const Amg& M, const double* b, double* x);

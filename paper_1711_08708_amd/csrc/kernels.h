@@ -92,6 +92,7 @@ enum ScalarSlot {
     S_ALPHA,        // step length of the latest PCG update
     S_EL_RR,        // |b - S_1 x|^2 of the elliptic solve of a Strang step
     S_EL_BB,        // |b|^2 of that solve
+    S_LZ,           // a dot product of the multigrid smoother-bound estimate
     S_COUNT = 32
 };
 

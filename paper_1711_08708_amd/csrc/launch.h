@@ -116,6 +116,21 @@ template <typename T>
 void launch_amg_smooth2(hipStream_t s, const AmgMat<T>& A, const double* dinv, const double* b, double a0, double c1,
                         double c2, const double* base, double* z, double* r1, double* d0, double* d1,
                         bool write_rd);
+// A new gamma for a multigrid level (see amg.hip): A += dg M (FP64 and FP32
+// copies), D^-1 (0 on the excluded row, < 0: none), A D^-1, the Lanczos
+// steps of the smoother bound, and the dense inverse of the coarsest level
+// (m: n x n output, f: n scratch; Gauss-Jordan, one pivot per launch)
+void launch_amg_shift(hipStream_t s, int64_t nnz, double dg, const double* mass, double* a64, float* a32);
+void launch_amg_dinv(hipStream_t s, int64_t n, const int64_t* ptr, const int32_t* col, const double* val,
+                     int64_t excluded, double* dinv);
+void launch_amg_colscale(hipStream_t s, int64_t nnz, const int32_t* col, const double* val, const double* dinv,
+                         double* s64, float* s32);
+void launch_lz_in(hipStream_t s, int64_t n, const double* dinv, const double* v, double* t);
+void launch_lz_w(hipStream_t s, int64_t n, const double* dinv, const double* y, double beta, const double* vp,
+                 double* w);
+void launch_lz_next(hipStream_t s, int64_t n, const double* w, double inv_b, double* v, double* vp);
+void launch_amg_dense_inverse(hipStream_t s, int64_t n, const int64_t* ptr, const int32_t* col, const double* val,
+                              int64_t excluded, double* m, double* f);
 // z = base + a0 D^-1 b (base may be null): one Chebyshev step from zero
 void launch_amg_jacobi(hipStream_t s, int64_t n, const double* b, const double* dinv, double a0, const double* base,
                        double* z);

@@ -211,9 +211,13 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
         if (!multifrontal(Kmp, hs.pk, -1, nth, err)) { err = "P_K: " + err; return false; }
     } else {
         hs.pk.n = NH;
-        if (P.inner_pk == BIDO_PK_AMG && !amg_build(Kmp, -1, AmgOptions(), hs.amgk, err)) {
-            err = "P_K: " + err;
-            return false;
+        if (P.inner_pk == BIDO_PK_AMG) {
+            std::vector<double> m0(NH);
+            for (int64_t l = 0; l < NH; ++l) m0[l] = A.mH[tk.perm[l]];
+            if (!amg_build(Kmp, -1, AmgOptions(), hs.amgk, err) || !amg_split_mass(hs.amgk, m0, hs.gamma, err)) {
+                err = "P_K: " + err;
+                return false;
+            }
         }
     }
     {   // coordinates (tree order) and the accuracy of the hierarchical top
@@ -398,11 +402,11 @@ bool host_set_dt(HostSetup& hs, double dt, bool refactor, std::string& err) {
     }
     if (!found) { err = "missing diagonal in S_i"; return false; }
     if (refactor && !hs.pk_factored) {
+        // multigrid K_m: the same aggregation and transfers, each level's
+        // matrix moved by (gamma' - gamma) times its Galerkin mass part
         if (P.inner_pk == BIDO_PK_AMG) {
-            Amg na;
             std::string e2;
-            if (!amg_build(Kmp, -1, AmgOptions(), na, e2)) { err = "P_K: " + e2; return false; }
-            hs.amgk = std::move(na);
+            if (!amg_refresh_gamma(hs.amgk, gamma, e2)) { err = "P_K: " + e2; return false; }
         }
     } else if (refactor) {
         Factor nf;

@@ -61,8 +61,9 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
 // New time step: gamma (the coefficient of M_H in Lambda and K_m, Sec. 3.2)
 // and the stimulus step range follow dt; the v-v diagonal of Lambda and
 // K_m are recomputed as at set-up (bit-identical to a set-up at dt).  With
-// refactor, K_m is factored again in its elimination tree (P_1 does not
-// depend on dt).
+// refactor, K_m is factored again in its elimination tree, or its multigrid
+// hierarchy is moved to the new gamma on the same aggregation
+// (amg_refresh_gamma); P_1 does not depend on dt.
 bool host_set_dt(HostSetup& hs, double dt, bool refactor, std::string& err);
 
 // The blocked form of hs.lam (LamBlocked); false when the heart is not the

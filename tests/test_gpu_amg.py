@@ -147,8 +147,8 @@ def test_learned_stencil_with_multigrid_pk(torch):
 
 
 def test_set_dt_with_multigrid_pk(torch):
-    """A time-step change rebuilds the hierarchy of the new K_m; steps after
-    it match the oracle at the new step."""
+    """A time-step change moves the hierarchy to the new K_m; steps after it
+    match the oracle at the new step."""
     import paper_1711_08708_amd as B
     from oracle import bidomain as bd
     cfg = CASES["slab16"]()
@@ -162,6 +162,32 @@ def test_set_dt_with_multigrid_pk(torch):
         Uo, Vo, _ = s.step(Vn, hn, n)
         eu, ev = _errs(u.cpu().numpy(), v.cpu().numpy(), s.to_global_u(Uo), Vo)
         assert eu <= TOL_PARITY and ev <= TOL_PARITY, (n, eu, ev)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_new_time_step_moves_the_hierarchy_on_the_device(torch, precision):
+    """bido_set_dt with a multigrid P_K moves every level to the new gamma on
+    the device (mass parts, D^-1, the smoother copy, the Lanczos bound, the
+    coarsest inverse by Gauss-Jordan): one device V-cycle equals the host
+    cycle of a set-up moved the same way (the host's refresh is pinned to the
+    Galerkin products and the oracle cycle on the CPU), twice in a row; and
+    it takes a fraction of a fresh set-up."""
+    import paper_1711_08708_amd as B
+    cfg = CASES["slab16"]()
+    solver = B.Solver(cfg, eps_h=0.0, tol=1e-11, inner_p1=B.P1_AMG, inner_pk=B.PK_AMG,
+                      precision=B.PREC_MIXED if precision == "mixed" else B.PREC_FP64)
+    hs = B.HostSetup(cfg, eps_h=0.0, inner_p1=B.P1_AMG, inner_pk=B.PK_AMG)
+    rng = np.random.default_rng(2)
+    for dt in (cfg["dt"] / 3, cfg["dt"] * 2):
+        sec = solver.set_dt(dt)
+        hs.set_dt(dt)
+        b = rng.normal(size=solver.NH)
+        x = torch.zeros(solver.NH, dtype=torch.float64, device="cuda")
+        solver.inner_solve(B.FACTOR_PK, torch.tensor(b, device="cuda"), x)
+        xh = hs.amg_apply(B.FACTOR_PK, b)
+        err = np.linalg.norm(x.cpu().numpy() - xh) / np.linalg.norm(xh)
+        print(f"dt {dt}: set_dt {sec * 1e3:.1f} ms, device vs host cycle {err:.2e}", flush=True)
+        assert err <= (1e-5 if precision == "mixed" else 1e-11)
 
 
 def test_factor_only_calls_refuse_multigrid_blocks(torch):

@@ -128,6 +128,39 @@ def test_library_hierarchy_is_galerkin_and_its_cycle_is_the_oracle_cycle(mk):
             assert xl[-1] == 0.0 and levels[0]["dinv"][-1] == 0.0   # the grounded vertex
 
 
+def test_new_time_step_keeps_the_aggregation_and_moves_every_level():
+    """A change of time step moves K_m = gamma M_H + S_m; the multigrid P_K
+    keeps its prolongations and each level becomes the Galerkin product of
+    the new K_m (checked level by level against P^T A P in NumPy), with new
+    D^-1 and a smoother bound above the spectrum of D^-1 A; the library's
+    host cycle is the oracle cycle on the moved hierarchy."""
+    import paper_1711_08708_amd as B
+    cfg = w.slab3d(n=10)
+    hs = B.HostSetup(cfg, eps_h=0.0, inner_p1=B.P1_AMG, inner_pk=B.PK_AMG)
+    info = hs.amg_info(B.FACTOR_PK)
+    before = [hs.amg_level(B.FACTOR_PK, l) for l in range(info["levels"])]
+    hs.set_dt(cfg["dt"] / 4)
+    assert hs.amg_info(B.FACTOR_PK)["levels"] == info["levels"]
+    after = [hs.amg_level(B.FACTOR_PK, l) for l in range(info["levels"])]
+    K = hs.csr(B.MAT_KM)
+    A = K
+    for l, (b, a) in enumerate(zip(before, after)):
+        np.testing.assert_allclose(a["A"].toarray(), A.toarray(), atol=1e-12 * abs(A).max())
+        assert not np.allclose(a["A"].toarray(), b["A"].toarray())        # really moved
+        if a["P"] is None:
+            break
+        assert (a["P"] != b["P"]).nnz == 0                                 # same transfer
+        np.testing.assert_allclose(a["dinv"], 1.0 / a["A"].diagonal(), rtol=1e-14)
+        lam = np.linalg.eigvalsh((sp.diags(np.sqrt(a["dinv"])) @ a["A"] @ sp.diags(np.sqrt(a["dinv"]))).toarray())
+        assert lam.max() <= a["hi"] <= 1.2 * lam.max()
+        G = (a["P"].T @ a["A"] @ a["P"])
+        A = sp.csr_matrix(0.5 * (G + G.T))
+    bvec = np.random.default_rng(9).normal(size=K.shape[0])
+    xo = mg.vcycle(after, info["smooth_steps"], bvec)
+    xl = hs.amg_apply(B.FACTOR_PK, bvec)
+    assert np.linalg.norm(xl - xo) <= 1e-11 * np.linalg.norm(xo)
+
+
 @pytest.mark.parametrize("n", [16, 24])
 def test_multigrid_p1_converges_in_few_iterations(n):
     """CG on the grounded S_1 of a slab with the library's host V-cycle:
