@@ -469,6 +469,7 @@ struct GnnState {
     double *s_zz = nullptr;
     double *pend_t = nullptr, *pend_v = nullptr;
     bool stencil_ready = false;
+    bool wk_like_k = false;                // Wk stores K_m's pattern in K_m's order
     // pairs from consecutive steps instead of PCG iterates (an inexact P_1):
     // K (V^{n+1} - V^n) = Y_2^n - Y_2^{n-1}, exact whatever the inner solves
     bool increments = false, inc_ok = false;
@@ -480,7 +481,10 @@ struct GnnState {
                         (void*)act.f, (void*)act.m0, (void*)act.h1, (void*)act.m1, (void*)act.h2,
                         (void*)act.o, (void*)act.dout, (void*)act.dz2, (void*)act.g2, (void*)act.dz1,
                         (void*)partials, (void*)dloss, (void*)ft, (void*)fy, (void*)tz, (void*)s_t,
-                        (void*)s_y, (void*)s_tn2, (void*)pend, (void*)inc_v, (void*)inc_y})
+                        (void*)s_y, (void*)s_tn2, (void*)pend, (void*)inc_v, (void*)inc_y, (void*)P.ptr,
+                        (void*)P.col, (void*)P.row, (void*)P.tpos, (void*)K.ptr, (void*)K.col, (void*)K.val,
+                        (void*)cval, (void*)G, (void*)r, (void*)s_z, (void*)s_b, (void*)s_zz, (void*)pend_t,
+                        (void*)pend_v})
             hipFree(b);
         *this = GnnState();
     }
@@ -547,6 +551,7 @@ struct bido_ctx {
     std::unique_ptr<Factor> pk_learned_host;   // its host factor (a fused batch merges it)
     AmgDev amg1, amgk;                // multigrid P_1 / P_K (inner_p1 / inner_pk = AMG)
     LamBlk lamb;                      // blocked Lambda (heart = whole mesh, one order)
+    int64_t* lam_vdiag = nullptr;     // positions of the v-v diagonal in Lambda's values
     float *avu32 = nullptr, *auv32 = nullptr;   // FP32 values of S_i Pi, Pi^T S_i (mixed precision)
     AmgDev amgk_learned;              // multigrid of K_m + C (learned stencil with a multigrid P_K)
     int precond = BIDO_PRECOND_PLAIN;
@@ -593,6 +598,7 @@ struct bido_ctx {
         rec.release();
         CsrHostView::release(lam);
         release_lam_blk(lamb);
+        hipFree(lam_vdiag);
         hipFree(avu32);
         hipFree(auv32);
         CsrHostView::release(avu);
@@ -1299,6 +1305,30 @@ bido_status step_once(bido_ctx* c, double* v, double* w, double* u, int64_t n, b
     return step_end(c, v, w, u, ps, st);
 }
 
+// Weights: fan-in scaled normal, zero biases; the readout starts at zero so
+// that an untrained correction is exactly the plain preconditioner.  Adam's
+// moments start at zero.
+bido_status gnn_init_weights(bido_ctx* c) {
+    GnnState& g = c->gnn;
+    std::vector<float> th(GNN_P, 0.0f);
+    std::mt19937_64 rng(12345);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (int k = 0; k < GNN_H * GNN_F; ++k) {
+        th[GNN_OFF_W1S + k] = (float)(nd(rng) / std::sqrt((double)GNN_F));
+        th[GNN_OFF_W1N + k] = (float)(nd(rng) / std::sqrt((double)GNN_F));
+    }
+    for (int k = 0; k < GNN_H * GNN_H; ++k) {
+        th[GNN_OFF_W2S + k] = (float)(nd(rng) / std::sqrt((double)GNN_H));
+        th[GNN_OFF_W2N + k] = (float)(nd(rng) / std::sqrt((double)GNN_H));
+    }
+    HIP_OK(hipMemcpy(g.theta, th.data(), GNN_P * sizeof(float), hipMemcpyHostToDevice));
+    for (float* b : {g.m, g.v, g.grad}) HIP_OK(hipMemset(b, 0, GNN_P * sizeof(float)));
+    launch_gnn_to_bf16(c->stream, g.theta, g.wbf);
+    g.adam_step = 0;
+    g.out_scale = 1.0f;
+    return BIDO_OK;
+}
+
 bido_status gnn_setup(bido_ctx* c) {
     GnnState& g = c->gnn;
     const HostSetup& hs = c->hs;
@@ -1383,26 +1413,18 @@ bido_status gnn_setup(bido_ctx* c) {
             }
         if ((e = up_graph(wrows, g.Wk))) return e;
     }
-    // weights: fan-in scaled normal, zero biases; the readout starts at zero
-    // so that an untrained correction is exactly the plain preconditioner
-    std::vector<float> th(GNN_P, 0.0f);
-    std::mt19937_64 rng(12345);
-    std::normal_distribution<double> nd(0.0, 1.0);
-    for (int k = 0; k < GNN_H * GNN_F; ++k) {
-        th[GNN_OFF_W1S + k] = (float)(nd(rng) / std::sqrt((double)GNN_F));
-        th[GNN_OFF_W1N + k] = (float)(nd(rng) / std::sqrt((double)GNN_F));
+    g.wk_like_k = g.Wk.n == NH && hs.km_int.ptr.size() == (size_t)NH + 1;
+    if (g.wk_like_k) {       // the scaled copy shares K_m's stored pattern (a new step moves values only)
+        std::vector<int64_t> wp(NH + 1);
+        std::vector<int32_t> wc(std::max<int64_t>(hs.km_int.nnz(), 1));
+        HIP_OK(hipMemcpy(wp.data(), g.Wk.ptr, wp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(wc.data(), g.Wk.col, wc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        g.wk_like_k = wp == hs.km_int.ptr &&
+                      std::equal(hs.km_int.col.begin(), hs.km_int.col.end(), wc.begin());
     }
-    for (int k = 0; k < GNN_H * GNN_H; ++k) {
-        th[GNN_OFF_W2S + k] = (float)(nd(rng) / std::sqrt((double)GNN_H));
-        th[GNN_OFF_W2N + k] = (float)(nd(rng) / std::sqrt((double)GNN_H));
-    }
-    HIP_OK(upload(&g.theta, th.data(), th.size()));
-    for (float** b : {&g.m, &g.v, &g.grad}) {
-        HIP_OK(hipMalloc((void**)b, GNN_P * sizeof(float)));
-        HIP_OK(hipMemset(*b, 0, GNN_P * sizeof(float)));
-    }
+    for (float** b : {&g.theta, &g.m, &g.v, &g.grad}) HIP_OK(hipMalloc((void**)b, GNN_P * sizeof(float)));
     HIP_OK(hipMalloc((void**)&g.wbf, GNN_P * sizeof(uint16_t)));
-    launch_gnn_to_bf16(c->stream, g.theta, g.wbf);
+    if ((e = gnn_init_weights(c))) return e;
     const int64_t nh = std::max<int64_t>(NH, 1);
     for (uint16_t** b : {&g.act.f, &g.act.m0}) HIP_OK(hipMalloc((void**)b, nh * GNN_F * sizeof(uint16_t)));
     for (uint16_t** b : {&g.act.h1, &g.act.m1, &g.act.h2}) HIP_OK(hipMalloc((void**)b, nh * GNN_H * sizeof(uint16_t)));
@@ -1414,6 +1436,46 @@ bido_status gnn_setup(bido_ctx* c) {
     HIP_OK(hipMalloc((void**)&g.partials, np * sizeof(float)));
     HIP_OK(hipMalloc((void**)&g.dloss, 4 * sizeof(double)));
     HIP_OK(hipMalloc((void**)&g.tz, nh * sizeof(double)));
+    return BIDO_OK;
+}
+
+// A new time step: K_m's values (its device copy, its mean diagonal and the
+// loss weights K_m / mean diagonal) move with gamma, its pattern does not;
+// the pairs, weights and stencil fitted at the old step are dropped and the
+// weights start again from their initial values.
+bido_status gnn_new_step(bido_ctx* c) {
+    GnnState& g = c->gnn;
+    const HostSetup& hs = c->hs;
+    const Csr& Km = hs.km_int;
+    const int64_t NH = c->NH;
+    if (!g.wk_like_k) {                    // (not expected: a full set-up again)
+        g.release();
+        return gnn_setup(c);
+    }
+    HIP_OK(hipMemcpy(g.K.val, Km.val.data(), std::max<size_t>(Km.val.size(), 1) * sizeof(double),
+                     hipMemcpyHostToDevice));
+    double dsum = 0.0;
+    for (int64_t i = 0; i < NH; ++i)
+        for (int64_t p = Km.ptr[i]; p < Km.ptr[i + 1]; ++p)
+            if (Km.col[p] == i) dsum += Km.val[p];
+    g.dbar = dsum / std::max<int64_t>(NH, 1);
+    double ds = 0.0;                       // the loss weights' scale, in the set-up's order
+    for (int64_t k = 0; k < NH; ++k) ds += hs.gamma * hs.A.mH[k];
+    for (int64_t k = 0; k < NH; ++k)
+        for (int64_t p = hs.A.Sm.ptr[k]; p < hs.A.Sm.ptr[k + 1]; ++p)
+            if (hs.A.Sm.col[p] == k) ds += hs.A.Sm.val[p];
+    const double dmean = ds / std::max<int64_t>(NH, 1);
+    std::vector<float> wv(std::max<int64_t>(Km.nnz(), 1), 0.0f);
+    for (int64_t p = 0; p < Km.nnz(); ++p) wv[p] = (float)(Km.val[p] / dmean);
+    HIP_OK(hipMemcpy(g.Wk.val, wv.data(), wv.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (bido_status e = gnn_init_weights(c)) return e;
+    g.n_samples = 0;
+    g.n_pending = 0;
+    g.collecting = false;
+    g.stencil_ready = false;
+    g.increments = false;
+    g.inc_ok = false;
+    HIP_OK(hipStreamSynchronize(c->stream));
     return BIDO_OK;
 }
 
@@ -1821,6 +1883,13 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     bido_status e;
     if ((e = CsrHostView::up(hs.lam, c->lam))) return e;
     if ((e = upload_lam_blk(hs, c->lamb))) return e;
+    {
+        std::vector<int64_t> pos(std::max<int64_t>(c->NH, 1), 0);
+        for (int64_t k = 0; k < c->NH; ++k)
+            for (int64_t q = hs.lam.ptr[c->N + k]; q < hs.lam.ptr[c->N + k + 1]; ++q)
+                if (hs.lam.col[q] == c->N + k) pos[k] = q;
+        HIP_OK(upload(&c->lam_vdiag, pos.data(), pos.size()));
+    }
     if ((e = CsrHostView::up(hs.avu, c->avu))) return e;
     if ((e = CsrHostView::up(hs.auv, c->auv))) return e;
     for (auto [src, dst] : {std::pair<const Csr*, float**>{&hs.avu, &c->avu32}, {&hs.auv, &c->auv32}}) {
@@ -2631,11 +2700,22 @@ static bido_status amg_refresh_device(bido_ctx* c, AmgDev& M, double gamma) {
 }
 
 static bido_status set_dt_device(bido_ctx* c, bool refactor) {
-    // Lambda: only its v-v diagonal changed, but the values go up whole
-    HIP_OK(hipMemcpy(c->lam.val, c->hs.lam.val.data(), c->hs.lam.val.size() * sizeof(double),
-                     hipMemcpyHostToDevice));
-    if (c->lamb.on())
-        if (bido_status e = upload_lam_blk(c->hs, c->lamb)) return e;
+    // Lambda: only its v-v diagonal changed; its new values go to their
+    // positions (and gm of the blocked form)
+    {
+        const Csr& L = c->hs.lam;
+        const int64_t N = c->N, NH = c->NH;
+        std::vector<double> dv(NH);
+        for (int64_t k = 0; k < NH; ++k)
+            for (int64_t q = L.ptr[N + k]; q < L.ptr[N + k + 1]; ++q)
+                if (L.col[q] == N + k) dv[k] = L.val[q];
+        HIP_OK(hipMemcpy(c->tB, dv.data(), NH * sizeof(double), hipMemcpyHostToDevice));
+        launch_scatter_in(c->stream, NH, c->lam_vdiag, c->tB, c->lam.val);
+        if (c->lamb.on())
+            HIP_OK(hipMemcpyAsync(c->lamb.gm, c->hs.lamb.gm.data(), c->lamb.n * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+    }
     if (c->amgk.on())      // (also when another P_K is active: kept at the current gamma)
         if (bido_status e = amg_refresh_device(c, c->amgk, c->hs.gamma)) return e;
     if (refactor && c->pk_kind == BIDO_PK_CHOLESKY) {
@@ -2664,8 +2744,7 @@ static bido_status set_dt_device(bido_ctx* c, bool refactor) {
     if (c->pk_learned.nodes) c->pk_learned.release();
     c->pk_learned_host.reset();
     c->amgk_learned.release();
-    c->gnn.release();
-    if (bido_status e = gnn_setup(c)) return e;
+    if (bido_status e = gnn_new_step(c)) return e;
     c->precond = BIDO_PRECOND_PLAIN;
     HIP_OK(hipDeviceSynchronize());
     return BIDO_OK;

@@ -387,10 +387,19 @@ bool host_set_dt(HostSetup& hs, double dt, bool refactor, std::string& err) {
     const int64_t N = A.N, NH = A.NH;
     const double gamma = P.chi * P.cm / dt * (P.scheme == BIDO_SCHEME_EULER ? 1.0 : 2.0);
     const NdTree& tk = hs.pk.tree;
-    // K_m = gamma M_H + S_m, as at set-up
-    Csr Km = add_diag(A.Sm, A.mH, gamma);
-    if (Km.n < 0) { err = "missing diagonal in S_m"; return false; }
-    Csr Kmp = permute(Km, tk.perm, tk.iperm);
+    // K_m = gamma M_H + S_m, as at set-up: only its diagonal moves, written
+    // with the set-up's arithmetic (S_m's diagonal plus gamma m) into a copy
+    Csr Kmp = hs.km_int;
+    for (int64_t l = 0; l < NH; ++l) {
+        const int64_t k = tk.perm[l];
+        double sm = 0.0;
+        bool f = false;
+        for (int64_t q = A.Sm.ptr[k]; q < A.Sm.ptr[k + 1]; ++q)
+            if (A.Sm.col[q] == k) { sm = A.Sm.val[q]; f = true; }
+        if (!f) { err = "missing diagonal in S_m"; return false; }
+        for (int64_t q = Kmp.ptr[l]; q < Kmp.ptr[l + 1]; ++q)
+            if (Kmp.col[q] == l) Kmp.val[q] = sm + gamma * A.mH[k];
+    }
     // the v-v diagonal of Lambda: S_i(k, k) + gamma m_k
     std::vector<double> sdiag(NH, 0.0);
     bool found = true;
@@ -425,7 +434,17 @@ bool host_set_dt(HostSetup& hs, double dt, bool refactor, std::string& err) {
     hs.km_int = std::move(Kmp);
     hs.gamma = gamma;
     P.dt = dt;
-    if (hs.lamb.n > 0 && !build_lam_blocked(hs, hs.lamb)) { err = "blocked Lambda"; return false; }
+    if (hs.lamb.n > 0) {     // only gm = the v-v diagonal minus S_i's moves
+        LamBlocked& b = hs.lamb;
+        for (int64_t k = 0; k < b.n; ++k) {
+            double si = 0.0, vv = 0.0;
+            for (int64_t q = b.ptr[k]; q < b.ptr[k + 1]; ++q)
+                if (b.col[q] == k) si = b.val[2 * q + 1];
+            for (int64_t q = L.ptr[N + k]; q < L.ptr[N + k + 1]; ++q)
+                if (L.col[q] == N + k) vv = L.val[q];
+            b.gm[k] = vv - si;
+        }
+    }
     hs.stim_n0 = std::llround(hs.stim_t0 / dt);
     hs.stim_n1 = std::llround(hs.stim_t1 / dt);
     return true;

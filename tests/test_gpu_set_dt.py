@@ -99,13 +99,16 @@ def test_set_dt_resets_the_learned_correction(torch):
     import paper_1711_08708_amd as B
     cfg = w.thorax2d(n_target=3000, seed=11)
     sv = B.Solver(cfg, tol=1e-10)
+    w0 = sv.weights()
     v, h, u = sv.state()
     col = sv.learn_collect(v, h, u, 0, 6, max_samples=64)
     assert col["samples"] > 0
     ts = sv.learn_train(kind=B.LEARN_STENCIL, epochs=2, batch=8, lr=2e-3, seed=0, n_val=1)
     if ts["spd"]:
         sv.set_precond(B.PRECOND_LEARNED)
+    assert not np.array_equal(sv.weights(), w0)
     sv.set_dt(0.05)
+    assert np.array_equal(sv.weights(), w0)          # the weights start again
     n = ctypes.c_int()
     B._check(B.lib.bido_learn_samples(sv.ctx, ctypes.byref(n)))
     assert n.value == 0
