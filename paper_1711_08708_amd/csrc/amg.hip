@@ -16,8 +16,11 @@ namespace bido {
 namespace {
 
 constexpr int BLOCK = 256;
-constexpr int RU = 4;
-constexpr int ITER = 2;       // row rounds of RU rows per lane group and workgroup
+// rows per lane group in flight, and rounds of them per workgroup: many
+// small workgroups (128^3 slab, mixed: RU 2 / ITER 1 gives 20.2 steps/s,
+// 4 / 1 19.7, 4 / 2 18.2, 8 / 1 13.1, 4 / 4 16.0)
+constexpr int RU = 2;
+constexpr int ITER = 1;
 
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {

@@ -380,18 +380,32 @@ def test_fused_batch_chebyshev_pk(torch):
         sv.close()
 
 
-def test_fused_batch64_sampled_slices_full_size(torch):
-    """batch64 at full size, in the fused configuration the bench times: the
-    smallest and the largest of its 64 slices plus two others (one of them
-    with a heart in two parts), 3 steps in one fused batch, each slice's last
-    step against the FP64 oracle at 1e-8."""
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("mode", ["fp64", "mixed_learned"])
+def test_fused_batch64_sampled_slices_full_size(torch, mode):
+    """batch64 at full size, in the fused configuration the bench times (FP64
+    plain, and mixed precision with every slice's learned stencil, trained
+    on pairs of its first steps): the smallest, the median and the largest
+    of its 64 slices plus two others (one of them with a heart in two
+    parts), 3 steps in one fused batch, each slice's last step against the
+    FP64 oracle at 1e-8."""
     import paper_1711_08708_amd as B
-    from oracle import bidomain as bd
+    from oracle import bidomain as bd, mpnn
     kws = w.make_config("batch64")
     sizes = [kw["n_target"] for kw in kws]
-    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 20})
+    pick = sorted({int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2]), int(np.argmax(sizes)), 7, 20})
     cfgs = [w.thorax2d(**kws[k]) for k in pick]
-    solvers = [B.Solver(cfg, tol=1e-10, eps_h=1e-8) for cfg in cfgs]
+    prec = B.PREC_MIXED if mode == "mixed_learned" else B.PREC_FP64
+    solvers = [B.Solver(cfg, tol=1e-10, eps_h=1e-8, precision=prec) for cfg in cfgs]
+    if mode == "mixed_learned":
+        theta = mpnn.init_params(3) * np.concatenate([np.ones(mpnn.N_PARAMS - 33), np.zeros(33)])
+        for sv in solvers:
+            sv.set_weights(theta)
+            v, h, u = sv.state()
+            sv.learn_collect(v, h, u, 0, 6, max_samples=48)
+            ts = sv.learn_train(kind=B.LEARN_STENCIL, epochs=10, batch=8, lr=2e-3, seed=0, n_val=2)
+            assert ts["spd"] == 1
+            sv.set_precond(B.PRECOND_LEARNED)
     batch = B.Batch(solvers, fused=True)
     states = [s.state() for s in solvers]
     batch.run(states, 0, 2)
