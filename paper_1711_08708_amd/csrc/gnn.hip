@@ -61,53 +61,6 @@ __global__ void k_agg(int64_t n, const int64_t* __restrict__ ptr, const int32_t*
     out[id] = f2bf(s);
 }
 
-// h_i = relu(Ws x_i + Wn m_i + b); with READOUT also o_i = w3 . h_i + b3,
-// added (times rms(t) * out_scale) to z2 in inference mode.  8 vertices x 32 units
-// per block; weights staged in LDS.
-template <int IN, bool READOUT>
-__global__ __launch_bounds__(BLOCK) void k_layer(int64_t n, const uint16_t* __restrict__ x,
-                                                 const uint16_t* __restrict__ m,
-                                                 const uint16_t* __restrict__ wbf, int off_ws, int off_wn,
-                                                 int off_b, uint16_t* __restrict__ h, float* __restrict__ o,
-                                                 const double* __restrict__ tn2, double* __restrict__ z2,
-                                                 float out_scale) {
-    __shared__ float ws[GNN_H * IN], wn[GNN_H * IN], bb[GNN_H], w3[GNN_H];
-    __shared__ float xs[BLOCK / GNN_H][IN], ms[BLOCK / GNN_H][IN];
-    for (int k = threadIdx.x; k < GNN_H * IN; k += BLOCK) {
-        ws[k] = bf2f(wbf[off_ws + k]);
-        wn[k] = bf2f(wbf[off_wn + k]);
-    }
-    if (threadIdx.x < GNN_H) {
-        bb[threadIdx.x] = bf2f(wbf[off_b + threadIdx.x]);
-        w3[threadIdx.x] = bf2f(wbf[GNN_OFF_W3 + threadIdx.x]);
-    }
-    const int nl = threadIdx.x / GNN_H, a = threadIdx.x % GNN_H;
-    const int64_t i = blockIdx.x * (int64_t)(BLOCK / GNN_H) + nl;
-    for (int k = a; k < IN; k += GNN_H)
-        if (i < n) {
-            xs[nl][k] = bf2f(x[i * IN + k]);
-            ms[nl][k] = bf2f(m[i * IN + k]);
-        }
-    __syncthreads();
-    if (i >= n) return;   // whole 32-lane groups leave together
-    float z = bb[a];
-#pragma unroll 8
-    for (int k = 0; k < IN; ++k) z += ws[a * IN + k] * xs[nl][k] + wn[a * IN + k] * ms[nl][k];
-    const float hv = z > 0.0f ? z : 0.0f;
-    const uint16_t hb = f2bf(hv);
-    if (h) h[i * GNN_H + a] = hb;
-    if (READOUT) {
-        float s = w3[a] * bf2f(hb);
-#pragma unroll
-        for (int msk = GNN_H / 2; msk > 0; msk >>= 1) s += __shfl_xor(s, msk, WAVE);
-        if (a == 0) {
-            const float ov = s + bf2f(wbf[GNN_OFF_B3]);
-            if (o) o[i] = ov;
-            if (z2) z2[i] += sqrt(*tn2 / (double)n) * (double)out_scale * (double)ov;
-        }
-    }
-}
-
 // r_i = o_i - y_i * yinv
 __global__ void k_resid(int64_t n, const float* __restrict__ o, const float* __restrict__ y, float yinv,
                         float* __restrict__ r) {
@@ -339,16 +292,84 @@ __global__ void k_finish_targets(int64_t n, const double* __restrict__ vstar, co
     y[i] = rms > 0.0 ? (float)((vstar[i] - d[i]) / rms) : 0.0f;
 }
 
+// One layer, h_i = relu(Ws x_i + Wn m_i + b); with READOUT also
+// o_i = w3 . h_i + b3, added (times rms(t) * out_scale) to z2 in inference
+// mode.  On the matrix cores: each wave computes a tile of 32 vertices x 32
+// units as X Ws^T + M Wn^T with FP32 MFMA 32x32x2 steps
+// (lane l feeds A = X[v0 + l % 32][k0 + l / 32] from the wave's LDS copy of
+// the tile's inputs and B = Ws[l % 32][k0 + l / 32], held in registers for
+// every k0), BF16 inputs widened exactly to FP32, FP32 accumulation.
+// D[row][col]: row = 8 (r / 4) + 4 (l / 32) + r % 4 (vertex),
+// col = l % 32 (unit).  The readout sums the 32 units of a vertex across
+// the lanes of one half-wave.  Workgroups of four waves take 128 vertices
+// per round (a round count uniform over the workgroup).
+template <int IN, bool READOUT>
+__global__ __launch_bounds__(256) void k_layer_mfma(int64_t n, const uint16_t* __restrict__ x,
+                                                    const uint16_t* __restrict__ m,
+                                                    const uint16_t* __restrict__ wbf, int off_ws, int off_wn,
+                                                    int off_b, uint16_t* __restrict__ h, float* __restrict__ o,
+                                                    const double* __restrict__ tn2, double* __restrict__ z2,
+                                                    float out_scale) {
+    __shared__ float xs[4][32][IN + 1], ms[4][32][IN + 1];
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int a = lane % 32, half = lane / 32;
+    float wsr[IN / 2], wnr[IN / 2];
+#pragma unroll
+    for (int j = 0; j < IN / 2; ++j) {
+        wsr[j] = bf2f(wbf[off_ws + a * IN + 2 * j + half]);
+        wnr[j] = bf2f(wbf[off_wn + a * IN + 2 * j + half]);
+    }
+    const float bias = bf2f(wbf[off_b + a]);
+    const float w3 = READOUT ? bf2f(wbf[GNN_OFF_W3 + a]) : 0.0f;
+    const float b3 = READOUT ? bf2f(wbf[GNN_OFF_B3]) : 0.0f;
+    const double zscale = (READOUT && z2) ? sqrt(*tn2 / (double)n) * (double)out_scale : 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * 128; base < n; base += (int64_t)gridDim.x * 128) {
+        const int64_t v0 = base + wave * 32;
+        for (int e = lane; e < 32 * IN; e += WAVE) {
+            const int r = e / IN, k = e % IN;
+            const int64_t v = v0 + r;
+            xs[wave][r][k] = v < n ? bf2f(x[v * IN + k]) : 0.0f;
+            ms[wave][r][k] = v < n ? bf2f(m[v * IN + k]) : 0.0f;
+        }
+        __syncthreads();
+        floatx16 acc = {};
+#pragma unroll
+        for (int j = 0; j < IN / 2; ++j) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[wave][a][2 * j + half], wsr[j], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ms[wave][a][2 * j + half], wnr[j], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r / 4) + 4 * half + (r % 4);
+            const int64_t v = v0 + row;
+            const float z = acc[r] + bias;
+            const uint16_t hb = f2bf(z > 0.0f ? z : 0.0f);
+            if (h && v < n) h[v * GNN_H + a] = hb;
+            if (READOUT) {
+                float s = w3 * bf2f(hb);
+#pragma unroll
+                for (int msk = 16; msk > 0; msk >>= 1) s += __shfl_xor(s, msk, 32);
+                if (a == 0 && v < n) {
+                    const float ov = s + b3;
+                    if (o) o[v] = ov;
+                    if (z2) z2[v] += zscale * (double)ov;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 void forward_common(hipStream_t s, int64_t n, const GnnGraph& A, const uint16_t* wbf, GnnAct& a, int mode,
                     const double* tn2, double* z2, float out_scale) {
     k_agg<GNN_F><<<blocks_for(n * GNN_F), BLOCK, 0, s>>>(n, A.ptr, A.col, A.val, a.f, a.m0);
-    const unsigned gb = blocks_for(n * GNN_H);
-    k_layer<GNN_F, false><<<gb, BLOCK, 0, s>>>(n, a.f, a.m0, wbf, GNN_OFF_W1S, GNN_OFF_W1N, GNN_OFF_B1, a.h1,
-                                               nullptr, nullptr, nullptr, 1.0f);
+    const unsigned gb = (unsigned)std::min<int64_t>((n + 127) / 128, 16384);
+    k_layer_mfma<GNN_F, false><<<gb, 256, 0, s>>>(n, a.f, a.m0, wbf, GNN_OFF_W1S, GNN_OFF_W1N, GNN_OFF_B1, a.h1,
+                                                   nullptr, nullptr, nullptr, 1.0f);
     k_agg<GNN_H><<<blocks_for(n * GNN_H), BLOCK, 0, s>>>(n, A.ptr, A.col, A.val, a.h1, a.m1);
-    k_layer<GNN_H, true><<<gb, BLOCK, 0, s>>>(n, a.h1, a.m1, wbf, GNN_OFF_W2S, GNN_OFF_W2N, GNN_OFF_B2,
-                                              mode == 1 ? a.h2 : nullptr, mode == 1 ? a.o : nullptr,
-                                              tn2, mode == 0 ? z2 : nullptr, out_scale);
+    k_layer_mfma<GNN_H, true><<<gb, 256, 0, s>>>(n, a.h1, a.m1, wbf, GNN_OFF_W2S, GNN_OFF_W2N, GNN_OFF_B2,
+                                                  mode == 1 ? a.h2 : nullptr, mode == 1 ? a.o : nullptr,
+                                                  tn2, mode == 0 ? z2 : nullptr, out_scale);
 }
 
 }  // namespace
