@@ -362,6 +362,7 @@ void launch_amg_dense_inverse(hipStream_t s, int64_t n, const int64_t* ptr, cons
     {                                                                               \
         const int kk = unroll_for(A);                                               \
         switch (A.group) {                                                          \
+            case 2: { constexpr int GG = 2; BIDO_K_SWITCH(kk, __VA_ARGS__) } break;   \
             case 4: { constexpr int GG = 4; BIDO_K_SWITCH(kk, __VA_ARGS__) } break;   \
             case 8: { constexpr int GG = 8; BIDO_K_SWITCH(kk, __VA_ARGS__) } break;   \
             case 16: { constexpr int GG = 16; BIDO_K_SWITCH(kk, __VA_ARGS__) } break; \

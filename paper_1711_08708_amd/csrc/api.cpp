@@ -355,13 +355,15 @@ struct AmgDev {
 };
 
 // lanes per row of a multigrid product: one lane per two to four entries
-// of the average row (4 to 64 lanes; the kernels unroll the passes the row
+// of the average row (2 to 64 lanes; the kernels unroll the passes the row
 // needs).  Measured on the 128^3 slab against one lane per one or two
 // entries (fine-level products 10-15 % faster) and per four to eight
-// entries (restriction and coarser levels 5-20 % slower).
+// entries (restriction and coarser levels 5-20 % slower, the finest
+// level's A with 2 lanes 20 % slower; the prolongations, ~6 entries per
+// row, 6 % faster with 2).
 int group_for(const Csr& a) {
     const double avg = a.n > 0 ? (double)a.nnz() / (double)a.n : 0.0;
-    return avg <= 16 ? 4 : avg <= 32 ? 8 : avg <= 64 ? 16 : avg <= 128 ? 32 : 64;
+    return avg <= 8 ? 2 : avg <= 16 ? 4 : avg <= 32 ? 8 : avg <= 64 ? 16 : avg <= 128 ? 32 : 64;
 }
 
 bido_status upload_amg(const Amg& M, AmgDev& d) {
