@@ -399,7 +399,8 @@ def _bench_slab128(args):
     n_val = max(1, col["samples"] // 10)
     ts = solver.learn_train(kind=B.LEARN_STENCIL, epochs=args.epochs, batch=8, lr=2e-3, seed=0, n_val=n_val)
     print(f"[bench] trained the stencil in {ts['seconds']:.1f} s (hierarchy of K_m + C "
-          f"{ts['refactor_seconds']:.1f} s), loss {ts['loss_zero']:.3g} -> {ts['loss_last']:.3g}",
+          f"{ts['refactor_seconds']:.1f} s), loss {ts['loss_zero']:.3g} -> {ts['loss_last']:.3g}, "
+          f"held-out {ts['loss_zero_val']:.3g} -> {ts['loss_val']:.3g}, kept epoch {ts['best_epoch']}",
           file=sys.stderr, flush=True)
     saved = [t.clone() for t in (v, h, u)]
     n1 = args.collect_steps
@@ -510,7 +511,8 @@ def _bench_slab128(args):
                      "collect_s": round(t_col, 2), "train_s": round(ts["seconds"], 2),
                      "hierarchy_s": round(ts["refactor_seconds"], 2), "spd": ts["spd"], "epochs": args.epochs,
                      "loss_zero": ts["loss_zero"], "loss_trained": ts["loss_last"],
-                     "loss_zero_val": ts["loss_zero_val"], "loss_val": ts["loss_val"]},
+                     "loss_zero_val": ts["loss_zero_val"], "loss_val": ts["loss_val"],
+                     "best_epoch": ts["best_epoch"]},
         "roofline": roofline,
         "kernels": kernels,
         "dt_change": dt_change,

@@ -372,6 +372,9 @@ typedef struct {
     double seconds;
     int spd;                /* stencil: K_m + C factored (1) or not (0)       */
     double refactor_seconds;
+    int best_epoch;         /* stencil: the epoch whose weights are kept (the
+                               lowest validation loss, or training loss when
+                               n_val = 0; 0: the weights before training)   */
 } bido_train_stats;
 
 /* BIDO_PRECOND_* for later solves; BIDO_PRECOND_LEARNED needs a trained
@@ -386,7 +389,9 @@ bido_status bido_learn_samples(const bido_ctx* ctx, int* n_samples);
 
 /* Train for `kind` (BIDO_LEARN_*): Adam on the FP32 master weights over the
  * first (samples - n_val) pairs, mini-batches of `batch`, shuffled by
- * `seed`; the last n_val pairs are held out for the validation loss.     */
+ * `seed`; the last n_val pairs are held out for the validation loss.  The
+ * stencil keeps the weights of the epoch with the lowest validation loss
+ * (training loss when n_val = 0), the weights before training included.  */
 bido_status bido_learn_train(bido_ctx* ctx, int kind, int epochs, int batch, float lr, uint64_t seed,
                              int n_val, bido_train_stats* st);
 

@@ -85,7 +85,7 @@ class TrainStats(ctypes.Structure):
                 ("loss_zero", ctypes.c_double), ("loss_zero_val", ctypes.c_double),
                 ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
                 ("loss_val", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("spd", ctypes.c_int), ("refactor_seconds", ctypes.c_double)]
+                ("spd", ctypes.c_int), ("refactor_seconds", ctypes.c_double), ("best_epoch", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -447,6 +447,7 @@ struct GnnState {
     GnnGraph A, At;                        // neighbour weights and their transpose
     GnnGraph Wk;                           // K_m / mean diag: norm of the training loss
     float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    float* theta_best = nullptr;           // the kept weights of a stencil training
     uint16_t* wbf = nullptr;               // BF16 working weights
     GnnAct act;
     float* partials = nullptr;
@@ -479,7 +480,8 @@ struct GnnState {
     void release() {
         for (void* b : {(void*)stat, (void*)A.ptr, (void*)A.col, (void*)A.val, (void*)At.ptr, (void*)At.col,
                         (void*)At.val, (void*)Wk.ptr, (void*)Wk.col, (void*)Wk.val, (void*)act.res,
-                        (void*)act.zero, (void*)theta, (void*)m, (void*)v, (void*)grad, (void*)wbf,
+                        (void*)act.zero, (void*)theta, (void*)theta_best, (void*)m, (void*)v, (void*)grad,
+                        (void*)wbf,
                         (void*)act.f, (void*)act.m0, (void*)act.h1, (void*)act.m1, (void*)act.h2,
                         (void*)act.o, (void*)act.dout, (void*)act.dz2, (void*)act.g2, (void*)act.dz1,
                         (void*)partials, (void*)dloss, (void*)ft, (void*)fy, (void*)tz, (void*)s_t,
@@ -1424,7 +1426,8 @@ bido_status gnn_setup(bido_ctx* c) {
         g.wk_like_k = wp == hs.km_int.ptr &&
                       std::equal(hs.km_int.col.begin(), hs.km_int.col.end(), wc.begin());
     }
-    for (float** b : {&g.theta, &g.m, &g.v, &g.grad}) HIP_OK(hipMalloc((void**)b, GNN_P * sizeof(float)));
+    for (float** b : {&g.theta, &g.theta_best, &g.m, &g.v, &g.grad})
+        HIP_OK(hipMalloc((void**)b, GNN_P * sizeof(float)));
     HIP_OK(hipMalloc((void**)&g.wbf, GNN_P * sizeof(uint16_t)));
     if ((e = gnn_init_weights(c))) return e;
     const int64_t nh = std::max<int64_t>(NH, 1);
@@ -3000,8 +3003,16 @@ static bido_status train_stencil(bido_ctx* c, int epochs, int batch, float lr, u
     launch_gnn_embed(s, NH, g.stat, g.A, g.wbf, g.act);
     launch_stencil_values(s, g.P, g.act.h2, g.wbf, g.cval);
     eval(0, n_tr, g.dloss + 2, false);
+    eval(n_tr, g.n_samples, g.dloss + 3, false);
     HIP_OK(hipMemcpyAsync(hl, g.dloss, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    // model selection: the weights of the epoch with the lowest held-out
+    // loss (training loss without held-out pairs), those before training
+    // included
+    const int sel0 = n_val > 0 ? n_tr : 0, sel1 = n_val > 0 ? g.n_samples : n_tr;
+    double best = n_val > 0 ? hl[3] : hl[2];
+    int best_epoch = 0;
+    HIP_OK(hipMemcpyAsync(g.theta_best, g.theta, GNN_P * sizeof(float), hipMemcpyDeviceToDevice, s));
     if (ts) {
         std::memset(ts, 0, sizeof(*ts));
         ts->samples = g.n_samples;
@@ -3029,6 +3040,22 @@ static bido_status train_stencil(bido_ctx* c, int epochs, int batch, float lr, u
             launch_stencil_backward(s, g.P, g.At, g.G, g.wbf, g.act, g.partials, g.grad);
             launch_gnn_adam(s, g.theta, g.m, g.v, g.grad, 1.0f / (float)(b1 - b0), lr, ++g.adam_step, g.wbf);
         }
+        launch_gnn_embed(s, NH, g.stat, g.A, g.wbf, g.act);
+        launch_stencil_values(s, g.P, g.act.h2, g.wbf, g.cval);
+        HIP_OK(hipMemsetAsync(g.dloss, 0, sizeof(double), s));
+        eval(sel0, sel1, g.dloss, false);
+        double l = 0.0;
+        HIP_OK(hipMemcpyAsync(&l, g.dloss, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (l < best) {
+            best = l;
+            best_epoch = ep + 1;
+            HIP_OK(hipMemcpyAsync(g.theta_best, g.theta, GNN_P * sizeof(float), hipMemcpyDeviceToDevice, s));
+        }
+    }
+    if (best_epoch != epochs) {            // back to the kept weights
+        HIP_OK(hipMemcpyAsync(g.theta, g.theta_best, GNN_P * sizeof(float), hipMemcpyDeviceToDevice, s));
+        launch_gnn_to_bf16(s, g.theta, g.wbf);
     }
     launch_gnn_embed(s, NH, g.stat, g.A, g.wbf, g.act);
     launch_stencil_values(s, g.P, g.act.h2, g.wbf, g.cval);
@@ -3043,6 +3070,7 @@ static bido_status train_stencil(bido_ctx* c, int epochs, int batch, float lr, u
         ts->epochs = epochs;
         ts->loss_last = hl[2] / n_tr;
         ts->loss_val = n_val ? hl[3] / n_val : 0.0;
+        ts->best_epoch = best_epoch;
     }
     // factor K_m + C on the host and upload it as the learned P_K (without a
     // factored K_m: a multigrid hierarchy of K_m + C instead)

@@ -136,6 +136,9 @@ def test_learned_stencil_and_flexible_cg(torch, setup, collected):
     ts = solver.learn_train(kind=B.LEARN_STENCIL, epochs=30, batch=4, lr=2e-3, seed=1, n_val=4)
     print("train stencil", ts)
     assert ts["loss_last"] < ts["loss_first"] and ts["loss_last"] < ts["loss_zero"]
+    # the kept weights are those of the lowest held-out loss, the untrained
+    # ones (C = 0 here) included
+    assert ts["best_epoch"] > 0 and ts["loss_val"] <= ts["loss_zero_val"]
     assert ts["spd"] == 1
     it_p, wp, _, _ = _solve_steps(torch, solver, s, collected, 12, 6, learned=0)
     it_l, wl, fb, _ = _solve_steps(torch, solver, s, collected, 12, 6, learned=B.PRECOND_LEARNED)
