@@ -109,6 +109,11 @@ typedef struct {
     int scheme;        /* BIDO_SCHEME_*: time discretisation                 */
     int inner_p1;      /* BIDO_P1_*: the inner solve P_1 ~ S_1 (Sec. 5.3)    */
     int inner_pk;      /* BIDO_PK_*: the inner solve P_K ~ K_m (Sec. 5.3)    */
+    int amg_columns;   /* column indices of the multigrid levels and the
+                          coupling blocks: 0 = 16-bit offsets from a per-row
+                          base wherever every row of a matrix spans fewer
+                          than 65536 columns (the default), 1 = always
+                          32-bit; the result is the same                  */
 } bido_params;
 
 /* Inner solves inside the block-LU preconditioner (Def. 2).  Sec. 5.3 lets
@@ -117,8 +122,10 @@ typedef struct {
  * nested-dissection order with the hierarchical top (the default; the
  * paper's choice).  AMG: a symmetric V-cycle of smoothed-aggregation
  * algebraic multigrid (Chebyshev smoothing, dense coarsest solve), set up
- * without any factorisation (linear in the non-zeros), FP64 in both
- * precisions.  CHEBYSHEV (P_K only): Chebyshev-accelerated Jacobi steps on
+ * without any factorisation (linear in the non-zeros), with FP32 level
+ * values in mixed precision; its block takes the reverse Cuthill-McKee
+ * order instead of nested dissection (one order for u and v when the heart
+ * is the whole mesh).  CHEBYSHEV (P_K only): Chebyshev-accelerated Jacobi steps on
  * K_m (see bido_set_pk).  A block that is not CHOLESKY is never factored,
  * so the factor-only calls (plans, autotuning, the allocation-free inner
  * solve) refuse it with BIDO_ERR_STATE, and so does a fused batch.       */

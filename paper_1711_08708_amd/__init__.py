@@ -53,7 +53,8 @@ class Params(ctypes.Structure):
                 ("eps_h", ctypes.c_double), ("eta", ctypes.c_double), ("tol", ctypes.c_double),
                 ("leaf", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("precond", ctypes.c_int), ("ionic", ctypes.c_int), ("n_threads", ctypes.c_int),
-                ("scheme", ctypes.c_int), ("inner_p1", ctypes.c_int), ("inner_pk", ctypes.c_int)]
+                ("scheme", ctypes.c_int), ("inner_p1", ctypes.c_int), ("inner_pk", ctypes.c_int),
+                ("amg_columns", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -14,7 +14,11 @@
 //   * aggregation in three passes: (1) a vertex whose strong neighbours are
 //     all free starts an aggregate with them; (2) a free vertex joins the
 //     aggregate of its strongest neighbour from pass 1; (3) what is left
-//     forms aggregates with its free strong neighbours;
+//     forms aggregates with its free strong neighbours.  The passes visit
+//     the finest level in index order and a coarser level in the order its
+//     aggregates were made (equal strengths in pass 2: the neighbour
+//     visited first); aggregates are numbered by their first vertex, so a
+//     banded fine order gives banded coarse matrices;
 //   * tentative prolongation P^ (the constant vector, the kernel of the
 //     Neumann Laplacian, restricted to each aggregate and normalised);
 //   * smoothed prolongation P = (I - omega D^-1 A) P^ with
@@ -306,6 +310,10 @@ bool amg_build(const Csr& A0, int64_t excluded, const AmgOptions& opt, Amg& out,
     out.smooth_ratio = opt.smooth_ratio;
     out.coarse_steps = opt.coarse_steps > 0 ? opt.coarse_steps : out.smooth_steps;
     Csr A = A0;
+    // the order the aggregation visits a level's vertices: index order on
+    // the finest level, the order the aggregates were made on the coarser
+    std::vector<int64_t> visit(A0.n);
+    std::iota(visit.begin(), visit.end(), 0);
     for (int lev = 0;; ++lev) {
         const int64_t n = A.n;
         AmgLevel L;
@@ -355,8 +363,11 @@ bool amg_build(const Csr& A0, int64_t excluded, const AmgOptions& opt, Amg& out,
             }
             agg.assign(n, -1);
             if (lev == 0 && excluded >= 0) agg[excluded] = -2;
+            std::vector<int64_t> pos(n);
+            for (int64_t k = 0; k < n; ++k) pos[visit[k]] = k;
             na = 0;
-            for (int64_t i = 0; i < n; ++i) {              // pass 1
+            for (int64_t k = 0; k < n; ++k) {              // pass 1
+                const int64_t i = visit[k];
                 if (agg[i] != -1 || sptr[i + 1] == sptr[i]) continue;
                 bool free = true;
                 for (int64_t p = sptr[i]; p < sptr[i + 1] && free; ++p) free = agg[scol[p]] == -1;
@@ -366,16 +377,23 @@ bool amg_build(const Csr& A0, int64_t excluded, const AmgOptions& opt, Amg& out,
                 ++na;
             }
             const std::vector<int64_t> agg1 = agg;
-            for (int64_t i = 0; i < n; ++i) {              // pass 2
+            for (int64_t k = 0; k < n; ++k) {              // pass 2
+                const int64_t i = visit[k];
                 if (agg[i] != -1) continue;
                 double best = -1.0;
-                for (int64_t p = sptr[i]; p < sptr[i + 1]; ++p)
-                    if (agg1[scol[p]] >= 0 && sval[p] > best) {
+                int64_t bpos = n;
+                for (int64_t p = sptr[i]; p < sptr[i + 1]; ++p) {
+                    const int64_t j = scol[p];
+                    // equal strengths: the neighbour visited first
+                    if (agg1[j] >= 0 && (sval[p] > best || (sval[p] == best && pos[j] < bpos))) {
                         best = sval[p];
-                        agg[i] = agg1[scol[p]];
+                        bpos = pos[j];
+                        agg[i] = agg1[j];
                     }
+                }
             }
-            for (int64_t i = 0; i < n; ++i) {              // pass 3
+            for (int64_t k = 0; k < n; ++k) {              // pass 3
+                const int64_t i = visit[k];
                 if (agg[i] != -1) continue;
                 agg[i] = na;
                 for (int64_t p = sptr[i]; p < sptr[i + 1]; ++p)
@@ -401,6 +419,19 @@ bool amg_build(const Csr& A0, int64_t excluded, const AmgOptions& opt, Amg& out,
             }
             err = "multigrid: aggregation did not coarsen at level " + std::to_string(lev);
             return false;
+        }
+        // aggregates numbered by their first vertex; the next level is
+        // visited in the order they were made
+        {
+            std::vector<int64_t> first(na, n), ord(na), id(na);
+            for (int64_t i = 0; i < n; ++i)
+                if (agg[i] >= 0) first[agg[i]] = std::min(first[agg[i]], i);
+            std::iota(ord.begin(), ord.end(), 0);
+            std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return first[a] < first[b]; });
+            for (int64_t k = 0; k < na; ++k) id[ord[k]] = k;
+            for (int64_t i = 0; i < n; ++i)
+                if (agg[i] >= 0) agg[i] = id[agg[i]];
+            visit = std::move(id);
         }
         // tentative prolongation (normalised constants per aggregate)
         std::vector<int64_t> asz(na, 0);

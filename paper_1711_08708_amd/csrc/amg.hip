@@ -3,7 +3,10 @@
 // api.cpp).  Every product is a CSR row product by a group of G lanes with
 // RU rows in flight (the row helper of the Lambda product), with the matrix
 // values in FP64 or, in mixed precision, FP32 (FP64 accumulation, FP64
-// vectors): the cycle is bound by the bytes of its level matrices.
+// vectors): the cycle is bound by the bytes of its level matrices.  A
+// matrix whose rows each span fewer than 65536 columns (a banded order)
+// holds its columns as 16-bit offsets from a per-row base (C = uint16_t,
+// 2 instead of 4 bytes per entry); C = int32_t is the plain column.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,18 +34,23 @@ __device__ __forceinline__ double group_sum(double v) {
 
 // s[u] = sum_j A[row_u, j] * f(j) for RU rows, f(j) = x[j] (or x[j] * w[j]
 // when w is given: the scaled input of a fused smoother step); entries
-// past a row's end reread entry 0 and are dropped by a select.
-template <int G, int K, typename T>
-__device__ __forceinline__ void rows_dot(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                         const T* __restrict__ val, const double* __restrict__ x,
-                                         const double* __restrict__ w, const int64_t (&row)[RU],
-                                         const bool (&ok)[RU], int lane, double (&s)[RU]) {
+// past a row's end reread entry 0 and are dropped by a select.  Column j of
+// an entry is col[q] (C = int32_t) or cb[row] + col[q] (C = uint16_t).
+template <int G, int K, typename T, typename C>
+__device__ __forceinline__ void rows_dot(const int64_t* __restrict__ ptr, const C* __restrict__ col,
+                                         const int32_t* __restrict__ cb, const T* __restrict__ val,
+                                         const double* __restrict__ x, const double* __restrict__ w,
+                                         const int64_t (&row)[RU], const bool (&ok)[RU], int lane,
+                                         double (&s)[RU]) {
     int64_t pb[RU], pe[RU];
+    int32_t c0[RU];
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
         const int64_t rr = ok[u] ? row[u] : row[0];
         pb[u] = ptr[rr];
         pe[u] = ptr[rr + 1];
+        if constexpr (sizeof(C) == 2) c0[u] = cb[rr];
+        else c0[u] = 0;
         s[u] = 0.0;
     }
 #pragma unroll
@@ -52,7 +60,7 @@ __device__ __forceinline__ void rows_dot(const int64_t* __restrict__ ptr, const 
             const int64_t q = pb[u] + lane + k * G;
             const bool in = q < pe[u];
             const int64_t qc = in ? q : 0;
-            const int32_t c = col[qc];
+            const int32_t c = c0[u] + (int32_t)col[qc];
             double xv = x[c];
             if (w) xv *= w[c];
             const double v = (double)val[qc] * xv;
@@ -61,7 +69,7 @@ __device__ __forceinline__ void rows_dot(const int64_t* __restrict__ ptr, const 
 #pragma unroll
     for (int u = 0; u < RU; ++u)
         for (int64_t q = pb[u] + lane + K * G; q < pe[u]; q += G) {
-            const int32_t c = col[q];
+            const int32_t c = c0[u] + (int32_t)col[q];
             double xv = x[c];
             if (w) xv *= w[c];
             s[u] += (double)val[q] * xv;
@@ -71,9 +79,10 @@ __device__ __forceinline__ void rows_dot(const int64_t* __restrict__ ptr, const 
 }
 
 // y = b + sign * A x  (b may be null)
-template <int G, int K, typename T>
+template <int G, int K, typename T, typename C>
 __global__ __launch_bounds__(BLOCK) void k_amg_spmv(int64_t n, const int64_t* __restrict__ ptr,
-                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                    const C* __restrict__ col, const int32_t* __restrict__ cb,
+                                                    const T* __restrict__ val,
                                                     const double* __restrict__ x, const double* __restrict__ b,
                                                     double sign, double* __restrict__ y) {
     const int lane = threadIdx.x % G;
@@ -88,7 +97,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_spmv(int64_t n, const int64_t* __
             ok[u] = row[u] < rr.r1;
         }
         double s[RU];
-        rows_dot<G, K, T>(ptr, col, val, x, nullptr, row, ok, lane, s);
+        rows_dot<G, K, T, C>(ptr, col, cb, val, x, nullptr, row, ok, lane, s);
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < RU; ++u)
@@ -111,9 +120,9 @@ __global__ __launch_bounds__(BLOCK) void k_amg_jacobi(int64_t n, const double* _
 // As = A D^-1 of the level matrix, so one gather per entry),
 // d1 = c1 d0 + c2 D^-1 r1, z = base + d0 + d1 (base may be null); r1, d0
 // and d1 are kept when more steps follow (write_rd).
-template <int G, int K, typename T>
+template <int G, int K, typename T, typename C>
 __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t* __restrict__ ptr,
-                                                       const int32_t* __restrict__ col,
+                                                       const C* __restrict__ col, const int32_t* __restrict__ cb,
                                                        const T* __restrict__ val, const double* __restrict__ dinv,
                                                        const double* __restrict__ b, double a0, double c1, double c2,
                                                        const double* __restrict__ base,
@@ -136,7 +145,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t*
             di[u] = dinv[i];
         }
         double s[RU];
-        rows_dot<G, K, T>(ptr, col, val, b, nullptr, row, ok, lane, s);   // (A D^-1 b)_i with val = As
+        rows_dot<G, K, T, C>(ptr, col, cb, val, b, nullptr, row, ok, lane, s);   // (A D^-1 b)_i, val = As
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
@@ -180,7 +189,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cheb(int64_t n, const int64_t* __
             zv[u] = z[i];
         }
         double s[RU];
-        rows_dot<G, K, T>(ptr, col, val, dp, nullptr, row, ok, lane, s);
+        rows_dot<G, K, T, int32_t>(ptr, col, nullptr, val, dp, nullptr, row, ok, lane, s);
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
@@ -381,8 +390,12 @@ int unroll_for(const AmgMat<T>& A) {
 template <typename T>
 void launch_amg_spmv(hipStream_t s, const AmgMat<T>& A, const double* x, const double* b, double sign, double* y) {
     if (A.n <= 0) return;
-    BIDO_G_SWITCH(A, k_amg_spmv<GG, KK, T><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(A.n, A.ptr, A.col, A.val, x, b,
-                                                                                    sign, y))
+    if (A.c16)
+        BIDO_G_SWITCH(A, k_amg_spmv<GG, KK, T, uint16_t><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
+                             A.n, A.ptr, A.c16, A.cb, A.val, x, b, sign, y))
+    else
+        BIDO_G_SWITCH(A, k_amg_spmv<GG, KK, T, int32_t><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
+                             A.n, A.ptr, A.col, nullptr, A.val, x, b, sign, y))
 }
 
 template <typename T>
@@ -390,8 +403,14 @@ void launch_amg_smooth2(hipStream_t s, const AmgMat<T>& A, const double* dinv, c
                         double c2, const double* base, double* z, double* r1, double* d0, double* d1,
                         bool write_rd) {
     if (A.n <= 0) return;
-    BIDO_G_SWITCH(A, k_amg_smooth2<GG, KK, T><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
-                         A.n, A.ptr, A.col, A.val, dinv, b, a0, c1, c2, base, z, r1, d0, d1, write_rd ? 1 : 0))
+    if (A.c16)
+        BIDO_G_SWITCH(A, k_amg_smooth2<GG, KK, T, uint16_t><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
+                             A.n, A.ptr, A.c16, A.cb, A.val, dinv, b, a0, c1, c2, base, z, r1, d0, d1,
+                             write_rd ? 1 : 0))
+    else
+        BIDO_G_SWITCH(A, k_amg_smooth2<GG, KK, T, int32_t><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
+                             A.n, A.ptr, A.col, nullptr, A.val, dinv, b, a0, c1, c2, base, z, r1, d0, d1,
+                             write_rd ? 1 : 0))
 }
 
 void launch_amg_jacobi(hipStream_t s, int64_t n, const double* b, const double* dinv, double a0, const double* base,

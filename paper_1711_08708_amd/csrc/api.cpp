@@ -155,8 +155,30 @@ struct CsrHostView {
         return BIDO_OK;
     }
     static void release(CsrDev& d) {
-        hipFree(d.ptr); hipFree(d.col); hipFree(d.val);
+        hipFree(d.ptr); hipFree(d.col); hipFree(d.val); hipFree(d.c16); hipFree(d.cb);
         d = CsrDev();
+    }
+    // the compact columns of d (c16, cb) when every row of a spans fewer
+    // than 65536 columns; otherwise none (the products read col)
+    static bido_status compact(const Csr& a, CsrDev& d) {
+        if (a.nnz() == 0 || a.n <= 0) return BIDO_OK;
+        std::vector<int32_t> base(a.n, 0);
+        for (int64_t i = 0; i < a.n; ++i) {
+            if (a.ptr[i] == a.ptr[i + 1]) continue;
+            int32_t lo = a.col[a.ptr[i]], hi = lo;
+            for (int64_t q = a.ptr[i]; q < a.ptr[i + 1]; ++q) {
+                lo = std::min(lo, a.col[q]);
+                hi = std::max(hi, a.col[q]);
+            }
+            if ((int64_t)hi - lo > 65535) return BIDO_OK;
+            base[i] = lo;
+        }
+        std::vector<uint16_t> c16(a.nnz());
+        for (int64_t i = 0; i < a.n; ++i)
+            for (int64_t q = a.ptr[i]; q < a.ptr[i + 1]; ++q) c16[q] = (uint16_t)(a.col[q] - base[i]);
+        HIP_OK(upload(&d.c16, c16.data(), c16.size()));
+        HIP_OK(upload(&d.cb, base.data(), base.size()));
+        return BIDO_OK;
     }
 };
 
@@ -304,6 +326,8 @@ struct AmgDev {
             if constexpr (sizeof(T) == 4) o.val = v32;
             else o.val = m.val;
             o.group = g;
+            o.c16 = m.c16;
+            o.cb = m.cb;
             return o;
         }
     };
@@ -323,8 +347,11 @@ struct AmgDev {
         double b = 8.0 * (double)nc * nc + 16.0 * nc;
         for (size_t l = 0; l + 1 < lv.size(); ++l) {
             const Lev& L = lv[l];
-            auto mb = [&](int64_t nnz, int64_t rows) { return (4.0 + w) * nnz + 8.0 * (rows + 1); };
-            const double A = mb(L.nnz_A, L.n), vec = 8.0 * L.n;
+            auto mb = [&](const CsrDev& m, int64_t nnz, int64_t rows) {
+                return (m.col_bytes() + w) * nnz + m.row_bytes() * rows + 8.0;
+            };
+            const double A = mb(L.A, L.nnz_A, L.n), vec = 8.0 * L.n;
+            const double A32 = (4.0 + w) * L.nnz_A + 8.0 * (L.n + 1);
             const double nc_l = 8.0 * lv[l + 1].n;
             // two smoothings (one step: b and D^-1 read, z written; the fused first two
             // steps read A D^-1, b and D^-1 and write z, plus r1, d0 and d1 when more
@@ -333,16 +360,16 @@ struct AmgDev {
             const int steps = L.steps;
             const double sm = steps < 2    ? 3.0 * vec
                               : steps == 2 ? A + 3.0 * vec
-                                           : A + 6.0 * vec + (steps - 2) * (A + 7.0 * vec);
-            b += 2.0 * sm + vec + 2.0 * (A + 3.0 * vec) + mb(L.nnz_R, lv[l + 1].n) + vec + nc_l +
-                 mb(L.nnz_P, L.n) + nc_l + 2.0 * vec;
+                                           : A + 6.0 * vec + (steps - 2) * (A32 + 7.0 * vec);
+            b += 2.0 * sm + vec + 2.0 * (A + 3.0 * vec) + mb(L.R, L.nnz_R, lv[l + 1].n) + vec + nc_l +
+                 mb(L.P, L.nnz_P, L.n) + nc_l + 2.0 * vec;
         }
         return b;
     }
     void release() {
         for (auto& L : lv) {
             for (CsrDev* m : {&L.A, &L.P, &L.R}) {
-                hipFree(m->ptr); hipFree(m->col); hipFree(m->val);
+                hipFree(m->ptr); hipFree(m->col); hipFree(m->val); hipFree(m->c16); hipFree(m->cb);
             }
             for (float* v : {L.A32, L.P32, L.R32, L.As32}) hipFree(v);
             for (double* v : {L.dinv, L.b, L.out, L.x, L.r, L.d0, L.d1, L.xp, L.As64, L.mass}) hipFree(v);
@@ -366,7 +393,8 @@ int group_for(const Csr& a) {
     return avg <= 8 ? 2 : avg <= 16 ? 4 : avg <= 32 ? 8 : avg <= 64 ? 16 : avg <= 128 ? 32 : 64;
 }
 
-bido_status upload_amg(const Amg& M, AmgDev& d) {
+// compact: 16-bit column offsets for the matrices whose rows allow them
+bido_status upload_amg(const Amg& M, AmgDev& d, bool compact) {
     d.release();
     d.op_complexity = M.op_complexity;
     d.setup_seconds = M.setup_seconds;
@@ -400,6 +428,8 @@ bido_status upload_amg(const Amg& M, AmgDev& d) {
         if ((e = CsrHostView::up(h.A, v.A))) return e;
         if ((e = CsrHostView::up(h.P, v.P))) return e;
         if ((e = CsrHostView::up(h.R, v.R))) return e;
+        for (auto [hm, dm] : {std::pair<const Csr*, CsrDev*>{&h.A, &v.A}, {&h.P, &v.P}, {&h.R, &v.R}})
+            if (compact && (e = CsrHostView::compact(*hm, *dm))) return e;
         auto up32 = [&](const Csr& m, float** dst) -> hipError_t {
             std::vector<float> f(m.val.begin(), m.val.end());
             if (f.empty()) f.push_back(0.0f);
@@ -724,7 +754,8 @@ void amg_smooth(C* c, const AmgDev& M, const AmgDev::Lev& L, const double* b, do
     AmgMat<T> As = A;                      // the column-scaled copy A D^-1
     if constexpr (sizeof(T) == 4) As.val = L.As32;
     else As.val = L.As64;
-    const double Ab = (4.0 + sizeof(T)) * L.nnz_A + 8.0 * (n + 1);
+    const double Ab = (L.A.col_bytes() + sizeof(T)) * L.nnz_A + L.A.row_bytes() * n + 8.0;
+    const double Ab32 = (4.0 + sizeof(T)) * L.nnz_A + 8.0 * (n + 1);   // the further steps read col
     const double bb = base ? 8.0 * n : 0.0;
     if (L.steps < 2) {
         PROF(c, cls, 24.0 * n + bb, launch_amg_jacobi(s, n, b, L.dinv, L.cf.inv_theta, base, z));
@@ -735,7 +766,7 @@ void amg_smooth(C* c, const AmgDev& M, const AmgDev::Lev& L, const double* b, do
                                L.d1, L.steps > 2));
     double* d[2] = {L.d0, L.d1};
     for (int k = 2; k < L.steps; ++k)
-        PROF(c, cls, Ab + 56.0 * n,
+        PROF(c, cls, Ab32 + 56.0 * n,
              launch_amg_cheb<T>(s, A, L.dinv, L.r, d[(k - 1) & 1], d[k & 1], z, L.cf.c1[k - 1], L.cf.c2[k - 1]));
 }
 
@@ -751,11 +782,14 @@ void amg_vcycle_t(C* c, const AmgDev& M, size_t l, const double* b, double* out)
         return;
     }
     const AmgDev::Lev& Lc = M.lv[l + 1];
-    const double vec = 8.0 * L.n, w = 4.0 + sizeof(T);
+    const double vec = 8.0 * L.n, w = sizeof(T);
     const AmgMat<T> A = L.mat<T>(L.A, L.A32, L.gA);
     const AmgMat<T> P = L.mat<T>(L.P, L.P32, L.gP);
     const AmgMat<T> R = L.mat<T>(L.R, L.R32, L.gR);
-    const double Ab = w * L.nnz_A + vec, Pb = w * L.nnz_P + vec, Rb = w * L.nnz_R + 8.0 * Lc.n;
+    // values and columns per entry, row pointers (and column bases) per row
+    const double Ab = (w + L.A.col_bytes()) * L.nnz_A + L.A.row_bytes() * L.n,
+                 Pb = (w + L.P.col_bytes()) * L.nnz_P + L.P.row_bytes() * L.n,
+                 Rb = (w + L.R.col_bytes()) * L.nnz_R + L.R.row_bytes() * Lc.n;
     // profiler classes: the finest level by kernel (its smoother is one
     // kernel on one matrix), the coarser levels together
     const bool fine = l == 0;
@@ -844,13 +878,13 @@ void coupling_product(bido_ctx* c, const CsrDev& B, const float* v32, const doub
     const int64_t avg = B.n > 0 ? (B.nnz + B.n - 1) / B.n : 1;
     const int g = avg <= 16 ? 4 : avg <= 32 ? 8 : avg <= 64 ? 16 : 32;
     const bool f32 = c->precision == BIDO_PREC_MIXED;
-    const double bytes = (f32 ? 8.0 : 12.0) * B.nnz + 8.0 * (B.n + 1) + 8.0 * B.n * (b ? 2 : 1) +
-                         8.0 * (B.nnz > 0 ? B.n : 0);
+    const double bytes = (B.col_bytes() + (f32 ? 4.0 : 8.0)) * B.nnz + B.row_bytes() * B.n + 8.0 +
+                         8.0 * B.n * (b ? 2 : 1) + 8.0 * (B.nnz > 0 ? B.n : 0);
     if (f32) {
-        AmgMat<float> m{B.n, B.nnz, B.ptr, B.col, v32, g};
+        AmgMat<float> m{B.n, B.nnz, B.ptr, B.col, v32, g, B.c16, B.cb};
         PROF(c, K_SPMV_CSR, bytes, launch_amg_spmv<float>(c->stream, m, x, b, sign, y));
     } else {
-        AmgMat<double> m{B.n, B.nnz, B.ptr, B.col, B.val, g};
+        AmgMat<double> m{B.n, B.nnz, B.ptr, B.col, B.val, g, B.c16, B.cb};
         PROF(c, K_SPMV_CSR, bytes, launch_amg_spmv<double>(c->stream, m, x, b, sign, y));
     }
 }
@@ -1897,6 +1931,9 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     }
     if ((e = CsrHostView::up(hs.avu, c->avu))) return e;
     if ((e = CsrHostView::up(hs.auv, c->auv))) return e;
+    const bool compact = params->amg_columns == 0;
+    if (compact && (e = CsrHostView::compact(hs.avu, c->avu))) return e;
+    if (compact && (e = CsrHostView::compact(hs.auv, c->auv))) return e;
     for (auto [src, dst] : {std::pair<const Csr*, float**>{&hs.avu, &c->avu32}, {&hs.auv, &c->auv32}}) {
         std::vector<float> v32(src->val.begin(), src->val.end());
         if (v32.empty()) v32.push_back(0.0f);
@@ -1906,14 +1943,14 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
         if ((e = build_factor_dev(hs.p1, true, c->p1, hs.params.n_threads))) return e;
         hs.p1.trim_top_cache(c->p1.top_h);  // a fused batch reuses hierarchical tops
     } else {
-        if ((e = upload_amg(hs.amg1, c->amg1))) return e;
+        if ((e = upload_amg(hs.amg1, c->amg1, compact))) return e;
         hs.amg1 = Amg();                    // the device copy is the only one kept
     }
     if (hs.pk_factored) {
         if ((e = build_factor_dev(hs.pk, true, c->pk, hs.params.n_threads))) return e;
         hs.pk.trim_top_cache(c->pk.top_h);
     } else if (params->inner_pk == BIDO_PK_AMG) {
-        if ((e = upload_amg(hs.amgk, c->amgk))) return e;
+        if ((e = upload_amg(hs.amgk, c->amgk, compact))) return e;
         hs.amgk = Amg();                    // (a time-step change moves it on the device)
         c->pk_kind = BIDO_PK_AMG;
     }
@@ -3085,7 +3122,7 @@ static bido_status train_stencil(bido_ctx* c, int epochs, int batch, float lr, u
         Amg am;
         spd = amg_build(Kt, -1, AmgOptions(), am, err);
         if (spd) {
-            if (bido_status e = upload_amg(am, c->amgk_learned)) return e;
+            if (bido_status e = upload_amg(am, c->amgk_learned, c->params.amg_columns == 0)) return e;
         }
     } else if ((spd = multifrontal(Kt, f, -1, c->params.n_threads, err))) {
         set_top_compression(f, c->hs.pk.xyz.data(), c->hs.pk.dim, c->hs.pk.eps);

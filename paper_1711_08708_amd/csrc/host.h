@@ -74,6 +74,10 @@ struct NdTree {
 void nested_dissection(const Csr& g, const double* xyz, int dim, int leaf,
                        NdTree& t);
 
+// Reverse Cuthill-McKee order of a symmetric pattern: only t.perm and
+// t.iperm are set (the order of the inner solves that need no factor).
+void rcm_order(const Csr& g, NdTree& t);
+
 // Symmetric permutation B = P A P^T with perm = new -> old.
 Csr permute(const Csr& a, const std::vector<int64_t>& perm,
             const std::vector<int64_t>& iperm);

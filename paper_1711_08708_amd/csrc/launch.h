@@ -13,6 +13,13 @@ struct CsrDev {
     int64_t* ptr = nullptr;
     int32_t* col = nullptr;
     double* val = nullptr;
+    // compact columns (or null): col[q] = cb[row] + c16[q] for every entry
+    // of a row, when each row spans fewer than 65536 columns
+    uint16_t* c16 = nullptr;
+    int32_t* cb = nullptr;
+    // index bytes of the products that read it: per entry and per row
+    double col_bytes() const { return c16 ? 2.0 : 4.0; }
+    double row_bytes() const { return c16 ? 12.0 : 8.0; }
 };
 
 // partial-sum scratch of k_dot_reduce (the last block reduces)
@@ -107,6 +114,8 @@ struct AmgMat {
     const int32_t* col = nullptr;
     const T* val = nullptr;
     int group = 4;
+    const uint16_t* c16 = nullptr;   // compact columns (CsrDev), read instead of col when set
+    const int32_t* cb = nullptr;
 };
 // y = b + sign A x (b may be null)
 template <typename T>

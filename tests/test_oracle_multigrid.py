@@ -124,8 +124,9 @@ def test_library_hierarchy_is_galerkin_and_its_cycle_is_the_oracle_cycle(mk):
         err = np.linalg.norm(xl - xo) / np.linalg.norm(xo)
         print(which, info, "host vs oracle cycle", err)
         assert err <= 1e-11
-        if which == B.FACTOR_P1:
-            assert xl[-1] == 0.0 and levels[0]["dinv"][-1] == 0.0   # the grounded vertex
+        if which == B.FACTOR_P1:                                     # the grounded vertex
+            g = np.flatnonzero(levels[0]["dinv"] == 0.0)
+            assert len(g) == 1 and xl[g[0]] == 0.0 and xo[g[0]] == 0.0
 
 
 def test_new_time_step_keeps_the_aggregation_and_moves_every_level():
@@ -170,10 +171,12 @@ def test_multigrid_p1_converges_in_few_iterations(n):
     hs = B.HostSetup(w.slab3d(n=n), eps_h=0.0, inner_p1=B.P1_AMG)
     A = hs.amg_level(B.FACTOR_P1, 0)["A"]
     N = A.shape[0]
+    g = np.flatnonzero(hs.amg_level(B.FACTOR_P1, 0)["dinv"] == 0.0)[0]    # the grounded vertex
+    keep = np.arange(N) != g
     rng = np.random.default_rng(0)
     b = rng.normal(size=N)
-    b[-1] = 0.0
-    b[:-1] -= b[:-1].mean()
+    b[g] = 0.0
+    b[keep] -= b[keep].mean()
     x = np.zeros(N)
     r = b.copy()
     z = hs.amg_apply(B.FACTOR_P1, r)
@@ -181,7 +184,7 @@ def test_multigrid_p1_converges_in_few_iterations(n):
     rz = r @ z
     for it in range(100):
         q = A @ p
-        q[-1] = 0.0
+        q[g] = 0.0
         a = rz / (p @ q)
         x += a * p
         r -= a * q
@@ -192,3 +195,37 @@ def test_multigrid_p1_converges_in_few_iterations(n):
         p = z + (rz / rz_old) * p
     print("slab", n, "CG iterations with the multigrid P_1", it + 1, hs.amg_info(B.FACTOR_P1))
     assert it + 1 <= 25
+
+
+def test_multigrid_blocks_take_a_banded_order():
+    """A block that is not factored takes the reverse Cuthill-McKee order:
+    the internal orders are permutations, u and v share one order when the
+    heart is the whole mesh, and S_1 in that order has a band no wider than
+    in the slab's own lexicographic numbering (about n^2 + n + 1 for an
+    n^3 grid of cells); a factored block keeps nested dissection, whose
+    separators couple far-apart indices."""
+    import paper_1711_08708_amd as B
+    n = 16
+    cfg = w.slab3d(n=n)
+    band = lambda M: np.abs(M.tocoo().row - M.tocoo().col).max()
+    hs = B.HostSetup(cfg, eps_h=0.0, inner_p1=B.P1_AMG, inner_pk=B.PK_AMG)
+    up, vp, heart = hs.index(B.IDX_UPOS), hs.index(B.IDX_VPOS), hs.index(B.IDX_HEART)
+    N = len(up)
+    assert sorted(up) == list(range(N)) and sorted(vp) == list(range(len(vp)))
+    assert np.array_equal(up[heart], vp)
+    S = hs.csr(B.MAT_S1)                        # caller's numbering
+    perm = np.argsort(up)                       # internal -> caller
+    Sint = S[perm][:, perm]
+    print("band: caller order", band(S), "internal", band(Sint))
+    assert band(Sint) <= band(S) <= (n + 1) ** 2 + (n + 1) + 1
+    A0 = hs.amg_level(B.FACTOR_P1, 0)["A"]
+    assert band(A0) == band(Sint)
+    # the grounded vertex of the multigrid P_1: the one nearest the centroid
+    g = np.flatnonzero(hs.amg_level(B.FACTOR_P1, 0)["dinv"] == 0.0)
+    xyz = np.asarray(cfg["xyz"])
+    dist = np.linalg.norm(xyz - xyz.mean(axis=0), axis=1)
+    assert len(g) == 1 and dist[perm[g[0]]] == dist.min()
+    hf = B.HostSetup(cfg, eps_h=0.0)
+    upf = hf.index(B.IDX_UPOS)
+    pf = np.argsort(upf)
+    assert band(S[pf][:, pf]) > N // 2
