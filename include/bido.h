@@ -109,8 +109,10 @@ typedef struct {
     int scheme;        /* BIDO_SCHEME_*: time discretisation                 */
     int inner_p1;      /* BIDO_P1_*: the inner solve P_1 ~ S_1 (Sec. 5.3)    */
     int inner_pk;      /* BIDO_PK_*: the inner solve P_K ~ K_m (Sec. 5.3)    */
-    int amg_columns;   /* column indices of the multigrid levels and the
-                          coupling blocks: 0 = 16-bit offsets from a per-row
+    int amg_columns;   /* column indices of the multigrid levels, the
+                          coupling blocks and the blocked Lambda (all in a
+                          banded order when the inner solves are not
+                          factored): 0 = 16-bit offsets from a per-row
                           base wherever every row of a matrix spans fewer
                           than 65536 columns (the default), 1 = always
                           32-bit; the result is the same                  */
@@ -163,9 +165,10 @@ typedef struct {
     int64_t nnz_lambda;          /* stored entries of Lambda                  */
     int64_t bytes_lambda;        /* bytes one Lambda product moves: the blocked
                                     form (one column and the S_1, S_i values
-                                    per position, 20 bytes) when the heart is
-                                    the whole mesh, else the CSR (12 bytes per
-                                    stored entry)                             */
+                                    per position, 20 bytes, or 18 with 16-bit
+                                    column offsets and a 4-byte base per row)
+                                    when the heart is the whole mesh, else the
+                                    CSR (12 bytes per stored entry)          */
     int64_t bytes_p1, bytes_pk;  /* bytes of the P_1 / P_K factors as stored
                                     (the active precision); for a multigrid
                                     block, the bytes one V-cycle reads and

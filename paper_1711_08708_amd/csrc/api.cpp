@@ -527,11 +527,11 @@ struct GnnState {
 }  // namespace
 
 void release_lam_blk(LamBlk& b) {
-    hipFree(b.ptr); hipFree(b.col); hipFree(b.val); hipFree(b.gm);
+    hipFree(b.ptr); hipFree(b.col); hipFree(b.val); hipFree(b.gm); hipFree(b.c16); hipFree(b.cb);
     b = LamBlk();
 }
 
-bido_status upload_lam_blk(const HostSetup& hs, LamBlk& b) {
+bido_status upload_lam_blk(const HostSetup& hs, LamBlk& b, bool compact) {
     release_lam_blk(b);
     const LamBlocked& h = hs.lamb;
     if (h.n == 0) return BIDO_OK;
@@ -541,6 +541,16 @@ bido_status upload_lam_blk(const HostSetup& hs, LamBlk& b) {
     HIP_OK(upload(&b.gm, h.gm.data(), h.gm.size()));
     b.npos = (int64_t)h.col.size();
     b.n = h.n;
+    if (compact) {              // 16-bit offsets when every row's positions allow them
+        Csr pat;
+        pat.n = h.n;
+        pat.ptr = h.ptr;
+        pat.col = h.col;
+        CsrDev d;
+        if (bido_status e = CsrHostView::compact(pat, d)) return e;
+        b.c16 = d.c16;
+        b.cb = d.cb;
+    }
     return BIDO_OK;
 }
 
@@ -702,7 +712,8 @@ double csr_bytes(const CsrDev& a, int64_t ncols_read) {
 // blocked Lambda product: positions (4 + 16 bytes), row pointers, gm, x (u
 // and v), the output (u and v), and y in mode 1
 double blk_bytes(const LamBlk& b, int mode) {
-    return 20.0 * b.npos + 8.0 * (b.n + 1) + 8.0 * b.n + 32.0 * b.n + (mode == 1 ? 16.0 * b.n : 0.0);
+    const double colb = b.c16 ? 2.0 : 4.0, rowb = b.c16 ? 12.0 : 8.0;
+    return (16.0 + colb) * b.npos + rowb * b.n + 8.0 + 8.0 * b.n + 32.0 * b.n + (mode == 1 ? 16.0 * b.n : 0.0);
 }
 
 template <typename T> const T* top_inv(const FactorDev& f);
@@ -1921,7 +1932,8 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     c->heart_ids = hs.A.heart;
     bido_status e;
     if ((e = CsrHostView::up(hs.lam, c->lam))) return e;
-    if ((e = upload_lam_blk(hs, c->lamb))) return e;
+    const bool compact = params->amg_columns == 0;
+    if ((e = upload_lam_blk(hs, c->lamb, compact))) return e;
     {
         std::vector<int64_t> pos(std::max<int64_t>(c->NH, 1), 0);
         for (int64_t k = 0; k < c->NH; ++k)
@@ -1931,7 +1943,6 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     }
     if ((e = CsrHostView::up(hs.avu, c->avu))) return e;
     if ((e = CsrHostView::up(hs.auv, c->auv))) return e;
-    const bool compact = params->amg_columns == 0;
     if (compact && (e = CsrHostView::compact(hs.avu, c->avu))) return e;
     if (compact && (e = CsrHostView::compact(hs.auv, c->auv))) return e;
     for (auto [src, dst] : {std::pair<const Csr*, float**>{&hs.avu, &c->avu32}, {&hs.auv, &c->auv32}}) {

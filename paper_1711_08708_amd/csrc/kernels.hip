@@ -311,9 +311,10 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lambda(int64_t n, const int64_t*
 // and v): row k gives the u output k and the v output N + k from one pass
 // over its positions (column, {S_1, S_i}), gathering x_u and x_v at each
 // column; partials as in k_spmv_lambda.
-template <int G, int K, int MODE>
+template <int G, int K, int MODE, typename C>
 __global__ __launch_bounds__(BLOCK) void k_spmv_lam_blk(int64_t n, const int64_t* __restrict__ ptr,
-                                                        const int32_t* __restrict__ col,
+                                                        const C* __restrict__ col,
+                                                        const int32_t* __restrict__ cb,
                                                         const double2* __restrict__ val,
                                                         const double* __restrict__ gm,
                                                         const double* __restrict__ x,
@@ -328,6 +329,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lam_blk(int64_t n, const int64_t
     double acc0 = 0.0, acc1 = 0.0;
     for (int64_t rb = rr.r0 + threadIdx.x / G; rb < rr.r1; rb += RU * GPB) {
         int64_t row[RU], pb[RU], pe[RU];
+        int32_t c0[RU];
         bool ok[RU];
         double su[RU], sv[RU];
 #pragma unroll
@@ -337,6 +339,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lam_blk(int64_t n, const int64_t
             const int64_t r = ok[u] ? row[u] : rb;
             pb[u] = ptr[r];
             pe[u] = ptr[r + 1];
+            if constexpr (sizeof(C) == 2) c0[u] = cb[r];     // 16-bit offsets from the row's base
+            else c0[u] = 0;
             su[u] = 0.0;
             sv[u] = 0.0;
         }
@@ -349,7 +353,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lam_blk(int64_t n, const int64_t
                 const int64_t q = pb[u] + lane + k * G;
                 const bool in = q < pe[u];
                 const int64_t qc = in ? q : 0;
-                const int32_t c = col[qc];
+                const int32_t c = c0[u] + (int32_t)col[qc];
                 const double2 w = val[qc];
                 const double a = x[c], b = xv[c];
                 su[u] += in ? w.x * a + w.y * b : 0.0;
@@ -358,7 +362,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_lam_blk(int64_t n, const int64_t
 #pragma unroll
         for (int u = 0; u < RU; ++u)
             for (int64_t q = pb[u] + lane + K * G; q < pe[u]; q += G) {
-                const int32_t c = col[q];
+                const int32_t c = c0[u] + (int32_t)col[q];
                 const double2 w = val[q];
                 const double a = x[c], b = xv[c];
                 su[u] += w.x * a + w.y * b;
@@ -1409,13 +1413,21 @@ unsigned launch_spmv_lam_blk(hipStream_t s, const LamBlk& A, int group, int mode
     const int g4 = avg <= 8 ? 4 : avg <= 16 ? 8 : avg <= 32 ? 16 : 32;
     const unsigned g = grid_for(A.n * g4, BLOCK * 2, PP_MAX);
     const double2* v = reinterpret_cast<const double2*>(A.val);
-#define BIDO_BLK_CASE(G)                                                                              \
-    if (g4 == G) {                                                                                    \
-        if (mode == 0)                                                                                \
-            k_spmv_lam_blk<G, 2, 0><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, v, A.gm, x, y, out, pp);   \
-        else                                                                                          \
-            k_spmv_lam_blk<G, 2, 1><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, v, A.gm, x, y, out, pp);   \
-        return g;                                                                                     \
+#define BIDO_BLK_CASE(G)                                                                                    \
+    if (g4 == G) {                                                                                          \
+        if (A.c16 && mode == 0)                                                                             \
+            k_spmv_lam_blk<G, 2, 0, uint16_t><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.c16, A.cb, v, A.gm, x, y, out, \
+                                                                  pp);                                      \
+        else if (A.c16)                                                                                     \
+            k_spmv_lam_blk<G, 2, 1, uint16_t><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.c16, A.cb, v, A.gm, x, y, out, \
+                                                                  pp);                                      \
+        else if (mode == 0)                                                                                 \
+            k_spmv_lam_blk<G, 2, 0, int32_t><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, nullptr, v, A.gm, x, y,    \
+                                                                 out, pp);                                  \
+        else                                                                                                \
+            k_spmv_lam_blk<G, 2, 1, int32_t><<<g, BLOCK, 0, s>>>(A.n, A.ptr, A.col, nullptr, v, A.gm, x, y,    \
+                                                                 out, pp);                                  \
+        return g;                                                                                           \
     }
     BIDO_BLK_CASE(4) BIDO_BLK_CASE(8) BIDO_BLK_CASE(16) BIDO_BLK_CASE(32)
 #undef BIDO_BLK_CASE

@@ -194,6 +194,8 @@ struct LamBlk {
     int32_t* col = nullptr;             // npos
     double* val = nullptr;              // 2 npos: S_1, S_i per position
     double* gm = nullptr;               // n
+    uint16_t* c16 = nullptr;            // compact columns (or null): col = cb[row] + c16
+    int32_t* cb = nullptr;
     bool on() const { return n > 0; }
 };
 // the Lambda product on the blocked form (modes and partials of

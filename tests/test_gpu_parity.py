@@ -236,7 +236,9 @@ def test_lambda_blocked_form(torch):
     """A slab (heart = whole mesh, one internal order for u and v) runs the
     Lambda product on the blocked form (20 bytes per position instead of 12
     per entry of the four CSR blocks) and a solve still matches the oracle to
-    1e-8; a thorax slice (torso rows) keeps the CSR product."""
+    1e-8; a thorax slice (torso rows) keeps the CSR product.  With multigrid
+    blocks (a banded order) the positions hold 16-bit column offsets (18
+    bytes per position) and the solve matches the oracle too."""
     import paper_1711_08708_amd as B
     cfg = w.slab3d(n=12)
     solver = B.Solver(cfg, eps_h=0.0)
@@ -246,6 +248,15 @@ def test_lambda_blocked_form(torch):
     _check_solve_cg(torch, cfg, solver, "slab12 blocked Lambda")
     th = B.Solver(w.thorax2d(n_target=3000, seed=7), eps_h=0.0)
     assert th.info["bytes_lambda"] > 12 * th.info["nnz_lambda"]
+    kw = dict(eps_h=0.0, inner_p1=B.P1_AMG, inner_pk=B.PK_AMG)
+    s16 = B.Solver(cfg, amg_columns=0, **kw)
+    s32 = B.Solver(cfg, amg_columns=1, **kw)
+    assert s16.info["nnz_lambda"] % 4 == 0
+    npos = s16.info["nnz_lambda"] // 4                     # Lambda = four blocks of one pattern
+    print("slab12 multigrid Lambda bytes, 16-bit / 32-bit columns", s16.info["bytes_lambda"],
+          s32.info["bytes_lambda"], flush=True)
+    assert s32.info["bytes_lambda"] - s16.info["bytes_lambda"] == 2 * npos - 4 * s16.N
+    _check_solve_cg(torch, cfg, s16, "slab12 blocked Lambda, 16-bit columns")
 
 
 def test_range_and_dt_errors(torch):
