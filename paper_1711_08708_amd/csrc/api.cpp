@@ -611,6 +611,8 @@ struct bido_ctx {
     double* vs = nullptr;             // Strang splitting: V* after the first reaction half-step
     // recording of the steps (bido_record): activation times, probe rows
     int64_t step_n = 0;               // index of the step in progress
+    double* xh = nullptr;             // the initial state of step xh_n (extrapolated guess)
+    int64_t xh_n = -2;
     struct Recording {
         bool on = false;
         double v_act = 0.0;
@@ -648,7 +650,7 @@ struct bido_ctx {
         CsrHostView::release(avu);
         CsrHostView::release(auv);
         CsrHostView::release(km);
-        for (double* b : {x, r, z, p, q, Y, tA, tB, tC, tD, r_old, sc, m_int, mh_loc, stim_loc, km_dinv, ch_r,
+        for (double* b : {x, xh, r, z, p, q, Y, tA, tB, tC, tD, r_old, sc, m_int, mh_loc, stim_loc, km_dinv, ch_r,
                           ch_d[0], ch_d[1], vs})
             hipFree(b);
         hipFree(rd.partials);
@@ -1299,6 +1301,12 @@ void step_prepare(bido_ctx* c, double* v, double* w, double* u, int64_t n) {
          launch_ionic(s, NH, vin, w, c->stim_loc, on, c->mh_loc, c->v_pos, c->Y + N, c->x + N, sub,
                       ionic_consts(c)));                               // Steps 1 and 3
     PROF(c, K_MISC, 8.0 * N, launch_fill(s, N, c->Y, 0.0));           // Y1 = 0
+    if (c->params.extrapolate) {
+        // X0 = 2 X^n - X^{n-1} when this context's previous step was n - 1
+        // at the same dt; the state of this step is kept for the next
+        PROF(c, K_MISC, 24.0 * c->n2, launch_extrapolate(s, c->n2, c->x, c->xh, c->xh_n == n - 1));
+        c->xh_n = n;
+    }
 }
 
 // Steps 1 and 3 and the start of Step 2 (no wait).
@@ -1898,6 +1906,7 @@ void bido_default_params(bido_params* p) {
     p->ionic = 0;
     p->n_threads = 0;
     p->scheme = BIDO_SCHEME_EULER;
+    p->extrapolate = 1;
 }
 
 bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const bido_params* params,
@@ -1968,6 +1977,7 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     const int64_t n2 = c->n2;
     for (double** b : {&c->x, &c->r, &c->z, &c->p, &c->q, &c->Y, &c->r_old})
         HIP_OK(hipMalloc((void**)b, n2 * sizeof(double)));
+    if (params->extrapolate) HIP_OK(hipMalloc((void**)&c->xh, n2 * sizeof(double)));
     for (double** b : {&c->tA, &c->tC, &c->tD}) HIP_OK(hipMalloc((void**)b, c->N * sizeof(double)));
     HIP_OK(hipMalloc((void**)&c->tB, std::max<int64_t>(c->NH, 1) * sizeof(double)));
     if (hs.params.scheme == BIDO_SCHEME_STRANG)
@@ -2821,6 +2831,7 @@ bido_status bido_set_dt(bido_ctx* c, double dt, double* seconds) {
     // the context refusing every step (dt NaN) until a later call succeeds
     c->params.dt = std::nan("");
     c->drop_graphs();
+    c->xh_n = -2;                 // no extrapolation across a change of step
     bido_status e = set_dt_device(c, refactor);
     if (e) return e;
     c->params.dt = dt;

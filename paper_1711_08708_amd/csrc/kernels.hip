@@ -82,6 +82,16 @@ __global__ void k_fill(int64_t n, double* x, double v) {
         x[i] = v;
 }
 
+// initial guess from the two previous states: x = 2 x - h (extrapolate) or
+// x kept, and h = the x passed in
+__global__ void k_extrapolate(int64_t n, double* __restrict__ x, double* __restrict__ h, int extrapolate) {
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        const double t = x[i];
+        if (extrapolate) x[i] = 2.0 * t - h[i];
+        h[i] = t;
+    }
+}
+
 __global__ void k_add2(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
                        double* __restrict__ out) {
     for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
@@ -1334,6 +1344,10 @@ void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y)
 void launch_fill(hipStream_t s, int64_t n, double* x, double v) {
     if (n <= 0) return;
     k_fill<<<grid_for(n), BLOCK, 0, s>>>(n, x, v);
+}
+void launch_extrapolate(hipStream_t s, int64_t n, double* x, double* h, bool extrapolate) {
+    if (n <= 0) return;
+    k_extrapolate<<<grid_for(n), BLOCK, 0, s>>>(n, x, h, extrapolate ? 1 : 0);
 }
 void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst) {
     if (n <= 0) return;

@@ -103,6 +103,9 @@ constexpr int64_t NOALLOC_SCRATCH_DOUBLES = int64_t(8) << 20;
 hipError_t noalloc_scratch(int device, double** ptr);
 
 void launch_fill(hipStream_t s, int64_t n, double* x, double v);
+// x = 2 x - h when extrapolate, then h = the x passed in (the initial guess
+// from the states of the two previous steps)
+void launch_extrapolate(hipStream_t s, int64_t n, double* x, double* h, bool extrapolate);
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y);   // y += a x
 void launch_add2(hipStream_t s, int64_t n, const double* a, const double* b, double* out);   // out = a + b
 // A CSR matrix of a multigrid level with FP64 or FP32 values, and the lanes

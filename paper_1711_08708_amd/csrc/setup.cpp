@@ -163,6 +163,10 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
         err = "bad amg_columns";
         return false;
     }
+    if (P.extrapolate != 0 && P.extrapolate != 1) {
+        err = "bad extrapolate";
+        return false;
+    }
     if (P.inner_pk != BIDO_PK_CHOLESKY && P.inner_pk != BIDO_PK_CHEBYSHEV && P.inner_pk != BIDO_PK_AMG) {
         err = "bad inner_pk";
         return false;

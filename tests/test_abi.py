@@ -34,9 +34,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header():
     import paper_1711_08708_amd as B
-    # bido_params: 6 doubles + 9 ints (+ 4 bytes of tail padding); bido_stats:
+    # bido_params: 6 doubles + 11 ints (+ 4 bytes of tail padding); bido_stats:
     # 2 ints, 2 doubles, int, double, int64
-    assert ctypes.sizeof(B.Params) == 6 * 8 + 9 * 4 + 4
+    assert ctypes.sizeof(B.Params) == 6 * 8 + 11 * 4 + 4
     assert B.default_params().scheme == B.SCHEME_EULER
     assert ctypes.sizeof(B.Stats) == 48
     p = B.default_params()
@@ -459,3 +459,22 @@ def test_setup_refuses_malformed_input(case, msg):
     with pytest.raises(B.BidoError, match=msg) as ei:
         B.HostSetup(cfg)
     assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("field,value", [("amg_columns", 2), ("amg_columns", -1), ("extrapolate", 2),
+                                         ("inner_pk", 9), ("inner_p1", 4)])
+def test_setup_refuses_bad_options(field, value):
+    """Option fields outside their documented values are refused at set-up
+    with BIDO_ERR_ARG and a message naming the field."""
+    import paper_1711_08708_amd as B
+    with pytest.raises(B.BidoError, match=field) as ei:
+        B.HostSetup(w.square2d(n=6), **{field: value})
+    assert ei.value.code == -1
+
+
+def test_default_options():
+    """Defaults: 16-bit multigrid columns where they fit, extrapolated
+    initial guesses."""
+    import paper_1711_08708_amd as B
+    p = B.default_params()
+    assert p.amg_columns == 0 and p.extrapolate == 1

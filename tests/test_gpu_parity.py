@@ -125,6 +125,36 @@ def test_step_trajectory_square48(torch):
     print("square48 worst per-step error", worst)
 
 
+@pytest.mark.parametrize("name", ["square48", "thorax3000"])
+def test_extrapolated_initial_guess(torch, name):
+    """The default initial guess X0 = 2 X^n - X^{n-1} (the previous step's
+    starting state) with multigrid inner solves: steps match the oracle's
+    step from the same state, and a run takes fewer PCG iterations than
+    with X0 = X^n (extrapolate = 0), ending in the same state."""
+    import paper_1711_08708_amd as B
+    from oracle import bidomain as bd
+    cfg = w.make_config("square48") if name == "square48" else w.thorax2d(n_target=3000, seed=11)
+    s = bd.System(cfg)
+    n_steps = 16
+    tot, final = {}, {}
+    for ex in (0, 1):
+        solver = B.Solver(cfg, eps_h=0.0, tol=1e-12, inner_p1=B.P1_AMG, inner_pk=B.PK_AMG, extrapolate=ex)
+        v, h, u = solver.state()
+        tot[ex] = 0
+        for n in range(n_steps):
+            Vn, hn = v.cpu().numpy().copy(), h.cpu().numpy().copy()
+            tot[ex] += solver.step(v, h, u, n)["iterations"]
+            if ex == 1 and n % 4 == 3:
+                Uo_p, Vo, _ = s.step(Vn, hn, n, method="dense")
+                eu, ev = _errs(u.cpu().numpy(), v.cpu().numpy(), s.to_global_u(Uo_p), Vo)
+                assert eu <= TOL_PARITY and ev <= TOL_PARITY, (n, eu, ev)
+        final[ex] = (u.cpu().numpy(), v.cpu().numpy())
+    print(f"{name}: PCG iterations over {n_steps} steps, X0 = X^n {tot[0]}, extrapolated {tot[1]}", flush=True)
+    assert tot[1] < tot[0]
+    eu, ev = _errs(final[1][0], final[1][1], final[0][0], final[0][1])
+    assert eu <= TOL_PARITY and ev <= TOL_PARITY
+
+
 @pytest.mark.parametrize("mk,eps,n_steps", [(lambda: w.make_config("square48"), 0.0, 20),
                                              (lambda: w.thorax2d(n_target=3000, seed=11), 1e-8, 12)],
                          ids=["square48", "thorax3000"])
