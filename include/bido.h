@@ -116,12 +116,14 @@ typedef struct {
                           base wherever every row of a matrix spans fewer
                           than 65536 columns (the default), 1 = always
                           32-bit; the result is the same                  */
-    int extrapolate;   /* initial guess of a step's solve: 0 = X0 = (U^n,
-                          V^n); 1 (the default) = X0 = 2 X^n - X^{n-1}
-                          when the previous step of this context was step
-                          n - 1 at the same dt (else X^n); X^{n-1} is the
-                          state that step started from.  Only the
-                          iteration count moves (128^3 slab: 20 -> 18). */
+    int guess_states;  /* initial guess of a step's solve: 0 = X0 = (U^n,
+                          V^n); k = 1..16 (default 8) = the projection of
+                          the solution onto the span of the states the
+                          last k consecutive steps of this context started
+                          from (X^n included), orthogonal in the Lambda
+                          inner product: X0 = W c, (W^T Lambda W) c = W^T Y.
+                          A change of dt restarts the span.  Only the
+                          iteration count moves.                        */
 } bido_params;
 
 /* Inner solves inside the block-LU preconditioner (Def. 2).  Sec. 5.3 lets
@@ -196,7 +198,7 @@ const char* bido_last_error(void);
 /* Fill *p with the defaults (chi 200, cm 1, dt 0.1, eps 1e-3, eta 2,
  * tol 1e-10, leaf 64, max_iter 200, FP64, plain, MS, semi-implicit Euler,
  * Cholesky inner solves, 16-bit multigrid columns where they fit,
- * extrapolated initial guesses).                                         */
+ * projected initial guesses over 8 states).                              */
 void bido_default_params(bido_params* p);
 
 /* Assemble S_1, S_i, S_m and the lumped M, M_H from the mesh (Sec. 3.1,

@@ -54,7 +54,7 @@ class Params(ctypes.Structure):
                 ("leaf", ctypes.c_int), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("precond", ctypes.c_int), ("ionic", ctypes.c_int), ("n_threads", ctypes.c_int),
                 ("scheme", ctypes.c_int), ("inner_p1", ctypes.c_int), ("inner_pk", ctypes.c_int),
-                ("amg_columns", ctypes.c_int), ("extrapolate", ctypes.c_int)]
+                ("amg_columns", ctypes.c_int), ("guess_states", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -611,8 +611,16 @@ struct bido_ctx {
     double* vs = nullptr;             // Strang splitting: V* after the first reaction half-step
     // recording of the steps (bido_record): activation times, probe rows
     int64_t step_n = 0;               // index of the step in progress
-    double* xh = nullptr;             // the initial state of step xh_n (extrapolated guess)
-    int64_t xh_n = -2;
+    // projected initial guess: a ring of params.guess_states states (the
+    // ones the last steps started from) and their Lambda images, gw[g_head]
+    // the state of step g_n and g_len consecutive ones; their Gram matrix
+    // (by slot), dot and coefficient scratch, and the reduction of the dots
+    double* gw[GUESS_MAX] = {};
+    double* gaw[GUESS_MAX] = {};
+    double *gG = nullptr, *gd = nullptr, *gb = nullptr, *gc = nullptr;
+    Reduce grd;
+    int g_head = 0, g_len = 0;
+    int64_t g_n = -2;
     struct Recording {
         bool on = false;
         double v_act = 0.0;
@@ -650,7 +658,13 @@ struct bido_ctx {
         CsrHostView::release(avu);
         CsrHostView::release(auv);
         CsrHostView::release(km);
-        for (double* b : {x, xh, r, z, p, q, Y, tA, tB, tC, tD, r_old, sc, m_int, mh_loc, stim_loc, km_dinv, ch_r,
+        for (double* b : gw) hipFree(b);
+        for (double* b : gaw) hipFree(b);
+        hipFree(gG);
+        hipFree(gd);
+        hipFree(grd.partials);
+        hipFree(grd.counter);
+        for (double* b : {x, r, z, p, q, Y, tA, tB, tC, tD, r_old, sc, m_int, mh_loc, stim_loc, km_dinv, ch_r,
                           ch_d[0], ch_d[1], vs})
             hipFree(b);
         hipFree(rd.partials);
@@ -1250,6 +1264,47 @@ void elliptic_refine(bido_ctx* c) {
     }
 }
 
+// The initial guess of step n from the states the previous steps of this
+// context started from (consecutive steps n - 1, n - 2, ... at the same
+// dt): X^n (the state passed in) joins the ring with its Lambda image and
+// its Gram row, and X0 = W c with (W^T Lambda W) c = W^T Y over the ring,
+// the Lambda-orthogonal projection of the solution onto the span of the
+// states (Fischer's projection for a sequence of right-hand sides), which
+// holds X^n: the guess is never farther from the solution in the Lambda
+// norm than X^n.  Launches only; no host wait.
+void project_guess(bido_ctx* c, int64_t n) {
+    hipStream_t s = c->stream;
+    const int K = c->params.guess_states;
+    const int64_t n2 = c->n2;
+    if (c->g_n != n - 1) c->g_len = 0;
+    const int slot = (c->g_head + K - 1) % K;       // the oldest (or a free) slot becomes the newest
+    c->g_head = slot;
+    c->g_len = std::min(c->g_len + 1, K);
+    c->g_n = n;
+    if (hipMemcpyAsync(c->gw[slot], c->x, n2 * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        c->g_len = 0;                               // X0 = X^n; the next step starts a new span
+        c->g_n = -2;
+        return;
+    }
+    if (c->lamb.on())
+        PROF(c, K_SPMV_LAMBDA, blk_bytes(c->lamb, 0),
+             launch_spmv_lam_blk(s, c->lamb, c->spmv_group, 0, c->x, nullptr, c->gaw[slot], c->sc));
+    else
+        PROF(c, K_SPMV_LAMBDA, csr_bytes(c->lam, n2),
+             launch_spmv_lambda(s, c->lam, c->spmv_group, 0, c->x, nullptr, c->gaw[slot], c->sc));
+    GuessList W;
+    W.m = c->g_len;
+    for (int k = 0; k < W.m; ++k) {
+        W.slot[k] = (slot + k) % K;
+        W.v[k] = c->gw[W.slot[k]];
+    }
+    const double vb = 8.0 * n2 * (W.m + 1);
+    PROF(c, K_MISC, vb, launch_multidot(s, n2, W, c->gaw[slot], c->grd, c->gd));     // the new Gram row
+    PROF(c, K_MISC, vb, launch_multidot(s, n2, W, c->Y, c->grd, c->gb));             // W^T Y
+    PROF(c, K_MISC, 0.0, launch_guess_solve(s, W, c->gd, c->gG, c->gb, c->gc));
+    PROF(c, K_MISC, vb, launch_guess_combine(s, n2, W, c->gc, c->x));
+}
+
 // Steps 1 and 3 on the device: X0 = (U^n, V^n) and the right-hand side Y.
 void step_prepare(bido_ctx* c, double* v, double* w, double* u, int64_t n) {
     hipStream_t s = c->stream;
@@ -1301,12 +1356,7 @@ void step_prepare(bido_ctx* c, double* v, double* w, double* u, int64_t n) {
          launch_ionic(s, NH, vin, w, c->stim_loc, on, c->mh_loc, c->v_pos, c->Y + N, c->x + N, sub,
                       ionic_consts(c)));                               // Steps 1 and 3
     PROF(c, K_MISC, 8.0 * N, launch_fill(s, N, c->Y, 0.0));           // Y1 = 0
-    if (c->params.extrapolate) {
-        // X0 = 2 X^n - X^{n-1} when this context's previous step was n - 1
-        // at the same dt; the state of this step is kept for the next
-        PROF(c, K_MISC, 24.0 * c->n2, launch_extrapolate(s, c->n2, c->x, c->xh, c->xh_n == n - 1));
-        c->xh_n = n;
-    }
+    if (c->params.guess_states) project_guess(c, n);
 }
 
 // Steps 1 and 3 and the start of Step 2 (no wait).
@@ -1906,7 +1956,7 @@ void bido_default_params(bido_params* p) {
     p->ionic = 0;
     p->n_threads = 0;
     p->scheme = BIDO_SCHEME_EULER;
-    p->extrapolate = 1;
+    p->guess_states = 8;
 }
 
 bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const bido_params* params,
@@ -1977,7 +2027,20 @@ bido_status bido_create(const bido_mesh* mesh, const bido_tissue* tissue, const 
     const int64_t n2 = c->n2;
     for (double** b : {&c->x, &c->r, &c->z, &c->p, &c->q, &c->Y, &c->r_old})
         HIP_OK(hipMalloc((void**)b, n2 * sizeof(double)));
-    if (params->extrapolate) HIP_OK(hipMalloc((void**)&c->xh, n2 * sizeof(double)));
+    for (int k = 0; k < params->guess_states; ++k) {
+        HIP_OK(hipMalloc((void**)&c->gw[k], n2 * sizeof(double)));
+        HIP_OK(hipMalloc((void**)&c->gaw[k], n2 * sizeof(double)));
+    }
+    if (params->guess_states) {
+        HIP_OK(hipMalloc((void**)&c->gG, GUESS_MAX * GUESS_MAX * sizeof(double)));
+        HIP_OK(hipMalloc((void**)&c->gd, 3 * GUESS_MAX * sizeof(double)));
+        c->gb = c->gd + GUESS_MAX;
+        c->gc = c->gd + 2 * GUESS_MAX;
+        c->grd.max_blocks = 1024;
+        HIP_OK(hipMalloc((void**)&c->grd.partials, (size_t)GUESS_MAX * c->grd.max_blocks * sizeof(double)));
+        HIP_OK(hipMalloc((void**)&c->grd.counter, sizeof(unsigned)));
+        HIP_OK(hipMemset(c->grd.counter, 0, sizeof(unsigned)));
+    }
     for (double** b : {&c->tA, &c->tC, &c->tD}) HIP_OK(hipMalloc((void**)b, c->N * sizeof(double)));
     HIP_OK(hipMalloc((void**)&c->tB, std::max<int64_t>(c->NH, 1) * sizeof(double)));
     if (hs.params.scheme == BIDO_SCHEME_STRANG)
@@ -2831,7 +2894,7 @@ bido_status bido_set_dt(bido_ctx* c, double dt, double* seconds) {
     // the context refusing every step (dt NaN) until a later call succeeds
     c->params.dt = std::nan("");
     c->drop_graphs();
-    c->xh_n = -2;                 // no extrapolation across a change of step
+    c->g_n = -2;                  // the states of another dt leave the projection
     bido_status e = set_dt_device(c, refactor);
     if (e) return e;
     c->params.dt = dt;

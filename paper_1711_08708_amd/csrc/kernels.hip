@@ -82,16 +82,6 @@ __global__ void k_fill(int64_t n, double* x, double v) {
         x[i] = v;
 }
 
-// initial guess from the two previous states: x = 2 x - h (extrapolate) or
-// x kept, and h = the x passed in
-__global__ void k_extrapolate(int64_t n, double* __restrict__ x, double* __restrict__ h, int extrapolate) {
-    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
-        const double t = x[i];
-        if (extrapolate) x[i] = 2.0 * t - h[i];
-        h[i] = t;
-    }
-}
-
 __global__ void k_add2(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
                        double* __restrict__ out) {
     for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
@@ -181,6 +171,92 @@ __global__ void k_dot_reduce(int64_t n, const double* __restrict__ a, const doub
     s = block_sum(s, sh);
     double part[1] = {s};
     finish_reduce<1>(part, partials, counter, out, sh);
+}
+
+// ---------------------------------------------------------------------------
+// Initial guess of a step's solve: the Lambda-orthogonal projection of the
+// solution onto the span of the states W_k the last steps started from
+// (Fischer's projection for a sequence of right-hand sides): x0 = W c with
+// (W^T Lambda W) c = W^T Y.  The Gram matrix G is kept by ring slot and gets
+// one new row per step; everything stays on the device.
+// ---------------------------------------------------------------------------
+// out[k] = W_k . y for k < W.m (out[k] = 0 beyond), last-block reduction
+__global__ void k_multidot(int64_t n, GuessList W, const double* __restrict__ y, double* partials,
+                           unsigned* counter, double* out) {
+    __shared__ double sh[BLOCK / WAVE];
+    double part[GUESS_MAX];
+#pragma unroll
+    for (int k = 0; k < GUESS_MAX; ++k) part[k] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        const double yi = y[i];
+#pragma unroll
+        for (int k = 0; k < GUESS_MAX; ++k)
+            if (k < W.m) part[k] += W.v[k][i] * yi;
+    }
+#pragma unroll
+    for (int k = 0; k < GUESS_MAX; ++k) part[k] = block_sum(part[k], sh);
+    finish_reduce<GUESS_MAX>(part, partials, counter, out, sh);
+}
+
+// One thread: the new Gram row (d[k] = W_k . Lambda W_0, W_0 the newest, at
+// ring slot W.slot[0]) into G (ld GUESS_MAX, by slot), then, when b is
+// given, c from (G_W + delta I) c = b by Cholesky, delta = 1e-13 times the
+// largest diagonal entry (the states are close to dependent); a failed
+// factorisation keeps x0 = W_0 (c = e_0).
+__global__ void k_guess_solve(GuessList W, const double* __restrict__ d, double* G, const double* __restrict__ b,
+                              double* __restrict__ c) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int m = W.m;
+    if (d)
+        for (int k = 0; k < m; ++k) {
+            G[W.slot[0] * GUESS_MAX + W.slot[k]] = d[k];
+            G[W.slot[k] * GUESS_MAX + W.slot[0]] = d[k];
+        }
+    if (!b) return;
+    double L[GUESS_MAX * GUESS_MAX], z[GUESS_MAX];
+    double dmax = 0.0;
+    for (int k = 0; k < m; ++k) dmax = fmax(dmax, G[W.slot[k] * GUESS_MAX + W.slot[k]]);
+    const double delta = 1e-13 * dmax;
+    bool ok = dmax > 0.0;
+    for (int i = 0; i < m && ok; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = G[W.slot[i] * GUESS_MAX + W.slot[j]] + (i == j ? delta : 0.0);
+            for (int k = 0; k < j; ++k) s -= L[i * GUESS_MAX + k] * L[j * GUESS_MAX + k];
+            if (i == j) {
+                if (!(s > 0.0)) { ok = false; break; }
+                L[i * GUESS_MAX + i] = sqrt(s);
+            } else {
+                L[i * GUESS_MAX + j] = s / L[j * GUESS_MAX + j];
+            }
+        }
+    if (!ok) {
+        for (int k = 0; k < m; ++k) c[k] = k == 0 ? 1.0 : 0.0;
+        return;
+    }
+    for (int i = 0; i < m; ++i) {                  // L z = b
+        double s = b[i];
+        for (int k = 0; k < i; ++k) s -= L[i * GUESS_MAX + k] * z[k];
+        z[i] = s / L[i * GUESS_MAX + i];
+    }
+    for (int i = m - 1; i >= 0; --i) {             // L^T c = z
+        double s = z[i];
+        for (int k = i + 1; k < m; ++k) s -= L[k * GUESS_MAX + i] * c[k];
+        c[i] = s / L[i * GUESS_MAX + i];
+    }
+}
+
+// x = sum_k c[k] W_k
+__global__ void k_guess_combine(int64_t n, GuessList W, const double* __restrict__ c, double* __restrict__ x) {
+    double ck[GUESS_MAX];
+#pragma unroll
+    for (int k = 0; k < GUESS_MAX; ++k) ck[k] = k < W.m ? c[k] : 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < GUESS_MAX; ++k)
+            if (k < W.m) s += ck[k] * W.v[k][i];
+        x[i] = s;
+    }
 }
 
 // x[i] -= sc[slot] / den   for i < n
@@ -1345,10 +1421,6 @@ void launch_fill(hipStream_t s, int64_t n, double* x, double v) {
     if (n <= 0) return;
     k_fill<<<grid_for(n), BLOCK, 0, s>>>(n, x, v);
 }
-void launch_extrapolate(hipStream_t s, int64_t n, double* x, double* h, bool extrapolate) {
-    if (n <= 0) return;
-    k_extrapolate<<<grid_for(n), BLOCK, 0, s>>>(n, x, h, extrapolate ? 1 : 0);
-}
 void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst) {
     if (n <= 0) return;
     k_scatter_in<<<grid_for(n), BLOCK, 0, s>>>(n, pos, src, dst);
@@ -1389,6 +1461,15 @@ void launch_probe(hipStream_t s, int np, int nv, const int64_t* ids, const doubl
 }
 void launch_dot_reduce(hipStream_t s, int64_t n, const double* a, const double* b, Reduce rd, double* out) {
     k_dot_reduce<<<grid_for(n, BLOCK * 4, rd.max_blocks), BLOCK, 0, s>>>(n, a, b, rd.partials, rd.counter, out);
+}
+void launch_multidot(hipStream_t s, int64_t n, const GuessList& W, const double* y, Reduce rd, double* out) {
+    k_multidot<<<grid_for(n, BLOCK * 4, rd.max_blocks), BLOCK, 0, s>>>(n, W, y, rd.partials, rd.counter, out);
+}
+void launch_guess_solve(hipStream_t s, const GuessList& W, const double* d, double* G, const double* b, double* c) {
+    k_guess_solve<<<1, 64, 0, s>>>(W, d, G, b, c);
+}
+void launch_guess_combine(hipStream_t s, int64_t n, const GuessList& W, const double* c, double* x) {
+    if (n > 0) k_guess_combine<<<grid_for(n), BLOCK, 0, s>>>(n, W, c, x);
 }
 void launch_shift(hipStream_t s, int64_t n, double* x, const double* sc, int slot, double den) {
     if (n <= 0) return;

@@ -103,9 +103,18 @@ constexpr int64_t NOALLOC_SCRATCH_DOUBLES = int64_t(8) << 20;
 hipError_t noalloc_scratch(int device, double** ptr);
 
 void launch_fill(hipStream_t s, int64_t n, double* x, double v);
-// x = 2 x - h when extrapolate, then h = the x passed in (the initial guess
-// from the states of the two previous steps)
-void launch_extrapolate(hipStream_t s, int64_t n, double* x, double* h, bool extrapolate);
+// Projected initial guess (kernels.hip): the states W_k of the last steps,
+// newest first, with their ring slots; out[k] = W_k . y (Reduce: partials
+// of GUESS_MAX x max_blocks); the Gram row and the small solve; x = W c.
+constexpr int GUESS_MAX = 16;
+struct GuessList {
+    const double* v[GUESS_MAX] = {};
+    int slot[GUESS_MAX] = {};
+    int m = 0;
+};
+void launch_multidot(hipStream_t s, int64_t n, const GuessList& W, const double* y, Reduce rd, double* out);
+void launch_guess_solve(hipStream_t s, const GuessList& W, const double* d, double* G, const double* b, double* c);
+void launch_guess_combine(hipStream_t s, int64_t n, const GuessList& W, const double* c, double* x);
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y);   // y += a x
 void launch_add2(hipStream_t s, int64_t n, const double* a, const double* b, double* out);   // out = a + b
 // A CSR matrix of a multigrid level with FP64 or FP32 values, and the lanes

@@ -163,8 +163,8 @@ bool build_host(const bido_mesh* mesh, const bido_tissue* tissue, const bido_par
         err = "bad amg_columns";
         return false;
     }
-    if (P.extrapolate != 0 && P.extrapolate != 1) {
-        err = "bad extrapolate";
+    if (P.guess_states < 0 || P.guess_states > 16) {
+        err = "bad guess_states (0 to 16)";
         return false;
     }
     if (P.inner_pk != BIDO_PK_CHOLESKY && P.inner_pk != BIDO_PK_CHEBYSHEV && P.inner_pk != BIDO_PK_AMG) {

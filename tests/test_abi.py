@@ -461,7 +461,7 @@ def test_setup_refuses_malformed_input(case, msg):
     assert ei.value.code == -1
 
 
-@pytest.mark.parametrize("field,value", [("amg_columns", 2), ("amg_columns", -1), ("extrapolate", 2),
+@pytest.mark.parametrize("field,value", [("amg_columns", 2), ("amg_columns", -1), ("guess_states", 17), ("guess_states", -1),
                                          ("inner_pk", 9), ("inner_p1", 4)])
 def test_setup_refuses_bad_options(field, value):
     """Option fields outside their documented values are refused at set-up
@@ -473,8 +473,8 @@ def test_setup_refuses_bad_options(field, value):
 
 
 def test_default_options():
-    """Defaults: 16-bit multigrid columns where they fit, extrapolated
-    initial guesses."""
+    """Defaults: 16-bit multigrid columns where they fit, initial guesses
+    projected onto the span of 8 previous states."""
     import paper_1711_08708_amd as B
     p = B.default_params()
-    assert p.amg_columns == 0 and p.extrapolate == 1
+    assert p.amg_columns == 0 and p.guess_states == 8
