@@ -320,6 +320,7 @@ def _variants(torch, B, solver, args, w_cfg):
         solver.set_precision(prec)
         solver.set_precond(pc)
         solver.set_pk(pk, args.pk_steps)
+        solver.reset_guess()                      # every variant starts its span of states afresh
         st = [t.clone() for t in saved]
         _, ws, it = _timed_steps(torch, solver, st, n1, args.variant_steps)
         out[name] = {"steps_per_s": round(args.variant_steps / ws, 3),
@@ -414,6 +415,7 @@ def _bench_slab128(args):
     for name, prec, pc in runs:
         solver.set_precision(prec)
         solver.set_precond(pc)
+        solver.reset_guess()                      # every variant starts its span of states afresh
         st = [t.clone() for t in saved]
         for n in range(n1, n1 + args.warmup):                 # warm-up steps of this variant
             solver.step(st[0], st[1], st[2], n)
@@ -439,6 +441,7 @@ def _bench_slab128(args):
     # replay the headline variant's timed steps with per-launch events
     solver.set_precision(B.PREC_MIXED)
     solver.set_precond(B.PRECOND_LEARNED if head == "learned_mixed" else B.PRECOND_PLAIN)
+    solver.reset_guess()
     st = [t.clone() for t in saved]
     for n in range(n1, n1 + args.warmup):
         solver.step(st[0], st[1], st[2], n)

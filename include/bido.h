@@ -401,6 +401,12 @@ typedef struct {
  * stencil (BIDO_ERR_STATE otherwise).                                      */
 bido_status bido_set_precond(bido_ctx* ctx, int precond);
 
+/* Forget the states of the previous steps that span the projected initial
+ * guess (bido_params.guess_states): the next step starts a new span from
+ * its own state.  For callers that restart a run from another state, and
+ * for comparing runs from equal starting points.  Enqueues nothing.       */
+bido_status bido_reset_guess(bido_ctx* ctx);
+
 /* Run n_steps plain steps (as bido_run) recording training pairs, up to
  * max_samples in total (device memory: 16 N_H + 16 bytes per sample).            */
 bido_status bido_learn_collect(bido_ctx* ctx, double* v, double* w, double* u, double dt,

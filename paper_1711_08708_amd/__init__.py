@@ -157,6 +157,7 @@ ABI = {
     "bido_inner_solve_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                                 ctypes.c_void_p, _c_i64_p]),
     "bido_set_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "bido_reset_guess": (ctypes.c_int, [ctypes.c_void_p]),
     "bido_set_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, _c_double_p]),
     "bido_set_pk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_double]),
@@ -442,6 +443,10 @@ class Solver:
     # ---- learned correction -------------------------------------------------
     def set_precond(self, precond):
         _check(lib.bido_set_precond(self.ctx, int(precond)))
+
+    def reset_guess(self):
+        """The next step starts a new span of states for its initial guess."""
+        _check(lib.bido_reset_guess(self.ctx))
 
     def learn_collect(self, v, w, u, n0, n_steps, max_samples):
         st = Stats()

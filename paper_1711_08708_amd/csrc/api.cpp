@@ -2962,6 +2962,13 @@ bido_status bido_get_pk(const bido_ctx* c, int* kind, int* steps, double* lo, do
     return BIDO_OK;
 }
 
+bido_status bido_reset_guess(bido_ctx* c) {
+    if (!c) return fail(BIDO_ERR_ARG, "null context");
+    c->g_n = -2;
+    c->g_len = 0;
+    return BIDO_OK;
+}
+
 bido_status bido_set_precond(bido_ctx* c, int precond) {
     if (!c) return fail(BIDO_ERR_ARG, "null context");
     if (precond != BIDO_PRECOND_PLAIN && precond != BIDO_PRECOND_LEARNED &&

@@ -101,6 +101,7 @@ def _solve_steps(torch, solver, s, state, n0, n_steps, learned):
     import paper_1711_08708_amd as B
     v, h, u = [x.clone() for x in state]
     solver.set_precond(learned if learned else B.PRECOND_PLAIN)
+    solver.reset_guess()                # runs compared from equal starting points
     iters, worst, fb = [], 0.0, 0
     for n in range(n0, n0 + n_steps):
         Vn, hn = v.cpu().numpy().copy(), h.cpu().numpy().copy()
