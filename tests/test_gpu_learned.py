@@ -163,29 +163,41 @@ def test_learned_additive_and_flexible_cg(torch, setup, collected):
     assert wp <= 1e-8 and wl <= 1e-8
 
 
-@pytest.mark.xfail(reason="the trained corrections do not lower the iteration count: measured "
-                          "thorax200k 8.00 plain vs 8.14-8.22 stencil per step, thorax6000 5 vs 6 "
-                          "additive; the stencil on the S_m pattern cannot represent the non-local "
-                          "S_i S_1^+ S_i part of the Schur complement", strict=False)
-@pytest.mark.parametrize("kind", ["stencil", "additive"])
-def test_learned_gain(torch, setup, collected, kind):
-    """What the trained network gains over the plain block-LU preconditioner
-    on held-out steps (after the 12 collected ones), both at 1e-8 parity:
-    the total iteration count with the correction must not exceed the plain
-    one."""
+def _gain(torch, setup, collected, kind):
+    """Iterations of the plain block-LU preconditioner and of the trained
+    correction on the 6 held-out steps after the 12 collected ones, each run
+    from the same state and a fresh span of initial-guess states, both at
+    1e-8 parity."""
     B, mpnn, s, A, st, solver, theta = setup
     solver.set_weights(mpnn.init_params(3) * np.concatenate([np.ones(mpnn.N_PARAMS - 33), np.zeros(33)]))
     if kind == "stencil":
-        solver.learn_train(kind=B.LEARN_STENCIL, epochs=30, batch=4, lr=2e-3, seed=1, n_val=4)
+        ts = solver.learn_train(kind=B.LEARN_STENCIL, epochs=30, batch=4, lr=2e-3, seed=1, n_val=4)
         mode = B.PRECOND_LEARNED
     else:
-        solver.learn_train(kind=B.LEARN_ADDITIVE, epochs=40, batch=4, lr=2e-3, seed=1, n_val=4)
+        ts = solver.learn_train(kind=B.LEARN_ADDITIVE, epochs=40, batch=4, lr=2e-3, seed=1, n_val=4)
         mode = B.PRECOND_LEARNED_ADDITIVE
     it_p, wp, _, _ = _solve_steps(torch, solver, s, collected, 12, 6, learned=0)
     it_l, wl, _, _ = _solve_steps(torch, solver, s, collected, 12, 6, learned=mode)
-    print(f"gain {kind}: plain {sum(it_p)} ({it_p}) learned {sum(it_l)} ({it_l})", flush=True)
+    print(f"gain {kind}: plain {sum(it_p)} ({it_p}) learned {sum(it_l)} ({it_l}), kept epoch {ts['best_epoch']}",
+          flush=True)
     assert wp <= 1e-8 and wl <= 1e-8
-    assert sum(it_l) <= sum(it_p)
+    return it_p, it_l
+
+
+def test_learned_stencil_gain(torch, setup, collected):
+    """What the trained stencil gains over the plain block-LU preconditioner
+    on held-out steps (thorax6000 with exact inner factors: 23 -> 21
+    iterations over 6 steps): fewer iterations in total."""
+    it_p, it_l = _gain(torch, setup, collected, "stencil")
+    assert sum(it_l) < sum(it_p)
+
+
+@pytest.mark.xfail(reason="the trained additive correction does not lower the iteration count: "
+                          "measured thorax6000 23 plain vs 25 additive over 6 held-out steps", strict=False)
+def test_learned_additive_gain(torch, setup, collected):
+    """The same for the additive correction of the Schur-complement solve."""
+    it_p, it_l = _gain(torch, setup, collected, "additive")
+    assert sum(it_l) < sum(it_p)
 
 
 def test_fallback_keeps_parity(torch, setup):
