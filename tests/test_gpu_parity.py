@@ -166,6 +166,34 @@ def test_projected_initial_guess(torch, name):
     assert eu <= TOL_PARITY and ev <= TOL_PARITY
 
 
+def test_reset_guess_matches_a_fresh_context(torch):
+    """After bido_reset_guess the next steps start a new span of states:
+    from the same state they are bit-identical to those of a fresh context
+    (stale states in the ring are never read); a context that keeps its
+    states starts from another guess and reaches other iterates."""
+    import paper_1711_08708_amd as B
+    cfg = w.slab3d(n=10)
+    kw = dict(eps_h=0.0, tol=1e-12, inner_p1=B.P1_AMG, inner_pk=B.PK_AMG)
+    runs = {}
+    for name in ("reset", "kept", "fresh"):
+        sv = B.Solver(cfg, **kw)
+        v, h, u = sv.state()
+        if name != "fresh":
+            for n in range(6):
+                sv.step(v, h, u, n)
+            st0 = [t.clone() for t in (v, h, u)]
+            if name == "reset":
+                sv.reset_guess()
+        st = [t.clone() for t in st0]
+        its = [sv.step(st[0], st[1], st[2], n)["iterations"] for n in range(6, 10)]
+        runs[name] = (its, [t.cpu().numpy() for t in st])
+        sv.close()
+    print("iterations after reset / kept / fresh", runs["reset"][0], runs["kept"][0], runs["fresh"][0], flush=True)
+    assert runs["reset"][0] == runs["fresh"][0]
+    assert all(np.array_equal(x, y) for x, y in zip(runs["reset"][1], runs["fresh"][1]))
+    assert not all(np.array_equal(x, y) for x, y in zip(runs["kept"][1], runs["fresh"][1]))
+
+
 @pytest.mark.parametrize("mk,eps,n_steps", [(lambda: w.make_config("square48"), 0.0, 20),
                                              (lambda: w.thorax2d(n_target=3000, seed=11), 1e-8, 12)],
                          ids=["square48", "thorax3000"])
