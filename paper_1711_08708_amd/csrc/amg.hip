@@ -2,8 +2,10 @@
 // P_K of the block-LU preconditioner; host side in amg.cpp, driver in
 // api.cpp).  Every product is a CSR row product by a group of G lanes with
 // RU rows in flight (the row helper of the Lambda product), with the matrix
-// values in FP64 or, in mixed precision, FP32 (FP64 accumulation, FP64
-// vectors): the cycle is bound by the bytes of its level matrices.  A
+// values in FP64 or, in mixed precision, FP32 (FP64 accumulation); the
+// level vectors are FP64 or FP32 (XV, BV, YV, VV, ZV: the input, added,
+// output, level and result vector types of a kernel): the cycle is bound
+// by the bytes of its level matrices and vectors.  A
 // matrix whose rows each span fewer than 65536 columns (a banded order)
 // holds its columns as 16-bit offsets from a per-row base (C = uint16_t,
 // 2 instead of 4 bytes per entry); C = int32_t is the plain column.
@@ -32,16 +34,14 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
-// s[u] = sum_j A[row_u, j] * f(j) for RU rows, f(j) = x[j] (or x[j] * w[j]
-// when w is given: the scaled input of a fused smoother step); entries
+// s[u] = sum_j A[row_u, j] x[j] for RU rows (FP64 accumulation); entries
 // past a row's end reread entry 0 and are dropped by a select.  Column j of
 // an entry is col[q] (C = int32_t) or cb[row] + col[q] (C = uint16_t).
-template <int G, int K, typename T, typename C>
+template <int G, int K, typename T, typename C, typename XV>
 __device__ __forceinline__ void rows_dot(const int64_t* __restrict__ ptr, const C* __restrict__ col,
                                          const int32_t* __restrict__ cb, const T* __restrict__ val,
-                                         const double* __restrict__ x, const double* __restrict__ w,
-                                         const int64_t (&row)[RU], const bool (&ok)[RU], int lane,
-                                         double (&s)[RU]) {
+                                         const XV* __restrict__ x, const int64_t (&row)[RU], const bool (&ok)[RU],
+                                         int lane, double (&s)[RU]) {
     int64_t pb[RU], pe[RU];
     int32_t c0[RU];
 #pragma unroll
@@ -61,30 +61,26 @@ __device__ __forceinline__ void rows_dot(const int64_t* __restrict__ ptr, const 
             const bool in = q < pe[u];
             const int64_t qc = in ? q : 0;
             const int32_t c = c0[u] + (int32_t)col[qc];
-            double xv = x[c];
-            if (w) xv *= w[c];
-            const double v = (double)val[qc] * xv;
+            const double v = (double)val[qc] * (double)x[c];
             s[u] += in ? v : 0.0;
         }
 #pragma unroll
     for (int u = 0; u < RU; ++u)
         for (int64_t q = pb[u] + lane + K * G; q < pe[u]; q += G) {
             const int32_t c = c0[u] + (int32_t)col[q];
-            double xv = x[c];
-            if (w) xv *= w[c];
-            s[u] += (double)val[q] * xv;
+            s[u] += (double)val[q] * (double)x[c];
         }
 #pragma unroll
     for (int u = 0; u < RU; ++u) s[u] = group_sum<G>(s[u]);
 }
 
 // y = b + sign * A x  (b may be null)
-template <int G, int K, typename T, typename C>
+template <int G, int K, typename T, typename C, typename XV, typename BV, typename YV>
 __global__ __launch_bounds__(BLOCK) void k_amg_spmv(int64_t n, const int64_t* __restrict__ ptr,
                                                     const C* __restrict__ col, const int32_t* __restrict__ cb,
                                                     const T* __restrict__ val,
-                                                    const double* __restrict__ x, const double* __restrict__ b,
-                                                    double sign, double* __restrict__ y) {
+                                                    const XV* __restrict__ x, const BV* __restrict__ b,
+                                                    double sign, YV* __restrict__ y) {
     const int lane = threadIdx.x % G;
     constexpr int GPB = BLOCK / G;     // lane groups per workgroup
     const RowRange rr = block_rows(n);
@@ -97,22 +93,23 @@ __global__ __launch_bounds__(BLOCK) void k_amg_spmv(int64_t n, const int64_t* __
             ok[u] = row[u] < rr.r1;
         }
         double s[RU];
-        rows_dot<G, K, T, C>(ptr, col, cb, val, x, nullptr, row, ok, lane, s);
+        rows_dot<G, K, T, C, XV>(ptr, col, cb, val, x, row, ok, lane, s);
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < RU; ++u)
-                if (ok[u]) y[row[u]] = (b ? b[row[u]] : 0.0) + sign * s[u];
+                if (ok[u]) y[row[u]] = (YV)((b ? (double)b[row[u]] : 0.0) + sign * s[u]);
         }
     }
 }
 
 // One Chebyshev step from zero, the damped Jacobi sweep, plus an optional
 // base: z = base + a0 D^-1 b.
-__global__ __launch_bounds__(BLOCK) void k_amg_jacobi(int64_t n, const double* __restrict__ b,
-                                                      const double* __restrict__ dinv, double a0,
-                                                      const double* __restrict__ base, double* __restrict__ z) {
+template <typename BV, typename VV, typename ZV>
+__global__ __launch_bounds__(BLOCK) void k_amg_jacobi(int64_t n, const BV* __restrict__ b,
+                                                      const VV* __restrict__ dinv, double a0,
+                                                      const VV* __restrict__ base, ZV* __restrict__ z) {
     for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
-        z[i] = (base ? base[i] : 0.0) + a0 * dinv[i] * b[i];
+        z[i] = (ZV)((base ? (double)base[i] : 0.0) + a0 * (double)dinv[i] * (double)b[i]);
 }
 
 // The first two Chebyshev smoothing steps from z = 0 in one pass:
@@ -120,14 +117,14 @@ __global__ __launch_bounds__(BLOCK) void k_amg_jacobi(int64_t n, const double* _
 // As = A D^-1 of the level matrix, so one gather per entry),
 // d1 = c1 d0 + c2 D^-1 r1, z = base + d0 + d1 (base may be null); r1, d0
 // and d1 are kept when more steps follow (write_rd).
-template <int G, int K, typename T, typename C>
+template <int G, int K, typename T, typename C, typename BV, typename VV, typename ZV>
 __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t* __restrict__ ptr,
                                                        const C* __restrict__ col, const int32_t* __restrict__ cb,
-                                                       const T* __restrict__ val, const double* __restrict__ dinv,
-                                                       const double* __restrict__ b, double a0, double c1, double c2,
-                                                       const double* __restrict__ base,
-                                                       double* __restrict__ z, double* __restrict__ r1,
-                                                       double* __restrict__ d0o, double* __restrict__ d1o,
+                                                       const T* __restrict__ val, const VV* __restrict__ dinv,
+                                                       const BV* __restrict__ b, double a0, double c1, double c2,
+                                                       const VV* __restrict__ base,
+                                                       ZV* __restrict__ z, VV* __restrict__ r1,
+                                                       VV* __restrict__ d0o, VV* __restrict__ d1o,
                                                        int write_rd) {
     const int lane = threadIdx.x % G;
     constexpr int GPB = BLOCK / G;     // lane groups per workgroup
@@ -141,11 +138,11 @@ __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t*
             row[u] = rb + u * GPB;
             ok[u] = row[u] < rr.r1;
             const int64_t i = ok[u] ? row[u] : rb;
-            bv[u] = b[i];
-            di[u] = dinv[i];
+            bv[u] = (double)b[i];
+            di[u] = (double)dinv[i];
         }
         double s[RU];
-        rows_dot<G, K, T, C>(ptr, col, cb, val, b, nullptr, row, ok, lane, s);   // (A D^-1 b)_i, val = As
+        rows_dot<G, K, T, C, BV>(ptr, col, cb, val, b, row, ok, lane, s);        // (A D^-1 b)_i, val = As
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
@@ -153,11 +150,11 @@ __global__ __launch_bounds__(BLOCK) void k_amg_smooth2(int64_t n, const int64_t*
                 const double d0 = a0 * di[u] * bv[u];
                 const double r = bv[u] - a0 * s[u];
                 const double d1 = c1 * d0 + c2 * di[u] * r;
-                z[row[u]] = (base ? base[row[u]] : 0.0) + d0 + d1;
+                z[row[u]] = (ZV)((base ? (double)base[row[u]] : 0.0) + d0 + d1);
                 if (write_rd) {
-                    r1[row[u]] = r;
-                    d0o[row[u]] = d0;
-                    d1o[row[u]] = d1;
+                    r1[row[u]] = (VV)r;
+                    d0o[row[u]] = (VV)d0;
+                    d1o[row[u]] = (VV)d1;
                 }
             }
         }
@@ -189,7 +186,7 @@ __global__ __launch_bounds__(BLOCK) void k_amg_cheb(int64_t n, const int64_t* __
             zv[u] = z[i];
         }
         double s[RU];
-        rows_dot<G, K, T, int32_t>(ptr, col, nullptr, val, dp, nullptr, row, ok, lane, s);
+        rows_dot<G, K, T, int32_t, double>(ptr, col, nullptr, val, dp, row, ok, lane, s);
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
@@ -224,15 +221,18 @@ __global__ __launch_bounds__(BLOCK) void k_amg_shift(int64_t nnz, double dg, con
     }
 }
 
-// D^-1 of every row (the excluded row keeps 0)
+// D^-1 of every row (the excluded row keeps 0), FP64 and FP32
 __global__ __launch_bounds__(BLOCK) void k_amg_dinv(int64_t n, const int64_t* __restrict__ ptr,
                                                     const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                    int64_t excluded, double* __restrict__ dinv) {
+                                                    int64_t excluded, double* __restrict__ dinv,
+                                                    float* __restrict__ dinv32) {
     for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
         double d = 0.0;
         for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q)
             if (col[q] == i) d += val[q];
-        dinv[i] = i == excluded ? 0.0 : 1.0 / d;
+        const double v = i == excluded ? 0.0 : 1.0 / d;
+        dinv[i] = v;
+        if (dinv32) dinv32[i] = (float)v;
     }
 }
 
@@ -329,8 +329,8 @@ void launch_amg_shift(hipStream_t s, int64_t nnz, double dg, const double* mass,
     if (nnz > 0) k_amg_shift<<<grid_elems(nnz), BLOCK, 0, s>>>(nnz, dg, mass, a64, a32);
 }
 void launch_amg_dinv(hipStream_t s, int64_t n, const int64_t* ptr, const int32_t* col, const double* val,
-                     int64_t excluded, double* dinv) {
-    if (n > 0) k_amg_dinv<<<grid_elems(n), BLOCK, 0, s>>>(n, ptr, col, val, excluded, dinv);
+                     int64_t excluded, double* dinv, float* dinv32) {
+    if (n > 0) k_amg_dinv<<<grid_elems(n), BLOCK, 0, s>>>(n, ptr, col, val, excluded, dinv, dinv32);
 }
 void launch_amg_colscale(hipStream_t s, int64_t nnz, const int32_t* col, const double* val, const double* dinv,
                          double* s64, float* s32) {
@@ -387,37 +387,36 @@ int unroll_for(const AmgMat<T>& A) {
     return (int)std::min<int64_t>(4, std::max<int64_t>(2, k));
 }
 
-template <typename T>
-void launch_amg_spmv(hipStream_t s, const AmgMat<T>& A, const double* x, const double* b, double sign, double* y) {
+template <typename T, typename XV, typename BV, typename YV>
+void launch_amg_spmv(hipStream_t s, const AmgMat<T>& A, const XV* x, const BV* b, double sign, YV* y) {
     if (A.n <= 0) return;
     if (A.c16)
-        BIDO_G_SWITCH(A, k_amg_spmv<GG, KK, T, uint16_t><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
+        BIDO_G_SWITCH(A, k_amg_spmv<GG, KK, T, uint16_t, XV, BV, YV><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
                              A.n, A.ptr, A.c16, A.cb, A.val, x, b, sign, y))
     else
-        BIDO_G_SWITCH(A, k_amg_spmv<GG, KK, T, int32_t><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
+        BIDO_G_SWITCH(A, k_amg_spmv<GG, KK, T, int32_t, XV, BV, YV><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
                              A.n, A.ptr, A.col, nullptr, A.val, x, b, sign, y))
 }
 
-template <typename T>
-void launch_amg_smooth2(hipStream_t s, const AmgMat<T>& A, const double* dinv, const double* b, double a0, double c1,
-                        double c2, const double* base, double* z, double* r1, double* d0, double* d1,
-                        bool write_rd) {
+template <typename T, typename BV, typename VV, typename ZV>
+void launch_amg_smooth2(hipStream_t s, const AmgMat<T>& A, const VV* dinv, const BV* b, double a0, double c1,
+                        double c2, const VV* base, ZV* z, VV* r1, VV* d0, VV* d1, bool write_rd) {
     if (A.n <= 0) return;
     if (A.c16)
-        BIDO_G_SWITCH(A, k_amg_smooth2<GG, KK, T, uint16_t><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
+        BIDO_G_SWITCH(A, k_amg_smooth2<GG, KK, T, uint16_t, BV, VV, ZV><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
                              A.n, A.ptr, A.c16, A.cb, A.val, dinv, b, a0, c1, c2, base, z, r1, d0, d1,
                              write_rd ? 1 : 0))
     else
-        BIDO_G_SWITCH(A, k_amg_smooth2<GG, KK, T, int32_t><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
+        BIDO_G_SWITCH(A, k_amg_smooth2<GG, KK, T, int32_t, BV, VV, ZV><<<grid_rows(A.n, GG), BLOCK, 0, s>>>(
                              A.n, A.ptr, A.col, nullptr, A.val, dinv, b, a0, c1, c2, base, z, r1, d0, d1,
                              write_rd ? 1 : 0))
 }
 
-void launch_amg_jacobi(hipStream_t s, int64_t n, const double* b, const double* dinv, double a0, const double* base,
-                       double* z) {
+template <typename BV, typename VV, typename ZV>
+void launch_amg_jacobi(hipStream_t s, int64_t n, const BV* b, const VV* dinv, double a0, const VV* base, ZV* z) {
     if (n <= 0) return;
     const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + BLOCK - 1) / BLOCK, 4096));
-    k_amg_jacobi<<<g, BLOCK, 0, s>>>(n, b, dinv, a0, base, z);
+    k_amg_jacobi<BV, VV, ZV><<<g, BLOCK, 0, s>>>(n, b, dinv, a0, base, z);
 }
 
 template <typename T>
@@ -431,14 +430,35 @@ void launch_amg_cheb(hipStream_t s, const AmgMat<T>& A, const double* dinv, doub
 #undef BIDO_G_SWITCH
 #undef BIDO_K_SWITCH
 
-#define BIDO_INST(T)                                                                                              \
-    template void launch_amg_spmv<T>(hipStream_t, const AmgMat<T>&, const double*, const double*, double, double*); \
-    template void launch_amg_smooth2<T>(hipStream_t, const AmgMat<T>&, const double*, const double*, double,       \
-                                        double, double, const double*, double*, double*, double*, double*, bool);  \
-    template void launch_amg_cheb<T>(hipStream_t, const AmgMat<T>&, const double*, double*, const double*,         \
+// the vector types in use: FP64 throughout (FP64 cycles, the coupling
+// blocks), and in the mixed-precision cycle FP32 level vectors with the
+// finest level's FP64 input and output
+#define BIDO_SPMV(T, XV, BV, YV) \
+    template void launch_amg_spmv<T, XV, BV, YV>(hipStream_t, const AmgMat<T>&, const XV*, const BV*, double, YV*);
+#define BIDO_SM(T, BV, VV, ZV)                                                                                    \
+    template void launch_amg_smooth2<T, BV, VV, ZV>(hipStream_t, const AmgMat<T>&, const VV*, const BV*, double,  \
+                                                    double, double, const VV*, ZV*, VV*, VV*, VV*, bool);
+#define BIDO_JAC(BV, VV, ZV) \
+    template void launch_amg_jacobi<BV, VV, ZV>(hipStream_t, int64_t, const BV*, const VV*, double, const VV*, ZV*);
+BIDO_SPMV(double, double, double, double)
+BIDO_SPMV(float, double, double, double)
+BIDO_SPMV(float, float, double, float)
+BIDO_SPMV(float, float, float, float)
+BIDO_SM(double, double, double, double)
+BIDO_SM(float, double, double, double)
+BIDO_SM(float, double, float, float)
+BIDO_SM(float, float, float, double)
+BIDO_SM(float, float, float, float)
+BIDO_JAC(double, double, double)
+BIDO_JAC(double, float, float)
+BIDO_JAC(float, float, double)
+BIDO_JAC(float, float, float)
+template void launch_amg_cheb<double>(hipStream_t, const AmgMat<double>&, const double*, double*, const double*,
+                                      double*, double*, double, double);
+template void launch_amg_cheb<float>(hipStream_t, const AmgMat<float>&, const double*, double*, const double*,
                                      double*, double*, double, double);
-BIDO_INST(double)
-BIDO_INST(float)
-#undef BIDO_INST
+#undef BIDO_SPMV
+#undef BIDO_SM
+#undef BIDO_JAC
 
 }  // namespace bido

@@ -19,6 +19,7 @@
 #include <memory>
 #include <random>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/bido.h"
@@ -315,6 +316,9 @@ struct AmgDev {
         ChebCoef cf;
         double *b = nullptr, *out = nullptr;   // input and output of this level (levels >= 1)
         double *x = nullptr, *r = nullptr, *d0 = nullptr, *d1 = nullptr, *xp = nullptr;
+        // FP32 copies of D^-1 and of the level vectors (the mixed-precision cycle)
+        float *dinv32 = nullptr, *b32 = nullptr, *out32 = nullptr, *x32 = nullptr, *r32 = nullptr,
+              *xp32 = nullptr;
         int64_t nnz_A = 0, nnz_P = 0, nnz_R = 0;
         template <typename T>
         AmgMat<T> mat(const CsrDev& m, const float* v32, int g) const {
@@ -340,19 +344,29 @@ struct AmgDev {
     int lanczos_steps = 20;
     double smooth_ratio = 10.0;
     bool refreshable() const { return !lv.empty() && lv[0].mass; }
+    // the mixed-precision cycle keeps FP32 level vectors when no level
+    // smooths with more than two Chebyshev steps
+    bool fp32_vectors() const {
+        for (const Lev& L : lv)
+            if (L.steps > 2) return false;
+        return true;
+    }
     double op_complexity = 1.0, setup_seconds = 0.0;
     bool on() const { return !lv.empty(); }
     // algorithmic bytes of one V-cycle with value bytes w (8 or 4)
+    // (level vectors of vb bytes: FP32 in the mixed-precision cycle; the
+    // finest level's input and output counted at that width too)
     double bytes(int w) const {
-        double b = 8.0 * (double)nc * nc + 16.0 * nc;
+        const double vb = (w == 4 && fp32_vectors()) ? 4.0 : 8.0;
+        double b = 8.0 * (double)nc * nc + 2.0 * vb * nc;
         for (size_t l = 0; l + 1 < lv.size(); ++l) {
             const Lev& L = lv[l];
             auto mb = [&](const CsrDev& m, int64_t nnz, int64_t rows) {
                 return (m.col_bytes() + w) * nnz + m.row_bytes() * rows + 8.0;
             };
-            const double A = mb(L.A, L.nnz_A, L.n), vec = 8.0 * L.n;
+            const double A = mb(L.A, L.nnz_A, L.n), vec = vb * L.n;
             const double A32 = (4.0 + w) * L.nnz_A + 8.0 * (L.n + 1);
-            const double nc_l = 8.0 * lv[l + 1].n;
+            const double nc_l = vb * lv[l + 1].n;
             // two smoothings (one step: b and D^-1 read, z written; the fused first two
             // steps read A D^-1, b and D^-1 and write z, plus r1, d0 and d1 when more
             // steps follow; each further step A + 7 vectors; the post-smoothing also
@@ -371,7 +385,7 @@ struct AmgDev {
             for (CsrDev* m : {&L.A, &L.P, &L.R}) {
                 hipFree(m->ptr); hipFree(m->col); hipFree(m->val); hipFree(m->c16); hipFree(m->cb);
             }
-            for (float* v : {L.A32, L.P32, L.R32, L.As32}) hipFree(v);
+            for (float* v : {L.A32, L.P32, L.R32, L.As32, L.dinv32, L.b32, L.out32, L.x32, L.r32, L.xp32}) hipFree(v);
             for (double* v : {L.dinv, L.b, L.out, L.x, L.r, L.d0, L.d1, L.xp, L.As64, L.mass}) hipFree(v);
         }
         lv.clear();
@@ -414,6 +428,8 @@ bido_status upload_amg(const Amg& M, AmgDev& d, bool compact) {
         if (l > 0) {
             HIP_OK(hipMalloc((void**)&v.b, n * sizeof(double)));
             HIP_OK(hipMalloc((void**)&v.out, n * sizeof(double)));
+            HIP_OK(hipMalloc((void**)&v.b32, n * sizeof(float)));
+            HIP_OK(hipMalloc((void**)&v.out32, n * sizeof(float)));
         }
         bido_status e;
         if (last) {
@@ -452,12 +468,17 @@ bido_status upload_amg(const Amg& M, AmgDev& d, bool compact) {
         v.nnz_P = h.P.nnz();
         v.nnz_R = h.R.nnz();
         HIP_OK(upload(&v.dinv, h.dinv.data(), h.dinv.size()));
+        {
+            std::vector<float> d32(h.dinv.begin(), h.dinv.end());
+            HIP_OK(upload(&v.dinv32, d32.data(), d32.size()));
+        }
         v.steps = h.steps;
         v.lo = h.lo;
         v.hi = h.hi;
         v.cf = chebyshev_coefficients(h.lo, h.hi, std::max(2, h.steps));
         if (refresh) HIP_OK(upload(&v.mass, M.mass[l].data(), std::max<size_t>(M.mass[l].size(), 1)));
         for (double** b : {&v.x, &v.r, &v.d0, &v.d1, &v.xp}) HIP_OK(hipMalloc((void**)b, n * sizeof(double)));
+        for (float** b : {&v.x32, &v.r32, &v.xp32}) HIP_OK(hipMalloc((void**)b, n * sizeof(float)));
     }
     d.nc = M.levels.back().A.n;
     HIP_OK(upload(&d.cinv, M.coarse_inv.data(), M.coarse_inv.size()));
@@ -767,49 +788,71 @@ void inner_solve(C* c, const FactorDev& f, const double* in, double* out) {
         tri_solve<double>(c, f, f.panel64, f.panel64_cm, in, out);
 }
 
-// Z2 = P_K^-1 t: the factor of K_m, or `cheb_steps` steps of the Chebyshev
-// acceleration of the Jacobi iteration on K_m (always FP64; z_0 = 0).
+// The level vectors of a cycle in type V: FP64 ones, or the FP32 copies
+// of the mixed-precision cycle.
+template <typename V>
+struct LevVecs {
+    V *b, *out, *x, *r, *xp, *d0, *d1;
+    const V* dinv;
+};
+inline LevVecs<double> lev_vecs(const AmgDev::Lev& L, double*) { return {L.b, L.out, L.x, L.r, L.xp, L.d0, L.d1, L.dinv}; }
+inline LevVecs<float> lev_vecs(const AmgDev::Lev& L, float*) {
+    return {L.b32, L.out32, L.x32, L.r32, L.xp32, nullptr, nullptr, L.dinv32};
+}
+
 // z = S b for level L of a multigrid hierarchy: the Chebyshev steps of the
 // smoother from z = 0 (the recurrence of the Chebyshev P_K on the level's
-// interval of D^-1 A; the first two steps in one fused pass).
-template <typename T, typename C>
-void amg_smooth(C* c, const AmgDev& M, const AmgDev::Lev& L, const double* b, double* z, int cls,
-                const double* base = nullptr) {
+// interval of D^-1 A; the first two steps in one fused pass).  V: the level
+// vectors; BT, ZT: the input and output (FP64 on the finest level).  More
+// than two steps run on FP64 level vectors only.
+template <typename T, typename V, typename BT, typename ZT, typename C>
+void amg_smooth(C* c, const AmgDev& M, const AmgDev::Lev& L, const BT* b, ZT* z, int cls,
+                const V* base = nullptr) {
     hipStream_t s = c->stream;
     const int64_t n = L.n;
+    const LevVecs<V> lv = lev_vecs(L, (V*)nullptr);
     const AmgMat<T> A = L.mat<T>(L.A, L.A32, L.gA);
     AmgMat<T> As = A;                      // the column-scaled copy A D^-1
     if constexpr (sizeof(T) == 4) As.val = L.As32;
     else As.val = L.As64;
     const double Ab = (L.A.col_bytes() + sizeof(T)) * L.nnz_A + L.A.row_bytes() * n + 8.0;
     const double Ab32 = (4.0 + sizeof(T)) * L.nnz_A + 8.0 * (n + 1);   // the further steps read col
-    const double bb = base ? 8.0 * n : 0.0;
+    // b and D^-1 read, z written, and the base added
+    const double vb = (sizeof(BT) + sizeof(V) + sizeof(ZT)) * (double)n + (base ? sizeof(V) * (double)n : 0.0);
     if (L.steps < 2) {
-        PROF(c, cls, 24.0 * n + bb, launch_amg_jacobi(s, n, b, L.dinv, L.cf.inv_theta, base, z));
+        PROF(c, cls, vb, (launch_amg_jacobi<BT, V, ZT>(s, n, b, lv.dinv, L.cf.inv_theta, base, z)));
         return;
     }
-    PROF(c, cls, Ab + 8.0 * n * (L.steps > 2 ? 6 : 3) + bb,
-         launch_amg_smooth2<T>(s, As, L.dinv, b, L.cf.inv_theta, L.cf.c1[0], L.cf.c2[0], base, z, L.r, L.d0,
-                               L.d1, L.steps > 2));
-    double* d[2] = {L.d0, L.d1};
-    for (int k = 2; k < L.steps; ++k)
-        PROF(c, cls, Ab32 + 56.0 * n,
-             launch_amg_cheb<T>(s, A, L.dinv, L.r, d[(k - 1) & 1], d[k & 1], z, L.cf.c1[k - 1], L.cf.c2[k - 1]));
+    const bool more = L.steps > 2;
+    PROF(c, cls, Ab + vb + (more ? 3.0 * sizeof(V) * n : 0.0),
+         (launch_amg_smooth2<T, BT, V, ZT>(s, As, lv.dinv, b, L.cf.inv_theta, L.cf.c1[0], L.cf.c2[0], base, z,
+                                           lv.r, lv.d0, lv.d1, more)));
+    if constexpr (std::is_same<V, double>::value && std::is_same<ZT, double>::value) {
+        double* d[2] = {L.d0, L.d1};
+        for (int k = 2; k < L.steps; ++k)
+            PROF(c, cls, Ab32 + 56.0 * n,
+                 launch_amg_cheb<T>(s, A, L.dinv, L.r, d[(k - 1) & 1], d[k & 1], z, L.cf.c1[k - 1], L.cf.c2[k - 1]));
+    }
 }
 
 // out = B b: the symmetric V-cycle from level l (pre-smoothing, residual,
 // restriction, the coarser cycle, prolongation, residual, post-smoothing;
-// the coarsest level by its dense inverse).
-template <typename T, typename C>
-void amg_vcycle_t(C* c, const AmgDev& M, size_t l, const double* b, double* out) {
+// the coarsest level by its dense inverse).  V: the level vectors; BT, OT:
+// the cycle's input and output (FP64 on the finest level, V below).
+template <typename T, typename V, typename BT, typename OT, typename C>
+void amg_vcycle_t(C* c, const AmgDev& M, size_t l, const BT* b, OT* out) {
     hipStream_t s = c->stream;
     const AmgDev::Lev& L = M.lv[l];
     if (l + 1 == M.lv.size()) {
-        PROF(c, K_AMG_COARSE, 8.0 * (double)M.nc * M.nc + 16.0 * M.nc, launch_dense_gemv(s, M.nc, M.cinv, b, out));
+        if constexpr (std::is_same<BT, OT>::value)
+            PROF(c, K_AMG_COARSE, 8.0 * (double)M.nc * M.nc + 2.0 * sizeof(BT) * M.nc,
+                 launch_dense_gemv<BT>(s, M.nc, M.cinv, b, out));
         return;
     }
     const AmgDev::Lev& Lc = M.lv[l + 1];
-    const double vec = 8.0 * L.n, w = sizeof(T);
+    const LevVecs<V> lv = lev_vecs(L, (V*)nullptr), lc = lev_vecs(Lc, (V*)nullptr);
+    const double vec = (double)sizeof(V) * L.n, bvec = (double)sizeof(BT) * L.n, w = sizeof(T);
+    const double cvec = (double)sizeof(V) * Lc.n;
     const AmgMat<T> A = L.mat<T>(L.A, L.A32, L.gA);
     const AmgMat<T> P = L.mat<T>(L.P, L.P32, L.gP);
     const AmgMat<T> R = L.mat<T>(L.R, L.R32, L.gR);
@@ -822,20 +865,26 @@ void amg_vcycle_t(C* c, const AmgDev& M, size_t l, const double* b, double* out)
     const bool fine = l == 0;
     const int c_sm = fine ? K_AMG_SMOOTH : K_AMG_COARSE, c_re = fine ? K_AMG_SPMV : K_AMG_COARSE,
               c_tr = fine ? K_AMG_TRANSFER : K_AMG_COARSE;
-    amg_smooth<T>(c, M, L, b, L.x, c_sm);
-    PROF(c, c_re, Ab + 3 * vec, launch_amg_spmv<T>(s, A, L.x, b, -1.0, L.r));                // r = b - A x
-    PROF(c, c_tr, Rb + vec + 8.0 * Lc.n, launch_amg_spmv<T>(s, R, L.r, nullptr, 1.0, Lc.b));
-    amg_vcycle_t<T>(c, M, l + 1, Lc.b, Lc.out);
-    PROF(c, c_tr, Pb + 8.0 * Lc.n + 2 * vec, launch_amg_spmv<T>(s, P, Lc.out, L.x, 1.0, L.xp));  // xp = x + P e
-    PROF(c, c_re, Ab + 3 * vec, launch_amg_spmv<T>(s, A, L.xp, b, -1.0, L.r));               // r = b - A xp
-    amg_smooth<T>(c, M, L, L.r, out, c_sm, L.xp);                                            // out = xp + S r
+    amg_smooth<T, V, BT, V>(c, M, L, b, lv.x, c_sm);
+    PROF(c, c_re, Ab + 2 * vec + bvec, (launch_amg_spmv<T, V, BT, V>(s, A, lv.x, b, -1.0, lv.r)));  // r = b - A x
+    PROF(c, c_tr, Rb + vec + cvec, (launch_amg_spmv<T, V, V, V>(s, R, lv.r, (const V*)nullptr, 1.0, lc.b)));
+    amg_vcycle_t<T, V, V, V>(c, M, l + 1, (const V*)lc.b, lc.out);
+    PROF(c, c_tr, Pb + cvec + 2 * vec, (launch_amg_spmv<T, V, V, V>(s, P, lc.out, lv.x, 1.0, lv.xp)));  // xp = x + P e
+    PROF(c, c_re, Ab + 2 * vec + bvec, (launch_amg_spmv<T, V, BT, V>(s, A, lv.xp, b, -1.0, lv.r)));  // r = b - A xp
+    amg_smooth<T, V, V, OT>(c, M, L, (const V*)lv.r, out, c_sm, (const V*)lv.xp);                // out = xp + S r
 }
 
-// The cycle with FP32 level values in mixed precision, FP64 otherwise.
+// The cycle with FP32 level values and vectors in mixed precision (FP64
+// level vectors when a level smooths with more than two steps), FP64
+// otherwise; the input and output stay FP64.
 template <typename C>
 void amg_vcycle(C* c, const AmgDev& M, size_t l, const double* b, double* out, bool fp64 = false) {
-    if (c->precision == BIDO_PREC_MIXED && !fp64) amg_vcycle_t<float>(c, M, l, b, out);
-    else amg_vcycle_t<double>(c, M, l, b, out);
+    if (c->precision == BIDO_PREC_MIXED && !fp64) {
+        if (M.fp32_vectors()) amg_vcycle_t<float, float, double, double>(c, M, l, b, out);
+        else amg_vcycle_t<float, double, double, double>(c, M, l, b, out);
+    } else {
+        amg_vcycle_t<double, double, double, double>(c, M, l, b, out);
+    }
 }
 
 // Z1 = P_1^-1 r1: the factor's sweeps, or the multigrid V-cycle.
@@ -845,6 +894,9 @@ void p1_solve(C* c, const double* in, double* out) {
     else inner_solve(c, c->p1, in, out);
 }
 
+// Z2 = P_K^-1 t: the factor of K_m, the multigrid V-cycle, or `cheb_steps`
+// steps of the Chebyshev acceleration of the Jacobi iteration on K_m
+// (always FP64; z_0 = 0).
 void pk_solve(bido_ctx* c, const double* in, double* out, double* ch_r, double* ch_d0, double* ch_d1);
 void pk_solve(bido_ctx* c, const double* in, double* out) {
     pk_solve(c, in, out, c->ch_r, c->ch_d[0], c->ch_d[1]);
@@ -2776,7 +2828,7 @@ static bido_status device_lambda_max(bido_ctx* c, const AmgDev& M, AmgDev::Lev& 
     const int steps = (int)std::min<int64_t>(M.lanczos_steps, n);
     for (int j = 0; j < steps; ++j) {
         launch_lz_in(s, n, L.dinv, v, t);
-        launch_amg_spmv<double>(s, A, t, nullptr, 1.0, y);
+        launch_amg_spmv<double>(s, A, t, (const double*)nullptr, 1.0, y);
         launch_lz_w(s, n, L.dinv, y, beta, vp, w);
         double a = 0.0, b = 0.0;
         if (bido_status e = device_dot(c, n, w, v, &a)) return e;
@@ -2812,7 +2864,7 @@ static bido_status amg_refresh_device(bido_ctx* c, AmgDev& M, double gamma) {
             launch_amg_dense_inverse(s, L.n, L.A.ptr, L.A.col, L.A.val, excl, M.cinv, L.x);
             break;
         }
-        launch_amg_dinv(s, L.n, L.A.ptr, L.A.col, L.A.val, excl, L.dinv);
+        launch_amg_dinv(s, L.n, L.A.ptr, L.A.col, L.A.val, excl, L.dinv, L.dinv32);
         launch_amg_colscale(s, L.nnz_A, L.A.col, L.A.val, L.dinv, L.As64, L.As32);
         double lmax = 1.0;
         if (bido_status e = device_lambda_max(c, M, L, &lmax)) return e;

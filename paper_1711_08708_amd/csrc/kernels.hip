@@ -90,16 +90,17 @@ __global__ void k_add2(int64_t n, const double* __restrict__ a, const double* __
 
 // y = A x for a dense n x n row-major A: one wave per row, the lanes stride
 // the row (coalesced), a wave reduction.
+template <typename V>
 __global__ __launch_bounds__(BLOCK) void k_dense_gemv(int64_t n, const double* __restrict__ A,
-                                                      const double* __restrict__ x, double* __restrict__ y) {
+                                                      const V* __restrict__ x, V* __restrict__ y) {
     const int lane = threadIdx.x % WAVE;
     const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
     for (int64_t r = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) / WAVE; r < n; r += nw) {
         const double* a = A + r * n;
         double s = 0.0;
-        for (int64_t j = lane; j < n; j += WAVE) s += a[j] * x[j];
+        for (int64_t j = lane; j < n; j += WAVE) s += a[j] * (double)x[j];
         s = wave_sum(s);
-        if (lane == 0) y[r] = s;
+        if (lane == 0) y[r] = (V)s;
     }
 }
 
@@ -1408,11 +1409,14 @@ void launch_add2(hipStream_t s, int64_t n, const double* a, const double* b, dou
     if (n <= 0) return;
     k_add2<<<grid_for(n), BLOCK, 0, s>>>(n, a, b, out);
 }
-void launch_dense_gemv(hipStream_t s, int64_t n, const double* A, const double* x, double* y) {
+template <typename V>
+void launch_dense_gemv(hipStream_t s, int64_t n, const double* A, const V* x, V* y) {
     if (n <= 0) return;
     const unsigned g = (unsigned)std::min<int64_t>((n + BLOCK / WAVE - 1) / (BLOCK / WAVE), 65535);
-    k_dense_gemv<<<g, BLOCK, 0, s>>>(n, A, x, y);
+    k_dense_gemv<V><<<g, BLOCK, 0, s>>>(n, A, x, y);
 }
+template void launch_dense_gemv<double>(hipStream_t, int64_t, const double*, const double*, double*);
+template void launch_dense_gemv<float>(hipStream_t, int64_t, const double*, const float*, float*);
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
     if (n <= 0) return;
     k_axpy<<<grid_for(n), BLOCK, 0, s>>>(n, a, x, y);

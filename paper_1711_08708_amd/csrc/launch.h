@@ -129,21 +129,20 @@ struct AmgMat {
     const uint16_t* c16 = nullptr;   // compact columns (CsrDev), read instead of col when set
     const int32_t* cb = nullptr;
 };
-// y = b + sign A x (b may be null)
-template <typename T>
-void launch_amg_spmv(hipStream_t s, const AmgMat<T>& A, const double* x, const double* b, double sign, double* y);
+// y = b + sign A x (b may be null); vector types as instantiated in amg.hip
+template <typename T, typename XV, typename BV, typename YV>
+void launch_amg_spmv(hipStream_t s, const AmgMat<T>& A, const XV* x, const BV* b, double sign, YV* y);
 // the first two Chebyshev smoothing steps from z = 0 in one pass (see amg.hip)
-template <typename T>
-void launch_amg_smooth2(hipStream_t s, const AmgMat<T>& A, const double* dinv, const double* b, double a0, double c1,
-                        double c2, const double* base, double* z, double* r1, double* d0, double* d1,
-                        bool write_rd);
+template <typename T, typename BV, typename VV, typename ZV>
+void launch_amg_smooth2(hipStream_t s, const AmgMat<T>& A, const VV* dinv, const BV* b, double a0, double c1,
+                        double c2, const VV* base, ZV* z, VV* r1, VV* d0, VV* d1, bool write_rd);
 // A new gamma for a multigrid level (see amg.hip): A += dg M (FP64 and FP32
 // copies), D^-1 (0 on the excluded row, < 0: none), A D^-1, the Lanczos
 // steps of the smoother bound, and the dense inverse of the coarsest level
 // (m: n x n output, f: n scratch; Gauss-Jordan, one pivot per launch)
 void launch_amg_shift(hipStream_t s, int64_t nnz, double dg, const double* mass, double* a64, float* a32);
 void launch_amg_dinv(hipStream_t s, int64_t n, const int64_t* ptr, const int32_t* col, const double* val,
-                     int64_t excluded, double* dinv);
+                     int64_t excluded, double* dinv, float* dinv32);
 void launch_amg_colscale(hipStream_t s, int64_t nnz, const int32_t* col, const double* val, const double* dinv,
                          double* s64, float* s32);
 void launch_lz_in(hipStream_t s, int64_t n, const double* dinv, const double* v, double* t);
@@ -153,8 +152,8 @@ void launch_lz_next(hipStream_t s, int64_t n, const double* w, double inv_b, dou
 void launch_amg_dense_inverse(hipStream_t s, int64_t n, const int64_t* ptr, const int32_t* col, const double* val,
                               int64_t excluded, double* m, double* f);
 // z = base + a0 D^-1 b (base may be null): one Chebyshev step from zero
-void launch_amg_jacobi(hipStream_t s, int64_t n, const double* b, const double* dinv, double a0, const double* base,
-                       double* z);
+template <typename BV, typename VV, typename ZV>
+void launch_amg_jacobi(hipStream_t s, int64_t n, const BV* b, const VV* dinv, double a0, const VV* base, ZV* z);
 // one further Chebyshev step: r -= A dp, dn = c1 dp + c2 D^-1 r, z += dn
 template <typename T>
 void launch_amg_cheb(hipStream_t s, const AmgMat<T>& A, const double* dinv, double* r, const double* dp, double* dn,
@@ -165,7 +164,8 @@ void launch_seg_stop(hipStream_t s, int S, const SegTable& T, const double* part
                      const double* yy, const double* tol, const int* max_it, uint8_t* done, int* iters, int* status,
                      double* rel);
 // y = A x, A dense n x n row-major (the coarsest level of a multigrid V-cycle)
-void launch_dense_gemv(hipStream_t s, int64_t n, const double* A, const double* x, double* y);
+template <typename V>
+void launch_dense_gemv(hipStream_t s, int64_t n, const double* A, const V* x, V* y);
 void launch_scatter_in(hipStream_t s, int64_t n, const int64_t* pos, const double* src, double* dst);
 void launch_scatter_in_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst);
 void launch_gather_f(hipStream_t s, int64_t n, const int64_t* pos, const float* src, float* dst);
