@@ -133,7 +133,8 @@ typedef struct {
  * paper's choice).  AMG: a symmetric V-cycle of smoothed-aggregation
  * algebraic multigrid (Chebyshev smoothing, dense coarsest solve), set up
  * without any factorisation (linear in the non-zeros), with FP32 level
- * values in mixed precision; its block takes the reverse Cuthill-McKee
+ * values and vectors in mixed precision (FP64 accumulation, input and
+ * output); its block takes the reverse Cuthill-McKee
  * order instead of nested dissection (one order for u and v when the heart
  * is the whole mesh).  CHEBYSHEV (P_K only): Chebyshev-accelerated Jacobi steps on
  * K_m (see bido_set_pk).  A block that is not CHOLESKY is never factored,

@@ -39,12 +39,18 @@ def _errs(U, V, Uo, Vo):
             np.linalg.norm(V - Vo) / max(np.linalg.norm(Vo), 1e-300))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_device_vcycle_matches_host_cycle(torch, name):
+def test_device_vcycle_matches_host_cycle(torch, name, precision):
+    """One device V-cycle against the host cycle of the same hierarchy: to
+    1e-12 in FP64; in mixed precision (FP32 level values and level vectors,
+    FP64 input, output and accumulation) to 1e-5."""
     import paper_1711_08708_amd as B
     cfg = CASES[name]()
     hs = B.HostSetup(cfg, eps_h=0.0, inner_p1=B.P1_AMG, inner_pk=B.PK_AMG)
-    solver = B.Solver(cfg, eps_h=0.0, inner_p1=B.P1_AMG, inner_pk=B.PK_AMG)
+    solver = B.Solver(cfg, eps_h=0.0, inner_p1=B.P1_AMG, inner_pk=B.PK_AMG,
+                      precision=B.PREC_MIXED if precision == "mixed" else B.PREC_FP64)
+    tol = 1e-5 if precision == "mixed" else 1e-12
     for which in (0, 1):
         n = solver.N if which == 0 else solver.NH
         b = np.random.default_rng(3 + which).normal(size=n)
@@ -53,8 +59,8 @@ def test_device_vcycle_matches_host_cycle(torch, name):
         solver.inner_solve(which, torch.tensor(b, device="cuda"), xd)
         x = xd.cpu().numpy()
         err = np.abs(x - ref).max() / np.abs(ref).max()
-        print(f"{name} block {which}: {hs.amg_info(which)} max rel diff {err:.2e}", flush=True)
-        assert np.isfinite(x).all() and err < 1e-12
+        print(f"{name} {precision} block {which}: {hs.amg_info(which)} max rel diff {err:.2e}", flush=True)
+        assert np.isfinite(x).all() and err < tol
         if which == 0:
             g = solver.info["ground_index"]
             assert x[g] == 0.0             # the grounded vertex, the one nearest the centroid
