@@ -181,10 +181,16 @@ __global__ void k_dot_reduce(int64_t n, const double* __restrict__ a, const doub
 // (W^T Lambda W) c = W^T Y.  The Gram matrix G is kept by ring slot and gets
 // one new row per step; everything stays on the device.
 // ---------------------------------------------------------------------------
-// out[k] = W_k . y for k < W.m (out[k] = 0 beyond), last-block reduction
+// out[k] = W_k . y for k < W.m (out[k] = 0 beyond).  The m sums of a block
+// are reduced wave by wave with shuffles and combined after one barrier;
+// the last block to finish (a counter) sums the blocks' partials, one wave
+// per sum (the counter is reset for the next call).
 __global__ void k_multidot(int64_t n, GuessList W, const double* __restrict__ y, double* partials,
                            unsigned* counter, double* out) {
-    __shared__ double sh[BLOCK / WAVE];
+    constexpr int NW = BLOCK / WAVE;
+    __shared__ double sh[GUESS_MAX][NW];
+    __shared__ bool last;
+    const int m = W.m, lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
     double part[GUESS_MAX];
 #pragma unroll
     for (int k = 0; k < GUESS_MAX; ++k) part[k] = 0.0;
@@ -192,11 +198,35 @@ __global__ void k_multidot(int64_t n, GuessList W, const double* __restrict__ y,
         const double yi = y[i];
 #pragma unroll
         for (int k = 0; k < GUESS_MAX; ++k)
-            if (k < W.m) part[k] += W.v[k][i] * yi;
+            if (k < m) part[k] += W.v[k][i] * yi;
     }
 #pragma unroll
-    for (int k = 0; k < GUESS_MAX; ++k) part[k] = block_sum(part[k], sh);
-    finish_reduce<GUESS_MAX>(part, partials, counter, out, sh);
+    for (int k = 0; k < GUESS_MAX; ++k)
+        if (k < m) {
+            const double v = wave_sum(part[k]);
+            if (lane == 0) sh[k][wv] = v;
+        }
+    __syncthreads();
+    if ((int)threadIdx.x < m) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += sh[threadIdx.x][w];
+        partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int k = wv; k < GUESS_MAX; k += NW) {
+        double s = 0.0;
+        if (k < m)
+            for (unsigned b = lane; b < gridDim.x; b += WAVE) s += partials[(size_t)k * gridDim.x + b];
+        s = wave_sum(s);
+        if (lane == 0) out[k] = k < m ? s : 0.0;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
 }
 
 // One thread: the new Gram row (d[k] = W_k . Lambda W_0, W_0 the newest, at
