@@ -229,51 +229,60 @@ __global__ void k_multidot(int64_t n, GuessList W, const double* __restrict__ y,
     if (threadIdx.x == 0) *counter = 0u;
 }
 
-// One thread: the new Gram row (d[k] = W_k . Lambda W_0, W_0 the newest, at
-// ring slot W.slot[0]) into G (ld GUESS_MAX, by slot), then, when b is
+// One workgroup: the new Gram row (d[k] = W_k . Lambda W_0, W_0 the newest,
+// at ring slot W.slot[0]) into G (ld GUESS_MAX, by slot), then, when b is
 // given, c from (G_W + delta I) c = b by Cholesky, delta = 1e-13 times the
 // largest diagonal entry (the states are close to dependent); a failed
-// factorisation keeps x0 = W_0 (c = e_0).
+// factorisation keeps x0 = W_0 (c = e_0).  The threads stage G_W in LDS;
+// one thread factors and solves there.
 __global__ void k_guess_solve(GuessList W, const double* __restrict__ d, double* G, const double* __restrict__ b,
                               double* __restrict__ c) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int m = W.m;
-    if (d)
-        for (int k = 0; k < m; ++k) {
-            G[W.slot[0] * GUESS_MAX + W.slot[k]] = d[k];
-            G[W.slot[k] * GUESS_MAX + W.slot[0]] = d[k];
-        }
+    __shared__ double L[GUESS_MAX][GUESS_MAX];
+    __shared__ double z[GUESS_MAX];
+    const int m = W.m, t = threadIdx.x;
+    if (d && t < m) {
+        G[W.slot[0] * GUESS_MAX + W.slot[t]] = d[t];
+        G[W.slot[t] * GUESS_MAX + W.slot[0]] = d[t];
+    }
     if (!b) return;
-    double L[GUESS_MAX * GUESS_MAX], z[GUESS_MAX];
+    __syncthreads();
+    for (int e = t; e < m * m; e += blockDim.x) {
+        const int i = e / m, k = e - i * m;
+        L[i][k] = G[W.slot[i] * GUESS_MAX + W.slot[k]];
+    }
+    if (t < m) z[t] = b[t];
+    __syncthreads();
+    if (t != 0) return;
     double dmax = 0.0;
-    for (int k = 0; k < m; ++k) dmax = fmax(dmax, G[W.slot[k] * GUESS_MAX + W.slot[k]]);
+    for (int k = 0; k < m; ++k) dmax = fmax(dmax, L[k][k]);
     const double delta = 1e-13 * dmax;
     bool ok = dmax > 0.0;
-    for (int i = 0; i < m && ok; ++i)
+    for (int i = 0; i < m && ok; ++i)                 // lower triangle in place
         for (int j = 0; j <= i; ++j) {
-            double s = G[W.slot[i] * GUESS_MAX + W.slot[j]] + (i == j ? delta : 0.0);
-            for (int k = 0; k < j; ++k) s -= L[i * GUESS_MAX + k] * L[j * GUESS_MAX + k];
+            double s = L[i][j] + (i == j ? delta : 0.0);
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
             if (i == j) {
                 if (!(s > 0.0)) { ok = false; break; }
-                L[i * GUESS_MAX + i] = sqrt(s);
+                L[i][i] = sqrt(s);
             } else {
-                L[i * GUESS_MAX + j] = s / L[j * GUESS_MAX + j];
+                L[i][j] = s / L[j][j];
             }
         }
     if (!ok) {
         for (int k = 0; k < m; ++k) c[k] = k == 0 ? 1.0 : 0.0;
         return;
     }
-    for (int i = 0; i < m; ++i) {                  // L z = b
-        double s = b[i];
-        for (int k = 0; k < i; ++k) s -= L[i * GUESS_MAX + k] * z[k];
-        z[i] = s / L[i * GUESS_MAX + i];
-    }
-    for (int i = m - 1; i >= 0; --i) {             // L^T c = z
+    for (int i = 0; i < m; ++i) {                      // L z = b
         double s = z[i];
-        for (int k = i + 1; k < m; ++k) s -= L[k * GUESS_MAX + i] * c[k];
-        c[i] = s / L[i * GUESS_MAX + i];
+        for (int k = 0; k < i; ++k) s -= L[i][k] * z[k];
+        z[i] = s / L[i][i];
     }
+    for (int i = m - 1; i >= 0; --i) {                 // L^T c = z, c kept in z
+        double s = z[i];
+        for (int k = i + 1; k < m; ++k) s -= L[k][i] * z[k];
+        z[i] = s / L[i][i];
+    }
+    for (int k = 0; k < m; ++k) c[k] = z[k];
 }
 
 // x = sum_k c[k] W_k
