@@ -229,3 +229,23 @@ def test_multigrid_blocks_take_a_banded_order():
     upf = hf.index(B.IDX_UPOS)
     pf = np.argsort(upf)
     assert band(S[pf][:, pf]) > N // 2
+
+
+def test_banded_orders_on_a_heart_torso_slice():
+    """Heart and torso (the heart a part of the mesh): multigrid blocks take
+    one reverse Cuthill-McKee order for u (over S_1's graph) and another for
+    v (over S_i's graph on the heart); both are permutations and neither
+    widens the band of its matrix against the generator's numbering."""
+    import paper_1711_08708_amd as B
+    cfg = w.thorax2d(n_target=3000, seed=4)
+    band = lambda M: np.abs(M.tocoo().row - M.tocoo().col).max()
+    hs = B.HostSetup(cfg, eps_h=0.0, inner_p1=B.P1_AMG, inner_pk=B.PK_AMG)
+    up, vp = hs.index(B.IDX_UPOS), hs.index(B.IDX_VPOS)
+    assert sorted(up) == list(range(len(up))) and sorted(vp) == list(range(len(vp)))
+    assert len(vp) < len(up)
+    S1, Si = hs.csr(B.MAT_S1), hs.csr(B.MAT_SI)
+    pu, pv = np.argsort(up), np.argsort(vp)
+    bu, bv = band(S1[pu][:, pu]), band(Si[pv][:, pv])
+    print("bands: S_1", band(S1), "->", bu, " S_i", band(Si), "->", bv)
+    assert bu <= band(S1) and bv <= band(Si)
+    assert band(hs.amg_level(B.FACTOR_P1, 0)["A"]) == bu
